@@ -1,0 +1,472 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every test here checks the oracle against something other than itself: a
+textbook closed form, a theorem of the paper, a brute-force computation through
+a different route, or numbers printed in the paper.  CPU only.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.linalg import expm
+
+from oracle import ch_oracle as O
+from paper_2502_14589_amd.inputs import fourier_mode, uniform_field
+
+
+def fourier_eig(prob, k):
+    """Textbook eigenvalue of the periodic (2d+1)-point -Laplacian for mode k."""
+    return sum(4.0 / prob.h ** 2 * math.sin(math.pi * kk / prob.n) ** 2 for kk in k)
+
+
+# --- P1: A and A^2 ------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,k", [(2, 16, (1, 3)), (2, 12, (5, 0)), (3, 8, (1, 2, 3)), (2, 9, (4, 4))])
+def test_lap_fourier_eigenvalues(dim, n, k):
+    prob = O.Problem(dim, n, 0.05)
+    v = fourier_mode(n, dim, k, 1.0)
+    lam = fourier_eig(prob, k)
+    np.testing.assert_allclose(O.lap(v, prob), lam * v, atol=1e-12 * lam)
+    np.testing.assert_allclose(O.lap(O.lap(v, prob), prob), lam ** 2 * v, atol=1e-12 * lam ** 2)
+
+
+def test_biharmonic_stencils_match_textbook():
+    # 2-D 13-point and 3-D 25-point stencils of A^2 (times h^4)
+    for dim, centre, axis1, diag, axis2, ndiag in [(2, 20, -8, 2, 1, 4), (3, 42, -12, 2, 1, 12)]:
+        prob = O.Problem(dim, 10, 0.05)
+        offs = O._stencil_columns(prob)
+        h4 = prob.h ** 4
+        seen_diag = 0
+        for off, (a, b) in offs.items():
+            nz = [abs(o) for o in off if o != 0]
+            b = b * h4
+            if not nz:
+                assert b == pytest.approx(centre)
+                assert a * prob.h ** 2 == pytest.approx(2 * dim)
+            elif nz == [1]:
+                assert b == pytest.approx(axis1)
+                assert a * prob.h ** 2 == pytest.approx(-1)
+            elif nz == [2]:
+                assert b == pytest.approx(axis2)
+                assert a == 0
+            else:
+                assert nz == [1, 1]
+                assert b == pytest.approx(diag)
+                seen_diag += 1
+        assert seen_diag == ndiag
+        assert len(offs) == 1 + 2 * dim + 2 * dim + ndiag
+
+
+def test_lap_matches_sparse_kronecker_assembly():
+    for dim, n in [(2, 7), (3, 5)]:
+        prob = O.Problem(dim, n, 0.05)
+        A = O.assemble_A(prob)
+        y = np.random.default_rng(1).standard_normal(prob.N)
+        np.testing.assert_allclose(O.lap(y, prob), A @ y, rtol=0, atol=1e-10 * np.abs(A @ y).max())
+        assert abs(A - A.T).max() == 0
+        np.testing.assert_allclose(A @ np.ones(prob.N), 0.0, atol=1e-9)
+        ev = np.linalg.eigvalsh(A.toarray())
+        assert ev.min() > -1e-9 * ev.max()
+
+
+# --- P2: Ahat, Propositions 1 and 2 ----------------------------------------------
+
+@pytest.mark.parametrize("ubar", [0.0, 0.3, 0.8])
+def test_ahat_constant_state_mode(ubar):
+    prob = O.Problem(2, 16, 0.07)
+    y = np.full(prob.N, ubar)
+    k = (2, 1)
+    v = fourier_mode(16, 2, k, 1.0)
+    lam = fourier_eig(prob, k)
+    mu = lam * (3 * ubar ** 2 - 1 + prob.eps ** 2 * lam)
+    np.testing.assert_allclose(O.ahat_mv(v, y, prob), mu * v, atol=1e-11 * abs(lam ** 2 * prob.eps ** 2))
+
+
+def test_prop1_real_spectrum_and_inertia():
+    prob = O.Problem(2, 8, 0.05)
+    y = uniform_field(8, 2, 0.0, 0.9, seed=5)
+    Ah = O.assemble_ahat(y, prob).toarray()
+    ev = np.linalg.eigvals(Ah)
+    scale = np.abs(ev).max()
+    assert np.abs(ev.imag).max() <= 1e-9 * scale
+    A = O.assemble_A(prob).toarray()
+    B = np.diag(O.jac_diag(y, prob)) + prob.eps ** 2 * A
+    neg_B = int(np.sum(np.linalg.eigvalsh(B) < 0))
+    neg_Ah = int(np.sum(ev.real < -1e-9 * scale))
+    assert neg_Ah <= neg_B
+    assert neg_Ah >= 1  # the field is in the spinodal region: the test is not vacuous
+
+
+def test_prop2_eyre_nonnegative_spectrum():
+    prob = O.Problem(2, 8, 0.05, eyre=True)
+    y = uniform_field(8, 2, 0.0, 0.9, seed=5)
+    ev = np.linalg.eigvals(O.assemble_ahat(y, prob).toarray())
+    scale = np.abs(ev).max()
+    assert np.abs(ev.imag).max() <= 1e-9 * scale
+    assert ev.real.min() >= -1e-9 * scale
+
+
+def test_F1_start_vector_is_rhs():
+    for eyre in (False, True):
+        prob = O.Problem(2, 16, 0.05, eyre=eyre)
+        y = uniform_field(16, 2, 0.1, 0.5, seed=2)
+        v1 = O.ghat(y, prob) - O.ahat_mv(y, y, prob)
+        f = O.rhs(y, prob)
+        np.testing.assert_allclose(v1, f, atol=1e-12 * np.abs(f).max())
+
+
+# --- P4: small phi ---------------------------------------------------------------
+
+def test_phiv_small_scalar_and_zero():
+    for lam, s in [(3.0, 0.5), (-2.0, 0.3), (1e6, 1e-3), (1e-9, 2.0)]:
+        u = O.phiv_small(np.array([[lam]]), s)
+        z = -s * lam
+        ref = s * (np.expm1(z) / z)
+        assert u[0] == pytest.approx(ref, rel=1e-13)
+    u = O.phiv_small(np.zeros((3, 3)), 0.7)        # phi(0) = 1
+    np.testing.assert_allclose(u, [0.7, 0, 0], atol=1e-15)
+
+
+def test_phiv_small_vs_eigendecomposition():
+    rng = np.random.default_rng(3)
+    for j in (2, 5, 12):
+        H = np.triu(rng.standard_normal((j, j)), -1) + np.diag(np.arange(1, j + 1) * 2.0)
+        s = 0.37
+        lam, W = np.linalg.eig(H)
+        z = -s * lam
+        phi = np.expm1(z) / z
+        ref = (W @ (s * phi * np.linalg.solve(W, np.eye(j)[:, 0]))).real
+        np.testing.assert_allclose(O.phiv_small(H, s), ref, rtol=1e-10, atol=1e-13)
+
+
+# --- P3, P5, P14: EE2 Krylov step --------------------------------------------------
+
+def brute_force_ee(y, prob, tau):
+    """y + [expm([[-tau Ahat, tau v1], [0, 0]])]_{1:N, N+1} with dense Ahat."""
+    Ah = O.assemble_ahat(y, prob).toarray()
+    v1 = O.ghat(y, prob) - Ah @ y
+    N = y.size
+    M = np.zeros((N + 1, N + 1))
+    M[:N, :N] = -tau * Ah
+    M[:N, N] = tau * v1
+    return y + expm(M)[:N, N]
+
+
+def test_ee_step_matches_dense_expm_8x8():
+    prob = O.Problem(2, 8, 0.05)
+    y = uniform_field(8, 2, 0.0, 0.3, seed=7)
+    tau = 2e-3          # tau * lambda_max ~ 0.56: several Krylov vectors needed
+    ref = brute_force_ee(y, prob, tau)
+    y1, t1, info = O.ee_step(y, prob, tau, 1e-13, 64)
+    assert t1 == tau and info.converged
+    assert O.rel_error(y1, ref) <= 1e-11
+    # small Krylov space: the trace shortens the step; compare at the accepted tau
+    y2, t2, info2 = O.ee_step(y, prob, tau, 1e-6, 4)
+    assert t2 < tau and not info2.converged and info2.j == 4
+    assert info2.resnorm <= 1e-6
+    ref2 = brute_force_ee(y, prob, t2)
+    dy = np.linalg.norm(ref2 - y)
+    assert np.linalg.norm(y2 - ref2) <= 1e-5 * dy
+
+
+def test_trace_is_maximal_admissible_step():
+    prob = O.Problem(2, 16, 0.05)
+    y = uniform_field(16, 2, 0.1, 0.05, seed=8)
+    tol_phi = 1e-7
+    _, tau, info = O.ee_step(y, prob, 1e-3, tol_phi, 6, keep_basis=True)
+    assert not info.converged
+    Hj, h = info.H[:6, :6], info.H[6, 5]
+    assert O.resnorm_at(Hj, h, tau) <= tol_phi
+    assert O.resnorm_at(Hj, h, tau * (1 + 1e-12)) > tol_phi
+    # resnorm is nondecreasing on a fine grid below tau (Section 4.1)
+    ss = np.linspace(tau / 50, tau, 50)
+    rs = [O.resnorm_at(Hj, h, s) for s in ss]
+    assert all(b >= a * (1 - 1e-9) for a, b in zip(rs, rs[1:]))
+
+
+def test_residual_identity_and_arnoldi_health():
+    prob = O.Problem(2, 16, 0.05)
+    y = uniform_field(16, 2, 0.1, 0.05, seed=9)
+    tau0 = 5e-6
+    y1, tau, info = O.ee_step(y, prob, tau0, 1e-12, 10, keep_basis=True)
+    j = info.j
+    V, H = info.V, info.H
+    mv = lambda v: O.ahat_mv(v, y, prob)
+    AV = np.column_stack([mv(V[:, i]) for i in range(j)])
+    normA = np.abs(O.assemble_ahat(y, prob)).sum(axis=0).max()
+    assert np.abs(AV - V @ H).max() <= 1e-12 * normA
+    assert np.abs(V.T @ V - np.eye(j + 1)).max() <= 1e-12
+    # explicit residual r = -Ahat y_m + ghat - y_m' (eq. rm)
+    g = O.ghat(y, prob)
+    dexp = expm(-tau * H[:j, :j])[:, 0]
+    ym_dot = V[:, :j] @ (info.beta * dexp)
+    r = -mv(y1) + g - ym_dot
+    res = np.linalg.norm(r) / info.beta
+    assert res == pytest.approx(info.resnorm, rel=1e-6, abs=1e-14)
+
+
+# --- P6: linearised growth of a small mode --------------------------------------------
+
+def test_linearised_mode_growth_ee():
+    prob = O.Problem(2, 16, 0.05)
+    k, delta = (1, 2), 1e-6
+    y0 = fourier_mode(16, 2, k, delta)
+    lam = fourier_eig(prob, k)
+    mu = lam * (-1 + prob.eps ** 2 * lam)
+    assert mu < 0  # spinodal: the mode grows
+    tau = 2e-3
+    y1, t1, info = O.ee_step(y0, prob, tau, 1e-10, 30)
+    assert t1 == tau and info.j <= 3
+    exact = math.exp(-mu * tau) * y0
+    assert O.rel_error(y1, exact) <= 1e-9
+    y2, rec = O.ee_adaptive(y0, prob, 1e-3, 0.02, 1e-6, 10)
+    exact2 = math.exp(-mu * rec.t) * y0
+    assert rec.t == 0.02
+    assert O.rel_error(y2, exact2) <= 1e-6
+
+
+def test_linearised_mode_growth_lim():
+    # with tau lambda_max <= 1, p = 1 and LIM is explicit Euler: amplitude (1 - tau mu)
+    prob = O.Problem(2, 16, 0.05)
+    k, delta = (1, 1), 1e-7
+    y0 = fourier_mode(16, 2, k, delta, mean=0.3)
+    lam = fourier_eig(prob, k)
+    mu = lam * (3 * 0.3 ** 2 - 1 + prob.eps ** 2 * lam)
+    tau = 0.5 / O.lambda_max(y0, prob)
+    y1, p = O.lim_step(y0, prob, tau)
+    assert p == 1
+    mask = np.abs(y0 - 0.3) > 0.5 * delta
+    amp = (y1[mask] - 0.3) / (y0[mask] - 0.3)
+    np.testing.assert_allclose(amp, 1 - tau * mu, rtol=1e-6)
+
+
+# --- P7, P8: LIM recurrence ------------------------------------------------------------
+
+@pytest.mark.parametrize("tl", [0.3, 3.0, 30.0, 1e3, 1e5])
+def test_lim_chebyshev_stability_polynomial(tl):
+    """Per eigenvalue the LIM step is Richardson on (I + tau Ahat) y = y^n + tau g.
+
+    Its error factor is (-tau mu) prod_{m>=2} [tau (a_m - mu)/(1 + tau a_m)]^2 and
+    the Chebyshev design keeps it inside [-1, 1] on [0, lambda_max].
+    """
+    lam, tau = 1.0, tl
+    mu = np.linspace(0.0, lam, 4001)
+    y, p = O.lim_iterate(lambda v: mu * v, np.zeros_like(mu), np.ones_like(mu), tau, lam)
+    # the first node of the ordered set is the largest, a_1 = 0
+    betas, a = O.lim_coefficients(p, lam)
+    assert a[0] == 0.0 and betas[0] == max(betas)
+    # error factor: y - y* = P (y^n - y*), y* = 1/(1 + tau mu)
+    ystar = 1.0 / (1.0 + tau * mu)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        P = (y - ystar) / (1.0 - ystar)
+    P = P[1:]
+    assert np.all(np.abs(P) <= 1.0 + 1e-12)
+    # the zeros of the factor are at mu = a_m (m >= 2) and at mu = 0 (m = 1)
+    for am in a[1:]:
+        ya, _ = O.lim_iterate(lambda v: am * v, np.zeros(1), np.ones(1), tau, lam)
+        assert ya[0] == pytest.approx(1.0 / (1.0 + tau * am), rel=1e-12, abs=1e-300)
+
+
+def test_lim_p1_is_explicit_euler():
+    prob = O.Problem(2, 16, 0.05)
+    y = uniform_field(16, 2, 0.1, 0.05, seed=11)
+    lam = O.lambda_max(y, prob)
+    tau = 0.9 / lam
+    assert O.lim_order(tau, lam) == 1
+    y1, p = O.lim_step(y, prob, tau)
+    np.testing.assert_allclose(y1, y + tau * O.rhs(y, prob), atol=1e-15)
+
+
+def test_lim_order_formula_bounds():
+    # eq. p_est: (pi/4)/(pi/2 - atan sqrt(x)) <= (pi/4) sqrt(x + 1), equality in the limit
+    for x in [0.0, 0.5, 1.0, 7.0, 1e2, 1e4, 1e8]:
+        p = O.lim_order(x, 1.0)
+        assert p <= math.ceil(math.pi / 4 * math.sqrt(x + 1)) + 1
+        assert p >= 1
+    assert O.lim_order(1.0, 1.0) == 1      # atan 1 = pi/4: ratio exactly 1
+    assert O.lim_order(1e-12, 1.0) == 1
+
+
+# --- P9: lambda_max --------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,eyre", [(2, 12, False), (2, 12, True), (3, 6, False), (2, 5, False)])
+def test_lambda_max_equals_dense_one_norm(dim, n, eyre):
+    prob = O.Problem(dim, n, 0.05, eyre)
+    y = uniform_field(n, dim, 0.2, 0.9, seed=12)
+    Ah = O.assemble_ahat(y, prob)
+    ref = float(abs(Ah).sum(axis=0).max())
+    assert O.lambda_max(y, prob) == pytest.approx(ref, rel=1e-13)
+
+
+def test_lambda_max_closed_form():
+    """Convex column-sum g(d) maximised at an end of [d_min, d_max]."""
+    for dim, n, eps in [(2, 64, 0.05), (2, 32, 0.001), (3, 16, 0.02)]:
+        prob = O.Problem(dim, n, eps)
+        y = uniform_field(n, dim, 0.1, 0.6, seed=13)
+        h2, e4 = prob.h ** 2, eps ** 2 / prob.h ** 4
+        if dim == 2:
+            g = lambda d: abs(4 * d / h2 + 20 * e4) + 4 * abs(d / h2 + 8 * e4) + 12 * e4
+        else:
+            g = lambda d: abs(6 * d / h2 + 42 * e4) + 6 * abs(d / h2 + 12 * e4) + 30 * e4
+        d = O.jac_diag(y, prob)
+        assert O.lambda_max(y, prob) == pytest.approx(max(g(d.min()), g(d.max())), rel=1e-13)
+
+
+# --- P10, P11: invariants --------------------------------------------------------------
+
+def test_mass_conservation_ee_and_lim():
+    prob = O.Problem(2, 32, 0.03)
+    y0 = uniform_field(32, 2, 0.1, 0.05, seed=14)
+    m0, s0 = O.mass(y0), np.abs(y0).sum()
+    y1, _ = O.ee_adaptive(y0, prob, 1e-4, np.inf, 1e-4, 20, max_steps=15)
+    assert abs(O.mass(y1) - m0) <= 1e-12 * s0
+    y2, _ = O.lim_adaptive(y0, prob, 1e-7, np.inf, 1e-4, max_steps=15)
+    assert abs(O.mass(y2) - m0) <= 1e-12 * s0
+
+
+def test_energy_nonincreasing_small_constant_steps():
+    prob = O.Problem(2, 64, 0.05)
+    y = uniform_field(64, 2, 0.0, 0.05, seed=0)
+    E = [O.energy(y, prob)]
+    yl = y.copy()
+    El = [E[0]]
+    for _ in range(8):
+        y, _ = O.ee_step_const(y, prob, 1e-5, 1e-8, 30)
+        E.append(O.energy(y, prob))
+        yl, _ = O.lim_step(yl, prob, 1e-5)
+        El.append(O.energy(yl, prob))
+    for seq in (E, El):
+        assert all(b <= a + 1e-12 * abs(a) for a, b in zip(seq, seq[1:]))
+        assert seq[-1] < seq[0]
+
+
+def test_semidiscrete_energy_dissipation_identity():
+    """dE/dt = -h^d mu^T A mu <= 0 along eq. IVP, mu = F'(y) + eps^2 A y."""
+    prob = O.Problem(2, 24, 0.05)
+    y = uniform_field(24, 2, 0.1, 0.3, seed=15)
+    f = O.rhs(y, prob)
+    dt = 1e-9
+    dE = (O.energy(y + dt * f, prob) - O.energy(y - dt * f, prob)) / (2 * dt)
+    mu = O.Fprime(y) + prob.eps ** 2 * O.lap(y, prob)
+    assert dE == pytest.approx(-prob.h ** 2 * mu @ O.lap(mu, prob), rel=1e-5)
+
+
+# --- P12: orders -------------------------------------------------------------------------
+
+def _smooth_field(n):
+    x = np.arange(n) / n
+    X, Y = np.meshgrid(x, x)
+    return (0.3 * np.cos(2 * np.pi * X) * np.cos(2 * np.pi * Y) + 0.2 * np.sin(4 * np.pi * X)).ravel()
+
+
+def test_order_ee2_two_lim_one():
+    prob = O.Problem(2, 16, 0.05)
+    y0 = _smooth_field(16)
+    T = 8e-4
+    ref, _ = O.ee_const_run(y0, prob, T / 256, 256, 1e-13, 30)
+    errs_ee = [O.rel_error(O.ee_const_run(y0, prob, T / k, k, 1e-13, 30)[0], ref) for k in (4, 8, 16)]
+    errs_lim = [O.rel_error(O.lim_const_run(y0, prob, T / k, k)[0], ref) for k in (8, 16, 32)]
+    r_ee = [math.log2(a / b) for a, b in zip(errs_ee, errs_ee[1:])]
+    r_lim = [math.log2(a / b) for a, b in zip(errs_lim, errs_lim[1:])]
+    assert all(1.7 <= r <= 2.3 for r in r_ee), (errs_ee, r_ee)
+    assert all(0.8 <= r <= 1.3 for r in r_lim), (errs_lim, r_lim)
+
+
+# --- P13: controller rules ------------------------------------------------------------------
+
+def test_controller_rules_table():
+    # eq. tol_phi: each of the four terms decides in turn
+    assert O.tol_phi_rule(1.0, 1.0, 1e-4) == pytest.approx(1e-3)          # 10 tol
+    assert O.tol_phi_rule(1.0, 1.0, 1.0) == pytest.approx(0.1)            # 1/10 and ghat/(10 beta) tie
+    assert O.tol_phi_rule(1e-3, 1.0, 1.0) == pytest.approx(1e-4)          # ||ghat||/(10 beta)
+    assert O.tol_phi_rule(1.0, 1.0, 1e-10) == pytest.approx(1e-7)         # floor
+    # eq. EEdt: growth capped at 5/4; eq. LIMdt: proportional
+    assert O.ee_dt(2.0, 1e-6, 1e-4) == pytest.approx(2.5)
+    assert O.ee_dt(2.0, 4e-4, 1e-4) == pytest.approx(1.0)
+    assert O.ee_dt(2.0, 0.0, 1e-4) == pytest.approx(2.5)
+    assert O.lim_dt(2.0, 4e-4, 1e-4) == pytest.approx(0.5)
+    assert O.lim_dt(2.0, 0.0, 1e-4) == 2.0
+
+
+def test_adaptive_clip_lands_on_T():
+    prob = O.Problem(2, 16, 0.05)
+    y0 = uniform_field(16, 2, 0.0, 0.05, seed=16)
+    _, rec = O.ee_adaptive(y0, prob, 3e-4, 1e-3, 1e-3, 20)
+    assert rec.t == 1e-3
+    _, rec = O.lim_adaptive(y0, prob, 3e-7, 1e-5, 1e-3)
+    assert rec.t == 1e-5
+
+
+# --- P15: the paper's printed LIM matvec counts (Tables 1 and 2) --------------------------------
+
+def _paper_eps4():
+    # eq. eps with h = 1 (64 cells on (0,64)) and m = 4
+    return 4.0 / (2 * math.sqrt(2) * math.atanh(0.9))
+
+
+def _read_golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def test_paper_lim_matvec_counts():
+    """Constant-step LIM counts of Tables 1-2 follow from eq. p with lambda_max = ||Ahat||_1.
+
+    The paper's grid is (0,64)^2 with n cells per direction (h = 64/n) and
+    eps = eps_4 of the 64^2 grid.  In the rows used here p is the same for every
+    state with |y| <= 1, so the count is (2p - 1) T / tau.
+    """
+    eps = _paper_eps4()
+    assert eps == pytest.approx(0.9606, abs=5e-5)
+    rows = _read_golden("paper_lim_counts.txt")
+    assert len(rows) >= 8
+    for grid, eyre, tau, count in rows:
+        n = int(grid)
+        # periodic grid with the paper's spacing: same interior columns as the paper's grid
+        # Mapping (0,64) onto (0,1) divides lengths by 64: eps by 64, time by 64^2,
+        # and leaves tau * lambda_max unchanged.
+        prob = O.Problem(2, n, eps / 64.0, eyre == "1")
+        tau_u = float(tau) / 64.0 ** 2
+        ps = set()
+        for ybar in (0.0, 0.5, 1.0):
+            y = np.full(prob.N, ybar)
+            ps.add(O.lim_order(tau_u, O.lambda_max(y, prob)))
+        assert len(ps) == 1, (grid, tau, ps)
+        p = ps.pop()
+        steps = round(1000.0 / float(tau))
+        assert (2 * p - 1) * steps == int(count), (grid, eyre, tau, p)
+
+
+def test_linear_rt_restart_solves_frozen_linear_problem():
+    """Constant-step EE2 with restarts reaches the exact linear solution (eq. yt) at the full tau."""
+    prob = O.Problem(2, 8, 0.05)
+    y = uniform_field(8, 2, 0.0, 0.3, seed=7)
+    tau = 4e-3
+    ref = brute_force_ee(y, prob, tau)
+    y1, info = O.ee_step_const(y, prob, tau, 1e-10, 4)
+    assert info.restarts >= 1
+    assert info.matvecs == sum(1 + j for j in info.js)
+    assert np.linalg.norm(y1 - ref) <= 1e-7 * np.linalg.norm(ref - y)
+
+
+def test_krylov_beta_zero_and_breakdown():
+    prob = O.Problem(2, 16, 0.05)
+    # constant state: f(y) = 0, the step is the identity (reading R3)
+    y = np.full(prob.N, 0.5)      # binary-exact state: the stencils cancel exactly
+    y1, tau, info = O.ee_step(y, prob, 1e-3, 1e-8, 10)
+    assert info.j == 0 and tau == 1e-3 and np.array_equal(y1, y)
+    # an exact eigenvector start: Krylov space of dimension 1 (h_21 ~ 0)
+    lam = fourier_eig(prob, (1, 0))
+    v = fourier_mode(16, 2, (1, 0), 1.0)
+    g = -lam * v
+    y2, tau2, info2 = O.krylov_phi_cycle(lambda x: lam * x, np.zeros(prob.N), g, 0.01, 1e-12, 10)
+    assert info2.j == 1 and info2.converged
+    np.testing.assert_allclose(y2, -(1 - math.exp(-lam * 0.01)) * v, atol=1e-13)
