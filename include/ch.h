@@ -1,0 +1,160 @@
+/*
+ * ch.h -- C ABI of the MI355X (gfx950) library for the explicit time steps of
+ * the space-discretised Cahn-Hilliard equation
+ *
+ *     y' = -A (F'(y) + eps^2 A y),   F'(y) = y^3 - y        (Section 2, eq. IVP, eq. F)
+ *
+ * on a periodic grid of n^dim points over [0,1]^dim (h = 1/n), where -A is the
+ * standard (2 dim + 1)-point Laplacian.  Two schemes of Botchev (arXiv
+ * 2502.14589) are provided:
+ *
+ *   EE2  exponential Euler of order 2 (Section 4): the Jacobian is frozen at
+ *        y^n, giving y' = -Ahat_n y + ghat^n (eq. IVPlin) with
+ *        Ahat_n = A (J_n + eps^2 A), ghat^n = A (J_n y^n - F'(y^n)) (eq. A_g);
+ *        its solution y^n + tau phi(-tau Ahat_n)(ghat^n - Ahat_n y^n) (eq. yt) is
+ *        evaluated by Arnoldi with modified Gram-Schmidt and the residual-time
+ *        (RT) restart of the Krylov algorithm (Fig. 3); adaptive steps follow
+ *        Fig. 4 (eqs. tol_phi, LIMest, EEdt).
+ *   LIM  the Chebyshev local-iteration scheme (Fig. 1), 2p-1 explicit-Euler-like
+ *        stages with p from eq. p and lambda_max = ||Ahat_n||_1; adaptive steps
+ *        follow Fig. 2 (eqs. LIMest, LIMdt).
+ *
+ * With eyre != 0 both use the Eyre splitting (eq. A_g_cs).
+ *
+ * Memory and streams.  Every field argument is a DEVICE pointer to a
+ * contiguous FP64 array of n^dim values, row-major with x fastest
+ * (index = (z n + y) n + x), owned by the caller.  The library owns all
+ * scratch (Krylov basis, state ping-pong buffers, reduction partials, control
+ * block); it is sized lazily to the largest problem seen and freed by
+ * ch_destroy.  All work is issued on the stream given to ch_create; every
+ * call below returns after that stream has drained the call's work (host and
+ * device agree on the result when the call returns).
+ *
+ * Errors.  Every call returns a ch_status; nothing aborts or throws across
+ * the ABI.  When a call fails, the caller's field holds the last state that
+ * was fully accepted (for a one-step call: its input, unchanged).
+ *
+ * Threading.  A context is used by one host thread at a time.
+ */
+#ifndef CH_H
+#define CH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ch_ctx ch_ctx;
+
+enum ch_status {
+    CH_OK = 0,
+    CH_EINVAL = -1,          /* bad argument: dim not 2/3, n < 5, eps <= 0, tau <= 0, m_max out of range, NULL */
+    CH_ENOMEM = -2,          /* device allocation failed */
+    CH_ENONFINITE = -3,      /* a NaN/Inf appeared in the input or in a step */
+    CH_ETAU_UNDERFLOW = -4,  /* the residual-time trace found no admissible step >= tau_min */
+    CH_EBUSY = -5,           /* serving queue full */
+    CH_ENOENT = -6,          /* unknown ticket */
+    CH_EDEVICE = -7          /* HIP runtime error (see ch_last_error_message) */
+};
+
+enum ch_precision {
+    CH_FP64 = 0,        /* every vector and stencil in FP64 */
+    CH_FP32_MIXED = 1   /* Krylov basis, matvecs and MGS axpys in FP32; state, reductions,
+                           Hessenberg phi, solution update and error estimate in FP64 */
+};
+
+/* Largest Krylov dimension m_max (the phi of H_{m,m} is evaluated in one workgroup's LDS). */
+#define CH_MMAX 48
+/* Largest Chebyshev order p of one LIM step. */
+#define CH_PMAX 4096
+
+typedef struct {
+    int dim;        /* 2 or 3 */
+    int n;          /* grid points per direction, >= 5; periodic; h = 1/n */
+    double eps;     /* interface parameter epsilon > 0 */
+    int eyre;       /* 0: eq. A_g; 1: Eyre splitting eq. A_g_cs */
+    int prec;       /* ch_precision (EE2 only; LIM always runs in FP64) */
+} ch_problem;
+
+typedef struct {
+    int m_max;              /* Krylov dimension, 1..CH_MMAX */
+    double tol;             /* accuracy tolerance of eq. EEdt and eq. tol_phi */
+    double tol_phi_fixed;   /* > 0: use this tol_phi instead of eq. tol_phi */
+    double tau_min;         /* trace underflow threshold (>= 0) */
+    int constant_step;      /* 1: constant tau with linear RT restarts (no controller) */
+} ch_ee_opts;
+
+/* Per-step record (one per accepted step). */
+typedef struct {
+    double t;           /* time after the step */
+    double tau;         /* accepted step */
+    double tau_next;    /* proposal for the next step */
+    double est;         /* eq. LIMest estimate */
+    double tol_phi;     /* Krylov tolerance used (EE2) */
+    double beta;        /* ||ghat - Ahat y^n|| (EE2) */
+    double resnorm;     /* final ||r||/beta of the last Krylov cycle (EE2) */
+    double lambda_max;  /* ||Ahat||_1 (LIM) */
+    int j;              /* Krylov dimension of the last cycle (EE2) / Chebyshev order p (LIM) */
+    int cycles;         /* Krylov cycles in the step (EE2; > 1 only with constant_step) */
+    int traced;         /* the RT trace shortened the step (EE2) */
+    int matvecs;        /* matvecs with Ahat_n in the step, counted as the paper does */
+} ch_step_record;
+
+typedef struct {
+    double t;               /* time reached */
+    double tau_next;        /* proposed next step */
+    int steps;              /* accepted steps */
+    long long matvecs;      /* total matvecs with Ahat_n */
+    int restarts;           /* Krylov cycles beyond the first, summed over steps */
+    int traces;             /* steps shortened by the RT trace */
+    int status;             /* ch_status of the run */
+} ch_run_stats;
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL: the null stream). */
+int ch_create(ch_ctx **ctx, int device, void *hip_stream);
+int ch_destroy(ch_ctx *ctx);
+const char *ch_strerror(int status);
+/* Text of the last HIP runtime error seen by this context ("" if none). */
+const char *ch_last_error_message(ch_ctx *ctx);
+
+/*
+ * Adaptive (Fig. 4) or constant-step EE2 run on the field y (in/out).
+ * Starts at time t0 with proposed step tau0 and advances until t >= T or
+ * max_steps steps were accepted (T may be INFINITY; max_steps <= 0: no limit,
+ * then T must be finite).  Every step clips tau to T - t (Fig. 4, lines 3-5).
+ * records: NULL or an array of max_steps ch_step_record (host memory).
+ */
+int ch_run_ee(ch_ctx *ctx, const ch_problem *prob, double *y, double tau0, double t0, double T,
+              int max_steps, const ch_ee_opts *opts, ch_run_stats *stats, ch_step_record *records);
+
+/* One EE2 step (Fig. 3 with the controller of Fig. 4): ch_run_ee with max_steps = 1. */
+int ch_step_ee(ch_ctx *ctx, const ch_problem *prob, double *y, double tau, double t, double T,
+               const ch_ee_opts *opts, ch_step_record *out);
+
+/*
+ * Adaptive (Fig. 2, tol > 0) or constant-step (tol <= 0) LIM run on y (in/out),
+ * same conventions as ch_run_ee.
+ */
+int ch_run_lim(ch_ctx *ctx, const ch_problem *prob, double *y, double tau0, double t0, double T,
+               int max_steps, double tol, ch_run_stats *stats, ch_step_record *records);
+
+/* One LIM step (Fig. 1 with the controller of Fig. 2). */
+int ch_step_lim(ch_ctx *ctx, const ch_problem *prob, double *y, double tau, double t, double T,
+                double tol, ch_step_record *out);
+
+enum ch_phi_mode {
+    CH_PHI_SHRINK = 0,   /* one Fig. 3 cycle: the RT trace may shorten tau (nonlinear RT restart) */
+    CH_PHI_RESTART = 1   /* linear RT restarts until the whole tau is covered */
+};
+
+/*
+ * y_out = y + tau phi(-tau Ahat_n)(ghat^n - Ahat_n y) (eq. yt) with Ahat_n, ghat^n frozen
+ * at y (eq. A_g / A_g_cs); y is not modified; y_out may not alias y.
+ * out->tau is the step actually covered (< tau0 only in CH_PHI_SHRINK mode).
+ */
+int ch_phiv(ch_ctx *ctx, const ch_problem *prob, const double *y, double *y_out, double tau0,
+            int mode, double tol_phi, int m_max, ch_step_record *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CH_H */

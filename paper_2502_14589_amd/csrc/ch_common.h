@@ -1,0 +1,254 @@
+// Device helpers shared by the libch kernels: deterministic two-stage
+// reductions, 16-byte vector access and the stencil tile geometry.
+#pragma once
+
+#include "ch_internal.h"
+
+// ---------------------------------------------------------------------------
+// Reductions.  Wave64 butterfly, then the waves of a workgroup through LDS,
+// then one partial per workgroup in global memory; the last workgroup to
+// arrive (atomic ticket) adds the partials in a fixed order, so the result
+// does not depend on scheduling.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+enum RedOp { RED_SUM = 0, RED_MIN = 1, RED_MAX = 2 };
+
+template <int OP>
+__device__ __forceinline__ double red_wave(double x) {
+    if (OP == RED_SUM) return wave_sum(x);
+    if (OP == RED_MIN) return wave_min(x);
+    return wave_max(x);
+}
+
+template <int OP>
+__device__ __forceinline__ double red_combine(double a, double b) {
+    if (OP == RED_SUM) return a + b;
+    if (OP == RED_MIN) return fmin(a, b);
+    return fmax(a, b);
+}
+
+template <int OP>
+__device__ __forceinline__ double red_identity() {
+    if (OP == RED_SUM) return 0.0;
+    if (OP == RED_MIN) return __builtin_inf();
+    return -__builtin_inf();
+}
+
+// Workgroup reduction of NR values; the result is valid in thread 0.
+template <int NR, int OP>
+__device__ __forceinline__ void block_reduce(double (&x)[NR], double (*lds)[NR]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) x[r] = red_wave<OP>(x[r]);
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) lds[wid][r] = x[r];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            double s = lds[0][r];
+            for (int w = 1; w < nw; ++w) s = red_combine<OP>(s, lds[w][r]);
+            x[r] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Grid-wide reduction with the last-workgroup finalisation.  Every workgroup
+// of the launch must call it exactly once.  Returns true in thread 0 of the
+// last workgroup, with the totals in `tot`; the ticket is re-armed there.
+template <int NR, int OP>
+__device__ bool grid_reduce(double (&x)[NR], double* __restrict__ part, unsigned int* ticket,
+                            double (&tot)[NR]) {
+    __shared__ double lds[16][NR];
+    __shared__ int is_last;
+    block_reduce<NR, OP>(x, lds);
+    const unsigned int nb = gridDim.x;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            __hip_atomic_store(&part[r * CH_MAXB + blockIdx.x], x[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned int t = atomicAdd(ticket, 1u);
+        is_last = (t == nb - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double s[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s[r] = red_identity<OP>();
+    for (unsigned int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            s[r] = red_combine<OP>(
+                s[r], __hip_atomic_load(&part[r * CH_MAXB + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    block_reduce<NR, OP>(s, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) tot[r] = s[r];
+        *ticket = 0u;
+    }
+    return threadIdx.x == 0;
+}
+
+// ---------------------------------------------------------------------------
+// 16-byte vectors
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
+template <> struct Vec16<float> { using type = float4; static constexpr int W = 4; };
+
+// ---------------------------------------------------------------------------
+// Stencil tiles.  A workgroup owns a TX x TY (x TZ) block of outputs; the
+// operand is staged in LDS with a halo of 2 (A applied twice) and the frozen
+// state with a halo of 1.  Periodic wrap by index arithmetic.
+// ---------------------------------------------------------------------------
+template <int DIM> struct Geo;
+template <> struct Geo<2> {
+    static constexpr int TX = 64, TY = 8, TZ = 1;
+};
+template <> struct Geo<3> {
+    static constexpr int TX = 32, TY = 4, TZ = 4;
+};
+
+template <int DIM, int H> struct Region {
+    static constexpr int X = Geo<DIM>::TX + 2 * H;
+    static constexpr int Y = Geo<DIM>::TY + 2 * H;
+    static constexpr int Z = DIM == 3 ? Geo<DIM>::TZ + 2 * H : 1;
+    static constexpr int SIZE = X * Y * Z;
+};
+
+__device__ __forceinline__ int wrapi(int g, int n) {
+    int w = g % n;
+    return w < 0 ? w + n : w;
+}
+
+struct TileOrigin {
+    int x0, y0, z0;
+};
+
+template <int DIM>
+__device__ __forceinline__ int num_tiles(int n, int& ntx, int& nty) {
+    ntx = (n + Geo<DIM>::TX - 1) / Geo<DIM>::TX;
+    nty = (n + Geo<DIM>::TY - 1) / Geo<DIM>::TY;
+    const int ntz = DIM == 3 ? (n + Geo<DIM>::TZ - 1) / Geo<DIM>::TZ : 1;
+    return ntx * nty * ntz;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous band of tiles so that halo rows shared by neighbouring tiles
+// are re-read from the same L2.  Bijective on [0, G).
+__device__ __forceinline__ int xcd_remap(int bid, int G) {
+    const int q = G >> 3, r = G & 7;
+    const int x = bid & 7, local = bid >> 3;
+    return x * q + min(x, r) + local;
+}
+
+template <int DIM>
+__device__ __forceinline__ TileOrigin tile_origin(int t, int ntx, int nty) {
+    TileOrigin o;
+    o.x0 = (t % ntx) * Geo<DIM>::TX;
+    const int r = t / ntx;
+    o.y0 = (r % nty) * Geo<DIM>::TY;
+    o.z0 = DIM == 3 ? (r / nty) * Geo<DIM>::TZ : 0;
+    return o;
+}
+
+// Load the region of halo H around the tile, calling put(i, value) with the
+// region's linear index.
+template <int DIM, int H, typename TS, typename Put>
+__device__ __forceinline__ void load_region(const TileOrigin& o, int n, const TS* __restrict__ src, Put&& put) {
+    using R = Region<DIM, H>;
+    const bool interior = o.x0 >= H && o.x0 + Geo<DIM>::TX + H <= n && o.y0 >= H &&
+                          o.y0 + Geo<DIM>::TY + H <= n &&
+                          (DIM == 2 || (o.z0 >= H && o.z0 + Geo<DIM>::TZ + H <= n));
+    for (int i = threadIdx.x; i < R::SIZE; i += blockDim.x) {
+        const int cx = i % R::X;
+        const int rr = i / R::X;
+        const int cy = rr % R::Y;
+        const int cz = rr / R::Y;
+        int gx = o.x0 + cx - H, gy = o.y0 + cy - H, gz = DIM == 3 ? o.z0 + cz - H : 0;
+        if (!interior) {
+            gx = wrapi(gx, n);
+            gy = wrapi(gy, n);
+            if (DIM == 3) gz = wrapi(gz, n);
+        }
+        put(i, src[((size_t)gz * n + gy) * n + gx]);
+    }
+}
+
+// Index in the halo-2 region of the centre of halo-1 point i1.
+template <int DIM>
+__device__ __forceinline__ int r1_to_r2(int i1) {
+    using R1 = Region<DIM, 1>;
+    using R2 = Region<DIM, 2>;
+    const int cx = i1 % R1::X;
+    const int rr = i1 / R1::X;
+    const int cy = rr % R1::Y;
+    const int cz = rr / R1::Y;
+    return ((cz + (DIM == 3 ? 1 : 0)) * R2::Y + (cy + 1)) * R2::X + (cx + 1);
+}
+
+// Unscaled -Laplacian (2 dim c - neighbours) at index c of a region with row
+// length RX and plane size RXY.
+template <int DIM, int RX, int RXY, typename T>
+__device__ __forceinline__ T lap_at(const T* s, int c) {
+    T nb = (s[c - 1] + s[c + 1]) + (s[c - RX] + s[c + RX]);
+    if (DIM == 3) nb += s[c - RXY] + s[c + RXY];
+    return T(2 * DIM) * s[c] - nb;
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ T lap2_at_r1(const T* s2, int i1) {
+    using R2 = Region<DIM, 2>;
+    return lap_at<DIM, R2::X, R2::X * R2::Y>(s2, r1_to_r2<DIM>(i1));
+}
+
+// Output point i0 of the tile: its halo-1 index and global coordinates.
+template <int DIM>
+__device__ __forceinline__ bool out_point(int i0, const TileOrigin& o, int n, int& i1, size_t& gi) {
+    constexpr int TX = Geo<DIM>::TX, TY = Geo<DIM>::TY;
+    using R1 = Region<DIM, 1>;
+    const int cx = i0 % TX;
+    const int rr = i0 / TX;
+    const int cy = rr % TY;
+    const int cz = rr / TY;
+    i1 = ((cz + (DIM == 3 ? 1 : 0)) * R1::Y + (cy + 1)) * R1::X + (cx + 1);
+    const int gx = o.x0 + cx, gy = o.y0 + cy, gz = o.z0 + cz;
+    gi = ((size_t)gz * n + gy) * n + gx;
+    return gx < n && gy < n && (DIM == 2 || gz < n);
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ T lap1_at(const T* s1, int i1) {
+    using R1 = Region<DIM, 1>;
+    return lap_at<DIM, R1::X, R1::X * R1::Y>(s1, i1);
+}
+
+template <int DIM>
+constexpr int tile_points() {
+    return Geo<DIM>::TX * Geo<DIM>::TY * Geo<DIM>::TZ;
+}

@@ -1,0 +1,304 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Element-by-element comparison on identical seeded inputs: relative L2 error
+<= 1e-10 for the FP64 path (steps and runs), accepted steps agreeing to
+<= 1e-12 relative, equal Krylov dimensions and Chebyshev orders.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import ch_oracle as O
+from paper_2502_14589_amd import ch
+from paper_2502_14589_amd.inputs import fourier_mode, small_2d_field, uniform_field
+
+TOL_FP64 = 1e-10
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = ch.Context(0)
+    yield c
+    c.close()
+
+
+def dev(y):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(y, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def probs(dim, n, eps, eyre=False):
+    return O.Problem(dim, n, eps, eyre), ch.Problem(dim, n, eps, eyre)
+
+
+# --- single EE2 steps (Fig. 3) -------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,eps,tau", [
+    (2, 40, 0.05, 2e-5),     # one ragged tile column, 5 tile rows
+    (2, 130, 0.02, 2e-6),    # 3 tiles across with a ragged tail, ragged rows
+    (3, 12, 0.05, 1e-4),     # 3-D, ragged tiles
+    (3, 21, 0.04, 5e-5),
+])
+def test_ee_step_converged_parity(ctx, dim, n, eps, tau):
+    say(f"EE step dim={dim} n={n}")
+    po, pg = probs(dim, n, eps)
+    y0 = uniform_field(n, dim, 0.1, 0.3, seed=100 + n)
+    y_ref, tau_ref, info = O.ee_step(y0, po, tau, 1e-8, 30)
+    assert info.converged
+    yg = dev(y0)
+    rec = ctx.step_ee(pg, yg, tau, m_max=30, tol_phi_fixed=1e-8)
+    assert rec["j"] == info.j
+    assert rec["tau"] == tau_ref
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
+@pytest.mark.parametrize("dim,n", [(2, 40), (2, 70), (3, 10)])
+def test_ee_step_trace_parity(ctx, dim, n):
+    say(f"EE trace dim={dim} n={n}")
+    po, pg = probs(dim, n, 0.05)
+    y0 = uniform_field(n, dim, 0.1, 0.05, seed=200 + n)
+    tau0 = 1e-2
+    y_ref, tau_ref, info = O.ee_step(y0, po, tau0, 1e-7, 6)
+    assert not info.converged and tau_ref < tau0
+    yg = dev(y0)
+    rec = ctx.step_ee(pg, yg, tau0, m_max=6, tol_phi_fixed=1e-7)
+    assert rec["traced"] == 1 and rec["j"] == 6
+    assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12)
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
+def test_ee_adaptive_run_parity(ctx):
+    say("EE adaptive run 48^2")
+    po, pg = probs(2, 48, 0.03)
+    y0 = uniform_field(48, 2, 0.1, 0.05, seed=301)
+    y_ref, rec_ref = O.ee_adaptive(y0, po, 1e-3, math.inf, 1e-4, 10, max_steps=25)
+    yg = dev(y0)
+    st, recs = ctx.run_ee(pg, yg, 1e-3, max_steps=25, m_max=10, tol=1e-4, records=True)
+    assert st["steps"] == 25
+    assert [r["j"] for r in recs] == rec_ref.js
+    np.testing.assert_allclose([r["tau"] for r in recs], rec_ref.taus, rtol=1e-10)
+    assert st["matvecs"] == rec_ref.matvecs
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
+def test_ee_adaptive_to_final_time(ctx):
+    say("EE adaptive run to T")
+    po, pg = probs(2, 32, 0.05)
+    y0 = uniform_field(32, 2, 0.0, 0.05, seed=302)
+    T = 2e-3
+    y_ref, rec_ref = O.ee_adaptive(y0, po, 3e-4, T, 1e-3, 20)
+    yg = dev(y0)
+    st, _ = ctx.run_ee(pg, yg, 3e-4, T=T, m_max=20, tol=1e-3)
+    assert st["t"] == T and rec_ref.t == T
+    assert st["steps"] == rec_ref.steps
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
+# --- constant-step EE2 (linear RT restarts) ------------------------------------------------
+
+def test_small_2d_constant_ee_200_steps(ctx):
+    """64^2, eps = 0.05, tau = 1e-5, 200 steps, m = 30, tol_phi = 1e-8."""
+    say("EE constant 64^2 x 200")
+    po, pg = probs(2, 64, 0.05)
+    y0 = small_2d_field(0)
+    y_ref, infos = O.ee_const_run(y0, po, 1e-5, 200, 1e-8, 30)
+    yg = dev(y0)
+    st, recs = ctx.run_ee(pg, yg, 1e-5, max_steps=200, m_max=30, tol_phi_fixed=1e-8, constant_step=True,
+                          records=True)
+    assert st["steps"] == 200
+    assert [r["j"] for r in recs] == [i.js[-1] for i in infos]
+    assert st["matvecs"] == sum(i.matvecs for i in infos)
+    assert rel(host(yg), y_ref) <= TOL_FP64
+    assert st["t"] == pytest.approx(200 * 1e-5, rel=1e-12)
+
+
+def test_constant_ee_with_restarts(ctx):
+    say("EE constant restarts")
+    po, pg = probs(2, 64, 0.05)
+    y0 = small_2d_field(0)
+    y_ref, infos = O.ee_const_run(y0, po, 1e-5, 5, 1e-8, 8)
+    assert sum(i.restarts for i in infos) > 0
+    yg = dev(y0)
+    st, recs = ctx.run_ee(pg, yg, 1e-5, max_steps=5, m_max=8, tol_phi_fixed=1e-8, constant_step=True,
+                          records=True)
+    assert st["restarts"] == sum(i.restarts for i in infos)
+    assert st["matvecs"] == sum(i.matvecs for i in infos)
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
+# --- LIM (Fig. 1, Fig. 2) ------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,eps,tau", [(2, 40, 0.05, 1e-4), (2, 130, 0.02, 1e-5), (3, 12, 0.05, 1e-4)])
+def test_lim_constant_steps_parity(ctx, dim, n, eps, tau):
+    say(f"LIM const dim={dim} n={n}")
+    po, pg = probs(dim, n, eps)
+    y0 = uniform_field(n, dim, 0.1, 0.3, seed=400 + n)
+    y_ref, ps = O.lim_const_run(y0, po, tau, 6)
+    yg = dev(y0)
+    st, recs = ctx.run_lim(pg, yg, tau, max_steps=6, records=True)
+    assert [r["j"] for r in recs] == ps
+    assert st["matvecs"] == sum(2 * p - 1 for p in ps)
+    lam = O.lambda_max(y0, po)
+    assert recs[0]["lambda_max"] == pytest.approx(lam, rel=1e-13)
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
+def test_small_2d_lim_200_steps(ctx):
+    say("LIM constant 64^2 x 200")
+    po, pg = probs(2, 64, 0.05)
+    y0 = small_2d_field(0)
+    y_ref, ps = O.lim_const_run(y0, po, 1e-5, 200)
+    yg = dev(y0)
+    st, recs = ctx.run_lim(pg, yg, 1e-5, max_steps=200, records=True)
+    assert [r["j"] for r in recs] == ps
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
+def test_lim_adaptive_parity(ctx):
+    say("LIM adaptive 48^2")
+    po, pg = probs(2, 48, 0.03)
+    y0 = uniform_field(48, 2, 0.1, 0.05, seed=501)
+    y_ref, rec_ref = O.lim_adaptive(y0, po, 1e-7, math.inf, 1e-3, max_steps=20)
+    yg = dev(y0)
+    st, recs = ctx.run_lim(pg, yg, 1e-7, max_steps=20, tol=1e-3, records=True)
+    assert [r["j"] for r in recs] == rec_ref.js
+    np.testing.assert_allclose([r["tau"] for r in recs], rec_ref.taus, rtol=1e-10)
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
+# --- Eyre splitting (eq. A_g_cs) ------------------------------------------------------------
+
+def test_eyre_ee_and_lim(ctx):
+    say("Eyre EE/LIM")
+    po, pg = probs(2, 40, 0.05, eyre=True)
+    y0 = uniform_field(40, 2, 0.0, 0.5, seed=601)
+    y_ref, tau_ref, info = O.ee_step(y0, po, 5e-5, 1e-8, 30)
+    yg = dev(y0)
+    rec = ctx.step_ee(pg, yg, 5e-5, m_max=30, tol_phi_fixed=1e-8)
+    assert rec["j"] == info.j
+    assert rel(host(yg), y_ref) <= TOL_FP64
+    y_ref2, ps = O.lim_const_run(y0, po, 1e-4, 3)
+    yg2 = dev(y0)
+    _, recs = ctx.run_lim(pg, yg2, 1e-4, max_steps=3, records=True)
+    assert [r["j"] for r in recs] == ps
+    assert rel(host(yg2), y_ref2) <= TOL_FP64
+
+
+# --- phi action (eq. yt) ---------------------------------------------------------------------
+
+def test_phiv_shrink_and_restart(ctx):
+    say("phiv modes")
+    import torch
+
+    po, pg = probs(2, 40, 0.05)
+    y0 = uniform_field(40, 2, 0.1, 0.05, seed=701)
+    g = O.ghat(y0, po)
+    mv = lambda v: O.ahat_mv(v, y0, po)
+    tau0 = 2e-3
+    ref_s, tau_s, info_s = O.krylov_phi_cycle(mv, y0, g - mv(y0), tau0, 1e-8, 8)
+    yg = dev(y0)
+    out = torch.empty_like(yg)
+    rec = ctx.phiv(pg, yg, out, tau0, mode=ch.CH_PHI_SHRINK, tol_phi=1e-8, m_max=8)
+    assert rec["tau"] == pytest.approx(tau_s, rel=1e-12)
+    assert rel(host(out), ref_s) <= TOL_FP64
+    assert np.array_equal(host(yg), y0)
+    ref_r, info_r = O.ee_step_const(y0, po, tau0, 1e-8, 8)
+    rec = ctx.phiv(pg, yg, out, tau0, mode=ch.CH_PHI_RESTART, tol_phi=1e-8, m_max=8)
+    assert rec["cycles"] == info_r.restarts + 1
+    assert rec["tau"] == pytest.approx(tau0, rel=1e-14)
+    assert rel(host(out), ref_r) <= TOL_FP64
+
+
+# --- edge cases -----------------------------------------------------------------------------
+
+def test_constant_field_is_a_fixed_point(ctx):
+    say("edge: constant field")
+    _, pg = probs(2, 32, 0.05)
+    y0 = np.full(32 * 32, 0.5)
+    yg = dev(y0)
+    st, recs = ctx.run_ee(pg, yg, 1e-3, max_steps=3, m_max=10, tol=1e-4, records=True)
+    assert st["steps"] == 3 and all(r["j"] == 0 for r in recs)
+    assert np.array_equal(host(yg), y0)
+
+
+def test_nonfinite_input_rejected_and_field_kept(ctx):
+    say("edge: NaN input")
+    _, pg = probs(2, 32, 0.05)
+    y0 = uniform_field(32, 2, 0.0, 0.05, seed=9)
+    y0[100] = np.nan
+    yg = dev(y0)
+    st, _ = ctx.run_ee(pg, yg, 1e-5, max_steps=2, m_max=10, tol=1e-4, raise_on_error=False)
+    assert st["rc"] == ch.CH_ENONFINITE and st["steps"] == 0
+    assert np.array_equal(host(yg), y0, equal_nan=True)
+    st, _ = ctx.run_lim(pg, yg, 1e-5, max_steps=2, raise_on_error=False)
+    assert st["rc"] == ch.CH_ENONFINITE and st["steps"] == 0
+
+
+def test_invalid_arguments(ctx):
+    say("edge: invalid arguments")
+    yg = dev(np.zeros(16))
+    with pytest.raises(ch.ChError) as e:
+        ctx.run_ee(ch.Problem(2, 4, 0.05), yg, 1e-5, max_steps=1)
+    assert e.value.status == ch.CH_EINVAL
+    yg = dev(np.zeros(64 * 64))
+    for kw in ({"m_max": 0}, {"m_max": ch.CH_MMAX + 1}):
+        with pytest.raises(ch.ChError) as e:
+            ctx.run_ee(ch.Problem(2, 64, 0.05), yg, 1e-5, max_steps=1, **kw)
+        assert e.value.status == ch.CH_EINVAL
+    with pytest.raises(ch.ChError) as e:
+        ctx.run_ee(ch.Problem(2, 64, -1.0), yg, 1e-5, max_steps=1)
+    assert e.value.status == ch.CH_EINVAL
+
+
+def test_tau_underflow(ctx):
+    say("edge: tau underflow")
+    _, pg = probs(2, 40, 0.05)
+    y0 = uniform_field(40, 2, 0.1, 0.05, seed=11)
+    yg = dev(y0)
+    st, _ = ctx.run_ee(pg, yg, 1e-2, max_steps=1, m_max=3, tol_phi_fixed=1e-7, tau_min=1e-3,
+                       raise_on_error=False)
+    assert st["rc"] == ch.CH_ETAU_UNDERFLOW and st["steps"] == 0
+    assert np.array_equal(host(yg), y0)
+
+
+def test_deterministic_repeat(ctx):
+    say("determinism")
+    _, pg = probs(2, 130, 0.02)
+    y0 = uniform_field(130, 2, 0.1, 0.05, seed=12)
+    a, b = dev(y0), dev(y0)
+    ctx.run_ee(pg, a, 1e-4, max_steps=3, m_max=12, tol=1e-4)
+    ctx.run_ee(pg, b, 1e-4, max_steps=3, m_max=12, tol=1e-4)
+    assert np.array_equal(host(a), host(b))
+
+
+def test_mass_conserved_on_gpu(ctx):
+    say("mass")
+    _, pg = probs(2, 130, 0.02)
+    y0 = uniform_field(130, 2, 0.1, 0.05, seed=13)
+    yg = dev(y0)
+    ctx.run_ee(pg, yg, 1e-4, max_steps=10, m_max=20, tol=1e-4)
+    assert abs(host(yg).sum() - y0.sum()) <= 1e-12 * np.abs(y0).sum()
+    yl = dev(y0)
+    ctx.run_lim(pg, yl, 1e-7, max_steps=10, tol=1e-4)
+    assert abs(host(yl).sum() - y0.sum()) <= 1e-12 * np.abs(y0).sum()
