@@ -154,6 +154,24 @@ enum ch_phi_mode {
 int ch_phiv(ch_ctx *ctx, const ch_problem *prob, const double *y, double *y_out, double tau0,
             int mode, double tol_phi, int m_max, ch_step_record *out);
 
+enum ch_kernel {
+    CH_KERNEL_MGS = 0,      /* one modified Gram-Schmidt pass (axpy + next dot) over the grid */
+    CH_KERNEL_MATVEC = 1,   /* one fused Jacobian matvec Ahat v with its first dot */
+    CH_KERNEL_PHI = 2       /* one small-matrix phi evaluation of the last step's H (no trace) */
+};
+
+/*
+ * Measurement aid for the roofline figures: average duration in microseconds
+ * of `reps` back-to-back launches of one kernel of the EE2 path, bracketed by
+ * HIP events on the context's stream, on the workspace of the last ch_run_ee
+ * call (same problem, precision and Krylov dimension m_max >= 2 are required).
+ * *bytes receives the algorithmic bytes one launch must move (each operand
+ * vector read or written once).  Overwrites basis columns 1-2 and the control
+ * block; a later run re-initialises both.
+ */
+int ch_time_kernel(ch_ctx *ctx, const ch_problem *prob, int kernel, int m_max, int reps,
+                   double *avg_us, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,8 +22,9 @@ CH_PMAX = 4096
 
 EXPORTED = (
     "ch_create", "ch_destroy", "ch_strerror", "ch_last_error_message",
-    "ch_run_ee", "ch_step_ee", "ch_run_lim", "ch_step_lim", "ch_phiv",
+    "ch_run_ee", "ch_step_ee", "ch_run_lim", "ch_step_lim", "ch_phiv", "ch_time_kernel",
 )
+CH_KERNEL_MGS, CH_KERNEL_MATVEC, CH_KERNEL_PHI = 0, 1, 2
 
 
 class ChProblem(ctypes.Structure):
@@ -86,7 +87,9 @@ def load_library(path: str = LIB_PATH):
                                 P(ChStepRecord)]
     lib.ch_phiv.argtypes = [c_void_p, P(ChProblem), c_void_p, c_void_p, c_double, c_int, c_double, c_int,
                             P(ChStepRecord)]
-    for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_lim", "ch_step_lim", "ch_phiv"):
+    lib.ch_time_kernel.argtypes = [c_void_p, P(ChProblem), c_int, c_int, c_int, P(c_double), P(c_double)]
+    for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_lim", "ch_step_lim", "ch_phiv",
+                 "ch_time_kernel"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -223,3 +226,12 @@ class Context:
                               float(tau0), int(mode), float(tol_phi), int(m_max), byref(rec))
         self._raise(rc, "ch_phiv")
         return rec.as_dict()
+
+    # -- measurement aid -----------------------------------------------------
+    def time_kernel(self, prob: Problem, kernel: int, m_max: int, reps: int = 50):
+        """(average microseconds per launch, algorithmic bytes per launch) of one EE2 kernel."""
+        us, by = c_double(), c_double()
+        pb = prob.c()
+        rc = self.lib.ch_time_kernel(self._ptr, byref(pb), int(kernel), int(m_max), int(reps), byref(us), byref(by))
+        self._raise(rc, "ch_time_kernel")
+        return us.value, by.value

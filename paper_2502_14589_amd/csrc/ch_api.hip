@@ -402,4 +402,65 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     return ctx->hctl->status;
 }
 
+int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, int reps, double* avg_us,
+                   double* bytes) {
+    if (!ctx || !avg_us || !bytes || reps < 1) return CH_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
+    Grid g;
+    int rc = check_problem(prob, &g);
+    if (rc) return rc;
+    if (m_max < 2 || m_max > CH_MMAX) return CH_EINVAL;
+    const int prec = prob->prec;
+    const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
+    const DevBuffers& b = ctx->b;
+    if (!b.ctl || ctx->state_n < (size_t)g.N || ctx->v_bytes < (size_t)(m_max + 1) * b.ldv * esz ||
+        b.ldv < (size_t)g.N || (prec == CH_FP32_MIXED && ctx->y32_n < (size_t)g.N))
+        return CH_EINVAL;   // no run on this problem yet
+    // Control block: live, coefficients of a no-op axpy, unit scales.
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl, b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    Ctl& h = *ctx->hctl;
+    const int jlast = h.j;
+    h.done = 0;
+    h.halted = 0;
+    h.ticket[0] = 0;
+    h.coef[0] = 0.0;
+    h.vscale[0] = h.vscale[1] = h.vscale[2] = 1.0;
+    h.tol_phi = 1.0;   // phi timing: the convergence branch, no trace
+    HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+    const double* y = b.ybuf[0];
+    auto launch = [&]() -> hipError_t {
+        switch (kernel) {
+            case CH_KERNEL_MGS: return launch_mgs_pass(g, prec, b, 1, 1, ctx->stream);
+            case CH_KERNEL_MATVEC: return launch_matvec(g, prec, b, y, 0, ctx->stream);
+            default: return launch_phi(b, jlast > 0 ? jlast - 1 : 0, ctx->stream);
+        }
+    };
+    if (kernel != CH_KERNEL_MGS && kernel != CH_KERNEL_MATVEC && kernel != CH_KERNEL_PHI) return CH_EINVAL;
+    if (kernel == CH_KERNEL_PHI && jlast < 1) return CH_EINVAL;
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    HIP_TRY(ctx, launch());   // warm
+    HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+    for (int r = 0; r < reps; ++r) {
+        if (kernel == CH_KERNEL_PHI)   // phi sets `done`; re-arm it between launches
+            HIP_TRY(ctx, hipMemsetAsync(&b.ctl->done, 0, sizeof(int), ctx->stream));
+        HIP_TRY(ctx, launch());
+    }
+    HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+    HIP_TRY(ctx, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_us = 1000.0 * ms / reps;
+    const double N = double(g.N);
+    const double ysz = prec == CH_FP64 ? 8.0 : 4.0;
+    if (kernel == CH_KERNEL_MGS) *bytes = 4.0 * esz * N;                 // read w, v_{i-1}, v_i; write w
+    else if (kernel == CH_KERNEL_MATVEC) *bytes = (3.0 * esz + ysz) * N; // read v_k, y, v_1; write w
+    else *bytes = 0.0;
+    return CH_OK;
+}
+
 }  // extern "C"

@@ -71,6 +71,8 @@ hipError_t launch_cycle_begin(const DevBuffers& b, hipStream_t s);
 hipError_t launch_after_resid(const DevBuffers& b, hipStream_t s);
 hipError_t launch_matvec(const Grid& g, int prec, const DevBuffers& b, const double* y, int k, hipStream_t s);
 hipError_t launch_arnoldi(const Grid& g, int prec, const DevBuffers& b, const double* y, int m_max, hipStream_t s);
+hipError_t launch_mgs_pass(const Grid& g, int prec, const DevBuffers& b, int k, int i, hipStream_t s);
+hipError_t launch_phi(const DevBuffers& b, int k, hipStream_t s);
 hipError_t launch_update(const Grid& g, int prec, const DevBuffers& b, const double* y, double* ynew, hipStream_t s);
 hipError_t launch_est_ee(const Grid& g, int prec, const DevBuffers& b, const double* y0, const double* y1,
                          hipStream_t s);

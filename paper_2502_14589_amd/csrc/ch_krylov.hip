@@ -580,6 +580,26 @@ hipError_t launch_arnoldi(const Grid& g, int prec, const DevBuffers& b, const do
                            : launch_arnoldi_t<float>(g, prec, b, y, m_max, s);
 }
 
+hipError_t launch_mgs_pass(const Grid& g, int prec, const DevBuffers& b, int k, int i, hipStream_t s) {
+    if (prec == CH_FP64) {
+        double* V = static_cast<double*>(b.V);
+        hipLaunchKernelGGL((k_mgs<double, false>), dim3(stream_grid(g.N, 2)), dim3(CH_BLOCK), 0, s, b.ctl,
+                           V + (size_t)(k + 1) * b.ldv, V + (size_t)(i - 1) * b.ldv, V + (size_t)i * b.ldv, k, i,
+                           g.N, b.part);
+    } else {
+        float* V = static_cast<float*>(b.V);
+        hipLaunchKernelGGL((k_mgs<float, false>), dim3(stream_grid(g.N, 4)), dim3(CH_BLOCK), 0, s, b.ctl,
+                           V + (size_t)(k + 1) * b.ldv, V + (size_t)(i - 1) * b.ldv, V + (size_t)i * b.ldv, k, i,
+                           g.N, b.part);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_phi(const DevBuffers& b, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_phi, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, k);
+    return hipGetLastError();
+}
+
 hipError_t launch_update(const Grid& g, int prec, const DevBuffers& b, const double* y, double* ynew,
                          hipStream_t s) {
     const int G = stream_grid(g.N, 2);
