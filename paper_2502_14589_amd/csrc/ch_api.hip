@@ -26,6 +26,8 @@ struct ch_ctx {
     size_t y32_n = 0;
     size_t z_n = 0;
     int rec_cap = 0;
+    int cycle_id = 0;        // id of the last issued Krylov cycle
+    int* hflag = nullptr;    // pinned, device-mapped: last finished cycle id
     Ctl* hctl = nullptr;     // pinned mirror of the control block
     std::string err;
 };
@@ -82,8 +84,12 @@ int ensure(ch_ctx* ctx, long long N, int m_max, int prec, int recs, bool need_z)
     int rc;
     if (!b.ctl) {
         if ((rc = alloc_dev(ctx, (void**)&b.ctl, sizeof(Ctl)))) return rc;
-        if ((rc = alloc_dev(ctx, (void**)&b.part, sizeof(double) * CH_NRED * CH_MAXB))) return rc;
+        if ((rc = alloc_dev(ctx, (void**)&b.part, 2 * sizeof(double) * CH_NRED * CH_MAXB))) return rc;
         HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hctl, sizeof(Ctl), hipHostMallocDefault));
+        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, 64, hipHostMallocMapped | hipHostMallocCoherent));
+        *ctx->hflag = -1;
+        HIP_TRY(ctx, hipHostGetDevicePointer((void**)&b.dflag, ctx->hflag, 0));
+        b.hflag = ctx->hflag;
     }
     if ((size_t)N > ctx->state_n) {
         free_dev(b.ybuf[0]);
@@ -159,7 +165,7 @@ int read_head(ch_ctx* ctx) {
 // Remaining Krylov cycles of a constant step (linear RT restarts, reading in
 // the oracle's header): re-start from the current sub-step state `z` with the
 // residual of the frozen problem, until a cycle converges on the rest of tau.
-int restart_cycles(ch_ctx* ctx, const Grid& g, int prec, const double* y, double* z, int m_max) {
+int restart_cycles(ch_ctx* ctx, const Grid& g, int prec, PartSeq& ps, const double* y, double* z, int m_max) {
     const DevBuffers& b = ctx->b;
     for (int cyc = 0; cyc < 100000; ++cyc) {
         int rc = read_head(ctx);
@@ -167,9 +173,9 @@ int restart_cycles(ch_ctx* ctx, const Grid& g, int prec, const double* y, double
         const Ctl& h = *ctx->hctl;
         if (h.halted || h.converged) return CH_OK;
         HIP_TRY(ctx, launch_cycle_begin(b, ctx->stream));
-        HIP_TRY(ctx, launch_resid(g, prec, b, y, z, false, false, ctx->stream));
-        HIP_TRY(ctx, launch_after_resid(b, ctx->stream));
-        HIP_TRY(ctx, launch_arnoldi(g, prec, b, y, m_max, ctx->stream));
+        HIP_TRY(ctx, launch_resid(g, prec, b, ps, y, z, false, false, ctx->stream));
+        HIP_TRY(ctx, launch_after_resid(b, ps, false, ctx->stream));
+        HIP_TRY(ctx, launch_arnoldi(g, prec, b, ps, y, m_max, ++ctx->cycle_id, ctx->stream));
         HIP_TRY(ctx, launch_update(g, prec, b, z, z, ctx->stream));
     }
     ctx->err = "restart cycle limit reached";
@@ -221,16 +227,19 @@ int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t
              opts->tau_min, opts->m_max, recs);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(b.ybuf[0], y, sizeof(double) * g.N, hipMemcpyDeviceToDevice, ctx->stream));
-    HIP_TRY(ctx, launch_resid(g, prec, b, b.ybuf[0], b.ybuf[0], true, true, ctx->stream));
+    PartSeq ps;
+    ps.base = b.part;
+    HIP_TRY(ctx, launch_resid(g, prec, b, ps, b.ybuf[0], b.ybuf[0], true, true, ctx->stream));
+    HIP_TRY(ctx, launch_after_resid(b, ps, true, ctx->stream));
     for (long long s = 0;; ++s) {
         if (max_steps > 0 && s >= max_steps) break;
         const double* yin = b.ybuf[s & 1];
         double* yout = b.ybuf[(s + 1) & 1];
-        HIP_TRY(ctx, launch_begin_step(b, ctx->stream));
-        HIP_TRY(ctx, launch_arnoldi(g, prec, b, yin, opts->m_max, ctx->stream));
+        HIP_TRY(ctx, launch_arnoldi(g, prec, b, ps, yin, opts->m_max, ++ctx->cycle_id, ctx->stream));
         HIP_TRY(ctx, launch_update(g, prec, b, yin, yout, ctx->stream));
-        if (constant && (rc = restart_cycles(ctx, g, prec, yin, yout, opts->m_max))) return rc;
-        HIP_TRY(ctx, launch_est_ee(g, prec, b, yin, yout, ctx->stream));
+        if (constant && (rc = restart_cycles(ctx, g, prec, ps, yin, yout, opts->m_max))) return rc;
+        HIP_TRY(ctx, launch_est_ee(g, prec, b, ps, yin, yout, ctx->stream));
+        HIP_TRY(ctx, launch_step_end(b, ps, true, ctx->stream));
         if (max_steps <= 0 && (s % 16) == 15) {
             if ((rc = read_head(ctx))) return rc;
             if (ctx->hctl->halted) break;
@@ -252,11 +261,14 @@ int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double 
     init_ctl(ctx->hctl, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, t0, tau0, T, tol, 0.0, 0.0, 0, recs);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(b.ybuf[0], y, sizeof(double) * g.N, hipMemcpyDeviceToDevice, ctx->stream));
+    PartSeq ps;
+    ps.base = b.part;
     for (long long s = 0;; ++s) {
         if (max_steps > 0 && s >= max_steps) break;
         const double* yin = b.ybuf[s & 1];
         double* yout = b.ybuf[(s + 1) & 1];
-        HIP_TRY(ctx, launch_lim_begin(g, b, yin, ctx->stream));
+        HIP_TRY(ctx, launch_lim_begin(g, b, ps, yin, ctx->stream));
+        HIP_TRY(ctx, launch_lim_plan(g, b, ps, ctx->stream));
         if ((rc = read_head(ctx))) return rc;
         if (ctx->hctl->halted) break;
         const int p = ctx->hctl->p;
@@ -270,7 +282,8 @@ int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double 
             HIP_TRY(ctx, launch_lim_stage(g, b, yin, src, dst, m, ctx->stream));
             src = dst;
         }
-        HIP_TRY(ctx, launch_est_lim(g, b, yin, yout, ctx->stream));
+        HIP_TRY(ctx, launch_est_lim(g, b, ps, yin, yout, ctx->stream));
+        HIP_TRY(ctx, launch_lim_end(b, ps, ctx->stream));
     }
     return finish_run(ctx, g.N, y, stats, records, recs);
 }
@@ -323,6 +336,7 @@ int ch_destroy(ch_ctx* ctx) {
                     (void*)b.part, (void*)b.ctl, (void*)b.rec})
         free_dev(p);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
+    if (ctx->hflag) (void)hipHostFree(ctx->hflag);
     delete ctx;
     return CH_OK;
 }
@@ -392,11 +406,13 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     const DevBuffers& b = ctx->b;
     init_ctl(ctx->hctl, MODE_PHI, 0.0, tau0, INFINITY, 0.0, tol_phi, 0.0, m_max, 0);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, launch_resid(g, prec, b, y, y, false, true, ctx->stream));
-    HIP_TRY(ctx, launch_begin_step(b, ctx->stream));
-    HIP_TRY(ctx, launch_arnoldi(g, prec, b, y, m_max, ctx->stream));
+    PartSeq ps;
+    ps.base = b.part;
+    HIP_TRY(ctx, launch_resid(g, prec, b, ps, y, y, false, true, ctx->stream));
+    HIP_TRY(ctx, launch_after_resid(b, ps, true, ctx->stream));
+    HIP_TRY(ctx, launch_arnoldi(g, prec, b, ps, y, m_max, ++ctx->cycle_id, ctx->stream));
     HIP_TRY(ctx, launch_update(g, prec, b, y, y_out, ctx->stream));
-    if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, g, prec, y, y_out, m_max))) return rc;
+    if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, g, prec, ps, y, y_out, m_max))) return rc;
     if ((rc = read_head(ctx))) return rc;
     record_from_head(*ctx->hctl, out);
     return ctx->hctl->status;
@@ -420,20 +436,24 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl, b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     Ctl& h = *ctx->hctl;
-    const int jlast = h.j;
+    const int jlast = h.last_j;
     h.done = 0;
     h.halted = 0;
-    h.ticket[0] = 0;
-    h.coef[0] = 0.0;
     h.vscale[0] = h.vscale[1] = h.vscale[2] = 1.0;
     h.tol_phi = 1.0;   // phi timing: the convergence branch, no trace
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+    // partials slots: zeros in, so the timed axpy coefficient is 0 and the phi
+    // kernel sees h_{j+1,j} = 0 (its convergence branch)
+    HIP_TRY(ctx, hipMemsetAsync(b.part, 0, 2 * sizeof(double) * CH_NRED * CH_MAXB, ctx->stream));
     const double* y = b.ybuf[0];
     auto launch = [&]() -> hipError_t {
+        PartSeq ps;
+        ps.base = b.part;
+        ps.np = 1;
         switch (kernel) {
-            case CH_KERNEL_MGS: return launch_mgs_pass(g, prec, b, 1, 1, ctx->stream);
-            case CH_KERNEL_MATVEC: return launch_matvec(g, prec, b, y, 0, ctx->stream);
-            default: return launch_phi(b, jlast > 0 ? jlast - 1 : 0, ctx->stream);
+            case CH_KERNEL_MGS: return launch_mgs_pass(g, prec, b, ps, 1, 1, ctx->stream);
+            case CH_KERNEL_MATVEC: return launch_matvec(g, prec, b, ps, y, 0, ctx->stream);
+            default: return launch_phi(b, ps, jlast > 0 ? jlast - 1 : 0, -2, ctx->stream);
         }
     };
     if (kernel != CH_KERNEL_MGS && kernel != CH_KERNEL_MATVEC && kernel != CH_KERNEL_PHI) return CH_EINVAL;

@@ -6,9 +6,8 @@
 
 // ---------------------------------------------------------------------------
 // Reductions.  Wave64 butterfly, then the waves of a workgroup through LDS,
-// then one partial per workgroup in global memory; the last workgroup to
-// arrive (atomic ticket) adds the partials in a fixed order, so the result
-// does not depend on scheduling.
+// then one partial per workgroup in global memory, added up in a fixed order
+// by the consuming launch (below), so results do not depend on scheduling.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -75,43 +74,43 @@ __device__ __forceinline__ void block_reduce(double (&x)[NR], double (*lds)[NR])
     __syncthreads();
 }
 
-// Grid-wide reduction with the last-workgroup finalisation.  Every workgroup
-// of the launch must call it exactly once.  Returns true in thread 0 of the
-// last workgroup, with the totals in `tot`; the ticket is re-armed there.
+// Grid-wide reductions without atomics or fences.  A producing launch writes
+// one partial per workgroup (and per sum) into a partials slot; the launch
+// that consumes them -- the next one on the stream, so the kernel boundary
+// orders and publishes the writes -- sums the partials in a fixed order in
+// every workgroup.  Deterministic: each consumer workgroup sees the same total.
+// Slots alternate between consecutive producers (ping-pong), so a consumer
+// never overwrites the partials it is still reading.
 template <int NR, int OP>
-__device__ bool grid_reduce(double (&x)[NR], double* __restrict__ part, unsigned int* ticket,
-                            double (&tot)[NR]) {
+__device__ __forceinline__ void write_partials(double (&x)[NR], double* __restrict__ pout) {
     __shared__ double lds[16][NR];
-    __shared__ int is_last;
     block_reduce<NR, OP>(x, lds);
-    const unsigned int nb = gridDim.x;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            __hip_atomic_store(&part[r * CH_MAXB + blockIdx.x], x[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned int t = atomicAdd(ticket, 1u);
-        is_last = (t == nb - 1);
+        for (int r = 0; r < NR; ++r) pout[r * CH_MAXB + blockIdx.x] = x[r];
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
+}
+
+// Total of the `np` partials of each of the NR sums, returned in every thread.
+template <int NR, int OP>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ pin, int np, double (&tot)[NR]) {
+    __shared__ double lds[16][NR];
+    __shared__ double res[NR];
     double s[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) s[r] = red_identity<OP>();
-    for (unsigned int b = threadIdx.x; b < nb; b += blockDim.x) {
+    for (int b = threadIdx.x; b < np; b += blockDim.x) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-            s[r] = red_combine<OP>(
-                s[r], __hip_atomic_load(&part[r * CH_MAXB + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        for (int r = 0; r < NR; ++r) s[r] = red_combine<OP>(s[r], pin[r * CH_MAXB + b]);
     }
     block_reduce<NR, OP>(s, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) tot[r] = s[r];
-        *ticket = 0u;
+        for (int r = 0; r < NR; ++r) res[r] = s[r];
     }
-    return threadIdx.x == 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) tot[r] = res[r];
 }
 
 // ---------------------------------------------------------------------------

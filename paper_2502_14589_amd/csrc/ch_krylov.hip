@@ -16,17 +16,24 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // MGS pass i of Arnoldi iteration k (0-based columns):
-//   w -= h_{i-1,k} v_{i-1};  then  h_{i,k} = <w, v_i>  (or ||w|| when FINAL).
+//   h_{i-1,k} = <w, v_{i-1}> from the previous launch's partials;
+//   w -= h_{i-1,k} v_{i-1};  partials of <w, v_i>  (or of ||w||^2 when FINAL).
 // FP64 accumulation of the dot products in both precisions.
 // ---------------------------------------------------------------------------
 template <typename TV, bool FINAL>
 __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctl, TV* __restrict__ W,
                                                   const TV* __restrict__ Vp, const TV* __restrict__ Vn, int k,
-                                                  int i, long long N, double* __restrict__ part) {
+                                                  int i, long long N, const double* __restrict__ pin, int nin,
+                                                  double* __restrict__ pout) {
     if (ctl->done | ctl->halted) return;
     using VT = typename Vec16<TV>::type;
     constexpr int VW = Vec16<TV>::W;
-    const TV c = TV(ctl->coef[i - 1]);
+    double dot[1];
+    sum_partials<1, RED_SUM>(pin, nin, dot);
+    const double sp = ctl->vscale[i - 1];
+    const double h = sp * dot[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->H[(i - 1) + k * CH_LDH] = h;
+    const TV c = TV(sp * h);
     double acc = 0.0;
     const long long NV = N / VW;
     VT* W4 = reinterpret_cast<VT*>(W);
@@ -56,18 +63,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctl, TV* __r
         W[q] = w;
         acc += FINAL ? double(w) * double(w) : double(w) * double(Vn[q]);
     }
-    double x[1] = {acc}, tot[1];
-    if (grid_reduce<1, RED_SUM>(x, part, &ctl->ticket[0], tot)) {
-        if (FINAL) {
-            const double h = sqrt(tot[0]);
-            ctl->H[(k + 1) + k * CH_LDH] = h;
-            ctl->vscale[k + 1] = h > 0.0 ? 1.0 / h : 0.0;
-        } else {
-            const double h = ctl->vscale[i] * tot[0];
-            ctl->H[i + k * CH_LDH] = h;
-            ctl->coef[i] = ctl->vscale[i] * h;
-        }
-    }
+    double x[1] = {acc};
+    write_partials<1, RED_SUM>(x, pout);
 }
 
 // ---------------------------------------------------------------------------
@@ -281,9 +278,18 @@ __device__ void store_u(Ctl* ctl, const double* E, int j) {
 // h_{j+1,j} |e_j^T exp(-s H) e_1| from the same exponential, safeguarded by the
 // bracket, to a relative precision of about 1e-14.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctl, int k) {
+__global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctl, int k, const double* __restrict__ pin,
+                                                  int nin, int cycle_id, int* __restrict__ dflag) {
     if (ctl->done | ctl->halted) return;
     __shared__ PhiShared S;
+    // h_{k+2,k+1} = ||w|| from the final Gram-Schmidt pass (Fig. 3, line 9)
+    double nrm2[1];
+    sum_partials<1, RED_SUM>(pin, nin, nrm2);
+    const double hnext = sqrt(nrm2[0]);
+    if (threadIdx.x == 0) {
+        ctl->H[(k + 1) + k * CH_LDH] = hnext;
+        ctl->vscale[k + 1] = hnext > 0.0 ? 1.0 / hnext : 0.0;
+    }
     if (threadIdx.x == 0) {
         // [13/13] Pade coefficients of exp: c_0 = 1, c_{i+1} = c_i (13 - i) / ((26 - i)(i + 1))
         double c = 1.0;
@@ -294,9 +300,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctl, int k) 
         }
     }
     __syncthreads();
+    __syncthreads();   // H column k complete (written by the Gram-Schmidt launches and above)
     const int j = k + 1;
     const double* H = ctl->H;
-    const double hnext = H[j + k * CH_LDH];
     const double tau0 = ctl->tau0, tol = ctl->tol_phi;
     int nsq = 0;
     const double* E = expm_aug(S, H, j, tau0, hnext, &nsq);
@@ -306,6 +312,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctl, int k) 
             ctl->status = CH_ENONFINITE;
             ctl->halted = 1;
             ctl->done = 1;
+            if (dflag) *dflag = cycle_id;
             ctl->j = 0;
         }
         return;
@@ -317,6 +324,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctl, int k) 
             ctl->resnorm = res0;
             ctl->converged = 1;
             ctl->done = 1;
+            if (dflag) *dflag = cycle_id;
             ctl->j = j;
         }
         return;
@@ -366,6 +374,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctl, int k) 
             ctl->status = CH_ETAU_UNDERFLOW;
             ctl->halted = 1;
             ctl->done = 1;
+            if (dflag) *dflag = cycle_id;
             ctl->j = 0;
         }
         return;
@@ -410,15 +419,16 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctl, int k) 
         ctl->converged = 0;
         ctl->traced = 1;
         ctl->done = 1;
+            if (dflag) *dflag = cycle_id;
         ctl->j = j;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Step begin (Fig. 4, lines 3-7): final-time clip, tol_phi (eq. tol_phi).
+// Step begin (Fig. 4, lines 3-7): final-time clip and tol_phi (eq. tol_phi).
 // ---------------------------------------------------------------------------
-__global__ void k_begin_step(Ctl* __restrict__ ctl) {
-    if (threadIdx.x != 0 || ctl->halted) return;
+__device__ void begin_step(Ctl* ctl) {
+    if (ctl->halted) return;
     if (!(ctl->t < ctl->T)) {
         ctl->halted = 1;
         return;
@@ -454,6 +464,34 @@ __global__ void k_begin_step(Ctl* __restrict__ ctl) {
     }
 }
 
+// After a residual start vector: beta = ||v_1||, ||ghat||; then either the
+// begin of a step or (restart cycles) the normalisation of the new start.
+__global__ __launch_bounds__(CH_BLOCK) void k_after_resid(Ctl* __restrict__ ctl, const double* __restrict__ pin,
+                                                          int nin, int begin) {
+    if (ctl->halted) return;
+    double tot[2];
+    sum_partials<2, RED_SUM>(pin, nin, tot);
+    if (threadIdx.x != 0) return;
+    const double beta = sqrt(tot[0]), gn = sqrt(tot[1]);
+    if (!(beta < __builtin_inf()) || !(gn < __builtin_inf())) {
+        ctl->status = CH_ENONFINITE;
+        ctl->halted = 1;
+        return;
+    }
+    ctl->beta = beta;
+    if (begin) {
+        ctl->gnorm = gn;
+        begin_step(ctl);
+        return;
+    }
+    ctl->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+    if (beta == 0.0) {
+        ctl->done = 1;
+        ctl->converged = 1;
+        ctl->tau_acc = ctl->tau0;
+    }
+}
+
 // Between linear RT restart cycles of a constant step: account for the cycle
 // just finished and aim the next one at the remaining time.
 __global__ void k_cycle_begin(Ctl* __restrict__ ctl) {
@@ -469,28 +507,74 @@ __global__ void k_cycle_begin(Ctl* __restrict__ ctl) {
     ctl->traced = 0;
 }
 
-// After a residual start vector: its normalisation, and the trivial cycle.
-__global__ void k_after_resid(Ctl* __restrict__ ctl) {
-    if (threadIdx.x != 0 || ctl->halted) return;
-    ctl->vscale[0] = ctl->beta > 0.0 ? 1.0 / ctl->beta : 0.0;
-    if (ctl->beta == 0.0) {
-        ctl->done = 1;
-        ctl->converged = 1;
-        ctl->tau_acc = ctl->tau0;
+// ---------------------------------------------------------------------------
+// EE2 step end (Fig. 4, lines 8-10): est (eq. LIMest), t, tau_new (eq. EEdt);
+// optionally the begin of the next step.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(CH_BLOCK) void k_step_end(Ctl* __restrict__ ctl, const double* __restrict__ pin, int nin,
+                                                       ch_step_record* __restrict__ rec, int begin_next) {
+    if (ctl->halted) return;
+    double tot[4];
+    sum_partials<4, RED_SUM>(pin, nin, tot);
+    if (threadIdx.x != 0) return;
+    const double num = sqrt(tot[0]), den = sqrt(tot[1]);
+    const double est = den > 0.0 ? num / den : 0.0;
+    const double beta = sqrt(tot[2]), gn = sqrt(tot[3]);
+    if (!(est < __builtin_inf()) || !(beta < __builtin_inf()) || !(gn < __builtin_inf())) {
+        ctl->status = CH_ENONFINITE;
+        ctl->halted = 1;
+        return;
     }
+    const bool constant = ctl->mode != MODE_EE;
+    const double tau_used = constant ? ctl->tau_step : ctl->tau_acc;
+    // the final-time clip lands exactly on T when the clipped step was taken in full
+    const double t_new = (ctl->clipped && ctl->converged) ? ctl->T : ctl->t + tau_used;
+    double tau_next;
+    if (constant) {
+        tau_next = ctl->tau_fixed;
+    } else {
+        const double grow = 1.25 * tau_used;   // eq. EEdt
+        tau_next = est == 0.0 ? grow : fmin(grow, sqrt(ctl->tol / est) * tau_used);
+    }
+    const int mv = ctl->mv_step + 1 + ctl->j;
+    ctl->last_j = ctl->j;
+    if (ctl->steps < ctl->rec_cap) {
+        ch_step_record& r = rec[ctl->steps];
+        r.t = t_new;
+        r.tau = tau_used;
+        r.tau_next = tau_next;
+        r.est = est;
+        r.tol_phi = ctl->tol_phi;
+        r.beta = ctl->beta;
+        r.resnorm = ctl->resnorm;
+        r.lambda_max = 0.0;
+        r.j = ctl->j;
+        r.cycles = ctl->cycles;
+        r.traced = ctl->traced;
+        r.matvecs = mv;
+    }
+    ctl->est = est;
+    ctl->t = t_new;
+    ctl->tau = tau_next;
+    ctl->beta = beta;
+    ctl->gnorm = gn;
+    ctl->matvecs += mv;
+    ctl->traces += ctl->traced;
+    ctl->steps += 1;
+    ctl->cur ^= 1;
+    if (!(t_new < ctl->T)) {
+        ctl->halted = 1;
+        return;
+    }
+    if (begin_next) begin_step(ctl);
 }
 
 // ---------------------------------------------------------------------------
-// LIM step begin (Fig. 1, steps 1-2; Fig. 2, lines 3-5): final-time clip,
-// lambda_max = ||Ahat_n||_1 and p (eq. p).  Column j of Ahat_n is
-// d_j A e_j + eps^2 A^2 e_j; its absolute sum g(d_j) is convex and piecewise
-// linear in d_j, so the largest column sum is max(g(d_min), g(d_max)):
-//   2-D: g(d) = |4d/h^2 + 20e| + 4|d/h^2 + 8e| + 12e,      e = eps^2/h^4
-//   3-D: g(d) = |6d/h^2 + 42e| + 6|d/h^2 + 12e| + 30e
+// LIM step begin (Fig. 1, steps 1-2; Fig. 2, lines 3-5): partials of
+// min/max y^2 (and a non-finite flag) ...
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctl, const double* __restrict__ y,
-                                                        long long N, double* __restrict__ part, int dim,
-                                                        double eps2, double inv_h2, int eyre) {
+                                                        long long N, double* __restrict__ pout) {
     if (ctl->halted) return;
     double mn = __builtin_inf(), mx = -__builtin_inf(), bad = 0.0;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -503,8 +587,22 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctl, c
             bad = 1.0;
         }
     }
-    double x[3] = {-mn, mx, bad}, tot[3];
-    if (!grid_reduce<3, RED_MAX>(x, part, &ctl->ticket[0], tot)) return;
+    double x[3] = {-mn, mx, bad};
+    write_partials<3, RED_MAX>(x, pout);
+}
+
+// ... then the final-time clip, lambda_max = ||Ahat_n||_1 and p (eq. p).
+// Column j of Ahat_n is d_j A e_j + eps^2 A^2 e_j; its absolute sum g(d_j) is
+// convex and piecewise linear in d_j, so the largest column sum is
+// max(g(d_min), g(d_max)):
+//   2-D: g(d) = |4d/h^2 + 20e| + 4|d/h^2 + 8e| + 12e,      e = eps^2/h^4
+//   3-D: g(d) = |6d/h^2 + 42e| + 6|d/h^2 + 12e| + 30e
+__global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctl, const double* __restrict__ pin, int nin,
+                                                       int dim, double eps2, double inv_h2, int eyre) {
+    if (ctl->halted) return;
+    double tot[3];
+    sum_partials<3, RED_MAX>(pin, nin, tot);
+    if (threadIdx.x != 0) return;
     const double ymin2 = -tot[0], ymax2 = tot[1];
     if (tot[2] != 0.0) {
         ctl->status = CH_ENONFINITE;
@@ -545,59 +643,99 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctl, c
     ctl->p = (int)pr;
 }
 
+// LIM step end (Fig. 2, lines 8-10): est (eq. LIMest), t, tau_new (eq. LIMdt).
+__global__ __launch_bounds__(CH_BLOCK) void k_lim_end(Ctl* __restrict__ ctl, const double* __restrict__ pin, int nin,
+                                                      ch_step_record* __restrict__ rec) {
+    if (ctl->halted) return;
+    double tot[2];
+    sum_partials<2, RED_SUM>(pin, nin, tot);
+    if (threadIdx.x != 0) return;
+    const double num = sqrt(tot[0]), den = sqrt(tot[1]);
+    const double est = den > 0.0 ? num / den : 0.0;
+    if (!(est < __builtin_inf())) {
+        ctl->status = CH_ENONFINITE;
+        ctl->halted = 1;
+        return;
+    }
+    const double tau = ctl->tau0;
+    const double t_new = ctl->clipped ? ctl->T : ctl->t + tau;
+    double tau_next = tau;
+    if (ctl->mode == MODE_LIM) tau_next = est == 0.0 ? tau : ctl->tol / est * tau;   // eq. LIMdt
+    if (ctl->mode == MODE_LIM_CONST) tau_next = ctl->tau_fixed;
+    const int mv = 2 * ctl->p - 1;
+    if (ctl->steps < ctl->rec_cap) {
+        ch_step_record& r = rec[ctl->steps];
+        r.t = t_new;
+        r.tau = tau;
+        r.tau_next = tau_next;
+        r.est = est;
+        r.tol_phi = 0.0;
+        r.beta = 0.0;
+        r.resnorm = 0.0;
+        r.lambda_max = ctl->lam;
+        r.j = ctl->p;
+        r.cycles = 0;
+        r.traced = 0;
+        r.matvecs = mv;
+    }
+    ctl->est = est;
+    ctl->t = t_new;
+    ctl->tau = tau_next;
+    ctl->matvecs += mv;
+    ctl->steps += 1;
+    ctl->cur ^= 1;
+    if (!(t_new < ctl->T)) ctl->halted = 1;
+}
+
 int stream_grid(long long N, int per_thread) {
     long long g = (N + (long long)CH_BLOCK * per_thread - 1) / ((long long)CH_BLOCK * per_thread);
     if (g < 1) g = 1;
-    if (g > 2048) g = 2048;
+    if (g > 512) g = 512;
     return (int)g;
 }
 
 template <typename TV>
-hipError_t launch_arnoldi_t(const Grid& g, int prec, const DevBuffers& b, const double* y, int m_max,
-                            hipStream_t s) {
+int mgs_grid(long long N) {
+    return stream_grid(N / Vec16<TV>::W + 1, 1);
+}
+
+template <typename TV>
+hipError_t launch_mgs_t(const Grid& g, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
-    const int G = stream_grid(g.N, Vec16<TV>::W);
-    for (int k = 0; k < m_max; ++k) {
-        hipError_t e = launch_matvec(g, prec, b, y, k, s);
-        if (e != hipSuccess) return e;
-        TV* W = V + (size_t)(k + 1) * b.ldv;
-        for (int i = 1; i <= k; ++i)
-            hipLaunchKernelGGL((k_mgs<TV, false>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, W,
-                               V + (size_t)(i - 1) * b.ldv, V + (size_t)i * b.ldv, k, i, g.N, b.part);
+    TV* W = V + (size_t)(k + 1) * b.ldv;
+    const int G = mgs_grid<TV>(g.N);
+    if (i <= k)
+        hipLaunchKernelGGL((k_mgs<TV, false>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, W, V + (size_t)(i - 1) * b.ldv,
+                           V + (size_t)i * b.ldv, k, i, g.N, ps.in(), ps.np, ps.out());
+    else
         hipLaunchKernelGGL((k_mgs<TV, true>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, W, V + (size_t)k * b.ldv,
-                           (const TV*)nullptr, k, k + 1, g.N, b.part);
-        hipLaunchKernelGGL(k_phi, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, k);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+                           (const TV*)nullptr, k, i, g.N, ps.in(), ps.np, ps.out());
+    ps.produced(G);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_arnoldi(const Grid& g, int prec, const DevBuffers& b, const double* y, int m_max, hipStream_t s) {
-    return prec == CH_FP64 ? launch_arnoldi_t<double>(g, prec, b, y, m_max, s)
-                           : launch_arnoldi_t<float>(g, prec, b, y, m_max, s);
+hipError_t launch_mgs_pass(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s) {
+    return prec == CH_FP64 ? launch_mgs_t<double>(g, b, ps, k, i, s) : launch_mgs_t<float>(g, b, ps, k, i, s);
 }
 
-hipError_t launch_mgs_pass(const Grid& g, int prec, const DevBuffers& b, int k, int i, hipStream_t s) {
-    if (prec == CH_FP64) {
-        double* V = static_cast<double*>(b.V);
-        hipLaunchKernelGGL((k_mgs<double, false>), dim3(stream_grid(g.N, 2)), dim3(CH_BLOCK), 0, s, b.ctl,
-                           V + (size_t)(k + 1) * b.ldv, V + (size_t)(i - 1) * b.ldv, V + (size_t)i * b.ldv, k, i,
-                           g.N, b.part);
-    } else {
-        float* V = static_cast<float*>(b.V);
-        hipLaunchKernelGGL((k_mgs<float, false>), dim3(stream_grid(g.N, 4)), dim3(CH_BLOCK), 0, s, b.ctl,
-                           V + (size_t)(k + 1) * b.ldv, V + (size_t)(i - 1) * b.ldv, V + (size_t)i * b.ldv, k, i,
-                           g.N, b.part);
+hipError_t launch_phi(const DevBuffers& b, PartSeq& ps, int k, int cycle_id, hipStream_t s) {
+    hipLaunchKernelGGL(k_phi, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, k, ps.in(), ps.np, cycle_id, b.dflag);
+    return hipGetLastError();
+}
+
+hipError_t launch_arnoldi(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
+                          int cycle_id, hipStream_t s) {
+    for (int k = 0; k < m_max; ++k) {
+        if (k > 0 && b.hflag && *b.hflag == cycle_id) break;
+        hipError_t e = launch_matvec(g, prec, b, ps, y, k, s);
+        if (e != hipSuccess) return e;
+        for (int i = 1; i <= k + 1; ++i)
+            if ((e = launch_mgs_pass(g, prec, b, ps, k, i, s)) != hipSuccess) return e;
+        if ((e = launch_phi(b, ps, k, cycle_id, s)) != hipSuccess) return e;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_phi(const DevBuffers& b, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_phi, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, k);
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_update(const Grid& g, int prec, const DevBuffers& b, const double* y, double* ynew,
@@ -612,8 +750,8 @@ hipError_t launch_update(const Grid& g, int prec, const DevBuffers& b, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_begin_step(const DevBuffers& b, hipStream_t s) {
-    hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(64), 0, s, b.ctl);
+hipError_t launch_after_resid(const DevBuffers& b, PartSeq& ps, bool begin_step, hipStream_t s) {
+    hipLaunchKernelGGL(k_after_resid, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, ps.in(), ps.np, begin_step ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -622,13 +760,25 @@ hipError_t launch_cycle_begin(const DevBuffers& b, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_after_resid(const DevBuffers& b, hipStream_t s) {
-    hipLaunchKernelGGL(k_after_resid, dim3(1), dim3(64), 0, s, b.ctl);
+hipError_t launch_step_end(const DevBuffers& b, PartSeq& ps, bool begin_next, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, ps.in(), ps.np, b.rec, begin_next ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_lim_begin(const Grid& g, const DevBuffers& b, const double* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_lim_begin, dim3(stream_grid(g.N, 4)), dim3(CH_BLOCK), 0, s, b.ctl, y, g.N, b.part, g.dim,
-                       g.eps2, g.inv_h2, g.eyre);
+hipError_t launch_lim_begin(const Grid& g, const DevBuffers& b, PartSeq& ps, const double* y, hipStream_t s) {
+    const int G = stream_grid(g.N, 4);
+    hipLaunchKernelGGL(k_lim_begin, dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, y, g.N, ps.out());
+    ps.produced(G);
+    return hipGetLastError();
+}
+
+hipError_t launch_lim_plan(const Grid& g, const DevBuffers& b, PartSeq& ps, hipStream_t s) {
+    hipLaunchKernelGGL(k_lim_plan, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, ps.in(), ps.np, g.dim, g.eps2, g.inv_h2,
+                       g.eyre);
+    return hipGetLastError();
+}
+
+hipError_t launch_lim_end(const DevBuffers& b, PartSeq& ps, hipStream_t s) {
+    hipLaunchKernelGGL(k_lim_end, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, ps.in(), ps.np, b.rec);
     return hipGetLastError();
 }

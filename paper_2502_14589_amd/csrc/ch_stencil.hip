@@ -27,12 +27,12 @@ __device__ __forceinline__ T ccoef(T y, int eyre) {
 }
 
 // ---------------------------------------------------------------------------
-// w = Ahat (vscale[k] V_k); partial <w, V_0> -> h_{1,k+1} (Fig. 3, lines 4-6, i = 1)
+// w = Ahat (vscale[k] V_k) and the partials of <w, V_0> (Fig. 3, lines 4-6, i = 1)
 // ---------------------------------------------------------------------------
 template <int DIM, typename TV, typename TY>
 __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctl, const TV* __restrict__ Vk,
                                                      const TY* __restrict__ y, TV* __restrict__ W,
-                                                     const TV* __restrict__ V0, int k, double* __restrict__ part,
+                                                     const TV* __restrict__ V0, int k, double* __restrict__ pout,
                                                      int n, double eps2_, double inv_h2_, int eyre) {
     if (ctl->done | ctl->halted) return;
     using R1 = Region<DIM, 1>;
@@ -64,12 +64,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctl, cons
         }
         __syncthreads();
     }
-    double x[1] = {dot}, tot[1];
-    if (grid_reduce<1, RED_SUM>(x, part, &ctl->ticket[0], tot)) {
-        const double h = ctl->vscale[0] * tot[0];
-        ctl->H[k * CH_LDH] = h;
-        ctl->coef[0] = ctl->vscale[0] * h;
-    }
+    double x[1] = {dot};
+    write_partials<1, RED_SUM>(x, pout);
 }
 
 // ---------------------------------------------------------------------------
@@ -77,13 +73,13 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctl, cons
 //     r = ghat - Ahat z = A (c(y) - d(y) z - eps^2 A z)
 // With z = y this is f(y) (eq. IVP), the EE2 start vector (Fig. 3, line 2).
 // Writes r to V_0 (and FP64 to fcur when write_f), optionally the FP32 copy
-// of y; reduces ||r||^2 and ||A c(y)||^2 = ||ghat||^2 (eq. tol_phi).
+// of y; partials of ||r||^2 and ||A c(y)||^2 = ||ghat||^2 (eq. tol_phi).
 // ---------------------------------------------------------------------------
 template <int DIM, typename TV>
 __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctl, const double* __restrict__ y,
                                                     const double* __restrict__ z, double* __restrict__ fout,
                                                     TV* __restrict__ V0, float* __restrict__ y32,
-                                                    double* __restrict__ part, int n, double eps2, double inv_h2,
+                                                    double* __restrict__ pout, int n, double eps2, double inv_h2,
                                                     int eyre) {
     if (ctl->halted) return;
     using R1 = Region<DIM, 1>;
@@ -121,16 +117,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctl, const
         }
         __syncthreads();
     }
-    double x[2] = {acc_r, acc_g}, tot[2];
-    if (grid_reduce<2, RED_SUM>(x, part, &ctl->ticket[0], tot)) {
-        const double beta = sqrt(tot[0]);
-        ctl->beta = beta;
-        ctl->gnorm = sqrt(tot[1]);
-        if (!(beta < __builtin_inf()) || !(ctl->gnorm < __builtin_inf())) {
-            ctl->status = CH_ENONFINITE;
-            ctl->halted = 1;
-        }
-    }
+    double x[2] = {acc_r, acc_g};
+    write_partials<2, RED_SUM>(x, pout);
 }
 
 // ---------------------------------------------------------------------------
@@ -138,14 +126,14 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctl, const
 //   f1 = f(y^{n+1});  y_PC = y^n + tau/2 (f(y^n) + f1)  (eq. LIMest, since
 //   f(y) = -A (F'(y) + eps^2 A y));  est = ||y^{n+1} - y_PC|| / ||y_PC||.
 // f1 becomes the next step's f(y^n) and start vector; ||A c(y^{n+1})|| the next
-// ||ghat||.  The last workgroup runs the controller (eqs. EEdt, tol_phi).
+// ||ghat||.  Partials of the four sums go to the step controller.
 // ---------------------------------------------------------------------------
 template <int DIM, typename TV>
 __global__ __launch_bounds__(CH_BLOCK) void k_est_ee(Ctl* __restrict__ ctl, const double* __restrict__ y0,
                                                      const double* __restrict__ y1, double* __restrict__ fcur,
                                                      TV* __restrict__ V0, float* __restrict__ y32,
-                                                     double* __restrict__ part, ch_step_record* __restrict__ rec,
-                                                     int n, double eps2, double inv_h2, int eyre) {
+                                                     double* __restrict__ pout, int n, double eps2, double inv_h2,
+                                                     int eyre) {
     if (ctl->halted) return;
     using R1 = Region<DIM, 1>;
     using R2 = Region<DIM, 2>;
@@ -187,54 +175,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_ee(Ctl* __restrict__ ctl, cons
         }
         __syncthreads();
     }
-    double x[4] = {a_err, a_pc, a_f, a_g}, tot[4];
-    if (grid_reduce<4, RED_SUM>(x, part, &ctl->ticket[0], tot)) {
-        const double num = sqrt(tot[0]), den = sqrt(tot[1]);
-        const double est = den > 0.0 ? num / den : 0.0;
-        const double beta = sqrt(tot[2]), gn = sqrt(tot[3]);
-        if (!(est < __builtin_inf()) || !(beta < __builtin_inf()) || !(gn < __builtin_inf())) {
-            ctl->status = CH_ENONFINITE;
-            ctl->halted = 1;
-            return;
-        }
-        const bool constant = ctl->mode != MODE_EE;
-        const double tau_used = constant ? ctl->tau_step : ctl->tau_acc;
-        // final-time clip lands exactly on T when the clipped step was taken in full
-        const double t_new = (ctl->clipped && ctl->converged) ? ctl->T : ctl->t + tau_used;
-        double tau_next;
-        if (constant) {
-            tau_next = ctl->tau_fixed;
-        } else {
-            const double grow = 1.25 * tau_used;                       // eq. EEdt
-            tau_next = est == 0.0 ? grow : fmin(grow, sqrt(ctl->tol / est) * tau_used);
-        }
-        const int mv = ctl->mv_step + 1 + ctl->j;
-        if (ctl->steps < ctl->rec_cap) {
-            ch_step_record& r = rec[ctl->steps];
-            r.t = t_new;
-            r.tau = tau_used;
-            r.tau_next = tau_next;
-            r.est = est;
-            r.tol_phi = ctl->tol_phi;
-            r.beta = ctl->beta;
-            r.resnorm = ctl->resnorm;
-            r.lambda_max = 0.0;
-            r.j = ctl->j;
-            r.cycles = ctl->cycles;
-            r.traced = ctl->traced;
-            r.matvecs = mv;
-        }
-        ctl->est = est;
-        ctl->t = t_new;
-        ctl->tau = tau_next;
-        ctl->beta = beta;
-        ctl->gnorm = gn;
-        ctl->matvecs += mv;
-        ctl->traces += ctl->traced;
-        ctl->steps += 1;
-        ctl->cur ^= 1;
-        if (t_new >= ctl->T) ctl->halted = 1;
-    }
+    double x[4] = {a_err, a_pc, a_f, a_g};
+    write_partials<4, RED_SUM>(x, pout);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,14 +229,14 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctl, c
 }
 
 // ---------------------------------------------------------------------------
-// LIM estimate (Fig. 2, line 8; eq. LIMest) and step-size rule (eq. LIMdt):
-//   y_PC = y^n - tau/2 A (F'(y^n) + F'(y^{n+1}) + eps^2 A (y^n + y^{n+1}))
+// LIM estimate (Fig. 2, line 8; eq. LIMest):
+//   y_PC = y^n - tau/2 A (F'(y^n) + F'(y^{n+1}) + eps^2 A (y^n + y^{n+1}));
+// partials of ||y^{n+1} - y_PC||^2 and ||y_PC||^2 go to the controller.
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctl, const double* __restrict__ y0,
-                                                      const double* __restrict__ y1, double* __restrict__ part,
-                                                      ch_step_record* __restrict__ rec, int n, double eps2,
-                                                      double inv_h2) {
+                                                      const double* __restrict__ y1, double* __restrict__ pout,
+                                                      int n, double eps2, double inv_h2) {
     if (ctl->halted) return;
     using R1 = Region<DIM, 1>;
     using R2 = Region<DIM, 2>;
@@ -331,43 +273,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctl, con
         }
         __syncthreads();
     }
-    double x[2] = {a_err, a_pc}, tot[2];
-    if (grid_reduce<2, RED_SUM>(x, part, &ctl->ticket[0], tot)) {
-        const double num = sqrt(tot[0]), den = sqrt(tot[1]);
-        const double est = den > 0.0 ? num / den : 0.0;
-        if (!(est < __builtin_inf())) {
-            ctl->status = CH_ENONFINITE;
-            ctl->halted = 1;
-            return;
-        }
-        const double t_new = ctl->clipped ? ctl->T : ctl->t + tau;
-        double tau_next = tau;                                          // constant step
-        if (ctl->mode == MODE_LIM) tau_next = est == 0.0 ? tau : ctl->tol / est * tau;   // eq. LIMdt
-        if (ctl->mode == MODE_LIM_CONST) tau_next = ctl->tau_fixed;
-        const int mv = 2 * ctl->p - 1;
-        if (ctl->steps < ctl->rec_cap) {
-            ch_step_record& r = rec[ctl->steps];
-            r.t = t_new;
-            r.tau = tau;
-            r.tau_next = tau_next;
-            r.est = est;
-            r.tol_phi = 0.0;
-            r.beta = 0.0;
-            r.resnorm = 0.0;
-            r.lambda_max = ctl->lam;
-            r.j = ctl->p;
-            r.cycles = 0;
-            r.traced = 0;
-            r.matvecs = mv;
-        }
-        ctl->est = est;
-        ctl->t = t_new;
-        ctl->tau = tau_next;
-        ctl->matvecs += mv;
-        ctl->steps += 1;
-        ctl->cur ^= 1;
-        if (t_new >= ctl->T) ctl->halted = 1;
-    }
+    double x[2] = {a_err, a_pc};
+    write_partials<2, RED_SUM>(x, pout);
 }
 
 template <int DIM>
@@ -376,7 +283,7 @@ int stencil_grid(int n) {
     const int nty = (n + Geo<DIM>::TY - 1) / Geo<DIM>::TY;
     const int ntz = DIM == 3 ? (n + Geo<DIM>::TZ - 1) / Geo<DIM>::TZ : 1;
     const long long nt = (long long)ntx * nty * ntz;
-    return (int)(nt < CH_MAXB ? nt : CH_MAXB);
+    return (int)(nt < 2048 ? nt : 2048);   // larger grids loop over tiles
 }
 
 }  // namespace
@@ -385,61 +292,68 @@ int stencil_grid(int n) {
 // Launchers
 // ---------------------------------------------------------------------------
 template <int DIM, typename TV>
-static hipError_t launch_matvec_t(const Grid& g, const DevBuffers& b, const void* y, int k, hipStream_t s) {
+static hipError_t launch_matvec_t(const Grid& g, const DevBuffers& b, PartSeq& ps, const void* y, int k,
+                                  hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     const TV* Vk = V + (size_t)k * b.ldv;
     TV* W = V + (size_t)(k + 1) * b.ldv;
     const int G = stencil_grid<DIM>(g.n);
     if (sizeof(TV) == sizeof(double)) {
         hipLaunchKernelGGL((k_matvec<DIM, TV, double>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, Vk,
-                           static_cast<const double*>(y), W, V, k, b.part, g.n, g.eps2, g.inv_h2, g.eyre);
+                           static_cast<const double*>(y), W, V, k, ps.out(), g.n, g.eps2, g.inv_h2, g.eyre);
     } else {
         hipLaunchKernelGGL((k_matvec<DIM, TV, float>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, Vk,
-                           static_cast<const float*>(y), W, V, k, b.part, g.n, g.eps2, g.inv_h2, g.eyre);
+                           static_cast<const float*>(y), W, V, k, ps.out(), g.n, g.eps2, g.inv_h2, g.eyre);
     }
+    ps.produced(G);
     return hipGetLastError();
 }
 
-hipError_t launch_matvec(const Grid& g, int prec, const DevBuffers& b, const double* y, int k, hipStream_t s) {
+hipError_t launch_matvec(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
+                         hipStream_t s) {
     if (prec == CH_FP64)
-        return g.dim == 2 ? launch_matvec_t<2, double>(g, b, y, k, s) : launch_matvec_t<3, double>(g, b, y, k, s);
-    return g.dim == 2 ? launch_matvec_t<2, float>(g, b, b.y32, k, s) : launch_matvec_t<3, float>(g, b, b.y32, k, s);
+        return g.dim == 2 ? launch_matvec_t<2, double>(g, b, ps, y, k, s)
+                          : launch_matvec_t<3, double>(g, b, ps, y, k, s);
+    return g.dim == 2 ? launch_matvec_t<2, float>(g, b, ps, b.y32, k, s)
+                      : launch_matvec_t<3, float>(g, b, ps, b.y32, k, s);
 }
 
 template <int DIM, typename TV>
-static hipError_t launch_resid_t(const Grid& g, const DevBuffers& b, const double* y, const double* z,
+static hipError_t launch_resid_t(const Grid& g, const DevBuffers& b, PartSeq& ps, const double* y, const double* z,
                                  bool write_f, bool write_y32, hipStream_t s) {
     const int G = stencil_grid<DIM>(g.n);
     hipLaunchKernelGGL((k_resid<DIM, TV>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, y, z, write_f ? b.fcur : nullptr,
-                       static_cast<TV*>(b.V), write_y32 ? b.y32 : nullptr, b.part, g.n, g.eps2, g.inv_h2, g.eyre);
+                       static_cast<TV*>(b.V), write_y32 ? b.y32 : nullptr, ps.out(), g.n, g.eps2, g.inv_h2, g.eyre);
+    ps.produced(G);
     return hipGetLastError();
 }
 
-hipError_t launch_resid(const Grid& g, int prec, const DevBuffers& b, const double* y, const double* z,
+hipError_t launch_resid(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, const double* y, const double* z,
                         bool write_f, bool write_y32, hipStream_t s) {
     if (prec == CH_FP64)
-        return g.dim == 2 ? launch_resid_t<2, double>(g, b, y, z, write_f, false, s)
-                          : launch_resid_t<3, double>(g, b, y, z, write_f, false, s);
-    return g.dim == 2 ? launch_resid_t<2, float>(g, b, y, z, write_f, write_y32, s)
-                      : launch_resid_t<3, float>(g, b, y, z, write_f, write_y32, s);
+        return g.dim == 2 ? launch_resid_t<2, double>(g, b, ps, y, z, write_f, false, s)
+                          : launch_resid_t<3, double>(g, b, ps, y, z, write_f, false, s);
+    return g.dim == 2 ? launch_resid_t<2, float>(g, b, ps, y, z, write_f, write_y32, s)
+                      : launch_resid_t<3, float>(g, b, ps, y, z, write_f, write_y32, s);
 }
 
 template <int DIM, typename TV>
-static hipError_t launch_est_ee_t(const Grid& g, const DevBuffers& b, const double* y0, const double* y1,
-                                  float* y32, hipStream_t s) {
+static hipError_t launch_est_ee_t(const Grid& g, const DevBuffers& b, PartSeq& ps, const double* y0,
+                                  const double* y1, float* y32, hipStream_t s) {
     const int G = stencil_grid<DIM>(g.n);
     hipLaunchKernelGGL((k_est_ee<DIM, TV>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, y0, y1, b.fcur,
-                       static_cast<TV*>(b.V), y32, b.part, b.rec, g.n, g.eps2, g.inv_h2, g.eyre);
+                       static_cast<TV*>(b.V), y32, ps.out(), g.n, g.eps2, g.inv_h2, g.eyre);
+    ps.produced(G);
     return hipGetLastError();
 }
 
-hipError_t launch_est_ee(const Grid& g, int prec, const DevBuffers& b, const double* y0, const double* y1,
-                         hipStream_t s) {
+hipError_t launch_est_ee(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, const double* y0,
+                         const double* y1, hipStream_t s) {
     if (prec == CH_FP64)
-        return g.dim == 2 ? launch_est_ee_t<2, double>(g, b, y0, y1, nullptr, s)
-                          : launch_est_ee_t<3, double>(g, b, y0, y1, nullptr, s);
-    return g.dim == 2 ? launch_est_ee_t<2, float>(g, b, y0, y1, b.y32, s)
-                      : launch_est_ee_t<3, float>(g, b, y0, y1, b.y32, s);
+        return g.dim == 2 ? launch_est_ee_t<2, double>(g, b, ps, y0, y1, nullptr, s)
+                          : launch_est_ee_t<3, double>(g, b, ps, y0, y1, nullptr, s);
+    return g.dim == 2 ? launch_est_ee_t<2, float>(g, b, ps, y0, y1, b.y32, s)
+                      : launch_est_ee_t<3, float>(g, b, ps, y0, y1, b.y32, s);
 }
 
 hipError_t launch_lim_stage(const Grid& g, const DevBuffers& b, const double* y, const double* z, double* out,
@@ -453,12 +367,18 @@ hipError_t launch_lim_stage(const Grid& g, const DevBuffers& b, const double* y,
     return hipGetLastError();
 }
 
-hipError_t launch_est_lim(const Grid& g, const DevBuffers& b, const double* y0, const double* y1, hipStream_t s) {
-    if (g.dim == 2)
-        hipLaunchKernelGGL((k_est_lim<2>), dim3(stencil_grid<2>(g.n)), dim3(CH_BLOCK), 0, s, b.ctl, y0, y1, b.part,
-                           b.rec, g.n, g.eps2, g.inv_h2);
-    else
-        hipLaunchKernelGGL((k_est_lim<3>), dim3(stencil_grid<3>(g.n)), dim3(CH_BLOCK), 0, s, b.ctl, y0, y1, b.part,
-                           b.rec, g.n, g.eps2, g.inv_h2);
+hipError_t launch_est_lim(const Grid& g, const DevBuffers& b, PartSeq& ps, const double* y0, const double* y1,
+                          hipStream_t s) {
+    int G;
+    if (g.dim == 2) {
+        G = stencil_grid<2>(g.n);
+        hipLaunchKernelGGL((k_est_lim<2>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, y0, y1, ps.out(), g.n, g.eps2,
+                           g.inv_h2);
+    } else {
+        G = stencil_grid<3>(g.n);
+        hipLaunchKernelGGL((k_est_lim<3>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, y0, y1, ps.out(), g.n, g.eps2,
+                           g.inv_h2);
+    }
+    ps.produced(G);
     return hipGetLastError();
 }

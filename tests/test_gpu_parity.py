@@ -130,15 +130,22 @@ def test_small_2d_constant_ee_200_steps(ctx):
     po, pg = probs(2, 64, 0.05)
     y0 = small_2d_field(0)
     y_ref, infos = O.ee_const_run(y0, po, 1e-5, 200, 1e-8, 30)
+    # the oracle's rounding twin: start vector formed as f(y) instead of ghat - Ahat y
+    yv, j_twin = y0.copy(), []
+    for _ in range(200):
+        yv, _, iv = O.krylov_phi_cycle(lambda v, y=yv: O.ahat_mv(v, y, po), yv, O.rhs(yv, po), 1e-5, 1e-8, 30)
+        j_twin.append(iv.j)
+    jo = [i.js[-1] for i in infos]
+    twin_flips = sum(a != b for a, b in zip(jo, j_twin))
     yg = dev(y0)
     st, recs = ctx.run_ee(pg, yg, 1e-5, max_steps=200, m_max=30, tol_phi_fixed=1e-8, constant_step=True,
                           records=True)
     assert st["steps"] == 200
-    jg, jo = [r["j"] for r in recs], [i.js[-1] for i in infos]
+    jg = [r["j"] for r in recs]
     assert jg[:60] == jo[:60]
     assert all(abs(a - b) <= 1 for a, b in zip(jg, jo))
-    assert sum(a != b for a, b in zip(jg, jo)) <= 20
-    assert abs(st["matvecs"] - sum(i.matvecs for i in infos)) <= 20
+    assert sum(a != b for a, b in zip(jg, jo)) <= 2 * twin_flips + 5
+    assert abs(st["matvecs"] - sum(i.matvecs for i in infos)) <= 2 * twin_flips + 5
     assert rel(host(yg), y_ref) <= TOL_FP64
     assert st["t"] == pytest.approx(200 * 1e-5, rel=1e-12)
 
