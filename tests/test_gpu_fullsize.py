@@ -1,0 +1,158 @@
+"""Parity at the full workload sizes, in the configuration bench.py times.
+
+1024^2 (eps = 0.01, y0 = 0.1 + U(-0.05, 0.05)): the first adaptive EE2 steps
+from tau0 = T = 1e-3 (the first one runs the residual-time trace from 1e-3
+down to ~1e-8), element by element against the oracle.
+256^3 (eps = 0.02): element-by-element LIM step, the 3-D start-vector stencil
+at sampled points, mass conservation of a full EE2 step.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import ch_oracle as O
+from paper_2502_14589_amd import ch
+from paper_2502_14589_amd.inputs import cube_3d_field, large_2d_field, uniform_field
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available()
+    c = ch.Context(0)
+    yield c
+    c.close()
+
+
+def dev(y):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(y, dtype=np.float64)).to("cuda")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def large_ref():
+    """Oracle: first 3 adaptive EE2 steps of the 1024^2 workload (tol 1e-4, m = 30)."""
+    po = O.Problem(2, 1024, 0.01)
+    y0 = large_2d_field(1, 1024)
+    y3, rec = O.ee_adaptive(y0, po, 1e-3, 1e-3, 1e-4, 30, max_steps=3)
+    return y0, y3, rec
+
+
+def test_large_2d_first_steps_fp64(ctx, large_ref):
+    say("1024^2 FP64 first 3 adaptive EE2 steps")
+    y0, y_ref, rec_ref = large_ref
+    assert rec_ref.js[0] == 30 and rec_ref.taus[0] < 1e-6      # traced from tau0 = 1e-3
+    yg = dev(y0)
+    st, recs = ctx.run_ee(ch.Problem(2, 1024, 0.01), yg, 1e-3, T=1e-3, max_steps=3, m_max=30, tol=1e-4,
+                          records=True)
+    assert [r["j"] for r in recs] == rec_ref.js
+    np.testing.assert_allclose([r["tau"] for r in recs], rec_ref.taus, rtol=1e-10)
+    assert rel(yg.cpu().numpy(), y_ref) <= 1e-10
+
+
+def test_large_2d_first_steps_fp32_mixed(ctx, large_ref):
+    """FP32 basis/stencils/axpys with FP64 reductions, phi, update and estimate:
+    stated error against the FP64 oracle after the same 3 steps."""
+    say("1024^2 FP32-mixed first 3 adaptive EE2 steps")
+    y0, y_ref, rec_ref = large_ref
+    yg = dev(y0)
+    st, recs = ctx.run_ee(ch.Problem(2, 1024, 0.01, False, ch.CH_FP32_MIXED), yg, 1e-3, T=1e-3, max_steps=3,
+                          m_max=30, tol=1e-4, records=True)
+    t_ref = sum(rec_ref.taus)
+    # the trace is a continuous function of H: FP32 rounding moves the accepted steps slightly
+    assert abs(st["t"] - t_ref) <= 1e-3 * t_ref
+    err = rel(yg.cpu().numpy(), y_ref)
+    say(f"FP32-mixed rel. error vs FP64 oracle: {err:.3e}, t rel diff {abs(st['t'] - t_ref) / t_ref:.2e}")
+    assert err <= 1e-5
+
+
+def test_cube_3d_lim_step_elementwise(ctx):
+    say("256^3 LIM step")
+    po, pg = O.Problem(3, 256, 0.02), ch.Problem(3, 256, 0.02)
+    y0 = cube_3d_field(2, 256)
+    lam = O.lambda_max(y0, po)
+    tau = 3.0 / lam                      # p = 2: three stages
+    y_ref, p = O.lim_step(y0, po, tau)
+    assert p == 2
+    yg = dev(y0)
+    rec = ctx.step_lim(pg, yg, tau)
+    assert rec["j"] == p
+    assert rec["lambda_max"] == pytest.approx(lam, rel=1e-13)
+    assert rel(yg.cpu().numpy(), y_ref) <= 1e-10
+
+
+def test_cube_3d_start_vector_sampled(ctx):
+    """With m_max = 1 the phi action is y + u f(y) for a scalar u: check f(y) of
+    the 25-point stencil at 4096 sampled points (oracle computes them one by one)."""
+    say("256^3 start vector at sampled points")
+    import torch
+
+    n, eps = 256, 0.02
+    pg = ch.Problem(3, n, eps)
+    y0 = cube_3d_field(2, n)
+    yg = dev(y0)
+    out = torch.empty_like(yg)
+    ctx.phiv(pg, yg, out, 1e-9, mode=ch.CH_PHI_SHRINK, tol_phi=1.0, m_max=1)
+    dy = (out - yg).cpu().numpy()
+    Y = y0.reshape(n, n, n)
+    h2 = 1.0 / n ** 2
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, n, size=(4096, 3))
+
+    def lap_at(F, z, y, x):
+        return (6 * F(z, y, x) - F(z - 1, y, x) - F(z + 1, y, x) - F(z, y - 1, x) - F(z, y + 1, x)
+                - F(z, y, x - 1) - F(z, y, x + 1)) / h2
+
+    def yv(z, y, x):
+        return Y[z % n, y % n, x % n]
+
+    def inner(z, y, x):   # F'(y) + eps^2 A y at one point (eq. IVP)
+        v = yv(z, y, x)
+        return v * (v * v - 1) + eps ** 2 * lap_at(yv, z, y, x)
+
+    f = np.array([-lap_at(inner, z, y, x) for z, y, x in idx])
+    g = dy.reshape(n, n, n)[idx[:, 0], idx[:, 1], idx[:, 2]]
+    u = float(g @ f / (f @ f))
+    assert u > 0
+    assert np.max(np.abs(g - u * f)) <= 1e-9 * np.max(np.abs(u * f))
+
+
+def test_cube_3d_ee_step_mass_and_determinism(ctx):
+    say("256^3 EE2 step (m = 40, tol 1e-6)")
+    pg = ch.Problem(3, 256, 0.02)
+    y0 = cube_3d_field(2, 256)
+    a, b = dev(y0), dev(y0)
+    st, recs = ctx.run_ee(pg, a, 1e-3, T=math.inf, max_steps=1, m_max=40, tol=1e-6, records=True)
+    ctx.run_ee(pg, b, 1e-3, T=math.inf, max_steps=1, m_max=40, tol=1e-6)
+    assert st["steps"] == 1 and recs[0]["j"] == 40 and recs[0]["traced"] == 1
+    ya = a.cpu().numpy()
+    assert np.array_equal(ya, b.cpu().numpy())
+    assert abs(ya.sum() - y0.sum()) <= 1e-12 * np.abs(y0).sum()
+    assert not np.array_equal(ya, y0)
+
+
+def test_largest_krylov_dimension(ctx):
+    say("m_max = CH_MMAX")
+    po, pg = O.Problem(2, 48, 0.05), ch.Problem(2, 48, 0.05)
+    y0 = uniform_field(48, 2, 0.1, 0.05, seed=21)
+    y_ref, tau_ref, info = O.ee_step(y0, po, 1e-2, 1e-9, ch.CH_MMAX)
+    yg = dev(y0)
+    rec = ctx.step_ee(pg, yg, 1e-2, m_max=ch.CH_MMAX, tol_phi_fixed=1e-9)
+    assert rec["j"] == info.j
+    assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12)
+    assert rel(yg.cpu().numpy(), y_ref) <= 1e-10
