@@ -130,6 +130,30 @@ int ch_run_ee(ch_ctx *ctx, const ch_problem *prob, double *y, double tau0, doubl
 int ch_step_ee(ch_ctx *ctx, const ch_problem *prob, double *y, double tau, double t, double T,
                const ch_ee_opts *opts, ch_step_record *out);
 
+/* One instance of a batched run: a periodic grid of n^dim points. */
+typedef struct {
+    int n;          /* points per direction, >= 5 */
+    double eps;     /* interface parameter epsilon > 0 */
+    double *y;      /* DEVICE field, in/out, FP64, n^dim values (x fastest) */
+    double tau0;    /* first proposed step > 0 */
+    double T;       /* final time (INFINITY: limited by max_steps) */
+    int max_steps;  /* accepted steps to take (<= 0: until T) */
+} ch_batch_item;
+
+/*
+ * Adaptive EE2 (Fig. 4) on `count` independent instances at once: every
+ * kernel launch covers all instances (ragged sizes, each with its own eps,
+ * step sizes, Krylov convergence, final time and step limit), so the small
+ * per-instance launches of separate runs become one launch per kernel.  dim,
+ * eyre, precision, Krylov dimension and tolerances (opts) are common;
+ * opts->constant_step must be 0.  Each instance's result equals that of a
+ * separate ch_run_ee call up to the order of floating-point sums, and does not
+ * depend on the other members of the batch.  stats: NULL or `count` entries.
+ * Returns the first failing instance's status; the other instances complete.
+ */
+int ch_run_ee_batch(ch_ctx *ctx, int count, ch_batch_item *items, int dim, int eyre, int prec,
+                    const ch_ee_opts *opts, ch_run_stats *stats);
+
 /*
  * Adaptive (Fig. 2, tol > 0) or constant-step (tol <= 0) LIM run on y (in/out),
  * same conventions as ch_run_ee.

@@ -12,7 +12,8 @@ import os
 from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_void_p
 from dataclasses import dataclass
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libch.so")
+# CH_LIB_PATH selects another build of the same library (e.g. to compare two builds on one GPU).
+LIB_PATH = os.environ.get("CH_LIB_PATH") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libch.so")
 
 CH_OK, CH_EINVAL, CH_ENOMEM, CH_ENONFINITE, CH_ETAU_UNDERFLOW, CH_EBUSY, CH_ENOENT, CH_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 CH_FP64, CH_FP32_MIXED = 0, 1
@@ -22,7 +23,7 @@ CH_PMAX = 4096
 
 EXPORTED = (
     "ch_create", "ch_destroy", "ch_strerror", "ch_last_error_message",
-    "ch_run_ee", "ch_step_ee", "ch_run_lim", "ch_step_lim", "ch_phiv", "ch_time_kernel",
+    "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_step_lim", "ch_phiv", "ch_time_kernel",
 )
 CH_KERNEL_MGS, CH_KERNEL_MATVEC, CH_KERNEL_PHI = 0, 1, 2
 
@@ -51,6 +52,11 @@ class ChRunStats(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ChBatchItem(ctypes.Structure):
+    _fields_ = [("n", c_int), ("eps", c_double), ("y", c_void_p), ("tau0", c_double), ("T", c_double),
+                ("max_steps", c_int)]
 
 
 class ChError(RuntimeError):
@@ -87,9 +93,11 @@ def load_library(path: str = LIB_PATH):
                                 P(ChStepRecord)]
     lib.ch_phiv.argtypes = [c_void_p, P(ChProblem), c_void_p, c_void_p, c_double, c_int, c_double, c_int,
                             P(ChStepRecord)]
+    lib.ch_run_ee_batch.argtypes = [c_void_p, c_int, P(ChBatchItem), c_int, c_int, c_int, P(ChEeOpts),
+                                    P(ChRunStats)]
     lib.ch_time_kernel.argtypes = [c_void_p, P(ChProblem), c_int, c_int, c_int, P(c_double), P(c_double)]
-    for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_lim", "ch_step_lim", "ch_phiv",
-                 "ch_time_kernel"):
+    for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim",
+                 "ch_step_lim", "ch_phiv", "ch_time_kernel"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -188,6 +196,26 @@ class Context:
                                  byref(opts), byref(rec))
         self._raise(rc, "ch_step_ee")
         return rec.as_dict()
+
+    def run_ee_batch(self, fields, ns, eps, *, dim: int = 2, eyre: bool = False, precision: int = CH_FP64,
+                     tau0=1e-3, T=math.inf, max_steps=50, m_max: int = 30, tol: float = 1e-4,
+                     tol_phi_fixed: float = 0.0, tau_min: float = 0.0, raise_on_error: bool = True):
+        """Adaptive EE2 on many instances at once (each field updated in place); returns per-instance stats."""
+        count = len(fields)
+        as_list = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * count
+        tau0s, Ts, steps = as_list(tau0), as_list(T), as_list(max_steps)
+        items = (ChBatchItem * count)()
+        for i, y in enumerate(fields):
+            _check_field(y, ns[i] ** dim)
+            items[i] = ChBatchItem(int(ns[i]), float(eps[i]), c_void_p(y.data_ptr()), float(tau0s[i]),
+                                   float(Ts[i]), int(steps[i]))
+        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), 0)
+        st = (ChRunStats * count)()
+        rc = self.lib.ch_run_ee_batch(self._ptr, count, items, int(dim), int(bool(eyre)), int(precision),
+                                      byref(opts), st)
+        if raise_on_error:
+            self._raise(rc, "ch_run_ee_batch")
+        return [s.as_dict() for s in st], rc
 
     # -- LIM ---------------------------------------------------------------
     def run_lim(self, prob: Problem, y, tau0: float, *, t0: float = 0.0, T: float = math.inf, max_steps: int = 0,

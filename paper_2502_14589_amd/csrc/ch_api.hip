@@ -1,12 +1,14 @@
 // Host driver and C ABI of libch (declared in include/ch.h).
 //
-// A run keeps its state in two library-owned FP64 buffers (ping-pong); the
-// caller's field is copied in at the start and the last accepted state is
-// copied back at the end, so a failing step never touches the caller's data.
-// All step control lives in the device control block (Ctl): a run of EE2 steps
-// is issued without host synchronisation, except where the number of launches
-// depends on device data (LIM's Chebyshev order p, restarted Krylov cycles of a
-// constant step) and a periodic check for t >= T when no step limit is given.
+// Every run works on a batch of instances laid out in pooled device arrays
+// (a single-field call is a batch of one).  A run keeps each state in two
+// library-owned FP64 buffers (ping-pong); the caller's fields are copied in at
+// the start and the last accepted states are copied back at the end, so a
+// failing step never touches the caller's data.  All step control lives in
+// per-instance device control blocks (Ctl): a run of EE2 steps is issued
+// without host synchronisation, except where the number of launches depends
+// on device data (LIM's Chebyshev order p, restarted Krylov cycles of a
+// constant step) and a periodic check for the end of the run.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -14,6 +16,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "ch_internal.h"
 
@@ -22,25 +25,33 @@ struct ch_ctx {
     hipStream_t stream = nullptr;
     DevBuffers b{};
     size_t v_bytes = 0;      // bytes allocated for the Krylov basis
-    size_t state_n = 0;      // points allocated for the FP64 state buffers
-    size_t y32_n = 0;
-    size_t z_n = 0;
-    int rec_cap = 0;
+    size_t pts = 0;          // points allocated for the pooled FP64 state arrays
+    size_t y32_pts = 0;
+    size_t z_pts = 0;
+    int slots = 0;           // control blocks allocated
+    size_t rec_n = 0;        // step records allocated
+    ch_step_record* rec = nullptr;
     int cycle_id = 0;        // id of the last issued Krylov cycle
-    int* hflag = nullptr;    // pinned, device-mapped: last finished cycle id
-    Ctl* hctl = nullptr;     // pinned mirror of the control block
+    int* hflag = nullptr;    // pinned, device-mapped: last finished cycle id per slot
+    Ctl* hctl = nullptr;     // pinned mirror of the control blocks
+    // instance table
+    Inst* d_inst = nullptr;
+    int* d_sb2i = nullptr;
+    int* d_cb2i = nullptr;
+    size_t inst_cap = 0, map_cap = 0;
+    std::vector<Inst> h_inst;
     std::string err;
 };
 
 namespace {
 
-#define HIP_TRY(ctx, call)                                          \
-    do {                                                            \
-        hipError_t e_ = (call);                                     \
-        if (e_ != hipSuccess) {                                     \
+#define HIP_TRY(ctx, call)                                                  \
+    do {                                                                    \
+        hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) {                                             \
             (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_); \
-            return CH_EDEVICE;                                      \
-        }                                                           \
+            return CH_EDEVICE;                                              \
+        }                                                                   \
     } while (0)
 
 int alloc_dev(ch_ctx* ctx, void** p, size_t bytes) {
@@ -58,51 +69,72 @@ void free_dev(void* p) {
     if (p) (void)hipFree(p);
 }
 
-int check_problem(const ch_problem* p, Grid* g) {
-    if (!p) return CH_EINVAL;
-    if (p->dim != 2 && p->dim != 3) return CH_EINVAL;
-    if (p->n < 5) return CH_EINVAL;
-    if (!(p->eps > 0.0) || !(p->eps < INFINITY)) return CH_EINVAL;
-    if (p->eyre != 0 && p->eyre != 1) return CH_EINVAL;
-    if (p->prec != CH_FP64 && p->prec != CH_FP32_MIXED) return CH_EINVAL;
+size_t pad64(size_t x) { return (x + 63) / 64 * 64; }
+
+struct Shape {
+    int dim, n;
+    long long N;
+};
+
+int check_grid(int dim, int n, double eps, int eyre, Shape* sh) {
+    if (dim != 2 && dim != 3) return CH_EINVAL;
+    if (n < 5) return CH_EINVAL;
+    if (!(eps > 0.0) || !(eps < INFINITY)) return CH_EINVAL;
+    if (eyre != 0 && eyre != 1) return CH_EINVAL;
     long long N = 1;
-    for (int d = 0; d < p->dim; ++d) N *= p->n;
+    for (int d = 0; d < dim; ++d) N *= n;
     if (N >= (1LL << 31)) return CH_EINVAL;
-    g->dim = p->dim;
-    g->n = p->n;
-    g->N = N;
-    g->eps2 = p->eps * p->eps;
-    g->inv_h2 = double(p->n) * double(p->n);
-    g->eyre = p->eyre;
+    sh->dim = dim;
+    sh->n = n;
+    sh->N = N;
     return CH_OK;
 }
 
-// Size the workspace for N points, a basis of m_max + 1 columns in `prec`,
-// `recs` step records and (optionally) the LIM stage buffer.
-int ensure(ch_ctx* ctx, long long N, int m_max, int prec, int recs, bool need_z) {
+int check_problem(const ch_problem* p, Shape* sh) {
+    if (!p) return CH_EINVAL;
+    if (p->prec != CH_FP64 && p->prec != CH_FP32_MIXED) return CH_EINVAL;
+    return check_grid(p->dim, p->n, p->eps, p->eyre, sh);
+}
+
+// Workspace for `pts` pooled points, a basis of m_max + 1 columns in `prec`,
+// `nslots` control blocks, `recs` step records and (optionally) the LIM stage buffer.
+int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs, bool need_z) {
     DevBuffers& b = ctx->b;
     int rc;
-    if (!b.ctl) {
-        if ((rc = alloc_dev(ctx, (void**)&b.ctl, sizeof(Ctl)))) return rc;
+    if (!b.part) {
         if ((rc = alloc_dev(ctx, (void**)&b.part, 2 * sizeof(double) * CH_NRED * CH_MAXB))) return rc;
-        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hctl, sizeof(Ctl), hipHostMallocDefault));
-        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, 64, hipHostMallocMapped | hipHostMallocCoherent));
-        *ctx->hflag = -1;
+    }
+    if (nslots > ctx->slots) {
+        free_dev(b.ctl);
+        b.ctl = nullptr;
+        if (ctx->hctl) (void)hipHostFree(ctx->hctl);
+        if (ctx->hflag) (void)hipHostFree(ctx->hflag);
+        ctx->hctl = nullptr;
+        ctx->hflag = nullptr;
+        b.hflag = nullptr;
+        b.dflag = nullptr;
+        ctx->slots = 0;
+        if ((rc = alloc_dev(ctx, (void**)&b.ctl, sizeof(Ctl) * nslots))) return rc;
+        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hctl, sizeof(Ctl) * nslots, hipHostMallocDefault));
+        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, sizeof(int) * nslots,
+                                   hipHostMallocMapped | hipHostMallocCoherent));
+        for (int i = 0; i < nslots; ++i) ctx->hflag[i] = -1;
         HIP_TRY(ctx, hipHostGetDevicePointer((void**)&b.dflag, ctx->hflag, 0));
         b.hflag = ctx->hflag;
+        ctx->slots = nslots;
     }
-    if ((size_t)N > ctx->state_n) {
+    if (pts > ctx->pts) {
         free_dev(b.ybuf[0]);
         free_dev(b.ybuf[1]);
         free_dev(b.fcur);
         b.ybuf[0] = b.ybuf[1] = b.fcur = nullptr;
-        ctx->state_n = 0;
+        ctx->pts = 0;
         for (double** p : {&b.ybuf[0], &b.ybuf[1], &b.fcur})
-            if ((rc = alloc_dev(ctx, (void**)p, sizeof(double) * N))) return rc;
-        ctx->state_n = N;
+            if ((rc = alloc_dev(ctx, (void**)p, sizeof(double) * pts))) return rc;
+        ctx->pts = pts;
     }
     if (m_max > 0) {
-        const size_t ldv = ((size_t)N + 63) / 64 * 64;
+        const size_t ldv = pad64(pts);
         const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
         const size_t bytes = (size_t)(m_max + 1) * ldv * esz;
         if (bytes > ctx->v_bytes) {
@@ -113,33 +145,107 @@ int ensure(ch_ctx* ctx, long long N, int m_max, int prec, int recs, bool need_z)
             ctx->v_bytes = bytes;
         }
         b.ldv = ldv;
-        if (prec == CH_FP32_MIXED && (size_t)N > ctx->y32_n) {
+        if (prec == CH_FP32_MIXED && pts > ctx->y32_pts) {
             free_dev(b.y32);
             b.y32 = nullptr;
-            ctx->y32_n = 0;
-            if ((rc = alloc_dev(ctx, (void**)&b.y32, sizeof(float) * N))) return rc;
-            ctx->y32_n = N;
+            ctx->y32_pts = 0;
+            if ((rc = alloc_dev(ctx, (void**)&b.y32, sizeof(float) * pts))) return rc;
+            ctx->y32_pts = pts;
         }
     }
-    if (need_z && (size_t)N > ctx->z_n) {
+    if (need_z && pts > ctx->z_pts) {
         free_dev(b.zbuf);
         b.zbuf = nullptr;
-        ctx->z_n = 0;
-        if ((rc = alloc_dev(ctx, (void**)&b.zbuf, sizeof(double) * N))) return rc;
-        ctx->z_n = N;
+        ctx->z_pts = 0;
+        if ((rc = alloc_dev(ctx, (void**)&b.zbuf, sizeof(double) * pts))) return rc;
+        ctx->z_pts = pts;
     }
-    if (recs > ctx->rec_cap) {
-        free_dev(b.rec);
-        b.rec = nullptr;
-        ctx->rec_cap = 0;
-        if ((rc = alloc_dev(ctx, (void**)&b.rec, sizeof(ch_step_record) * recs))) return rc;
-        ctx->rec_cap = recs;
+    if (recs > ctx->rec_n) {
+        free_dev(ctx->rec);
+        ctx->rec = nullptr;
+        ctx->rec_n = 0;
+        if ((rc = alloc_dev(ctx, (void**)&ctx->rec, sizeof(ch_step_record) * recs))) return rc;
+        ctx->rec_n = recs;
     }
     return CH_OK;
 }
 
+struct Member {
+    Shape sh;
+    double eps;
+    int eyre;
+    size_t off;   // pooled offset (points)
+};
+
+// Workgroup ranges of each instance and the block-to-instance maps.
+int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, Table* t) {
+    const int ni = (int)ms.size();
+    ctx->h_inst.assign(ni, Inst{});
+    std::vector<int> sb, cb;
+    for (int i = 0; i < ni; ++i) {
+        const Member& m = ms[i];
+        Inst& I = ctx->h_inst[i];
+        const int n = m.sh.n;
+        long long tiles;
+        if (dim == 2) tiles = (long long)((n + 63) / 64) * ((n + 7) / 8);
+        else tiles = (long long)((n + 31) / 32) * ((n + 3) / 4) * ((n + 3) / 4);
+        const int sblk = (int)std::min<long long>(tiles, CH_SBLK_MAX);
+        const int cblk = (int)std::max<long long>(1, std::min<long long>((m.sh.N + 2047) / 2048, CH_CBLK_MAX));
+        I.off = (long long)m.off;
+        I.N = m.sh.N;
+        I.n = n;
+        I.slot = i;
+        I.sblk0 = (int)sb.size();
+        I.sblk = sblk;
+        I.cblk0 = (int)cb.size();
+        I.cblk = cblk;
+        I.eps2 = m.eps * m.eps;
+        I.inv_h2 = double(n) * double(n);
+        I.eyre = m.eyre;
+        sb.insert(sb.end(), sblk, i);
+        cb.insert(cb.end(), cblk, i);
+    }
+    if (sb.size() > (size_t)CH_MAXB || cb.size() > (size_t)CH_MAXB) {
+        ctx->err = "batch too large for one launch (workgroup table)";
+        return CH_EINVAL;
+    }
+    int rc;
+    if ((size_t)ni > ctx->inst_cap) {
+        free_dev(ctx->d_inst);
+        ctx->d_inst = nullptr;
+        ctx->inst_cap = 0;
+        if ((rc = alloc_dev(ctx, (void**)&ctx->d_inst, sizeof(Inst) * ni))) return rc;
+        ctx->inst_cap = ni;
+    }
+    const size_t mneed = std::max(sb.size(), cb.size());
+    if (mneed > ctx->map_cap) {
+        free_dev(ctx->d_sb2i);
+        free_dev(ctx->d_cb2i);
+        ctx->d_sb2i = ctx->d_cb2i = nullptr;
+        ctx->map_cap = 0;
+        if ((rc = alloc_dev(ctx, (void**)&ctx->d_sb2i, sizeof(int) * mneed))) return rc;
+        if ((rc = alloc_dev(ctx, (void**)&ctx->d_cb2i, sizeof(int) * mneed))) return rc;
+        ctx->map_cap = mneed;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_inst, ctx->h_inst.data(), sizeof(Inst) * ni, hipMemcpyHostToDevice,
+                                ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_sb2i, sb.data(), sizeof(int) * sb.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_cb2i, cb.data(), sizeof(int) * cb.size(), hipMemcpyHostToDevice, ctx->stream));
+    // the host vectors must outlive the asynchronous copies
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    t->inst = ctx->d_inst;
+    t->sb2i = ctx->d_sb2i;
+    t->cb2i = ctx->d_cb2i;
+    t->ninst = ni;
+    t->sgrid = (int)sb.size();
+    t->cgrid = (int)cb.size();
+    t->dim = dim;
+    t->hinst = ctx->h_inst.data();
+    return CH_OK;
+}
+
 void init_ctl(Ctl* c, int mode, double t0, double tau0, double T, double tol, double tol_phi_fixed, double tau_min,
-              int m_max, int rec_cap) {
+              int m_max, int max_steps, ch_step_record* rec, int rec_cap) {
     memset(c, 0, sizeof(Ctl));
     c->mode = mode;
     c->t = t0;
@@ -150,33 +256,43 @@ void init_ctl(Ctl* c, int mode, double t0, double tau0, double T, double tol, do
     c->tol_phi_fixed = tol_phi_fixed;
     c->tau_min = tau_min;
     c->m_max = m_max;
-    c->rec_cap = rec_cap;
+    c->max_steps = max_steps;
+    c->rec = rec;
+    c->rec_cap = rec ? rec_cap : 0;
 }
 
 // Bytes of the control block's scalar head (everything before the Arnoldi arrays).
 constexpr size_t CTL_HEAD = offsetof(Ctl, H);
 
-int read_head(ch_ctx* ctx) {
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl, ctx->b.ctl, CTL_HEAD, hipMemcpyDeviceToHost, ctx->stream));
+int read_heads(ch_ctx* ctx, int n) {
+    for (int i = 0; i < n; ++i)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl + i, ctx->b.ctl + i, CTL_HEAD, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return CH_OK;
 }
 
-// Remaining Krylov cycles of a constant step (linear RT restarts, reading in
-// the oracle's header): re-start from the current sub-step state `z` with the
-// residual of the frozen problem, until a cycle converges on the rest of tau.
-int restart_cycles(ch_ctx* ctx, const Grid& g, int prec, PartSeq& ps, const double* y, double* z, int m_max) {
+bool all_halted(const ch_ctx* ctx, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!ctx->hctl[i].halted) return false;
+    return true;
+}
+
+// Remaining Krylov cycles of a constant step of one instance (linear RT
+// restarts, reading in the oracle's header): re-start from the current
+// sub-step state `z` with the residual of the frozen problem, until a cycle
+// converges on the rest of tau.
+int restart_cycles(ch_ctx* ctx, const Table& t, int prec, PartSeq& ps, const double* y, double* z, int m_max) {
     const DevBuffers& b = ctx->b;
     for (int cyc = 0; cyc < 100000; ++cyc) {
-        int rc = read_head(ctx);
+        int rc = read_heads(ctx, 1);
         if (rc) return rc;
-        const Ctl& h = *ctx->hctl;
+        const Ctl& h = ctx->hctl[0];
         if (h.halted || h.converged) return CH_OK;
-        HIP_TRY(ctx, launch_cycle_begin(b, ctx->stream));
-        HIP_TRY(ctx, launch_resid(g, prec, b, ps, y, z, false, false, ctx->stream));
-        HIP_TRY(ctx, launch_after_resid(b, ps, false, ctx->stream));
-        HIP_TRY(ctx, launch_arnoldi(g, prec, b, ps, y, m_max, ++ctx->cycle_id, ctx->stream));
-        HIP_TRY(ctx, launch_update(g, prec, b, z, z, ctx->stream));
+        HIP_TRY(ctx, launch_cycle_begin(t, b, ctx->stream));
+        HIP_TRY(ctx, launch_resid(t, prec, b, ps, y, z, false, false, ctx->stream));
+        HIP_TRY(ctx, launch_after_resid(t, b, ps, false, ctx->stream));
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, y, m_max, ++ctx->cycle_id, ctx->stream));
+        HIP_TRY(ctx, launch_update(t, prec, b, z, z, ctx->stream));
     }
     ctx->err = "restart cycle limit reached";
     return CH_ETAU_UNDERFLOW;
@@ -193,24 +309,48 @@ void fill_stats(const Ctl& h, ch_run_stats* st) {
     st->status = h.status;
 }
 
-int finish_run(ch_ctx* ctx, long long N, double* y, ch_run_stats* stats, ch_step_record* records, int max_rec) {
-    int rc = read_head(ctx);
-    if (rc) return rc;
-    const Ctl h = *ctx->hctl;
-    HIP_TRY(ctx, hipMemcpyAsync(y, ctx->b.ybuf[h.cur], sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
-    const int nrec = std::min(h.steps, max_rec);
-    if (records && nrec > 0)
-        HIP_TRY(ctx, hipMemcpyAsync(records, ctx->b.rec, sizeof(ch_step_record) * nrec, hipMemcpyDeviceToHost,
-                                    ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    fill_stats(h, stats);
-    return h.status;
+// Issue EE2 steps for every instance of the table until all are halted (each
+// stops at its own T or step limit) or `max_launch` steps have been issued.
+int issue_ee_steps(ch_ctx* ctx, const Table& t, int prec, int m_max, bool constant, long long max_launch) {
+    const DevBuffers& b = ctx->b;
+    PartSeq ps;
+    ps.base = b.part;
+    int rc;
+    HIP_TRY(ctx, launch_resid(t, prec, b, ps, b.ybuf[0], b.ybuf[0], true, true, ctx->stream));
+    HIP_TRY(ctx, launch_after_resid(t, b, ps, true, ctx->stream));
+    for (long long s = 0; s < max_launch; ++s) {
+        const double* yin = b.ybuf[s & 1];
+        double* yout = b.ybuf[(s + 1) & 1];
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, yin, m_max, ++ctx->cycle_id, ctx->stream));
+        HIP_TRY(ctx, launch_update(t, prec, b, yin, yout, ctx->stream));
+        if (constant && (rc = restart_cycles(ctx, t, prec, ps, yin, yout, m_max))) return rc;
+        HIP_TRY(ctx, launch_est_ee(t, prec, b, ps, yin, yout, ctx->stream));
+        HIP_TRY(ctx, launch_step_end(t, b, ps, true, ctx->stream));
+        if ((s % 16) == 15) {
+            if ((rc = read_heads(ctx, t.ninst))) return rc;
+            if (all_halted(ctx, t.ninst)) break;
+        }
+    }
+    return CH_OK;
+}
+
+int copy_in(ch_ctx* ctx, const Member& m, const double* y) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->b.ybuf[0] + m.off, y, sizeof(double) * m.sh.N, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    return CH_OK;
+}
+
+int copy_out(ch_ctx* ctx, const Member& m, int slot, double* y) {
+    const Ctl& h = ctx->hctl[slot];
+    HIP_TRY(ctx, hipMemcpyAsync(y, ctx->b.ybuf[h.cur] + m.off, sizeof(double) * m.sh.N, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    return CH_OK;
 }
 
 int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t0, double T, int max_steps,
            const ch_ee_opts* opts, ch_run_stats* stats, ch_step_record* records) {
-    Grid g;
-    int rc = check_problem(prob, &g);
+    Shape sh;
+    int rc = check_problem(prob, &sh);
     if (rc) return rc;
     if (!y || !opts) return CH_EINVAL;
     if (opts->m_max < 1 || opts->m_max > CH_MMAX) return CH_EINVAL;
@@ -220,72 +360,123 @@ int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t
     if (!(t0 < INFINITY)) return CH_EINVAL;
     const int prec = prob->prec;
     const int recs = (records && max_steps > 0) ? max_steps : 0;
-    if ((rc = ensure(ctx, g.N, opts->m_max, prec, recs, false))) return rc;
-    const DevBuffers& b = ctx->b;
+    if ((rc = ensure(ctx, pad64(sh.N), opts->m_max, prec, 1, recs, false))) return rc;
+    Member m{sh, prob->eps, prob->eyre, 0};
+    Table t;
+    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
     const bool constant = opts->constant_step != 0;
     init_ctl(ctx->hctl, constant ? MODE_EE_CONST : MODE_EE, t0, tau0, T, opts->tol, opts->tol_phi_fixed,
-             opts->tau_min, opts->m_max, recs);
-    HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(b.ybuf[0], y, sizeof(double) * g.N, hipMemcpyDeviceToDevice, ctx->stream));
-    PartSeq ps;
-    ps.base = b.part;
-    HIP_TRY(ctx, launch_resid(g, prec, b, ps, b.ybuf[0], b.ybuf[0], true, true, ctx->stream));
-    HIP_TRY(ctx, launch_after_resid(b, ps, true, ctx->stream));
-    for (long long s = 0;; ++s) {
-        if (max_steps > 0 && s >= max_steps) break;
-        const double* yin = b.ybuf[s & 1];
-        double* yout = b.ybuf[(s + 1) & 1];
-        HIP_TRY(ctx, launch_arnoldi(g, prec, b, ps, yin, opts->m_max, ++ctx->cycle_id, ctx->stream));
-        HIP_TRY(ctx, launch_update(g, prec, b, yin, yout, ctx->stream));
-        if (constant && (rc = restart_cycles(ctx, g, prec, ps, yin, yout, opts->m_max))) return rc;
-        HIP_TRY(ctx, launch_est_ee(g, prec, b, ps, yin, yout, ctx->stream));
-        HIP_TRY(ctx, launch_step_end(b, ps, true, ctx->stream));
-        if (max_steps <= 0 && (s % 16) == 15) {
-            if ((rc = read_head(ctx))) return rc;
-            if (ctx->hctl->halted) break;
-        }
+             opts->tau_min, opts->m_max, max_steps, recs ? ctx->rec : nullptr, recs);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+    if ((rc = copy_in(ctx, m, y))) return rc;
+    const long long limit = max_steps > 0 ? max_steps : (1LL << 40);
+    if ((rc = issue_ee_steps(ctx, t, prec, opts->m_max, constant, limit))) return rc;
+    if ((rc = read_heads(ctx, 1))) return rc;
+    if ((rc = copy_out(ctx, m, 0, y))) return rc;
+    const Ctl& h = ctx->hctl[0];
+    const int nrec = std::min(h.steps, recs);
+    if (records && nrec > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(records, ctx->rec, sizeof(ch_step_record) * nrec, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    fill_stats(h, stats);
+    return h.status;
+}
+
+int run_ee_batch(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, int eyre, int prec,
+                 const ch_ee_opts* opts, ch_run_stats* stats) {
+    if (count < 1 || !items || !opts) return CH_EINVAL;
+    if (prec != CH_FP64 && prec != CH_FP32_MIXED) return CH_EINVAL;
+    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step) return CH_EINVAL;
+    if (!(opts->tol > 0.0) && !(opts->tol_phi_fixed > 0.0)) return CH_EINVAL;
+    std::vector<Member> ms(count);
+    size_t pts = 0;
+    for (int i = 0; i < count; ++i) {
+        const ch_batch_item& it = items[i];
+        int rc = check_grid(dim, it.n, it.eps, eyre, &ms[i].sh);
+        if (rc) return rc;
+        if (!it.y || !(it.tau0 > 0.0) || (it.max_steps <= 0 && !(it.T < INFINITY))) return CH_EINVAL;
+        ms[i].eps = it.eps;
+        ms[i].eyre = eyre;
+        ms[i].off = pts;
+        pts += pad64(ms[i].sh.N);
     }
-    return finish_run(ctx, g.N, y, stats, records, recs);
+    int rc;
+    if ((rc = ensure(ctx, pts, opts->m_max, prec, count, 0, false))) return rc;
+    Table t;
+    if ((rc = build_table(ctx, ms, dim, &t))) return rc;
+    long long limit = 0;
+    for (int i = 0; i < count; ++i) {
+        const ch_batch_item& it = items[i];
+        init_ctl(ctx->hctl + i, MODE_EE, 0.0, it.tau0, it.T, opts->tol, opts->tol_phi_fixed, opts->tau_min,
+                 opts->m_max, it.max_steps, nullptr, 0);
+        limit = it.max_steps > 0 ? std::max<long long>(limit, it.max_steps) : (1LL << 40);
+        if ((rc = copy_in(ctx, ms[i], it.y))) return rc;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->b.ctl, ctx->hctl, sizeof(Ctl) * count, hipMemcpyHostToDevice, ctx->stream));
+    if ((rc = issue_ee_steps(ctx, t, prec, opts->m_max, false, limit))) return rc;
+    if ((rc = read_heads(ctx, count))) return rc;
+    int status = CH_OK;
+    for (int i = 0; i < count; ++i) {
+        if ((rc = copy_out(ctx, ms[i], i, items[i].y))) return rc;
+        if (stats) fill_stats(ctx->hctl[i], stats + i);
+        if (ctx->hctl[i].status != CH_OK && status == CH_OK) status = ctx->hctl[i].status;
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return status;
 }
 
 int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t0, double T, int max_steps,
             double tol, ch_run_stats* stats, ch_step_record* records) {
-    Grid g;
-    int rc = check_problem(prob, &g);
+    Shape sh;
+    int rc = check_problem(prob, &sh);
     if (rc) return rc;
     if (!y || !(tau0 > 0.0)) return CH_EINVAL;
     if (max_steps <= 0 && !(T < INFINITY)) return CH_EINVAL;
     const int recs = (records && max_steps > 0) ? max_steps : 0;
-    if ((rc = ensure(ctx, g.N, 0, CH_FP64, recs, true))) return rc;
+    if ((rc = ensure(ctx, pad64(sh.N), 0, CH_FP64, 1, recs, true))) return rc;
+    Member m{sh, prob->eps, prob->eyre, 0};
+    Table t;
+    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
     const DevBuffers& b = ctx->b;
-    init_ctl(ctx->hctl, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, t0, tau0, T, tol, 0.0, 0.0, 0, recs);
+    init_ctl(ctx->hctl, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, t0, tau0, T, tol, 0.0, 0.0, 0, max_steps,
+             recs ? ctx->rec : nullptr, recs);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(b.ybuf[0], y, sizeof(double) * g.N, hipMemcpyDeviceToDevice, ctx->stream));
+    if ((rc = copy_in(ctx, m, y))) return rc;
     PartSeq ps;
     ps.base = b.part;
     for (long long s = 0;; ++s) {
         if (max_steps > 0 && s >= max_steps) break;
         const double* yin = b.ybuf[s & 1];
         double* yout = b.ybuf[(s + 1) & 1];
-        HIP_TRY(ctx, launch_lim_begin(g, b, ps, yin, ctx->stream));
-        HIP_TRY(ctx, launch_lim_plan(g, b, ps, ctx->stream));
-        if ((rc = read_head(ctx))) return rc;
-        if (ctx->hctl->halted) break;
-        const int p = ctx->hctl->p;
+        HIP_TRY(ctx, launch_lim_begin(t, b, ps, yin, ctx->stream));
+        HIP_TRY(ctx, launch_lim_plan(t, b, ps, ctx->stream));
+        if ((rc = read_heads(ctx, 1))) return rc;
+        if (ctx->hctl[0].halted) break;
+        const int p = ctx->hctl[0].p;
         // 2p - 1 stages (m = 1..p, then m = 2..p) ping-pong between zbuf and
         // yout so that the last one lands in yout.
         const int nst = 2 * p - 1;
         const double* src = yin;
         for (int q = 0; q < nst; ++q) {
-            const int m = q < p ? q + 1 : q - p + 2;
+            const int mm = q < p ? q + 1 : q - p + 2;
             double* dst = ((nst - 1 - q) % 2 == 0) ? yout : b.zbuf;
-            HIP_TRY(ctx, launch_lim_stage(g, b, yin, src, dst, m, ctx->stream));
+            HIP_TRY(ctx, launch_lim_stage(t, b, yin, src, dst, mm, ctx->stream));
             src = dst;
         }
-        HIP_TRY(ctx, launch_est_lim(g, b, ps, yin, yout, ctx->stream));
-        HIP_TRY(ctx, launch_lim_end(b, ps, ctx->stream));
+        HIP_TRY(ctx, launch_est_lim(t, b, ps, yin, yout, ctx->stream));
+        HIP_TRY(ctx, launch_lim_end(t, b, ps, ctx->stream));
     }
-    return finish_run(ctx, g.N, y, stats, records, recs);
+    if ((rc = read_heads(ctx, 1))) return rc;
+    if ((rc = copy_out(ctx, m, 0, y))) return rc;
+    const Ctl& h = ctx->hctl[0];
+    const int nrec = std::min(h.steps, recs);
+    if (records && nrec > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(records, ctx->rec, sizeof(ch_step_record) * nrec, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    fill_stats(h, stats);
+    return h.status;
 }
 
 void record_from_head(const Ctl& h, ch_step_record* out) {
@@ -333,7 +524,8 @@ int ch_destroy(ch_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     DevBuffers& b = ctx->b;
     for (void* p : {(void*)b.V, (void*)b.ybuf[0], (void*)b.ybuf[1], (void*)b.fcur, (void*)b.y32, (void*)b.zbuf,
-                    (void*)b.part, (void*)b.ctl, (void*)b.rec})
+                    (void*)b.part, (void*)b.ctl, (void*)ctx->rec, (void*)ctx->d_inst, (void*)ctx->d_sb2i,
+                    (void*)ctx->d_cb2i})
         free_dev(p);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
     if (ctx->hflag) (void)hipHostFree(ctx->hflag);
@@ -374,6 +566,13 @@ int ch_step_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau, doubl
     return rc;
 }
 
+int ch_run_ee_batch(ch_ctx* ctx, int count, ch_batch_item* items, int dim, int eyre, int prec,
+                    const ch_ee_opts* opts, ch_run_stats* stats) {
+    if (!ctx) return CH_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
+    return run_ee_batch(ctx, count, items, dim, eyre, prec, opts, stats);
+}
+
 int ch_run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t0, double T, int max_steps,
                double tol, ch_run_stats* stats, ch_step_record* records) {
     if (!ctx) return CH_EINVAL;
@@ -395,69 +594,78 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
             double tol_phi, int m_max, ch_step_record* out) {
     if (!ctx) return CH_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
-    Grid g;
-    int rc = check_problem(prob, &g);
+    Shape sh;
+    int rc = check_problem(prob, &sh);
     if (rc) return rc;
     if (!y || !y_out || y == y_out) return CH_EINVAL;
     if (!(tau0 > 0.0) || !(tol_phi > 0.0) || m_max < 1 || m_max > CH_MMAX) return CH_EINVAL;
     if (mode != CH_PHI_SHRINK && mode != CH_PHI_RESTART) return CH_EINVAL;
     const int prec = prob->prec;
-    if ((rc = ensure(ctx, g.N, m_max, prec, 0, false))) return rc;
+    if ((rc = ensure(ctx, pad64(sh.N), m_max, prec, 1, 0, false))) return rc;
+    Member m{sh, prob->eps, prob->eyre, 0};
+    Table t;
+    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
     const DevBuffers& b = ctx->b;
-    init_ctl(ctx->hctl, MODE_PHI, 0.0, tau0, INFINITY, 0.0, tol_phi, 0.0, m_max, 0);
+    init_ctl(ctx->hctl, MODE_PHI, 0.0, tau0, INFINITY, 0.0, tol_phi, 0.0, m_max, 0, nullptr, 0);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+    if ((rc = copy_in(ctx, m, y))) return rc;
     PartSeq ps;
     ps.base = b.part;
-    HIP_TRY(ctx, launch_resid(g, prec, b, ps, y, y, false, true, ctx->stream));
-    HIP_TRY(ctx, launch_after_resid(b, ps, true, ctx->stream));
-    HIP_TRY(ctx, launch_arnoldi(g, prec, b, ps, y, m_max, ++ctx->cycle_id, ctx->stream));
-    HIP_TRY(ctx, launch_update(g, prec, b, y, y_out, ctx->stream));
-    if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, g, prec, ps, y, y_out, m_max))) return rc;
-    if ((rc = read_head(ctx))) return rc;
-    record_from_head(*ctx->hctl, out);
-    return ctx->hctl->status;
+    HIP_TRY(ctx, launch_resid(t, prec, b, ps, b.ybuf[0], b.ybuf[0], false, true, ctx->stream));
+    HIP_TRY(ctx, launch_after_resid(t, b, ps, true, ctx->stream));
+    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, ++ctx->cycle_id, ctx->stream));
+    HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[0], b.ybuf[1], ctx->stream));
+    if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[0], b.ybuf[1], m_max))) return rc;
+    if ((rc = read_heads(ctx, 1))) return rc;
+    const Ctl& h = ctx->hctl[0];
+    if (h.status == CH_OK)
+        HIP_TRY(ctx, hipMemcpyAsync(y_out, b.ybuf[1], sizeof(double) * sh.N, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    record_from_head(h, out);
+    return h.status;
 }
 
 int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, int reps, double* avg_us,
                    double* bytes) {
     if (!ctx || !avg_us || !bytes || reps < 1) return CH_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
-    Grid g;
-    int rc = check_problem(prob, &g);
+    Shape sh;
+    int rc = check_problem(prob, &sh);
     if (rc) return rc;
     if (m_max < 2 || m_max > CH_MMAX) return CH_EINVAL;
+    if (kernel != CH_KERNEL_MGS && kernel != CH_KERNEL_MATVEC && kernel != CH_KERNEL_PHI) return CH_EINVAL;
     const int prec = prob->prec;
     const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
     const DevBuffers& b = ctx->b;
-    if (!b.ctl || ctx->state_n < (size_t)g.N || ctx->v_bytes < (size_t)(m_max + 1) * b.ldv * esz ||
-        b.ldv < (size_t)g.N || (prec == CH_FP32_MIXED && ctx->y32_n < (size_t)g.N))
+    if (!b.ctl || ctx->pts < (size_t)sh.N || ctx->v_bytes < (size_t)(m_max + 1) * b.ldv * esz ||
+        (prec == CH_FP32_MIXED && ctx->y32_pts < (size_t)sh.N))
         return CH_EINVAL;   // no run on this problem yet
-    // Control block: live, coefficients of a no-op axpy, unit scales.
+    Member m{sh, prob->eps, prob->eyre, 0};
+    Table t;
+    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
+    // Control block: live, unit scales; zero partials in, so the timed axpy
+    // coefficient is 0 and the phi kernel sees h_{j+1,j} = 0 (its convergence branch)
     HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl, b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    Ctl& h = *ctx->hctl;
+    Ctl& h = ctx->hctl[0];
     const int jlast = h.last_j;
+    if (kernel == CH_KERNEL_PHI && jlast < 1) return CH_EINVAL;
     h.done = 0;
     h.halted = 0;
     h.vscale[0] = h.vscale[1] = h.vscale[2] = 1.0;
-    h.tol_phi = 1.0;   // phi timing: the convergence branch, no trace
+    h.tol_phi = 1.0;
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
-    // partials slots: zeros in, so the timed axpy coefficient is 0 and the phi
-    // kernel sees h_{j+1,j} = 0 (its convergence branch)
     HIP_TRY(ctx, hipMemsetAsync(b.part, 0, 2 * sizeof(double) * CH_NRED * CH_MAXB, ctx->stream));
     const double* y = b.ybuf[0];
     auto launch = [&]() -> hipError_t {
         PartSeq ps;
         ps.base = b.part;
-        ps.np = 1;
         switch (kernel) {
-            case CH_KERNEL_MGS: return launch_mgs_pass(g, prec, b, ps, 1, 1, ctx->stream);
-            case CH_KERNEL_MATVEC: return launch_matvec(g, prec, b, ps, y, 0, ctx->stream);
-            default: return launch_phi(b, ps, jlast > 0 ? jlast - 1 : 0, -2, ctx->stream);
+            case CH_KERNEL_MGS: return launch_mgs_pass(t, prec, b, ps, 1, 1, ctx->stream);
+            case CH_KERNEL_MATVEC: return launch_matvec(t, prec, b, ps, y, 0, ctx->stream);
+            default: return launch_phi(t, b, ps, jlast - 1, -2, ctx->stream);
         }
     };
-    if (kernel != CH_KERNEL_MGS && kernel != CH_KERNEL_MATVEC && kernel != CH_KERNEL_PHI) return CH_EINVAL;
-    if (kernel == CH_KERNEL_PHI && jlast < 1) return CH_EINVAL;
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
@@ -475,7 +683,7 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *avg_us = 1000.0 * ms / reps;
-    const double N = double(g.N);
+    const double N = double(sh.N);
     const double ysz = prec == CH_FP64 ? 8.0 : 4.0;
     if (kernel == CH_KERNEL_MGS) *bytes = 4.0 * esz * N;                 // read w, v_{i-1}, v_i; write w
     else if (kernel == CH_KERNEL_MATVEC) *bytes = (3.0 * esz + ysz) * N; // read v_k, y, v_1; write w

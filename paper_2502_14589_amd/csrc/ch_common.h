@@ -55,7 +55,7 @@ __device__ __forceinline__ double red_identity() {
 template <int NR, int OP>
 __device__ __forceinline__ void block_reduce(double (&x)[NR], double (*lds)[NR]) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nw = (blockDim.x + 63) >> 6;
+    constexpr int nw = CH_BLOCK / 64;
 #pragma unroll
     for (int r = 0; r < NR; ++r) x[r] = red_wave<OP>(x[r]);
     if (lane == 0) {
@@ -91,17 +91,27 @@ __device__ __forceinline__ void write_partials(double (&x)[NR], double* __restri
     }
 }
 
-// Total of the `np` partials of each of the NR sums, returned in every thread.
+// Total of the partials [p0, p0 + np) of each of the NR sums, returned in every
+// thread.  np <= CH_PART_PER_THREAD * CH_BLOCK; every thread issues its loads
+// at once (one memory latency), then adds them in a fixed order.
+#define CH_PART_PER_THREAD 8
 template <int NR, int OP>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ pin, int np, double (&tot)[NR]) {
+__device__ __forceinline__ void sum_partials(const double* __restrict__ pin, int p0, int np, double (&tot)[NR]) {
     __shared__ double lds[16][NR];
     __shared__ double res[NR];
+    double v[NR][CH_PART_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < CH_PART_PER_THREAD; ++u) {
+        const int b = threadIdx.x + u * CH_BLOCK;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r][u] = b < np ? pin[r * CH_MAXB + p0 + b] : red_identity<OP>();
+    }
     double s[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) s[r] = red_identity<OP>();
-    for (int b = threadIdx.x; b < np; b += blockDim.x) {
+    for (int r = 0; r < NR; ++r) {
+        s[r] = v[r][0];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) s[r] = red_combine<OP>(s[r], pin[r * CH_MAXB + b]);
+        for (int u = 1; u < CH_PART_PER_THREAD; ++u) s[r] = red_combine<OP>(s[r], v[r][u]);
     }
     block_reduce<NR, OP>(s, lds);
     if (threadIdx.x == 0) {
@@ -111,6 +121,17 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ pin, int
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < NR; ++r) tot[r] = res[r];
+}
+
+// The partials an instance's consumer adds up: those of its stencil or of its
+// streaming workgroups, whichever kind produced them.
+template <int NR, int OP>
+__device__ __forceinline__ void sum_inst_partials(const double* __restrict__ pin, const Inst& I, int by_stencil,
+                                                  double (&tot)[NR]) {
+    if (by_stencil)
+        sum_partials<NR, OP>(pin, I.sblk0, I.sblk, tot);
+    else
+        sum_partials<NR, OP>(pin, I.cblk0, I.cblk, tot);
 }
 
 // ---------------------------------------------------------------------------
@@ -184,7 +205,7 @@ __device__ __forceinline__ void load_region(const TileOrigin& o, int n, const TS
     const bool interior = o.x0 >= H && o.x0 + Geo<DIM>::TX + H <= n && o.y0 >= H &&
                           o.y0 + Geo<DIM>::TY + H <= n &&
                           (DIM == 2 || (o.z0 >= H && o.z0 + Geo<DIM>::TZ + H <= n));
-    for (int i = threadIdx.x; i < R::SIZE; i += blockDim.x) {
+    for (int i = threadIdx.x; i < R::SIZE; i += CH_BLOCK) {
         const int cx = i % R::X;
         const int rr = i / R::X;
         const int cy = rr % R::Y;

@@ -7,7 +7,10 @@
 #include "../../include/ch.h"
 
 #define CH_LDH (CH_MMAX + 1)     // leading dimension of the Hessenberg matrix
-#define CH_MAXB 4096             // most workgroups of a reducing launch (partials per reduction)
+#define CH_MAXB 32768            // most workgroups of a reducing launch (partials per reduction)
+#define CH_SBLK_MAX 2048         // most stencil workgroups per instance (larger grids loop over tiles);
+                                 // <= 8 * CH_BLOCK partials per instance (sum_partials)
+#define CH_CBLK_MAX 512          // most streaming workgroups per instance
 #define CH_NRED 4                // most sums reduced by one launch
 #define CH_BLOCK 256             // threads per workgroup of the streaming and stencil kernels
 
@@ -20,7 +23,8 @@ enum CtlMode { MODE_EE = 0, MODE_EE_CONST = 1, MODE_LIM = 2, MODE_LIM_CONST = 3,
 struct Ctl {
     // run constants
     double T, tol, tol_phi_fixed, tau_min, tau_fixed;
-    int mode, m_max, rec_cap, pad0;
+    int mode, m_max, rec_cap, max_steps;   // max_steps <= 0: no step limit
+    ch_step_record* rec;                   // rec_cap records (device), or null
     // run state
     double t, tau;
     int cur;         // ping-pong buffer holding the latest accepted state
@@ -43,63 +47,82 @@ struct Ctl {
     double u[CH_MMAX];            // tau phi(-tau H) e_1
 };
 
+// One instance of a batch: a periodic grid whose fields live at `off` in
+// every pooled array.  Kernels cover all instances of a batch in one launch;
+// a block-to-instance map gives each workgroup its instance, and each
+// instance owns a contiguous range of workgroups (and so of partials).
+struct Inst {
+    long long off;      // first point of the instance in the pooled arrays
+    long long N;        // points
+    int n;              // points per direction
+    int slot;           // control block index
+    int sblk0, sblk;    // stencil workgroups [sblk0, sblk0 + sblk)
+    int cblk0, cblk;    // streaming workgroups [cblk0, cblk0 + cblk)
+    double eps2, inv_h2;
+    int eyre, pad;
+};
+
 struct DevBuffers {
-    void* V;            // Krylov basis, (m_max + 1) columns of ldv elements (FP64 or FP32)
+    void* V;            // Krylov basis: (m_max + 1) pooled columns of ldv elements (FP64 or FP32)
     size_t ldv;
-    double* ybuf[2];    // FP64 state ping-pong
+    double* ybuf[2];    // FP64 state ping-pong (pooled)
     double* fcur;       // FP64 f(y^n) (start vector of the step, unnormalised)
     float* y32;         // FP32 copy of y^n (mixed precision only)
     double* zbuf;       // FP64 scratch (LIM stages)
     double* part;       // reduction partials: two slots of CH_NRED * CH_MAXB
-    Ctl* ctl;
-    ch_step_record* rec;
-    int* dflag;                  // device view of `hflag`
-    const volatile int* hflag;   // pinned host word: id of the last finished Krylov cycle
+    Ctl* ctl;           // control blocks, one per slot
+    int* dflag;         // device view of `hflag`, one word per slot
+    const volatile int* hflag;   // pinned host words: id of the last finished Krylov cycle per slot
 };
 
-struct Grid {
-    int dim, n;
-    long long N;
-    double eps2, inv_h2;
-    int eyre;
+// The instance table of one launch sequence (device pointers + host mirror sizes).
+struct Table {
+    const Inst* inst;   // ninst entries
+    const int* sb2i;    // stencil workgroup -> instance
+    const int* cb2i;    // streaming workgroup -> instance
+    int ninst, sgrid, cgrid, dim;
+    const Inst* hinst;  // host copy
 };
+
 
 // Partials of the grid reductions alternate between two slots: a producer
 // writes slot `par`, the next consumer reads the other one (written by the
-// previous producer).
+// previous producer).  `stencil` records which workgroup ranges produced them.
 struct PartSeq {
     double* base = nullptr;
     int par = 0;
-    int np = 0;   // workgroups (partials) of the last producer
+    int stencil = 0;
     double* in() const { return base + (size_t)(par ^ 1) * CH_NRED * CH_MAXB; }
     double* out() const { return base + (size_t)par * CH_NRED * CH_MAXB; }
-    void produced(int G) {
-        np = G;
+    void produced(bool by_stencil) {
+        stencil = by_stencil ? 1 : 0;
         par ^= 1;
     }
 };
 
 // Kernel launchers (ch_stencil.hip, ch_krylov.hip); all asynchronous on `s`.
-hipError_t launch_resid(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, const double* y, const double* z,
+// `dim` and `prec` are common to all instances of a table.  Field arguments
+// are pooled FP64 arrays; each instance reads and writes its slice at `off`.
+hipError_t launch_resid(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, const double* z,
                         bool write_f, bool write_y32, hipStream_t s);
-hipError_t launch_after_resid(const DevBuffers& b, PartSeq& ps, bool begin_step, hipStream_t s);
-hipError_t launch_cycle_begin(const DevBuffers& b, hipStream_t s);
-hipError_t launch_matvec(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
+hipError_t launch_after_resid(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_step, hipStream_t s);
+hipError_t launch_cycle_begin(const Table& t, const DevBuffers& b, hipStream_t s);
+hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
                          hipStream_t s);
-hipError_t launch_mgs_pass(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
-hipError_t launch_phi(const DevBuffers& b, PartSeq& ps, int k, int cycle_id, hipStream_t s);
-// Issues the Arnoldi iterations of one Krylov cycle; stops issuing once the
-// device has reported the cycle finished (those launches would exit at once).
-hipError_t launch_arnoldi(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
+hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
+hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int cycle_id, hipStream_t s);
+// Issues the Arnoldi iterations of one Krylov cycle; stops issuing once every
+// instance has reported the cycle finished (later launches would exit at once).
+hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
                           int cycle_id, hipStream_t s);
-hipError_t launch_update(const Grid& g, int prec, const DevBuffers& b, const double* y, double* ynew, hipStream_t s);
-hipError_t launch_est_ee(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, const double* y0,
+hipError_t launch_update(const Table& t, int prec, const DevBuffers& b, const double* y, double* ynew, hipStream_t s);
+hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y0,
                          const double* y1, hipStream_t s);
-hipError_t launch_step_end(const DevBuffers& b, PartSeq& ps, bool begin_next, hipStream_t s);
-hipError_t launch_lim_begin(const Grid& g, const DevBuffers& b, PartSeq& ps, const double* y, hipStream_t s);
-hipError_t launch_lim_plan(const Grid& g, const DevBuffers& b, PartSeq& ps, hipStream_t s);
-hipError_t launch_lim_stage(const Grid& g, const DevBuffers& b, const double* y, const double* z, double* out,
+hipError_t launch_step_end(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_next, hipStream_t s);
+hipError_t launch_lim_begin(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y, hipStream_t s);
+hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s);
+hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
                             int m, hipStream_t s);
-hipError_t launch_est_lim(const Grid& g, const DevBuffers& b, PartSeq& ps, const double* y0, const double* y1,
+hipError_t launch_est_lim(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y0, const double* y1,
                           hipStream_t s);
-hipError_t launch_lim_end(const DevBuffers& b, PartSeq& ps, hipStream_t s);
+hipError_t launch_lim_end(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s);

@@ -9,7 +9,10 @@
 // then y^{n+1} = y^n + V_j (beta u).
 //
 // Storage: column i of the basis is kept unnormalised, v_i = vscale[i] V(:,i),
-// so the normalisation of line 21 is folded into the next reads.
+// so the normalisation of line 21 is folded into the next reads.  One launch
+// covers every instance of a batch; streaming kernels give each instance the
+// workgroups [cblk0, cblk0 + cblk) (map cb2i), single-workgroup kernels one
+// workgroup per instance.
 #include "ch_common.h"
 
 namespace {
@@ -20,27 +23,37 @@ namespace {
 //   w -= h_{i-1,k} v_{i-1};  partials of <w, v_i>  (or of ||w||^2 when FINAL).
 // FP64 accumulation of the dot products in both precisions.
 // ---------------------------------------------------------------------------
-template <typename TV, bool FINAL>
-__global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctl, TV* __restrict__ W,
-                                                  const TV* __restrict__ Vp, const TV* __restrict__ Vn, int k,
-                                                  int i, long long N, const double* __restrict__ pin, int nin,
+template <typename TV, bool FINAL, bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                  const int* __restrict__ cb2i, const Inst inst0, int ninst, TV* __restrict__ V, size_t ldv, int k,
+                                                  int i, const double* __restrict__ pin, int pin_stencil,
                                                   double* __restrict__ pout) {
-    if (ctl->done | ctl->halted) return;
+    const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    // the exit flag and the partials are fetched together (the partials of a
+    // finished cycle are simply not used)
+    const int finished = ctl->done | ctl->halted;
     using VT = typename Vec16<TV>::type;
     constexpr int VW = Vec16<TV>::W;
+    TV* W = V + (size_t)(k + 1) * ldv + I.off;
+    const TV* Vp = V + (size_t)(FINAL ? k : i - 1) * ldv + I.off;
+    const TV* Vn = V + (size_t)i * ldv + I.off;
     double dot[1];
-    sum_partials<1, RED_SUM>(pin, nin, dot);
+    sum_inst_partials<1, RED_SUM>(pin, I, pin_stencil, dot);
+    if (finished) return;
     const double sp = ctl->vscale[i - 1];
     const double h = sp * dot[0];
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->H[(i - 1) + k * CH_LDH] = h;
+    if (blockIdx.x == I.cblk0 && threadIdx.x == 0) ctl->H[(i - 1) + k * CH_LDH] = h;
     const TV c = TV(sp * h);
     double acc = 0.0;
+    const long long N = I.N;
     const long long NV = N / VW;
     VT* W4 = reinterpret_cast<VT*>(W);
     const VT* P4 = reinterpret_cast<const VT*>(Vp);
     const VT* N4 = reinterpret_cast<const VT*>(Vn);
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < NV; q += stride) {
+    const long long stride = (long long)I.cblk * CH_BLOCK;
+    const long long first = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
+    for (long long q = first; q < NV; q += stride) {
         VT w = W4[q];
         const VT p = P4[q];
         TV* we = reinterpret_cast<TV*>(&w);
@@ -58,7 +71,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctl, TV* __r
             for (int e = 0; e < VW; ++e) acc += double(we[e]) * double(ne[e]);
         }
     }
-    for (long long q = NV * VW + (long long)blockIdx.x * blockDim.x + threadIdx.x; q < N; q += stride) {
+    for (long long q = NV * VW + first; q < N; q += stride) {
         const TV w = W[q] - c * Vp[q];
         W[q] = w;
         acc += FINAL ? double(w) * double(w) : double(w) * double(Vn[q]);
@@ -70,19 +83,25 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctl, TV* __r
 // ---------------------------------------------------------------------------
 // y^{n+1} = y^n + V_j (beta u)  (Fig. 3, line 23)
 // ---------------------------------------------------------------------------
-template <typename TV>
-__global__ __launch_bounds__(CH_BLOCK) void k_update(Ctl* __restrict__ ctl, const double* y,
-                                                     const TV* __restrict__ V, size_t ldv, double* ynew,
-                                                     long long N) {   // y may alias ynew (restart cycles)
+template <typename TV, bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                     const int* __restrict__ cb2i, const Inst inst0, int ninst, const double* ybase,
+                                                     const TV* __restrict__ V, size_t ldv, double* ynewbase) {
+    // ybase may alias ynewbase (restart cycles update the sub-step state in place)
+    const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
     __shared__ double cf[CH_MMAX];
     const int j = ctl->j;
     if ((int)threadIdx.x < j) cf[threadIdx.x] = ctl->beta * ctl->u[threadIdx.x] * ctl->vscale[threadIdx.x];
     __syncthreads();
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < N; q += stride) {
+    const double* y = ybase + I.off;
+    double* ynew = ynewbase + I.off;
+    const TV* Vi = V + I.off;
+    const long long stride = (long long)I.cblk * CH_BLOCK;
+    for (long long q = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x; q < I.N; q += stride) {
         double acc = 0.0;
-        for (int i = 0; i < j; ++i) acc += cf[i] * double(V[(size_t)i * ldv + q]);
+        for (int i = 0; i < j; ++i) acc += cf[i] * double(Vi[(size_t)i * ldv + q]);
         ynew[q] = y[q] + acc;
     }
 }
@@ -108,7 +127,7 @@ struct PhiShared {
 };
 
 __device__ void mm(double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B, int n) {
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
         const int r = idx / n, c = idx - r * n;
         const double* a = A + r * PLD;
         double acc = 0.0;
@@ -140,7 +159,7 @@ __device__ void lu_solve(PhiShared& S, double* Q, double* P, int n) {
         __syncthreads();
         const int piv = S.ired;
         if (piv != col) {
-            for (int c = threadIdx.x; c < 2 * n; c += blockDim.x) {
+            for (int c = threadIdx.x; c < 2 * n; c += CH_BLOCK) {
                 double* Mx = c < n ? Q : P;
                 const int cc = c < n ? c : c - n;
                 const double tmp = Mx[col * PLD + cc];
@@ -151,7 +170,7 @@ __device__ void lu_solve(PhiShared& S, double* Q, double* P, int n) {
         __syncthreads();
         const double pv = Q[col * PLD + col];
         const int rows = n - col - 1, qc = n - col - 1, cols = qc + n;
-        for (int idx = threadIdx.x; idx < rows * cols; idx += blockDim.x) {
+        for (int idx = threadIdx.x; idx < rows * cols; idx += CH_BLOCK) {
             const int rr = col + 1 + idx / cols;
             const int kk = idx % cols;
             const double l = Q[rr * PLD + col] / pv;
@@ -167,9 +186,9 @@ __device__ void lu_solve(PhiShared& S, double* Q, double* P, int n) {
     }
     for (int col = n - 1; col >= 0; --col) {
         const double pv = Q[col * PLD + col];
-        for (int c = threadIdx.x; c < n; c += blockDim.x) P[col * PLD + c] /= pv;
+        for (int c = threadIdx.x; c < n; c += CH_BLOCK) P[col * PLD + c] /= pv;
         __syncthreads();
-        for (int idx = threadIdx.x; idx < col * n; idx += blockDim.x) {
+        for (int idx = threadIdx.x; idx < col * n; idx += CH_BLOCK) {
             const int rr = idx / n, c = idx - rr * n;
             P[rr * PLD + c] -= Q[rr * PLD + col] * P[col * PLD + c];
         }
@@ -189,7 +208,7 @@ __device__ const double* expm_aug(PhiShared& S, const double* __restrict__ H, in
     double* A6 = S.B[3];
     double* T1 = S.B[4];
     double* T2 = S.B[5];
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
         const int r = idx / n, c = idx - r * n;
         double v = 0.0;
         if (r < j && c < j) v = -s * H[r + c * CH_LDH];
@@ -210,7 +229,7 @@ __device__ const double* expm_aug(PhiShared& S, const double* __restrict__ H, in
     if (nrm > THETA13 && nrm < __builtin_inf()) nsq = (int)ceil(log2(nrm / THETA13));
     if (nsq > 1100) nsq = 1100;
     const double scale = ldexp(1.0, -nsq);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
         const int r = idx / n, c = idx - r * n;
         M[r * PLD + c] *= scale;
     }
@@ -219,25 +238,25 @@ __device__ const double* expm_aug(PhiShared& S, const double* __restrict__ H, in
     mm(A2, M, M, n);
     mm(A4, A2, A2, n);
     mm(A6, A4, A2, n);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
         const int o = (idx / n) * PLD + idx % n;
         T1[o] = cf[13] * A6[o] + cf[11] * A4[o] + cf[9] * A2[o];
     }
     __syncthreads();
     mm(T2, A6, T1, n);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
         const int r = idx / n, c = idx - r * n, o = r * PLD + c;
         T2[o] += cf[7] * A6[o] + cf[5] * A4[o] + cf[3] * A2[o] + (r == c ? cf[1] : 0.0);
     }
     __syncthreads();
     mm(T1, M, T2, n);   // U (odd part)
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
         const int o = (idx / n) * PLD + idx % n;
         T2[o] = cf[12] * A6[o] + cf[10] * A4[o] + cf[8] * A2[o];
     }
     __syncthreads();
     mm(M, A6, T2, n);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
         const int r = idx / n, c = idx - r * n, o = r * PLD + c;
         const double V = M[o] + cf[6] * A6[o] + cf[4] * A4[o] + cf[2] * A2[o] + (r == c ? cf[0] : 0.0);
         const double U = T1[o];
@@ -263,7 +282,7 @@ __device__ const double* expm_aug(PhiShared& S, const double* __restrict__ H, in
 }
 
 __device__ void store_u(Ctl* ctl, const double* E, int j) {
-    for (int i = threadIdx.x; i < j; i += blockDim.x) ctl->u[i] = E[i * PLD + j];
+    for (int i = threadIdx.x; i < j; i += CH_BLOCK) ctl->u[i] = E[i * PLD + j];
 }
 
 // ---------------------------------------------------------------------------
@@ -278,13 +297,18 @@ __device__ void store_u(Ctl* ctl, const double* E, int j) {
 // h_{j+1,j} |e_j^T exp(-s H) e_1| from the same exponential, safeguarded by the
 // bracket, to a relative precision of about 1e-14.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctl, int k, const double* __restrict__ pin,
-                                                  int nin, int cycle_id, int* __restrict__ dflag) {
+template <bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst, int k,
+                                                  const double* __restrict__ pin, int pin_stencil, int cycle_id,
+                                                  int* __restrict__ dflags) {
+    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];   // one workgroup per instance
+    Ctl* ctl = ctls + I.slot;
+    int* dflag = dflags ? dflags + I.slot : nullptr;
     if (ctl->done | ctl->halted) return;
     __shared__ PhiShared S;
     // h_{k+2,k+1} = ||w|| from the final Gram-Schmidt pass (Fig. 3, line 9)
     double nrm2[1];
-    sum_partials<1, RED_SUM>(pin, nin, nrm2);
+    sum_inst_partials<1, RED_SUM>(pin, I, pin_stencil, nrm2);
     const double hnext = sqrt(nrm2[0]);
     if (threadIdx.x == 0) {
         ctl->H[(k + 1) + k * CH_LDH] = hnext;
@@ -429,7 +453,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctl, int k, 
 // ---------------------------------------------------------------------------
 __device__ void begin_step(Ctl* ctl) {
     if (ctl->halted) return;
-    if (!(ctl->t < ctl->T)) {
+    if (!(ctl->t < ctl->T) || (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps)) {
         ctl->halted = 1;
         return;
     }
@@ -466,11 +490,14 @@ __device__ void begin_step(Ctl* ctl) {
 
 // After a residual start vector: beta = ||v_1||, ||ghat||; then either the
 // begin of a step or (restart cycles) the normalisation of the new start.
-__global__ __launch_bounds__(CH_BLOCK) void k_after_resid(Ctl* __restrict__ ctl, const double* __restrict__ pin,
-                                                          int nin, int begin) {
+template <bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_after_resid(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst,
+                                                          const double* __restrict__ pin, int pin_stencil, int begin) {
+    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];
+    Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
     double tot[2];
-    sum_partials<2, RED_SUM>(pin, nin, tot);
+    sum_inst_partials<2, RED_SUM>(pin, I, pin_stencil, tot);
     if (threadIdx.x != 0) return;
     const double beta = sqrt(tot[0]), gn = sqrt(tot[1]);
     if (!(beta < __builtin_inf()) || !(gn < __builtin_inf())) {
@@ -494,8 +521,10 @@ __global__ __launch_bounds__(CH_BLOCK) void k_after_resid(Ctl* __restrict__ ctl,
 
 // Between linear RT restart cycles of a constant step: account for the cycle
 // just finished and aim the next one at the remaining time.
-__global__ void k_cycle_begin(Ctl* __restrict__ ctl) {
-    if (threadIdx.x != 0 || ctl->halted) return;
+template <bool SINGLE>
+__global__ void k_cycle_begin(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst) {
+    Ctl* ctl = ctls + (SINGLE ? inst0.slot : insts[blockIdx.x].slot);
+    if (threadIdx.x != 0 || ctl->halted || ctl->converged) return;
     ctl->covered += ctl->tau_acc;
     ctl->restarts += 1;
     ctl->mv_step += 1 + ctl->j;
@@ -511,11 +540,15 @@ __global__ void k_cycle_begin(Ctl* __restrict__ ctl) {
 // EE2 step end (Fig. 4, lines 8-10): est (eq. LIMest), t, tau_new (eq. EEdt);
 // optionally the begin of the next step.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(CH_BLOCK) void k_step_end(Ctl* __restrict__ ctl, const double* __restrict__ pin, int nin,
-                                                       ch_step_record* __restrict__ rec, int begin_next) {
+template <bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_step_end(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst,
+                                                       const double* __restrict__ pin, int pin_stencil,
+                                                       int begin_next) {
+    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];
+    Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
     double tot[4];
-    sum_partials<4, RED_SUM>(pin, nin, tot);
+    sum_inst_partials<4, RED_SUM>(pin, I, pin_stencil, tot);
     if (threadIdx.x != 0) return;
     const double num = sqrt(tot[0]), den = sqrt(tot[1]);
     const double est = den > 0.0 ? num / den : 0.0;
@@ -538,8 +571,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_step_end(Ctl* __restrict__ ctl, co
     }
     const int mv = ctl->mv_step + 1 + ctl->j;
     ctl->last_j = ctl->j;
-    if (ctl->steps < ctl->rec_cap) {
-        ch_step_record& r = rec[ctl->steps];
+    if (ctl->rec && ctl->steps < ctl->rec_cap) {
+        ch_step_record& r = ctl->rec[ctl->steps];
         r.t = t_new;
         r.tau = tau_used;
         r.tau_next = tau_next;
@@ -562,7 +595,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_step_end(Ctl* __restrict__ ctl, co
     ctl->traces += ctl->traced;
     ctl->steps += 1;
     ctl->cur ^= 1;
-    if (!(t_new < ctl->T)) {
+    if (!(t_new < ctl->T) || (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps)) {
         ctl->halted = 1;
         return;
     }
@@ -573,12 +606,17 @@ __global__ __launch_bounds__(CH_BLOCK) void k_step_end(Ctl* __restrict__ ctl, co
 // LIM step begin (Fig. 1, steps 1-2; Fig. 2, lines 3-5): partials of
 // min/max y^2 (and a non-finite flag) ...
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctl, const double* __restrict__ y,
-                                                        long long N, double* __restrict__ pout) {
+template <bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                        const int* __restrict__ cb2i, const Inst inst0, int ninst, const double* __restrict__ ybase,
+                                                        double* __restrict__ pout) {
+    const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
+    const double* y = ybase + I.off;
     double mn = __builtin_inf(), mx = -__builtin_inf(), bad = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < N; q += stride) {
+    const long long stride = (long long)I.cblk * CH_BLOCK;
+    for (long long q = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x; q < I.N; q += stride) {
         const double v = y[q] * y[q];
         if (v < __builtin_inf()) {
             mn = fmin(mn, v);
@@ -597,11 +635,14 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctl, c
 // max(g(d_min), g(d_max)):
 //   2-D: g(d) = |4d/h^2 + 20e| + 4|d/h^2 + 8e| + 12e,      e = eps^2/h^4
 //   3-D: g(d) = |6d/h^2 + 42e| + 6|d/h^2 + 12e| + 30e
-__global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctl, const double* __restrict__ pin, int nin,
-                                                       int dim, double eps2, double inv_h2, int eyre) {
+template <bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst,
+                                                       const double* __restrict__ pin, int pin_stencil, int dim) {
+    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];
+    Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
     double tot[3];
-    sum_partials<3, RED_MAX>(pin, nin, tot);
+    sum_inst_partials<3, RED_MAX>(pin, I, pin_stencil, tot);
     if (threadIdx.x != 0) return;
     const double ymin2 = -tot[0], ymax2 = tot[1];
     if (tot[2] != 0.0) {
@@ -609,7 +650,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctl, co
         ctl->halted = 1;
         return;
     }
-    if (!(ctl->t < ctl->T)) {
+    if (!(ctl->t < ctl->T) || (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps)) {
         ctl->halted = 1;
         return;
     }
@@ -619,8 +660,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctl, co
         tau = ctl->T - ctl->t;
         clipped = 1;
     }
-    const double e = eps2 * inv_h2 * inv_h2;
-    const double dmin = 3.0 * ymin2 - 1.0 + eyre, dmax = 3.0 * ymax2 - 1.0 + eyre;
+    const double inv_h2 = I.inv_h2;
+    const double e = I.eps2 * inv_h2 * inv_h2;
+    const double dmin = 3.0 * ymin2 - 1.0 + I.eyre, dmax = 3.0 * ymax2 - 1.0 + I.eyre;
     double gmin, gmax;
     if (dim == 2) {
         gmin = fabs(4.0 * dmin * inv_h2 + 20.0 * e) + 4.0 * fabs(dmin * inv_h2 + 8.0 * e) + 12.0 * e;
@@ -644,11 +686,14 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctl, co
 }
 
 // LIM step end (Fig. 2, lines 8-10): est (eq. LIMest), t, tau_new (eq. LIMdt).
-__global__ __launch_bounds__(CH_BLOCK) void k_lim_end(Ctl* __restrict__ ctl, const double* __restrict__ pin, int nin,
-                                                      ch_step_record* __restrict__ rec) {
+template <bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_lim_end(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst,
+                                                      const double* __restrict__ pin, int pin_stencil) {
+    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];
+    Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
     double tot[2];
-    sum_partials<2, RED_SUM>(pin, nin, tot);
+    sum_inst_partials<2, RED_SUM>(pin, I, pin_stencil, tot);
     if (threadIdx.x != 0) return;
     const double num = sqrt(tot[0]), den = sqrt(tot[1]);
     const double est = den > 0.0 ? num / den : 0.0;
@@ -663,8 +708,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_end(Ctl* __restrict__ ctl, con
     if (ctl->mode == MODE_LIM) tau_next = est == 0.0 ? tau : ctl->tol / est * tau;   // eq. LIMdt
     if (ctl->mode == MODE_LIM_CONST) tau_next = ctl->tau_fixed;
     const int mv = 2 * ctl->p - 1;
-    if (ctl->steps < ctl->rec_cap) {
-        ch_step_record& r = rec[ctl->steps];
+    if (ctl->rec && ctl->steps < ctl->rec_cap) {
+        ch_step_record& r = ctl->rec[ctl->steps];
         r.t = t_new;
         r.tau = tau;
         r.tau_next = tau_next;
@@ -684,101 +729,135 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_end(Ctl* __restrict__ ctl, con
     ctl->matvecs += mv;
     ctl->steps += 1;
     ctl->cur ^= 1;
-    if (!(t_new < ctl->T)) ctl->halted = 1;
-}
-
-int stream_grid(long long N, int per_thread) {
-    long long g = (N + (long long)CH_BLOCK * per_thread - 1) / ((long long)CH_BLOCK * per_thread);
-    if (g < 1) g = 1;
-    if (g > 512) g = 512;
-    return (int)g;
-}
-
-template <typename TV>
-int mgs_grid(long long N) {
-    return stream_grid(N / Vec16<TV>::W + 1, 1);
-}
-
-template <typename TV>
-hipError_t launch_mgs_t(const Grid& g, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s) {
-    TV* V = static_cast<TV*>(b.V);
-    TV* W = V + (size_t)(k + 1) * b.ldv;
-    const int G = mgs_grid<TV>(g.N);
-    if (i <= k)
-        hipLaunchKernelGGL((k_mgs<TV, false>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, W, V + (size_t)(i - 1) * b.ldv,
-                           V + (size_t)i * b.ldv, k, i, g.N, ps.in(), ps.np, ps.out());
-    else
-        hipLaunchKernelGGL((k_mgs<TV, true>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, W, V + (size_t)k * b.ldv,
-                           (const TV*)nullptr, k, i, g.N, ps.in(), ps.np, ps.out());
-    ps.produced(G);
-    return hipGetLastError();
+    if (!(t_new < ctl->T) || (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps)) ctl->halted = 1;
 }
 
 }  // namespace
 
-hipError_t launch_mgs_pass(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s) {
-    return prec == CH_FP64 ? launch_mgs_t<double>(g, b, ps, k, i, s) : launch_mgs_t<float>(g, b, ps, k, i, s);
-}
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+#define CARGS dim3(t.cgrid), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i, t.hinst[0], t.ninst
+#define IARGS dim3(t.ninst), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst
 
-hipError_t launch_phi(const DevBuffers& b, PartSeq& ps, int k, int cycle_id, hipStream_t s) {
-    hipLaunchKernelGGL(k_phi, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, k, ps.in(), ps.np, cycle_id, b.dflag);
+hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s) {
+    const bool fin = i > k;
+    if (prec == CH_FP64) {
+        double* V = static_cast<double*>(b.V);
+        if (fin)
+            if (t.ninst == 1)
+                hipLaunchKernelGGL((k_mgs<double, true, true>), CARGS, V, b.ldv, k, i, ps.in(), ps.stencil, ps.out());
+            else
+                hipLaunchKernelGGL((k_mgs<double, true, false>), CARGS, V, b.ldv, k, i, ps.in(), ps.stencil, ps.out());
+        else
+            if (t.ninst == 1)
+                hipLaunchKernelGGL((k_mgs<double, false, true>), CARGS, V, b.ldv, k, i, ps.in(), ps.stencil, ps.out());
+            else
+                hipLaunchKernelGGL((k_mgs<double, false, false>), CARGS, V, b.ldv, k, i, ps.in(), ps.stencil, ps.out());
+    } else {
+        float* V = static_cast<float*>(b.V);
+        if (fin)
+            if (t.ninst == 1)
+                hipLaunchKernelGGL((k_mgs<float, true, true>), CARGS, V, b.ldv, k, i, ps.in(), ps.stencil, ps.out());
+            else
+                hipLaunchKernelGGL((k_mgs<float, true, false>), CARGS, V, b.ldv, k, i, ps.in(), ps.stencil, ps.out());
+        else
+            if (t.ninst == 1)
+                hipLaunchKernelGGL((k_mgs<float, false, true>), CARGS, V, b.ldv, k, i, ps.in(), ps.stencil, ps.out());
+            else
+                hipLaunchKernelGGL((k_mgs<float, false, false>), CARGS, V, b.ldv, k, i, ps.in(), ps.stencil, ps.out());
+    }
+    ps.produced(false);
     return hipGetLastError();
 }
 
-hipError_t launch_arnoldi(const Grid& g, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
+hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int cycle_id, hipStream_t s) {
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_phi<true>), IARGS, k, ps.in(), ps.stencil, cycle_id, b.dflag);
+    else
+        hipLaunchKernelGGL((k_phi<false>), IARGS, k, ps.in(), ps.stencil, cycle_id, b.dflag);
+    return hipGetLastError();
+}
+
+static bool all_cycles_done(const Table& t, const DevBuffers& b, int cycle_id) {
+    if (!b.hflag) return false;
+    for (int i = 0; i < t.ninst; ++i)
+        if (b.hflag[t.hinst[i].slot] != cycle_id) return false;
+    return true;
+}
+
+hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
                           int cycle_id, hipStream_t s) {
     for (int k = 0; k < m_max; ++k) {
-        if (k > 0 && b.hflag && *b.hflag == cycle_id) break;
-        hipError_t e = launch_matvec(g, prec, b, ps, y, k, s);
+        if (k > 0 && all_cycles_done(t, b, cycle_id)) break;
+        hipError_t e = launch_matvec(t, prec, b, ps, y, k, s);
         if (e != hipSuccess) return e;
         for (int i = 1; i <= k + 1; ++i)
-            if ((e = launch_mgs_pass(g, prec, b, ps, k, i, s)) != hipSuccess) return e;
-        if ((e = launch_phi(b, ps, k, cycle_id, s)) != hipSuccess) return e;
+            if ((e = launch_mgs_pass(t, prec, b, ps, k, i, s)) != hipSuccess) return e;
+        if ((e = launch_phi(t, b, ps, k, cycle_id, s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_update(const Grid& g, int prec, const DevBuffers& b, const double* y, double* ynew,
-                         hipStream_t s) {
-    const int G = stream_grid(g.N, 2);
+hipError_t launch_update(const Table& t, int prec, const DevBuffers& b, const double* y, double* ynew, hipStream_t s) {
     if (prec == CH_FP64)
-        hipLaunchKernelGGL((k_update<double>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, y,
-                           static_cast<const double*>(b.V), b.ldv, ynew, g.N);
+        if (t.ninst == 1)
+            hipLaunchKernelGGL((k_update<double, true>), CARGS, y, static_cast<const double*>(b.V), b.ldv, ynew);
+        else
+            hipLaunchKernelGGL((k_update<double, false>), CARGS, y, static_cast<const double*>(b.V), b.ldv, ynew);
     else
-        hipLaunchKernelGGL((k_update<float>), dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, y, static_cast<const float*>(b.V),
-                           b.ldv, ynew, g.N);
+        if (t.ninst == 1)
+            hipLaunchKernelGGL((k_update<float, true>), CARGS, y, static_cast<const float*>(b.V), b.ldv, ynew);
+        else
+            hipLaunchKernelGGL((k_update<float, false>), CARGS, y, static_cast<const float*>(b.V), b.ldv, ynew);
     return hipGetLastError();
 }
 
-hipError_t launch_after_resid(const DevBuffers& b, PartSeq& ps, bool begin_step, hipStream_t s) {
-    hipLaunchKernelGGL(k_after_resid, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, ps.in(), ps.np, begin_step ? 1 : 0);
+hipError_t launch_after_resid(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_step, hipStream_t s) {
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_after_resid<true>), IARGS, ps.in(), ps.stencil, begin_step ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_after_resid<false>), IARGS, ps.in(), ps.stencil, begin_step ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_cycle_begin(const DevBuffers& b, hipStream_t s) {
-    hipLaunchKernelGGL(k_cycle_begin, dim3(1), dim3(64), 0, s, b.ctl);
+hipError_t launch_cycle_begin(const Table& t, const DevBuffers& b, hipStream_t s) {
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_cycle_begin<true>), dim3(t.ninst), dim3(64), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst);
+    else
+        hipLaunchKernelGGL((k_cycle_begin<false>), dim3(t.ninst), dim3(64), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst);
     return hipGetLastError();
 }
 
-hipError_t launch_step_end(const DevBuffers& b, PartSeq& ps, bool begin_next, hipStream_t s) {
-    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, ps.in(), ps.np, b.rec, begin_next ? 1 : 0);
+hipError_t launch_step_end(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_next, hipStream_t s) {
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_step_end<true>), IARGS, ps.in(), ps.stencil, begin_next ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_step_end<false>), IARGS, ps.in(), ps.stencil, begin_next ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_lim_begin(const Grid& g, const DevBuffers& b, PartSeq& ps, const double* y, hipStream_t s) {
-    const int G = stream_grid(g.N, 4);
-    hipLaunchKernelGGL(k_lim_begin, dim3(G), dim3(CH_BLOCK), 0, s, b.ctl, y, g.N, ps.out());
-    ps.produced(G);
+hipError_t launch_lim_begin(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y, hipStream_t s) {
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_lim_begin<true>), CARGS, y, ps.out());
+    else
+        hipLaunchKernelGGL((k_lim_begin<false>), CARGS, y, ps.out());
+    ps.produced(false);
     return hipGetLastError();
 }
 
-hipError_t launch_lim_plan(const Grid& g, const DevBuffers& b, PartSeq& ps, hipStream_t s) {
-    hipLaunchKernelGGL(k_lim_plan, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, ps.in(), ps.np, g.dim, g.eps2, g.inv_h2,
-                       g.eyre);
+hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s) {
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_lim_plan<true>), IARGS, ps.in(), ps.stencil, t.dim);
+    else
+        hipLaunchKernelGGL((k_lim_plan<false>), IARGS, ps.in(), ps.stencil, t.dim);
     return hipGetLastError();
 }
 
-hipError_t launch_lim_end(const DevBuffers& b, PartSeq& ps, hipStream_t s) {
-    hipLaunchKernelGGL(k_lim_end, dim3(1), dim3(CH_BLOCK), 0, s, b.ctl, ps.in(), ps.np, b.rec);
+hipError_t launch_lim_end(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s) {
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_lim_end<true>), IARGS, ps.in(), ps.stencil);
+    else
+        hipLaunchKernelGGL((k_lim_end<false>), IARGS, ps.in(), ps.stencil);
     return hipGetLastError();
 }

@@ -1,0 +1,129 @@
+"""Batched EE2 (many ragged instances per launch): parity with the oracle,
+independence from the batch composition, per-instance stopping."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import ch_oracle as O
+from paper_2502_14589_amd import ch
+from paper_2502_14589_amd.inputs import batch_instances, uniform_field
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available()
+    c = ch.Context(0)
+    yield c
+    c.close()
+
+
+def dev(y):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(y, dtype=np.float64)).to("cuda")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+NS = [40, 64, 70, 96, 33]
+EPS = [0.05, 0.03, 0.04, 0.02, 0.06]
+MEANS = [0.1, -0.2, 0.0, 0.25, 0.05]
+
+
+def fields():
+    return [uniform_field(n, 2, mu, 0.05, seed=900 + i) for i, (n, mu) in enumerate(zip(NS, MEANS))]
+
+
+def test_batch_matches_oracle_per_instance(ctx):
+    say("batch of 5 ragged instances vs oracle")
+    ys = fields()
+    steps = [12, 12, 7, 12, 12]
+    refs = [O.ee_adaptive(y, O.Problem(2, n, e), 1e-3, math.inf, 1e-4, 12, max_steps=k)
+            for y, n, e, k in zip(ys, NS, EPS, steps)]
+    gs = [dev(y) for y in ys]
+    st, rc = ctx.run_ee_batch(gs, NS, EPS, tau0=1e-3, max_steps=steps, m_max=12, tol=1e-4)
+    assert rc == ch.CH_OK
+    for i, (g, (yr, rec)) in enumerate(zip(gs, refs)):
+        assert st[i]["steps"] == steps[i]
+        assert st[i]["matvecs"] == rec.matvecs
+        assert st[i]["t"] == pytest.approx(rec.t, rel=1e-10)
+        assert rel(g.cpu().numpy(), yr) <= 1e-10, i
+
+
+def test_batch_result_independent_of_membership(ctx):
+    say("alone vs in the mix")
+    ys = fields()
+    gs = [dev(y) for y in ys]
+    ctx.run_ee_batch(gs, NS, EPS, tau0=1e-3, max_steps=10, m_max=12, tol=1e-4)
+    for i in (0, 3):
+        alone = dev(ys[i])
+        ctx.run_ee_batch([alone], [NS[i]], [EPS[i]], tau0=1e-3, max_steps=10, m_max=12, tol=1e-4)
+        assert np.array_equal(alone.cpu().numpy(), gs[i].cpu().numpy()), i
+        single = dev(ys[i])
+        ctx.run_ee(ch.Problem(2, NS[i], EPS[i]), single, 1e-3, max_steps=10, m_max=12, tol=1e-4)
+        assert np.array_equal(single.cpu().numpy(), gs[i].cpu().numpy()), i
+
+
+def test_batch_per_instance_final_times(ctx):
+    say("per-instance final times")
+    ys = fields()[:3]
+    Ts = [2e-4, 5e-4, 1e-4]
+    gs = [dev(y) for y in ys]
+    st, rc = ctx.run_ee_batch(gs, NS[:3], EPS[:3], tau0=1e-4, T=Ts, max_steps=0, m_max=12, tol=1e-3)
+    for i in range(3):
+        yr, rec = O.ee_adaptive(ys[i], O.Problem(2, NS[i], EPS[i]), 1e-4, Ts[i], 1e-3, 12)
+        assert st[i]["t"] == Ts[i] and rec.t == Ts[i]
+        assert st[i]["steps"] == rec.steps
+        assert rel(gs[i].cpu().numpy(), yr) <= 1e-10
+
+
+def test_batch_3d_and_fp32(ctx):
+    say("3-D batch, FP32-mixed batch")
+    ys = [uniform_field(n, 3, 0.0, 0.05, seed=950 + n) for n in (12, 17)]
+    refs = [O.ee_adaptive(y, O.Problem(3, n, 0.05), 1e-4, math.inf, 1e-4, 10, max_steps=5)[0]
+            for y, n in zip(ys, (12, 17))]
+    gs = [dev(y) for y in ys]
+    ctx.run_ee_batch(gs, [12, 17], [0.05, 0.05], dim=3, tau0=1e-4, max_steps=5, m_max=10, tol=1e-4)
+    for g, r in zip(gs, refs):
+        assert rel(g.cpu().numpy(), r) <= 1e-10
+    y2 = fields()
+    g2 = [dev(y) for y in y2]
+    ctx.run_ee_batch(g2, NS, EPS, precision=ch.CH_FP32_MIXED, tau0=1e-3, max_steps=6, m_max=12, tol=1e-4)
+    for i, y in enumerate(y2):
+        yr, _ = O.ee_adaptive(y, O.Problem(2, NS[i], EPS[i]), 1e-3, math.inf, 1e-4, 12, max_steps=6)
+        assert rel(g2[i].cpu().numpy(), yr) <= 1e-5, i
+
+
+def test_batched_workload_64_instances(ctx):
+    """The 64-instance ragged workload (sides 128..512), 10 adaptive steps each
+    in FP32-mixed; the three smallest instances checked against the FP64 oracle,
+    every instance for mass conservation to FP32 rounding (the FP32 basis
+    columns sum to zero only up to the FP32 unit, 6e-8)."""
+    say("64-instance batch")
+    inst = batch_instances()
+    gs = [dev(it.y0) for it in inst]
+    st, rc = ctx.run_ee_batch(gs, [it.n for it in inst], [it.eps for it in inst], precision=ch.CH_FP32_MIXED,
+                              tau0=1e-3, max_steps=10, m_max=30, tol=1e-4)
+    assert rc == ch.CH_OK and all(s["steps"] == 10 for s in st)
+    for it, g in zip(inst, gs):
+        y = g.cpu().numpy()
+        assert np.all(np.isfinite(y))
+        assert abs(y.sum() - it.y0.sum()) <= 1e-7 * np.abs(it.y0).sum()
+    order = sorted(range(len(inst)), key=lambda i: inst[i].n)[:3]
+    for i in order:
+        yr, rec = O.ee_adaptive(inst[i].y0, O.Problem(2, inst[i].n, inst[i].eps), 1e-3, math.inf, 1e-4, 30,
+                                max_steps=10)
+        assert rel(gs[i].cpu().numpy(), yr) <= 1e-5, (i, inst[i].n)
