@@ -99,6 +99,97 @@ def precision_gap(ctx, ch, torch, y0, steps: int = 10, tau: float = 1e-9):
             "compared": f"{steps} constant EE2 steps of tau={tau:g} from y0, Krylov dim {M_MAX}, tol_phi 1e-8"}
 
 
+def batched(ctx, ch, torch, steps: int = 50, sequential_sample: int = 8):
+    """64 ragged 2-D instances (sides 128..512, eps log-uniform in [0.01, 0.05],
+    mean U(-0.3, 0.3) + U(-0.05, 0.05), seed 3), each advanced `steps` adaptive
+    EE2 steps (tol 1e-4, Krylov dimension 30, tau0 1e-3) in FP32-mixed, all in
+    one batched run; compared with the same instances run one at a time."""
+    from paper_2502_14589_amd.inputs import batch_instances
+
+    inst = batch_instances()
+    ns, eps = [it.n for it in inst], [it.eps for it in inst]
+    fields = [torch.from_numpy(it.y0.copy()).to("cuda") for it in inst]
+    ctx.run_ee_batch(fields[:2], ns[:2], eps[:2], precision=ch.CH_FP32_MIXED, tau0=TAU0, max_steps=2,
+                     m_max=M_MAX, tol=TOL)    # warm-up (allocations, code objects)
+    fields = [torch.from_numpy(it.y0.copy()).to("cuda") for it in inst]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rc = ctx.run_ee_batch(fields, ns, eps, precision=ch.CH_FP32_MIXED, tau0=TAU0, max_steps=steps,
+                              m_max=M_MAX, tol=TOL)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    total_steps = sum(x["steps"] for x in st)
+    points = sum(n * n for n in ns)
+    # one-at-a-time reference on a sample (every 8th instance), scaled to all 64
+    idx = list(range(0, len(inst), len(inst) // sequential_sample))
+    seq_time, seq_steps = 0.0, 0
+    for i in idx:
+        y = torch.from_numpy(inst[i].y0.copy()).to("cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s1, _ = ctx.run_ee(ch.Problem(2, ns[i], eps[i], False, ch.CH_FP32_MIXED), y, TAU0, max_steps=steps,
+                           m_max=M_MAX, tol=TOL)
+        torch.cuda.synchronize()
+        seq_time += time.perf_counter() - t1
+        seq_steps += s1["steps"]
+    seq_rate = seq_steps / seq_time
+    return {"workload": "64 ragged 2-D periodic instances, sides {128,192,256,384,512}, eps log-uniform "
+                        "[0.01,0.05], 50 adaptive EE2 steps each, FP32-mixed, Krylov dim 30, tol 1e-4",
+            "instances": len(inst), "points": points, "instance_steps": total_steps, "seconds": round(dt, 4),
+            "instance_steps_per_s": round(total_steps / dt, 1),
+            "point_steps_per_s": round(sum(n * n * x["steps"] for n, x in zip(ns, st)) / dt, 1),
+            "one_at_a_time_instance_steps_per_s": round(seq_rate, 1),
+            "one_at_a_time_sample": f"{len(idx)} of {len(inst)} instances",
+            "speedup_vs_one_at_a_time": round(total_steps / dt / seq_rate, 2), "status": rc}
+
+
+def serving(ch, torch, count: int = 60, rate: float = 200.0):
+    """Replay `count` Poisson arrivals (rate 200/s) of 2-D requests: sides
+    128/256/512/1024 w.p. 0.4/0.3/0.2/0.1, eps log-uniform [0.005, 0.05],
+    horizons U{10..200} adaptive EE2 steps, FP32-mixed, seed 4; fields resident
+    on the device before the trace starts."""
+    from paper_2502_14589_amd.inputs import request_trace
+
+    reqs = request_trace(count, rate)
+    fields = [torch.from_numpy(r.y0.copy()).to("cuda") for r in reqs]
+    outs = [torch.empty_like(f) for f in fields]
+    torch.cuda.synchronize()
+    lat, done, tickets = {}, {}, []
+    with ch.Server(0, ch.CH_FP32_MIXED, m_max=M_MAX, tol=TOL, hbm_budget=32 << 30, max_slots=128) as srv:
+        t0 = time.perf_counter()
+        while len(done) < count:
+            now = time.perf_counter() - t0
+            while len(tickets) < count and reqs[len(tickets)].arrival <= now:
+                r = reqs[len(tickets)]
+                tickets.append(srv.submit(fields[len(tickets)], r.n, r.eps, r.steps, tau0=TAU0))
+            for k, t in enumerate(tickets):
+                if k in done:
+                    continue
+                state, rc, st, lt = srv.poll(t, outs[k])
+                if state in (ch.CH_REQ_DONE, ch.CH_REQ_FAILED):
+                    done[k] = (state, st)
+                    lat[k] = lt
+            if now > 300:
+                raise RuntimeError("serving trace did not finish")
+            time.sleep(0.0005)
+        makespan = time.perf_counter() - t0
+    import numpy as np
+
+    tot = np.array([lat[k][2] for k in range(count)])
+    que = np.array([lat[k][0] for k in range(count)])
+    steps = sum(done[k][1]["steps"] for k in range(count))
+    psteps = sum(done[k][1]["steps"] * reqs[k].n ** 2 for k in range(count))
+    return {"workload": f"{count} Poisson arrivals at {rate:g}/s, sides 128/256/512/1024 (0.4/0.3/0.2/0.1), "
+                        "eps log-uniform [0.005,0.05], horizons U{10..200} adaptive EE2 steps, FP32-mixed",
+            "requests": count, "failed": sum(1 for k in range(count) if done[k][0] != ch.CH_REQ_DONE),
+            "makespan_s": round(makespan, 3), "latency_p50_s": round(float(np.percentile(tot, 50)), 4),
+            "latency_p99_s": round(float(np.percentile(tot, 99)), 4),
+            "queue_p50_s": round(float(np.percentile(que, 50)), 4),
+            "queue_p99_s": round(float(np.percentile(que, 99)), 4),
+            "request_steps_per_s": round(steps / makespan, 1), "point_steps_per_s": round(psteps / makespan, 1),
+            "offered_point_steps_per_s": round(rate * float(np.mean([r.n ** 2 * r.steps for r in reqs])), 1)}
+
+
 def roofline(form):
     achieved = form["mgs_bytes"] / (form["mgs_us"] * 1e-6) / 1e9
     return {"bound": "hbm", "kernel": "k_mgs (one modified Gram-Schmidt pass)", "achieved": round(achieved, 1),
@@ -136,6 +227,7 @@ def main():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -156,6 +248,8 @@ def main():
         f32 = run_form(ctx, ch, torch, y0, ch.CH_FP32_MIXED, args.steps, args.warmup)
         f64 = run_form(ctx, ch, torch, y0, ch.CH_FP64, args.steps, args.warmup)
         acc = precision_gap(ctx, ch, torch, y0)
+        batch = None if args.no_batch else batched(ctx, ch, torch)
+    serve = None if args.no_batch else serving(ch, torch)
     t_rel = abs(f32["t_end"] - f64["t_end"]) / f64["t_end"]
     out = {
         "metric": METRIC,
@@ -187,6 +281,10 @@ def main():
         "accuracy": dict(acc, adaptive_t_rel_diff=t_rel),
         "speedup_fp32_vs_fp64": round(f32["steps_per_s"] / f64["steps_per_s"], 3),
     }
+    if batch is not None:
+        out["batched"] = batch
+    if serve is not None:
+        out["serving"] = serve
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(y0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

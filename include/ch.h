@@ -178,6 +178,50 @@ enum ch_phi_mode {
 int ch_phiv(ch_ctx *ctx, const ch_problem *prob, const double *y, double *y_out, double tau0,
             int mode, double tol_phi, int m_max, ch_step_record *out);
 
+/*
+ * Serving: continuous batching of EE2 solve requests on one GPU.
+ *
+ * A server owns a private context and stream and a scheduler thread.  Each
+ * request is copied to device memory at submit and queued.  Between batch
+ * steps, the scheduler admits queued requests in arrival order while a control
+ * block, pooled HBM for the request's footprint and workgroup-table room are
+ * free.  The footprint is ((m_max + 1) w + 28) bytes per grid point, where
+ * w = 8 (FP64) or 4 (FP32-mixed).  All admitted requests advance together,
+ * one adaptive EE2 step per batch step, each with its own grid, eps, steps and
+ * horizon.  Finished requests leave the batch, freeing their slot and memory
+ * for the queue.  A request's result does not depend on what else was in the
+ * batch: it equals that of a separate ch_run_ee call.
+ */
+typedef struct ch_server ch_server;
+
+typedef struct {
+    int n;              /* points per direction (2-D periodic, h = 1/n), >= 5 */
+    double eps;         /* interface parameter epsilon > 0 */
+    const double *y0;   /* DEVICE field, FP64, n*n values; copied at submit */
+    int steps;          /* horizon: accepted adaptive EE2 steps (> 0) */
+    double tau0;        /* first proposed step > 0 */
+} ch_request;
+
+enum ch_request_state { CH_REQ_QUEUED = 0, CH_REQ_RUNNING = 1, CH_REQ_DONE = 2, CH_REQ_FAILED = 3 };
+
+/* Create a server on `device`: precision, Krylov dimension and tolerances
+ * (opts; constant_step must be 0) are common to all requests; hbm_budget is
+ * the pooled footprint in bytes; max_slots bounds the requests in flight. */
+int ch_server_create(int device, int prec, const ch_ee_opts *opts, size_t hbm_budget, int max_slots,
+                     ch_server **out);
+/* Stops admitting, finishes the requests in flight, fails the queued ones, frees everything. */
+int ch_server_destroy(ch_server *srv);
+/* Queue a request; CH_ENOMEM if its footprint can never fit the budget.  Thread-safe. */
+int ch_submit(ch_server *srv, const ch_request *req, unsigned long long *ticket);
+/*
+ * State of a request.  When it is CH_REQ_DONE and y_out (DEVICE, n*n FP64) is
+ * not NULL, the result is copied there and the ticket is released (later
+ * polls return CH_ENOENT).  stats and latency_s (queue wait, service, total in
+ * seconds) may be NULL.  Thread-safe.
+ */
+int ch_poll(ch_server *srv, unsigned long long ticket, int *state, double *y_out, ch_run_stats *stats,
+            double *latency_s);
+
 enum ch_kernel {
     CH_KERNEL_MGS = 0,      /* one modified Gram-Schmidt pass (axpy + next dot) over the grid */
     CH_KERNEL_MATVEC = 1,   /* one fused Jacobian matvec Ahat v with its first dot */

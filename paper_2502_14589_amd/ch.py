@@ -24,7 +24,9 @@ CH_PMAX = 4096
 EXPORTED = (
     "ch_create", "ch_destroy", "ch_strerror", "ch_last_error_message",
     "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_step_lim", "ch_phiv", "ch_time_kernel",
+    "ch_server_create", "ch_server_destroy", "ch_submit", "ch_poll",
 )
+CH_REQ_QUEUED, CH_REQ_RUNNING, CH_REQ_DONE, CH_REQ_FAILED = 0, 1, 2, 3
 CH_KERNEL_MGS, CH_KERNEL_MATVEC, CH_KERNEL_PHI = 0, 1, 2
 
 
@@ -57,6 +59,10 @@ class ChRunStats(ctypes.Structure):
 class ChBatchItem(ctypes.Structure):
     _fields_ = [("n", c_int), ("eps", c_double), ("y", c_void_p), ("tau0", c_double), ("T", c_double),
                 ("max_steps", c_int)]
+
+
+class ChRequest(ctypes.Structure):
+    _fields_ = [("n", c_int), ("eps", c_double), ("y0", c_void_p), ("steps", c_int), ("tau0", c_double)]
 
 
 class ChError(RuntimeError):
@@ -95,9 +101,14 @@ def load_library(path: str = LIB_PATH):
                             P(ChStepRecord)]
     lib.ch_run_ee_batch.argtypes = [c_void_p, c_int, P(ChBatchItem), c_int, c_int, c_int, P(ChEeOpts),
                                     P(ChRunStats)]
+    lib.ch_server_create.argtypes = [c_int, c_int, P(ChEeOpts), ctypes.c_size_t, c_int, P(c_void_p)]
+    lib.ch_server_destroy.argtypes = [c_void_p]
+    lib.ch_submit.argtypes = [c_void_p, P(ChRequest), P(ctypes.c_ulonglong)]
+    lib.ch_poll.argtypes = [c_void_p, ctypes.c_ulonglong, P(c_int), c_void_p, P(ChRunStats), P(c_double)]
     lib.ch_time_kernel.argtypes = [c_void_p, P(ChProblem), c_int, c_int, c_int, P(c_double), P(c_double)]
     for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim",
-                 "ch_step_lim", "ch_phiv", "ch_time_kernel"):
+                 "ch_step_lim", "ch_phiv", "ch_time_kernel", "ch_server_create", "ch_server_destroy", "ch_submit",
+                 "ch_poll"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -263,3 +274,53 @@ class Context:
         rc = self.lib.ch_time_kernel(self._ptr, byref(pb), int(kernel), int(m_max), int(reps), byref(us), byref(by))
         self._raise(rc, "ch_time_kernel")
         return us.value, by.value
+
+
+class Server:
+    """Continuous-batching EE2 server (ch_server_create / ch_submit / ch_poll)."""
+
+    def __init__(self, device: int = 0, precision: int = CH_FP64, m_max: int = 30, tol: float = 1e-4,
+                 tol_phi_fixed: float = 0.0, hbm_budget: int = 8 << 30, max_slots: int = 64):
+        self.lib = load_library()
+        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), 0.0, 0)
+        self._ptr = c_void_p()
+        rc = self.lib.ch_server_create(device, int(precision), byref(opts), int(hbm_budget), int(max_slots),
+                                       byref(self._ptr))
+        if rc != CH_OK:
+            raise ChError(rc, f"ch_server_create: {self.lib.ch_strerror(rc).decode()}")
+
+    def submit(self, y0, n: int, eps: float, steps: int, tau0: float = 1e-3) -> int:
+        """Queue a 2-D request (y0 is copied); returns its ticket."""
+        _check_field(y0, n * n)
+        req = ChRequest(int(n), float(eps), c_void_p(y0.data_ptr()), int(steps), float(tau0))
+        t = ctypes.c_ulonglong()
+        rc = self.lib.ch_submit(self._ptr, byref(req), byref(t))
+        if rc != CH_OK:
+            raise ChError(rc, f"ch_submit: {self.lib.ch_strerror(rc).decode()}")
+        return t.value
+
+    def poll(self, ticket: int, y_out=None):
+        """(state, status, stats, (queue, service, total) latency in s); copies the result when done."""
+        state = c_int()
+        st = ChRunStats()
+        lat = (c_double * 3)()
+        ptr = c_void_p(y_out.data_ptr()) if y_out is not None else None
+        rc = self.lib.ch_poll(self._ptr, ctypes.c_ulonglong(ticket), byref(state), ptr, byref(st), lat)
+        return state.value, rc, st.as_dict(), tuple(lat)
+
+    def close(self):
+        if self._ptr:
+            self.lib.ch_server_destroy(self._ptr)
+            self._ptr = c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

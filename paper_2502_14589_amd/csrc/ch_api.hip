@@ -14,8 +14,15 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "ch_internal.h"
@@ -174,8 +181,19 @@ struct Member {
     Shape sh;
     double eps;
     int eyre;
-    size_t off;   // pooled offset (points)
+    size_t off;     // pooled offset (points)
+    int slot = -1;  // control block (default: the member's index)
 };
+
+// Workgroups of one instance: stencil tiles (at most CH_SBLK_MAX, larger
+// grids loop) and streaming chunks of 2048 points (at most CH_CBLK_MAX).
+void inst_blocks(int dim, int n, long long N, int* sblk, int* cblk) {
+    long long tiles;
+    if (dim == 2) tiles = (long long)((n + 63) / 64) * ((n + 7) / 8);
+    else tiles = (long long)((n + 31) / 32) * ((n + 3) / 4) * ((n + 3) / 4);
+    *sblk = (int)std::min<long long>(tiles, CH_SBLK_MAX);
+    *cblk = (int)std::max<long long>(1, std::min<long long>((N + 2047) / 2048, CH_CBLK_MAX));
+}
 
 // Workgroup ranges of each instance and the block-to-instance maps.
 int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, Table* t) {
@@ -186,15 +204,12 @@ int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, Table* t) {
         const Member& m = ms[i];
         Inst& I = ctx->h_inst[i];
         const int n = m.sh.n;
-        long long tiles;
-        if (dim == 2) tiles = (long long)((n + 63) / 64) * ((n + 7) / 8);
-        else tiles = (long long)((n + 31) / 32) * ((n + 3) / 4) * ((n + 3) / 4);
-        const int sblk = (int)std::min<long long>(tiles, CH_SBLK_MAX);
-        const int cblk = (int)std::max<long long>(1, std::min<long long>((m.sh.N + 2047) / 2048, CH_CBLK_MAX));
+        int sblk, cblk;
+        inst_blocks(dim, n, m.sh.N, &sblk, &cblk);
         I.off = (long long)m.off;
         I.N = m.sh.N;
         I.n = n;
-        I.slot = i;
+        I.slot = m.slot >= 0 ? m.slot : i;
         I.sblk0 = (int)sb.size();
         I.sblk = sblk;
         I.cblk0 = (int)cb.size();
@@ -494,6 +509,231 @@ void record_from_head(const Ctl& h, ch_step_record* out) {
     out->matvecs = h.mv_step + 1 + h.j;
 }
 
+// ---------------------------------------------------------------------------
+// Serving: continuous batching (ch_server_create / ch_submit / ch_poll)
+// ---------------------------------------------------------------------------
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+    unsigned long long id = 0;
+    int n = 0, steps = 0;
+    double eps = 0, tau0 = 0;
+    long long N = 0;
+    size_t len = 0;            // pooled points (padded)
+    int sblk = 0, cblk = 0;    // workgroups in a batched launch
+    double* buf = nullptr;     // device: y0 until admission, the result after
+    int state = CH_REQ_QUEUED;
+    int status = CH_OK;
+    ch_run_stats stats{};
+    double t_submit = 0, t_start = 0, t_done = 0;
+    int slot = -1;
+    size_t off = 0;
+};
+
+}  // namespace
+
+struct ch_server {
+    ch_ctx* ctx = nullptr;     // private context on a private stream
+    hipStream_t stream = nullptr;
+    int device = 0, prec = CH_FP64, max_slots = 0;
+    ch_ee_opts opts{};
+    size_t pool_pts = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req*> queue;
+    std::unordered_map<unsigned long long, Req*> reqs;
+    std::vector<Req*> slot_req;         // slot -> request in flight
+    std::map<size_t, size_t> free_;     // free pooled ranges: offset -> points
+    int sblk_used = 0, cblk_used = 0, running = 0;
+    unsigned long long next_id = 1;
+    bool stop = false;
+    int fatal = CH_OK;
+    std::thread th;
+};
+
+namespace {
+
+bool pool_alloc(ch_server* S, size_t len, size_t* off) {
+    for (auto it = S->free_.begin(); it != S->free_.end(); ++it) {
+        if (it->second >= len) {
+            *off = it->first;
+            const size_t rest = it->second - len;
+            const size_t roff = it->first + len;
+            S->free_.erase(it);
+            if (rest) S->free_[roff] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void pool_free(ch_server* S, size_t off, size_t len) {
+    auto it = S->free_.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != S->free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        S->free_.erase(nx);
+    }
+    if (it != S->free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            S->free_.erase(it);
+        }
+    }
+}
+
+int read_slot_heads(ch_ctx* ctx, const std::vector<Req*>& rs) {
+    for (Req* r : rs)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl + r->slot, ctx->b.ctl + r->slot, CTL_HEAD, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return CH_OK;
+}
+
+Member member_of(const Req* r) {
+    Member m;
+    m.sh.dim = 2;
+    m.sh.n = r->n;
+    m.sh.N = r->N;
+    m.eps = r->eps;
+    m.eyre = 0;
+    m.off = r->off;
+    m.slot = r->slot;
+    return m;
+}
+
+// One iteration of the scheduler: admit, start, one batch step, retire.
+int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
+    ch_ctx* ctx = S->ctx;
+    const DevBuffers& b = ctx->b;
+    std::vector<Req*> admitted, live;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || S->running > 0; });
+        if (S->stop && S->running == 0) return 1;
+        while (!S->stop && !S->queue.empty()) {
+            Req* r = S->queue.front();
+            int slot = -1;
+            for (int i = 0; i < S->max_slots; ++i)
+                if (!S->slot_req[i]) {
+                    slot = i;
+                    break;
+                }
+            if (slot < 0) break;
+            if (S->sblk_used + r->sblk > CH_MAXB || S->cblk_used + r->cblk > CH_MAXB) break;
+            size_t off;
+            if (!pool_alloc(S, r->len, &off)) break;
+            S->queue.pop_front();
+            r->slot = slot;
+            r->off = off;
+            r->state = CH_REQ_RUNNING;
+            r->t_start = now_s();
+            S->slot_req[slot] = r;
+            S->sblk_used += r->sblk;
+            S->cblk_used += r->cblk;
+            S->running += 1;
+            admitted.push_back(r);
+        }
+        for (Req* r : S->slot_req)
+            if (r) live.push_back(r);
+    }
+    int rc;
+    const int p = (int)(*par & 1);
+    if (!admitted.empty()) {
+        // start: state into the buffer of the current parity, f(y0), first step begin
+        std::vector<Member> ms;
+        for (Req* r : admitted) {
+            init_ctl(ctx->hctl + r->slot, MODE_EE, 0.0, r->tau0, INFINITY, S->opts.tol, S->opts.tol_phi_fixed,
+                     S->opts.tau_min, S->opts.m_max, r->steps, nullptr, 0);
+            ctx->hctl[r->slot].cur = p;
+            HIP_TRY(ctx, hipMemcpyAsync(b.ctl + r->slot, ctx->hctl + r->slot, sizeof(Ctl), hipMemcpyHostToDevice,
+                                        ctx->stream));
+            HIP_TRY(ctx, hipMemcpyAsync(b.ybuf[p] + r->off, r->buf, sizeof(double) * r->N, hipMemcpyDeviceToDevice,
+                                        ctx->stream));
+            ms.push_back(member_of(r));
+        }
+        Table ta;
+        if ((rc = build_table(ctx, ms, 2, &ta))) return rc;
+        PartSeq ps;
+        ps.base = b.part;
+        HIP_TRY(ctx, launch_resid(ta, S->prec, b, ps, b.ybuf[p], b.ybuf[p], true, true, ctx->stream));
+        HIP_TRY(ctx, launch_after_resid(ta, b, ps, true, ctx->stream));
+        *dirty = true;
+    }
+    if (live.empty()) return CH_OK;
+    if (*dirty) {
+        std::vector<Member> ms;
+        for (Req* r : live) ms.push_back(member_of(r));
+        if ((rc = build_table(ctx, ms, 2, t))) return rc;
+        *dirty = false;
+    }
+    PartSeq ps;
+    ps.base = b.part;
+    HIP_TRY(ctx, launch_arnoldi(*t, S->prec, b, ps, b.ybuf[p], S->opts.m_max, ++ctx->cycle_id, ctx->stream));
+    HIP_TRY(ctx, launch_update(*t, S->prec, b, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
+    HIP_TRY(ctx, launch_est_ee(*t, S->prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
+    HIP_TRY(ctx, launch_step_end(*t, b, ps, true, ctx->stream));
+    *par += 1;
+    if ((rc = read_slot_heads(ctx, live))) return rc;
+    std::vector<Req*> done;
+    for (Req* r : live)
+        if (ctx->hctl[r->slot].halted) {
+            const Ctl& h = ctx->hctl[r->slot];
+            HIP_TRY(ctx, hipMemcpyAsync(r->buf, b.ybuf[h.cur] + r->off, sizeof(double) * r->N,
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+            done.push_back(r);
+        }
+    if (!done.empty()) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        const double tnow = now_s();
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (Req* r : done) {
+            const Ctl& h = ctx->hctl[r->slot];
+            fill_stats(h, &r->stats);
+            r->status = h.status;
+            r->state = h.status == CH_OK ? CH_REQ_DONE : CH_REQ_FAILED;
+            r->t_done = tnow;
+            S->slot_req[r->slot] = nullptr;
+            pool_free(S, r->off, r->len);
+            S->sblk_used -= r->sblk;
+            S->cblk_used -= r->cblk;
+            S->running -= 1;
+        }
+        *dirty = true;
+    }
+    return CH_OK;
+}
+
+void serve_loop(ch_server* S) {
+    (void)hipSetDevice(S->device);
+    long long par = 0;
+    Table t{};
+    bool dirty = true;
+    for (;;) {
+        const int rc = serve_once(S, &par, &t, &dirty);
+        if (rc == 1) break;
+        if (rc != CH_OK) {   // device error: fail everything and stop
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->fatal = rc;
+            for (Req* r : S->slot_req)
+                if (r) {
+                    r->state = CH_REQ_FAILED;
+                    r->status = rc;
+                }
+            for (Req* r : S->queue) {
+                r->state = CH_REQ_FAILED;
+                r->status = rc;
+            }
+            S->queue.clear();
+            S->stop = true;
+            break;
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -689,6 +929,144 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     else if (kernel == CH_KERNEL_MATVEC) *bytes = (3.0 * esz + ysz) * N; // read v_k, y, v_1; write w
     else *bytes = 0.0;
     return CH_OK;
+}
+
+int ch_server_create(int device, int prec, const ch_ee_opts* opts, size_t hbm_budget, int max_slots,
+                     ch_server** out) {
+    if (!out || !opts) return CH_EINVAL;
+    *out = nullptr;
+    if (prec != CH_FP64 && prec != CH_FP32_MIXED) return CH_EINVAL;
+    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step) return CH_EINVAL;
+    if (!(opts->tol > 0.0) && !(opts->tol_phi_fixed > 0.0)) return CH_EINVAL;
+    if (max_slots < 1 || max_slots > 4096) return CH_EINVAL;
+    const size_t esz = prec == CH_FP64 ? 8 : 4;
+    const size_t per_pt = (size_t)(opts->m_max + 1) * esz + 28;
+    const size_t pts = hbm_budget / per_pt / 64 * 64;
+    if (pts < 64) return CH_EINVAL;
+    ch_server* S = new (std::nothrow) ch_server();
+    if (!S) return CH_ENOMEM;
+    S->device = device;
+    S->prec = prec;
+    S->opts = *opts;
+    S->max_slots = max_slots;
+    S->pool_pts = pts;
+    S->slot_req.assign(max_slots, nullptr);
+    S->free_[0] = pts;
+    int rc;
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&S->stream) != hipSuccess) {
+        delete S;
+        return CH_EDEVICE;
+    }
+    if ((rc = ch_create(&S->ctx, device, S->stream)) != CH_OK ||
+        (rc = ensure(S->ctx, pts, opts->m_max, prec, max_slots, 0, false)) != CH_OK) {
+        if (S->ctx) ch_destroy(S->ctx);
+        (void)hipStreamDestroy(S->stream);
+        delete S;
+        return rc;
+    }
+    S->th = std::thread(serve_loop, S);
+    *out = S;
+    return CH_OK;
+}
+
+int ch_server_destroy(ch_server* S) {
+    if (!S) return CH_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        for (Req* r : S->queue) {
+            r->state = CH_REQ_FAILED;
+            r->status = CH_EBUSY;
+        }
+        S->queue.clear();
+    }
+    S->cv.notify_all();
+    if (S->th.joinable()) S->th.join();
+    (void)hipSetDevice(S->device);
+    for (auto& kv : S->reqs) {
+        free_dev(kv.second->buf);
+        delete kv.second;
+    }
+    ch_destroy(S->ctx);
+    (void)hipStreamDestroy(S->stream);
+    delete S;
+    return CH_OK;
+}
+
+int ch_submit(ch_server* S, const ch_request* q, unsigned long long* ticket) {
+    if (!S || !q || !ticket || !q->y0) return CH_EINVAL;
+    Shape sh;
+    int rc = check_grid(2, q->n, q->eps, 0, &sh);
+    if (rc) return rc;
+    if (q->steps < 1 || !(q->tau0 > 0.0)) return CH_EINVAL;
+    Req* r = new (std::nothrow) Req();
+    if (!r) return CH_ENOMEM;
+    r->n = q->n;
+    r->eps = q->eps;
+    r->steps = q->steps;
+    r->tau0 = q->tau0;
+    r->N = sh.N;
+    r->len = pad64(sh.N);
+    inst_blocks(2, q->n, sh.N, &r->sblk, &r->cblk);
+    if (r->len > S->pool_pts || r->sblk > CH_MAXB || r->cblk > CH_MAXB) {
+        delete r;
+        return CH_ENOMEM;
+    }
+    if (hipSetDevice(S->device) != hipSuccess || hipMalloc(&r->buf, sizeof(double) * r->N) != hipSuccess) {
+        (void)hipGetLastError();
+        delete r;
+        return CH_ENOMEM;
+    }
+    if (hipMemcpy(r->buf, q->y0, sizeof(double) * r->N, hipMemcpyDeviceToDevice) != hipSuccess) {
+        (void)hipFree(r->buf);
+        delete r;
+        return CH_EDEVICE;
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) {
+            (void)hipFree(r->buf);
+            delete r;
+            return S->fatal != CH_OK ? S->fatal : CH_EBUSY;
+        }
+        r->id = S->next_id++;
+        r->t_submit = now_s();
+        S->reqs[r->id] = r;
+        S->queue.push_back(r);
+        *ticket = r->id;
+    }
+    S->cv.notify_all();
+    return CH_OK;
+}
+
+int ch_poll(ch_server* S, unsigned long long ticket, int* state, double* y_out, ch_run_stats* stats,
+            double* latency_s) {
+    if (!S || !state) return CH_EINVAL;
+    Req* r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->reqs.find(ticket);
+        if (it == S->reqs.end()) return CH_ENOENT;
+        r = it->second;
+        *state = r->state;
+        if (stats) *stats = r->stats;
+        if (latency_s) {
+            const bool fin = r->state == CH_REQ_DONE || r->state == CH_REQ_FAILED;
+            latency_s[0] = r->t_start > 0 ? r->t_start - r->t_submit : 0.0;
+            latency_s[1] = fin ? r->t_done - r->t_start : 0.0;
+            latency_s[2] = fin ? r->t_done - r->t_submit : 0.0;
+        }
+        if (!((r->state == CH_REQ_DONE || r->state == CH_REQ_FAILED) && y_out)) return r->status;
+        S->reqs.erase(it);   // released: the result is handed over below
+    }
+    int rc = r->status;
+    if (r->state == CH_REQ_DONE) {
+        (void)hipSetDevice(S->device);
+        if (hipMemcpy(y_out, r->buf, sizeof(double) * r->N, hipMemcpyDeviceToDevice) != hipSuccess) rc = CH_EDEVICE;
+    }
+    free_dev(r->buf);
+    delete r;
+    return rc;
 }
 
 }  // extern "C"
