@@ -38,8 +38,8 @@ struct ch_ctx {
     int slots = 0;           // control blocks allocated
     size_t rec_n = 0;        // step records allocated
     ch_step_record* rec = nullptr;
-    int cycle_id = 0;        // id of the last issued Krylov cycle
-    int* hflag = nullptr;    // pinned, device-mapped: last finished cycle id per slot
+    std::vector<int> expect; // per slot: Krylov cycles issued (compared with the device's `cyc`)
+    int* hflag = nullptr;    // pinned, device-mapped: `cyc` of the last finished cycle per slot
     Ctl* hctl = nullptr;     // pinned mirror of the control blocks
     // instance table
     Inst* d_inst = nullptr;
@@ -126,6 +126,7 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, sizeof(int) * nslots,
                                    hipHostMallocMapped | hipHostMallocCoherent));
         for (int i = 0; i < nslots; ++i) ctx->hflag[i] = -1;
+        ctx->expect.assign(nslots, 0);
         HIP_TRY(ctx, hipHostGetDevicePointer((void**)&b.dflag, ctx->hflag, 0));
         b.hflag = ctx->hflag;
         ctx->slots = nslots;
@@ -259,9 +260,12 @@ int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, Table* t) {
     return CH_OK;
 }
 
+// cyc0: the slot's count of Krylov cycles issued so far.  The count only
+// grows (across runs), so a flag left by an earlier run never matches.
 void init_ctl(Ctl* c, int mode, double t0, double tau0, double T, double tol, double tol_phi_fixed, double tau_min,
-              int m_max, int max_steps, ch_step_record* rec, int rec_cap) {
+              int m_max, int max_steps, ch_step_record* rec, int rec_cap, int cyc0) {
     memset(c, 0, sizeof(Ctl));
+    c->cyc = cyc0;
     c->mode = mode;
     c->t = t0;
     c->tau = tau0;
@@ -304,9 +308,10 @@ int restart_cycles(ch_ctx* ctx, const Table& t, int prec, PartSeq& ps, const dou
         const Ctl& h = ctx->hctl[0];
         if (h.halted || h.converged) return CH_OK;
         HIP_TRY(ctx, launch_cycle_begin(t, b, ctx->stream));
+        ctx->expect[t.hinst[0].slot] += 1;
         HIP_TRY(ctx, launch_resid(t, prec, b, ps, y, z, false, false, ctx->stream));
         HIP_TRY(ctx, launch_after_resid(t, b, ps, false, ctx->stream));
-        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, y, m_max, ++ctx->cycle_id, ctx->stream));
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, y, m_max, ctx->expect.data(), ctx->stream));
         HIP_TRY(ctx, launch_update(t, prec, b, z, z, ctx->stream));
     }
     ctx->err = "restart cycle limit reached";
@@ -333,14 +338,15 @@ int issue_ee_steps(ch_ctx* ctx, const Table& t, int prec, int m_max, bool consta
     int rc;
     HIP_TRY(ctx, launch_resid(t, prec, b, ps, b.ybuf[0], b.ybuf[0], true, true, ctx->stream));
     HIP_TRY(ctx, launch_after_resid(t, b, ps, true, ctx->stream));
+    for (int i = 0; i < t.ninst; ++i) ctx->expect[t.hinst[i].slot] += 1;
     for (long long s = 0; s < max_launch; ++s) {
-        const double* yin = b.ybuf[s & 1];
-        double* yout = b.ybuf[(s + 1) & 1];
-        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, yin, m_max, ++ctx->cycle_id, ctx->stream));
-        HIP_TRY(ctx, launch_update(t, prec, b, yin, yout, ctx->stream));
-        if (constant && (rc = restart_cycles(ctx, t, prec, ps, yin, yout, m_max))) return rc;
-        HIP_TRY(ctx, launch_est_ee(t, prec, b, ps, yin, yout, ctx->stream));
+        const int p = (int)(s & 1);
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[p], m_max, ctx->expect.data(), ctx->stream));
+        HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
+        if (constant && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[p], b.ybuf[p ^ 1], m_max))) return rc;
+        HIP_TRY(ctx, launch_est_ee(t, prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
         HIP_TRY(ctx, launch_step_end(t, b, ps, true, ctx->stream));
+        for (int i = 0; i < t.ninst; ++i) ctx->expect[t.hinst[i].slot] += 1;
         if ((s % 16) == 15) {
             if ((rc = read_heads(ctx, t.ninst))) return rc;
             if (all_halted(ctx, t.ninst)) break;
@@ -381,7 +387,7 @@ int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t
     if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
     const bool constant = opts->constant_step != 0;
     init_ctl(ctx->hctl, constant ? MODE_EE_CONST : MODE_EE, t0, tau0, T, opts->tol, opts->tol_phi_fixed,
-             opts->tau_min, opts->m_max, max_steps, recs ? ctx->rec : nullptr, recs);
+             opts->tau_min, opts->m_max, max_steps, recs ? ctx->rec : nullptr, recs, ctx->expect[0]);
     HIP_TRY(ctx, hipMemcpyAsync(ctx->b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     if ((rc = copy_in(ctx, m, y))) return rc;
     const long long limit = max_steps > 0 ? max_steps : (1LL << 40);
@@ -424,7 +430,7 @@ int run_ee_batch(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, in
     for (int i = 0; i < count; ++i) {
         const ch_batch_item& it = items[i];
         init_ctl(ctx->hctl + i, MODE_EE, 0.0, it.tau0, it.T, opts->tol, opts->tol_phi_fixed, opts->tau_min,
-                 opts->m_max, it.max_steps, nullptr, 0);
+                 opts->m_max, it.max_steps, nullptr, 0, ctx->expect[i]);
         limit = it.max_steps > 0 ? std::max<long long>(limit, it.max_steps) : (1LL << 40);
         if ((rc = copy_in(ctx, ms[i], it.y))) return rc;
     }
@@ -455,7 +461,7 @@ int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double 
     if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
     const DevBuffers& b = ctx->b;
     init_ctl(ctx->hctl, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, t0, tau0, T, tol, 0.0, 0.0, 0, max_steps,
-             recs ? ctx->rec : nullptr, recs);
+             recs ? ctx->rec : nullptr, recs, ctx->expect[0]);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     if ((rc = copy_in(ctx, m, y))) return rc;
     PartSeq ps;
@@ -647,7 +653,7 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
         std::vector<Member> ms;
         for (Req* r : admitted) {
             init_ctl(ctx->hctl + r->slot, MODE_EE, 0.0, r->tau0, INFINITY, S->opts.tol, S->opts.tol_phi_fixed,
-                     S->opts.tau_min, S->opts.m_max, r->steps, nullptr, 0);
+                     S->opts.tau_min, S->opts.m_max, r->steps, nullptr, 0, ctx->expect[r->slot]);
             ctx->hctl[r->slot].cur = p;
             HIP_TRY(ctx, hipMemcpyAsync(b.ctl + r->slot, ctx->hctl + r->slot, sizeof(Ctl), hipMemcpyHostToDevice,
                                         ctx->stream));
@@ -661,6 +667,7 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
         ps.base = b.part;
         HIP_TRY(ctx, launch_resid(ta, S->prec, b, ps, b.ybuf[p], b.ybuf[p], true, true, ctx->stream));
         HIP_TRY(ctx, launch_after_resid(ta, b, ps, true, ctx->stream));
+        for (Req* r : admitted) ctx->expect[r->slot] += 1;
         *dirty = true;
     }
     if (live.empty()) return CH_OK;
@@ -672,10 +679,11 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
     }
     PartSeq ps;
     ps.base = b.part;
-    HIP_TRY(ctx, launch_arnoldi(*t, S->prec, b, ps, b.ybuf[p], S->opts.m_max, ++ctx->cycle_id, ctx->stream));
+    HIP_TRY(ctx, launch_arnoldi(*t, S->prec, b, ps, b.ybuf[p], S->opts.m_max, ctx->expect.data(), ctx->stream));
     HIP_TRY(ctx, launch_update(*t, S->prec, b, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
     HIP_TRY(ctx, launch_est_ee(*t, S->prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
     HIP_TRY(ctx, launch_step_end(*t, b, ps, true, ctx->stream));
+    for (Req* r : live) ctx->expect[r->slot] += 1;
     *par += 1;
     if ((rc = read_slot_heads(ctx, live))) return rc;
     std::vector<Req*> done;
@@ -846,14 +854,15 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     Table t;
     if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
     const DevBuffers& b = ctx->b;
-    init_ctl(ctx->hctl, MODE_PHI, 0.0, tau0, INFINITY, 0.0, tol_phi, 0.0, m_max, 0, nullptr, 0);
+    init_ctl(ctx->hctl, MODE_PHI, 0.0, tau0, INFINITY, 0.0, tol_phi, 0.0, m_max, 0, nullptr, 0, ctx->expect[0]);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     if ((rc = copy_in(ctx, m, y))) return rc;
     PartSeq ps;
     ps.base = b.part;
     HIP_TRY(ctx, launch_resid(t, prec, b, ps, b.ybuf[0], b.ybuf[0], false, true, ctx->stream));
     HIP_TRY(ctx, launch_after_resid(t, b, ps, true, ctx->stream));
-    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, ++ctx->cycle_id, ctx->stream));
+    ctx->expect[0] += 1;
+    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, ctx->expect.data(), ctx->stream));
     HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[0], b.ybuf[1], ctx->stream));
     if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[0], b.ybuf[1], m_max))) return rc;
     if ((rc = read_heads(ctx, 1))) return rc;
@@ -903,7 +912,7 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
         switch (kernel) {
             case CH_KERNEL_MGS: return launch_mgs_pass(t, prec, b, ps, 1, 1, ctx->stream);
             case CH_KERNEL_MATVEC: return launch_matvec(t, prec, b, ps, y, 0, ctx->stream);
-            default: return launch_phi(t, b, ps, jlast - 1, -2, ctx->stream);
+            default: return launch_phi(t, b, ps, jlast - 1, ctx->stream);
         }
     };
     hipEvent_t e0, e1;

@@ -33,6 +33,7 @@ struct Ctl {
     int steps;
     long long matvecs;
     int restarts, traces;
+    int cyc;         // Krylov cycles begun (the host compares it with the cycles it issued)
     // current step
     double tau0;     // proposal of the current Krylov cycle (after the final-time clip)
     double tau_step; // whole step (constant mode: the fixed tau, clipped)
@@ -72,7 +73,7 @@ struct DevBuffers {
     double* part;       // reduction partials: two slots of CH_NRED * CH_MAXB
     Ctl* ctl;           // control blocks, one per slot
     int* dflag;         // device view of `hflag`, one word per slot
-    const volatile int* hflag;   // pinned host words: id of the last finished Krylov cycle per slot
+    const volatile int* hflag;   // pinned host words: `cyc` of the last finished Krylov cycle per slot
 };
 
 // The instance table of one launch sequence (device pointers + host mirror sizes).
@@ -110,11 +111,17 @@ hipError_t launch_cycle_begin(const Table& t, const DevBuffers& b, hipStream_t s
 hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
                          hipStream_t s);
 hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
-hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int cycle_id, hipStream_t s);
+hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, hipStream_t s);
+// Arnoldi iteration k: matvec, Gram-Schmidt passes, phi and residual test.
+hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
+                               hipStream_t s);
+// True when every instance has reported the current cycle finished:
+// expected[slot] is the number of cycles the host has issued for that slot.
+bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected);
 // Issues the Arnoldi iterations of one Krylov cycle; stops issuing once every
 // instance has reported the cycle finished (later launches would exit at once).
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
-                          int cycle_id, hipStream_t s);
+                          const int* expected, hipStream_t s);
 hipError_t launch_update(const Table& t, int prec, const DevBuffers& b, const double* y, double* ynew, hipStream_t s);
 hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y0,
                          const double* y1, hipStream_t s);

@@ -299,7 +299,7 @@ __device__ void store_u(Ctl* ctl, const double* E, int j) {
 // ---------------------------------------------------------------------------
 template <bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst, int k,
-                                                  const double* __restrict__ pin, int pin_stencil, int cycle_id,
+                                                  const double* __restrict__ pin, int pin_stencil,
                                                   int* __restrict__ dflags) {
     const Inst I = SINGLE ? inst0 : insts[blockIdx.x];   // one workgroup per instance
     Ctl* ctl = ctls + I.slot;
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
             ctl->status = CH_ENONFINITE;
             ctl->halted = 1;
             ctl->done = 1;
-            if (dflag) *dflag = cycle_id;
+            if (dflag) *dflag = ctl->cyc;
             ctl->j = 0;
         }
         return;
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
             ctl->resnorm = res0;
             ctl->converged = 1;
             ctl->done = 1;
-            if (dflag) *dflag = cycle_id;
+            if (dflag) *dflag = ctl->cyc;
             ctl->j = j;
         }
         return;
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
             ctl->status = CH_ETAU_UNDERFLOW;
             ctl->halted = 1;
             ctl->done = 1;
-            if (dflag) *dflag = cycle_id;
+            if (dflag) *dflag = ctl->cyc;
             ctl->j = 0;
         }
         return;
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
         ctl->converged = 0;
         ctl->traced = 1;
         ctl->done = 1;
-            if (dflag) *dflag = cycle_id;
+            if (dflag) *dflag = ctl->cyc;
         ctl->j = j;
     }
 }
@@ -463,6 +463,7 @@ __device__ void begin_step(Ctl* ctl) {
         tau = ctl->T - ctl->t;
         clipped = 1;
     }
+    ctl->cyc += 1;
     ctl->clipped = clipped;
     ctl->tau0 = tau;
     ctl->tau_step = tau;
@@ -525,6 +526,7 @@ template <bool SINGLE>
 __global__ void k_cycle_begin(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst) {
     Ctl* ctl = ctls + (SINGLE ? inst0.slot : insts[blockIdx.x].slot);
     if (threadIdx.x != 0 || ctl->halted || ctl->converged) return;
+    ctl->cyc += 1;
     ctl->covered += ctl->tau_acc;
     ctl->restarts += 1;
     ctl->mv_step += 1 + ctl->j;
@@ -771,30 +773,38 @@ hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSe
     return hipGetLastError();
 }
 
-hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int cycle_id, hipStream_t s) {
+hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, hipStream_t s) {
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_phi<true>), IARGS, k, ps.in(), ps.stencil, cycle_id, b.dflag);
+        hipLaunchKernelGGL((k_phi<true>), IARGS, k, ps.in(), ps.stencil, b.dflag);
     else
-        hipLaunchKernelGGL((k_phi<false>), IARGS, k, ps.in(), ps.stencil, cycle_id, b.dflag);
+        hipLaunchKernelGGL((k_phi<false>), IARGS, k, ps.in(), ps.stencil, b.dflag);
     return hipGetLastError();
 }
 
-static bool all_cycles_done(const Table& t, const DevBuffers& b, int cycle_id) {
-    if (!b.hflag) return false;
-    for (int i = 0; i < t.ninst; ++i)
-        if (b.hflag[t.hinst[i].slot] != cycle_id) return false;
+bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected) {
+    if (!b.hflag || !expected) return false;
+    for (int i = 0; i < t.ninst; ++i) {
+        const int slot = t.hinst[i].slot;
+        if (b.hflag[slot] != expected[slot]) return false;
+    }
     return true;
 }
 
+hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
+                               hipStream_t s) {
+    hipError_t e = launch_matvec(t, prec, b, ps, y, k, s);
+    if (e != hipSuccess) return e;
+    for (int i = 1; i <= k + 1; ++i)
+        if ((e = launch_mgs_pass(t, prec, b, ps, k, i, s)) != hipSuccess) return e;
+    return launch_phi(t, b, ps, k, s);
+}
+
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
-                          int cycle_id, hipStream_t s) {
+                          const int* expected, hipStream_t s) {
     for (int k = 0; k < m_max; ++k) {
-        if (k > 0 && all_cycles_done(t, b, cycle_id)) break;
-        hipError_t e = launch_matvec(t, prec, b, ps, y, k, s);
+        if (k > 0 && all_cycles_done(t, b, expected)) break;
+        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, s);
         if (e != hipSuccess) return e;
-        for (int i = 1; i <= k + 1; ++i)
-            if ((e = launch_mgs_pass(t, prec, b, ps, k, i, s)) != hipSuccess) return e;
-        if ((e = launch_phi(t, b, ps, k, cycle_id, s)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
