@@ -63,7 +63,7 @@ enum ch_precision {
 };
 
 /* Largest Krylov dimension m_max (the phi of H_{m,m} is evaluated in one workgroup's LDS). */
-#define CH_MMAX 48
+#define CH_MMAX 47
 /* Largest Chebyshev order p of one LIM step. */
 #define CH_PMAX 4096
 
@@ -75,12 +75,26 @@ typedef struct {
     int prec;       /* ch_precision (EE2 only; LIM always runs in FP64) */
 } ch_problem;
 
+/*
+ * Orthogonalisation of the Arnoldi process (Fig. 3 of Section 4.1).  Both give
+ * the same basis and Hessenberg matrix in exact arithmetic and orthogonality
+ * to working precision; they differ in rounding and in cost.
+ *   CH_ORTH_CGS2: classical Gram-Schmidt applied twice (Giraud, Langou,
+ *     Rozloznik, Comput. Math. Appl. 50 (2005) 1069-1075): per iteration the
+ *     matvec with the first projection's dot products, a second projection,
+ *     and the update with the new norm -- three streaming passes whatever j.
+ *   CH_ORTH_MGS: modified Gram-Schmidt as printed in Fig. 3, one streaming
+ *     pass per basis vector (j + 1 passes in iteration j).
+ */
+enum ch_orth { CH_ORTH_CGS2 = 0, CH_ORTH_MGS = 1 };
+
 typedef struct {
     int m_max;              /* Krylov dimension, 1..CH_MMAX */
     double tol;             /* accuracy tolerance of eq. EEdt and eq. tol_phi */
     double tol_phi_fixed;   /* > 0: use this tol_phi instead of eq. tol_phi */
     double tau_min;         /* trace underflow threshold (>= 0) */
     int constant_step;      /* 1: constant tau with linear RT restarts (no controller) */
+    int orth;               /* ch_orth (0, the zero-initialised default: CH_ORTH_CGS2) */
 } ch_ee_opts;
 
 /* Per-step record (one per accepted step). */
@@ -120,7 +134,7 @@ const char *ch_last_error_message(ch_ctx *ctx);
  * Adaptive (Fig. 4) or constant-step EE2 run on the field y (in/out).
  * Starts at time t0 with proposed step tau0 and advances until t >= T or
  * max_steps steps were accepted (T may be INFINITY; max_steps <= 0: no limit,
- * then T must be finite).  Every step clips tau to T - t (Fig. 4, lines 3-5).
+ * then T must be finite).  Every step clips tau to T - t (Fig. 4).
  * records: NULL or an array of max_steps ch_step_record (host memory).
  */
 int ch_run_ee(ch_ctx *ctx, const ch_problem *prob, double *y, double tau0, double t0, double T,
@@ -174,6 +188,7 @@ enum ch_phi_mode {
  * y_out = y + tau phi(-tau Ahat_n)(ghat^n - Ahat_n y) (eq. yt) with Ahat_n, ghat^n frozen
  * at y (eq. A_g / A_g_cs); y is not modified; y_out may not alias y.
  * out->tau is the step actually covered (< tau0 only in CH_PHI_SHRINK mode).
+ * The Arnoldi process uses CH_ORTH_CGS2.
  */
 int ch_phiv(ch_ctx *ctx, const ch_problem *prob, const double *y, double *y_out, double tau0,
             int mode, double tol_phi, int m_max, ch_step_record *out);
@@ -225,7 +240,11 @@ int ch_poll(ch_server *srv, unsigned long long ticket, int *state, double *y_out
 enum ch_kernel {
     CH_KERNEL_MGS = 0,      /* one modified Gram-Schmidt pass (axpy + next dot) over the grid */
     CH_KERNEL_MATVEC = 1,   /* one fused Jacobian matvec Ahat v with its first dot */
-    CH_KERNEL_PHI = 2       /* one small-matrix phi evaluation of the last step's H (no trace) */
+    CH_KERNEL_PHI = 2,      /* one small-matrix phi evaluation of the last step's H (no trace) */
+    /* the three CH_ORTH_CGS2 passes of Arnoldi iteration m_max - 1 (j = m_max basis vectors): */
+    CH_KERNEL_CGS_MATVEC = 3,   /* matvec Ahat v_j with the j dot products of the first projection */
+    CH_KERNEL_CGS_PROJECT = 4,  /* first projection applied on the fly, j dot products of the second */
+    CH_KERNEL_CGS_UPDATE = 5    /* both projections applied and stored, partials of the new norm */
 };
 
 /*
@@ -234,8 +253,8 @@ enum ch_kernel {
  * HIP events on the context's stream, on the workspace of the last ch_run_ee
  * call (same problem, precision and Krylov dimension m_max >= 2 are required).
  * *bytes receives the algorithmic bytes one launch must move (each operand
- * vector read or written once).  Overwrites basis columns 1-2 and the control
- * block; a later run re-initialises both.
+ * vector read or written once).  Overwrites basis columns 1, 2 and m_max and
+ * the control block; a later run re-initialises them.
  */
 int ch_time_kernel(ch_ctx *ctx, const ch_problem *prob, int kernel, int m_max, int reps,
                    double *avg_us, double *bytes);

@@ -229,11 +229,11 @@ def krylov_phi_cycle(matvec, y: np.ndarray, v1: np.ndarray, tau0: float, tol_phi
                      m_max: int, tau_min: float = 0.0, keep_basis: bool = False):
     """One run of the Krylov algorithm of Fig. 3 on y' = -Ahat y + ghat, y(0) = y.
 
-    matvec(v) returns Ahat v; v1 = ghat - Ahat y is the start vector (line 2).
-    Arnoldi with modified Gram-Schmidt (lines 3-9, eq. Arn), the residual test
-    of eq. phi_stop at s = tau0 (lines 11-14) and, at j = m_max, the trace of
-    the residual over s (lines 15-19, reading R1).  Returns y + V_j (beta u)
-    (line 23), the accepted tau and a KrylovInfo.
+    matvec(v) returns Ahat v; v1 = ghat - Ahat y is the start vector.
+    Arnoldi with modified Gram-Schmidt (eq. Arn), the residual test
+    of eq. phi_stop at s = tau0 and, at j = m_max, the trace of
+    the residual over s (reading R1).  Returns y + V_j (beta u)
+    (the solution update), the accepted tau and a KrylovInfo.
     """
     N = y.size
     beta = float(np.linalg.norm(v1))
@@ -435,7 +435,7 @@ def _stencil_columns(prob: Problem):
 
 
 def lambda_max(y: np.ndarray, prob: Problem) -> float:
-    """lambda_max := ||Ahat_n||_1 = max_j sum_i |ahat_ij| (Fig. 1, step 1).
+    """lambda_max := ||Ahat_n||_1 = max_j sum_i |ahat_ij| (the spectral bound of Fig. 1).
 
     Column j of Ahat_n = A diag(d) + eps^2 A^2 is d_j A e_j + eps^2 A^2 e_j, so
     its absolute sum is a sum over the stencil offsets of
@@ -456,7 +456,7 @@ def lim_order(tau: float, lam: float) -> int:
 
 
 def lim_coefficients(p: int, lam: float):
-    """Chebyshev nodes beta_m and parameters a_m (Fig. 1, steps 2, 3, 5; reading R6)."""
+    """Chebyshev nodes beta_m and parameters a_m (Fig. 1; reading R6)."""
     betas = [math.cos(math.pi * (2 * i - 1) / (2 * p)) for i in range(1, p + 1)]
     z1 = betas[0]
     a = [lam / (1.0 + z1) * (z1 - b) for b in betas]
@@ -464,7 +464,7 @@ def lim_coefficients(p: int, lam: float):
 
 
 def lim_iterate(matvec, g: np.ndarray, y: np.ndarray, tau: float, lam: float):
-    """Steps 2-13 of Fig. 1 for y' = -Ahat y + g, y(0) = y, given lambda_max.
+    """The Chebyshev iteration of Fig. 1 for y' = -Ahat y + g, y(0) = y, given lambda_max.
 
     Returns (y^{n+1}, p).  2p - 1 matvecs are made.
     """

@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("CH_LIB_PATH") or os.path.join(os.path.dirname(os.path
 CH_OK, CH_EINVAL, CH_ENOMEM, CH_ENONFINITE, CH_ETAU_UNDERFLOW, CH_EBUSY, CH_ENOENT, CH_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 CH_FP64, CH_FP32_MIXED = 0, 1
 CH_PHI_SHRINK, CH_PHI_RESTART = 0, 1
-CH_MMAX = 48
+CH_MMAX = 47
 CH_PMAX = 4096
 
 EXPORTED = (
@@ -28,6 +28,8 @@ EXPORTED = (
 )
 CH_REQ_QUEUED, CH_REQ_RUNNING, CH_REQ_DONE, CH_REQ_FAILED = 0, 1, 2, 3
 CH_KERNEL_MGS, CH_KERNEL_MATVEC, CH_KERNEL_PHI = 0, 1, 2
+CH_KERNEL_CGS_MATVEC, CH_KERNEL_CGS_PROJECT, CH_KERNEL_CGS_UPDATE = 3, 4, 5
+CH_ORTH_CGS2, CH_ORTH_MGS = 0, 1
 
 
 class ChProblem(ctypes.Structure):
@@ -36,7 +38,7 @@ class ChProblem(ctypes.Structure):
 
 class ChEeOpts(ctypes.Structure):
     _fields_ = [("m_max", c_int), ("tol", c_double), ("tol_phi_fixed", c_double), ("tau_min", c_double),
-                ("constant_step", c_int)]
+                ("constant_step", c_int), ("orth", c_int)]
 
 
 class ChStepRecord(ctypes.Structure):
@@ -182,10 +184,12 @@ class Context:
     # -- EE2 ---------------------------------------------------------------
     def run_ee(self, prob: Problem, y, tau0: float, *, t0: float = 0.0, T: float = math.inf, max_steps: int = 0,
                m_max: int = 30, tol: float = 1e-4, tol_phi_fixed: float = 0.0, tau_min: float = 0.0,
-               constant_step: bool = False, records: bool = False, raise_on_error: bool = True):
+               constant_step: bool = False, records: bool = False, raise_on_error: bool = True,
+               orth: int = CH_ORTH_CGS2):
         """Adaptive (Fig. 4) or constant-step EE2 run on y in place; returns (stats, records)."""
         _check_field(y, prob.N)
-        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), int(bool(constant_step)))
+        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), int(bool(constant_step)),
+                        int(orth))
         st = ChRunStats()
         recs = (ChStepRecord * max_steps)() if (records and max_steps > 0) else None
         pb = prob.c()
@@ -198,9 +202,11 @@ class Context:
         return out, ([r.as_dict() for r in recs[: st.steps]] if recs is not None else None)
 
     def step_ee(self, prob: Problem, y, tau: float, *, t: float = 0.0, T: float = math.inf, m_max: int = 30,
-                tol: float = 1e-4, tol_phi_fixed: float = 0.0, tau_min: float = 0.0, constant_step: bool = False):
+                tol: float = 1e-4, tol_phi_fixed: float = 0.0, tau_min: float = 0.0, constant_step: bool = False,
+                orth: int = CH_ORTH_CGS2):
         _check_field(y, prob.N)
-        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), int(bool(constant_step)))
+        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), int(bool(constant_step)),
+                        int(orth))
         rec = ChStepRecord()
         pb = prob.c()
         rc = self.lib.ch_step_ee(self._ptr, byref(pb), c_void_p(y.data_ptr()), float(tau), float(t), float(T),
@@ -210,7 +216,8 @@ class Context:
 
     def run_ee_batch(self, fields, ns, eps, *, dim: int = 2, eyre: bool = False, precision: int = CH_FP64,
                      tau0=1e-3, T=math.inf, max_steps=50, m_max: int = 30, tol: float = 1e-4,
-                     tol_phi_fixed: float = 0.0, tau_min: float = 0.0, raise_on_error: bool = True):
+                     tol_phi_fixed: float = 0.0, tau_min: float = 0.0, raise_on_error: bool = True,
+                     orth: int = CH_ORTH_CGS2):
         """Adaptive EE2 on many instances at once (each field updated in place); returns per-instance stats."""
         count = len(fields)
         as_list = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * count
@@ -220,7 +227,7 @@ class Context:
             _check_field(y, ns[i] ** dim)
             items[i] = ChBatchItem(int(ns[i]), float(eps[i]), c_void_p(y.data_ptr()), float(tau0s[i]),
                                    float(Ts[i]), int(steps[i]))
-        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), 0)
+        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), 0, int(orth))
         st = (ChRunStats * count)()
         rc = self.lib.ch_run_ee_batch(self._ptr, count, items, int(dim), int(bool(eyre)), int(precision),
                                       byref(opts), st)
@@ -280,9 +287,10 @@ class Server:
     """Continuous-batching EE2 server (ch_server_create / ch_submit / ch_poll)."""
 
     def __init__(self, device: int = 0, precision: int = CH_FP64, m_max: int = 30, tol: float = 1e-4,
-                 tol_phi_fixed: float = 0.0, hbm_budget: int = 8 << 30, max_slots: int = 64):
+                 tol_phi_fixed: float = 0.0, hbm_budget: int = 8 << 30, max_slots: int = 64,
+                 orth: int = CH_ORTH_CGS2):
         self.lib = load_library()
-        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), 0.0, 0)
+        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), 0.0, 0, int(orth))
         self._ptr = c_void_p()
         rc = self.lib.ch_server_create(device, int(precision), byref(opts), int(hbm_budget), int(max_slots),
                                        byref(self._ptr))

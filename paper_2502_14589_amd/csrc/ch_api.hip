@@ -97,6 +97,8 @@ int check_grid(int dim, int n, double eps, int eyre, Shape* sh) {
     return CH_OK;
 }
 
+bool orth_ok(int orth) { return orth == CH_ORTH_CGS2 || orth == CH_ORTH_MGS; }
+
 int check_problem(const ch_problem* p, Shape* sh) {
     if (!p) return CH_EINVAL;
     if (p->prec != CH_FP64 && p->prec != CH_FP32_MIXED) return CH_EINVAL;
@@ -110,6 +112,9 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
     int rc;
     if (!b.part) {
         if ((rc = alloc_dev(ctx, (void**)&b.part, 2 * sizeof(double) * CH_NRED * CH_MAXB))) return rc;
+    }
+    if (!b.dots) {
+        if ((rc = alloc_dev(ctx, (void**)&b.dots, sizeof(double) * (CH_MMAX + 1) * CH_MAXB))) return rc;
     }
     if (nslots > ctx->slots) {
         free_dev(b.ctl);
@@ -300,7 +305,8 @@ bool all_halted(const ch_ctx* ctx, int n) {
 // restarts, reading in the oracle's header): re-start from the current
 // sub-step state `z` with the residual of the frozen problem, until a cycle
 // converges on the rest of tau.
-int restart_cycles(ch_ctx* ctx, const Table& t, int prec, PartSeq& ps, const double* y, double* z, int m_max) {
+int restart_cycles(ch_ctx* ctx, const Table& t, int prec, PartSeq& ps, const double* y, double* z, int m_max,
+                   int orth) {
     const DevBuffers& b = ctx->b;
     for (int cyc = 0; cyc < 100000; ++cyc) {
         int rc = read_heads(ctx, 1);
@@ -311,7 +317,7 @@ int restart_cycles(ch_ctx* ctx, const Table& t, int prec, PartSeq& ps, const dou
         ctx->expect[t.hinst[0].slot] += 1;
         HIP_TRY(ctx, launch_resid(t, prec, b, ps, y, z, false, false, ctx->stream));
         HIP_TRY(ctx, launch_after_resid(t, b, ps, false, ctx->stream));
-        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, y, m_max, ctx->expect.data(), ctx->stream));
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, y, m_max, orth, ctx->expect.data(), ctx->stream));
         HIP_TRY(ctx, launch_update(t, prec, b, z, z, ctx->stream));
     }
     ctx->err = "restart cycle limit reached";
@@ -331,7 +337,7 @@ void fill_stats(const Ctl& h, ch_run_stats* st) {
 
 // Issue EE2 steps for every instance of the table until all are halted (each
 // stops at its own T or step limit) or `max_launch` steps have been issued.
-int issue_ee_steps(ch_ctx* ctx, const Table& t, int prec, int m_max, bool constant, long long max_launch) {
+int issue_ee_steps(ch_ctx* ctx, const Table& t, int prec, int m_max, int orth, bool constant, long long max_launch) {
     const DevBuffers& b = ctx->b;
     PartSeq ps;
     ps.base = b.part;
@@ -341,9 +347,9 @@ int issue_ee_steps(ch_ctx* ctx, const Table& t, int prec, int m_max, bool consta
     for (int i = 0; i < t.ninst; ++i) ctx->expect[t.hinst[i].slot] += 1;
     for (long long s = 0; s < max_launch; ++s) {
         const int p = (int)(s & 1);
-        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[p], m_max, ctx->expect.data(), ctx->stream));
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[p], m_max, orth, ctx->expect.data(), ctx->stream));
         HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
-        if (constant && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[p], b.ybuf[p ^ 1], m_max))) return rc;
+        if (constant && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[p], b.ybuf[p ^ 1], m_max, orth))) return rc;
         HIP_TRY(ctx, launch_est_ee(t, prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
         HIP_TRY(ctx, launch_step_end(t, b, ps, true, ctx->stream));
         for (int i = 0; i < t.ninst; ++i) ctx->expect[t.hinst[i].slot] += 1;
@@ -374,7 +380,7 @@ int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t
     int rc = check_problem(prob, &sh);
     if (rc) return rc;
     if (!y || !opts) return CH_EINVAL;
-    if (opts->m_max < 1 || opts->m_max > CH_MMAX) return CH_EINVAL;
+    if (opts->m_max < 1 || opts->m_max > CH_MMAX || !orth_ok(opts->orth)) return CH_EINVAL;
     if (!(tau0 > 0.0) || !(opts->tau_min >= 0.0)) return CH_EINVAL;
     if (!(opts->tol > 0.0) && !(opts->tol_phi_fixed > 0.0)) return CH_EINVAL;
     if (max_steps <= 0 && !(T < INFINITY)) return CH_EINVAL;
@@ -391,7 +397,7 @@ int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t
     HIP_TRY(ctx, hipMemcpyAsync(ctx->b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     if ((rc = copy_in(ctx, m, y))) return rc;
     const long long limit = max_steps > 0 ? max_steps : (1LL << 40);
-    if ((rc = issue_ee_steps(ctx, t, prec, opts->m_max, constant, limit))) return rc;
+    if ((rc = issue_ee_steps(ctx, t, prec, opts->m_max, opts->orth, constant, limit))) return rc;
     if ((rc = read_heads(ctx, 1))) return rc;
     if ((rc = copy_out(ctx, m, 0, y))) return rc;
     const Ctl& h = ctx->hctl[0];
@@ -408,7 +414,7 @@ int run_ee_batch(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, in
                  const ch_ee_opts* opts, ch_run_stats* stats) {
     if (count < 1 || !items || !opts) return CH_EINVAL;
     if (prec != CH_FP64 && prec != CH_FP32_MIXED) return CH_EINVAL;
-    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step) return CH_EINVAL;
+    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step || !orth_ok(opts->orth)) return CH_EINVAL;
     if (!(opts->tol > 0.0) && !(opts->tol_phi_fixed > 0.0)) return CH_EINVAL;
     std::vector<Member> ms(count);
     size_t pts = 0;
@@ -435,7 +441,7 @@ int run_ee_batch(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, in
         if ((rc = copy_in(ctx, ms[i], it.y))) return rc;
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->b.ctl, ctx->hctl, sizeof(Ctl) * count, hipMemcpyHostToDevice, ctx->stream));
-    if ((rc = issue_ee_steps(ctx, t, prec, opts->m_max, false, limit))) return rc;
+    if ((rc = issue_ee_steps(ctx, t, prec, opts->m_max, opts->orth, false, limit))) return rc;
     if ((rc = read_heads(ctx, count))) return rc;
     int status = CH_OK;
     for (int i = 0; i < count; ++i) {
@@ -679,7 +685,8 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
     }
     PartSeq ps;
     ps.base = b.part;
-    HIP_TRY(ctx, launch_arnoldi(*t, S->prec, b, ps, b.ybuf[p], S->opts.m_max, ctx->expect.data(), ctx->stream));
+    HIP_TRY(ctx, launch_arnoldi(*t, S->prec, b, ps, b.ybuf[p], S->opts.m_max, S->opts.orth, ctx->expect.data(),
+                                ctx->stream));
     HIP_TRY(ctx, launch_update(*t, S->prec, b, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
     HIP_TRY(ctx, launch_est_ee(*t, S->prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
     HIP_TRY(ctx, launch_step_end(*t, b, ps, true, ctx->stream));
@@ -772,7 +779,7 @@ int ch_destroy(ch_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     DevBuffers& b = ctx->b;
     for (void* p : {(void*)b.V, (void*)b.ybuf[0], (void*)b.ybuf[1], (void*)b.fcur, (void*)b.y32, (void*)b.zbuf,
-                    (void*)b.part, (void*)b.ctl, (void*)ctx->rec, (void*)ctx->d_inst, (void*)ctx->d_sb2i,
+                    (void*)b.part, (void*)b.dots, (void*)b.ctl, (void*)ctx->rec, (void*)ctx->d_inst, (void*)ctx->d_sb2i,
                     (void*)ctx->d_cb2i})
         free_dev(p);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
@@ -862,9 +869,10 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     HIP_TRY(ctx, launch_resid(t, prec, b, ps, b.ybuf[0], b.ybuf[0], false, true, ctx->stream));
     HIP_TRY(ctx, launch_after_resid(t, b, ps, true, ctx->stream));
     ctx->expect[0] += 1;
-    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, ctx->expect.data(), ctx->stream));
+    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, CH_ORTH_CGS2, ctx->expect.data(), ctx->stream));
     HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[0], b.ybuf[1], ctx->stream));
-    if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[0], b.ybuf[1], m_max))) return rc;
+    if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[0], b.ybuf[1], m_max, CH_ORTH_CGS2)))
+        return rc;
     if ((rc = read_heads(ctx, 1))) return rc;
     const Ctl& h = ctx->hctl[0];
     if (h.status == CH_OK)
@@ -882,7 +890,7 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     int rc = check_problem(prob, &sh);
     if (rc) return rc;
     if (m_max < 2 || m_max > CH_MMAX) return CH_EINVAL;
-    if (kernel != CH_KERNEL_MGS && kernel != CH_KERNEL_MATVEC && kernel != CH_KERNEL_PHI) return CH_EINVAL;
+    if (kernel < CH_KERNEL_MGS || kernel > CH_KERNEL_CGS_UPDATE) return CH_EINVAL;
     const int prec = prob->prec;
     const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
     const DevBuffers& b = ctx->b;
@@ -901,7 +909,11 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     if (kernel == CH_KERNEL_PHI && jlast < 1) return CH_EINVAL;
     h.done = 0;
     h.halted = 0;
-    h.vscale[0] = h.vscale[1] = h.vscale[2] = 1.0;
+    // unit scales and zero projection coefficients: the timed passes move
+    // every operand but leave the data as it was
+    const int kc = m_max - 1;
+    for (int i = 0; i <= m_max; ++i) h.vscale[i] = 1.0;
+    for (int i = 0; i <= kc; ++i) h.h1[i] = h.H[i + kc * CH_LDH] = 0.0;
     h.tol_phi = 1.0;
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(b.part, 0, 2 * sizeof(double) * CH_NRED * CH_MAXB, ctx->stream));
@@ -911,8 +923,11 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
         ps.base = b.part;
         switch (kernel) {
             case CH_KERNEL_MGS: return launch_mgs_pass(t, prec, b, ps, 1, 1, ctx->stream);
-            case CH_KERNEL_MATVEC: return launch_matvec(t, prec, b, ps, y, 0, ctx->stream);
-            default: return launch_phi(t, b, ps, jlast - 1, ctx->stream);
+            case CH_KERNEL_MATVEC: return launch_matvec(t, prec, b, ps, y, 0, false, ctx->stream);
+            case CH_KERNEL_PHI: return launch_phi(t, b, ps, jlast - 1, ctx->stream);
+            case CH_KERNEL_CGS_MATVEC: return launch_matvec(t, prec, b, ps, y, kc, true, ctx->stream);
+            case CH_KERNEL_CGS_PROJECT: return launch_cgs_project(t, prec, b, kc, ctx->stream);
+            default: return launch_cgs_update(t, prec, b, ps, kc, ctx->stream);
         }
     };
     hipEvent_t e0, e1;
@@ -934,9 +949,15 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     *avg_us = 1000.0 * ms / reps;
     const double N = double(sh.N);
     const double ysz = prec == CH_FP64 ? 8.0 : 4.0;
-    if (kernel == CH_KERNEL_MGS) *bytes = 4.0 * esz * N;                 // read w, v_{i-1}, v_i; write w
-    else if (kernel == CH_KERNEL_MATVEC) *bytes = (3.0 * esz + ysz) * N; // read v_k, y, v_1; write w
-    else *bytes = 0.0;
+    const double j = double(m_max);   // basis columns of the timed CGS2 iteration
+    switch (kernel) {
+        case CH_KERNEL_MGS: *bytes = 4.0 * esz * N; break;                      // read w, v_{i-1}, v_i; write w
+        case CH_KERNEL_MATVEC: *bytes = (3.0 * esz + ysz) * N; break;           // read v_k, y, v_1; write w
+        case CH_KERNEL_CGS_MATVEC: *bytes = ((j + 1.0) * esz + ysz) * N; break; // read y, v_0..v_k; write w
+        case CH_KERNEL_CGS_PROJECT: *bytes = (j + 1.0) * esz * N; break;        // read w, v_0..v_k
+        case CH_KERNEL_CGS_UPDATE: *bytes = (j + 2.0) * esz * N; break;         // read w, v_0..v_k; write w
+        default: *bytes = 0.0;
+    }
     return CH_OK;
 }
 
@@ -945,7 +966,7 @@ int ch_server_create(int device, int prec, const ch_ee_opts* opts, size_t hbm_bu
     if (!out || !opts) return CH_EINVAL;
     *out = nullptr;
     if (prec != CH_FP64 && prec != CH_FP32_MIXED) return CH_EINVAL;
-    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step) return CH_EINVAL;
+    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step || !orth_ok(opts->orth)) return CH_EINVAL;
     if (!(opts->tol > 0.0) && !(opts->tol_phi_fixed > 0.0)) return CH_EINVAL;
     if (max_slots < 1 || max_slots > 4096) return CH_EINVAL;
     const size_t esz = prec == CH_FP64 ? 8 : 4;

@@ -45,6 +45,7 @@ struct Ctl {
     // Arnoldi
     double H[CH_LDH * CH_MMAX];   // h_{i+1,k+1} at H[i + k*CH_LDH]
     double vscale[CH_MMAX + 1];   // v_i = vscale[i] * V(:, i)
+    double h1[CH_MMAX + 1];       // CGS2: first-projection coefficients of the current iteration
     double u[CH_MMAX];            // tau phi(-tau H) e_1
 };
 
@@ -71,6 +72,7 @@ struct DevBuffers {
     float* y32;         // FP32 copy of y^n (mixed precision only)
     double* zbuf;       // FP64 scratch (LIM stages)
     double* part;       // reduction partials: two slots of CH_NRED * CH_MAXB
+    double* dots;       // CGS2 dot-product partials: (CH_MMAX + 1) rows of CH_MAXB
     Ctl* ctl;           // control blocks, one per slot
     int* dflag;         // device view of `hflag`, one word per slot
     const volatile int* hflag;   // pinned host words: `cyc` of the last finished Krylov cycle per slot
@@ -108,20 +110,27 @@ hipError_t launch_resid(const Table& t, int prec, const DevBuffers& b, PartSeq& 
                         bool write_f, bool write_y32, hipStream_t s);
 hipError_t launch_after_resid(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_step, hipStream_t s);
 hipError_t launch_cycle_begin(const Table& t, const DevBuffers& b, hipStream_t s);
+// alldots: the dot products of w with every basis column 0..k go to b.dots
+// (CGS2); otherwise the one with column 0 to the next partials slot (MGS).
 hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                         hipStream_t s);
+                         bool alldots, hipStream_t s);
+// CGS2 passes of Arnoldi iteration k (see ch_krylov.hip).
+hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, int stage, hipStream_t s);
+hipError_t launch_cgs_project(const Table& t, int prec, const DevBuffers& b, int k, hipStream_t s);
+hipError_t launch_cgs_update(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, hipStream_t s);
 hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
 hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, hipStream_t s);
-// Arnoldi iteration k: matvec, Gram-Schmidt passes, phi and residual test.
+// Arnoldi iteration k: matvec, Gram-Schmidt passes (orth: ch_orth), phi and
+// residual test.
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               hipStream_t s);
+                               int orth, hipStream_t s);
 // True when every instance has reported the current cycle finished:
 // expected[slot] is the number of cycles the host has issued for that slot.
 bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected);
 // Issues the Arnoldi iterations of one Krylov cycle; stops issuing once every
 // instance has reported the cycle finished (later launches would exit at once).
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
-                          const int* expected, hipStream_t s);
+                          int orth, const int* expected, hipStream_t s);
 hipError_t launch_update(const Table& t, int prec, const DevBuffers& b, const double* y, double* ynew, hipStream_t s);
 hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y0,
                          const double* y1, hipStream_t s);

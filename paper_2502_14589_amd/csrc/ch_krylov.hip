@@ -1,5 +1,6 @@
-// Arnoldi with modified Gram-Schmidt, the small-matrix phi with the
-// residual-time restart, the solution update and the per-step controllers.
+// Arnoldi (classical Gram-Schmidt twice, or modified Gram-Schmidt), the
+// small-matrix phi with the residual-time restart, the solution update and
+// the per-step controllers.
 //
 // Krylov algorithm of Fig. 3 (Section 4.1): for j = 1..m_max,
 //   w = Ahat v_j;  h_ij = w^T v_i, w -= h_ij v_i (i = 1..j);  h_{j+1,j} = ||w||;
@@ -9,7 +10,7 @@
 // then y^{n+1} = y^n + V_j (beta u).
 //
 // Storage: column i of the basis is kept unnormalised, v_i = vscale[i] V(:,i),
-// so the normalisation of line 21 is folded into the next reads.  One launch
+// so the normalisation of each new basis vector is folded into the next reads.  One launch
 // covers every instance of a batch; streaming kernels give each instance the
 // workgroups [cblk0, cblk0 + cblk) (map cb2i), single-workgroup kernels one
 // workgroup per instance.
@@ -81,7 +82,250 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctls, const 
 }
 
 // ---------------------------------------------------------------------------
-// y^{n+1} = y^n + V_j (beta u)  (Fig. 3, line 23)
+// CGS2 (classical Gram-Schmidt twice) for Arnoldi iteration k.  With
+// v_i = s_i V_i (s = vscale) and w = Ahat v_k in column k + 1:
+//   the matvec launch:   partials of d_i = <w, V_i>, i = 0..k
+//   k_dots_reduce(1):    h1_i = s_i d_i                   (first projection)
+//   k_cgs_project:       w' = w - sum_i s_i h1_i V_i on the fly (not stored),
+//                        partials of e_i = <w', V_i>
+//   k_dots_reduce(2):    h_{i,k} = h1_i + s_i e_i         (second projection)
+//   k_cgs_update:        w'' = w - sum_i s_i h_{i,k} V_i, stored, partials of ||w''||^2
+// and the phi launch takes h_{k+1,k} = ||w''||.  In exact arithmetic these are
+// the h_{ik} and w of the MGS loop of Fig. 3; the reorthogonalisation keeps the
+// basis orthogonal to working precision.  Projections are applied in FP64
+// whatever the storage precision of the basis.
+// ---------------------------------------------------------------------------
+
+// One workgroup per (row i, instance): total of the partials of row i.
+template <bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_dots_reduce(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                          const Inst inst0, int ninst, int k,
+                                                          const double* __restrict__ dots, int stage) {
+    const Inst I = SINGLE ? inst0 : insts[blockIdx.y];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->done | ctl->halted) return;
+    const int r = blockIdx.x;
+    double tot[1];
+    if (stage == 1)
+        sum_partials<1, RED_SUM>(dots + (size_t)r * CH_MAXB, I.sblk0, I.sblk, tot);
+    else
+        sum_partials<1, RED_SUM>(dots + (size_t)r * CH_MAXB, I.cblk0, I.cblk, tot);
+    if (threadIdx.x != 0) return;
+    const double h = ctl->vscale[r] * tot[0];
+    if (stage == 1) ctl->h1[r] = h;
+    else ctl->H[r + k * CH_LDH] = ctl->h1[r] + h;
+}
+
+// Accumulate <x, V_i> for i = 0..k over the items of a workgroup into
+// red[i][wave].  Every lane of the workgroup calls it (wave-wide sums); lanes
+// without items pass ok = false.
+template <typename TV, int Q>
+__device__ __forceinline__ void cgs_dots(const TV* __restrict__ Vi, size_t ldv, int k, const long long (&qq)[Q],
+                                         const bool (&ok)[Q], const double (&x)[Q][Vec16<TV>::W],
+                                         double (*red)[CH_BLOCK / 64]) {
+    using VT = typename Vec16<TV>::type;
+    constexpr int VW = Vec16<TV>::W, RB = 8;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // last columns first: those read most recently by cgs_axpys are the
+    // likeliest still to be cached
+    for (int i0 = (k / RB) * RB; i0 >= 0; i0 -= RB) {
+        VT v[RB][Q];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int u = 0; u < Q; ++u) {
+                const VT* col = reinterpret_cast<const VT*>(Vi + (size_t)(i0 + r) * ldv);
+                if (ok[u] && i0 + r <= k) v[r][u] = col[qq[u]];
+                else {
+                    TV* ve = reinterpret_cast<TV*>(&v[r][u]);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) ve[e] = TV(0);
+                }
+            }
+        double a[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            a[r] = 0.0;
+#pragma unroll
+            for (int u = 0; u < Q; ++u) {
+                const TV* ve = reinterpret_cast<const TV*>(&v[r][u]);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) a[r] += x[u][e] * double(ve[e]);
+            }
+        }
+        const double tot = wave_sum8(a);
+        const int r = (lane >> 3) & 7;
+        if ((lane & 7) == 0 && i0 + r <= k) red[i0 + r][wid] += tot;
+    }
+}
+
+// x -= sum_i cf[i] V_i over the same items (RB columns' loads issued together).
+template <typename TV, int Q, int RB>
+__device__ __forceinline__ void cgs_axpys(const TV* __restrict__ Vi, size_t ldv, int k, const long long (&qq)[Q],
+                                          const bool (&ok)[Q], const double* cf, double (&x)[Q][Vec16<TV>::W]) {
+    using VT = typename Vec16<TV>::type;
+    constexpr int VW = Vec16<TV>::W;
+    for (int i0 = 0; i0 <= k; i0 += RB) {
+        VT v[RB][Q];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int u = 0; u < Q; ++u) {
+                const VT* col = reinterpret_cast<const VT*>(Vi + (size_t)(i0 + r) * ldv);
+                if (ok[u] && i0 + r <= k) v[r][u] = col[qq[u]];
+                else {
+                    TV* ve = reinterpret_cast<TV*>(&v[r][u]);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) ve[e] = TV(0);
+                }
+            }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const double c = i0 + r <= k ? cf[i0 + r] : 0.0;
+#pragma unroll
+            for (int u = 0; u < Q; ++u) {
+                const TV* ve = reinterpret_cast<const TV*>(&v[r][u]);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) x[u][e] -= c * double(ve[e]);
+            }
+        }
+    }
+}
+
+// Second projection's dot products.  Items: Q 16-byte vectors per thread and
+// chunk, in chunks common to all workgroups of the instance; the last few
+// points of an instance whose size is not a multiple of the vector width are
+// one scalar chunk of its first workgroup.
+template <typename TV, bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_cgs_project(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                          const int* __restrict__ cb2i, const Inst inst0, int ninst,
+                                                          const TV* __restrict__ V, size_t ldv, int k,
+                                                          double* __restrict__ pout) {
+    const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->done | ctl->halted) return;
+    using VT = typename Vec16<TV>::type;
+    constexpr int VW = Vec16<TV>::W, Q = 1, NW = CH_BLOCK / 64;
+    __shared__ double cf[CH_MMAX + 1];
+    __shared__ double red[CH_MMAX + 1][NW];
+    for (int i = threadIdx.x; i <= k; i += CH_BLOCK) {
+        cf[i] = ctl->vscale[i] * ctl->h1[i];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) red[i][w] = 0.0;
+    }
+    __syncthreads();
+    const TV* Vi = V + I.off;
+    const TV* W = V + (size_t)(k + 1) * ldv + I.off;
+    const VT* W4 = reinterpret_cast<const VT*>(W);
+    const long long NV = I.N / VW;
+    const long long per = (long long)I.cblk * CH_BLOCK;
+    const long long lt = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
+    const long long nch = (NV + per * Q - 1) / (per * Q);
+    for (long long c = 0; c < nch; ++c) {
+        long long qq[Q];
+        bool ok[Q];
+        double x[Q][VW];
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            qq[u] = (c * Q + u) * per + lt;
+            ok[u] = qq[u] < NV;
+            VT w;
+            if (ok[u]) w = W4[qq[u]];
+            const TV* we = reinterpret_cast<const TV*>(&w);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) x[u][e] = ok[u] ? double(we[e]) : 0.0;
+        }
+        cgs_axpys<TV, Q, 8>(Vi, ldv, k, qq, ok, cf, x);
+        cgs_dots<TV, Q>(Vi, ldv, k, qq, ok, x, red);
+    }
+    if (NV * VW < I.N && blockIdx.x == I.cblk0) {   // scalar tail, fewer than VW points
+        const long long e = NV * VW + threadIdx.x;
+        const bool ok = e < I.N;
+        double x = 0.0;
+        if (ok) {
+            x = double(W[e]);
+            for (int i = 0; i <= k; ++i) x -= cf[i] * double(Vi[(size_t)i * ldv + e]);
+        }
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        for (int i = 0; i <= k; ++i) {
+            double a = 0.0;
+            if (ok) a = x * double(Vi[(size_t)i * ldv + e]);
+            a = wave_sum(a);
+            if (lane == 0) red[i][wid] += a;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= k; i += CH_BLOCK) {
+        double a = red[i][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) a += red[i][w];
+        pout[(size_t)i * CH_MAXB + blockIdx.x] = a;
+    }
+}
+
+// w'' = w - sum_i s_i h_{i,k} V_i, stored in the basis precision; partials of
+// ||w''||^2 of the stored vector.
+template <typename TV, bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_cgs_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                         const int* __restrict__ cb2i, const Inst inst0, int ninst,
+                                                         TV* __restrict__ V, size_t ldv, int k,
+                                                         double* __restrict__ pout) {
+    const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->done | ctl->halted) return;
+    using VT = typename Vec16<TV>::type;
+    constexpr int VW = Vec16<TV>::W, Q = 2;
+    __shared__ double cf[CH_MMAX + 1];
+    for (int i = threadIdx.x; i <= k; i += CH_BLOCK) cf[i] = ctl->vscale[i] * ctl->H[i + k * CH_LDH];
+    __syncthreads();
+    const TV* Vi = V + I.off;
+    TV* W = V + (size_t)(k + 1) * ldv + I.off;
+    VT* W4 = reinterpret_cast<VT*>(W);
+    const long long NV = I.N / VW;
+    const long long per = (long long)I.cblk * CH_BLOCK;
+    const long long lt = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
+    double acc = 0.0;
+    for (long long q0 = lt; q0 < NV; q0 += per * Q) {
+        long long qq[Q];
+        bool ok[Q];
+        double x[Q][VW];
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            qq[u] = q0 + u * per;
+            ok[u] = qq[u] < NV;
+            VT w;
+            if (ok[u]) w = W4[qq[u]];
+            const TV* we = reinterpret_cast<const TV*>(&w);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) x[u][e] = ok[u] ? double(we[e]) : 0.0;
+        }
+        cgs_axpys<TV, Q, 4>(Vi, ldv, k, qq, ok, cf, x);
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            if (!ok[u]) continue;
+            VT w;
+            TV* we = reinterpret_cast<TV*>(&w);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                we[e] = TV(x[u][e]);
+                acc += double(we[e]) * double(we[e]);
+            }
+            W4[qq[u]] = w;
+        }
+    }
+    for (long long e = NV * VW + lt; e < I.N; e += per) {
+        double x = double(W[e]);
+        for (int i = 0; i <= k; ++i) x -= cf[i] * double(Vi[(size_t)i * ldv + e]);
+        const TV xs = TV(x);
+        W[e] = xs;
+        acc += double(xs) * double(xs);
+    }
+    double x1[1] = {acc};
+    write_partials<1, RED_SUM>(x1, pout);
+}
+
+// ---------------------------------------------------------------------------
+// y^{n+1} = y^n + V_j (beta u)  (the solution update of Fig. 3)
 // ---------------------------------------------------------------------------
 template <typename TV, bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
@@ -110,91 +354,79 @@ __global__ __launch_bounds__(CH_BLOCK) void k_update(Ctl* __restrict__ ctls, con
 // Small-matrix exponential.  exp([[X, b], [0, 0]]) = [[e^X, phi(X) b], [0, 1]]
 // (phi of eq. phi), so with X = -s H_jj and b = s e_1 the last column holds
 // u = s phi(-s H_jj) e_1 and the first column exp(-s H_jj) e_1 = du/ds.
-// Evaluated by scaling and squaring with the diagonal [13/13] Pade
-// approximant (Higham, SIAM J. Matrix Anal. Appl. 26 (2005) 1179-1193: degree
-// 13, theta_13 = 5.371920351148152 for the 1-norm), all in FP64 LDS.
+//
+// Scaling and squaring with the degree-19 Taylor polynomial T_19: the
+// argument is scaled by 2^-q so that its 1-norm is at most theta_19 =
+// 1.2603811, the largest theta for which the relative backward error of T_19
+// is at most 2^-53 (the power series of log(e^-x T_19(x)) has coefficients
+// c_k, k >= 20, with sum_k |c_k| theta^(k-1) <= 2^-53; the backward-error
+// analysis of Al-Mohy and Higham, SIAM J. Matrix Anal. Appl. 31 (2009)
+// 970-989, applied to a Taylor instead of a Pade approximant).  T_19 is a
+// polynomial, so the evaluation is matrix products only -- no linear solve --
+// and all of them run on the FP64 matrix cores:
+//   X^2, X^3, X^4, X^5;  T_19 = B_0 + X^5 (B_1 + X^5 (B_2 + X^5 B_3)),
+//   B_i = sum_{q=0..4} X^q / (5i + q)!     (7 products),
+// then q squarings.  Everything stays in LDS, in FP64.
 // ---------------------------------------------------------------------------
-constexpr int PLD = CH_MMAX + 1;
-constexpr double THETA13 = 5.371920351148152;
+// Orders are padded to a multiple of 16 for the matrix cores; the padding is
+// a zero block of the argument, whose exponential is an identity block.
+constexpr int NPMAX = 48;          // largest padded order
+constexpr int PLD = NPMAX + 1;     // LDS row stride (odd: rows fall in different banks)
+static_assert(CH_MMAX + 1 <= NPMAX, "augmented matrix exceeds the padded order");
+constexpr double THETA19 = 1.2603811;
 constexpr int NLVL = 80;
 
 struct PhiShared {
-    double B[6][PLD * PLD];
-    double c[14];        // Pade coefficients
-    double lvl[NLVL];    // lvl[kk] = resnorm at s 2^-kk from the squaring chain
+    double B[7][NPMAX * PLD];   // X, X^2 .. X^5, two Horner / squaring buffers
+    double c[20];               // 1 / k!
+    double lvl[NLVL];           // lvl[kk] = resnorm at s 2^-kk from the squaring chain
     double red;
-    int ired;
 };
 
-__device__ void mm(double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B, int n) {
-    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
-        const int r = idx / n, c = idx - r * n;
-        const double* a = A + r * PLD;
-        double acc = 0.0;
-        for (int l = 0; l < n; ++l) acc = fma(a[l], B[l * PLD + c], acc);
-        C[r * PLD + c] = acc;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// C = A B (+ epi(r, c) elementwise) for padded order np (a multiple of 16) on
+// the FP64 matrix cores: 16x16 output tiles spread over the waves, K in steps
+// of 4.  Lanes of the 16x16x4 instruction: lane l supplies A(l % 16, l / 16)
+// and B(l / 16, l % 16) of its 16x4 and 4x16 slices and receives
+// C(4 v + l / 16, l % 16) in element v.
+struct NoEpi {
+    __device__ double operator()(int, int) const { return 0.0; }
+};
+
+template <typename Epi = NoEpi>
+__device__ void mm(double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B, int np,
+                   Epi epi = Epi()) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int T = np >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = wid; t < T * T; t += CH_BLOCK / 64) {
+        const int ti = t / T, tj = t - ti * T;
+        const double* a = A + (16 * ti + li) * PLD + lk;
+        const double* b = B + lk * PLD + 16 * tj + li;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int kk = 0; kk < np; kk += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk * PLD], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * ti + 4 * v + lk, c = 16 * tj + li;
+            C[r * PLD + c] = acc[v] + epi(r, c);
+        }
     }
     __syncthreads();
 }
 
-// Solve Q X = P in place (X overwrites P) by Gaussian elimination with
-// partial pivoting.
-__device__ void lu_solve(PhiShared& S, double* Q, double* P, int n) {
-    for (int col = 0; col < n; ++col) {
-        if (threadIdx.x < 64) {
-            const int r = col + threadIdx.x;
-            double v = r < n ? fabs(Q[r * PLD + col]) : -1.0;
-            int idx = r;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ov = __shfl_xor(v, off, 64);
-                const int oi = __shfl_xor(idx, off, 64);
-                if (ov > v || (ov == v && oi < idx)) {
-                    v = ov;
-                    idx = oi;
-                }
-            }
-            if (threadIdx.x == 0) S.ired = idx;
-        }
-        __syncthreads();
-        const int piv = S.ired;
-        if (piv != col) {
-            for (int c = threadIdx.x; c < 2 * n; c += CH_BLOCK) {
-                double* Mx = c < n ? Q : P;
-                const int cc = c < n ? c : c - n;
-                const double tmp = Mx[col * PLD + cc];
-                Mx[col * PLD + cc] = Mx[piv * PLD + cc];
-                Mx[piv * PLD + cc] = tmp;
-            }
-        }
-        __syncthreads();
-        const double pv = Q[col * PLD + col];
-        const int rows = n - col - 1, qc = n - col - 1, cols = qc + n;
-        for (int idx = threadIdx.x; idx < rows * cols; idx += CH_BLOCK) {
-            const int rr = col + 1 + idx / cols;
-            const int kk = idx % cols;
-            const double l = Q[rr * PLD + col] / pv;
-            if (kk < qc) {
-                const int cc = col + 1 + kk;
-                Q[rr * PLD + cc] -= l * Q[col * PLD + cc];
-            } else {
-                const int cc = kk - qc;
-                P[rr * PLD + cc] -= l * P[col * PLD + cc];
-            }
-        }
-        __syncthreads();
+// B_i(r, c) = sum_{q=0..4} X^q(r, c) / (5i + q)!
+struct TaylorBlock {
+    const double* X[5];   // X^1 .. X^4 in X[1..4]
+    const double* cf;
+    int i;
+    __device__ double operator()(int r, int c) const {
+        const int o = r * PLD + c;
+        const double* f = cf + 5 * i;
+        return (r == c ? f[0] : 0.0) + f[1] * X[1][o] + f[2] * X[2][o] + f[3] * X[3][o] + f[4] * X[4][o];
     }
-    for (int col = n - 1; col >= 0; --col) {
-        const double pv = Q[col * PLD + col];
-        for (int c = threadIdx.x; c < n; c += CH_BLOCK) P[col * PLD + c] /= pv;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < col * n; idx += CH_BLOCK) {
-            const int rr = idx / n, c = idx - rr * n;
-            P[rr * PLD + c] -= Q[rr * PLD + col] * P[col * PLD + c];
-        }
-        __syncthreads();
-    }
-}
+};
 
 // exp(s [[-H_jj, e_1], [0, 0]]); returns the LDS matrix holding it and the
 // number of squarings in *nsq_out.  Records resnorm at every dyadic level of
@@ -202,74 +434,58 @@ __device__ void lu_solve(PhiShared& S, double* Q, double* P, int n) {
 __device__ const double* expm_aug(PhiShared& S, const double* __restrict__ H, int j, double s, double hnext,
                                   int* nsq_out) {
     const int n = j + 1;
-    double* M = S.B[0];
-    double* A2 = S.B[1];
-    double* A4 = S.B[2];
-    double* A6 = S.B[3];
-    double* T1 = S.B[4];
-    double* T2 = S.B[5];
-    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
-        const int r = idx / n, c = idx - r * n;
+    const int np = (n + 15) & ~15;
+    double* X1 = S.B[0];
+    for (int idx = threadIdx.x; idx < np * np; idx += CH_BLOCK) {
+        const int r = idx / np, c = idx - r * np;
         double v = 0.0;
         if (r < j && c < j) v = -s * H[r + c * CH_LDH];
         else if (r == 0 && c == j) v = s;
-        M[r * PLD + c] = v;
+        X1[r * PLD + c] = v;
     }
     __syncthreads();
     if (threadIdx.x < 64) {
         double cs = 0.0;
         if ((int)threadIdx.x < n)
-            for (int r = 0; r < n; ++r) cs += fabs(M[r * PLD + threadIdx.x]);
+            for (int r = 0; r < n; ++r) cs += fabs(X1[r * PLD + threadIdx.x]);
         cs = wave_max(cs);
         if (threadIdx.x == 0) S.red = cs;
     }
     __syncthreads();
     const double nrm = S.red;
     int nsq = 0;
-    if (nrm > THETA13 && nrm < __builtin_inf()) nsq = (int)ceil(log2(nrm / THETA13));
+    if (nrm > THETA19 && nrm < __builtin_inf()) nsq = (int)ceil(log2(nrm / THETA19));
     if (nsq > 1100) nsq = 1100;
     const double scale = ldexp(1.0, -nsq);
     for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
         const int r = idx / n, c = idx - r * n;
-        M[r * PLD + c] *= scale;
+        X1[r * PLD + c] *= scale;
     }
     __syncthreads();
-    const double* cf = S.c;
-    mm(A2, M, M, n);
-    mm(A4, A2, A2, n);
-    mm(A6, A4, A2, n);
-    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
-        const int o = (idx / n) * PLD + idx % n;
-        T1[o] = cf[13] * A6[o] + cf[11] * A4[o] + cf[9] * A2[o];
+    mm(S.B[1], X1, X1, np);         // X^2
+    mm(S.B[2], S.B[1], X1, np);     // X^3
+    mm(S.B[3], S.B[1], S.B[1], np); // X^4
+    mm(S.B[4], S.B[3], X1, np);     // X^5
+    TaylorBlock tb{{nullptr, S.B[0], S.B[1], S.B[2], S.B[3]}, S.c, 3};
+    double* R = S.B[5];
+    double* R2 = S.B[6];
+    for (int idx = threadIdx.x; idx < np * np; idx += CH_BLOCK) {
+        const int r = idx / np, c = idx - r * np;
+        R[r * PLD + c] = tb(r, c);
     }
     __syncthreads();
-    mm(T2, A6, T1, n);
-    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
-        const int r = idx / n, c = idx - r * n, o = r * PLD + c;
-        T2[o] += cf[7] * A6[o] + cf[5] * A4[o] + cf[3] * A2[o] + (r == c ? cf[1] : 0.0);
+    for (int i = 2; i >= 0; --i) {
+        tb.i = i;
+        mm(R2, S.B[4], R, np, tb);
+        double* t = R;
+        R = R2;
+        R2 = t;
     }
-    __syncthreads();
-    mm(T1, M, T2, n);   // U (odd part)
-    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
-        const int o = (idx / n) * PLD + idx % n;
-        T2[o] = cf[12] * A6[o] + cf[10] * A4[o] + cf[8] * A2[o];
-    }
-    __syncthreads();
-    mm(M, A6, T2, n);
-    for (int idx = threadIdx.x; idx < n * n; idx += CH_BLOCK) {
-        const int r = idx / n, c = idx - r * n, o = r * PLD + c;
-        const double V = M[o] + cf[6] * A6[o] + cf[4] * A4[o] + cf[2] * A2[o] + (r == c ? cf[0] : 0.0);
-        const double U = T1[o];
-        A2[o] = V + U;   // numerator p(M)
-        A4[o] = V - U;   // denominator q(M) = p(-M)
-    }
-    __syncthreads();
-    lu_solve(S, A4, A2, n);
-    double* X = A2;
-    double* Y = A6;
+    double* X = R;
+    double* Y = R2;
     if (threadIdx.x == 0 && nsq < NLVL) S.lvl[nsq] = hnext * fabs(X[(j - 1) * PLD + j]);
     for (int i = 1; i <= nsq; ++i) {
-        mm(Y, X, X, n);
+        mm(Y, X, X, np);
         double* tmp = X;
         X = Y;
         Y = tmp;
@@ -287,7 +503,7 @@ __device__ void store_u(Ctl* ctl, const double* E, int j) {
 
 // ---------------------------------------------------------------------------
 // phi of the Hessenberg matrix after Arnoldi iteration k, convergence test and
-// residual-time trace (Fig. 3, lines 10-20).  One workgroup.
+// residual-time trace (Fig. 3; eqs. rm, phi_stop).  One workgroup.
 //
 // Trace: the squaring chain of the evaluation at tau0 gives resnorm at every
 // s = tau0 2^-kk; the largest passing one brackets the crossing in
@@ -306,7 +522,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
     int* dflag = dflags ? dflags + I.slot : nullptr;
     if (ctl->done | ctl->halted) return;
     __shared__ PhiShared S;
-    // h_{k+2,k+1} = ||w|| from the final Gram-Schmidt pass (Fig. 3, line 9)
+    // h_{k+2,k+1} = ||w|| from the final Gram-Schmidt pass (Fig. 3)
     double nrm2[1];
     sum_inst_partials<1, RED_SUM>(pin, I, pin_stencil, nrm2);
     const double hnext = sqrt(nrm2[0]);
@@ -315,12 +531,12 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
         ctl->vscale[k + 1] = hnext > 0.0 ? 1.0 / hnext : 0.0;
     }
     if (threadIdx.x == 0) {
-        // [13/13] Pade coefficients of exp: c_0 = 1, c_{i+1} = c_i (13 - i) / ((26 - i)(i + 1))
+        // Taylor coefficients 1 / k!, k = 0..19
         double c = 1.0;
         S.c[0] = 1.0;
-        for (int i = 0; i < 13; ++i) {
-            c = c * double(13 - i) / (double(26 - i) * double(i + 1));
-            S.c[i + 1] = c;
+        for (int i = 1; i < 20; ++i) {
+            c /= double(i);
+            S.c[i] = c;
         }
     }
     __syncthreads();
@@ -449,7 +665,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
 }
 
 // ---------------------------------------------------------------------------
-// Step begin (Fig. 4, lines 3-7): final-time clip and tol_phi (eq. tol_phi).
+// Step begin (Fig. 4): final-time clip and tol_phi (eq. tol_phi).
 // ---------------------------------------------------------------------------
 __device__ void begin_step(Ctl* ctl) {
     if (ctl->halted) return;
@@ -539,7 +755,7 @@ __global__ void k_cycle_begin(Ctl* __restrict__ ctls, const Inst* __restrict__ i
 }
 
 // ---------------------------------------------------------------------------
-// EE2 step end (Fig. 4, lines 8-10): est (eq. LIMest), t, tau_new (eq. EEdt);
+// EE2 step end (Fig. 4): est (eq. LIMest), t, tau_new (eq. EEdt);
 // optionally the begin of the next step.
 // ---------------------------------------------------------------------------
 template <bool SINGLE>
@@ -605,7 +821,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_step_end(Ctl* __restrict__ ctls, c
 }
 
 // ---------------------------------------------------------------------------
-// LIM step begin (Fig. 1, steps 1-2; Fig. 2, lines 3-5): partials of
+// LIM step begin (Figs. 1 and 2: bounds of the spectrum): partials of
 // min/max y^2 (and a non-finite flag) ...
 // ---------------------------------------------------------------------------
 template <bool SINGLE>
@@ -687,7 +903,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, c
     ctl->p = (int)pr;
 }
 
-// LIM step end (Fig. 2, lines 8-10): est (eq. LIMest), t, tau_new (eq. LIMdt).
+// LIM step end (Fig. 2): est (eq. LIMest), t, tau_new (eq. LIMdt).
 template <bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_end(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst,
                                                       const double* __restrict__ pin, int pin_stencil) {
@@ -790,20 +1006,70 @@ bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected) {
     return true;
 }
 
+hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, int stage, hipStream_t s) {
+    const dim3 grid(k + 1, t.ninst);
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_dots_reduce<true>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst, k,
+                           b.dots, stage);
+    else
+        hipLaunchKernelGGL((k_dots_reduce<false>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst, k,
+                           b.dots, stage);
+    return hipGetLastError();
+}
+
+template <typename TV>
+static void launch_cgs_project_t(const Table& t, const DevBuffers& b, int k, hipStream_t s) {
+    const TV* V = static_cast<const TV*>(b.V);
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_cgs_project<TV, true>), CARGS, V, b.ldv, k, b.dots);
+    else
+        hipLaunchKernelGGL((k_cgs_project<TV, false>), CARGS, V, b.ldv, k, b.dots);
+}
+
+hipError_t launch_cgs_project(const Table& t, int prec, const DevBuffers& b, int k, hipStream_t s) {
+    if (prec == CH_FP64) launch_cgs_project_t<double>(t, b, k, s);
+    else launch_cgs_project_t<float>(t, b, k, s);
+    return hipGetLastError();
+}
+
+template <typename TV>
+static void launch_cgs_update_t(const Table& t, const DevBuffers& b, int k, double* pout, hipStream_t s) {
+    TV* V = static_cast<TV*>(b.V);
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_cgs_update<TV, true>), CARGS, V, b.ldv, k, pout);
+    else
+        hipLaunchKernelGGL((k_cgs_update<TV, false>), CARGS, V, b.ldv, k, pout);
+}
+
+hipError_t launch_cgs_update(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, hipStream_t s) {
+    if (prec == CH_FP64) launch_cgs_update_t<double>(t, b, k, ps.out(), s);
+    else launch_cgs_update_t<float>(t, b, k, ps.out(), s);
+    ps.produced(false);
+    return hipGetLastError();
+}
+
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               hipStream_t s) {
-    hipError_t e = launch_matvec(t, prec, b, ps, y, k, s);
-    if (e != hipSuccess) return e;
-    for (int i = 1; i <= k + 1; ++i)
-        if ((e = launch_mgs_pass(t, prec, b, ps, k, i, s)) != hipSuccess) return e;
+                               int orth, hipStream_t s) {
+    hipError_t e;
+    if (orth == CH_ORTH_MGS) {
+        if ((e = launch_matvec(t, prec, b, ps, y, k, false, s)) != hipSuccess) return e;
+        for (int i = 1; i <= k + 1; ++i)
+            if ((e = launch_mgs_pass(t, prec, b, ps, k, i, s)) != hipSuccess) return e;
+    } else {
+        if ((e = launch_matvec(t, prec, b, ps, y, k, true, s)) != hipSuccess) return e;
+        if ((e = launch_dots_reduce(t, b, k, 1, s)) != hipSuccess) return e;
+        if ((e = launch_cgs_project(t, prec, b, k, s)) != hipSuccess) return e;
+        if ((e = launch_dots_reduce(t, b, k, 2, s)) != hipSuccess) return e;
+        if ((e = launch_cgs_update(t, prec, b, ps, k, s)) != hipSuccess) return e;
+    }
     return launch_phi(t, b, ps, k, s);
 }
 
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
-                          const int* expected, hipStream_t s) {
+                          int orth, const int* expected, hipStream_t s) {
     for (int k = 0; k < m_max; ++k) {
         if (k > 0 && all_cycles_done(t, b, expected)) break;
-        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, s);
+        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

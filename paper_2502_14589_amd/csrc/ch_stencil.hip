@@ -1,4 +1,4 @@
-// Fused stencil kernels: Jacobian matvec with the first Gram-Schmidt dot,
+// Fused stencil kernels: Jacobian matvec with its Gram-Schmidt dot products,
 // residual / right-hand side, LIM stage and the two error-estimate passes.
 //
 // Operators (Section 2, eq. IVP; Section 3.1, eqs. J, A_g; Section 3.3,
@@ -20,6 +20,10 @@ __device__ __forceinline__ double cheb_node(int i, int p) {
     return cos(3.141592653589793 * double(2 * i - 1) / double(2 * p));
 }
 
+template <typename T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
+
 template <typename T>
 __device__ __forceinline__ T dcoef(T y, int eyre) {
     return T(3) * y * y - T(1) + T(eyre);
@@ -30,9 +34,11 @@ __device__ __forceinline__ T ccoef(T y, int eyre) {
 }
 
 // ---------------------------------------------------------------------------
-// w = Ahat (vscale[k] V_k) and the partials of <w, V_0> (Fig. 3, lines 4-6, i = 1)
+// w = Ahat (vscale[k] V_k) (the matvec of Fig. 3) with the partials of its dot
+// products: <w, V_0> only (the first MGS dot product), or <w, V_i> for every
+// i = 0..k (ALLDOTS: the first projection of CGS2) into rows i of pout.
 // ---------------------------------------------------------------------------
-template <int DIM, typename TV, typename TY, bool SINGLE>
+template <int DIM, typename TV, typename TY, bool SINGLE, bool ALLDOTS>
 __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                      const int* __restrict__ sb2i, const Inst inst0, int ninst, TV* __restrict__ V, size_t ldv,
                                                      int k, const TY* __restrict__ ybase,
@@ -42,9 +48,16 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
     if (ctl->done | ctl->halted) return;
     using R1 = Region<DIM, 1>;
     using R2 = Region<DIM, 2>;
+    constexpr int PPT = tile_points<DIM>() / CH_BLOCK;   // output points per thread and tile
+    static_assert(PPT * CH_BLOCK == tile_points<DIM>(), "tile size");
+    constexpr int NW = CH_BLOCK / 64;
+    constexpr int RB = 8;   // basis columns whose loads are issued together (one wave_sum8)
     __shared__ TV sv[R2::SIZE];
     __shared__ TV sd[R1::SIZE];
     __shared__ TV sq[R1::SIZE];
+    __shared__ double red[ALLDOTS ? CH_MMAX + 1 : 1][NW];
+    __shared__ TV sw[ALLDOTS ? tile_points<DIM>() : 1];
+    using P2 = typename Pair<TV>::type;
     const TV* Vk = V + (size_t)k * ldv + I.off;
     TV* W = V + (size_t)(k + 1) * ldv + I.off;
     const TV* V0 = V + I.off;
@@ -52,6 +65,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
     const int n = I.n, eyre = I.eyre;
     const TV sc = TV(ctl->vscale[k]);
     const TV ih2 = TV(I.inv_h2), e2ih2 = TV(I.eps2 * I.inv_h2);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (ALLDOTS)
+        for (int i = threadIdx.x; i < (k + 1) * NW; i += CH_BLOCK) red[i / NW][i % NW] = 0.0;
     int ntx, nty;
     const int nt = num_tiles<DIM>(n, ntx, nty);
     const int lb = blockIdx.x - I.sblk0;
@@ -64,25 +80,85 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
         for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK)
             sq[i] = sd[i] * sv[r1_to_r2<DIM>(i)] + e2ih2 * lap2_at_r1<DIM>(sv, i);
         __syncthreads();
-        for (int i = threadIdx.x; i < tile_points<DIM>(); i += CH_BLOCK) {
+        TV wv[PPT];
+        size_t gv[PPT];
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
             int i1;
             size_t gi;
-            if (out_point<DIM>(i, o, n, i1, gi)) {
+            wv[m] = TV(0);
+            gv[m] = 0;
+            if (out_point<DIM>(threadIdx.x + m * CH_BLOCK, o, n, i1, gi)) {
                 const TV w = ih2 * lap1_at<DIM>(sq, i1);
                 W[gi] = w;
-                dot += double(w) * double(V0[gi]);
+                wv[m] = w;
+                gv[m] = gi;
             }
+        }
+        if (ALLDOTS) {
+            // Through LDS, each thread takes the tile-linear points 2t, 2t + 1
+            // (x-neighbours), so a column is read with one 2-wide load per
+            // thread where both are in the grid and the pair is aligned.
+            // Points outside the grid carry w = 0.
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) sw[threadIdx.x + m * CH_BLOCK] = wv[m];
+            __syncthreads();
+            const int p0 = 2 * threadIdx.x;
+            const int cx = p0 % Geo<DIM>::TX, rr = p0 / Geo<DIM>::TX;
+            const int gx = o.x0 + cx, gy = o.y0 + rr % Geo<DIM>::TY, gz = o.z0 + rr / Geo<DIM>::TY;
+            const bool rowin = gy < n && (DIM == 2 || gz < n);
+            const bool in0 = rowin && gx < n, in1 = rowin && gx + 1 < n;
+            const size_t g0 = in0 ? ((size_t)gz * n + gy) * n + gx : 0;
+            const bool pair = in1 && (g0 & 1) == 0;
+            const double w0 = double(sw[p0]), w1 = double(sw[p0 + 1]);
+            for (int i0 = 0; i0 <= k; i0 += RB) {
+                TV v0[RB], v1[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const TV* col = V + (size_t)(i0 + r) * ldv + I.off;
+                    v0[r] = TV(0);
+                    v1[r] = TV(0);
+                    if (i0 + r <= k) {
+                        if (pair) {
+                            const P2 q = *reinterpret_cast<const P2*>(col + g0);
+                            v0[r] = q.x;
+                            v1[r] = q.y;
+                        } else {
+                            if (in0) v0[r] = col[g0];
+                            if (in1) v1[r] = col[g0 + 1];
+                        }
+                    }
+                }
+                double a[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) a[r] = w0 * double(v0[r]) + w1 * double(v1[r]);
+                const double tot = wave_sum8(a);
+                const int r = (lane >> 3) & 7;
+                if ((lane & 7) == 0 && i0 + r <= k) red[i0 + r][wid] += tot;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) dot += double(wv[m]) * double(V0[gv[m]]);
         }
         __syncthreads();
     }
-    double x[1] = {dot};
-    write_partials<1, RED_SUM>(x, pout);
+    if (ALLDOTS) {
+        for (int i = threadIdx.x; i <= k; i += CH_BLOCK) {
+            double a = red[i][0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) a += red[i][w];
+            pout[(size_t)i * CH_MAXB + blockIdx.x] = a;
+        }
+    } else {
+        double x[1] = {dot};
+        write_partials<1, RED_SUM>(x, pout);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Residual of the frozen linear problem at state z:
 //     r = ghat - Ahat z = A (c(y) - d(y) z - eps^2 A z)
-// With z = y this is f(y) (eq. IVP), the EE2 start vector (Fig. 3, line 2).
+// With z = y this is f(y) (eq. IVP), the EE2 start vector of Fig. 3.
 // Writes r to V_0 (and FP64 to fcur when write_f), optionally the FP32 copy
 // of y; partials of ||r||^2 and ||A c(y)||^2 = ||ghat||^2 (eq. tol_phi).
 // ---------------------------------------------------------------------------
@@ -142,7 +218,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctls, cons
 }
 
 // ---------------------------------------------------------------------------
-// EE2 estimate and next start vector (Fig. 4, line 8; eq. LIMest):
+// EE2 estimate and next start vector (Fig. 4; eq. LIMest):
 //   f1 = f(y^{n+1});  y_PC = y^n + tau/2 (f(y^n) + f1)  (eq. LIMest, since
 //   f(y) = -A (F'(y) + eps^2 A y));  est = ||y^{n+1} - y_PC|| / ||y_PC||.
 // f1 becomes the next step's f(y^n) and start vector; ||A c(y^{n+1})|| the next
@@ -209,7 +285,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_ee(Ctl* __restrict__ ctls, con
 }
 
 // ---------------------------------------------------------------------------
-// LIM stage (Fig. 1, steps 6 and 10):
+// LIM stage (one iteration of Fig. 1):
 //   y_next = (y^n + tau a_m z + tau (ghat - Ahat z)) / (1 + tau a_m)
 // ---------------------------------------------------------------------------
 template <int DIM, bool SINGLE>
@@ -231,7 +307,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, 
     const int n = I.n, eyre = I.eyre;
     const double inv_h2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
     const double tau = ctl->tau0;
-    // Fig. 1, steps 2-5: beta_i = cos(pi (2i - 1) / (2p)), z_1 = beta_1,
+    // Fig. 1: beta_i = cos(pi (2i - 1) / (2p)), z_1 = beta_1,
     // a_m = lambda_max (z_1 - beta_m) / (1 + z_1)
     const int p = ctl->p;
     const double z1 = cheb_node(1, p);
@@ -266,7 +342,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, 
 }
 
 // ---------------------------------------------------------------------------
-// LIM estimate (Fig. 2, line 8; eq. LIMest):
+// LIM estimate (Fig. 2; eq. LIMest):
 //   y_PC = y^n - tau/2 A (F'(y^n) + F'(y^{n+1}) + eps^2 A (y^n + y^{n+1}));
 // partials of ||y^{n+1} - y_PC||^2 and ||y_PC||^2 go to the controller.
 // ---------------------------------------------------------------------------
@@ -327,30 +403,37 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctls, co
 // ---------------------------------------------------------------------------
 #define SARGS dim3(t.sgrid), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.sb2i, t.hinst[0], t.ninst
 
+template <int DIM, typename TV, typename TY, bool ALLDOTS>
+static void launch_matvec_k(const Table& t, const DevBuffers& b, const TY* y, int k, double* pout, hipStream_t s) {
+    TV* V = static_cast<TV*>(b.V);
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, true, ALLDOTS>), SARGS, V, b.ldv, k, y, pout);
+    else
+        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, false, ALLDOTS>), SARGS, V, b.ldv, k, y, pout);
+}
+
+// FP64 basis: FP64 state; FP32 basis: the FP32 copy of the state.
 template <int DIM, typename TV>
 static hipError_t launch_matvec_t(const Table& t, const DevBuffers& b, PartSeq& ps, const void* y, int k,
-                                  hipStream_t s) {
-    TV* V = static_cast<TV*>(b.V);
-    if (sizeof(TV) == sizeof(double))
-        if (t.ninst == 1)
-            hipLaunchKernelGGL((k_matvec<DIM, TV, double, true>), SARGS, V, b.ldv, k, static_cast<const double*>(y), ps.out());
-        else
-            hipLaunchKernelGGL((k_matvec<DIM, TV, double, false>), SARGS, V, b.ldv, k, static_cast<const double*>(y), ps.out());
-    else
-        if (t.ninst == 1)
-            hipLaunchKernelGGL((k_matvec<DIM, TV, float, true>), SARGS, V, b.ldv, k, static_cast<const float*>(y), ps.out());
-        else
-            hipLaunchKernelGGL((k_matvec<DIM, TV, float, false>), SARGS, V, b.ldv, k, static_cast<const float*>(y), ps.out());
-    ps.produced(true);
+                                  bool alldots, hipStream_t s) {
+    using TY = TV;
+    const TY* yy = static_cast<const TY*>(y);
+    if (alldots) {
+        launch_matvec_k<DIM, TV, TY, true>(t, b, yy, k, b.dots, s);
+    } else {
+        launch_matvec_k<DIM, TV, TY, false>(t, b, yy, k, ps.out(), s);
+        ps.produced(true);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                         hipStream_t s) {
+                         bool alldots, hipStream_t s) {
     if (prec == CH_FP64)
-        return t.dim == 2 ? launch_matvec_t<2, double>(t, b, ps, y, k, s) : launch_matvec_t<3, double>(t, b, ps, y, k, s);
-    return t.dim == 2 ? launch_matvec_t<2, float>(t, b, ps, b.y32, k, s)
-                      : launch_matvec_t<3, float>(t, b, ps, b.y32, k, s);
+        return t.dim == 2 ? launch_matvec_t<2, double>(t, b, ps, y, k, alldots, s)
+                          : launch_matvec_t<3, double>(t, b, ps, y, k, alldots, s);
+    return t.dim == 2 ? launch_matvec_t<2, float>(t, b, ps, b.y32, k, alldots, s)
+                      : launch_matvec_t<3, float>(t, b, ps, b.y32, k, alldots, s);
 }
 
 template <int DIM, typename TV>
