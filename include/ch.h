@@ -77,16 +77,21 @@ typedef struct {
 
 /*
  * Orthogonalisation of the Arnoldi process (Fig. 3 of Section 4.1).  Both give
- * the same basis and Hessenberg matrix in exact arithmetic and orthogonality
- * to working precision; they differ in rounding and in cost.
- *   CH_ORTH_CGS2: classical Gram-Schmidt applied twice (Giraud, Langou,
- *     Rozloznik, Comput. Math. Appl. 50 (2005) 1069-1075): per iteration the
- *     matvec with the first projection's dot products, a second projection,
- *     and the update with the new norm -- three streaming passes whatever j.
+ * the same basis and Hessenberg matrix in exact arithmetic; they differ in
+ * rounding and in cost.
+ *   CH_ORTH_DCGS2 (default): classical Gram-Schmidt applied twice -- twice is
+ *     enough for orthogonality to working precision (Giraud, Langou,
+ *     Rozloznik, Comput. Math. Appl. 50 (2005)) -- with the second projection
+ *     of each vector delayed into the next iteration (the low-synchronisation
+ *     Gram-Schmidt idea of Swirydowicz et al., Numer. Linear Algebra Appl.,
+ *     2021): one reduction and two streaming passes over the basis per
+ *     iteration, whatever j.  The test of dimension j waits for the matvec of
+ *     the (j+1)-th vector, so each Krylov cycle makes one matvec more than it
+ *     reports (the paper's count).
  *   CH_ORTH_MGS: modified Gram-Schmidt as printed in Fig. 3, one streaming
  *     pass per basis vector (j + 1 passes in iteration j).
  */
-enum ch_orth { CH_ORTH_CGS2 = 0, CH_ORTH_MGS = 1 };
+enum ch_orth { CH_ORTH_DCGS2 = 0, CH_ORTH_MGS = 1 };
 
 typedef struct {
     int m_max;              /* Krylov dimension, 1..CH_MMAX */
@@ -94,7 +99,7 @@ typedef struct {
     double tol_phi_fixed;   /* > 0: use this tol_phi instead of eq. tol_phi */
     double tau_min;         /* trace underflow threshold (>= 0) */
     int constant_step;      /* 1: constant tau with linear RT restarts (no controller) */
-    int orth;               /* ch_orth (0, the zero-initialised default: CH_ORTH_CGS2) */
+    int orth;               /* ch_orth (0, the zero-initialised default: CH_ORTH_DCGS2) */
 } ch_ee_opts;
 
 /* Per-step record (one per accepted step). */
@@ -188,7 +193,7 @@ enum ch_phi_mode {
  * y_out = y + tau phi(-tau Ahat_n)(ghat^n - Ahat_n y) (eq. yt) with Ahat_n, ghat^n frozen
  * at y (eq. A_g / A_g_cs); y is not modified; y_out may not alias y.
  * out->tau is the step actually covered (< tau0 only in CH_PHI_SHRINK mode).
- * The Arnoldi process uses CH_ORTH_CGS2.
+ * The Arnoldi process uses CH_ORTH_DCGS2.
  */
 int ch_phiv(ch_ctx *ctx, const ch_problem *prob, const double *y, double *y_out, double tau0,
             int mode, double tol_phi, int m_max, ch_step_record *out);
@@ -241,10 +246,9 @@ enum ch_kernel {
     CH_KERNEL_MGS = 0,      /* one modified Gram-Schmidt pass (axpy + next dot) over the grid */
     CH_KERNEL_MATVEC = 1,   /* one fused Jacobian matvec Ahat v with its first dot */
     CH_KERNEL_PHI = 2,      /* one small-matrix phi evaluation of the last step's H (no trace) */
-    /* the three CH_ORTH_CGS2 passes of Arnoldi iteration m_max - 1 (j = m_max basis vectors): */
-    CH_KERNEL_CGS_MATVEC = 3,   /* matvec Ahat v_j with the j dot products of the first projection */
-    CH_KERNEL_CGS_PROJECT = 4,  /* first projection applied on the fly, j dot products of the second */
-    CH_KERNEL_CGS_UPDATE = 5    /* both projections applied and stored, partials of the new norm */
+    /* the two CH_ORTH_DCGS2 passes of Arnoldi iteration j = m_max - 1: */
+    CH_KERNEL_DC_MATVEC = 3,   /* matvec Ahat u_j with the 2j + 2 dot products against the basis */
+    CH_KERNEL_DC_UPDATE = 4    /* q_j and u_{j+1} from one pass over the basis */
 };
 
 /*

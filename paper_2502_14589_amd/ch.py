@@ -28,8 +28,8 @@ EXPORTED = (
 )
 CH_REQ_QUEUED, CH_REQ_RUNNING, CH_REQ_DONE, CH_REQ_FAILED = 0, 1, 2, 3
 CH_KERNEL_MGS, CH_KERNEL_MATVEC, CH_KERNEL_PHI = 0, 1, 2
-CH_KERNEL_CGS_MATVEC, CH_KERNEL_CGS_PROJECT, CH_KERNEL_CGS_UPDATE = 3, 4, 5
-CH_ORTH_CGS2, CH_ORTH_MGS = 0, 1
+CH_KERNEL_DC_MATVEC, CH_KERNEL_DC_UPDATE = 3, 4
+CH_ORTH_DCGS2, CH_ORTH_MGS = 0, 1
 
 
 class ChProblem(ctypes.Structure):
@@ -185,7 +185,7 @@ class Context:
     def run_ee(self, prob: Problem, y, tau0: float, *, t0: float = 0.0, T: float = math.inf, max_steps: int = 0,
                m_max: int = 30, tol: float = 1e-4, tol_phi_fixed: float = 0.0, tau_min: float = 0.0,
                constant_step: bool = False, records: bool = False, raise_on_error: bool = True,
-               orth: int = CH_ORTH_CGS2):
+               orth: int = CH_ORTH_DCGS2):
         """Adaptive (Fig. 4) or constant-step EE2 run on y in place; returns (stats, records)."""
         _check_field(y, prob.N)
         opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), int(bool(constant_step)),
@@ -203,7 +203,7 @@ class Context:
 
     def step_ee(self, prob: Problem, y, tau: float, *, t: float = 0.0, T: float = math.inf, m_max: int = 30,
                 tol: float = 1e-4, tol_phi_fixed: float = 0.0, tau_min: float = 0.0, constant_step: bool = False,
-                orth: int = CH_ORTH_CGS2):
+                orth: int = CH_ORTH_DCGS2):
         _check_field(y, prob.N)
         opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), int(bool(constant_step)),
                         int(orth))
@@ -217,7 +217,7 @@ class Context:
     def run_ee_batch(self, fields, ns, eps, *, dim: int = 2, eyre: bool = False, precision: int = CH_FP64,
                      tau0=1e-3, T=math.inf, max_steps=50, m_max: int = 30, tol: float = 1e-4,
                      tol_phi_fixed: float = 0.0, tau_min: float = 0.0, raise_on_error: bool = True,
-                     orth: int = CH_ORTH_CGS2):
+                     orth: int = CH_ORTH_DCGS2):
         """Adaptive EE2 on many instances at once (each field updated in place); returns per-instance stats."""
         count = len(fields)
         as_list = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * count
@@ -288,7 +288,7 @@ class Server:
 
     def __init__(self, device: int = 0, precision: int = CH_FP64, m_max: int = 30, tol: float = 1e-4,
                  tol_phi_fixed: float = 0.0, hbm_budget: int = 8 << 30, max_slots: int = 64,
-                 orth: int = CH_ORTH_CGS2):
+                 orth: int = CH_ORTH_DCGS2):
         self.lib = load_library()
         opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), 0.0, 0, int(orth))
         self._ptr = c_void_p()

@@ -97,7 +97,7 @@ int check_grid(int dim, int n, double eps, int eyre, Shape* sh) {
     return CH_OK;
 }
 
-bool orth_ok(int orth) { return orth == CH_ORTH_CGS2 || orth == CH_ORTH_MGS; }
+bool orth_ok(int orth) { return orth == CH_ORTH_DCGS2 || orth == CH_ORTH_MGS; }
 
 int check_problem(const ch_problem* p, Shape* sh) {
     if (!p) return CH_EINVAL;
@@ -114,7 +114,7 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         if ((rc = alloc_dev(ctx, (void**)&b.part, 2 * sizeof(double) * CH_NRED * CH_MAXB))) return rc;
     }
     if (!b.dots) {
-        if ((rc = alloc_dev(ctx, (void**)&b.dots, sizeof(double) * (CH_MMAX + 1) * CH_MAXB))) return rc;
+        if ((rc = alloc_dev(ctx, (void**)&b.dots, sizeof(double) * CH_DROWS * CH_MAXB))) return rc;
     }
     if (nslots > ctx->slots) {
         free_dev(b.ctl);
@@ -869,9 +869,9 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     HIP_TRY(ctx, launch_resid(t, prec, b, ps, b.ybuf[0], b.ybuf[0], false, true, ctx->stream));
     HIP_TRY(ctx, launch_after_resid(t, b, ps, true, ctx->stream));
     ctx->expect[0] += 1;
-    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, CH_ORTH_CGS2, ctx->expect.data(), ctx->stream));
+    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, CH_ORTH_DCGS2, ctx->expect.data(), ctx->stream));
     HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[0], b.ybuf[1], ctx->stream));
-    if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[0], b.ybuf[1], m_max, CH_ORTH_CGS2)))
+    if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[0], b.ybuf[1], m_max, CH_ORTH_DCGS2)))
         return rc;
     if ((rc = read_heads(ctx, 1))) return rc;
     const Ctl& h = ctx->hctl[0];
@@ -890,7 +890,7 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     int rc = check_problem(prob, &sh);
     if (rc) return rc;
     if (m_max < 2 || m_max > CH_MMAX) return CH_EINVAL;
-    if (kernel < CH_KERNEL_MGS || kernel > CH_KERNEL_CGS_UPDATE) return CH_EINVAL;
+    if (kernel < CH_KERNEL_MGS || kernel > CH_KERNEL_DC_UPDATE) return CH_EINVAL;
     const int prec = prob->prec;
     const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
     const DevBuffers& b = ctx->b;
@@ -913,7 +913,10 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     // every operand but leave the data as it was
     const int kc = m_max - 1;
     for (int i = 0; i <= m_max; ++i) h.vscale[i] = 1.0;
-    for (int i = 0; i <= kc; ++i) h.h1[i] = h.H[i + kc * CH_LDH] = 0.0;
+    for (int i = 0; i <= kc; ++i) h.ca[i] = h.cb[i] = 0.0;
+    h.ca[kc] = 1.0;
+    h.cbw = 1.0;
+    h.cq = 0.0;
     h.tol_phi = 1.0;
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(b.part, 0, 2 * sizeof(double) * CH_NRED * CH_MAXB, ctx->stream));
@@ -923,11 +926,10 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
         ps.base = b.part;
         switch (kernel) {
             case CH_KERNEL_MGS: return launch_mgs_pass(t, prec, b, ps, 1, 1, ctx->stream);
-            case CH_KERNEL_MATVEC: return launch_matvec(t, prec, b, ps, y, 0, false, ctx->stream);
-            case CH_KERNEL_PHI: return launch_phi(t, b, ps, jlast - 1, ctx->stream);
-            case CH_KERNEL_CGS_MATVEC: return launch_matvec(t, prec, b, ps, y, kc, true, ctx->stream);
-            case CH_KERNEL_CGS_PROJECT: return launch_cgs_project(t, prec, b, kc, ctx->stream);
-            default: return launch_cgs_update(t, prec, b, ps, kc, ctx->stream);
+            case CH_KERNEL_MATVEC: return launch_matvec(t, prec, b, ps, y, 0, MV_DOTS_ONE, true, ctx->stream);
+            case CH_KERNEL_PHI: return launch_phi(t, b, ps, jlast - 1, false, ctx->stream);
+            case CH_KERNEL_DC_MATVEC: return launch_matvec(t, prec, b, ps, y, kc, MV_DOTS_DC, true, ctx->stream);
+            default: return launch_dc_update(t, prec, b, kc, ctx->stream);
         }
     };
     hipEvent_t e0, e1;
@@ -949,13 +951,12 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     *avg_us = 1000.0 * ms / reps;
     const double N = double(sh.N);
     const double ysz = prec == CH_FP64 ? 8.0 : 4.0;
-    const double j = double(m_max);   // basis columns of the timed CGS2 iteration
+    const double j = double(kc);   // basis vectors q_0..q_{j-1} of the timed DCGS2 iteration
     switch (kernel) {
-        case CH_KERNEL_MGS: *bytes = 4.0 * esz * N; break;                      // read w, v_{i-1}, v_i; write w
-        case CH_KERNEL_MATVEC: *bytes = (3.0 * esz + ysz) * N; break;           // read v_k, y, v_1; write w
-        case CH_KERNEL_CGS_MATVEC: *bytes = ((j + 1.0) * esz + ysz) * N; break; // read y, v_0..v_k; write w
-        case CH_KERNEL_CGS_PROJECT: *bytes = (j + 1.0) * esz * N; break;        // read w, v_0..v_k
-        case CH_KERNEL_CGS_UPDATE: *bytes = (j + 2.0) * esz * N; break;         // read w, v_0..v_k; write w
+        case CH_KERNEL_MGS: *bytes = 4.0 * esz * N; break;                     // read w, v_{i-1}, v_i; write w
+        case CH_KERNEL_MATVEC: *bytes = (3.0 * esz + ysz) * N; break;          // read v_k, y, v_1; write w
+        case CH_KERNEL_DC_MATVEC: *bytes = ((j + 2.0) * esz + ysz) * N; break; // read y, u, q_0..q_{j-1}; write w
+        case CH_KERNEL_DC_UPDATE: *bytes = (j + 4.0) * esz * N; break;         // read q_0..q_{j-1}, u, w; write q_j, u
         default: *bytes = 0.0;
     }
     return CH_OK;

@@ -10,46 +10,80 @@
 // by the consuming launch (below), so results do not depend on scheduling.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+// Lane exchanges.  Within a row of 16 lanes the data-parallel-primitive
+// (DPP) forms move data in the vector ALU; across rows a permute through the
+// LDS crossbar is needed.  Pairings used (each an involution):
+//   DPP_XOR1  quad_perm [1,0,3,2]     lane ^ 1
+//   DPP_XOR2  quad_perm [2,3,0,1]     lane ^ 2
+//   DPP_HMIR  row_half_mirror         lane <-> 7 - lane within 8 lanes
+//   DPP_MIR   row_mirror              lane <-> 15 - lane within 16 lanes
+enum DppCtrl { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HMIR = 0x141, DPP_MIR = 0x140 };
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Butterfly over the 64 lanes: DPP within rows, two permutes across them.
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double x, Op op) {
+    x = op(x, dpp_move<DPP_XOR1>(x));
+    x = op(x, dpp_move<DPP_XOR2>(x));
+    x = op(x, dpp_move<DPP_HMIR>(x));
+    x = op(x, dpp_move<DPP_MIR>(x));
+    x = op(x, __shfl_xor(x, 16, 64));
+    x = op(x, __shfl_xor(x, 32, 64));
     return x;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+    return wave_reduce(x, [](double a, double b) { return a + b; });
 }
 
 __device__ __forceinline__ double wave_max(double x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-    return x;
+    return wave_reduce(x, [](double a, double b) { return fmax(a, b); });
 }
 
 __device__ __forceinline__ double wave_min(double x) {
+    return wave_reduce(x, [](double a, double b) { return fmin(a, b); });
+}
+
+// Eight wave-wide sums at once.  In each of three exchanges (row mirror, half
+// mirror, lane ^ 2) a lane keeps half of its values, sends the other half to
+// its partner and adds the partner's copy of the half it kept; then plain
+// butterfly steps over the lanes that hold the same value (lane ^ 1, ^ 16,
+// ^ 32).  Seven DPP moves and two cross-row permutes per double instead of
+// the 48 permutes of eight wave_sum calls.  Lane L ends with the total of
+// value ((L >> 3) & 1) * 4 + ((L >> 2) & 1) * 2 + ((L >> 1) & 1); lanes 2v
+// (v = 0..7) hold value v (see wave_sum8_holder).
+template <int CTRL>
+__device__ __forceinline__ void keep_half(double* a, int h, bool hi) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x = fmin(x, __shfl_xor(x, off, 64));
+    for (int i = 0; i < h; ++i) {
+        const double send = hi ? a[i] : a[i + h];
+        const double keep = hi ? a[i + h] : a[i];
+        a[i] = keep + dpp_move<CTRL>(send);
+    }
+}
+
+__device__ __forceinline__ double wave_sum8(double (&a)[8]) {
+    const int lane = threadIdx.x & 63;
+    keep_half<DPP_MIR>(a, 4, (lane & 8) != 0);
+    keep_half<DPP_HMIR>(a, 2, (lane & 4) != 0);
+    keep_half<DPP_XOR2>(a, 1, (lane & 2) != 0);
+    double x = a[0];
+    x += dpp_move<DPP_XOR1>(x);
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
     return x;
 }
 
-// Eight wave-wide sums at once.  In each of the first three exchanges
-// (lane masks 32, 16, 8) a lane keeps half of its values, sends the other half
-// to its partner and adds the partner's copy of the half it kept; three plain
-// butterfly steps finish.  Ten exchanges instead of the 48 of eight
-// wave_sum calls.  Returns, in every lane L, the total of value (L >> 3) & 7.
-__device__ __forceinline__ double wave_sum8(double (&a)[8]) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int h = 4, m = 32; h > 0; h >>= 1, m >>= 1) {
-        const bool hi = (lane & m) != 0;
-#pragma unroll
-        for (int i = 0; i < h; ++i) {
-            const double send = hi ? a[i] : a[i + h];
-            const double keep = hi ? a[i + h] : a[i];
-            a[i] = keep + __shfl_xor(send, m, 64);
-        }
-    }
-    double x = a[0];
-#pragma unroll
-    for (int m = 4; m > 0; m >>= 1) x += __shfl_xor(x, m, 64);
-    return x;
-}
+// Index of the value whose total lane `lane` is to store after wave_sum8,
+// or -1 (each value is stored by one lane).
+__device__ __forceinline__ int wave_sum8_holder(int lane) { return (lane & 0x31) == 0 ? (lane >> 1) & 7 : -1; }
 
 enum RedOp { RED_SUM = 0, RED_MIN = 1, RED_MAX = 2 };
 

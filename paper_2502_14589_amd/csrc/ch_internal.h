@@ -13,6 +13,10 @@
 #define CH_CBLK_MAX 512          // most streaming workgroups per instance
 #define CH_NRED 4                // most sums reduced by one launch
 #define CH_BLOCK 256             // threads per workgroup of the streaming and stencil kernels
+#define CH_DROWS (2 * CH_MMAX + 2)   // dot-product rows of one DCGS2 iteration
+
+// Dot products a matvec launch produces (see k_matvec).
+enum MatvecDots { MV_DOTS_ONE = 0, MV_DOTS_DC = 1 };
 
 enum CtlMode { MODE_EE = 0, MODE_EE_CONST = 1, MODE_LIM = 2, MODE_LIM_CONST = 3, MODE_PHI = 4 };
 
@@ -45,7 +49,12 @@ struct Ctl {
     // Arnoldi
     double H[CH_LDH * CH_MMAX];   // h_{i+1,k+1} at H[i + k*CH_LDH]
     double vscale[CH_MMAX + 1];   // v_i = vscale[i] * V(:, i)
-    double h1[CH_MMAX + 1];       // CGS2: first-projection coefficients of the current iteration
+    double h1[CH_MMAX + 1];       // DCGS2: first-projection coefficients of the current column
+    // DCGS2: dot-product totals of the current iteration, and the coefficients
+    // of its update pass (q_j = sum_i ca[i] V_i; u_{j+1} = cbw w + sum_{i<j} cb[i] V_i + cq q_j)
+    double dt[CH_DROWS];
+    double ca[CH_MMAX + 1], cb[CH_MMAX + 1];
+    double cbw, cq;
     double u[CH_MMAX];            // tau phi(-tau H) e_1
 };
 
@@ -72,7 +81,7 @@ struct DevBuffers {
     float* y32;         // FP32 copy of y^n (mixed precision only)
     double* zbuf;       // FP64 scratch (LIM stages)
     double* part;       // reduction partials: two slots of CH_NRED * CH_MAXB
-    double* dots;       // CGS2 dot-product partials: (CH_MMAX + 1) rows of CH_MAXB
+    double* dots;       // DCGS2 dot-product partials: CH_DROWS rows of CH_MAXB
     Ctl* ctl;           // control blocks, one per slot
     int* dflag;         // device view of `hflag`, one word per slot
     const volatile int* hflag;   // pinned host words: `cyc` of the last finished Krylov cycle per slot
@@ -110,20 +119,21 @@ hipError_t launch_resid(const Table& t, int prec, const DevBuffers& b, PartSeq& 
                         bool write_f, bool write_y32, hipStream_t s);
 hipError_t launch_after_resid(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_step, hipStream_t s);
 hipError_t launch_cycle_begin(const Table& t, const DevBuffers& b, hipStream_t s);
-// alldots: the dot products of w with every basis column 0..k go to b.dots
-// (CGS2); otherwise the one with column 0 to the next partials slot (MGS).
+// dots (MatvecDots): MV_DOTS_ONE to the next partials slot, MV_DOTS_DC to
+// b.dots.  store_w: write w to column k + 1.
 hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                         bool alldots, hipStream_t s);
-// CGS2 passes of Arnoldi iteration k (see ch_krylov.hip).
-hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, int stage, hipStream_t s);
-hipError_t launch_cgs_project(const Table& t, int prec, const DevBuffers& b, int k, hipStream_t s);
-hipError_t launch_cgs_update(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, hipStream_t s);
+                         int dots, bool store_w, hipStream_t s);
+// DCGS2 passes of Arnoldi iteration k (see ch_krylov.hip).
+hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStream_t s);
+hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s);
 hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
-hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, hipStream_t s);
+// phi test of iteration k (MGS: dimension k + 1, from the norm
+// partials; dc: DCGS2 iteration k -- dimension k, then the update coefficients).
+hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, bool dc, hipStream_t s);
 // Arnoldi iteration k: matvec, Gram-Schmidt passes (orth: ch_orth), phi and
 // residual test.
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               int orth, hipStream_t s);
+                               int orth, int m_max, hipStream_t s);
 // True when every instance has reported the current cycle finished:
 // expected[slot] is the number of cycles the host has issued for that slot.
 bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected);

@@ -1,4 +1,4 @@
-// Arnoldi (classical Gram-Schmidt twice, or modified Gram-Schmidt), the
+// Arnoldi (delayed classical Gram-Schmidt twice, or modified Gram-Schmidt), the
 // small-matrix phi with the residual-time restart, the solution update and
 // the per-step controllers.
 //
@@ -82,246 +82,145 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctls, const 
 }
 
 // ---------------------------------------------------------------------------
-// CGS2 (classical Gram-Schmidt twice) for Arnoldi iteration k.  With
-// v_i = s_i V_i (s = vscale) and w = Ahat v_k in column k + 1:
-//   the matvec launch:   partials of d_i = <w, V_i>, i = 0..k
-//   k_dots_reduce(1):    h1_i = s_i d_i                   (first projection)
-//   k_cgs_project:       w' = w - sum_i s_i h1_i V_i on the fly (not stored),
-//                        partials of e_i = <w', V_i>
-//   k_dots_reduce(2):    h_{i,k} = h1_i + s_i e_i         (second projection)
-//   k_cgs_update:        w'' = w - sum_i s_i h_{i,k} V_i, stored, partials of ||w''||^2
-// and the phi launch takes h_{k+1,k} = ||w''||.  In exact arithmetic these are
-// the h_{ik} and w of the MGS loop of Fig. 3; the reorthogonalisation keeps the
-// basis orthogonal to working precision.  Projections are applied in FP64
-// whatever the storage precision of the basis.
+// DCGS2 for Arnoldi iteration j.  Column j holds u_j, the (j+1)-th vector
+// after one classical projection on q_0..q_{j-1} (columns 0..j-1, q_i =
+// vscale[i] V_i), not yet reorthogonalised nor normalised.
+//   the matvec launch:    w = Ahat u_j into column j + 1; partials of
+//                         sigma_i = <V_i, u_j>, tau_i = <V_i, w> (i < j),
+//                         alpha = <u_j, u_j>, beta' = <u_j, w>
+//   k_dots_reduce:        their totals
+//   the phi launch:       s = Q^T u_j, rho^2 = alpha - |s|^2 (Pythagoras: s is
+//                         the reorthogonalisation of a vector already
+//                         projected once, so no cancellation);
+//                         h_{:,j-1} += s, h_{j,j-1} = rho: column j - 1 of the
+//                         Hessenberg matrix is final, and dimension j is
+//                         tested.  Then, from the Arnoldi relation
+//                         A Q_{j-1} = Q_j H_j, A q_j = (w - Q_j H_j s) / rho, so
+//                         the first projection of A q_j on Q_j follows from the
+//                         same totals: with g = H_j s,
+//                         h'_i = (t_i - g_i) / rho  (i < j, t = Q^T w),
+//                         h'_j = ((beta' - s.t) / rho - g_j) / rho;
+//   k_dc_update:          q_j = (u_j - Q_{j-1} s) / rho into column j, and
+//                         u_{j+1} = A q_j - Q_j h' = w / rho - Q_j (g / rho + h')
+//                         into column j + 1, in one pass over the basis.
+// Iteration 0 has no columns to project on: rho = |u_0| (the start vector),
+// and only the coefficients are formed.
 // ---------------------------------------------------------------------------
+template <typename TV, bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                        const int* __restrict__ cb2i, const Inst inst0, int ninst,
+                                                        TV* __restrict__ V, size_t ldv, int j) {
+    const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->done | ctl->halted) return;
+    using VT = typename Vec16<TV>::type;
+    constexpr int VW = Vec16<TV>::W, Q = 2, RB = 4;
+    __shared__ double ca[CH_MMAX + 1], cb[CH_MMAX + 1];
+    for (int i = threadIdx.x; i <= j; i += CH_BLOCK) {
+        ca[i] = ctl->ca[i];
+        cb[i] = i < j ? ctl->cb[i] : 0.0;
+    }
+    __syncthreads();
+    const double cbw = ctl->cbw, cq = ctl->cq;
+    const TV* Vi = V + I.off;
+    TV* U = V + (size_t)j * ldv + I.off;
+    TV* Wc = V + (size_t)(j + 1) * ldv + I.off;
+    VT* U4 = reinterpret_cast<VT*>(U);
+    VT* W4 = reinterpret_cast<VT*>(Wc);
+    const long long NV = I.N / VW;
+    const long long per = (long long)I.cblk * CH_BLOCK;
+    const long long lt = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
+    for (long long q0 = lt; q0 < NV; q0 += per * Q) {
+        long long qq[Q];
+        bool ok[Q];
+        double xq[Q][VW], xu[Q][VW];
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            qq[u] = q0 + u * per;
+            ok[u] = qq[u] < NV;
+            VT uv, wv;
+            if (ok[u]) {
+                uv = U4[qq[u]];
+                wv = W4[qq[u]];
+            }
+            const TV* ue = reinterpret_cast<const TV*>(&uv);
+            const TV* we = reinterpret_cast<const TV*>(&wv);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                xq[u][e] = ok[u] ? ca[j] * double(ue[e]) : 0.0;
+                xu[u][e] = ok[u] ? cbw * double(we[e]) : 0.0;
+            }
+        }
+        for (int i0 = 0; i0 < j; i0 += RB) {
+            VT v[RB][Q];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int u = 0; u < Q; ++u) {
+                    const VT* col = reinterpret_cast<const VT*>(Vi + (size_t)(i0 + r) * ldv);
+                    if (ok[u] && i0 + r < j) v[r][u] = col[qq[u]];
+                    else {
+                        TV* ve = reinterpret_cast<TV*>(&v[r][u]);
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) ve[e] = TV(0);
+                    }
+                }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const double a = i0 + r < j ? ca[i0 + r] : 0.0;
+                const double c = i0 + r < j ? cb[i0 + r] : 0.0;
+#pragma unroll
+                for (int u = 0; u < Q; ++u) {
+                    const TV* ve = reinterpret_cast<const TV*>(&v[r][u]);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) {
+                        xq[u][e] += a * double(ve[e]);
+                        xu[u][e] += c * double(ve[e]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            if (!ok[u]) continue;
+            VT qv, nv;
+            TV* qe = reinterpret_cast<TV*>(&qv);
+            TV* ne = reinterpret_cast<TV*>(&nv);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                qe[e] = TV(xq[u][e]);
+                ne[e] = TV(xu[u][e] + cq * double(qe[e]));   // with q_j as stored
+            }
+            U4[qq[u]] = qv;
+            W4[qq[u]] = nv;
+        }
+    }
+    for (long long e = NV * VW + lt; e < I.N; e += per) {
+        double xq = ca[j] * double(U[e]), xu = cbw * double(Wc[e]);
+        for (int i = 0; i < j; ++i) {
+            const double v = double(Vi[(size_t)i * ldv + e]);
+            xq += ca[i] * v;
+            xu += cb[i] * v;
+        }
+        const TV qs = TV(xq);
+        U[e] = qs;
+        Wc[e] = TV(xu + cq * double(qs));
+    }
+}
 
-// One workgroup per (row i, instance): total of the partials of row i.
+// One workgroup per (row i, instance): the total of the partials of row i of
+// a DCGS2 matvec launch.
 template <bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_dots_reduce(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
-                                                          const Inst inst0, int ninst, int k,
-                                                          const double* __restrict__ dots, int stage) {
+                                                          const Inst inst0, int ninst,
+                                                          const double* __restrict__ dots) {
     const Inst I = SINGLE ? inst0 : insts[blockIdx.y];
     Ctl* ctl = ctls + I.slot;
     if (ctl->done | ctl->halted) return;
     const int r = blockIdx.x;
     double tot[1];
-    if (stage == 1)
-        sum_partials<1, RED_SUM>(dots + (size_t)r * CH_MAXB, I.sblk0, I.sblk, tot);
-    else
-        sum_partials<1, RED_SUM>(dots + (size_t)r * CH_MAXB, I.cblk0, I.cblk, tot);
-    if (threadIdx.x != 0) return;
-    const double h = ctl->vscale[r] * tot[0];
-    if (stage == 1) ctl->h1[r] = h;
-    else ctl->H[r + k * CH_LDH] = ctl->h1[r] + h;
-}
-
-// Accumulate <x, V_i> for i = 0..k over the items of a workgroup into
-// red[i][wave].  Every lane of the workgroup calls it (wave-wide sums); lanes
-// without items pass ok = false.
-template <typename TV, int Q>
-__device__ __forceinline__ void cgs_dots(const TV* __restrict__ Vi, size_t ldv, int k, const long long (&qq)[Q],
-                                         const bool (&ok)[Q], const double (&x)[Q][Vec16<TV>::W],
-                                         double (*red)[CH_BLOCK / 64]) {
-    using VT = typename Vec16<TV>::type;
-    constexpr int VW = Vec16<TV>::W, RB = 8;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    // last columns first: those read most recently by cgs_axpys are the
-    // likeliest still to be cached
-    for (int i0 = (k / RB) * RB; i0 >= 0; i0 -= RB) {
-        VT v[RB][Q];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int u = 0; u < Q; ++u) {
-                const VT* col = reinterpret_cast<const VT*>(Vi + (size_t)(i0 + r) * ldv);
-                if (ok[u] && i0 + r <= k) v[r][u] = col[qq[u]];
-                else {
-                    TV* ve = reinterpret_cast<TV*>(&v[r][u]);
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) ve[e] = TV(0);
-                }
-            }
-        double a[RB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            a[r] = 0.0;
-#pragma unroll
-            for (int u = 0; u < Q; ++u) {
-                const TV* ve = reinterpret_cast<const TV*>(&v[r][u]);
-#pragma unroll
-                for (int e = 0; e < VW; ++e) a[r] += x[u][e] * double(ve[e]);
-            }
-        }
-        const double tot = wave_sum8(a);
-        const int r = (lane >> 3) & 7;
-        if ((lane & 7) == 0 && i0 + r <= k) red[i0 + r][wid] += tot;
-    }
-}
-
-// x -= sum_i cf[i] V_i over the same items (RB columns' loads issued together).
-template <typename TV, int Q, int RB>
-__device__ __forceinline__ void cgs_axpys(const TV* __restrict__ Vi, size_t ldv, int k, const long long (&qq)[Q],
-                                          const bool (&ok)[Q], const double* cf, double (&x)[Q][Vec16<TV>::W]) {
-    using VT = typename Vec16<TV>::type;
-    constexpr int VW = Vec16<TV>::W;
-    for (int i0 = 0; i0 <= k; i0 += RB) {
-        VT v[RB][Q];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int u = 0; u < Q; ++u) {
-                const VT* col = reinterpret_cast<const VT*>(Vi + (size_t)(i0 + r) * ldv);
-                if (ok[u] && i0 + r <= k) v[r][u] = col[qq[u]];
-                else {
-                    TV* ve = reinterpret_cast<TV*>(&v[r][u]);
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) ve[e] = TV(0);
-                }
-            }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const double c = i0 + r <= k ? cf[i0 + r] : 0.0;
-#pragma unroll
-            for (int u = 0; u < Q; ++u) {
-                const TV* ve = reinterpret_cast<const TV*>(&v[r][u]);
-#pragma unroll
-                for (int e = 0; e < VW; ++e) x[u][e] -= c * double(ve[e]);
-            }
-        }
-    }
-}
-
-// Second projection's dot products.  Items: Q 16-byte vectors per thread and
-// chunk, in chunks common to all workgroups of the instance; the last few
-// points of an instance whose size is not a multiple of the vector width are
-// one scalar chunk of its first workgroup.
-template <typename TV, bool SINGLE>
-__global__ __launch_bounds__(CH_BLOCK) void k_cgs_project(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
-                                                          const int* __restrict__ cb2i, const Inst inst0, int ninst,
-                                                          const TV* __restrict__ V, size_t ldv, int k,
-                                                          double* __restrict__ pout) {
-    const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
-    Ctl* ctl = ctls + I.slot;
-    if (ctl->done | ctl->halted) return;
-    using VT = typename Vec16<TV>::type;
-    constexpr int VW = Vec16<TV>::W, Q = 1, NW = CH_BLOCK / 64;
-    __shared__ double cf[CH_MMAX + 1];
-    __shared__ double red[CH_MMAX + 1][NW];
-    for (int i = threadIdx.x; i <= k; i += CH_BLOCK) {
-        cf[i] = ctl->vscale[i] * ctl->h1[i];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) red[i][w] = 0.0;
-    }
-    __syncthreads();
-    const TV* Vi = V + I.off;
-    const TV* W = V + (size_t)(k + 1) * ldv + I.off;
-    const VT* W4 = reinterpret_cast<const VT*>(W);
-    const long long NV = I.N / VW;
-    const long long per = (long long)I.cblk * CH_BLOCK;
-    const long long lt = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
-    const long long nch = (NV + per * Q - 1) / (per * Q);
-    for (long long c = 0; c < nch; ++c) {
-        long long qq[Q];
-        bool ok[Q];
-        double x[Q][VW];
-#pragma unroll
-        for (int u = 0; u < Q; ++u) {
-            qq[u] = (c * Q + u) * per + lt;
-            ok[u] = qq[u] < NV;
-            VT w;
-            if (ok[u]) w = W4[qq[u]];
-            const TV* we = reinterpret_cast<const TV*>(&w);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) x[u][e] = ok[u] ? double(we[e]) : 0.0;
-        }
-        cgs_axpys<TV, Q, 8>(Vi, ldv, k, qq, ok, cf, x);
-        cgs_dots<TV, Q>(Vi, ldv, k, qq, ok, x, red);
-    }
-    if (NV * VW < I.N && blockIdx.x == I.cblk0) {   // scalar tail, fewer than VW points
-        const long long e = NV * VW + threadIdx.x;
-        const bool ok = e < I.N;
-        double x = 0.0;
-        if (ok) {
-            x = double(W[e]);
-            for (int i = 0; i <= k; ++i) x -= cf[i] * double(Vi[(size_t)i * ldv + e]);
-        }
-        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-        for (int i = 0; i <= k; ++i) {
-            double a = 0.0;
-            if (ok) a = x * double(Vi[(size_t)i * ldv + e]);
-            a = wave_sum(a);
-            if (lane == 0) red[i][wid] += a;
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= k; i += CH_BLOCK) {
-        double a = red[i][0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) a += red[i][w];
-        pout[(size_t)i * CH_MAXB + blockIdx.x] = a;
-    }
-}
-
-// w'' = w - sum_i s_i h_{i,k} V_i, stored in the basis precision; partials of
-// ||w''||^2 of the stored vector.
-template <typename TV, bool SINGLE>
-__global__ __launch_bounds__(CH_BLOCK) void k_cgs_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
-                                                         const int* __restrict__ cb2i, const Inst inst0, int ninst,
-                                                         TV* __restrict__ V, size_t ldv, int k,
-                                                         double* __restrict__ pout) {
-    const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
-    Ctl* ctl = ctls + I.slot;
-    if (ctl->done | ctl->halted) return;
-    using VT = typename Vec16<TV>::type;
-    constexpr int VW = Vec16<TV>::W, Q = 2;
-    __shared__ double cf[CH_MMAX + 1];
-    for (int i = threadIdx.x; i <= k; i += CH_BLOCK) cf[i] = ctl->vscale[i] * ctl->H[i + k * CH_LDH];
-    __syncthreads();
-    const TV* Vi = V + I.off;
-    TV* W = V + (size_t)(k + 1) * ldv + I.off;
-    VT* W4 = reinterpret_cast<VT*>(W);
-    const long long NV = I.N / VW;
-    const long long per = (long long)I.cblk * CH_BLOCK;
-    const long long lt = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
-    double acc = 0.0;
-    for (long long q0 = lt; q0 < NV; q0 += per * Q) {
-        long long qq[Q];
-        bool ok[Q];
-        double x[Q][VW];
-#pragma unroll
-        for (int u = 0; u < Q; ++u) {
-            qq[u] = q0 + u * per;
-            ok[u] = qq[u] < NV;
-            VT w;
-            if (ok[u]) w = W4[qq[u]];
-            const TV* we = reinterpret_cast<const TV*>(&w);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) x[u][e] = ok[u] ? double(we[e]) : 0.0;
-        }
-        cgs_axpys<TV, Q, 4>(Vi, ldv, k, qq, ok, cf, x);
-#pragma unroll
-        for (int u = 0; u < Q; ++u) {
-            if (!ok[u]) continue;
-            VT w;
-            TV* we = reinterpret_cast<TV*>(&w);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                we[e] = TV(x[u][e]);
-                acc += double(we[e]) * double(we[e]);
-            }
-            W4[qq[u]] = w;
-        }
-    }
-    for (long long e = NV * VW + lt; e < I.N; e += per) {
-        double x = double(W[e]);
-        for (int i = 0; i <= k; ++i) x -= cf[i] * double(Vi[(size_t)i * ldv + e]);
-        const TV xs = TV(x);
-        W[e] = xs;
-        acc += double(xs) * double(xs);
-    }
-    double x1[1] = {acc};
-    write_partials<1, RED_SUM>(x1, pout);
+    sum_partials<1, RED_SUM>(dots + (size_t)r * CH_MAXB, I.sblk0, I.sblk, tot);
+    if (threadIdx.x == 0) ctl->dt[r] = tot[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -381,6 +280,7 @@ struct PhiShared {
     double c[20];               // 1 / k!
     double lvl[NLVL];           // lvl[kk] = resnorm at s 2^-kk from the squaring chain
     double red;
+    double s[CH_MMAX + 1], t[CH_MMAX + 1], g[CH_MMAX + 1];   // DCGS2 combination
 };
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -502,8 +402,64 @@ __device__ void store_u(Ctl* ctl, const double* E, int j) {
 }
 
 // ---------------------------------------------------------------------------
-// phi of the Hessenberg matrix after Arnoldi iteration k, convergence test and
-// residual-time trace (Fig. 3; eqs. rm, phi_stop).  One workgroup.
+// DCGS2, iteration j (see k_dc_update): s, t from the totals, rho, and the
+// final column j - 1 of the Hessenberg matrix.  Returns rho = h_{j,j-1}.
+__device__ double dc_finalize(PhiShared& S, Ctl* ctl, int j) {
+    for (int i = threadIdx.x; i < j; i += CH_BLOCK) {
+        S.s[i] = ctl->vscale[i] * ctl->dt[i];
+        S.t[i] = ctl->vscale[i] * ctl->dt[j + i];
+    }
+    __syncthreads();
+    double ss = 0.0;
+    for (int i = 0; i < j; ++i) ss += S.s[i] * S.s[i];
+    const double rho2 = ctl->dt[2 * j] - ss;
+    const double rho = rho2 > 0.0 ? sqrt(rho2) : (rho2 <= 0.0 ? 0.0 : rho2);   // NaN stays NaN
+    if (j >= 1) {
+        for (int i = threadIdx.x; i < j; i += CH_BLOCK) ctl->H[i + (j - 1) * CH_LDH] = ctl->h1[i] + S.s[i];
+        if (threadIdx.x == 0) ctl->H[j + (j - 1) * CH_LDH] = rho;
+    }
+    __syncthreads();
+    return rho;
+}
+
+// DCGS2, iteration j, dimension j not accepted: coefficients of the update
+// pass and the first-projection column h' of column j.
+__device__ void dc_coefficients(PhiShared& S, Ctl* ctl, int j, double rho) {
+    const double* H = ctl->H;
+    for (int r = threadIdx.x; r <= j; r += CH_BLOCK) {   // g = H_j s (Hessenberg: c >= r - 1)
+        double g = 0.0;
+        for (int c = r > 0 ? r - 1 : 0; c < j; ++c) g += H[r + c * CH_LDH] * S.s[c];
+        S.g[r] = g;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double st = 0.0;
+    for (int i = 0; i < j; ++i) st += S.s[i] * S.t[i];
+    const double ir = 1.0 / rho;
+    const double qw = (ctl->dt[2 * j + 1] - st) * ir;   // q_j^T w
+    for (int i = 0; i <= j; ++i) {
+        const double hp = ((i < j ? S.t[i] : qw) - S.g[i]) * ir;   // h'_i
+        const double c = S.g[i] * ir + hp;
+        ctl->h1[i] = hp;
+        if (i < j) {
+            ctl->ca[i] = -S.s[i] * ctl->vscale[i] * ir;
+            ctl->cb[i] = -c * ctl->vscale[i];
+        } else {
+            ctl->ca[j] = ctl->vscale[j] * ir;
+            ctl->cq = -c;
+        }
+    }
+    ctl->cbw = ir;
+    for (int i = 0; i < j; ++i) ctl->vscale[i] = 1.0;   // the update pass stores q_0..q_j normalised
+    ctl->vscale[j] = 1.0;
+    ctl->vscale[j + 1] = 1.0;
+}
+
+// phi of the Hessenberg matrix after an Arnoldi iteration, convergence test
+// and residual-time trace (Fig. 3; eqs. rm, phi_stop).  One workgroup.
+// MGS iteration k: dimension j = k + 1, h_{j+1,j} from the norm
+// partials.  DCGS2 (DC) iteration k: dimension j = k after dc_finalize
+// (iteration 0 only prepares the update pass).
 //
 // Trace: the squaring chain of the evaluation at tau0 gives resnorm at every
 // s = tau0 2^-kk; the largest passing one brackets the crossing in
@@ -513,7 +469,7 @@ __device__ void store_u(Ctl* ctl, const double* E, int j) {
 // h_{j+1,j} |e_j^T exp(-s H) e_1| from the same exponential, safeguarded by the
 // bracket, to a relative precision of about 1e-14.
 // ---------------------------------------------------------------------------
-template <bool SINGLE>
+template <bool SINGLE, bool DC>
 __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst, int k,
                                                   const double* __restrict__ pin, int pin_stencil,
                                                   int* __restrict__ dflags) {
@@ -522,13 +478,25 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
     int* dflag = dflags ? dflags + I.slot : nullptr;
     if (ctl->done | ctl->halted) return;
     __shared__ PhiShared S;
-    // h_{k+2,k+1} = ||w|| from the final Gram-Schmidt pass (Fig. 3)
-    double nrm2[1];
-    sum_inst_partials<1, RED_SUM>(pin, I, pin_stencil, nrm2);
-    const double hnext = sqrt(nrm2[0]);
-    if (threadIdx.x == 0) {
-        ctl->H[(k + 1) + k * CH_LDH] = hnext;
-        ctl->vscale[k + 1] = hnext > 0.0 ? 1.0 / hnext : 0.0;
+    int j;
+    double hnext;
+    if (DC) {
+        j = k;
+        hnext = dc_finalize(S, ctl, j);
+        if (j == 0) {
+            dc_coefficients(S, ctl, 0, hnext);
+            return;
+        }
+    } else {
+        // h_{k+2,k+1} = ||w|| from the final Gram-Schmidt pass (Fig. 3)
+        double nrm2[1];
+        sum_inst_partials<1, RED_SUM>(pin, I, pin_stencil, nrm2);
+        hnext = sqrt(nrm2[0]);
+        if (threadIdx.x == 0) {
+            ctl->H[(k + 1) + k * CH_LDH] = hnext;
+            ctl->vscale[k + 1] = hnext > 0.0 ? 1.0 / hnext : 0.0;
+        }
+        j = k + 1;
     }
     if (threadIdx.x == 0) {
         // Taylor coefficients 1 / k!, k = 0..19
@@ -540,8 +508,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
         }
     }
     __syncthreads();
-    __syncthreads();   // H column k complete (written by the Gram-Schmidt launches and above)
-    const int j = k + 1;
+    __syncthreads();   // H column j - 1 complete (written by the Gram-Schmidt launches and above)
     const double* H = ctl->H;
     const double tau0 = ctl->tau0, tol = ctl->tol_phi;
     int nsq = 0;
@@ -571,6 +538,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
     }
     if (j < ctl->m_max) {
         if (threadIdx.x == 0) ctl->resnorm = res0;
+        if (DC) dc_coefficients(S, ctl, j, hnext);
         return;
     }
     // ---- trace: largest passing dyadic step below tau0 ----
@@ -989,11 +957,17 @@ hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSe
     return hipGetLastError();
 }
 
-hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, hipStream_t s) {
-    if (t.ninst == 1)
-        hipLaunchKernelGGL((k_phi<true>), IARGS, k, ps.in(), ps.stencil, b.dflag);
+hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, bool dc, hipStream_t s) {
+    if (dc)
+        if (t.ninst == 1)
+            hipLaunchKernelGGL((k_phi<true, true>), IARGS, k, nullptr, 0, b.dflag);
+        else
+            hipLaunchKernelGGL((k_phi<false, true>), IARGS, k, nullptr, 0, b.dflag);
     else
-        hipLaunchKernelGGL((k_phi<false>), IARGS, k, ps.in(), ps.stencil, b.dflag);
+        if (t.ninst == 1)
+            hipLaunchKernelGGL((k_phi<true, false>), IARGS, k, ps.in(), ps.stencil, b.dflag);
+        else
+            hipLaunchKernelGGL((k_phi<false, false>), IARGS, k, ps.in(), ps.stencil, b.dflag);
     return hipGetLastError();
 }
 
@@ -1006,70 +980,57 @@ bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected) {
     return true;
 }
 
-hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, int stage, hipStream_t s) {
-    const dim3 grid(k + 1, t.ninst);
+hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStream_t s) {
+    const dim3 grid(2 * k + 2, t.ninst);
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_dots_reduce<true>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst, k,
-                           b.dots, stage);
+        hipLaunchKernelGGL((k_dots_reduce<true>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst,
+                           b.dots);
     else
-        hipLaunchKernelGGL((k_dots_reduce<false>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst, k,
-                           b.dots, stage);
+        hipLaunchKernelGGL((k_dots_reduce<false>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst,
+                           b.dots);
     return hipGetLastError();
 }
 
 template <typename TV>
-static void launch_cgs_project_t(const Table& t, const DevBuffers& b, int k, hipStream_t s) {
-    const TV* V = static_cast<const TV*>(b.V);
-    if (t.ninst == 1)
-        hipLaunchKernelGGL((k_cgs_project<TV, true>), CARGS, V, b.ldv, k, b.dots);
-    else
-        hipLaunchKernelGGL((k_cgs_project<TV, false>), CARGS, V, b.ldv, k, b.dots);
-}
-
-hipError_t launch_cgs_project(const Table& t, int prec, const DevBuffers& b, int k, hipStream_t s) {
-    if (prec == CH_FP64) launch_cgs_project_t<double>(t, b, k, s);
-    else launch_cgs_project_t<float>(t, b, k, s);
-    return hipGetLastError();
-}
-
-template <typename TV>
-static void launch_cgs_update_t(const Table& t, const DevBuffers& b, int k, double* pout, hipStream_t s) {
+static void launch_dc_update_t(const Table& t, const DevBuffers& b, int j, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_cgs_update<TV, true>), CARGS, V, b.ldv, k, pout);
+        hipLaunchKernelGGL((k_dc_update<TV, true>), CARGS, V, b.ldv, j);
     else
-        hipLaunchKernelGGL((k_cgs_update<TV, false>), CARGS, V, b.ldv, k, pout);
+        hipLaunchKernelGGL((k_dc_update<TV, false>), CARGS, V, b.ldv, j);
 }
 
-hipError_t launch_cgs_update(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, hipStream_t s) {
-    if (prec == CH_FP64) launch_cgs_update_t<double>(t, b, k, ps.out(), s);
-    else launch_cgs_update_t<float>(t, b, k, ps.out(), s);
-    ps.produced(false);
+hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s) {
+    if (prec == CH_FP64) launch_dc_update_t<double>(t, b, j, s);
+    else launch_dc_update_t<float>(t, b, j, s);
     return hipGetLastError();
 }
 
+// One Arnoldi iteration.  MGS: iteration k makes column k + 1 and tests
+// dimension k + 1.  DCGS2: iteration k (0..m_max) finishes column k - 1,
+// tests dimension k and (k < m_max) makes columns k and k + 1.
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               int orth, hipStream_t s) {
+                               int orth, int m_max, hipStream_t s) {
     hipError_t e;
-    if (orth == CH_ORTH_MGS) {
-        if ((e = launch_matvec(t, prec, b, ps, y, k, false, s)) != hipSuccess) return e;
-        for (int i = 1; i <= k + 1; ++i)
-            if ((e = launch_mgs_pass(t, prec, b, ps, k, i, s)) != hipSuccess) return e;
-    } else {
-        if ((e = launch_matvec(t, prec, b, ps, y, k, true, s)) != hipSuccess) return e;
-        if ((e = launch_dots_reduce(t, b, k, 1, s)) != hipSuccess) return e;
-        if ((e = launch_cgs_project(t, prec, b, k, s)) != hipSuccess) return e;
-        if ((e = launch_dots_reduce(t, b, k, 2, s)) != hipSuccess) return e;
-        if ((e = launch_cgs_update(t, prec, b, ps, k, s)) != hipSuccess) return e;
+    if (orth == CH_ORTH_DCGS2) {
+        if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_DC, k < m_max, s)) != hipSuccess) return e;
+        if ((e = launch_dots_reduce(t, b, k, s)) != hipSuccess) return e;
+        if ((e = launch_phi(t, b, ps, k, true, s)) != hipSuccess) return e;
+        if (k < m_max) return launch_dc_update(t, prec, b, k, s);
+        return hipSuccess;
     }
-    return launch_phi(t, b, ps, k, s);
+    if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_ONE, true, s)) != hipSuccess) return e;
+    for (int i = 1; i <= k + 1; ++i)
+        if ((e = launch_mgs_pass(t, prec, b, ps, k, i, s)) != hipSuccess) return e;
+    return launch_phi(t, b, ps, k, false, s);
 }
 
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
                           int orth, const int* expected, hipStream_t s) {
-    for (int k = 0; k < m_max; ++k) {
+    const int iters = orth == CH_ORTH_DCGS2 ? m_max + 1 : m_max;
+    for (int k = 0; k < iters; ++k) {
         if (k > 0 && all_cycles_done(t, b, expected)) break;
-        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, s);
+        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, m_max, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -34,29 +34,35 @@ __device__ __forceinline__ T ccoef(T y, int eyre) {
 }
 
 // ---------------------------------------------------------------------------
-// w = Ahat (vscale[k] V_k) (the matvec of Fig. 3) with the partials of its dot
-// products: <w, V_0> only (the first MGS dot product), or <w, V_i> for every
-// i = 0..k (ALLDOTS: the first projection of CGS2) into rows i of pout.
+// w = Ahat u, u = vscale[k] V_k (the matvec of Fig. 3), stored in column k + 1
+// (unless store_w is 0), with the partials of its dot products:
+//   DM_ONE  <w, V_0>                                   (the first MGS dot)
+//   DM_DC   rows i < k: <u, V_i>; rows k + i: <w, V_i>;
+//           row 2k: <u, u>; row 2k + 1: <u, w>          (DCGS2)
 // ---------------------------------------------------------------------------
-template <int DIM, typename TV, typename TY, bool SINGLE, bool ALLDOTS>
+enum DotMode { DM_ONE = 0, DM_DC = 1 };
+
+template <int DIM, typename TV, typename TY, bool SINGLE, int DM>
 __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                      const int* __restrict__ sb2i, const Inst inst0, int ninst, TV* __restrict__ V, size_t ldv,
-                                                     int k, const TY* __restrict__ ybase,
+                                                     int k, int store_w, const TY* __restrict__ ybase,
                                                      double* __restrict__ pout) {
     const Inst I = SINGLE ? inst0 : insts[sb2i[blockIdx.x]];
     Ctl* ctl = ctls + I.slot;
     if (ctl->done | ctl->halted) return;
     using R1 = Region<DIM, 1>;
     using R2 = Region<DIM, 2>;
+    constexpr int TX = Geo<DIM>::TX, TY_ = Geo<DIM>::TY;
     constexpr int PPT = tile_points<DIM>() / CH_BLOCK;   // output points per thread and tile
     static_assert(PPT * CH_BLOCK == tile_points<DIM>(), "tile size");
+    static_assert(PPT == 2, "the dot phase takes two points per thread");
     constexpr int NW = CH_BLOCK / 64;
-    constexpr int RB = 8;   // basis columns whose loads are issued together (one wave_sum8)
+    constexpr bool MANY = DM != DM_ONE;
     __shared__ TV sv[R2::SIZE];
     __shared__ TV sd[R1::SIZE];
     __shared__ TV sq[R1::SIZE];
-    __shared__ double red[ALLDOTS ? CH_MMAX + 1 : 1][NW];
-    __shared__ TV sw[ALLDOTS ? tile_points<DIM>() : 1];
+    __shared__ double red[DM == DM_DC ? CH_DROWS : 1][NW];
+    __shared__ TV sw[MANY ? tile_points<DIM>() : 1];
     using P2 = typename Pair<TV>::type;
     const TV* Vk = V + (size_t)k * ldv + I.off;
     TV* W = V + (size_t)(k + 1) * ldv + I.off;
@@ -66,8 +72,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
     const TV sc = TV(ctl->vscale[k]);
     const TV ih2 = TV(I.inv_h2), e2ih2 = TV(I.eps2 * I.inv_h2);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (ALLDOTS)
-        for (int i = threadIdx.x; i < (k + 1) * NW; i += CH_BLOCK) red[i / NW][i % NW] = 0.0;
+    const int nrows = 2 * k + 2;
+    if (MANY)
+        for (int i = threadIdx.x; i < nrows * NW; i += CH_BLOCK) red[i / NW][i % NW] = 0.0;
     int ntx, nty;
     const int nt = num_tiles<DIM>(n, ntx, nty);
     const int lb = blockIdx.x - I.sblk0;
@@ -90,51 +97,72 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
             gv[m] = 0;
             if (out_point<DIM>(threadIdx.x + m * CH_BLOCK, o, n, i1, gi)) {
                 const TV w = ih2 * lap1_at<DIM>(sq, i1);
-                W[gi] = w;
+                if (store_w) W[gi] = w;
                 wv[m] = w;
                 gv[m] = gi;
             }
         }
-        if (ALLDOTS) {
+        if (MANY) {
             // Through LDS, each thread takes the tile-linear points 2t, 2t + 1
             // (x-neighbours), so a column is read with one 2-wide load per
             // thread where both are in the grid and the pair is aligned.
-            // Points outside the grid carry w = 0.
+            // Points outside the grid carry w = u = 0.
 #pragma unroll
             for (int m = 0; m < PPT; ++m) sw[threadIdx.x + m * CH_BLOCK] = wv[m];
             __syncthreads();
             const int p0 = 2 * threadIdx.x;
-            const int cx = p0 % Geo<DIM>::TX, rr = p0 / Geo<DIM>::TX;
-            const int gx = o.x0 + cx, gy = o.y0 + rr % Geo<DIM>::TY, gz = o.z0 + rr / Geo<DIM>::TY;
+            const int cx = p0 % TX, rr = p0 / TX, cy = rr % TY_, cz = rr / TY_;
+            const int gx = o.x0 + cx, gy = o.y0 + cy, gz = o.z0 + cz;
             const bool rowin = gy < n && (DIM == 2 || gz < n);
             const bool in0 = rowin && gx < n, in1 = rowin && gx + 1 < n;
             const size_t g0 = in0 ? ((size_t)gz * n + gy) * n + gx : 0;
             const bool pair = in1 && (g0 & 1) == 0;
             const double w0 = double(sw[p0]), w1 = double(sw[p0 + 1]);
-            for (int i0 = 0; i0 <= k; i0 += RB) {
-                TV v0[RB], v1[RB];
-#pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    const TV* col = V + (size_t)(i0 + r) * ldv + I.off;
-                    v0[r] = TV(0);
-                    v1[r] = TV(0);
-                    if (i0 + r <= k) {
-                        if (pair) {
-                            const P2 q = *reinterpret_cast<const P2*>(col + g0);
-                            v0[r] = q.x;
-                            v1[r] = q.y;
-                        } else {
-                            if (in0) v0[r] = col[g0];
-                            if (in1) v1[r] = col[g0 + 1];
-                        }
-                    }
+            const int c2 = ((cz + (DIM == 3 ? 2 : 0)) * R2::Y + (cy + 2)) * R2::X + (cx + 2);
+            const double u0 = in0 ? double(sv[c2]) : 0.0, u1 = in1 ? double(sv[c2 + 1]) : 0.0;
+            auto load2 = [&](int i, TV& v0, TV& v1) {
+                const TV* col = V + (size_t)i * ldv + I.off;
+                if (pair) {
+                    const P2 q = *reinterpret_cast<const P2*>(col + g0);
+                    v0 = q.x;
+                    v1 = q.y;
+                } else {
+                    v0 = in0 ? col[g0] : TV(0);
+                    v1 = in1 ? col[g0 + 1] : TV(0);
                 }
-                double a[RB];
+            };
+            {
+                // four columns per wave_sum8 (two sums each); the loads of the
+                // next four are in flight while this block is summed
+                constexpr int RB = 4;
+                const int hv = wave_sum8_holder(lane);
+                auto fetch = [&](int i0, TV (&v0)[RB], TV (&v1)[RB]) {
 #pragma unroll
-                for (int r = 0; r < RB; ++r) a[r] = w0 * double(v0[r]) + w1 * double(v1[r]);
+                    for (int r = 0; r < RB; ++r) {
+                        v0[r] = v1[r] = TV(0);
+                        if (i0 + r < k) load2(i0 + r, v0[r], v1[r]);
+                    }
+                };
+                TV c0[RB], c1[RB];
+                fetch(0, c0, c1);
+                for (int i0 = 0; i0 < k; i0 += RB) {
+                    TV n0[RB], n1[RB];
+                    fetch(i0 + RB, n0, n1);
+                    double a[8];
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) {
+                        a[2 * r] = u0 * double(c0[r]) + u1 * double(c1[r]);
+                        a[2 * r + 1] = w0 * double(c0[r]) + w1 * double(c1[r]);
+                        c0[r] = n0[r];
+                        c1[r] = n1[r];
+                    }
+                    const double tot = wave_sum8(a);
+                    const int c = i0 + (hv >> 1);
+                    if (hv >= 0 && c < k) red[(hv & 1) ? k + c : c][wid] += tot;
+                }
+                double a[8] = {u0 * u0 + u1 * u1, u0 * w0 + u1 * w1, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                 const double tot = wave_sum8(a);
-                const int r = (lane >> 3) & 7;
-                if ((lane & 7) == 0 && i0 + r <= k) red[i0 + r][wid] += tot;
+                if (hv == 0 || hv == 1) red[2 * k + hv][wid] += tot;
             }
         } else {
 #pragma unroll
@@ -142,8 +170,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
         }
         __syncthreads();
     }
-    if (ALLDOTS) {
-        for (int i = threadIdx.x; i <= k; i += CH_BLOCK) {
+    if (MANY) {
+        for (int i = threadIdx.x; i < nrows; i += CH_BLOCK) {
             double a = red[i][0];
 #pragma unroll
             for (int w = 1; w < NW; ++w) a += red[i][w];
@@ -403,37 +431,39 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctls, co
 // ---------------------------------------------------------------------------
 #define SARGS dim3(t.sgrid), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.sb2i, t.hinst[0], t.ninst
 
-template <int DIM, typename TV, typename TY, bool ALLDOTS>
-static void launch_matvec_k(const Table& t, const DevBuffers& b, const TY* y, int k, double* pout, hipStream_t s) {
+template <int DIM, typename TV, typename TY, int DM>
+static void launch_matvec_k(const Table& t, const DevBuffers& b, const TY* y, int k, int store_w, double* pout,
+                            hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, true, ALLDOTS>), SARGS, V, b.ldv, k, y, pout);
+        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, true, DM>), SARGS, V, b.ldv, k, store_w, y, pout);
     else
-        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, false, ALLDOTS>), SARGS, V, b.ldv, k, y, pout);
+        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, false, DM>), SARGS, V, b.ldv, k, store_w, y, pout);
 }
 
 // FP64 basis: FP64 state; FP32 basis: the FP32 copy of the state.
 template <int DIM, typename TV>
 static hipError_t launch_matvec_t(const Table& t, const DevBuffers& b, PartSeq& ps, const void* y, int k,
-                                  bool alldots, hipStream_t s) {
+                                  int dots, bool store_w, hipStream_t s) {
     using TY = TV;
     const TY* yy = static_cast<const TY*>(y);
-    if (alldots) {
-        launch_matvec_k<DIM, TV, TY, true>(t, b, yy, k, b.dots, s);
+    const int sw = store_w ? 1 : 0;
+    if (dots == MV_DOTS_DC) {
+        launch_matvec_k<DIM, TV, TY, DM_DC>(t, b, yy, k, sw, b.dots, s);
     } else {
-        launch_matvec_k<DIM, TV, TY, false>(t, b, yy, k, ps.out(), s);
+        launch_matvec_k<DIM, TV, TY, DM_ONE>(t, b, yy, k, sw, ps.out(), s);
         ps.produced(true);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                         bool alldots, hipStream_t s) {
+                         int dots, bool store_w, hipStream_t s) {
     if (prec == CH_FP64)
-        return t.dim == 2 ? launch_matvec_t<2, double>(t, b, ps, y, k, alldots, s)
-                          : launch_matvec_t<3, double>(t, b, ps, y, k, alldots, s);
-    return t.dim == 2 ? launch_matvec_t<2, float>(t, b, ps, b.y32, k, alldots, s)
-                      : launch_matvec_t<3, float>(t, b, ps, b.y32, k, alldots, s);
+        return t.dim == 2 ? launch_matvec_t<2, double>(t, b, ps, y, k, dots, store_w, s)
+                          : launch_matvec_t<3, double>(t, b, ps, y, k, dots, store_w, s);
+    return t.dim == 2 ? launch_matvec_t<2, float>(t, b, ps, b.y32, k, dots, store_w, s)
+                      : launch_matvec_t<3, float>(t, b, ps, b.y32, k, dots, store_w, s);
 }
 
 template <int DIM, typename TV>
