@@ -47,6 +47,7 @@ struct ch_ctx {
     int* d_cb2i = nullptr;
     size_t inst_cap = 0, map_cap = 0;
     std::vector<Inst> h_inst;
+    SideStream side{};       // second stream for the DCGS2 phi tests
     std::string err;
 };
 
@@ -317,8 +318,8 @@ int restart_cycles(ch_ctx* ctx, const Table& t, int prec, PartSeq& ps, const dou
         ctx->expect[t.hinst[0].slot] += 1;
         HIP_TRY(ctx, launch_resid(t, prec, b, ps, y, z, false, false, ctx->stream));
         HIP_TRY(ctx, launch_after_resid(t, b, ps, false, ctx->stream));
-        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, y, m_max, orth, ctx->expect.data(), ctx->stream));
-        HIP_TRY(ctx, launch_update(t, prec, b, z, z, ctx->stream));
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, y, m_max, orth, ctx->expect.data(), &ctx->side, ctx->stream));
+        HIP_TRY(ctx, launch_update(t, prec, b, z, z, orth == CH_ORTH_DCGS2, ctx->stream));
     }
     ctx->err = "restart cycle limit reached";
     return CH_ETAU_UNDERFLOW;
@@ -347,8 +348,9 @@ int issue_ee_steps(ch_ctx* ctx, const Table& t, int prec, int m_max, int orth, b
     for (int i = 0; i < t.ninst; ++i) ctx->expect[t.hinst[i].slot] += 1;
     for (long long s = 0; s < max_launch; ++s) {
         const int p = (int)(s & 1);
-        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[p], m_max, orth, ctx->expect.data(), ctx->stream));
-        HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[p], m_max, orth, ctx->expect.data(), &ctx->side,
+                                    ctx->stream));
+        HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[p], b.ybuf[p ^ 1], orth == CH_ORTH_DCGS2, ctx->stream));
         if (constant && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[p], b.ybuf[p ^ 1], m_max, orth))) return rc;
         HIP_TRY(ctx, launch_est_ee(t, prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
         HIP_TRY(ctx, launch_step_end(t, b, ps, true, ctx->stream));
@@ -686,8 +688,8 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
     PartSeq ps;
     ps.base = b.part;
     HIP_TRY(ctx, launch_arnoldi(*t, S->prec, b, ps, b.ybuf[p], S->opts.m_max, S->opts.orth, ctx->expect.data(),
-                                ctx->stream));
-    HIP_TRY(ctx, launch_update(*t, S->prec, b, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
+                                &ctx->side, ctx->stream));
+    HIP_TRY(ctx, launch_update(*t, S->prec, b, b.ybuf[p], b.ybuf[p ^ 1], S->opts.orth == CH_ORTH_DCGS2, ctx->stream));
     HIP_TRY(ctx, launch_est_ee(*t, S->prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
     HIP_TRY(ctx, launch_step_end(*t, b, ps, true, ctx->stream));
     for (Req* r : live) ctx->expect[r->slot] += 1;
@@ -769,6 +771,16 @@ int ch_create(ch_ctx** out, int device, void* hip_stream) {
     if (!ctx) return CH_ENOMEM;
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    SideStream& sd = ctx->side;
+    if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sd.ev_main, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sd.ev_side, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (sd.ev_main) (void)hipEventDestroy(sd.ev_main);
+        if (sd.stream) (void)hipStreamDestroy(sd.stream);
+        delete ctx;
+        return CH_EDEVICE;
+    }
     *out = ctx;
     return CH_OK;
 }
@@ -777,6 +789,7 @@ int ch_destroy(ch_ctx* ctx) {
     if (!ctx) return CH_EINVAL;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->side.stream);
     DevBuffers& b = ctx->b;
     for (void* p : {(void*)b.V, (void*)b.ybuf[0], (void*)b.ybuf[1], (void*)b.fcur, (void*)b.y32, (void*)b.zbuf,
                     (void*)b.part, (void*)b.dots, (void*)b.ctl, (void*)ctx->rec, (void*)ctx->d_inst, (void*)ctx->d_sb2i,
@@ -784,6 +797,9 @@ int ch_destroy(ch_ctx* ctx) {
         free_dev(p);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
     if (ctx->hflag) (void)hipHostFree(ctx->hflag);
+    (void)hipEventDestroy(ctx->side.ev_main);
+    (void)hipEventDestroy(ctx->side.ev_side);
+    (void)hipStreamDestroy(ctx->side.stream);
     delete ctx;
     return CH_OK;
 }
@@ -869,8 +885,9 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     HIP_TRY(ctx, launch_resid(t, prec, b, ps, b.ybuf[0], b.ybuf[0], false, true, ctx->stream));
     HIP_TRY(ctx, launch_after_resid(t, b, ps, true, ctx->stream));
     ctx->expect[0] += 1;
-    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, CH_ORTH_DCGS2, ctx->expect.data(), ctx->stream));
-    HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[0], b.ybuf[1], ctx->stream));
+    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, CH_ORTH_DCGS2, ctx->expect.data(), &ctx->side,
+                                ctx->stream));
+    HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[0], b.ybuf[1], true, ctx->stream));
     if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[0], b.ybuf[1], m_max, CH_ORTH_DCGS2)))
         return rc;
     if ((rc = read_heads(ctx, 1))) return rc;
@@ -913,10 +930,10 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, i
     // every operand but leave the data as it was
     const int kc = m_max - 1;
     for (int i = 0; i <= m_max; ++i) h.vscale[i] = 1.0;
-    for (int i = 0; i <= kc; ++i) h.ca[i] = h.cb[i] = 0.0;
-    h.ca[kc] = 1.0;
-    h.cbw = 1.0;
-    h.cq = 0.0;
+    // DCGS2 totals of an orthonormal set: rho = 1, every projection 0
+    for (int i = 0; i < CH_DROWS; ++i) h.dt[i] = 0.0;
+    h.dt[2 * kc] = 1.0;
+    for (int i = 0; i <= kc; ++i) h.h1[0][i] = h.h1[1][i] = 0.0;
     h.tol_phi = 1.0;
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(b.part, 0, 2 * sizeof(double) * CH_NRED * CH_MAXB, ctx->stream));

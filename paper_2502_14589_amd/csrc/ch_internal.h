@@ -49,12 +49,11 @@ struct Ctl {
     // Arnoldi
     double H[CH_LDH * CH_MMAX];   // h_{i+1,k+1} at H[i + k*CH_LDH]
     double vscale[CH_MMAX + 1];   // v_i = vscale[i] * V(:, i)
-    double h1[CH_MMAX + 1];       // DCGS2: first-projection coefficients of the current column
-    // DCGS2: dot-product totals of the current iteration, and the coefficients
-    // of its update pass (q_j = sum_i ca[i] V_i; u_{j+1} = cbw w + sum_{i<j} cb[i] V_i + cq q_j)
+    // DCGS2: first-projection coefficients h' of the newest column, in two
+    // buffers (iteration j reads [j & 1], writes [(j + 1) & 1]), and the
+    // dot-product totals of the current iteration
+    double h1[2][CH_MMAX + 1];
     double dt[CH_DROWS];
-    double ca[CH_MMAX + 1], cb[CH_MMAX + 1];
-    double cbw, cq;
     double u[CH_MMAX];            // tau phi(-tau H) e_1
 };
 
@@ -126,22 +125,32 @@ hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq&
 // DCGS2 passes of Arnoldi iteration k (see ch_krylov.hip).
 hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStream_t s);
 hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s);
+hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStream_t s);
 hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
 // phi test of iteration k (MGS: dimension k + 1, from the norm
 // partials; dc: DCGS2 iteration k -- dimension k, then the update coefficients).
 hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, bool dc, hipStream_t s);
 // Arnoldi iteration k: matvec, Gram-Schmidt passes (orth: ch_orth), phi and
 // residual test.
+// A second stream for the phi tests of DCGS2: each test waits for its
+// iteration's update launch (ev_main) and then overlaps the next iterations;
+// the cycle's end waits for the last test (ev_side).  Null: all on `s`.
+struct SideStream {
+    hipStream_t stream;
+    hipEvent_t ev_main, ev_side;
+};
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               int orth, int m_max, hipStream_t s);
+                               int orth, int m_max, const SideStream* side, hipStream_t s);
 // True when every instance has reported the current cycle finished:
 // expected[slot] is the number of cycles the host has issued for that slot.
 bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected);
 // Issues the Arnoldi iterations of one Krylov cycle; stops issuing once every
 // instance has reported the cycle finished (later launches would exit at once).
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
-                          int orth, const int* expected, hipStream_t s);
-hipError_t launch_update(const Table& t, int prec, const DevBuffers& b, const double* y, double* ynew, hipStream_t s);
+                          int orth, const int* expected, const SideStream* side, hipStream_t s);
+// unit: the basis is stored normalised (DCGS2)
+hipError_t launch_update(const Table& t, int prec, const DevBuffers& b, const double* y, double* ynew, bool unit,
+                         hipStream_t s);
 hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y0,
                          const double* y1, hipStream_t s);
 hipError_t launch_step_end(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_next, hipStream_t s);

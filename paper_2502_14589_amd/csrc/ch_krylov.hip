@@ -83,29 +83,104 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctls, const 
 
 // ---------------------------------------------------------------------------
 // DCGS2 for Arnoldi iteration j.  Column j holds u_j, the (j+1)-th vector
-// after one classical projection on q_0..q_{j-1} (columns 0..j-1, q_i =
-// vscale[i] V_i), not yet reorthogonalised nor normalised.
+// after one classical projection on q_0..q_{j-1} (columns 0..j-1, stored
+// normalised), not yet reorthogonalised nor normalised (u_0 is the start
+// vector, scaled by vscale[0] = 1 / beta).
 //   the matvec launch:    w = Ahat u_j into column j + 1; partials of
-//                         sigma_i = <V_i, u_j>, tau_i = <V_i, w> (i < j),
+//                         sigma_i = <q_i, u_j>, tau_i = <q_i, w> (i < j),
 //                         alpha = <u_j, u_j>, beta' = <u_j, w>
 //   k_dots_reduce:        their totals
-//   the phi launch:       s = Q^T u_j, rho^2 = alpha - |s|^2 (Pythagoras: s is
-//                         the reorthogonalisation of a vector already
-//                         projected once, so no cancellation);
-//                         h_{:,j-1} += s, h_{j,j-1} = rho: column j - 1 of the
-//                         Hessenberg matrix is final, and dimension j is
-//                         tested.  Then, from the Arnoldi relation
+//   k_dc_update:          s = sigma, rho^2 = alpha - |s|^2 (Pythagoras: s is the
+//                         reorthogonalisation of a vector already projected
+//                         once, so no cancellation); h_{:,j-1} = h'_{:,j-1} + s
+//                         and h_{j,j-1} = rho make column j - 1 of the
+//                         Hessenberg matrix final.  From the Arnoldi relation
 //                         A Q_{j-1} = Q_j H_j, A q_j = (w - Q_j H_j s) / rho, so
 //                         the first projection of A q_j on Q_j follows from the
-//                         same totals: with g = H_j s,
-//                         h'_i = (t_i - g_i) / rho  (i < j, t = Q^T w),
-//                         h'_j = ((beta' - s.t) / rho - g_j) / rho;
-//   k_dc_update:          q_j = (u_j - Q_{j-1} s) / rho into column j, and
-//                         u_{j+1} = A q_j - Q_j h' = w / rho - Q_j (g / rho + h')
-//                         into column j + 1, in one pass over the basis.
-// Iteration 0 has no columns to project on: rho = |u_0| (the start vector),
-// and only the coefficients are formed.
+//                         same totals: with g = H_j s and t = tau,
+//                           h'_i = (t_i - g_i) / rho                 (i < j),
+//                           h'_j = ((beta' - s.t) / rho - g_j) / rho;
+//                         then, in one pass over the basis,
+//                           q_j = (u_j - Q_{j-1} s) / rho           -> column j,
+//                           u_{j+1} = w / rho - Q_j (g / rho + h')  -> column j + 1.
+//   the phi launch:       tests dimension j on the final columns 0..j-1; it
+//                         reads only H and can overlap the next iteration.
+// Every workgroup of the update forms the coefficients itself (same
+// arithmetic, same order: identical in all of them); the first workgroup of
+// an instance publishes column j - 1 and h'.  h' alternates between two
+// buffers, so the publishing workgroup never overwrites what another still
+// reads.  At j = m_max only column j - 1 is formed (FIN, one workgroup).
 // ---------------------------------------------------------------------------
+struct DcCoef {
+    double s[CH_MMAX + 1], t[CH_MMAX + 1], g[CH_MMAX + 1], hf[CH_MMAX + 1];
+    double ca[CH_MMAX + 1], cb[CH_MMAX + 1];
+    double hs[CH_MMAX * (CH_MMAX + 1)];   // H_j staged column by column, leading dimension j + 1
+    double rho, st, cbw, cq;
+};
+
+// Coefficients of iteration j into LDS; `publish`: this workgroup writes
+// column j - 1 of H and h' of column j.  Contains barriers: call from every
+// thread of the workgroup.  Sums over i < j (j < 64) are wave-0 butterflies,
+// the same in every workgroup.
+__device__ void dc_prepare(DcCoef& C, Ctl* ctl, int j, bool fin, bool publish) {
+    const double* dt = ctl->dt;
+    const double* hprev = ctl->h1[j & 1];   // h' of column j - 1
+    for (int i = threadIdx.x; i < j; i += CH_BLOCK) {
+        C.s[i] = dt[i];
+        C.t[i] = dt[j + i];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int i = threadIdx.x;
+        const double si = i < j ? C.s[i] : 0.0, ti = i < j ? C.t[i] : 0.0;
+        const double ss = wave_sum(si * si), st = wave_sum(si * ti);
+        if (i == 0) {
+            const double rho2 = dt[2 * j] - ss;
+            C.rho = rho2 > 0.0 ? sqrt(rho2) : (rho2 <= 0.0 ? 0.0 : rho2);   // NaN stays NaN
+            C.st = st;
+        }
+    }
+    __syncthreads();
+    const double rho = C.rho;
+    for (int i = threadIdx.x; i <= j; i += CH_BLOCK) {
+        const double h = i < j ? hprev[i] + C.s[i] : rho;
+        C.hf[i] = h;
+        if (publish && j >= 1) ctl->H[i + (j - 1) * CH_LDH] = h;
+    }
+    if (fin) return;
+    __syncthreads();
+    // H_j ((j + 1) x j, Hessenberg): columns 0..j-2 are final in ctl->H, column j - 1 is C.hf
+    const int ld = j + 1;
+    for (int idx = threadIdx.x; idx < ld * j; idx += CH_BLOCK) {
+        const int c = idx / ld, r = idx - c * ld;
+        C.hs[idx] = r > c + 1 ? 0.0 : (c == j - 1 ? C.hf[r] : ctl->H[r + c * CH_LDH]);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r <= j; r += CH_BLOCK) {   // g = H_j s
+        double g = 0.0;
+        for (int c = r > 0 ? r - 1 : 0; c < j; ++c) g += C.hs[r + c * ld] * C.s[c];
+        C.g[r] = g;
+    }
+    __syncthreads();
+    const double ir = 1.0 / rho;
+    const double qw = (dt[2 * j + 1] - C.st) * ir;   // q_j^T w
+    double* hnew = ctl->h1[(j + 1) & 1];
+    for (int i = threadIdx.x; i <= j; i += CH_BLOCK) {
+        const double hp = ((i < j ? C.t[i] : qw) - C.g[i]) * ir;   // h'_i
+        const double c = C.g[i] * ir + hp;
+        if (publish) hnew[i] = hp;
+        if (i < j) {
+            C.ca[i] = -C.s[i] * ir;
+            C.cb[i] = -c;
+        } else {
+            C.ca[j] = (j == 0 ? ctl->vscale[0] : 1.0) * ir;
+            C.cq = -c;
+        }
+    }
+    if (threadIdx.x == 0) C.cbw = ir;
+    __syncthreads();
+}
+
 template <typename TV, bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ cb2i, const Inst inst0, int ninst,
@@ -115,13 +190,11 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     if (ctl->done | ctl->halted) return;
     using VT = typename Vec16<TV>::type;
     constexpr int VW = Vec16<TV>::W, Q = 2, RB = 4;
-    __shared__ double ca[CH_MMAX + 1], cb[CH_MMAX + 1];
-    for (int i = threadIdx.x; i <= j; i += CH_BLOCK) {
-        ca[i] = ctl->ca[i];
-        cb[i] = i < j ? ctl->cb[i] : 0.0;
-    }
-    __syncthreads();
-    const double cbw = ctl->cbw, cq = ctl->cq;
+    __shared__ DcCoef C;
+    dc_prepare(C, ctl, j, false, (int)blockIdx.x == I.cblk0);
+    const double* ca = C.ca;
+    const double* cb = C.cb;
+    const double cbw = C.cbw, cq = C.cq;
     const TV* Vi = V + I.off;
     TV* U = V + (size_t)j * ldv + I.off;
     TV* Wc = V + (size_t)(j + 1) * ldv + I.off;
@@ -208,6 +281,17 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     }
 }
 
+// Iteration j = m_max: column j - 1 of H only (one workgroup per instance).
+template <bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK) void k_dc_finish(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                        const Inst inst0, int ninst, int j) {
+    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->done | ctl->halted) return;
+    __shared__ DcCoef C;
+    dc_prepare(C, ctl, j, true, true);
+}
+
 // One workgroup per (row i, instance): the total of the partials of row i of
 // a DCGS2 matvec launch.
 template <bool SINGLE>
@@ -229,14 +313,17 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dots_reduce(Ctl* __restrict__ ctls
 template <typename TV, bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                      const int* __restrict__ cb2i, const Inst inst0, int ninst, const double* ybase,
-                                                     const TV* __restrict__ V, size_t ldv, double* ynewbase) {
-    // ybase may alias ynewbase (restart cycles update the sub-step state in place)
+                                                     const TV* __restrict__ V, size_t ldv, double* ynewbase,
+                                                     int unit) {
+    // ybase may alias ynewbase (restart cycles update the sub-step state in place);
+    // unit: the basis is stored normalised (DCGS2), vscale is not used
     const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
     Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
     __shared__ double cf[CH_MMAX];
     const int j = ctl->j;
-    if ((int)threadIdx.x < j) cf[threadIdx.x] = ctl->beta * ctl->u[threadIdx.x] * ctl->vscale[threadIdx.x];
+    if ((int)threadIdx.x < j)
+        cf[threadIdx.x] = ctl->beta * ctl->u[threadIdx.x] * (unit ? 1.0 : ctl->vscale[threadIdx.x]);
     __syncthreads();
     const double* y = ybase + I.off;
     double* ynew = ynewbase + I.off;
@@ -280,7 +367,6 @@ struct PhiShared {
     double c[20];               // 1 / k!
     double lvl[NLVL];           // lvl[kk] = resnorm at s 2^-kk from the squaring chain
     double red;
-    double s[CH_MMAX + 1], t[CH_MMAX + 1], g[CH_MMAX + 1];   // DCGS2 combination
 };
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -402,64 +488,11 @@ __device__ void store_u(Ctl* ctl, const double* E, int j) {
 }
 
 // ---------------------------------------------------------------------------
-// DCGS2, iteration j (see k_dc_update): s, t from the totals, rho, and the
-// final column j - 1 of the Hessenberg matrix.  Returns rho = h_{j,j-1}.
-__device__ double dc_finalize(PhiShared& S, Ctl* ctl, int j) {
-    for (int i = threadIdx.x; i < j; i += CH_BLOCK) {
-        S.s[i] = ctl->vscale[i] * ctl->dt[i];
-        S.t[i] = ctl->vscale[i] * ctl->dt[j + i];
-    }
-    __syncthreads();
-    double ss = 0.0;
-    for (int i = 0; i < j; ++i) ss += S.s[i] * S.s[i];
-    const double rho2 = ctl->dt[2 * j] - ss;
-    const double rho = rho2 > 0.0 ? sqrt(rho2) : (rho2 <= 0.0 ? 0.0 : rho2);   // NaN stays NaN
-    if (j >= 1) {
-        for (int i = threadIdx.x; i < j; i += CH_BLOCK) ctl->H[i + (j - 1) * CH_LDH] = ctl->h1[i] + S.s[i];
-        if (threadIdx.x == 0) ctl->H[j + (j - 1) * CH_LDH] = rho;
-    }
-    __syncthreads();
-    return rho;
-}
-
-// DCGS2, iteration j, dimension j not accepted: coefficients of the update
-// pass and the first-projection column h' of column j.
-__device__ void dc_coefficients(PhiShared& S, Ctl* ctl, int j, double rho) {
-    const double* H = ctl->H;
-    for (int r = threadIdx.x; r <= j; r += CH_BLOCK) {   // g = H_j s (Hessenberg: c >= r - 1)
-        double g = 0.0;
-        for (int c = r > 0 ? r - 1 : 0; c < j; ++c) g += H[r + c * CH_LDH] * S.s[c];
-        S.g[r] = g;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double st = 0.0;
-    for (int i = 0; i < j; ++i) st += S.s[i] * S.t[i];
-    const double ir = 1.0 / rho;
-    const double qw = (ctl->dt[2 * j + 1] - st) * ir;   // q_j^T w
-    for (int i = 0; i <= j; ++i) {
-        const double hp = ((i < j ? S.t[i] : qw) - S.g[i]) * ir;   // h'_i
-        const double c = S.g[i] * ir + hp;
-        ctl->h1[i] = hp;
-        if (i < j) {
-            ctl->ca[i] = -S.s[i] * ctl->vscale[i] * ir;
-            ctl->cb[i] = -c * ctl->vscale[i];
-        } else {
-            ctl->ca[j] = ctl->vscale[j] * ir;
-            ctl->cq = -c;
-        }
-    }
-    ctl->cbw = ir;
-    for (int i = 0; i < j; ++i) ctl->vscale[i] = 1.0;   // the update pass stores q_0..q_j normalised
-    ctl->vscale[j] = 1.0;
-    ctl->vscale[j + 1] = 1.0;
-}
-
 // phi of the Hessenberg matrix after an Arnoldi iteration, convergence test
 // and residual-time trace (Fig. 3; eqs. rm, phi_stop).  One workgroup.
 // MGS iteration k: dimension j = k + 1, h_{j+1,j} from the norm
-// partials.  DCGS2 (DC) iteration k: dimension j = k after dc_finalize
-// (iteration 0 only prepares the update pass).
+// partials.  DCGS2 (DC) iteration k >= 1: dimension j = k, H final up to
+// column j - 1 (written by the update launch of the same iteration).
 //
 // Trace: the squaring chain of the evaluation at tau0 gives resnorm at every
 // s = tau0 2^-kk; the largest passing one brackets the crossing in
@@ -482,11 +515,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
     double hnext;
     if (DC) {
         j = k;
-        hnext = dc_finalize(S, ctl, j);
-        if (j == 0) {
-            dc_coefficients(S, ctl, 0, hnext);
-            return;
-        }
+        hnext = ctl->H[j + (j - 1) * CH_LDH];
     } else {
         // h_{k+2,k+1} = ||w|| from the final Gram-Schmidt pass (Fig. 3)
         double nrm2[1];
@@ -538,7 +567,6 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
     }
     if (j < ctl->m_max) {
         if (threadIdx.x == 0) ctl->resnorm = res0;
-        if (DC) dc_coefficients(S, ctl, j, hnext);
         return;
     }
     // ---- trace: largest passing dyadic step below tau0 ----
@@ -1006,18 +1034,31 @@ hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j
     return hipGetLastError();
 }
 
+hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStream_t s) {
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_dc_finish<true>), dim3(t.ninst), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0],
+                           t.ninst, j);
+    else
+        hipLaunchKernelGGL((k_dc_finish<false>), dim3(t.ninst), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0],
+                           t.ninst, j);
+    return hipGetLastError();
+}
+
 // One Arnoldi iteration.  MGS: iteration k makes column k + 1 and tests
 // dimension k + 1.  DCGS2: iteration k (0..m_max) finishes column k - 1,
 // tests dimension k and (k < m_max) makes columns k and k + 1.
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               int orth, int m_max, hipStream_t s) {
+                               int orth, int m_max, const SideStream* side, hipStream_t s) {
     hipError_t e;
     if (orth == CH_ORTH_DCGS2) {
         if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_DC, k < m_max, s)) != hipSuccess) return e;
         if ((e = launch_dots_reduce(t, b, k, s)) != hipSuccess) return e;
-        if ((e = launch_phi(t, b, ps, k, true, s)) != hipSuccess) return e;
-        if (k < m_max) return launch_dc_update(t, prec, b, k, s);
-        return hipSuccess;
+        e = k < m_max ? launch_dc_update(t, prec, b, k, s) : launch_dc_finish(t, b, k, s);
+        if (e != hipSuccess || k == 0) return e;
+        if (!side) return launch_phi(t, b, ps, k, true, s);
+        if ((e = hipEventRecord(side->ev_main, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(side->stream, side->ev_main, 0)) != hipSuccess) return e;
+        return launch_phi(t, b, ps, k, true, side->stream);
     }
     if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_ONE, true, s)) != hipSuccess) return e;
     for (int i = 1; i <= k + 1; ++i)
@@ -1026,27 +1067,35 @@ hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, Pa
 }
 
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
-                          int orth, const int* expected, hipStream_t s) {
-    const int iters = orth == CH_ORTH_DCGS2 ? m_max + 1 : m_max;
+                          int orth, const int* expected, const SideStream* side, hipStream_t s) {
+    const bool dc = orth == CH_ORTH_DCGS2;
+    const int iters = dc ? m_max + 1 : m_max;
     for (int k = 0; k < iters; ++k) {
         if (k > 0 && all_cycles_done(t, b, expected)) break;
-        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, m_max, s);
+        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, m_max, dc ? side : nullptr, s);
         if (e != hipSuccess) return e;
+    }
+    if (dc && side) {   // the cycle's result is the last phi test's
+        hipError_t e = hipEventRecord(side->ev_side, side->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, side->ev_side, 0);
+        return e;
     }
     return hipSuccess;
 }
 
-hipError_t launch_update(const Table& t, int prec, const DevBuffers& b, const double* y, double* ynew, hipStream_t s) {
+hipError_t launch_update(const Table& t, int prec, const DevBuffers& b, const double* y, double* ynew, bool unit,
+                         hipStream_t s) {
+    const int u = unit ? 1 : 0;
     if (prec == CH_FP64)
         if (t.ninst == 1)
-            hipLaunchKernelGGL((k_update<double, true>), CARGS, y, static_cast<const double*>(b.V), b.ldv, ynew);
+            hipLaunchKernelGGL((k_update<double, true>), CARGS, y, static_cast<const double*>(b.V), b.ldv, ynew, u);
         else
-            hipLaunchKernelGGL((k_update<double, false>), CARGS, y, static_cast<const double*>(b.V), b.ldv, ynew);
+            hipLaunchKernelGGL((k_update<double, false>), CARGS, y, static_cast<const double*>(b.V), b.ldv, ynew, u);
     else
         if (t.ninst == 1)
-            hipLaunchKernelGGL((k_update<float, true>), CARGS, y, static_cast<const float*>(b.V), b.ldv, ynew);
+            hipLaunchKernelGGL((k_update<float, true>), CARGS, y, static_cast<const float*>(b.V), b.ldv, ynew, u);
         else
-            hipLaunchKernelGGL((k_update<float, false>), CARGS, y, static_cast<const float*>(b.V), b.ldv, ynew);
+            hipLaunchKernelGGL((k_update<float, false>), CARGS, y, static_cast<const float*>(b.V), b.ldv, ynew, u);
     return hipGetLastError();
 }
 

@@ -69,7 +69,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
     const TV* V0 = V + I.off;
     const TY* y = ybase + I.off;
     const int n = I.n, eyre = I.eyre;
-    const TV sc = TV(ctl->vscale[k]);
+    // DCGS2 keeps its columns normalised, except the start vector
+    const TV sc = TV(DM == DM_DC && k > 0 ? 1.0 : ctl->vscale[k]);
     const TV ih2 = TV(I.inv_h2), e2ih2 = TV(I.eps2 * I.inv_h2);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nrows = 2 * k + 2;
