@@ -191,10 +191,6 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     using VT = typename Vec16<TV>::type;
     constexpr int VW = Vec16<TV>::W, Q = 2, RB = 4;
     __shared__ DcCoef C;
-    dc_prepare(C, ctl, j, false, (int)blockIdx.x == I.cblk0);
-    const double* ca = C.ca;
-    const double* cb = C.cb;
-    const double cbw = C.cbw, cq = C.cq;
     const TV* Vi = V + I.off;
     TV* U = V + (size_t)j * ldv + I.off;
     TV* Wc = V + (size_t)(j + 1) * ldv + I.off;
@@ -203,21 +199,52 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     const long long NV = I.N / VW;
     const long long per = (long long)I.cblk * CH_BLOCK;
     const long long lt = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
-    for (long long q0 = lt; q0 < NV; q0 += per * Q) {
-        long long qq[Q];
-        bool ok[Q];
-        double xq[Q][VW], xu[Q][VW];
+    long long qq[Q];
+    bool ok[Q];
+    VT uv[Q], wv[Q], v[RB][Q];
+    auto load_uw = [&](long long q0) {
 #pragma unroll
         for (int u = 0; u < Q; ++u) {
             qq[u] = q0 + u * per;
             ok[u] = qq[u] < NV;
-            VT uv, wv;
             if (ok[u]) {
-                uv = U4[qq[u]];
-                wv = W4[qq[u]];
+                uv[u] = U4[qq[u]];
+                wv[u] = W4[qq[u]];
             }
-            const TV* ue = reinterpret_cast<const TV*>(&uv);
-            const TV* we = reinterpret_cast<const TV*>(&wv);
+        }
+    };
+    auto load_cols = [&](int i0) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int u = 0; u < Q; ++u) {
+                const VT* col = reinterpret_cast<const VT*>(Vi + (size_t)(i0 + r) * ldv);
+                if (ok[u] && i0 + r < j) v[r][u] = col[qq[u]];
+                else {
+                    TV* ve = reinterpret_cast<TV*>(&v[r][u]);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) ve[e] = TV(0);
+                }
+            }
+    };
+    // the first vectors and basis columns are requested before the
+    // coefficients are formed, so the loads overlap that latency
+    load_uw(lt);
+    load_cols(0);
+    dc_prepare(C, ctl, j, false, (int)blockIdx.x == I.cblk0);
+    const double* ca = C.ca;
+    const double* cb = C.cb;
+    const double cbw = C.cbw, cq = C.cq;
+    for (long long q0 = lt; q0 < NV; q0 += per * Q) {
+        if (q0 != lt) {
+            load_uw(q0);
+            load_cols(0);
+        }
+        double xq[Q][VW], xu[Q][VW];
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            const TV* ue = reinterpret_cast<const TV*>(&uv[u]);
+            const TV* we = reinterpret_cast<const TV*>(&wv[u]);
 #pragma unroll
             for (int e = 0; e < VW; ++e) {
                 xq[u][e] = ok[u] ? ca[j] * double(ue[e]) : 0.0;
@@ -225,19 +252,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
             }
         }
         for (int i0 = 0; i0 < j; i0 += RB) {
-            VT v[RB][Q];
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-#pragma unroll
-                for (int u = 0; u < Q; ++u) {
-                    const VT* col = reinterpret_cast<const VT*>(Vi + (size_t)(i0 + r) * ldv);
-                    if (ok[u] && i0 + r < j) v[r][u] = col[qq[u]];
-                    else {
-                        TV* ve = reinterpret_cast<TV*>(&v[r][u]);
-#pragma unroll
-                        for (int e = 0; e < VW; ++e) ve[e] = TV(0);
-                    }
-                }
+            if (i0 > 0) load_cols(i0);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const double a = i0 + r < j ? ca[i0 + r] : 0.0;

@@ -20,10 +20,6 @@ __device__ __forceinline__ double cheb_node(int i, int p) {
     return cos(3.141592653589793 * double(2 * i - 1) / double(2 * p));
 }
 
-template <typename T> struct Pair;
-template <> struct Pair<double> { using type = double2; };
-template <> struct Pair<float> { using type = float2; };
-
 template <typename T>
 __device__ __forceinline__ T dcoef(T y, int eyre) {
     return T(3) * y * y - T(1) + T(eyre);
@@ -63,7 +59,11 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
     __shared__ TV sq[R1::SIZE];
     __shared__ double red[DM == DM_DC ? CH_DROWS : 1][NW];
     __shared__ TV sw[MANY ? tile_points<DIM>() : 1];
-    using P2 = typename Pair<TV>::type;
+    using VT = typename Vec16<TV>::type;
+    constexpr int PD = Vec16<TV>::W;                                   // dot-phase points per thread
+    constexpr int CG = PD * CH_BLOCK / tile_points<DIM>();             // column groups
+    static_assert(CG * tile_points<DIM>() == PD * CH_BLOCK && (CH_BLOCK / CG) % 64 == 0, "dot-phase split");
+    static_assert(Geo<DIM>::TX % PD == 0, "dot-phase points stay in one row");
     const TV* Vk = V + (size_t)k * ldv + I.off;
     TV* W = V + (size_t)(k + 1) * ldv + I.off;
     const TV* V0 = V + I.off;
@@ -104,66 +104,90 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
             }
         }
         if (MANY) {
-            // Through LDS, each thread takes the tile-linear points 2t, 2t + 1
-            // (x-neighbours), so a column is read with one 2-wide load per
-            // thread where both are in the grid and the pair is aligned.
-            // Points outside the grid carry w = u = 0.
+            // Through LDS, each thread takes PD consecutive tile-linear points
+            // (x-neighbours), so a column is read with one 16-byte load per
+            // thread where all are in the grid and aligned.  FP32 (PD = 4)
+            // splits the columns between two thread groups, each covering the
+            // whole tile.  Points outside the grid carry w = u = 0.
 #pragma unroll
             for (int m = 0; m < PPT; ++m) sw[threadIdx.x + m * CH_BLOCK] = wv[m];
             __syncthreads();
-            const int p0 = 2 * threadIdx.x;
+            constexpr int GT = CH_BLOCK / CG;   // threads per column group
+            const int grp = threadIdx.x / GT, p0 = PD * (threadIdx.x % GT);
             const int cx = p0 % TX, rr = p0 / TX, cy = rr % TY_, cz = rr / TY_;
             const int gx = o.x0 + cx, gy = o.y0 + cy, gz = o.z0 + cz;
             const bool rowin = gy < n && (DIM == 2 || gz < n);
-            const bool in0 = rowin && gx < n, in1 = rowin && gx + 1 < n;
-            const size_t g0 = in0 ? ((size_t)gz * n + gy) * n + gx : 0;
-            const bool pair = in1 && (g0 & 1) == 0;
-            const double w0 = double(sw[p0]), w1 = double(sw[p0 + 1]);
+            bool in[PD];
+#pragma unroll
+            for (int e = 0; e < PD; ++e) in[e] = rowin && gx + e < n;
+            const size_t g0 = in[0] ? ((size_t)gz * n + gy) * n + gx : 0;
+            const bool vec = in[PD - 1] && g0 % PD == 0;
             const int c2 = ((cz + (DIM == 3 ? 2 : 0)) * R2::Y + (cy + 2)) * R2::X + (cx + 2);
-            const double u0 = in0 ? double(sv[c2]) : 0.0, u1 = in1 ? double(sv[c2 + 1]) : 0.0;
-            auto load2 = [&](int i, TV& v0, TV& v1) {
+            double wd[PD], ud[PD];
+#pragma unroll
+            for (int e = 0; e < PD; ++e) {
+                wd[e] = double(sw[p0 + e]);
+                ud[e] = in[e] ? double(sv[c2 + e]) : 0.0;
+            }
+            auto loadv = [&](int i, TV (&v)[PD]) {
                 const TV* col = V + (size_t)i * ldv + I.off;
-                if (pair) {
-                    const P2 q = *reinterpret_cast<const P2*>(col + g0);
-                    v0 = q.x;
-                    v1 = q.y;
+                if (vec) {
+                    const VT q = *reinterpret_cast<const VT*>(col + g0);
+                    const TV* qe = reinterpret_cast<const TV*>(&q);
+#pragma unroll
+                    for (int e = 0; e < PD; ++e) v[e] = qe[e];
                 } else {
-                    v0 = in0 ? col[g0] : TV(0);
-                    v1 = in1 ? col[g0 + 1] : TV(0);
+#pragma unroll
+                    for (int e = 0; e < PD; ++e) v[e] = in[e] ? col[g0 + e] : TV(0);
                 }
             };
             {
-                // four columns per wave_sum8 (two sums each); the loads of the
-                // next four are in flight while this block is summed
+                // four of the group's columns per wave_sum8 (two sums each);
+                // the loads of the next four are in flight while this block
+                // is summed
                 constexpr int RB = 4;
                 const int hv = wave_sum8_holder(lane);
-                auto fetch = [&](int i0, TV (&v0)[RB], TV (&v1)[RB]) {
+                const int kg = (k - grp + CG - 1) / CG;   // columns grp, grp + CG, ... below k
+                auto fetch = [&](int l0, TV (&v)[RB][PD]) {
 #pragma unroll
                     for (int r = 0; r < RB; ++r) {
-                        v0[r] = v1[r] = TV(0);
-                        if (i0 + r < k) load2(i0 + r, v0[r], v1[r]);
+                        if (l0 + r < kg) loadv(grp + CG * (l0 + r), v[r]);
+                        else
+#pragma unroll
+                            for (int e = 0; e < PD; ++e) v[r][e] = TV(0);
                     }
                 };
-                TV c0[RB], c1[RB];
-                fetch(0, c0, c1);
-                for (int i0 = 0; i0 < k; i0 += RB) {
-                    TV n0[RB], n1[RB];
-                    fetch(i0 + RB, n0, n1);
+                TV cur[RB][PD];
+                fetch(0, cur);
+                for (int l0 = 0; l0 < kg; l0 += RB) {
+                    TV nxt[RB][PD];
+                    fetch(l0 + RB, nxt);
                     double a[8];
 #pragma unroll
                     for (int r = 0; r < RB; ++r) {
-                        a[2 * r] = u0 * double(c0[r]) + u1 * double(c1[r]);
-                        a[2 * r + 1] = w0 * double(c0[r]) + w1 * double(c1[r]);
-                        c0[r] = n0[r];
-                        c1[r] = n1[r];
+                        a[2 * r] = a[2 * r + 1] = 0.0;
+#pragma unroll
+                        for (int e = 0; e < PD; ++e) {
+                            a[2 * r] += ud[e] * double(cur[r][e]);
+                            a[2 * r + 1] += wd[e] * double(cur[r][e]);
+                            cur[r][e] = nxt[r][e];
+                        }
                     }
                     const double tot = wave_sum8(a);
-                    const int c = i0 + (hv >> 1);
-                    if (hv >= 0 && c < k) red[(hv & 1) ? k + c : c][wid] += tot;
+                    const int l = l0 + (hv >> 1);
+                    if (hv >= 0 && l < kg) {
+                        const int c = grp + CG * l;
+                        red[(hv & 1) ? k + c : c][wid] += tot;
+                    }
                 }
-                double a[8] = {u0 * u0 + u1 * u1, u0 * w0 + u1 * w1, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int e = 0; e < PD; ++e) {
+                    a[0] += ud[e] * ud[e];
+                    a[1] += ud[e] * wd[e];
+                }
                 const double tot = wave_sum8(a);
-                if (hv == 0 || hv == 1) red[2 * k + hv][wid] += tot;
+                if (grp == 0 && (hv == 0 || hv == 1)) red[2 * k + hv][wid] += tot;
             }
         } else {
 #pragma unroll
