@@ -248,20 +248,29 @@ enum ch_kernel {
     CH_KERNEL_PHI = 2,      /* one small-matrix phi evaluation of the last step's H (no trace) */
     /* the two CH_ORTH_DCGS2 passes of Arnoldi iteration j = m_max - 1: */
     CH_KERNEL_DC_MATVEC = 3,   /* matvec Ahat u_j with the 2j + 2 dot products against the basis */
-    CH_KERNEL_DC_UPDATE = 4    /* q_j and u_{j+1} from one pass over the basis */
+    CH_KERNEL_DC_UPDATE = 4,   /* q_j and u_{j+1} from one pass over the basis */
+    CH_KERNEL_LIM_STAGE = 5    /* one LIM Chebyshev stage */
 };
 
 /*
- * Measurement aid for the roofline figures: average duration in microseconds
- * of `reps` back-to-back launches of one kernel of the EE2 path, bracketed by
- * HIP events on the context's stream, on the workspace of the last ch_run_ee
- * call (same problem, precision and Krylov dimension m_max >= 2 are required).
- * *bytes receives the algorithmic bytes one launch must move (each operand
- * vector read or written once).  Overwrites basis columns 1, 2 and m_max and
- * the control block; a later run re-initialises them.
+ * Measurement aid for the roofline figures: `count` back-to-back launches of
+ * one kernel of the path, bracketed by HIP events on the context's stream, on
+ * the workspace of an earlier run on this problem (ch_run_ee with Krylov
+ * dimension >= m_max; ch_run_lim for CH_KERNEL_LIM_STAGE).  iters[i] is the
+ * Arnoldi iteration of launch i: CH_KERNEL_DC_MATVEC 0..m_max (w stored below
+ * m_max), CH_KERNEL_DC_UPDATE 0..m_max-1, CH_KERNEL_MGS (pass 1 of the
+ * iteration) 1..m_max-1, CH_KERNEL_MATVEC 0..m_max-1, CH_KERNEL_PHI (a
+ * not-converged test of that dimension) 1..min(m_max-1, last step's j);
+ * ignored (may be NULL) for CH_KERNEL_LIM_STAGE.  The DCGS2 and LIM kernels
+ * are launched under a symbol of their own, so a profiler reports these
+ * launches apart from the path's.  *total_us: elapsed time of the sequence;
+ * *total_bytes: its algorithmic bytes (each operand vector read or written
+ * once).  Overwrites basis columns and the control block with values of no
+ * meaning; a later run re-initialises them.
  */
-int ch_time_kernel(ch_ctx *ctx, const ch_problem *prob, int kernel, int m_max, int reps,
-                   double *avg_us, double *bytes);
+int ch_time_kernel(ch_ctx *ctx, const ch_problem *prob, int kernel, int m_max, const int *iters, int count,
+                   double *total_us, double *total_bytes);
+
 
 #ifdef __cplusplus
 }

@@ -24,11 +24,12 @@ CH_PMAX = 4096
 EXPORTED = (
     "ch_create", "ch_destroy", "ch_strerror", "ch_last_error_message",
     "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_step_lim", "ch_phiv", "ch_time_kernel",
+
     "ch_server_create", "ch_server_destroy", "ch_submit", "ch_poll",
 )
 CH_REQ_QUEUED, CH_REQ_RUNNING, CH_REQ_DONE, CH_REQ_FAILED = 0, 1, 2, 3
 CH_KERNEL_MGS, CH_KERNEL_MATVEC, CH_KERNEL_PHI = 0, 1, 2
-CH_KERNEL_DC_MATVEC, CH_KERNEL_DC_UPDATE = 3, 4
+CH_KERNEL_DC_MATVEC, CH_KERNEL_DC_UPDATE, CH_KERNEL_LIM_STAGE = 3, 4, 5
 CH_ORTH_DCGS2, CH_ORTH_MGS = 0, 1
 
 
@@ -107,7 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.ch_server_destroy.argtypes = [c_void_p]
     lib.ch_submit.argtypes = [c_void_p, P(ChRequest), P(ctypes.c_ulonglong)]
     lib.ch_poll.argtypes = [c_void_p, ctypes.c_ulonglong, P(c_int), c_void_p, P(ChRunStats), P(c_double)]
-    lib.ch_time_kernel.argtypes = [c_void_p, P(ChProblem), c_int, c_int, c_int, P(c_double), P(c_double)]
+    lib.ch_time_kernel.argtypes = [c_void_p, P(ChProblem), c_int, c_int, P(c_int), c_int, P(c_double), P(c_double)]
     for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim",
                  "ch_step_lim", "ch_phiv", "ch_time_kernel", "ch_server_create", "ch_server_destroy", "ch_submit",
                  "ch_poll"):
@@ -274,11 +275,17 @@ class Context:
         return rec.as_dict()
 
     # -- measurement aid -----------------------------------------------------
-    def time_kernel(self, prob: Problem, kernel: int, m_max: int, reps: int = 50):
-        """(average microseconds per launch, algorithmic bytes per launch) of one EE2 kernel."""
+    def time_kernel(self, prob: Problem, kernel: int, m_max: int, iters=None, count: int = 0):
+        """(elapsed microseconds, algorithmic bytes) of back-to-back launches of one kernel:
+        one per entry of `iters` (Arnoldi iterations), or `count` LIM stages."""
         us, by = c_double(), c_double()
         pb = prob.c()
-        rc = self.lib.ch_time_kernel(self._ptr, byref(pb), int(kernel), int(m_max), int(reps), byref(us), byref(by))
+        if iters is None:
+            arr, n = None, int(count)
+        else:
+            n = len(iters)
+            arr = (c_int * n)(*[int(k) for k in iters])
+        rc = self.lib.ch_time_kernel(self._ptr, byref(pb), int(kernel), int(m_max), arr, n, byref(us), byref(by))
         self._raise(rc, "ch_time_kernel")
         return us.value, by.value
 

@@ -47,7 +47,7 @@ struct ch_ctx {
     int* d_cb2i = nullptr;
     size_t inst_cap = 0, map_cap = 0;
     std::vector<Inst> h_inst;
-    SideStream side{};       // second stream for the DCGS2 phi tests
+    LaunchEnv env{};         // second stream for the DCGS2 phi tests
     std::string err;
 };
 
@@ -128,6 +128,9 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         b.dflag = nullptr;
         ctx->slots = 0;
         if ((rc = alloc_dev(ctx, (void**)&b.ctl, sizeof(Ctl) * nslots))) return rc;
+        free_dev(b.lorder);
+        b.lorder = nullptr;
+        if ((rc = alloc_dev(ctx, (void**)&b.lorder, sizeof(int) * CH_PMAX * nslots))) return rc;
         HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hctl, sizeof(Ctl) * nslots, hipHostMallocDefault));
         HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, sizeof(int) * nslots,
                                    hipHostMallocMapped | hipHostMallocCoherent));
@@ -318,7 +321,7 @@ int restart_cycles(ch_ctx* ctx, const Table& t, int prec, PartSeq& ps, const dou
         ctx->expect[t.hinst[0].slot] += 1;
         HIP_TRY(ctx, launch_resid(t, prec, b, ps, y, z, false, false, ctx->stream));
         HIP_TRY(ctx, launch_after_resid(t, b, ps, false, ctx->stream));
-        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, y, m_max, orth, ctx->expect.data(), &ctx->side, ctx->stream));
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, y, m_max, orth, ctx->expect.data(), &ctx->env, ctx->stream));
         HIP_TRY(ctx, launch_update(t, prec, b, z, z, orth == CH_ORTH_DCGS2, ctx->stream));
     }
     ctx->err = "restart cycle limit reached";
@@ -348,7 +351,7 @@ int issue_ee_steps(ch_ctx* ctx, const Table& t, int prec, int m_max, int orth, b
     for (int i = 0; i < t.ninst; ++i) ctx->expect[t.hinst[i].slot] += 1;
     for (long long s = 0; s < max_launch; ++s) {
         const int p = (int)(s & 1);
-        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[p], m_max, orth, ctx->expect.data(), &ctx->side,
+        HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[p], m_max, orth, ctx->expect.data(), &ctx->env,
                                     ctx->stream));
         HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[p], b.ybuf[p ^ 1], orth == CH_ORTH_DCGS2, ctx->stream));
         if (constant && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[p], b.ybuf[p ^ 1], m_max, orth))) return rc;
@@ -483,14 +486,13 @@ int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double 
         if ((rc = read_heads(ctx, 1))) return rc;
         if (ctx->hctl[0].halted) break;
         const int p = ctx->hctl[0].p;
-        // 2p - 1 stages (m = 1..p, then m = 2..p) ping-pong between zbuf and
-        // yout so that the last one lands in yout.
+        // 2p - 1 stages (the nodes in the plan's order, then again without
+        // beta_1) ping-pong between zbuf and yout so that the last one lands in yout.
         const int nst = 2 * p - 1;
         const double* src = yin;
         for (int q = 0; q < nst; ++q) {
-            const int mm = q < p ? q + 1 : q - p + 2;
             double* dst = ((nst - 1 - q) % 2 == 0) ? yout : b.zbuf;
-            HIP_TRY(ctx, launch_lim_stage(t, b, yin, src, dst, mm, ctx->stream));
+            HIP_TRY(ctx, launch_lim_stage(t, b, yin, src, dst, q, ctx->stream));
             src = dst;
         }
         HIP_TRY(ctx, launch_est_lim(t, b, ps, yin, yout, ctx->stream));
@@ -688,7 +690,7 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
     PartSeq ps;
     ps.base = b.part;
     HIP_TRY(ctx, launch_arnoldi(*t, S->prec, b, ps, b.ybuf[p], S->opts.m_max, S->opts.orth, ctx->expect.data(),
-                                &ctx->side, ctx->stream));
+                                &ctx->env, ctx->stream));
     HIP_TRY(ctx, launch_update(*t, S->prec, b, b.ybuf[p], b.ybuf[p ^ 1], S->opts.orth == CH_ORTH_DCGS2, ctx->stream));
     HIP_TRY(ctx, launch_est_ee(*t, S->prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
     HIP_TRY(ctx, launch_step_end(*t, b, ps, true, ctx->stream));
@@ -771,13 +773,13 @@ int ch_create(ch_ctx** out, int device, void* hip_stream) {
     if (!ctx) return CH_ENOMEM;
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
-    SideStream& sd = ctx->side;
-    if (hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking) != hipSuccess ||
+    LaunchEnv& sd = ctx->env;
+    if (hipStreamCreateWithFlags(&sd.side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sd.ev_main, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&sd.ev_side, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         if (sd.ev_main) (void)hipEventDestroy(sd.ev_main);
-        if (sd.stream) (void)hipStreamDestroy(sd.stream);
+        if (sd.side) (void)hipStreamDestroy(sd.side);
         delete ctx;
         return CH_EDEVICE;
     }
@@ -789,17 +791,17 @@ int ch_destroy(ch_ctx* ctx) {
     if (!ctx) return CH_EINVAL;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipStreamSynchronize(ctx->side.stream);
+    (void)hipStreamSynchronize(ctx->env.side);
     DevBuffers& b = ctx->b;
     for (void* p : {(void*)b.V, (void*)b.ybuf[0], (void*)b.ybuf[1], (void*)b.fcur, (void*)b.y32, (void*)b.zbuf,
-                    (void*)b.part, (void*)b.dots, (void*)b.ctl, (void*)ctx->rec, (void*)ctx->d_inst, (void*)ctx->d_sb2i,
+                    (void*)b.part, (void*)b.dots, (void*)b.lorder, (void*)b.ctl, (void*)ctx->rec, (void*)ctx->d_inst, (void*)ctx->d_sb2i,
                     (void*)ctx->d_cb2i})
         free_dev(p);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
     if (ctx->hflag) (void)hipHostFree(ctx->hflag);
-    (void)hipEventDestroy(ctx->side.ev_main);
-    (void)hipEventDestroy(ctx->side.ev_side);
-    (void)hipStreamDestroy(ctx->side.stream);
+    (void)hipEventDestroy(ctx->env.ev_main);
+    (void)hipEventDestroy(ctx->env.ev_side);
+    (void)hipStreamDestroy(ctx->env.side);
     delete ctx;
     return CH_OK;
 }
@@ -885,7 +887,7 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     HIP_TRY(ctx, launch_resid(t, prec, b, ps, b.ybuf[0], b.ybuf[0], false, true, ctx->stream));
     HIP_TRY(ctx, launch_after_resid(t, b, ps, true, ctx->stream));
     ctx->expect[0] += 1;
-    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, CH_ORTH_DCGS2, ctx->expect.data(), &ctx->side,
+    HIP_TRY(ctx, launch_arnoldi(t, prec, b, ps, b.ybuf[0], m_max, CH_ORTH_DCGS2, ctx->expect.data(), &ctx->env,
                                 ctx->stream));
     HIP_TRY(ctx, launch_update(t, prec, b, b.ybuf[0], b.ybuf[1], true, ctx->stream));
     if (mode == CH_PHI_RESTART && (rc = restart_cycles(ctx, t, prec, ps, b.ybuf[0], b.ybuf[1], m_max, CH_ORTH_DCGS2)))
@@ -899,83 +901,107 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     return h.status;
 }
 
-int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, int reps, double* avg_us,
-                   double* bytes) {
-    if (!ctx || !avg_us || !bytes || reps < 1) return CH_EINVAL;
+int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, const int* iters, int count,
+                   double* total_us, double* total_bytes) {
+    if (!ctx || !total_us || !total_bytes || count < 1 || (!iters && kernel != CH_KERNEL_LIM_STAGE))
+        return CH_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
     Shape sh;
     int rc = check_problem(prob, &sh);
     if (rc) return rc;
-    if (m_max < 2 || m_max > CH_MMAX) return CH_EINVAL;
-    if (kernel < CH_KERNEL_MGS || kernel > CH_KERNEL_DC_UPDATE) return CH_EINVAL;
-    const int prec = prob->prec;
+    if (m_max < 1 || m_max > CH_MMAX || kernel < CH_KERNEL_MGS || kernel > CH_KERNEL_LIM_STAGE) return CH_EINVAL;
+    const bool lim = kernel == CH_KERNEL_LIM_STAGE;
+    const int prec = lim ? CH_FP64 : prob->prec;
     const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
     const DevBuffers& b = ctx->b;
-    if (!b.ctl || ctx->pts < (size_t)sh.N || ctx->v_bytes < (size_t)(m_max + 1) * b.ldv * esz ||
-        (prec == CH_FP32_MIXED && ctx->y32_pts < (size_t)sh.N))
-        return CH_EINVAL;   // no run on this problem yet
-    Member m{sh, prob->eps, prob->eyre, 0};
-    Table t;
-    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
-    // Control block: live, unit scales; zero partials in, so the timed axpy
-    // coefficient is 0 and the phi kernel sees h_{j+1,j} = 0 (its convergence branch)
+    // the workspace of an earlier run on this problem
+    if (!b.ctl || ctx->pts < (size_t)sh.N) return CH_EINVAL;
+    if (lim ? ctx->z_pts < (size_t)sh.N
+            : (ctx->v_bytes < (size_t)(m_max + 1) * b.ldv * esz ||
+               (prec == CH_FP32_MIXED && ctx->y32_pts < (size_t)sh.N)))
+        return CH_EINVAL;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl, b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     Ctl& h = ctx->hctl[0];
-    const int jlast = h.last_j;
-    if (kernel == CH_KERNEL_PHI && jlast < 1) return CH_EINVAL;
+    for (int i = 0; !lim && i < count; ++i) {
+        const int k = iters[i];
+        bool ok;
+        switch (kernel) {
+            case CH_KERNEL_MGS: ok = k >= 1 && k < m_max; break;
+            case CH_KERNEL_MATVEC: ok = k >= 0 && k < m_max; break;
+            case CH_KERNEL_PHI: ok = k >= 1 && k < m_max && k <= h.last_j; break;
+            case CH_KERNEL_DC_MATVEC: ok = k >= 0 && k <= m_max; break;
+            default: ok = k >= 0 && k < m_max;
+        }
+        if (!ok) return CH_EINVAL;
+    }
+    Member m{sh, prob->eps, prob->eyre, 0};
+    Table t;
+    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
+    // A live control block.  Unit scales and zero totals: the timed passes
+    // move every operand; values are not meaningful afterwards.  tol_phi = 0:
+    // every phi test takes the not-converged branch (one exponential).
     h.done = 0;
     h.halted = 0;
-    // unit scales and zero projection coefficients: the timed passes move
-    // every operand but leave the data as it was
-    const int kc = m_max - 1;
-    for (int i = 0; i <= m_max; ++i) h.vscale[i] = 1.0;
-    // DCGS2 totals of an orthonormal set: rho = 1, every projection 0
+    h.tol_phi = 0.0;
+    for (int i = 0; i <= CH_MMAX; ++i) h.vscale[i] = 1.0;
     for (int i = 0; i < CH_DROWS; ++i) h.dt[i] = 0.0;
-    h.dt[2 * kc] = 1.0;
-    for (int i = 0; i <= kc; ++i) h.h1[0][i] = h.h1[1][i] = 0.0;
-    h.tol_phi = 1.0;
+    for (int i = 0; i <= CH_MMAX; ++i) h.h1[0][i] = h.h1[1][i] = 0.0;
+    if (lim) {
+        h.p = 1;
+        h.lam = 1.0;
+        if (!(h.tau0 > 0.0)) h.tau0 = 1e-9;
+        const int zero = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(b.lorder, &zero, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    }
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(b.part, 0, 2 * sizeof(double) * CH_NRED * CH_MAXB, ctx->stream));
     const double* y = b.ybuf[0];
-    auto launch = [&]() -> hipError_t {
+    const double N = double(sh.N);
+    double bytes = 0.0;
+    auto launch = [&](int k) -> hipError_t {
         PartSeq ps;
         ps.base = b.part;
         switch (kernel) {
-            case CH_KERNEL_MGS: return launch_mgs_pass(t, prec, b, ps, 1, 1, ctx->stream);
-            case CH_KERNEL_MATVEC: return launch_matvec(t, prec, b, ps, y, 0, MV_DOTS_ONE, true, ctx->stream);
-            case CH_KERNEL_PHI: return launch_phi(t, b, ps, jlast - 1, false, ctx->stream);
-            case CH_KERNEL_DC_MATVEC: return launch_matvec(t, prec, b, ps, y, kc, MV_DOTS_DC, true, ctx->stream);
-            default: return launch_dc_update(t, prec, b, kc, ctx->stream);
+            case CH_KERNEL_MGS:
+                bytes += 4.0 * esz * N;   // read w, v_{i-1}, v_i; write w
+                return launch_mgs_pass(t, prec, b, ps, k, 1, ctx->stream);
+            case CH_KERNEL_MATVEC:
+                bytes += 4.0 * esz * N;   // read v_k, the state, v_0; write w
+                return launch_matvec(t, prec, b, ps, y, k, MV_DOTS_ONE, true, ctx->stream);
+            case CH_KERNEL_PHI:
+                return launch_phi(t, b, ps, k, true, ctx->stream);
+            case CH_KERNEL_DC_MATVEC:   // read u_k, the state, q_0..q_{k-1}; write w (k < m_max)
+                bytes += (k + 2 + (k < m_max ? 1 : 0)) * esz * N;
+                return launch_matvec(t, prec, b, ps, y, k, MV_DOTS_DC, k < m_max, ctx->stream, true);
+            case CH_KERNEL_DC_UPDATE:   // read q_0..q_{k-1}, u_k, w; write q_k, u_{k+1}
+                bytes += (k + 4) * esz * N;
+                return launch_dc_update(t, prec, b, k, ctx->stream, true);
+            default:                    // read y^n, the previous stage; write the next
+                bytes += 24.0 * N;
+                return launch_lim_stage(t, b, y, y, b.zbuf, 0, ctx->stream, true);
         }
     };
-    hipEvent_t e0, e1;
-    HIP_TRY(ctx, hipEventCreate(&e0));
-    HIP_TRY(ctx, hipEventCreate(&e1));
-    HIP_TRY(ctx, launch());   // warm
-    HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
-    for (int r = 0; r < reps; ++r) {
-        if (kernel == CH_KERNEL_PHI)   // phi sets `done`; re-arm it between launches
-            HIP_TRY(ctx, hipMemsetAsync(&b.ctl->done, 0, sizeof(int), ctx->stream));
-        HIP_TRY(ctx, launch());
-    }
-    HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
-    HIP_TRY(ctx, hipEventSynchronize(e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms = 0.f;
-    HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    *avg_us = 1000.0 * ms / reps;
-    const double N = double(sh.N);
-    const double ysz = prec == CH_FP64 ? 8.0 : 4.0;
-    const double j = double(kc);   // basis vectors q_0..q_{j-1} of the timed DCGS2 iteration
-    switch (kernel) {
-        case CH_KERNEL_MGS: *bytes = 4.0 * esz * N; break;                     // read w, v_{i-1}, v_i; write w
-        case CH_KERNEL_MATVEC: *bytes = (3.0 * esz + ysz) * N; break;          // read v_k, y, v_1; write w
-        case CH_KERNEL_DC_MATVEC: *bytes = ((j + 2.0) * esz + ysz) * N; break; // read y, u, q_0..q_{j-1}; write w
-        case CH_KERNEL_DC_UPDATE: *bytes = (j + 4.0) * esz * N; break;         // read q_0..q_{j-1}, u, w; write q_j, u
-        default: *bytes = 0.0;
-    }
+    auto timed_sequence = [&]() -> hipError_t {
+        hipError_t e;
+        if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) return e;
+        if ((e = launch(lim ? 0 : iters[0])) != hipSuccess) return e;   // warm
+        bytes = 0.0;
+        if ((e = hipEventRecord(e0, ctx->stream)) != hipSuccess) return e;
+        for (int i = 0; i < count; ++i)
+            if ((e = launch(lim ? 0 : iters[i])) != hipSuccess) return e;
+        if ((e = hipEventRecord(e1, ctx->stream)) != hipSuccess) return e;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+        return hipEventElapsedTime(&ms, e0, e1);
+    };
+    const hipError_t err = timed_sequence();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    HIP_TRY(ctx, err);
+    *total_us = 1000.0 * ms;
+    *total_bytes = bytes;
     return CH_OK;
 }
 

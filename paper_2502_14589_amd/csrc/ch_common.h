@@ -254,26 +254,82 @@ __device__ __forceinline__ TileOrigin tile_origin(int t, int ntx, int nty) {
     return o;
 }
 
-// Load the region of halo H around the tile, calling put(i, value) with the
-// region's linear index.
+// Global index of point i of the halo-H region around the tile (periodic wrap
+// unless the whole region is inside the grid).
+template <int DIM, int H>
+__device__ __forceinline__ size_t region_index(const TileOrigin& o, int n, int i, bool interior) {
+    using R = Region<DIM, H>;
+    const int cx = i % R::X;
+    const int rr = i / R::X;
+    const int cy = rr % R::Y;
+    const int cz = rr / R::Y;
+    int gx = o.x0 + cx - H, gy = o.y0 + cy - H, gz = DIM == 3 ? o.z0 + cz - H : 0;
+    if (!interior) {
+        gx = wrapi(gx, n);
+        gy = wrapi(gy, n);
+        if (DIM == 3) gz = wrapi(gz, n);
+    }
+    return ((size_t)gz * n + gy) * n + gx;
+}
+
+template <int DIM, int H>
+__device__ __forceinline__ bool region_inside(const TileOrigin& o, int n) {
+    return o.x0 >= H && o.x0 + Geo<DIM>::TX + H <= n && o.y0 >= H && o.y0 + Geo<DIM>::TY + H <= n &&
+           (DIM == 2 || (o.z0 >= H && o.z0 + Geo<DIM>::TZ + H <= n));
+}
+
+// Load the regions of halo HA around the tile from `a` and of halo HB from
+// `b`, calling putA(i, value) / putB(i, value) with the region's linear
+// index.  Every load of both regions is issued before the first value is
+// used, so a workgroup waits for memory once per tile.
+template <int DIM, int HA, int HB, typename TA, typename TB, typename PA, typename PB>
+__device__ __forceinline__ void load_regions(const TileOrigin& o, int n, const TA* __restrict__ a, PA&& putA,
+                                             const TB* __restrict__ b, PB&& putB) {
+    using RA = Region<DIM, HA>;
+    using RB = Region<DIM, HB>;
+    constexpr int NA = (RA::SIZE + CH_BLOCK - 1) / CH_BLOCK;
+    constexpr int NB = (RB::SIZE + CH_BLOCK - 1) / CH_BLOCK;
+    const bool ina = region_inside<DIM, HA>(o, n), inb = region_inside<DIM, HB>(o, n);
+    TA va[NA];
+    TB vb[NB];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+        const int i = threadIdx.x + u * CH_BLOCK;
+        if (i < RA::SIZE) va[u] = a[region_index<DIM, HA>(o, n, i, ina)];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int i = threadIdx.x + u * CH_BLOCK;
+        if (i < RB::SIZE) vb[u] = b[region_index<DIM, HB>(o, n, i, inb)];
+    }
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+        const int i = threadIdx.x + u * CH_BLOCK;
+        if (i < RA::SIZE) putA(i, va[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int i = threadIdx.x + u * CH_BLOCK;
+        if (i < RB::SIZE) putB(i, vb[u]);
+    }
+}
+
+// One region of halo H, its loads issued together (see load_regions).
 template <int DIM, int H, typename TS, typename Put>
 __device__ __forceinline__ void load_region(const TileOrigin& o, int n, const TS* __restrict__ src, Put&& put) {
     using R = Region<DIM, H>;
-    const bool interior = o.x0 >= H && o.x0 + Geo<DIM>::TX + H <= n && o.y0 >= H &&
-                          o.y0 + Geo<DIM>::TY + H <= n &&
-                          (DIM == 2 || (o.z0 >= H && o.z0 + Geo<DIM>::TZ + H <= n));
-    for (int i = threadIdx.x; i < R::SIZE; i += CH_BLOCK) {
-        const int cx = i % R::X;
-        const int rr = i / R::X;
-        const int cy = rr % R::Y;
-        const int cz = rr / R::Y;
-        int gx = o.x0 + cx - H, gy = o.y0 + cy - H, gz = DIM == 3 ? o.z0 + cz - H : 0;
-        if (!interior) {
-            gx = wrapi(gx, n);
-            gy = wrapi(gy, n);
-            if (DIM == 3) gz = wrapi(gz, n);
-        }
-        put(i, src[((size_t)gz * n + gy) * n + gx]);
+    constexpr int NL = (R::SIZE + CH_BLOCK - 1) / CH_BLOCK;
+    const bool in = region_inside<DIM, H>(o, n);
+    TS v[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int i = threadIdx.x + u * CH_BLOCK;
+        if (i < R::SIZE) v[u] = src[region_index<DIM, H>(o, n, i, in)];
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int i = threadIdx.x + u * CH_BLOCK;
+        if (i < R::SIZE) put(i, v[u]);
     }
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+
 #include "../../include/ch.h"
 
 #define CH_LDH (CH_MMAX + 1)     // leading dimension of the Hessenberg matrix
@@ -81,6 +82,7 @@ struct DevBuffers {
     double* zbuf;       // FP64 scratch (LIM stages)
     double* part;       // reduction partials: two slots of CH_NRED * CH_MAXB
     double* dots;       // DCGS2 dot-product partials: CH_DROWS rows of CH_MAXB
+    int* lorder;        // LIM node order, CH_PMAX per slot
     Ctl* ctl;           // control blocks, one per slot
     int* dflag;         // device view of `hflag`, one word per slot
     const volatile int* hflag;   // pinned host words: `cyc` of the last finished Krylov cycle per slot
@@ -120,11 +122,13 @@ hipError_t launch_after_resid(const Table& t, const DevBuffers& b, PartSeq& ps, 
 hipError_t launch_cycle_begin(const Table& t, const DevBuffers& b, hipStream_t s);
 // dots (MatvecDots): MV_DOTS_ONE to the next partials slot, MV_DOTS_DC to
 // b.dots.  store_w: write w to column k + 1.
+// timing: the instantiation used by the timing aid (same code, another symbol).
 hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                         int dots, bool store_w, hipStream_t s);
+                         int dots, bool store_w, hipStream_t s, bool timing = false);
 // DCGS2 passes of Arnoldi iteration k (see ch_krylov.hip).
 hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStream_t s);
-hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s);
+hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s,
+                            bool timing = false);
 hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStream_t s);
 hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
 // phi test of iteration k (MGS: dimension k + 1, from the norm
@@ -132,22 +136,23 @@ hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSe
 hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, bool dc, hipStream_t s);
 // Arnoldi iteration k: matvec, Gram-Schmidt passes (orth: ch_orth), phi and
 // residual test.
-// A second stream for the phi tests of DCGS2: each test waits for its
-// iteration's update launch (ev_main) and then overlaps the next iterations;
-// the cycle's end waits for the last test (ev_side).  Null: all on `s`.
-struct SideStream {
-    hipStream_t stream;
+// Launch environment of the Arnoldi iterations: a second stream for the phi
+// tests of DCGS2 (each test waits for its iteration's update launch through
+// ev_main, then overlaps the next iterations; the cycle's end waits for the
+// last test through ev_side).
+struct LaunchEnv {
+    hipStream_t side;
     hipEvent_t ev_main, ev_side;
 };
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               int orth, int m_max, const SideStream* side, hipStream_t s);
+                               int orth, int m_max, const LaunchEnv* env, hipStream_t s);
 // True when every instance has reported the current cycle finished:
 // expected[slot] is the number of cycles the host has issued for that slot.
 bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected);
 // Issues the Arnoldi iterations of one Krylov cycle; stops issuing once every
 // instance has reported the cycle finished (later launches would exit at once).
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
-                          int orth, const int* expected, const SideStream* side, hipStream_t s);
+                          int orth, const int* expected, const LaunchEnv* env, hipStream_t s);
 // unit: the basis is stored normalised (DCGS2)
 hipError_t launch_update(const Table& t, int prec, const DevBuffers& b, const double* y, double* ynew, bool unit,
                          hipStream_t s);
@@ -156,8 +161,9 @@ hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq&
 hipError_t launch_step_end(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_next, hipStream_t s);
 hipError_t launch_lim_begin(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y, hipStream_t s);
 hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s);
+// Stage pos (0 .. 2p - 2) of the LIM step.
 hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                            int m, hipStream_t s);
+                            int pos, hipStream_t s, bool timing = false);
 hipError_t launch_est_lim(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y0, const double* y1,
                           hipStream_t s);
 hipError_t launch_lim_end(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s);

@@ -181,7 +181,7 @@ __device__ void dc_prepare(DcCoef& C, Ctl* ctl, int j, bool fin, bool publish) {
     __syncthreads();
 }
 
-template <typename TV, bool SINGLE>
+template <typename TV, bool SINGLE, int TAG>   // TAG: as for the matvec
 __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ cb2i, const Inst inst0, int ninst,
                                                         TV* __restrict__ V, size_t ldv, int j) {
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     // coefficients are formed, so the loads overlap that latency
     load_uw(lt);
     load_cols(0);
-    dc_prepare(C, ctl, j, false, (int)blockIdx.x == I.cblk0);
+    dc_prepare(C, ctl, j, false, TAG == 0 && (int)blockIdx.x == I.cblk0);   // timing launches publish nothing
     const double* ca = C.ca;
     const double* cb = C.cb;
     const double cbw = C.cbw, cq = C.cq;
@@ -858,7 +858,56 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctls, 
     write_partials<3, RED_MAX>(x, pout);
 }
 
-// ... then the final-time clip, lambda_max = ||Ahat_n||_1 and p (eq. p).
+// Order of the Chebyshev nodes beta_i = cos(pi (2i - 1) / (2p)) in a LIM
+// step (Fig. 1 fixes only beta_1 as the first): Leja order -- beta_1, then
+// each time the node with the largest sum of log-distances to the nodes taken
+// so far, the smallest index among those within 1e-9 (relative) of the
+// largest.  Any order gives the same step in exact arithmetic; this one keeps
+// the growth of intermediate stages, and so the amplification of rounding,
+// small (below 10^7.2 up to p = 4096, against 10^105 at p = 209 for the
+// order i = 1..p).  0-based indices into order[0..p); one workgroup.
+__device__ void lim_leja_order(int p, int* __restrict__ order) {
+    __shared__ double nd[CH_PMAX], score[CH_PMAX];
+    __shared__ unsigned char taken[CH_PMAX];
+    __shared__ double red[CH_BLOCK / 64][1];
+    __shared__ double best_s;
+    __shared__ int pick;
+    const double pi = 3.141592653589793;
+    for (int i = threadIdx.x; i < p; i += CH_BLOCK) {
+        nd[i] = cos(pi * double(2 * i + 1) / double(2 * p));
+        score[i] = 0.0;
+        taken[i] = 0;
+    }
+    __syncthreads();
+    int r = 0;
+    for (int s = 0; s < p; ++s) {
+        if (threadIdx.x == 0) order[s] = r;
+        const double br = nd[r];
+        for (int i = threadIdx.x; i < p; i += CH_BLOCK) {
+            if (i == r) taken[i] = 1;
+            else score[i] += log(fabs(nd[i] - br));
+        }
+        __syncthreads();
+        if (s == p - 1) break;
+        double v[1] = {-__builtin_inf()};
+        for (int i = threadIdx.x; i < p; i += CH_BLOCK)
+            if (!taken[i]) v[0] = fmax(v[0], score[i]);
+        block_reduce<1, RED_MAX>(v, red);
+        if (threadIdx.x == 0) best_s = v[0];
+        __syncthreads();
+        const double lim = best_s - 1e-9 * fmax(1.0, fabs(best_s));
+        double c[1] = {double(p)};
+        for (int i = threadIdx.x; i < p; i += CH_BLOCK)
+            if (!taken[i] && score[i] >= lim) c[0] = fmin(c[0], double(i));
+        block_reduce<1, RED_MIN>(c, red);
+        if (threadIdx.x == 0) pick = (int)c[0];
+        __syncthreads();
+        r = pick;
+    }
+}
+
+// ... then the final-time clip, lambda_max = ||Ahat_n||_1, p (eq. p) and the
+// order of the nodes (lim_leja_order).
 // Column j of Ahat_n is d_j A e_j + eps^2 A^2 e_j; its absolute sum g(d_j) is
 // convex and piecewise linear in d_j, so the largest column sum is
 // max(g(d_min), g(d_max)):
@@ -866,52 +915,58 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctls, 
 //   3-D: g(d) = |6d/h^2 + 42e| + 6|d/h^2 + 12e| + 30e
 template <bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst,
-                                                       const double* __restrict__ pin, int pin_stencil, int dim) {
+                                                       const double* __restrict__ pin, int pin_stencil, int dim,
+                                                       int* __restrict__ orders) {
     const Inst I = SINGLE ? inst0 : insts[blockIdx.x];
     Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
     double tot[3];
     sum_inst_partials<3, RED_MAX>(pin, I, pin_stencil, tot);
-    if (threadIdx.x != 0) return;
-    const double ymin2 = -tot[0], ymax2 = tot[1];
-    if (tot[2] != 0.0) {
-        ctl->status = CH_ENONFINITE;
-        ctl->halted = 1;
-        return;
+    __shared__ int sp;
+    if (threadIdx.x == 0) {
+        sp = 0;
+        const double ymin2 = -tot[0], ymax2 = tot[1];
+        if (tot[2] != 0.0) {
+            ctl->status = CH_ENONFINITE;
+            ctl->halted = 1;
+        } else if (!(ctl->t < ctl->T) || (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps)) {
+            ctl->halted = 1;
+        } else {
+            double tau = ctl->tau;
+            int clipped = 0;
+            if (ctl->t + tau > ctl->T) {
+                tau = ctl->T - ctl->t;
+                clipped = 1;
+            }
+            const double inv_h2 = I.inv_h2;
+            const double e = I.eps2 * inv_h2 * inv_h2;
+            const double dmin = 3.0 * ymin2 - 1.0 + I.eyre, dmax = 3.0 * ymax2 - 1.0 + I.eyre;
+            double gmin, gmax;
+            if (dim == 2) {
+                gmin = fabs(4.0 * dmin * inv_h2 + 20.0 * e) + 4.0 * fabs(dmin * inv_h2 + 8.0 * e) + 12.0 * e;
+                gmax = fabs(4.0 * dmax * inv_h2 + 20.0 * e) + 4.0 * fabs(dmax * inv_h2 + 8.0 * e) + 12.0 * e;
+            } else {
+                gmin = fabs(6.0 * dmin * inv_h2 + 42.0 * e) + 6.0 * fabs(dmin * inv_h2 + 12.0 * e) + 30.0 * e;
+                gmax = fabs(6.0 * dmax * inv_h2 + 42.0 * e) + 6.0 * fabs(dmax * inv_h2 + 12.0 * e) + 30.0 * e;
+            }
+            const double lam = fmax(gmin, gmax);
+            const double pi = 3.141592653589793;
+            const double pr = ceil((pi / 4.0) / (pi / 2.0 - atan(sqrt(tau * lam))));
+            if (!(pr <= double(CH_PMAX))) {
+                ctl->status = CH_EINVAL;
+                ctl->halted = 1;
+            } else {
+                ctl->clipped = clipped;
+                ctl->tau0 = tau;
+                ctl->lam = lam;
+                ctl->p = (int)pr;
+                sp = (int)pr;
+            }
+        }
     }
-    if (!(ctl->t < ctl->T) || (ctl->max_steps > 0 && ctl->steps >= ctl->max_steps)) {
-        ctl->halted = 1;
-        return;
-    }
-    double tau = ctl->tau;
-    int clipped = 0;
-    if (ctl->t + tau > ctl->T) {
-        tau = ctl->T - ctl->t;
-        clipped = 1;
-    }
-    const double inv_h2 = I.inv_h2;
-    const double e = I.eps2 * inv_h2 * inv_h2;
-    const double dmin = 3.0 * ymin2 - 1.0 + I.eyre, dmax = 3.0 * ymax2 - 1.0 + I.eyre;
-    double gmin, gmax;
-    if (dim == 2) {
-        gmin = fabs(4.0 * dmin * inv_h2 + 20.0 * e) + 4.0 * fabs(dmin * inv_h2 + 8.0 * e) + 12.0 * e;
-        gmax = fabs(4.0 * dmax * inv_h2 + 20.0 * e) + 4.0 * fabs(dmax * inv_h2 + 8.0 * e) + 12.0 * e;
-    } else {
-        gmin = fabs(6.0 * dmin * inv_h2 + 42.0 * e) + 6.0 * fabs(dmin * inv_h2 + 12.0 * e) + 30.0 * e;
-        gmax = fabs(6.0 * dmax * inv_h2 + 42.0 * e) + 6.0 * fabs(dmax * inv_h2 + 12.0 * e) + 30.0 * e;
-    }
-    const double lam = fmax(gmin, gmax);
-    const double pi = 3.141592653589793;
-    const double pr = ceil((pi / 4.0) / (pi / 2.0 - atan(sqrt(tau * lam))));
-    if (!(pr <= double(CH_PMAX))) {
-        ctl->status = CH_EINVAL;
-        ctl->halted = 1;
-        return;
-    }
-    ctl->clipped = clipped;
-    ctl->tau0 = tau;
-    ctl->lam = lam;
-    ctl->p = (int)pr;
+    __syncthreads();
+    const int p = sp;
+    if (p > 0) lim_leja_order(p, orders + (size_t)I.slot * CH_PMAX);
 }
 
 // LIM step end (Fig. 2): est (eq. LIMest), t, tau_new (eq. LIMdt).
@@ -1035,17 +1090,19 @@ hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStr
 }
 
 template <typename TV>
-static void launch_dc_update_t(const Table& t, const DevBuffers& b, int j, hipStream_t s) {
+static void launch_dc_update_t(const Table& t, const DevBuffers& b, int j, bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
-    if (t.ninst == 1)
-        hipLaunchKernelGGL((k_dc_update<TV, true>), CARGS, V, b.ldv, j);
+    if (timing)
+        hipLaunchKernelGGL((k_dc_update<TV, true, 1>), CARGS, V, b.ldv, j);
+    else if (t.ninst == 1)
+        hipLaunchKernelGGL((k_dc_update<TV, true, 0>), CARGS, V, b.ldv, j);
     else
-        hipLaunchKernelGGL((k_dc_update<TV, false>), CARGS, V, b.ldv, j);
+        hipLaunchKernelGGL((k_dc_update<TV, false, 0>), CARGS, V, b.ldv, j);
 }
 
-hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s) {
-    if (prec == CH_FP64) launch_dc_update_t<double>(t, b, j, s);
-    else launch_dc_update_t<float>(t, b, j, s);
+hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s, bool timing) {
+    if (prec == CH_FP64) launch_dc_update_t<double>(t, b, j, timing, s);
+    else launch_dc_update_t<float>(t, b, j, timing, s);
     return hipGetLastError();
 }
 
@@ -1063,17 +1120,18 @@ hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStrea
 // dimension k + 1.  DCGS2: iteration k (0..m_max) finishes column k - 1,
 // tests dimension k and (k < m_max) makes columns k and k + 1.
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               int orth, int m_max, const SideStream* side, hipStream_t s) {
+                               int orth, int m_max, const LaunchEnv* env, hipStream_t s) {
     hipError_t e;
     if (orth == CH_ORTH_DCGS2) {
-        if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_DC, k < m_max, s)) != hipSuccess) return e;
+        const bool store = k < m_max;
+        if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_DC, store, s)) != hipSuccess) return e;
         if ((e = launch_dots_reduce(t, b, k, s)) != hipSuccess) return e;
-        e = k < m_max ? launch_dc_update(t, prec, b, k, s) : launch_dc_finish(t, b, k, s);
+        e = store ? launch_dc_update(t, prec, b, k, s) : launch_dc_finish(t, b, k, s);
         if (e != hipSuccess || k == 0) return e;
-        if (!side) return launch_phi(t, b, ps, k, true, s);
-        if ((e = hipEventRecord(side->ev_main, s)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(side->stream, side->ev_main, 0)) != hipSuccess) return e;
-        return launch_phi(t, b, ps, k, true, side->stream);
+        if (!env) return launch_phi(t, b, ps, k, true, s);
+        if ((e = hipEventRecord(env->ev_main, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(env->side, env->ev_main, 0)) != hipSuccess) return e;
+        return launch_phi(t, b, ps, k, true, env->side);
     }
     if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_ONE, true, s)) != hipSuccess) return e;
     for (int i = 1; i <= k + 1; ++i)
@@ -1082,17 +1140,17 @@ hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, Pa
 }
 
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
-                          int orth, const int* expected, const SideStream* side, hipStream_t s) {
+                          int orth, const int* expected, const LaunchEnv* env, hipStream_t s) {
     const bool dc = orth == CH_ORTH_DCGS2;
     const int iters = dc ? m_max + 1 : m_max;
     for (int k = 0; k < iters; ++k) {
         if (k > 0 && all_cycles_done(t, b, expected)) break;
-        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, m_max, dc ? side : nullptr, s);
+        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, m_max, env, s);
         if (e != hipSuccess) return e;
     }
-    if (dc && side) {   // the cycle's result is the last phi test's
-        hipError_t e = hipEventRecord(side->ev_side, side->stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, side->ev_side, 0);
+    if (dc && env) {   // the cycle's result is the last phi test's
+        hipError_t e = hipEventRecord(env->ev_side, env->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, env->ev_side, 0);
         return e;
     }
     return hipSuccess;
@@ -1149,9 +1207,9 @@ hipError_t launch_lim_begin(const Table& t, const DevBuffers& b, PartSeq& ps, co
 
 hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s) {
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_lim_plan<true>), IARGS, ps.in(), ps.stencil, t.dim);
+        hipLaunchKernelGGL((k_lim_plan<true>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder);
     else
-        hipLaunchKernelGGL((k_lim_plan<false>), IARGS, ps.in(), ps.stencil, t.dim);
+        hipLaunchKernelGGL((k_lim_plan<false>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder);
     return hipGetLastError();
 }
 

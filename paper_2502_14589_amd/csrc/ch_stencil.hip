@@ -38,7 +38,8 @@ __device__ __forceinline__ T ccoef(T y, int eyre) {
 // ---------------------------------------------------------------------------
 enum DotMode { DM_ONE = 0, DM_DC = 1 };
 
-template <int DIM, typename TV, typename TY, bool SINGLE, int DM>
+// TAG distinguishes the launches of the timing aid (same code, another symbol).
+template <int DIM, typename TV, typename TY, bool SINGLE, int DM, int TAG>
 __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                      const int* __restrict__ sb2i, const Inst inst0, int ninst, TV* __restrict__ V, size_t ldv,
                                                      int k, int store_w, const TY* __restrict__ ybase,
@@ -82,8 +83,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
     double dot = 0.0;
     for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
         const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_region<DIM, 2>(o, n, Vk, [&](int i, TV v) { sv[i] = sc * v; });
-        load_region<DIM, 1>(o, n, y, [&](int i, TY v) { sd[i] = dcoef(TV(v), eyre); });
+        load_regions<DIM, 2, 1>(o, n, Vk, [&](int i, TV v) { sv[i] = sc * v; },
+                                y, [&](int i, TY v) { sd[i] = dcoef(TV(v), eyre); });
         __syncthreads();
         for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK)
             sq[i] = sd[i] * sv[r1_to_r2<DIM>(i)] + e2ih2 * lap2_at_r1<DIM>(sv, i);
@@ -242,8 +243,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctls, cons
     double acc_r = 0.0, acc_g = 0.0;
     for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
         const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_region<DIM, 2>(o, n, z, [&](int i, double v) { sz[i] = v; });
-        load_region<DIM, 1>(o, n, y, [&](int i, double v) {
+        load_regions<DIM, 2, 1>(o, n, z, [&](int i, double v) { sz[i] = v; }, y, [&](int i, double v) {
             sdq[i] = dcoef(v, eyre);
             sc[i] = ccoef(v, eyre);
         });
@@ -341,14 +341,14 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_ee(Ctl* __restrict__ ctls, con
 // LIM stage (one iteration of Fig. 1):
 //   y_next = (y^n + tau a_m z + tau (ghat - Ahat z)) / (1 + tau a_m)
 // ---------------------------------------------------------------------------
-template <int DIM, bool SINGLE>
+template <int DIM, bool SINGLE, int TAG>
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ sb2i, const Inst inst0, int ninst, const double* __restrict__ ybase,
                                                         const double* __restrict__ zbase, double* __restrict__ obase,
-                                                        int m) {
+                                                        const int* __restrict__ orders, int pos) {
     const Inst I = SINGLE ? inst0 : insts[sb2i[blockIdx.x]];
     Ctl* ctl = ctls + I.slot;
-    if (ctl->halted || m > ctl->p) return;
+    if (ctl->halted || pos >= 2 * ctl->p - 1) return;
     using R1 = Region<DIM, 1>;
     using R2 = Region<DIM, 2>;
     __shared__ double sz[R2::SIZE];
@@ -361,8 +361,12 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, 
     const double inv_h2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
     const double tau = ctl->tau0;
     // Fig. 1: beta_i = cos(pi (2i - 1) / (2p)), z_1 = beta_1,
-    // a_m = lambda_max (z_1 - beta_m) / (1 + z_1)
+    // a_m = lambda_max (z_1 - beta_m) / (1 + z_1).  Stage pos takes the node
+    // order[pos] (first sweep, pos < p) or order[pos - p + 1] (second sweep,
+    // without beta_1), in the order set by the plan launch.
     const int p = ctl->p;
+    const int* order = orders + (size_t)I.slot * CH_PMAX;
+    const int m = 1 + order[pos < p ? pos : pos - p + 1];
     const double z1 = cheb_node(1, p);
     const double am = ctl->lam / (1.0 + z1) * (z1 - cheb_node(m, p));
     const double ta = tau * am;
@@ -372,8 +376,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, 
     const int lb = blockIdx.x - I.sblk0;
     for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
         const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_region<DIM, 2>(o, n, z, [&](int i, double v) { sz[i] = v; });
-        load_region<DIM, 1>(o, n, y, [&](int i, double v) {
+        load_regions<DIM, 2, 1>(o, n, z, [&](int i, double v) { sz[i] = v; }, y, [&](int i, double v) {
             sdq[i] = dcoef(v, eyre);
             sc[i] = ccoef(v, eyre);
         });
@@ -422,8 +425,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctls, co
     double a_err = 0.0, a_pc = 0.0;
     for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
         const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_region<DIM, 2>(o, n, y0, [&](int i, double v) { s0[i] = v; });
-        load_region<DIM, 2>(o, n, y1, [&](int i, double v) { s1[i] = v; });
+        load_regions<DIM, 2, 2>(o, n, y0, [&](int i, double v) { s0[i] = v; }, y1, [&](int i, double v) { s1[i] = v; });
         __syncthreads();
         for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK) {
             const int c = r1_to_r2<DIM>(i);
@@ -458,37 +460,39 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctls, co
 
 template <int DIM, typename TV, typename TY, int DM>
 static void launch_matvec_k(const Table& t, const DevBuffers& b, const TY* y, int k, int store_w, double* pout,
-                            hipStream_t s) {
+                            bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
-    if (t.ninst == 1)
-        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, true, DM>), SARGS, V, b.ldv, k, store_w, y, pout);
+    if (timing)
+        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, true, DM, 1>), SARGS, V, b.ldv, k, store_w, y, pout);
+    else if (t.ninst == 1)
+        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, true, DM, 0>), SARGS, V, b.ldv, k, store_w, y, pout);
     else
-        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, false, DM>), SARGS, V, b.ldv, k, store_w, y, pout);
+        hipLaunchKernelGGL((k_matvec<DIM, TV, TY, false, DM, 0>), SARGS, V, b.ldv, k, store_w, y, pout);
 }
 
 // FP64 basis: FP64 state; FP32 basis: the FP32 copy of the state.
 template <int DIM, typename TV>
 static hipError_t launch_matvec_t(const Table& t, const DevBuffers& b, PartSeq& ps, const void* y, int k,
-                                  int dots, bool store_w, hipStream_t s) {
+                                  int dots, bool store_w, bool timing, hipStream_t s) {
     using TY = TV;
     const TY* yy = static_cast<const TY*>(y);
     const int sw = store_w ? 1 : 0;
     if (dots == MV_DOTS_DC) {
-        launch_matvec_k<DIM, TV, TY, DM_DC>(t, b, yy, k, sw, b.dots, s);
+        launch_matvec_k<DIM, TV, TY, DM_DC>(t, b, yy, k, sw, b.dots, timing, s);
     } else {
-        launch_matvec_k<DIM, TV, TY, DM_ONE>(t, b, yy, k, sw, ps.out(), s);
+        launch_matvec_k<DIM, TV, TY, DM_ONE>(t, b, yy, k, sw, ps.out(), false, s);
         ps.produced(true);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                         int dots, bool store_w, hipStream_t s) {
+                         int dots, bool store_w, hipStream_t s, bool timing) {
     if (prec == CH_FP64)
-        return t.dim == 2 ? launch_matvec_t<2, double>(t, b, ps, y, k, dots, store_w, s)
-                          : launch_matvec_t<3, double>(t, b, ps, y, k, dots, store_w, s);
-    return t.dim == 2 ? launch_matvec_t<2, float>(t, b, ps, b.y32, k, dots, store_w, s)
-                      : launch_matvec_t<3, float>(t, b, ps, b.y32, k, dots, store_w, s);
+        return t.dim == 2 ? launch_matvec_t<2, double>(t, b, ps, y, k, dots, store_w, timing, s)
+                          : launch_matvec_t<3, double>(t, b, ps, y, k, dots, store_w, timing, s);
+    return t.dim == 2 ? launch_matvec_t<2, float>(t, b, ps, b.y32, k, dots, store_w, timing, s)
+                      : launch_matvec_t<3, float>(t, b, ps, b.y32, k, dots, store_w, timing, s);
 }
 
 template <int DIM, typename TV>
@@ -534,17 +538,21 @@ hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq&
 }
 
 hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                            int m, hipStream_t s) {
+                            int pos, hipStream_t s, bool timing) {
     if (t.dim == 2)
-        if (t.ninst == 1)
-            hipLaunchKernelGGL((k_lim_stage<2, true>), SARGS, y, z, out, m);
+        if (timing)
+            hipLaunchKernelGGL((k_lim_stage<2, true, 1>), SARGS, y, z, out, b.lorder, pos);
+        else if (t.ninst == 1)
+            hipLaunchKernelGGL((k_lim_stage<2, true, 0>), SARGS, y, z, out, b.lorder, pos);
         else
-            hipLaunchKernelGGL((k_lim_stage<2, false>), SARGS, y, z, out, m);
+            hipLaunchKernelGGL((k_lim_stage<2, false, 0>), SARGS, y, z, out, b.lorder, pos);
     else
-        if (t.ninst == 1)
-            hipLaunchKernelGGL((k_lim_stage<3, true>), SARGS, y, z, out, m);
+        if (timing)
+            hipLaunchKernelGGL((k_lim_stage<3, true, 1>), SARGS, y, z, out, b.lorder, pos);
+        else if (t.ninst == 1)
+            hipLaunchKernelGGL((k_lim_stage<3, true, 0>), SARGS, y, z, out, b.lorder, pos);
         else
-            hipLaunchKernelGGL((k_lim_stage<3, false>), SARGS, y, z, out, m);
+            hipLaunchKernelGGL((k_lim_stage<3, false, 0>), SARGS, y, z, out, b.lorder, pos);
     return hipGetLastError();
 }
 

@@ -184,6 +184,25 @@ def test_lim_constant_steps_parity(ctx, dim, n, eps, tau):
     assert rel(host(yg), y_ref) <= TOL_FP64
 
 
+@pytest.mark.parametrize("tl", [7e4, 1e6])
+def test_lim_large_order_parity(ctx, tl):
+    """p in the hundreds (tau lambda_max = 7e4) and above a thousand (1e6):
+    the node order chosen on the device equals the oracle's (Leja order), and
+    the step stays accurate (in the order i = 1..p this step is destroyed by
+    rounding)."""
+    say(f"LIM one step, tau lambda_max = {tl:g}")
+    po, pg = probs(2, 64, 0.01)
+    y0 = uniform_field(64, 2, 0.7, 0.05, seed=421)
+    lam = O.lambda_max(y0, po)
+    tau = tl / lam
+    y_ref, p = O.lim_step(y0, po, tau)
+    assert p > 150
+    yg = dev(y0)
+    rec = ctx.step_lim(pg, yg, tau)
+    assert rec["j"] == p
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
 def test_small_2d_lim_200_steps(ctx):
     say("LIM constant 64^2 x 200")
     po, pg = probs(2, 64, 0.05)

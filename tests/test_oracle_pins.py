@@ -268,6 +268,54 @@ def test_lim_chebyshev_stability_polynomial(tl):
         assert ya[0] == pytest.approx(1.0 / (1.0 + tau * am), rel=1e-12, abs=1e-300)
 
 
+@pytest.mark.parametrize("p", [2, 3, 5, 8, 13, 24])
+def test_lim_node_order_is_leja(p):
+    """Reading R6: beta_1 first, then each node maximises the product of
+    distances to those taken (ties: smallest index).  Checked with 40-digit
+    products, independently of the oracle's log-sum bookkeeping."""
+    import mpmath as mp
+
+    mp.mp.dps = 40
+    b = [mp.cos(mp.pi * (2 * i - 1) / (2 * p)) for i in range(1, p + 1)]
+    order = O.lim_node_order(p)
+    assert sorted(order) == list(range(p)) and order[0] == 0
+    for s in range(1, p):
+        prev = order[:s]
+        prods = {i: mp.fprod(abs(b[i] - b[o]) for o in prev) for i in range(p) if i not in prev}
+        top = max(prods.values())
+        expect = min(i for i, v in prods.items() if v >= top * (1 - mp.mpf(10) ** -30))
+        assert order[s] == expect, (s, order)
+
+
+def test_lim_large_order_single_mode_closed_form():
+    """A LIM step with p in the hundreds on ubar + delta cos(2 pi k.x), ubar
+    outside the spinodal interval (all mu >= 0): per Fourier mode the step
+    multiplies the deviation by y* + P (1 - y*), y* = 1/(1 + tau mu), P the
+    product of the stage factors (F4, order-free).  The grid result must match
+    it: rounding amplified by intermediate stages would show up in the other
+    modes (with the nodes in order i = 1..p the error here is ~1e119)."""
+    n, eps, ubar, delta, k = 64, 0.01, 0.7, 1e-6, (3, 2)
+    prob = O.Problem(2, n, eps)
+    y0 = fourier_mode(n, 2, k, delta, ubar)
+    lam = O.lambda_max(y0, prob)
+    tau = 7e4 / lam
+    y1, p = O.lim_step(y0, prob, tau)
+    assert p > 150
+    lk = (4.0 / prob.h ** 2) * sum(math.sin(math.pi * kk / n) ** 2 for kk in k)
+    mu = lk * (3 * ubar ** 2 - 1 + eps ** 2 * lk)
+    _, a = O.lim_coefficients(p, lam)
+    # error factor of the stages (order-free product), in log form
+    logP, sign = 0.0, 1.0
+    for i in [0] + list(range(1, p)) * 2:
+        f = tau * (a[i] - mu) / (1.0 + tau * a[i])
+        logP += math.log(abs(f))
+        sign *= math.copysign(1.0, f)
+    ys = 1.0 / (1.0 + tau * mu)
+    ratio = ys + sign * math.exp(logP) * (1.0 - ys)
+    ref = fourier_mode(n, 2, k, delta * ratio, ubar)
+    assert np.max(np.abs(y1 - ref)) <= 1e-10
+
+
 def test_lim_p1_is_explicit_euler():
     prob = O.Problem(2, 16, 0.05)
     y = uniform_field(16, 2, 0.1, 0.05, seed=11)
