@@ -45,6 +45,7 @@ struct ch_ctx {
     Inst* d_inst = nullptr;
     int* d_sb2i = nullptr;
     int* d_cb2i = nullptr;
+    int* d_wb2i = nullptr;
     size_t inst_cap = 0, map_cap = 0;
     std::vector<Inst> h_inst;
     LaunchEnv env{};         // second stream for the DCGS2 phi tests
@@ -129,8 +130,11 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         ctx->slots = 0;
         if ((rc = alloc_dev(ctx, (void**)&b.ctl, sizeof(Ctl) * nslots))) return rc;
         free_dev(b.lorder);
+        free_dev(b.lcoef);
         b.lorder = nullptr;
+        b.lcoef = nullptr;
         if ((rc = alloc_dev(ctx, (void**)&b.lorder, sizeof(int) * CH_PMAX * nslots))) return rc;
+        if ((rc = alloc_dev(ctx, (void**)&b.lcoef, sizeof(double) * 4 * CH_PMAX * nslots))) return rc;
         HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hctl, sizeof(Ctl) * nslots, hipHostMallocDefault));
         HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, sizeof(int) * nslots,
                                    hipHostMallocMapped | hipHostMallocCoherent));
@@ -205,17 +209,33 @@ void inst_blocks(int dim, int n, long long N, int* sblk, int* cblk) {
     *cblk = (int)std::max<long long>(1, std::min<long long>((N + 2047) / 2048, CH_CBLK_MAX));
 }
 
-// Workgroup ranges of each instance and the block-to-instance maps.
-int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, Table* t) {
+// 2-D strip workgroups of one instance (larger grids loop over strips).
+int strip_blocks(int n, int vx) {
+    const long long waves = strip_count(n, vx);
+    return (int)std::min<long long>((waves + CH_STRIP_WAVES - 1) / CH_STRIP_WAVES, CH_SBLK_MAX);
+}
+
+// Columns per lane of the 2-D strip kernels for one grid.
+int strip_vx(int n, int prec) {
+    int vx = prec == CH_FP64 ? 2 : 4;
+    while (n % vx) vx >>= 1;
+    return vx;
+}
+
+// Workgroup ranges of each instance and the block-to-instance maps.  prec:
+// the precision of the run's basis (selects the strip width).
+int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, int prec, Table* t) {
     const int ni = (int)ms.size();
     ctx->h_inst.assign(ni, Inst{});
-    std::vector<int> sb, cb;
+    std::vector<int> sb, cb, wb;
     for (int i = 0; i < ni; ++i) {
         const Member& m = ms[i];
         Inst& I = ctx->h_inst[i];
         const int n = m.sh.n;
         int sblk, cblk;
         inst_blocks(dim, n, m.sh.N, &sblk, &cblk);
+        const int vx = strip_vx(n, prec);
+        const int wblk = dim == 2 ? strip_blocks(n, vx) : 0;
         I.off = (long long)m.off;
         I.N = m.sh.N;
         I.n = n;
@@ -224,13 +244,17 @@ int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, Table* t) {
         I.sblk = sblk;
         I.cblk0 = (int)cb.size();
         I.cblk = cblk;
+        I.wblk0 = (int)wb.size();
+        I.wblk = wblk;
+        I.vx = vx;
         I.eps2 = m.eps * m.eps;
         I.inv_h2 = double(n) * double(n);
         I.eyre = m.eyre;
         sb.insert(sb.end(), sblk, i);
         cb.insert(cb.end(), cblk, i);
+        wb.insert(wb.end(), wblk, i);
     }
-    if (sb.size() > (size_t)CH_MAXB || cb.size() > (size_t)CH_MAXB) {
+    if (sb.size() > (size_t)CH_MAXB || cb.size() > (size_t)CH_MAXB || wb.size() > (size_t)CH_MAXB) {
         ctx->err = "batch too large for one launch (workgroup table)";
         return CH_EINVAL;
     }
@@ -242,28 +266,35 @@ int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, Table* t) {
         if ((rc = alloc_dev(ctx, (void**)&ctx->d_inst, sizeof(Inst) * ni))) return rc;
         ctx->inst_cap = ni;
     }
-    const size_t mneed = std::max(sb.size(), cb.size());
+    const size_t mneed = std::max(std::max(sb.size(), cb.size()), std::max(wb.size(), (size_t)1));
     if (mneed > ctx->map_cap) {
         free_dev(ctx->d_sb2i);
         free_dev(ctx->d_cb2i);
-        ctx->d_sb2i = ctx->d_cb2i = nullptr;
+        free_dev(ctx->d_wb2i);
+        ctx->d_sb2i = ctx->d_cb2i = ctx->d_wb2i = nullptr;
         ctx->map_cap = 0;
         if ((rc = alloc_dev(ctx, (void**)&ctx->d_sb2i, sizeof(int) * mneed))) return rc;
         if ((rc = alloc_dev(ctx, (void**)&ctx->d_cb2i, sizeof(int) * mneed))) return rc;
+        if ((rc = alloc_dev(ctx, (void**)&ctx->d_wb2i, sizeof(int) * mneed))) return rc;
         ctx->map_cap = mneed;
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_inst, ctx->h_inst.data(), sizeof(Inst) * ni, hipMemcpyHostToDevice,
                                 ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_sb2i, sb.data(), sizeof(int) * sb.size(), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(ctx->d_cb2i, cb.data(), sizeof(int) * cb.size(), hipMemcpyHostToDevice, ctx->stream));
+    if (!wb.empty())
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_wb2i, wb.data(), sizeof(int) * wb.size(), hipMemcpyHostToDevice,
+                                    ctx->stream));
     // the host vectors must outlive the asynchronous copies
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     t->inst = ctx->d_inst;
     t->sb2i = ctx->d_sb2i;
     t->cb2i = ctx->d_cb2i;
+    t->wb2i = ctx->d_wb2i;
     t->ninst = ni;
     t->sgrid = (int)sb.size();
     t->cgrid = (int)cb.size();
+    t->wgrid = (int)wb.size();
     t->dim = dim;
     t->hinst = ctx->h_inst.data();
     return CH_OK;
@@ -395,7 +426,7 @@ int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t
     if ((rc = ensure(ctx, pad64(sh.N), opts->m_max, prec, 1, recs, false))) return rc;
     Member m{sh, prob->eps, prob->eyre, 0};
     Table t;
-    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
+    if ((rc = build_table(ctx, {m}, sh.dim, prec, &t))) return rc;
     const bool constant = opts->constant_step != 0;
     init_ctl(ctx->hctl, constant ? MODE_EE_CONST : MODE_EE, t0, tau0, T, opts->tol, opts->tol_phi_fixed,
              opts->tau_min, opts->m_max, max_steps, recs ? ctx->rec : nullptr, recs, ctx->expect[0]);
@@ -436,7 +467,7 @@ int run_ee_batch(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, in
     int rc;
     if ((rc = ensure(ctx, pts, opts->m_max, prec, count, 0, false))) return rc;
     Table t;
-    if ((rc = build_table(ctx, ms, dim, &t))) return rc;
+    if ((rc = build_table(ctx, ms, dim, prec, &t))) return rc;
     long long limit = 0;
     for (int i = 0; i < count; ++i) {
         const ch_batch_item& it = items[i];
@@ -469,7 +500,7 @@ int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double 
     if ((rc = ensure(ctx, pad64(sh.N), 0, CH_FP64, 1, recs, true))) return rc;
     Member m{sh, prob->eps, prob->eyre, 0};
     Table t;
-    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
+    if ((rc = build_table(ctx, {m}, sh.dim, CH_FP64, &t))) return rc;
     const DevBuffers& b = ctx->b;
     init_ctl(ctx->hctl, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, t0, tau0, T, tol, 0.0, 0.0, 0, max_steps,
              recs ? ctx->rec : nullptr, recs, ctx->expect[0]);
@@ -539,6 +570,7 @@ struct Req {
     long long N = 0;
     size_t len = 0;            // pooled points (padded)
     int sblk = 0, cblk = 0;    // workgroups in a batched launch
+    int wblk = 0;              // 2-D strip workgroups
     double* buf = nullptr;     // device: y0 until admission, the result after
     int state = CH_REQ_QUEUED;
     int status = CH_OK;
@@ -562,7 +594,7 @@ struct ch_server {
     std::unordered_map<unsigned long long, Req*> reqs;
     std::vector<Req*> slot_req;         // slot -> request in flight
     std::map<size_t, size_t> free_;     // free pooled ranges: offset -> points
-    int sblk_used = 0, cblk_used = 0, running = 0;
+    int sblk_used = 0, cblk_used = 0, wblk_used = 0, running = 0;
     unsigned long long next_id = 1;
     bool stop = false;
     int fatal = CH_OK;
@@ -639,7 +671,9 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
                     break;
                 }
             if (slot < 0) break;
-            if (S->sblk_used + r->sblk > CH_MAXB || S->cblk_used + r->cblk > CH_MAXB) break;
+            if (S->sblk_used + r->sblk > CH_MAXB || S->cblk_used + r->cblk > CH_MAXB ||
+                S->wblk_used + r->wblk > CH_MAXB)
+                break;
             size_t off;
             if (!pool_alloc(S, r->len, &off)) break;
             S->queue.pop_front();
@@ -650,6 +684,7 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
             S->slot_req[slot] = r;
             S->sblk_used += r->sblk;
             S->cblk_used += r->cblk;
+            S->wblk_used += r->wblk;
             S->running += 1;
             admitted.push_back(r);
         }
@@ -672,7 +707,7 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
             ms.push_back(member_of(r));
         }
         Table ta;
-        if ((rc = build_table(ctx, ms, 2, &ta))) return rc;
+        if ((rc = build_table(ctx, ms, 2, S->prec, &ta))) return rc;
         PartSeq ps;
         ps.base = b.part;
         HIP_TRY(ctx, launch_resid(ta, S->prec, b, ps, b.ybuf[p], b.ybuf[p], true, true, ctx->stream));
@@ -684,7 +719,7 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
     if (*dirty) {
         std::vector<Member> ms;
         for (Req* r : live) ms.push_back(member_of(r));
-        if ((rc = build_table(ctx, ms, 2, t))) return rc;
+        if ((rc = build_table(ctx, ms, 2, S->prec, t))) return rc;
         *dirty = false;
     }
     PartSeq ps;
@@ -719,6 +754,7 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
             pool_free(S, r->off, r->len);
             S->sblk_used -= r->sblk;
             S->cblk_used -= r->cblk;
+            S->wblk_used -= r->wblk;
             S->running -= 1;
         }
         *dirty = true;
@@ -795,7 +831,7 @@ int ch_destroy(ch_ctx* ctx) {
     DevBuffers& b = ctx->b;
     for (void* p : {(void*)b.V, (void*)b.ybuf[0], (void*)b.ybuf[1], (void*)b.fcur, (void*)b.y32, (void*)b.zbuf,
                     (void*)b.part, (void*)b.dots, (void*)b.lorder, (void*)b.ctl, (void*)ctx->rec, (void*)ctx->d_inst, (void*)ctx->d_sb2i,
-                    (void*)ctx->d_cb2i})
+                    (void*)ctx->d_cb2i, (void*)ctx->d_wb2i, (void*)b.lcoef})
         free_dev(p);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
     if (ctx->hflag) (void)hipHostFree(ctx->hflag);
@@ -877,7 +913,7 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     if ((rc = ensure(ctx, pad64(sh.N), m_max, prec, 1, 0, false))) return rc;
     Member m{sh, prob->eps, prob->eyre, 0};
     Table t;
-    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
+    if ((rc = build_table(ctx, {m}, sh.dim, prec, &t))) return rc;
     const DevBuffers& b = ctx->b;
     init_ctl(ctx->hctl, MODE_PHI, 0.0, tau0, INFINITY, 0.0, tol_phi, 0.0, m_max, 0, nullptr, 0, ctx->expect[0]);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
@@ -937,7 +973,7 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, c
     }
     Member m{sh, prob->eps, prob->eyre, 0};
     Table t;
-    if ((rc = build_table(ctx, {m}, sh.dim, &t))) return rc;
+    if ((rc = build_table(ctx, {m}, sh.dim, prec, &t))) return rc;
     // A live control block.  Unit scales and zero totals: the timed passes
     // move every operand; values are not meaningful afterwards.  tol_phi = 0:
     // every phi test takes the not-converged branch (one exponential).
@@ -952,7 +988,9 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, c
         h.lam = 1.0;
         if (!(h.tau0 > 0.0)) h.tau0 = 1e-9;
         const int zero = 0;
+        const double cf[2] = {0.0, 1.0};   // node beta_1: a_1 = 0
         HIP_TRY(ctx, hipMemcpyAsync(b.lorder, &zero, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(b.lcoef, cf, sizeof(cf), hipMemcpyHostToDevice, ctx->stream));
     }
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(b.part, 0, 2 * sizeof(double) * CH_NRED * CH_MAXB, ctx->stream));
@@ -1082,7 +1120,8 @@ int ch_submit(ch_server* S, const ch_request* q, unsigned long long* ticket) {
     r->N = sh.N;
     r->len = pad64(sh.N);
     inst_blocks(2, q->n, sh.N, &r->sblk, &r->cblk);
-    if (r->len > S->pool_pts || r->sblk > CH_MAXB || r->cblk > CH_MAXB) {
+    r->wblk = strip_blocks(q->n, strip_vx(q->n, S->prec));
+    if (r->len > S->pool_pts || r->sblk > CH_MAXB || r->cblk > CH_MAXB || r->wblk > CH_MAXB) {
         delete r;
         return CH_ENOMEM;
     }

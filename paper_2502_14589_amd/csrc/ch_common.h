@@ -180,13 +180,15 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ pin, int
     for (int r = 0; r < NR; ++r) tot[r] = res[r];
 }
 
-// The partials an instance's consumer adds up: those of its stencil or of its
-// streaming workgroups, whichever kind produced them.
+// The partials an instance's consumer adds up: those of its tile, strip or
+// streaming workgroups, whichever kind (PartKind) produced them.
 template <int NR, int OP>
-__device__ __forceinline__ void sum_inst_partials(const double* __restrict__ pin, const Inst& I, int by_stencil,
+__device__ __forceinline__ void sum_inst_partials(const double* __restrict__ pin, const Inst& I, int kind,
                                                   double (&tot)[NR]) {
-    if (by_stencil)
+    if (kind == PK_TILE)
         sum_partials<NR, OP>(pin, I.sblk0, I.sblk, tot);
+    else if (kind == PK_STRIP)
+        sum_partials<NR, OP>(pin, I.wblk0, I.wblk, tot);
     else
         sum_partials<NR, OP>(pin, I.cblk0, I.cblk, tot);
 }

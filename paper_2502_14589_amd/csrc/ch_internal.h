@@ -67,11 +67,32 @@ struct Inst {
     long long N;        // points
     int n;              // points per direction
     int slot;           // control block index
-    int sblk0, sblk;    // stencil workgroups [sblk0, sblk0 + sblk)
+    int sblk0, sblk;    // stencil (tile) workgroups [sblk0, sblk0 + sblk)
     int cblk0, cblk;    // streaming workgroups [cblk0, cblk0 + cblk)
     double eps2, inv_h2;
-    int eyre, pad;
+    int eyre;
+    int wblk0, wblk;    // 2-D row-strip workgroups [wblk0, wblk0 + wblk)
+    int vx;             // 2-D strips: columns per lane (divides n)
 };
+
+// 2-D row strips (ch_strip.hip): each wave of a strip workgroup owns a strip
+// of CH_STRIP_ROWS rows by strip_cols(vx) columns; lane L holds vx
+// consecutive columns, the first and last CH_STRIP_HALO(vx) lanes only halo.
+// vx: 16-byte rows of the basis type (4 FP32 or 2 FP64 values), halved until
+// it divides n.
+#ifndef CH_STRIP_ROWS
+#define CH_STRIP_ROWS 4
+#endif
+static_assert(CH_STRIP_ROWS <= 4, "strip rows: the periodic row wrap assumes n > CH_STRIP_ROWS (n >= 5)");
+#define CH_STRIP_WAVES (CH_BLOCK / 64)
+#define CH_STRIP_HALO(vx) ((vx) >= 2 ? 1 : 2)
+__host__ __device__ constexpr int strip_cols(int vx) { return (64 - 2 * CH_STRIP_HALO(vx)) * vx; }
+__host__ __device__ constexpr long long strip_count(int n, int vx) {
+    return (long long)((n + strip_cols(vx) - 1) / strip_cols(vx)) * ((n + CH_STRIP_ROWS - 1) / CH_STRIP_ROWS);
+}
+
+// Kinds of workgroup ranges that produce reduction partials.
+enum PartKind { PK_STREAM = 0, PK_TILE = 1, PK_STRIP = 2 };
 
 struct DevBuffers {
     void* V;            // Krylov basis: (m_max + 1) pooled columns of ldv elements (FP64 or FP32)
@@ -83,6 +104,7 @@ struct DevBuffers {
     double* part;       // reduction partials: two slots of CH_NRED * CH_MAXB
     double* dots;       // DCGS2 dot-product partials: CH_DROWS rows of CH_MAXB
     int* lorder;        // LIM node order, CH_PMAX per slot
+    double* lcoef;      // LIM stage coefficients (tau a_m, 1 / (1 + tau a_m)) by stage position, 2 CH_PMAX per slot
     Ctl* ctl;           // control blocks, one per slot
     int* dflag;         // device view of `hflag`, one word per slot
     const volatile int* hflag;   // pinned host words: `cyc` of the last finished Krylov cycle per slot
@@ -91,9 +113,11 @@ struct DevBuffers {
 // The instance table of one launch sequence (device pointers + host mirror sizes).
 struct Table {
     const Inst* inst;   // ninst entries
-    const int* sb2i;    // stencil workgroup -> instance
+    const int* sb2i;    // stencil (tile) workgroup -> instance
     const int* cb2i;    // streaming workgroup -> instance
+    const int* wb2i;    // 2-D strip workgroup -> instance
     int ninst, sgrid, cgrid, dim;
+    int wgrid;          // 2-D strip workgroups
     const Inst* hinst;  // host copy
 };
 
@@ -104,11 +128,11 @@ struct Table {
 struct PartSeq {
     double* base = nullptr;
     int par = 0;
-    int stencil = 0;
+    int stencil = PK_STREAM;   // PartKind of the last producer
     double* in() const { return base + (size_t)(par ^ 1) * CH_NRED * CH_MAXB; }
     double* out() const { return base + (size_t)par * CH_NRED * CH_MAXB; }
-    void produced(bool by_stencil) {
-        stencil = by_stencil ? 1 : 0;
+    void produced(int kind) {
+        stencil = kind;
         par ^= 1;
     }
 };
@@ -127,6 +151,12 @@ hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq&
                          int dots, bool store_w, hipStream_t s, bool timing = false);
 // DCGS2 passes of Arnoldi iteration k (see ch_krylov.hip).
 hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStream_t s);
+// 2-D row-strip forms (ch_strip.hip); every 2-D launch uses them.
+inline bool uses_strips(const Table& t) { return t.dim == 2; }
+hipError_t launch_matvec_strip(const Table& t, int prec, const DevBuffers& b, const double* y, int k, int dots,
+                               bool store_w, double* pout, bool timing, hipStream_t s);
+hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
+                                  int pos, bool timing, hipStream_t s);
 hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s,
                             bool timing = false);
 hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStream_t s);

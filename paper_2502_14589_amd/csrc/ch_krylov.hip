@@ -312,13 +312,13 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_finish(Ctl* __restrict__ ctls, 
 template <bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_dots_reduce(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                           const Inst inst0, int ninst,
-                                                          const double* __restrict__ dots) {
+                                                          const double* __restrict__ dots, int kind) {
     const Inst I = SINGLE ? inst0 : insts[blockIdx.y];
     Ctl* ctl = ctls + I.slot;
     if (ctl->done | ctl->halted) return;
     const int r = blockIdx.x;
     double tot[1];
-    sum_partials<1, RED_SUM>(dots + (size_t)r * CH_MAXB, I.sblk0, I.sblk, tot);
+    sum_inst_partials<1, RED_SUM>(dots + (size_t)r * CH_MAXB, I, kind, tot);
     if (threadIdx.x == 0) ctl->dt[r] = tot[0];
 }
 
@@ -916,7 +916,7 @@ __device__ void lim_leja_order(int p, int* __restrict__ order) {
 template <bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst,
                                                        const double* __restrict__ pin, int pin_stencil, int dim,
-                                                       int* __restrict__ orders) {
+                                                       int* __restrict__ orders, double* __restrict__ coefs) {
     const Inst I = SINGLE ? inst0 : insts[blockIdx.x];
     Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
@@ -966,7 +966,26 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, c
     }
     __syncthreads();
     const int p = sp;
-    if (p > 0) lim_leja_order(p, orders + (size_t)I.slot * CH_PMAX);
+    if (p == 0) return;
+    int* order = orders + (size_t)I.slot * CH_PMAX;
+    lim_leja_order(p, order);
+    __syncthreads();
+    // Fig. 1: beta_i = cos(pi (2i - 1) / (2p)), z_1 = beta_1,
+    // a_m = lambda_max (z_1 - beta_m) / (1 + z_1).  Stage position pos takes
+    // the node order[pos] (first sweep, pos < p) or order[pos - p + 1]
+    // (second sweep, without beta_1); its coefficients are
+    // (tau a_m, 1 / (1 + tau a_m)).
+    const double pi = 3.141592653589793;
+    const double z1 = cos(pi / double(2 * p));
+    const double lam = ctl->lam, tau = ctl->tau0;
+    double* cf = coefs + (size_t)I.slot * 2 * CH_PMAX * 2;
+    for (int pos = threadIdx.x; pos < 2 * p - 1; pos += CH_BLOCK) {
+        const int m = 1 + order[pos < p ? pos : pos - p + 1];
+        const double am = lam / (1.0 + z1) * (z1 - cos(pi * double(2 * m - 1) / double(2 * p)));
+        const double ta = tau * am;
+        cf[2 * pos] = ta;
+        cf[2 * pos + 1] = 1.0 / (1.0 + ta);
+    }
 }
 
 // LIM step end (Fig. 2): est (eq. LIMest), t, tau_new (eq. LIMdt).
@@ -1080,12 +1099,13 @@ bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected) {
 
 hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStream_t s) {
     const dim3 grid(2 * k + 2, t.ninst);
+    const int kind = uses_strips(t) ? PK_STRIP : PK_TILE;
     if (t.ninst == 1)
         hipLaunchKernelGGL((k_dots_reduce<true>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst,
-                           b.dots);
+                           b.dots, kind);
     else
         hipLaunchKernelGGL((k_dots_reduce<false>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst,
-                           b.dots);
+                           b.dots, kind);
     return hipGetLastError();
 }
 
@@ -1207,9 +1227,9 @@ hipError_t launch_lim_begin(const Table& t, const DevBuffers& b, PartSeq& ps, co
 
 hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s) {
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_lim_plan<true>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder);
+        hipLaunchKernelGGL((k_lim_plan<true>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder, b.lcoef);
     else
-        hipLaunchKernelGGL((k_lim_plan<false>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder);
+        hipLaunchKernelGGL((k_lim_plan<false>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder, b.lcoef);
     return hipGetLastError();
 }
 

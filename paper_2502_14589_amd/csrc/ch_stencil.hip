@@ -16,10 +16,6 @@
 
 namespace {
 
-__device__ __forceinline__ double cheb_node(int i, int p) {
-    return cos(3.141592653589793 * double(2 * i - 1) / double(2 * p));
-}
-
 template <typename T>
 __device__ __forceinline__ T dcoef(T y, int eyre) {
     return T(3) * y * y - T(1) + T(eyre);
@@ -345,7 +341,7 @@ template <int DIM, bool SINGLE, int TAG>
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ sb2i, const Inst inst0, int ninst, const double* __restrict__ ybase,
                                                         const double* __restrict__ zbase, double* __restrict__ obase,
-                                                        const int* __restrict__ orders, int pos) {
+                                                        const double* __restrict__ coefs, int pos) {
     const Inst I = SINGLE ? inst0 : insts[sb2i[blockIdx.x]];
     Ctl* ctl = ctls + I.slot;
     if (ctl->halted || pos >= 2 * ctl->p - 1) return;
@@ -360,17 +356,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, 
     const int n = I.n, eyre = I.eyre;
     const double inv_h2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
     const double tau = ctl->tau0;
-    // Fig. 1: beta_i = cos(pi (2i - 1) / (2p)), z_1 = beta_1,
-    // a_m = lambda_max (z_1 - beta_m) / (1 + z_1).  Stage pos takes the node
-    // order[pos] (first sweep, pos < p) or order[pos - p + 1] (second sweep,
-    // without beta_1), in the order set by the plan launch.
-    const int p = ctl->p;
-    const int* order = orders + (size_t)I.slot * CH_PMAX;
-    const int m = 1 + order[pos < p ? pos : pos - p + 1];
-    const double z1 = cheb_node(1, p);
-    const double am = ctl->lam / (1.0 + z1) * (z1 - cheb_node(m, p));
-    const double ta = tau * am;
-    const double inv = 1.0 / (1.0 + ta);
+    // (tau a_m, 1 / (1 + tau a_m)) of stage position pos, set by the plan launch
+    const double* cf = coefs + ((size_t)I.slot * 2 * CH_PMAX + pos) * 2;
+    const double ta = cf[0], inv = cf[1];
     int ntx, nty;
     const int nt = num_tiles<DIM>(n, ntx, nty);
     const int lb = blockIdx.x - I.sblk0;
@@ -481,13 +469,19 @@ static hipError_t launch_matvec_t(const Table& t, const DevBuffers& b, PartSeq& 
         launch_matvec_k<DIM, TV, TY, DM_DC>(t, b, yy, k, sw, b.dots, timing, s);
     } else {
         launch_matvec_k<DIM, TV, TY, DM_ONE>(t, b, yy, k, sw, ps.out(), false, s);
-        ps.produced(true);
+        ps.produced(PK_TILE);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
                          int dots, bool store_w, hipStream_t s, bool timing) {
+    if (uses_strips(t)) {
+        if (dots == MV_DOTS_DC) return launch_matvec_strip(t, prec, b, y, k, dots, store_w, b.dots, timing, s);
+        const hipError_t e = launch_matvec_strip(t, prec, b, y, k, dots, store_w, ps.out(), false, s);
+        ps.produced(PK_STRIP);
+        return e;
+    }
     if (prec == CH_FP64)
         return t.dim == 2 ? launch_matvec_t<2, double>(t, b, ps, y, k, dots, store_w, timing, s)
                           : launch_matvec_t<3, double>(t, b, ps, y, k, dots, store_w, timing, s);
@@ -504,7 +498,7 @@ static hipError_t launch_resid_t(const Table& t, const DevBuffers& b, PartSeq& p
     else
         hipLaunchKernelGGL((k_resid<DIM, TV, false>), SARGS, y, z, write_f ? b.fcur : nullptr, static_cast<TV*>(b.V),
                        write_y32 ? b.y32 : nullptr, ps.out());
-    ps.produced(true);
+    ps.produced(PK_TILE);
     return hipGetLastError();
 }
 
@@ -524,7 +518,7 @@ static hipError_t launch_est_ee_t(const Table& t, const DevBuffers& b, PartSeq& 
         hipLaunchKernelGGL((k_est_ee<DIM, TV, true>), SARGS, y0, y1, b.fcur, static_cast<TV*>(b.V), y32, ps.out());
     else
         hipLaunchKernelGGL((k_est_ee<DIM, TV, false>), SARGS, y0, y1, b.fcur, static_cast<TV*>(b.V), y32, ps.out());
-    ps.produced(true);
+    ps.produced(PK_TILE);
     return hipGetLastError();
 }
 
@@ -539,20 +533,21 @@ hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq&
 
 hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
                             int pos, hipStream_t s, bool timing) {
+    if (uses_strips(t)) return launch_lim_stage_strip(t, b, y, z, out, pos, timing, s);
     if (t.dim == 2)
         if (timing)
-            hipLaunchKernelGGL((k_lim_stage<2, true, 1>), SARGS, y, z, out, b.lorder, pos);
+            hipLaunchKernelGGL((k_lim_stage<2, true, 1>), SARGS, y, z, out, b.lcoef, pos);
         else if (t.ninst == 1)
-            hipLaunchKernelGGL((k_lim_stage<2, true, 0>), SARGS, y, z, out, b.lorder, pos);
+            hipLaunchKernelGGL((k_lim_stage<2, true, 0>), SARGS, y, z, out, b.lcoef, pos);
         else
-            hipLaunchKernelGGL((k_lim_stage<2, false, 0>), SARGS, y, z, out, b.lorder, pos);
+            hipLaunchKernelGGL((k_lim_stage<2, false, 0>), SARGS, y, z, out, b.lcoef, pos);
     else
         if (timing)
-            hipLaunchKernelGGL((k_lim_stage<3, true, 1>), SARGS, y, z, out, b.lorder, pos);
+            hipLaunchKernelGGL((k_lim_stage<3, true, 1>), SARGS, y, z, out, b.lcoef, pos);
         else if (t.ninst == 1)
-            hipLaunchKernelGGL((k_lim_stage<3, true, 0>), SARGS, y, z, out, b.lorder, pos);
+            hipLaunchKernelGGL((k_lim_stage<3, true, 0>), SARGS, y, z, out, b.lcoef, pos);
         else
-            hipLaunchKernelGGL((k_lim_stage<3, false, 0>), SARGS, y, z, out, b.lorder, pos);
+            hipLaunchKernelGGL((k_lim_stage<3, false, 0>), SARGS, y, z, out, b.lcoef, pos);
     return hipGetLastError();
 }
 
@@ -568,6 +563,6 @@ hipError_t launch_est_lim(const Table& t, const DevBuffers& b, PartSeq& ps, cons
             hipLaunchKernelGGL((k_est_lim<3, true>), SARGS, y0, y1, ps.out());
         else
             hipLaunchKernelGGL((k_est_lim<3, false>), SARGS, y0, y1, ps.out());
-    ps.produced(true);
+    ps.produced(PK_TILE);
     return hipGetLastError();
 }

@@ -1,0 +1,496 @@
+// 2-D stencil kernels on row strips: the Jacobian matvec (with its
+// Gram-Schmidt dot products) and the LIM stage.
+//
+// Same operators as the tile kernels (Section 2, eq. IVP; Section 3.1,
+// eqs. J, A_g; Section 3.3, eq. A_g_cs):
+//     Ahat v        = A (d v + eps^2 A v),             d = 3 y^2 - 1 (+1 Eyre)
+//     ghat - Ahat z = A (c - d z - eps^2 A z),         c = 2 y^3 (+ y Eyre)
+//
+// Layout.  Each wave owns a strip of CH_STRIP_ROWS grid rows.  Lane L holds
+// VX consecutive columns of every row it touches, so one row of an operand is
+// one buffer load per lane (16 bytes for 4 FP32 or 2 FP64 values) with a
+// wave-uniform row offset: no per-element address arithmetic.  The x
+// neighbours of a lane's first and last column come from the adjacent lanes
+// by DPP whole-wave shifts; the y neighbours are the rows above and below,
+// held in registers.  The first and last CH_STRIP_HALO lanes cover the halo
+// columns only, so a wave needs nothing from other waves: there is no LDS
+// staging and no barrier until the final dot-product reduction.
+//
+// Wave w of strip workgroup b (counted from the instance's first one, XCD
+// banded) takes strips 4b' + w, 4b' + w + 4 wblk, ...; strip s covers columns
+// [(s % nsx) OW, + OW) and rows [(s / nsx) SR, + SR).
+#include "ch_common.h"
+
+namespace {
+
+constexpr int SR = CH_STRIP_ROWS;
+#ifndef CH_STRIP_RB
+#define CH_STRIP_RB 2
+#endif
+
+// Raw buffer resource over one grid row (wave-uniform base; lanes address it
+// by byte offset; an offset past the row reads zero and drops a store).  The
+// last word is the gfx9 data-format word.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+using u32x2 = unsigned __attribute__((ext_vector_type(2)));
+using u32x4 = unsigned __attribute__((ext_vector_type(4)));
+
+// VX consecutive values of type T at byte offset `bo` of row resource r.
+template <typename T, int VX>
+__device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t r, unsigned bo, T (&v)[VX]) {
+    constexpr unsigned so = 0;
+    constexpr int B = VX * (int)sizeof(T);
+    if constexpr (B == 4) {
+        v[0] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, bo, so, 0));
+    } else if constexpr (B == 8) {
+        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, bo, so, 0);
+        struct P { T e[VX]; };
+        const P p = __builtin_bit_cast(P, x);
+#pragma unroll
+        for (int e = 0; e < VX; ++e) v[e] = p.e[e];
+    } else {
+        static_assert(B == 16, "row chunk of 4, 8 or 16 bytes");
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, bo, so, 0);
+        struct P { T e[VX]; };
+        const P p = __builtin_bit_cast(P, x);
+#pragma unroll
+        for (int e = 0; e < VX; ++e) v[e] = p.e[e];
+    }
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void store_row(__amdgpu_buffer_rsrc_t r, unsigned bo, const T (&v)[VX]) {
+    constexpr unsigned so = 0;
+    constexpr int B = VX * (int)sizeof(T);
+    struct P { T e[VX]; };
+    P p;
+#pragma unroll
+    for (int e = 0; e < VX; ++e) p.e[e] = v[e];
+    if constexpr (B == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, p), r, bo, so, 0);
+    } else if constexpr (B == 8) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, p), r, bo, so, 0);
+    } else {
+        static_assert(B == 16, "row chunk of 4, 8 or 16 bytes");
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, p), r, bo, so, 0);
+    }
+}
+
+// Whole-wave DPP shifts: lane L receives lane L - 1 (from_left) or L + 1
+// (from_right); the wave's end lanes receive 0 (only halo lanes read them).
+enum { DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138 };
+
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double x) {
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Unscaled -Laplacian (4 c - (l + r) - (u + d)) at element e of row `c`,
+// with rows `up` and `dn` above and below.  The x neighbours across the
+// lane boundary arrive by DPP (xl: the left lane's last element, xr: the
+// right lane's first).
+template <typename T, int VX>
+__device__ __forceinline__ T lap5(const T (&up)[VX], const T (&c)[VX], const T (&dn)[VX], T xl, T xr, int e) {
+    const T l = e > 0 ? c[e - 1] : xl;
+    const T r = e < VX - 1 ? c[e + 1] : xr;
+    const T nb = (l + r) + (up[e] + dn[e]);
+    return T(4) * c[e] - nb;
+}
+
+template <typename T>
+__device__ __forceinline__ T dcoef(T y, int eyre) {
+    return T(3) * y * y - T(1) + T(eyre);
+}
+template <typename T>
+__device__ __forceinline__ T ccoef(T y, int eyre) {
+    return T(2) * y * y * y + (eyre ? y : T(0));
+}
+
+// Strip geometry of one wave.
+template <int VX>
+struct StripPos {
+    int r0;         // first row
+    int xl;         // lane's first column, in [0, n)
+    bool out;       // the lane's columns are outputs of this strip
+};
+
+template <int VX>
+__device__ __forceinline__ StripPos<VX> strip_pos(int s, int nsx, int n, int lane) {
+    constexpr int HL = CH_STRIP_HALO(VX), OW = strip_cols(VX);
+    StripPos<VX> p;
+    const int sx = s % nsx;
+    p.r0 = (s / nsx) * SR;
+    const int c = sx * OW + (lane - HL) * VX;     // first column, before the periodic wrap
+    int xl = c % n;
+    if (xl < 0) xl += n;
+    p.xl = xl;
+    p.out = lane >= HL && lane < 64 - HL && c < n;
+    return p;
+}
+
+// Periodic row index for r in [-n, 2n).
+__device__ __forceinline__ int wrap_row(int r, int n) { return r < 0 ? r + n : (r >= n ? r - n : r); }
+
+// Row r (periodic) of an instance's field of n x n values of type T.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t grid_row(const T* f, int r, int n) {
+    return row_rsrc(f + (size_t)wrap_row(r, n) * n, (unsigned)n * (unsigned)sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// w = Ahat u, u = vscale[k] V_k (the matvec of Fig. 3), stored in column k + 1
+// (unless store_w is 0), with the partials of its dot products:
+//   DM_ONE  <w, V_0>                                   (the first MGS dot)
+//   DM_DC   rows i < k: <u, V_i>; rows k + i: <w, V_i>;
+//           row 2k: <u, u>; row 2k + 1: <u, w>          (DCGS2)
+// Every instance uses its own strip width (VX = I.vx), so its arithmetic and
+// its partials do not depend on the other members of a batch.
+// ---------------------------------------------------------------------------
+enum DotMode { DM_ONE = 0, DM_DC = 1 };
+
+template <typename TV, int DM>
+struct MatvecArgs {
+    TV* V;
+    size_t ldv;
+    int k, store_w;
+    const TV* y;
+};
+
+// The strips of this wave; dot-product totals go to red[.][wv] (DM_DC) or
+// are returned per lane (DM_ONE).
+template <typename TV, int DM, int VX>
+__device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<TV, DM>& A, TV sc, int wv,
+                                                double (*red)[CH_STRIP_WAVES]) {
+    constexpr int NU = SR + 4, ND = SR + 2, W = CH_STRIP_WAVES;
+    const int lane = threadIdx.x & 63;
+    const int n = I.n, k = A.k;
+    const TV* U = A.V + (size_t)k * A.ldv + I.off;
+    TV* Wc = A.V + (size_t)(k + 1) * A.ldv + I.off;
+    const TV* Y = A.y + I.off;
+    const TV ih2 = TV(I.inv_h2), e2ih2 = TV(I.eps2 * I.inv_h2);
+    const int eyre = I.eyre;
+    const int nsx = (n + strip_cols(VX) - 1) / strip_cols(VX);
+    const int ns = nsx * ((n + SR - 1) / SR);
+    const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
+    const int hv = wave_sum8_holder(lane);
+    double one = 0.0;
+    for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
+        const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane);
+        const unsigned bo = (unsigned)P.xl * (unsigned)sizeof(TV);
+        TV u[NU][VX], d[ND][VX];
+#pragma unroll
+        for (int j = 0; j < NU; ++j) load_row<TV, VX>(grid_row(U, P.r0 - 2 + j, n), bo, u[j]);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) load_row<TV, VX>(grid_row(Y, P.r0 - 1 + j, n), bo, d[j]);
+#pragma unroll
+        for (int j = 0; j < NU; ++j)
+#pragma unroll
+            for (int e = 0; e < VX; ++e) u[j][e] *= sc;
+#pragma unroll
+        for (int j = 0; j < ND; ++j)
+#pragma unroll
+            for (int e = 0; e < VX; ++e) d[j][e] = dcoef(d[j][e], eyre);
+        // inner expression d u + eps^2 A u on rows r0 - 1 .. r0 + SR
+        TV q[ND][VX];
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+            const TV xl = wave_shift<DPP_WAVE_SHR1>(u[j + 1][VX - 1]), xr = wave_shift<DPP_WAVE_SHL1>(u[j + 1][0]);
+#pragma unroll
+            for (int e = 0; e < VX; ++e)
+                q[j][e] = d[j][e] * u[j + 1][e] + e2ih2 * lap5<TV, VX>(u[j], u[j + 1], u[j + 2], xl, xr, e);
+        }
+        // w = A q on rows r0 .. r0 + SR - 1
+        TV w[SR][VX];
+#pragma unroll
+        for (int i = 0; i < SR; ++i) {
+            const TV xl = wave_shift<DPP_WAVE_SHR1>(q[i + 1][VX - 1]), xr = wave_shift<DPP_WAVE_SHL1>(q[i + 1][0]);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) w[i][e] = ih2 * lap5<TV, VX>(q[i], q[i + 1], q[i + 2], xl, xr, e);
+        }
+        bool rowin[SR];
+#pragma unroll
+        for (int i = 0; i < SR; ++i) rowin[i] = P.r0 + i < n;
+        if (A.store_w && P.out) {
+#pragma unroll
+            for (int i = 0; i < SR; ++i)
+                if (rowin[i]) store_row<TV, VX>(grid_row(Wc, P.r0 + i, n), bo, w[i]);
+        }
+        // the strip's points (zero outside the grid), in FP64
+        double ud[SR][VX], wd[SR][VX];
+#pragma unroll
+        for (int i = 0; i < SR; ++i)
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const bool in = P.out && rowin[i];
+                ud[i][e] = in ? double(u[i + 2][e]) : 0.0;
+                wd[i][e] = in ? double(w[i][e]) : 0.0;
+            }
+        if (DM == DM_ONE) {
+            const TV* V0 = A.V + I.off;
+#pragma unroll
+            for (int i = 0; i < SR; ++i) {
+                TV v0[VX];
+                load_row<TV, VX>(grid_row(V0, P.r0 + i, n), bo, v0);
+#pragma unroll
+                for (int e = 0; e < VX; ++e) one += wd[i][e] * double(v0[e]);
+            }
+        } else {
+            // RB columns per block, four per wave_sum8; the loads of the
+            // next block are in flight while this one is summed
+            constexpr int RB = CH_STRIP_RB;
+            auto fetch = [&](int c0, TV (&bl)[RB][SR][VX]) {
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    if (c0 + r < k) {
+                        const TV* Q = A.V + (size_t)(c0 + r) * A.ldv + I.off;
+#pragma unroll
+                        for (int i = 0; i < SR; ++i) load_row<TV, VX>(grid_row(Q, P.r0 + i, n), bo, bl[r][i]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < SR; ++i)
+#pragma unroll
+                            for (int e = 0; e < VX; ++e) bl[r][i][e] = TV(0);
+                    }
+                }
+            };
+            TV cur[RB][SR][VX];
+            fetch(0, cur);
+            static_assert(4 % RB == 0, "blocks of 1, 2 or 4 columns");
+            for (int c0 = 0; c0 < k; c0 += 4) {
+                double a[8];
+#pragma unroll
+                for (int h = 0; h < 4 / RB; ++h) {
+                    TV nxt[RB][SR][VX];
+                    fetch(c0 + (h + 1) * RB, nxt);
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) {
+                        double su = 0.0, sw = 0.0;
+#pragma unroll
+                        for (int i = 0; i < SR; ++i)
+#pragma unroll
+                            for (int e = 0; e < VX; ++e) {
+                                const double qv = double(cur[r][i][e]);
+                                su += ud[i][e] * qv;
+                                sw += wd[i][e] * qv;
+                            }
+                        a[2 * (h * RB + r)] = su;
+                        a[2 * (h * RB + r) + 1] = sw;
+                    }
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+#pragma unroll
+                        for (int i = 0; i < SR; ++i)
+#pragma unroll
+                            for (int e = 0; e < VX; ++e) cur[r][i][e] = nxt[r][i][e];
+                }
+                const double tot = wave_sum8(a);
+                const int c = c0 + (hv >> 1);   // column of the value this lane holds
+                if (hv >= 0 && c < k) red[(hv & 1) ? k + c : c][wv] += tot;
+            }
+            double b8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < SR; ++i)
+#pragma unroll
+                for (int e = 0; e < VX; ++e) {
+                    b8[0] += ud[i][e] * ud[i][e];
+                    b8[1] += ud[i][e] * wd[i][e];
+                }
+            const double tot = wave_sum8(b8);
+            if (hv == 0 || hv == 1) red[2 * k + hv][wv] += tot;
+        }
+    }
+    return one;
+}
+
+// VX: the strip width of a single-instance launch; 0: per instance (batches).
+// TAG distinguishes the launches of the timing aid (same code, another symbol).
+template <typename TV, bool SINGLE, int DM, int TAG, int VX>
+__global__ __launch_bounds__(CH_BLOCK) void k_matvec_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                       const int* __restrict__ wb2i, const Inst inst0, int ninst,
+                                                       TV* __restrict__ V, size_t ldv, int k, int store_w,
+                                                       const TV* __restrict__ ybase, double* __restrict__ pout) {
+    constexpr int W = CH_STRIP_WAVES;
+    const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->done | ctl->halted) return;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    // DCGS2 keeps its columns normalised, except the start vector
+    const TV sc = TV(DM == DM_DC && k > 0 ? 1.0 : ctl->vscale[k]);
+    const int nrows = DM == DM_DC ? 2 * k + 2 : 1;
+    __shared__ double red[DM == DM_DC ? CH_DROWS : 1][W];
+    for (int i = lane; i < nrows; i += 64) red[i][wv] = 0.0;   // each wave clears its own column
+    const MatvecArgs<TV, DM> A{V, ldv, k, store_w, ybase};
+    double one;
+    if constexpr (VX > 0) {
+        one = matvec_strips<TV, DM, VX>(I, A, sc, wv, red);
+    } else {
+        if (I.vx == 1) {
+            one = matvec_strips<TV, DM, 1>(I, A, sc, wv, red);
+        } else if (sizeof(TV) == 8 || I.vx == 2) {
+            one = matvec_strips<TV, DM, 2>(I, A, sc, wv, red);
+        } else {
+            one = matvec_strips<TV, DM, (sizeof(TV) == 4 ? 4 : 2)>(I, A, sc, wv, red);
+        }
+    }
+    if (DM == DM_DC) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < nrows; i += CH_BLOCK) {
+            double t = red[i][0];
+#pragma unroll
+            for (int x = 1; x < W; ++x) t += red[i][x];
+            pout[(size_t)i * CH_MAXB + blockIdx.x] = t;
+        }
+    } else {
+        double x[1] = {one};
+        write_partials<1, RED_SUM>(x, pout);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LIM stage (one iteration of Fig. 1):
+//   y_next = (y^n + tau a_m z + tau (ghat - Ahat z)) / (1 + tau a_m)
+// The coefficients (tau a_m, 1 / (1 + tau a_m)) of stage position `pos` come
+// from the plan launch.
+// ---------------------------------------------------------------------------
+template <int VX>
+__device__ __forceinline__ void lim_strips(const Inst& I, const double* __restrict__ ybase,
+                                           const double* __restrict__ zbase, double* __restrict__ obase, double ta,
+                                           double inv, double tau, int wv) {
+    constexpr int NU = SR + 4, ND = SR + 2, W = CH_STRIP_WAVES;
+    const int lane = threadIdx.x & 63;
+    const int n = I.n;
+    const double* Z = zbase + I.off;
+    const double* Y = ybase + I.off;
+    double* O = obase + I.off;
+    const double inv_h2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
+    const int eyre = I.eyre;
+    const int nsx = (n + strip_cols(VX) - 1) / strip_cols(VX);
+    const int ns = nsx * ((n + SR - 1) / SR);
+    const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
+    for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
+        const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane);
+        const unsigned bo = (unsigned)P.xl * 8u;
+        double z[NU][VX], y[ND][VX];
+#pragma unroll
+        for (int j = 0; j < NU; ++j) load_row<double, VX>(grid_row(Z, P.r0 - 2 + j, n), bo, z[j]);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) load_row<double, VX>(grid_row(Y, P.r0 - 1 + j, n), bo, y[j]);
+        // inner expression d z + eps^2 A z - c on rows r0 - 1 .. r0 + SR
+        double q[ND][VX];
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+            const double xl = wave_shift<DPP_WAVE_SHR1>(z[j + 1][VX - 1]), xr = wave_shift<DPP_WAVE_SHL1>(z[j + 1][0]);
+#pragma unroll
+            for (int e = 0; e < VX; ++e)
+                q[j][e] = dcoef(y[j][e], eyre) * z[j + 1][e] + e2ih2 * lap5<double, VX>(z[j], z[j + 1], z[j + 2], xl, xr, e) -
+                          ccoef(y[j][e], eyre);
+        }
+#pragma unroll
+        for (int i = 0; i < SR; ++i) {
+            const double xl = wave_shift<DPP_WAVE_SHR1>(q[i + 1][VX - 1]), xr = wave_shift<DPP_WAVE_SHL1>(q[i + 1][0]);
+            double o[VX];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const double r = -inv_h2 * lap5<double, VX>(q[i], q[i + 1], q[i + 2], xl, xr, e);
+                o[e] = (y[i + 1][e] + ta * z[i + 2][e] + tau * r) * inv;
+            }
+            if (P.out && P.r0 + i < n) store_row<double, VX>(grid_row(O, P.r0 + i, n), bo, o);
+        }
+    }
+}
+
+template <bool SINGLE, int TAG, int VX>
+__global__ __launch_bounds__(CH_BLOCK) void k_lim_stage_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                          const int* __restrict__ wb2i, const Inst inst0, int ninst,
+                                                          const double* __restrict__ ybase,
+                                                          const double* __restrict__ zbase, double* __restrict__ obase,
+                                                          const double* __restrict__ coefs, int pos) {
+    const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->halted || pos >= 2 * ctl->p - 1) return;
+    const double* cf = coefs + ((size_t)I.slot * 2 * CH_PMAX + pos) * 2;
+    const double ta = cf[0], inv = cf[1], tau = ctl->tau0;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if constexpr (VX > 0) {
+        lim_strips<VX>(I, ybase, zbase, obase, ta, inv, tau, wv);
+    } else {
+        if (I.vx == 1) lim_strips<1>(I, ybase, zbase, obase, ta, inv, tau, wv);
+        else lim_strips<2>(I, ybase, zbase, obase, ta, inv, tau, wv);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+#define WARGS dim3(t.wgrid), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.wb2i, t.hinst[0], t.ninst
+
+template <typename TV, int DM, bool TIMING, int VX>
+static void launch_matvec_one(const Table& t, const DevBuffers& b, const TV* y, int k, int store_w, double* pout,
+                              hipStream_t s) {
+    hipLaunchKernelGGL((k_matvec_s<TV, true, DM, TIMING ? 1 : 0, VX>), WARGS, static_cast<TV*>(b.V), b.ldv, k,
+                       store_w, y, pout);
+}
+
+template <typename TV, int DM, bool TIMING>
+static void launch_matvec_single(const Table& t, const DevBuffers& b, const TV* y, int k, int store_w, double* pout,
+                                 hipStream_t s) {
+    const int vx = t.hinst[0].vx;
+    if constexpr (sizeof(TV) == 4) {
+        if (vx >= 4) return launch_matvec_one<TV, DM, TIMING, 4>(t, b, y, k, store_w, pout, s);
+    }
+    if (vx >= 2) launch_matvec_one<TV, DM, TIMING, 2>(t, b, y, k, store_w, pout, s);
+    else launch_matvec_one<TV, DM, TIMING, 1>(t, b, y, k, store_w, pout, s);
+}
+
+template <typename TV, int DM>
+static void launch_matvec_s(const Table& t, const DevBuffers& b, const TV* y, int k, int store_w, double* pout,
+                            bool timing, hipStream_t s) {
+    if (timing)
+        launch_matvec_single<TV, DM, true>(t, b, y, k, store_w, pout, s);
+    else if (t.ninst == 1)
+        launch_matvec_single<TV, DM, false>(t, b, y, k, store_w, pout, s);
+    else
+        hipLaunchKernelGGL((k_matvec_s<TV, false, DM, 0, 0>), WARGS, static_cast<TV*>(b.V), b.ldv, k, store_w, y,
+                           pout);
+}
+
+hipError_t launch_matvec_strip(const Table& t, int prec, const DevBuffers& b, const double* y, int k, int dots,
+                               bool store_w, double* pout, bool timing, hipStream_t s) {
+    const int sw = store_w ? 1 : 0;
+    if (prec == CH_FP64) {
+        if (dots == MV_DOTS_DC) launch_matvec_s<double, DM_DC>(t, b, y, k, sw, pout, timing, s);
+        else launch_matvec_s<double, DM_ONE>(t, b, y, k, sw, pout, timing, s);
+    } else {
+        if (dots == MV_DOTS_DC) launch_matvec_s<float, DM_DC>(t, b, b.y32, k, sw, pout, timing, s);
+        else launch_matvec_s<float, DM_ONE>(t, b, b.y32, k, sw, pout, timing, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
+                                  int pos, bool timing, hipStream_t s) {
+    const bool two = t.hinst[0].vx >= 2;
+    if (timing) {
+        if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 1, 2>), WARGS, y, z, out, b.lcoef, pos);
+        else hipLaunchKernelGGL((k_lim_stage_s<true, 1, 1>), WARGS, y, z, out, b.lcoef, pos);
+    } else if (t.ninst == 1) {
+        if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 0, 2>), WARGS, y, z, out, b.lcoef, pos);
+        else hipLaunchKernelGGL((k_lim_stage_s<true, 0, 1>), WARGS, y, z, out, b.lcoef, pos);
+    } else {
+        hipLaunchKernelGGL((k_lim_stage_s<false, 0, 0>), WARGS, y, z, out, b.lcoef, pos);
+    }
+    return hipGetLastError();
+}

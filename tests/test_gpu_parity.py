@@ -102,6 +102,34 @@ def test_ee_adaptive_run_parity(ctx):
     assert rel(host(yg), y_ref) <= TOL_FP64
 
 
+def test_mgs_option_parity(ctx):
+    """The literal Fig. 3 orthogonalisation (CH_ORTH_MGS): adaptive run and a
+    traced 3-D step against the oracle; FP32-mixed MGS against FP32 DCGS2."""
+    say("MGS option: EE adaptive 48^2, traced 3-D step, FP32")
+    po, pg = probs(2, 48, 0.03)
+    y0 = uniform_field(48, 2, 0.1, 0.05, seed=303)
+    y_ref, rec_ref = O.ee_adaptive(y0, po, 1e-3, math.inf, 1e-4, 10, max_steps=12)
+    yg = dev(y0)
+    st, recs = ctx.run_ee(pg, yg, 1e-3, max_steps=12, m_max=10, tol=1e-4, records=True, orth=ch.CH_ORTH_MGS)
+    assert [r["j"] for r in recs] == rec_ref.js
+    np.testing.assert_allclose([r["tau"] for r in recs], rec_ref.taus, rtol=1e-10)
+    assert rel(host(yg), y_ref) <= TOL_FP64
+    po3, pg3 = probs(3, 10, 0.05)
+    y3 = uniform_field(10, 3, 0.1, 0.05, seed=304)
+    y3_ref, tau_ref, info = O.ee_step(y3, po3, 1e-2, 1e-7, 6)
+    assert not info.converged and tau_ref < 1e-2
+    yg3 = dev(y3)
+    rec = ctx.step_ee(pg3, yg3, 1e-2, m_max=6, tol_phi_fixed=1e-7, orth=ch.CH_ORTH_MGS)
+    assert rec["j"] == 6 and rec["traced"] == 1
+    assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12)
+    assert rel(host(yg3), y3_ref) <= TOL_FP64
+    p32 = ch.Problem(2, 48, 0.03, False, ch.CH_FP32_MIXED)
+    a, b = dev(y0), dev(y0)
+    ctx.run_ee(p32, a, 1e-6, max_steps=5, m_max=10, tol_phi_fixed=1e-8, constant_step=True, orth=ch.CH_ORTH_MGS)
+    ctx.run_ee(p32, b, 1e-6, max_steps=5, m_max=10, tol_phi_fixed=1e-8, constant_step=True)
+    assert rel(host(a), host(b)) <= 1e-6
+
+
 def test_ee_adaptive_to_final_time(ctx):
     say("EE adaptive run to T")
     po, pg = probs(2, 32, 0.05)
