@@ -212,12 +212,15 @@ void inst_blocks(int dim, int n, long long N, int* sblk, int* cblk) {
 // 2-D strip workgroups of one instance (larger grids loop over strips).
 int strip_blocks(int n, int vx) {
     const long long waves = strip_count(n, vx);
-    return (int)std::min<long long>((waves + CH_STRIP_WAVES - 1) / CH_STRIP_WAVES, CH_SBLK_MAX);
+    return (int)std::min<long long>((waves + CH_STRIP_WAVES - 1) / CH_STRIP_WAVES, CH_WBLK_MAX);
 }
 
 // Columns per lane of the 2-D strip kernels for one grid.
+#ifndef CH_STRIP_VX32
+#define CH_STRIP_VX32 4
+#endif
 int strip_vx(int n, int prec) {
-    int vx = prec == CH_FP64 ? 2 : 4;
+    int vx = prec == CH_FP64 ? 2 : CH_STRIP_VX32;
     while (n % vx) vx >>= 1;
     return vx;
 }

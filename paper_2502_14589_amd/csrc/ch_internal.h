@@ -10,8 +10,13 @@
 #define CH_LDH (CH_MMAX + 1)     // leading dimension of the Hessenberg matrix
 #define CH_MAXB 32768            // most workgroups of a reducing launch (partials per reduction)
 #define CH_SBLK_MAX 2048         // most stencil workgroups per instance (larger grids loop over tiles);
+#ifndef CH_WBLK_MAX
+#define CH_WBLK_MAX 2048         // most strip workgroups per instance (larger grids loop over strips)
+#endif
                                  // <= 8 * CH_BLOCK partials per instance (sum_partials)
+#ifndef CH_CBLK_MAX
 #define CH_CBLK_MAX 512          // most streaming workgroups per instance
+#endif
 #define CH_NRED 4                // most sums reduced by one launch
 #define CH_BLOCK 256             // threads per workgroup of the streaming and stencil kernels
 #define CH_DROWS (2 * CH_MMAX + 2)   // dot-product rows of one DCGS2 iteration
@@ -81,7 +86,7 @@ struct Inst {
 // vx: 16-byte rows of the basis type (4 FP32 or 2 FP64 values), halved until
 // it divides n.
 #ifndef CH_STRIP_ROWS
-#define CH_STRIP_ROWS 4
+#define CH_STRIP_ROWS 2
 #endif
 static_assert(CH_STRIP_ROWS <= 4, "strip rows: the periodic row wrap assumes n > CH_STRIP_ROWS (n >= 5)");
 #define CH_STRIP_WAVES (CH_BLOCK / 64)
@@ -157,6 +162,8 @@ hipError_t launch_matvec_strip(const Table& t, int prec, const DevBuffers& b, co
                                bool store_w, double* pout, bool timing, hipStream_t s);
 hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
                                   int pos, bool timing, hipStream_t s);
+hipError_t launch_est_ee_strip(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
+                               double* pout, hipStream_t s);
 hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s,
                             bool timing = false);
 hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStream_t s);

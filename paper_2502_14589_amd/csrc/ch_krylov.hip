@@ -111,6 +111,13 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctls, const 
 // buffers, so the publishing workgroup never overwrites what another still
 // reads.  At j = m_max only column j - 1 is formed (FIN, one workgroup).
 // ---------------------------------------------------------------------------
+#ifndef CH_DCU_Q
+#define CH_DCU_Q 2
+#endif
+#ifndef CH_DCU_RB
+#define CH_DCU_RB 2
+#endif
+
 struct DcCoef {
     double s[CH_MMAX + 1], t[CH_MMAX + 1], g[CH_MMAX + 1], hf[CH_MMAX + 1];
     double ca[CH_MMAX + 1], cb[CH_MMAX + 1];
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     Ctl* ctl = ctls + I.slot;
     if (ctl->done | ctl->halted) return;
     using VT = typename Vec16<TV>::type;
-    constexpr int VW = Vec16<TV>::W, Q = 2, RB = 4;
+    constexpr int VW = Vec16<TV>::W, Q = CH_DCU_Q, RB = CH_DCU_RB;
     __shared__ DcCoef C;
     const TV* Vi = V + I.off;
     TV* U = V + (size_t)j * ldv + I.off;
@@ -201,7 +208,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     const long long lt = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
     long long qq[Q];
     bool ok[Q];
-    VT uv[Q], wv[Q], v[RB][Q];
+    VT uv[Q], wv[Q];
     auto load_uw = [&](long long q0) {
 #pragma unroll
         for (int u = 0; u < Q; ++u) {
@@ -213,7 +220,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
             }
         }
     };
-    auto load_cols = [&](int i0) {
+    auto load_cols = [&](int i0, VT (&v)[RB][Q]) {
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -228,9 +235,11 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
             }
     };
     // the first vectors and basis columns are requested before the
-    // coefficients are formed, so the loads overlap that latency
+    // coefficients are formed, so the loads overlap that latency; later
+    // blocks of RB columns are requested one block ahead
+    VT cur[RB][Q];
     load_uw(lt);
-    load_cols(0);
+    load_cols(0, cur);
     dc_prepare(C, ctl, j, false, TAG == 0 && (int)blockIdx.x == I.cblk0);   // timing launches publish nothing
     const double* ca = C.ca;
     const double* cb = C.cb;
@@ -238,7 +247,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     for (long long q0 = lt; q0 < NV; q0 += per * Q) {
         if (q0 != lt) {
             load_uw(q0);
-            load_cols(0);
+            load_cols(0, cur);
         }
         double xq[Q][VW], xu[Q][VW];
 #pragma unroll
@@ -252,14 +261,15 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
             }
         }
         for (int i0 = 0; i0 < j; i0 += RB) {
-            if (i0 > 0) load_cols(i0);
+            VT nxt[RB][Q];
+            load_cols(i0 + RB, nxt);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const double a = i0 + r < j ? ca[i0 + r] : 0.0;
                 const double c = i0 + r < j ? cb[i0 + r] : 0.0;
 #pragma unroll
                 for (int u = 0; u < Q; ++u) {
-                    const TV* ve = reinterpret_cast<const TV*>(&v[r][u]);
+                    const TV* ve = reinterpret_cast<const TV*>(&cur[r][u]);
 #pragma unroll
                     for (int e = 0; e < VW; ++e) {
                         xq[u][e] += a * double(ve[e]);
@@ -267,6 +277,10 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
                     }
                 }
             }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int u = 0; u < Q; ++u) cur[r][u] = nxt[r][u];
         }
 #pragma unroll
         for (int u = 0; u < Q; ++u) {
@@ -631,10 +645,29 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
         return;
     }
     // ---- refine the crossing inside [lo, hi] ----
-    double s;
-    if (rlo > 0.0 && rhi > rlo) s = lo * exp2(log2(tol / rlo) / log2(rhi / rlo));
-    else s = 0.5 * (lo + hi);
+    // First guess: log resnorm against log2(s / lo) through the chain's
+    // values at lo / 2, lo and hi (quadratic), else through lo and hi.
+    double s = -1.0;
+    if (rlo > 0.0 && rhi > rlo) {
+        const double y0 = log(rlo), y1 = log(rhi), yt = log(tol);
+        double x = (yt - y0) / (y1 - y0);
+        const int kl = (int)lrint(log2(tau0 / lo));   // lo = tau0 2^-kl
+        if (kl + 1 <= kmax && S.lvl[kl + 1] > 0.0 && S.lvl[kl + 1] < rlo) {
+            const double ym = log(S.lvl[kl + 1]);
+            const double bq = 0.5 * (y1 - ym), cq = 0.5 * (y1 + ym) - y0;
+            const double disc = bq * bq - 4.0 * cq * (y0 - yt);
+            if (fabs(cq) > 1e-12 * fabs(bq) && disc >= 0.0) {
+                const double xq = (-bq + sqrt(disc)) / (2.0 * cq);
+                if (xq > 0.0 && xq < 1.0) x = xq;
+            }
+        }
+        s = lo * exp2(x);
+    }
     if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
+    // Newton on log resnorm against log s; it converges quadratically, so a
+    // step below 1e-7 s after one below 1e-3 s leaves the next iterate within
+    // about 1e-14 of the crossing.
+    double step_prev = 1.0;
     for (int it = 0; it < 60; ++it) {
         int nq;
         const double* Es = expm_aug(S, H, j, s, hnext, &nq);
@@ -655,10 +688,12 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
         double sn = -1.0;
         if (r > 0.0 && dr > 0.0) sn = s * exp(-log(r / tol) * r / (s * dr));
         if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
-        if (fabs(sn - s) <= 1e-14 * s) {
+        const double step = fabs(sn - s) / s;
+        if (step <= 1e-14 || (step <= 1e-7 && step_prev <= 1e-3)) {
             s = sn;
             break;
         }
+        step_prev = step;
         s = sn;
     }
     int nq;

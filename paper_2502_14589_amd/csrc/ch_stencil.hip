@@ -524,6 +524,11 @@ static hipError_t launch_est_ee_t(const Table& t, const DevBuffers& b, PartSeq& 
 
 hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y0,
                          const double* y1, hipStream_t s) {
+    if (uses_strips(t)) {
+        const hipError_t e = launch_est_ee_strip(t, prec, b, y0, y1, ps.out(), s);
+        ps.produced(PK_STRIP);
+        return e;
+    }
     if (prec == CH_FP64)
         return t.dim == 2 ? launch_est_ee_t<2, double>(t, b, ps, y0, y1, nullptr, s)
                           : launch_est_ee_t<3, double>(t, b, ps, y0, y1, nullptr, s);

@@ -25,7 +25,7 @@ namespace {
 
 constexpr int SR = CH_STRIP_ROWS;
 #ifndef CH_STRIP_RB
-#define CH_STRIP_RB 2
+#define CH_STRIP_RB 1
 #endif
 
 // Raw buffer resource over one grid row (wave-uniform base; lanes address it
@@ -51,13 +51,23 @@ __device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t r, unsigned bo, 
         const P p = __builtin_bit_cast(P, x);
 #pragma unroll
         for (int e = 0; e < VX; ++e) v[e] = p.e[e];
-    } else {
-        static_assert(B == 16, "row chunk of 4, 8 or 16 bytes");
+    } else if constexpr (B == 16) {
         const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, bo, so, 0);
         struct P { T e[VX]; };
         const P p = __builtin_bit_cast(P, x);
 #pragma unroll
         for (int e = 0; e < VX; ++e) v[e] = p.e[e];
+    } else {
+        static_assert(B == 32, "row chunk of 4, 8, 16 or 32 bytes");
+        constexpr int H = VX / 2;
+        T a[H], c[H];
+        load_row<T, H>(r, bo, a);
+        load_row<T, H>(r, bo + 16u, c);
+#pragma unroll
+        for (int e = 0; e < H; ++e) {
+            v[e] = a[e];
+            v[H + e] = c[e];
+        }
     }
 }
 
@@ -73,9 +83,19 @@ __device__ __forceinline__ void store_row(__amdgpu_buffer_rsrc_t r, unsigned bo,
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, p), r, bo, so, 0);
     } else if constexpr (B == 8) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, p), r, bo, so, 0);
-    } else {
-        static_assert(B == 16, "row chunk of 4, 8 or 16 bytes");
+    } else if constexpr (B == 16) {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, p), r, bo, so, 0);
+    } else {
+        static_assert(B == 32, "row chunk of 4, 8, 16 or 32 bytes");
+        constexpr int H = VX / 2;
+        T a[H], c[H];
+#pragma unroll
+        for (int e = 0; e < H; ++e) {
+            a[e] = v[e];
+            c[e] = v[H + e];
+        }
+        store_row<T, H>(r, bo, a);
+        store_row<T, H>(r, bo + 16u, c);
     }
 }
 
@@ -122,7 +142,12 @@ struct StripPos {
     int r0;         // first row
     int xl;         // lane's first column, in [0, n)
     bool out;       // the lane's columns are outputs of this strip
+    bool need;      // ... or the halo of one
 };
+
+// A lane offset past every row: the load returns zeros without a memory
+// access (lanes that neither own nor border an output column).
+constexpr unsigned OFF_ROW = 0x80000000u;
 
 template <int VX>
 __device__ __forceinline__ StripPos<VX> strip_pos(int s, int nsx, int n, int lane) {
@@ -135,6 +160,7 @@ __device__ __forceinline__ StripPos<VX> strip_pos(int s, int nsx, int n, int lan
     if (xl < 0) xl += n;
     p.xl = xl;
     p.out = lane >= HL && lane < 64 - HL && c < n;
+    p.need = c < n + HL * VX;
     return p;
 }
 
@@ -187,11 +213,13 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
     for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
         const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane);
         const unsigned bo = (unsigned)P.xl * (unsigned)sizeof(TV);
+        const unsigned bs = P.need ? bo : OFF_ROW;   // stencil operands
+        const unsigned bd = P.out ? bo : OFF_ROW;    // basis columns of the dot products
         TV u[NU][VX], d[ND][VX];
 #pragma unroll
-        for (int j = 0; j < NU; ++j) load_row<TV, VX>(grid_row(U, P.r0 - 2 + j, n), bo, u[j]);
+        for (int j = 0; j < NU; ++j) load_row<TV, VX>(grid_row(U, P.r0 - 2 + j, n), bs, u[j]);
 #pragma unroll
-        for (int j = 0; j < ND; ++j) load_row<TV, VX>(grid_row(Y, P.r0 - 1 + j, n), bo, d[j]);
+        for (int j = 0; j < ND; ++j) load_row<TV, VX>(grid_row(Y, P.r0 - 1 + j, n), bs, d[j]);
 #pragma unroll
         for (int j = 0; j < NU; ++j)
 #pragma unroll
@@ -240,7 +268,7 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
 #pragma unroll
             for (int i = 0; i < SR; ++i) {
                 TV v0[VX];
-                load_row<TV, VX>(grid_row(V0, P.r0 + i, n), bo, v0);
+                load_row<TV, VX>(grid_row(V0, P.r0 + i, n), bd, v0);
 #pragma unroll
                 for (int e = 0; e < VX; ++e) one += wd[i][e] * double(v0[e]);
             }
@@ -254,7 +282,7 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
                     if (c0 + r < k) {
                         const TV* Q = A.V + (size_t)(c0 + r) * A.ldv + I.off;
 #pragma unroll
-                        for (int i = 0; i < SR; ++i) load_row<TV, VX>(grid_row(Q, P.r0 + i, n), bo, bl[r][i]);
+                        for (int i = 0; i < SR; ++i) load_row<TV, VX>(grid_row(Q, P.r0 + i, n), bd, bl[r][i]);
                     } else {
 #pragma unroll
                         for (int i = 0; i < SR; ++i)
@@ -381,11 +409,12 @@ __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restri
     for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
         const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane);
         const unsigned bo = (unsigned)P.xl * 8u;
+        const unsigned bs = P.need ? bo : OFF_ROW;
         double z[NU][VX], y[ND][VX];
 #pragma unroll
-        for (int j = 0; j < NU; ++j) load_row<double, VX>(grid_row(Z, P.r0 - 2 + j, n), bo, z[j]);
+        for (int j = 0; j < NU; ++j) load_row<double, VX>(grid_row(Z, P.r0 - 2 + j, n), bs, z[j]);
 #pragma unroll
-        for (int j = 0; j < ND; ++j) load_row<double, VX>(grid_row(Y, P.r0 - 1 + j, n), bo, y[j]);
+        for (int j = 0; j < ND; ++j) load_row<double, VX>(grid_row(Y, P.r0 - 1 + j, n), bs, y[j]);
         // inner expression d z + eps^2 A z - c on rows r0 - 1 .. r0 + SR
         double q[ND][VX];
 #pragma unroll
@@ -428,6 +457,111 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage_s(Ctl* __restrict__ ctls
         if (I.vx == 1) lim_strips<1>(I, ybase, zbase, obase, ta, inv, tau, wv);
         else lim_strips<2>(I, ybase, zbase, obase, ta, inv, tau, wv);
     }
+}
+
+// ---------------------------------------------------------------------------
+// EE2 estimate and next start vector (Fig. 4; eq. LIMest):
+//   f1 = f(y^{n+1});  y_PC = y^n + tau/2 (f(y^n) + f1)  (eq. LIMest, since
+//   f(y) = -A (F'(y) + eps^2 A y));  est = ||y^{n+1} - y_PC|| / ||y_PC||.
+// f1 becomes the next step's f(y^n) and start vector; ||A c(y^{n+1})|| the next
+// ||ghat||.  Lane partials of the four sums are returned in acc.
+// ---------------------------------------------------------------------------
+template <typename TV, int VX>
+__device__ __forceinline__ void est_strips(const Inst& I, const double* __restrict__ y0base,
+                                           const double* __restrict__ y1base, double* __restrict__ fbase,
+                                           TV* __restrict__ V0base, float* __restrict__ y32base, double half_tau,
+                                           int wv, double (&acc)[4]) {
+    constexpr int NU = SR + 4, ND = SR + 2, W = CH_STRIP_WAVES;
+    const int lane = threadIdx.x & 63;
+    const int n = I.n;
+    const double* Y0 = y0base + I.off;
+    const double* Y1 = y1base + I.off;
+    double* F = fbase + I.off;
+    TV* V0 = V0base + I.off;
+    float* Y32 = y32base ? y32base + I.off : nullptr;
+    const double inv_h2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
+    const int eyre = I.eyre;
+    const int nsx = (n + strip_cols(VX) - 1) / strip_cols(VX);
+    const int ns = nsx * ((n + SR - 1) / SR);
+    const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
+    for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
+        const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane);
+        const unsigned bo = (unsigned)P.xl * 8u;
+        const unsigned bs = P.need ? bo : OFF_ROW, bd = P.out ? bo : OFF_ROW;
+        double y1[NU][VX], y0[SR][VX], f0[SR][VX];
+#pragma unroll
+        for (int j = 0; j < NU; ++j) load_row<double, VX>(grid_row(Y1, P.r0 - 2 + j, n), bs, y1[j]);
+#pragma unroll
+        for (int i = 0; i < SR; ++i) {
+            load_row<double, VX>(grid_row(Y0, P.r0 + i, n), bd, y0[i]);
+            load_row<double, VX>(grid_row(F, P.r0 + i, n), bd, f0[i]);
+        }
+        // inner expressions on rows r0 - 1 .. r0 + SR: F'(y) + eps^2 A y and c(y)
+        double q[ND][VX], c[ND][VX];
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+            const double xl = wave_shift<DPP_WAVE_SHR1>(y1[j + 1][VX - 1]), xr = wave_shift<DPP_WAVE_SHL1>(y1[j + 1][0]);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const double v = y1[j + 1][e];
+                q[j][e] = v * (v * v - 1.0) + e2ih2 * lap5<double, VX>(y1[j], y1[j + 1], y1[j + 2], xl, xr, e);
+                c[j][e] = ccoef(v, eyre);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < SR; ++i) {
+            const double ql = wave_shift<DPP_WAVE_SHR1>(q[i + 1][VX - 1]), qr = wave_shift<DPP_WAVE_SHL1>(q[i + 1][0]);
+            const double cl = wave_shift<DPP_WAVE_SHR1>(c[i + 1][VX - 1]), cr = wave_shift<DPP_WAVE_SHL1>(c[i + 1][0]);
+            const bool in = P.out && P.r0 + i < n;
+            double f1[VX];
+            TV fv[VX];
+            float yf[VX];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                f1[e] = -inv_h2 * lap5<double, VX>(q[i], q[i + 1], q[i + 2], ql, qr, e);
+                const double g1 = inv_h2 * lap5<double, VX>(c[i], c[i + 1], c[i + 2], cl, cr, e);
+                const double ypc = y0[i][e] + half_tau * (f0[i][e] + f1[e]);
+                const double yv = y1[i + 2][e];
+                const double er = yv - ypc;
+                if (in) {
+                    acc[0] += er * er;
+                    acc[1] += ypc * ypc;
+                    acc[2] += f1[e] * f1[e];
+                    acc[3] += g1 * g1;
+                }
+                fv[e] = TV(f1[e]);
+                yf[e] = float(yv);
+            }
+            if (in) {
+                store_row<double, VX>(grid_row(F, P.r0 + i, n), bo, f1);
+                store_row<TV, VX>(grid_row(V0, P.r0 + i, n), (unsigned)P.xl * (unsigned)sizeof(TV), fv);
+                if (Y32) store_row<float, VX>(grid_row(Y32, P.r0 + i, n), (unsigned)P.xl * 4u, yf);
+            }
+        }
+    }
+}
+
+template <typename TV, bool SINGLE, int VX>
+__global__ __launch_bounds__(CH_BLOCK) void k_est_ee_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                       const int* __restrict__ wb2i, const Inst inst0, int ninst,
+                                                       const double* __restrict__ y0base,
+                                                       const double* __restrict__ y1base, double* __restrict__ fbase,
+                                                       TV* __restrict__ V0base, float* __restrict__ y32base,
+                                                       double* __restrict__ pout) {
+    const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->halted) return;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const double half_tau = 0.5 * (ctl->mode == MODE_EE ? ctl->tau_acc : ctl->tau_step);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (VX > 0) {
+        est_strips<TV, VX>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+    } else {
+        if (I.vx == 1) est_strips<TV, 1>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+        else if (sizeof(TV) == 8 || I.vx == 2) est_strips<TV, 2>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+        else est_strips<TV, (sizeof(TV) == 4 ? 4 : 2)>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+    }
+    write_partials<4, RED_SUM>(acc, pout);
 }
 
 }  // namespace
@@ -492,5 +626,31 @@ hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const dou
     } else {
         hipLaunchKernelGGL((k_lim_stage_s<false, 0, 0>), WARGS, y, z, out, b.lcoef, pos);
     }
+    return hipGetLastError();
+}
+
+template <typename TV>
+static void launch_est_ee_s(const Table& t, const DevBuffers& b, const double* y0, const double* y1, float* y32,
+                            double* pout, hipStream_t s) {
+    TV* V0 = static_cast<TV*>(b.V);
+    if (t.ninst > 1) {
+        hipLaunchKernelGGL((k_est_ee_s<TV, false, 0>), WARGS, y0, y1, b.fcur, V0, y32, pout);
+        return;
+    }
+    const int vx = t.hinst[0].vx;
+    if constexpr (sizeof(TV) == 4) {
+        if (vx >= 4) {
+            hipLaunchKernelGGL((k_est_ee_s<TV, true, 4>), WARGS, y0, y1, b.fcur, V0, y32, pout);
+            return;
+        }
+    }
+    if (vx >= 2) hipLaunchKernelGGL((k_est_ee_s<TV, true, 2>), WARGS, y0, y1, b.fcur, V0, y32, pout);
+    else hipLaunchKernelGGL((k_est_ee_s<TV, true, 1>), WARGS, y0, y1, b.fcur, V0, y32, pout);
+}
+
+hipError_t launch_est_ee_strip(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
+                               double* pout, hipStream_t s) {
+    if (prec == CH_FP64) launch_est_ee_s<double>(t, b, y0, y1, nullptr, pout, s);
+    else launch_est_ee_s<float>(t, b, y0, y1, b.y32, pout, s);
     return hipGetLastError();
 }
