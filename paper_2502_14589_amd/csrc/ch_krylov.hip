@@ -409,26 +409,46 @@ struct NoEpi {
     __device__ double operator()(int, int) const { return 0.0; }
 };
 
-template <typename Epi = NoEpi>
-__device__ void mm(double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B, int np,
-                   Epi epi = Epi()) {
+// NT = np / 16 tiles per direction.  The K loop is unrolled: every A and B
+// operand of a tile is read from LDS before the first product, and even and
+// odd K steps accumulate separately (two independent chains).
+template <int NT, typename Epi = NoEpi>
+__device__ void mm_t(double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B,
+                     Epi epi = Epi()) {
+    constexpr int NP = 16 * NT, KS = NP / 4;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int T = np >> 4;
     const int li = lane & 15, lk = lane >> 4;
-    for (int t = wid; t < T * T; t += CH_BLOCK / 64) {
-        const int ti = t / T, tj = t - ti * T;
+    for (int t = wid; t < NT * NT; t += CH_BLOCK / 64) {
+        const int ti = t / NT, tj = t - ti * NT;
         const double* a = A + (16 * ti + li) * PLD + lk;
         const double* b = B + lk * PLD + 16 * tj + li;
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int kk = 0; kk < np; kk += 4)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk * PLD], acc, 0, 0, 0);
+        double av[KS], bv[KS];
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            av[q] = a[4 * q];
+            bv[q] = b[4 * q * PLD];
+        }
+        dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < KS; q += 2) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc0, 0, 0, 0);
+            if (q + 1 < KS) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 1], bv[q + 1], acc1, 0, 0, 0);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = 16 * ti + 4 * v + lk, c = 16 * tj + li;
-            C[r * PLD + c] = acc[v] + epi(r, c);
+            C[r * PLD + c] = (acc0[v] + acc1[v]) + epi(r, c);
         }
     }
     __syncthreads();
+}
+
+template <typename Epi = NoEpi>
+__device__ void mm(double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B, int np,
+                   Epi epi = Epi()) {
+    if (np <= 16) mm_t<1>(C, A, B, epi);
+    else if (np <= 32) mm_t<2>(C, A, B, epi);
+    else mm_t<3>(C, A, B, epi);
 }
 
 // B_i(r, c) = sum_{q=0..4} X^q(r, c) / (5i + q)!
