@@ -45,9 +45,9 @@ LIM_TAU0 = 2.5e-7
 C3_SIDE, C3_EPS, C3_TOL, C3_M, C3_SEED = 256, 0.02, 1e-6, 40, 2
 HBM_PEAK_GBPS = 8000.0
 METRIC = "CH time steps/s and HBM GB/s at 1024² (EE Krylov), FP32/batched vs FP64 plain"
-DOMINANT = "k_matvec (DCGS2 Jacobian matvec with its 2j+2 basis dot products)"
+DOMINANT = "k_matvec_s (2-D row-strip DCGS2 Jacobian matvec with its 2j+2 basis dot products)"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dc_matvec_1024sq_fp32_traffic.md")
-KERNEL_SOURCES = ("ch_stencil.hip", "ch_common.h", "ch_internal.h")
+KERNEL_SOURCES = ("ch_strip.hip", "ch_common.h", "ch_internal.h")
 
 
 def ee_step_bytes(j: int, m_max: int, w: int, N: int, fp32: bool) -> float:

@@ -249,7 +249,8 @@ enum ch_kernel {
     /* the two CH_ORTH_DCGS2 passes of Arnoldi iteration j = m_max - 1: */
     CH_KERNEL_DC_MATVEC = 3,   /* matvec Ahat u_j with the 2j + 2 dot products against the basis */
     CH_KERNEL_DC_UPDATE = 4,   /* q_j and u_{j+1} from one pass over the basis */
-    CH_KERNEL_LIM_STAGE = 5    /* one LIM Chebyshev stage */
+    CH_KERNEL_LIM_STAGE = 5,   /* one LIM Chebyshev stage */
+    CH_KERNEL_DC_ITER = 6      /* one whole DCGS2 iteration: matvec, dot totals, update */
 };
 
 /*
@@ -258,7 +259,7 @@ enum ch_kernel {
  * the workspace of an earlier run on this problem (ch_run_ee with Krylov
  * dimension >= m_max; ch_run_lim for CH_KERNEL_LIM_STAGE).  iters[i] is the
  * Arnoldi iteration of launch i: CH_KERNEL_DC_MATVEC 0..m_max (w stored below
- * m_max), CH_KERNEL_DC_UPDATE 0..m_max-1, CH_KERNEL_MGS (pass 1 of the
+ * m_max), CH_KERNEL_DC_UPDATE and CH_KERNEL_DC_ITER 0..m_max-1, CH_KERNEL_MGS (pass 1 of the
  * iteration) 1..m_max-1, CH_KERNEL_MATVEC 0..m_max-1, CH_KERNEL_PHI (a
  * not-converged test of that dimension) 1..min(m_max-1, last step's j);
  * ignored (may be NULL) for CH_KERNEL_LIM_STAGE.  The DCGS2 and LIM kernels

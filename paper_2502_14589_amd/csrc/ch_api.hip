@@ -948,7 +948,7 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, c
     Shape sh;
     int rc = check_problem(prob, &sh);
     if (rc) return rc;
-    if (m_max < 1 || m_max > CH_MMAX || kernel < CH_KERNEL_MGS || kernel > CH_KERNEL_LIM_STAGE) return CH_EINVAL;
+    if (m_max < 1 || m_max > CH_MMAX || kernel < CH_KERNEL_MGS || kernel > CH_KERNEL_DC_ITER) return CH_EINVAL;
     const bool lim = kernel == CH_KERNEL_LIM_STAGE;
     const int prec = lim ? CH_FP64 : prob->prec;
     const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
@@ -1011,13 +1011,20 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, c
                 bytes += 4.0 * esz * N;   // read v_k, the state, v_0; write w
                 return launch_matvec(t, prec, b, ps, y, k, MV_DOTS_ONE, true, ctx->stream);
             case CH_KERNEL_PHI:
-                return launch_phi(t, b, ps, k, true, ctx->stream);
+                return launch_phi(t, b, ps, k, k, true, ctx->stream);
             case CH_KERNEL_DC_MATVEC:   // read u_k, the state, q_0..q_{k-1}; write w (k < m_max)
                 bytes += (k + 2 + (k < m_max ? 1 : 0)) * esz * N;
                 return launch_matvec(t, prec, b, ps, y, k, MV_DOTS_DC, k < m_max, ctx->stream, true);
             case CH_KERNEL_DC_UPDATE:   // read q_0..q_{k-1}, u_k, w; write q_k, u_{k+1}
                 bytes += (k + 4) * esz * N;
                 return launch_dc_update(t, prec, b, k, ctx->stream, true);
+            case CH_KERNEL_DC_ITER: {   // both passes and the dot totals between them
+                bytes += (2 * k + 7) * esz * N;
+                hipError_t e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_DC, true, ctx->stream, true);
+                if (e == hipSuccess) e = launch_dots_reduce(t, b, k, ctx->stream);
+                if (e == hipSuccess) e = launch_dc_update(t, prec, b, k, ctx->stream, true);
+                return e;
+            }
             default:                    // read y^n, the previous stage; write the next
                 bytes += 24.0 * N;
                 return launch_lim_stage(t, b, y, y, b.zbuf, 0, ctx->stream, true);

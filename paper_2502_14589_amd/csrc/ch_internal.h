@@ -170,7 +170,11 @@ hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStrea
 hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
 // phi test of iteration k (MGS: dimension k + 1, from the norm
 // partials; dc: DCGS2 iteration k -- dimension k, then the update coefficients).
-hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, bool dc, hipStream_t s);
+// Phi tests: MGS iteration k (dc false), or DCGS2 dimensions k .. k_last.
+hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int k_last, bool dc, hipStream_t s);
+#ifndef CH_PHI_BATCH
+#define CH_PHI_BATCH 1           // DCGS2 phi tests issued together on the second stream
+#endif
 // Arnoldi iteration k: matvec, Gram-Schmidt passes (orth: ch_orth), phi and
 // residual test.
 // Launch environment of the Arnoldi iterations: a second stream for the phi

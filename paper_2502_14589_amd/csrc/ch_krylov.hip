@@ -353,15 +353,82 @@ __global__ __launch_bounds__(CH_BLOCK) void k_update(Ctl* __restrict__ ctls, con
     const int j = ctl->j;
     if ((int)threadIdx.x < j)
         cf[threadIdx.x] = ctl->beta * ctl->u[threadIdx.x] * (unit ? 1.0 : ctl->vscale[threadIdx.x]);
-    __syncthreads();
     const double* y = ybase + I.off;
     double* ynew = ynewbase + I.off;
     const TV* Vi = V + I.off;
-    const long long stride = (long long)I.cblk * CH_BLOCK;
-    for (long long q = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x; q < I.N; q += stride) {
-        double acc = 0.0;
-        for (int i = 0; i < j; ++i) acc += cf[i] * double(Vi[(size_t)i * ldv + q]);
-        ynew[q] = y[q] + acc;
+    // 16-byte vectors of the basis (VW values), Q per thread, columns in
+    // blocks of RB requested one block ahead; the state in FP64
+    using VT = typename Vec16<TV>::type;
+    constexpr int VW = Vec16<TV>::W, Q = 2, RB = 4;
+    const long long NV = I.N / VW;
+    const long long per = (long long)I.cblk * CH_BLOCK;
+    const long long lt = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
+    __syncthreads();
+    for (long long q0 = lt; q0 < NV; q0 += per * Q) {
+        long long qq[Q];
+        bool ok[Q];
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            qq[u] = q0 + u * per;
+            ok[u] = qq[u] < NV;
+        }
+        auto load_cols = [&](int i0, VT (&v)[RB][Q]) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int u = 0; u < Q; ++u) {
+                    if (ok[u] && i0 + r < j) {
+                        v[r][u] = reinterpret_cast<const VT*>(Vi + (size_t)(i0 + r) * ldv)[qq[u]];
+                    } else {
+                        TV* ve = reinterpret_cast<TV*>(&v[r][u]);
+#pragma unroll
+                        for (int e = 0; e < VW; ++e) ve[e] = TV(0);
+                    }
+                }
+        };
+        double yv[Q][VW], acc[Q][VW];
+#pragma unroll
+        for (int u = 0; u < Q; ++u)
+#pragma unroll
+            for (int e = 0; e < VW; e += 2) {
+                const double2 t2 = ok[u] ? reinterpret_cast<const double2*>(y)[(qq[u] * VW + e) / 2] : double2{0.0, 0.0};
+                yv[u][e] = t2.x;
+                yv[u][e + 1] = t2.y;
+                acc[u][e] = acc[u][e + 1] = 0.0;
+            }
+        VT cur[RB][Q];
+        load_cols(0, cur);
+        for (int i0 = 0; i0 < j; i0 += RB) {
+            VT nxt[RB][Q];
+            load_cols(i0 + RB, nxt);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const double c = i0 + r < j ? cf[i0 + r] : 0.0;
+#pragma unroll
+                for (int u = 0; u < Q; ++u) {
+                    const TV* ve = reinterpret_cast<const TV*>(&cur[r][u]);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) acc[u][e] += c * double(ve[e]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int u = 0; u < Q; ++u) cur[r][u] = nxt[r][u];
+        }
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            if (!ok[u]) continue;
+#pragma unroll
+            for (int e = 0; e < VW; e += 2)
+                reinterpret_cast<double2*>(ynew)[(qq[u] * VW + e) / 2] =
+                    double2{yv[u][e] + acc[u][e], yv[u][e + 1] + acc[u][e + 1]};
+        }
+    }
+    for (long long q = NV * VW + lt; q < I.N; q += per) {   // the last N mod VW points
+        double a = 0.0;
+        for (int i = 0; i < j; ++i) a += cf[i] * double(Vi[(size_t)i * ldv + q]);
+        ynew[q] = y[q] + a;
     }
 }
 
@@ -551,42 +618,10 @@ __device__ void store_u(Ctl* ctl, const double* E, int j) {
 // h_{j+1,j} |e_j^T exp(-s H) e_1| from the same exponential, safeguarded by the
 // bracket, to a relative precision of about 1e-14.
 // ---------------------------------------------------------------------------
-template <bool SINGLE, bool DC>
-__global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst, int k,
-                                                  const double* __restrict__ pin, int pin_stencil,
-                                                  int* __restrict__ dflags) {
-    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];   // one workgroup per instance
-    Ctl* ctl = ctls + I.slot;
-    int* dflag = dflags ? dflags + I.slot : nullptr;
-    if (ctl->done | ctl->halted) return;
-    __shared__ PhiShared S;
-    int j;
-    double hnext;
-    if (DC) {
-        j = k;
-        hnext = ctl->H[j + (j - 1) * CH_LDH];
-    } else {
-        // h_{k+2,k+1} = ||w|| from the final Gram-Schmidt pass (Fig. 3)
-        double nrm2[1];
-        sum_inst_partials<1, RED_SUM>(pin, I, pin_stencil, nrm2);
-        hnext = sqrt(nrm2[0]);
-        if (threadIdx.x == 0) {
-            ctl->H[(k + 1) + k * CH_LDH] = hnext;
-            ctl->vscale[k + 1] = hnext > 0.0 ? 1.0 / hnext : 0.0;
-        }
-        j = k + 1;
-    }
-    if (threadIdx.x == 0) {
-        // Taylor coefficients 1 / k!, k = 0..19
-        double c = 1.0;
-        S.c[0] = 1.0;
-        for (int i = 1; i < 20; ++i) {
-            c /= double(i);
-            S.c[i] = c;
-        }
-    }
-    __syncthreads();
-    __syncthreads();   // H column j - 1 complete (written by the Gram-Schmidt launches and above)
+// One phi test of Krylov dimension j (h_{j+1,j} = hnext, H columns 0..j-1
+// final): returns true when the Krylov cycle is finished (converged, traced
+// at the last dimension, or failed).
+__device__ bool phi_test(PhiShared& S, Ctl* ctl, int* dflag, int j, double hnext) {
     const double* H = ctl->H;
     const double tau0 = ctl->tau0, tol = ctl->tol_phi;
     int nsq = 0;
@@ -600,7 +635,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
             if (dflag) *dflag = ctl->cyc;
             ctl->j = 0;
         }
-        return;
+        return true;
     }
     if (res0 <= tol) {
         store_u(ctl, E, j);
@@ -612,11 +647,11 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
             if (dflag) *dflag = ctl->cyc;
             ctl->j = j;
         }
-        return;
+        return true;
     }
     if (j < ctl->m_max) {
         if (threadIdx.x == 0) ctl->resnorm = res0;
-        return;
+        return false;
     }
     // ---- trace: largest passing dyadic step below tau0 ----
     const double tau_min = ctl->tau_min;
@@ -662,7 +697,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
             if (dflag) *dflag = ctl->cyc;
             ctl->j = 0;
         }
-        return;
+        return true;
     }
     // ---- refine the crossing inside [lo, hi] ----
     // First guess: log resnorm against log2(s / lo) through the chain's
@@ -728,6 +763,49 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
             if (dflag) *dflag = ctl->cyc;
         ctl->j = j;
     }
+    return true;
+}
+
+// MGS iteration k: dimension j = k + 1, h_{j+1,j} from the norm partials of
+// the final Gram-Schmidt pass.  DCGS2 (DC): dimensions k .. k_last (>= 1),
+// in order, until one ends the cycle; H is final up to column k_last - 1
+// (written by the update launches of those iterations).
+template <bool SINGLE, bool DC>
+__global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst, int k,
+                                                  int k_last, const double* __restrict__ pin, int pin_stencil,
+                                                  int* __restrict__ dflags) {
+    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];   // one workgroup per instance
+    Ctl* ctl = ctls + I.slot;
+    int* dflag = dflags ? dflags + I.slot : nullptr;
+    if (ctl->done | ctl->halted) return;
+    __shared__ PhiShared S;
+    if (threadIdx.x == 0) {
+        // Taylor coefficients 1 / k!, k = 0..19
+        double c = 1.0;
+        S.c[0] = 1.0;
+        for (int i = 1; i < 20; ++i) {
+            c /= double(i);
+            S.c[i] = c;
+        }
+    }
+    __syncthreads();
+    if (DC) {
+        for (int j = k; j <= k_last; ++j) {
+            __syncthreads();   // the previous test's reads of ctl are complete
+            if (phi_test(S, ctl, dflag, j, ctl->H[j + (j - 1) * CH_LDH])) return;
+        }
+        return;
+    }
+    // h_{k+2,k+1} = ||w|| from the final Gram-Schmidt pass (Fig. 3)
+    double nrm2[1];
+    sum_inst_partials<1, RED_SUM>(pin, I, pin_stencil, nrm2);
+    const double hnext = sqrt(nrm2[0]);
+    if (threadIdx.x == 0) {
+        ctl->H[(k + 1) + k * CH_LDH] = hnext;
+        ctl->vscale[k + 1] = hnext > 0.0 ? 1.0 / hnext : 0.0;
+    }
+    __syncthreads();   // H column k complete (written by the Gram-Schmidt launches and above)
+    phi_test(S, ctl, dflag, k + 1, hnext);
 }
 
 // ---------------------------------------------------------------------------
@@ -1129,17 +1207,17 @@ hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSe
     return hipGetLastError();
 }
 
-hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, bool dc, hipStream_t s) {
+hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int k_last, bool dc, hipStream_t s) {
     if (dc)
         if (t.ninst == 1)
-            hipLaunchKernelGGL((k_phi<true, true>), IARGS, k, nullptr, 0, b.dflag);
+            hipLaunchKernelGGL((k_phi<true, true>), IARGS, k, k_last, nullptr, 0, b.dflag);
         else
-            hipLaunchKernelGGL((k_phi<false, true>), IARGS, k, nullptr, 0, b.dflag);
+            hipLaunchKernelGGL((k_phi<false, true>), IARGS, k, k_last, nullptr, 0, b.dflag);
     else
         if (t.ninst == 1)
-            hipLaunchKernelGGL((k_phi<true, false>), IARGS, k, ps.in(), ps.stencil, b.dflag);
+            hipLaunchKernelGGL((k_phi<true, false>), IARGS, k, k, ps.in(), ps.stencil, b.dflag);
         else
-            hipLaunchKernelGGL((k_phi<false, false>), IARGS, k, ps.in(), ps.stencil, b.dflag);
+            hipLaunchKernelGGL((k_phi<false, false>), IARGS, k, k, ps.in(), ps.stencil, b.dflag);
     return hipGetLastError();
 }
 
@@ -1203,15 +1281,19 @@ hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, Pa
         if ((e = launch_dots_reduce(t, b, k, s)) != hipSuccess) return e;
         e = store ? launch_dc_update(t, prec, b, k, s) : launch_dc_finish(t, b, k, s);
         if (e != hipSuccess || k == 0) return e;
-        if (!env) return launch_phi(t, b, ps, k, true, s);
+        if (!env) return launch_phi(t, b, ps, k, k, true, s);
+        // the tests of CH_PHI_BATCH consecutive dimensions share one launch
+        // (and one cross-stream dependency); the last dimension closes a batch
+        if (k % CH_PHI_BATCH != 0 && k != m_max) return hipSuccess;
+        const int k0 = k % CH_PHI_BATCH == 0 ? k - CH_PHI_BATCH + 1 : k - k % CH_PHI_BATCH + 1;
         if ((e = hipEventRecord(env->ev_main, s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(env->side, env->ev_main, 0)) != hipSuccess) return e;
-        return launch_phi(t, b, ps, k, true, env->side);
+        return launch_phi(t, b, ps, k0 < 1 ? 1 : k0, k, true, env->side);
     }
     if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_ONE, true, s)) != hipSuccess) return e;
     for (int i = 1; i <= k + 1; ++i)
         if ((e = launch_mgs_pass(t, prec, b, ps, k, i, s)) != hipSuccess) return e;
-    return launch_phi(t, b, ps, k, false, s);
+    return launch_phi(t, b, ps, k, k, false, s);
 }
 
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,

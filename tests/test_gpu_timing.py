@@ -55,6 +55,8 @@ def test_time_kernel_bytes_and_workspace(ctx, prec):
     up = list(range(m))
     us, nb = ctx.time_kernel(pg, ch.CH_KERNEL_DC_UPDATE, m, up)
     assert us > 0 and nb == sum((k + 4) * w * N for k in up)
+    us, nb = ctx.time_kernel(pg, ch.CH_KERNEL_DC_ITER, m, up)
+    assert us > 0 and nb == sum((2 * k + 7) * w * N for k in up)
     us, nb = ctx.time_kernel(pg, ch.CH_KERNEL_PHI, m, list(range(1, min(last_j, m - 1) + 1)))
     assert us > 0 and nb == 0
     us, nb = ctx.time_kernel(pg, ch.CH_KERNEL_MATVEC, m, [0, 1, m - 1])
