@@ -405,3 +405,60 @@ def test_mass_conserved_on_gpu(ctx):
     yl = dev(y0)
     ctx.run_lim(pg, yl, 1e-7, max_steps=10, tol=1e-4)
     assert abs(host(yl).sum() - y0.sum()) <= 1e-12 * np.abs(y0).sum()
+
+
+# --- 2-D row-strip layout: strip widths, tiny grids, workgroups looping over strips ----
+
+@pytest.mark.parametrize("n", [5, 6, 33, 45, 98])
+def test_strip_widths_ee_trace_and_lim(ctx, n):
+    """Grid sides that give 1 (odd n), 2 (n = 2 mod 4) or 4 columns per lane in
+    the FP32 strips and 1 or 2 in the FP64 ones; n = 5 and 6 are smaller than
+    one strip's halo lanes: EE2 traced step and LIM steps against the oracle,
+    FP32-mixed against FP64."""
+    say(f"strip widths n={n}")
+    po, pg = probs(2, n, 0.05)
+    y0 = uniform_field(n, 2, 0.1, 0.05, seed=700 + n)
+    y_ref, tau_ref, info = O.ee_step(y0, po, 1e-2, 1e-7, 6)
+    yg = dev(y0)
+    rec = ctx.step_ee(pg, yg, 1e-2, m_max=6, tol_phi_fixed=1e-7)
+    assert rec["j"] == info.j
+    assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12)
+    assert rel(host(yg), y_ref) <= TOL_FP64
+    yc_ref, _ = O.ee_const_run(y0, po, 1e-7, 2, 1e-8, 30)
+    y32 = dev(y0)
+    ctx.run_ee(ch.Problem(2, n, 0.05, False, ch.CH_FP32_MIXED), y32, 1e-7, max_steps=2, m_max=30,
+               tol_phi_fixed=1e-8, constant_step=True)
+    assert rel(host(y32), yc_ref) <= 1e-6
+    tau = 1e-4 / n
+    yl_ref, ps = O.lim_const_run(y0, po, tau, 3)
+    yl = dev(y0)
+    st, recs = ctx.run_lim(pg, yl, tau, max_steps=3, records=True)
+    assert [r["j"] for r in recs] == ps
+    assert rel(host(yl), yl_ref) <= TOL_FP64
+
+
+def test_strip_workgroups_loop_over_strips(ctx):
+    """3000^2 (FP64: 25 x 1500 strips, more than the strip workgroups of one
+    instance take at once, so each loops): a phi action (Krylov dimension at
+    most 3) and one LIM step against the oracle."""
+    say("3000^2 strips in a loop: phiv m <= 3 and one LIM step")
+    n, eps = 3000, 0.01
+    po, pg = probs(2, n, eps)
+    y0 = uniform_field(n, 2, 0.1, 0.05, seed=791)
+    tau = 1e-9
+    y_ref, tau_ref, info = O.ee_step(y0, po, tau, 1e-10, 3)
+    yg = dev(y0)
+    import torch
+
+    out = torch.empty_like(yg)
+    rec = ctx.phiv(pg, yg, out, tau, mode=ch.CH_PHI_SHRINK, tol_phi=1e-10, m_max=3)
+    assert rec["j"] == info.j
+    assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12)
+    assert rel(host(out), y_ref) <= TOL_FP64
+    lam = O.lambda_max(y0, po)
+    tl = 2.0 / lam
+    yl_ref, p = O.lim_step(y0, po, tl)
+    yl = dev(y0)
+    rl = ctx.step_lim(pg, yl, tl)
+    assert rl["j"] == p
+    assert rel(host(yl), yl_ref) <= TOL_FP64
