@@ -164,8 +164,13 @@ hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const dou
                                   int pos, bool timing, hipStream_t s);
 hipError_t launch_est_ee_strip(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
                                double* pout, hipStream_t s);
+// with_phi: the same launch runs the phi test of Krylov dimension j (one
+// extra workgroup per instance; padded orders up to 32).
 hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s,
-                            bool timing = false);
+                            bool timing = false, bool with_phi = false);
+// DCGS2 cycles of Krylov dimension up to 31 test convergence inside the update
+// launches; larger ones on a second stream.
+inline bool phi_in_update(int m_max) { return m_max + 1 <= 32; }
 hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStream_t s);
 hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
 // phi test of iteration k (MGS: dimension k + 1, from the norm

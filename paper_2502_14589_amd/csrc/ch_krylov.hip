@@ -188,16 +188,17 @@ __device__ void dc_prepare(DcCoef& C, Ctl* ctl, int j, bool fin, bool publish) {
     __syncthreads();
 }
 
-template <typename TV, bool SINGLE, int TAG>   // TAG: as for the matvec
-__global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
-                                                        const int* __restrict__ cb2i, const Inst inst0, int ninst,
-                                                        TV* __restrict__ V, size_t ldv, int j) {
-    const Inst I = SINGLE ? inst0 : insts[cb2i[blockIdx.x]];
+// The update pass of one workgroup; bid: its index among the launch's
+// streaming workgroups.
+template <typename TV, bool SINGLE, int TAG>
+__device__ __forceinline__ void dc_update_wg(DcCoef& C, Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                             const int* __restrict__ cb2i, const Inst& inst0, int bid,
+                                             TV* __restrict__ V, size_t ldv, int j) {
+    const Inst I = SINGLE ? inst0 : insts[cb2i[bid]];
     Ctl* ctl = ctls + I.slot;
     if (ctl->done | ctl->halted) return;
     using VT = typename Vec16<TV>::type;
     constexpr int VW = Vec16<TV>::W, Q = CH_DCU_Q, RB = CH_DCU_RB;
-    __shared__ DcCoef C;
     const TV* Vi = V + I.off;
     TV* U = V + (size_t)j * ldv + I.off;
     TV* Wc = V + (size_t)(j + 1) * ldv + I.off;
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     VT* W4 = reinterpret_cast<VT*>(Wc);
     const long long NV = I.N / VW;
     const long long per = (long long)I.cblk * CH_BLOCK;
-    const long long lt = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x;
+    const long long lt = (long long)(bid - I.cblk0) * CH_BLOCK + threadIdx.x;
     long long qq[Q];
     bool ok[Q];
     VT uv[Q], wv[Q];
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
     VT cur[RB][Q];
     load_uw(lt);
     load_cols(0, cur);
-    dc_prepare(C, ctl, j, false, TAG == 0 && (int)blockIdx.x == I.cblk0);   // timing launches publish nothing
+    dc_prepare(C, ctl, j, false, TAG == 0 && bid == I.cblk0);   // timing launches publish nothing
     const double* ca = C.ca;
     const double* cb = C.cb;
     const double cbw = C.cbw, cq = C.cq;
@@ -308,6 +309,14 @@ __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, 
         U[e] = qs;
         Wc[e] = TV(xu + cq * double(qs));
     }
+}
+
+template <typename TV, bool SINGLE, int TAG>   // TAG: as for the matvec
+__global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                        const int* __restrict__ cb2i, const Inst inst0, int ninst,
+                                                        TV* __restrict__ V, size_t ldv, int j) {
+    __shared__ DcCoef C;
+    dc_update_wg<TV, SINGLE, TAG>(C, ctls, insts, cb2i, inst0, blockIdx.x, V, ldv, j);
 }
 
 // Iteration j = m_max: column j - 1 of H only (one workgroup per instance).
@@ -453,16 +462,20 @@ __global__ __launch_bounds__(CH_BLOCK) void k_update(Ctl* __restrict__ ctls, con
 // Orders are padded to a multiple of 16 for the matrix cores; the padding is
 // a zero block of the argument, whose exponential is an identity block.
 constexpr int NPMAX = 48;          // largest padded order
-constexpr int PLD = NPMAX + 1;     // LDS row stride (odd: rows fall in different banks)
 static_assert(CH_MMAX + 1 <= NPMAX, "augmented matrix exceeds the padded order");
 constexpr double THETA19 = 1.2603811;
 constexpr int NLVL = 80;
 
+// LDS of one phi evaluation for padded orders up to NPM; rows of stride
+// LD = NPM + 1 (odd: rows fall in different banks).
+template <int NPM>
 struct PhiShared {
-    double B[7][NPMAX * PLD];   // X, X^2 .. X^5, two Horner / squaring buffers
+    static constexpr int LD = NPM + 1;
+    double B[6][NPM * LD];      // X, X^2, X^3, X^4, two Horner / squaring buffers
     double c[20];               // 1 / k!
     double lvl[NLVL];           // lvl[kk] = resnorm at s 2^-kk from the squaring chain
     double red;
+    double hcol[NPM];           // column j - 1 of H when it is not yet in the control block
 };
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -479,12 +492,13 @@ struct NoEpi {
 // NT = np / 16 tiles per direction.  The K loop is unrolled: every A and B
 // operand of a tile is read from LDS before the first product, and even and
 // odd K steps accumulate separately (two independent chains).
-template <int NT, typename Epi = NoEpi>
+template <int NT, int PLD, typename Epi = NoEpi>
 __device__ void mm_t(double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B,
                      Epi epi = Epi()) {
     constexpr int NP = 16 * NT, KS = NP / 4;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 1
     for (int t = wid; t < NT * NT; t += CH_BLOCK / 64) {
         const int ti = t / NT, tj = t - ti * NT;
         const double* a = A + (16 * ti + li) * PLD + lk;
@@ -510,38 +524,43 @@ __device__ void mm_t(double* __restrict__ C, const double* __restrict__ A, const
     __syncthreads();
 }
 
-template <typename Epi = NoEpi>
+template <int NPM, typename Epi = NoEpi>
 __device__ void mm(double* __restrict__ C, const double* __restrict__ A, const double* __restrict__ B, int np,
                    Epi epi = Epi()) {
-    if (np <= 16) mm_t<1>(C, A, B, epi);
-    else if (np <= 32) mm_t<2>(C, A, B, epi);
-    else mm_t<3>(C, A, B, epi);
+    constexpr int PLD = NPM + 1;
+    if (np <= 16) mm_t<1, PLD>(C, A, B, epi);
+    else if (NPM >= 32 && np <= 32) mm_t<(NPM >= 32 ? 2 : 1), PLD>(C, A, B, epi);
+    else if (NPM >= 48) mm_t<(NPM >= 48 ? 3 : 1), PLD>(C, A, B, epi);
 }
 
-// B_i(r, c) = sum_{q=0..4} X^q(r, c) / (5i + q)!
+// B_i(r, c) = sum_{q=0..3} X^q(r, c) / (4i + q)!
+template <int PLD>
 struct TaylorBlock {
-    const double* X[5];   // X^1 .. X^4 in X[1..4]
+    const double* X[4];   // X^1 .. X^3 in X[1..3]
     const double* cf;
     int i;
     __device__ double operator()(int r, int c) const {
         const int o = r * PLD + c;
-        const double* f = cf + 5 * i;
-        return (r == c ? f[0] : 0.0) + f[1] * X[1][o] + f[2] * X[2][o] + f[3] * X[3][o] + f[4] * X[4][o];
+        const double* f = cf + 4 * i;
+        return (r == c ? f[0] : 0.0) + f[1] * X[1][o] + f[2] * X[2][o] + f[3] * X[3][o];
     }
 };
 
 // exp(s [[-H_jj, e_1], [0, 0]]); returns the LDS matrix holding it and the
 // number of squarings in *nsq_out.  Records resnorm at every dyadic level of
-// the squaring chain in S.lvl.
-__device__ const double* expm_aug(PhiShared& S, const double* __restrict__ H, int j, double s, double hnext,
-                                  int* nsq_out) {
+// the squaring chain in S.lvl.  Column j - 1 of H comes from hlast when it is
+// given (not yet in the control block), else from H.
+template <int NPM>
+__device__ const double* expm_aug(PhiShared<NPM>& S, const double* __restrict__ H, const double* hlast, int j,
+                                  double s, double hnext, int* nsq_out) {
+    constexpr int PLD = PhiShared<NPM>::LD;
     const int n = j + 1;
     const int np = (n + 15) & ~15;
     double* X1 = S.B[0];
     for (int idx = threadIdx.x; idx < np * np; idx += CH_BLOCK) {
         const int r = idx / np, c = idx - r * np;
         double v = 0.0;
-        if (r < j && c < j) v = -s * H[r + c * CH_LDH];
+        if (r < j && c < j) v = -s * (hlast && c == j - 1 ? hlast[r] : H[r + c * CH_LDH]);
         else if (r == 0 && c == j) v = s;
         X1[r * PLD + c] = v;
     }
@@ -564,21 +583,21 @@ __device__ const double* expm_aug(PhiShared& S, const double* __restrict__ H, in
         X1[r * PLD + c] *= scale;
     }
     __syncthreads();
-    mm(S.B[1], X1, X1, np);         // X^2
-    mm(S.B[2], S.B[1], X1, np);     // X^3
-    mm(S.B[3], S.B[1], S.B[1], np); // X^4
-    mm(S.B[4], S.B[3], X1, np);     // X^5
-    TaylorBlock tb{{nullptr, S.B[0], S.B[1], S.B[2], S.B[3]}, S.c, 3};
-    double* R = S.B[5];
-    double* R2 = S.B[6];
+    mm<NPM>(S.B[1], X1, X1, np);         // X^2
+    mm<NPM>(S.B[2], S.B[1], X1, np);     // X^3
+    mm<NPM>(S.B[3], S.B[1], S.B[1], np); // X^4
+    // T_19 = B_0 + X^4 (B_1 + X^4 (B_2 + X^4 (B_3 + X^4 B_4)))
+    TaylorBlock<PLD> tb{{nullptr, S.B[0], S.B[1], S.B[2]}, S.c, 4};
+    double* R = S.B[4];
+    double* R2 = S.B[5];
     for (int idx = threadIdx.x; idx < np * np; idx += CH_BLOCK) {
         const int r = idx / np, c = idx - r * np;
         R[r * PLD + c] = tb(r, c);
     }
     __syncthreads();
-    for (int i = 2; i >= 0; --i) {
+    for (int i = 3; i >= 0; --i) {
         tb.i = i;
-        mm(R2, S.B[4], R, np, tb);
+        mm<NPM>(R2, S.B[3], R, np, tb);
         double* t = R;
         R = R2;
         R2 = t;
@@ -587,7 +606,7 @@ __device__ const double* expm_aug(PhiShared& S, const double* __restrict__ H, in
     double* Y = R2;
     if (threadIdx.x == 0 && nsq < NLVL) S.lvl[nsq] = hnext * fabs(X[(j - 1) * PLD + j]);
     for (int i = 1; i <= nsq; ++i) {
-        mm(Y, X, X, np);
+        mm<NPM>(Y, X, X, np);
         double* tmp = X;
         X = Y;
         Y = tmp;
@@ -599,6 +618,7 @@ __device__ const double* expm_aug(PhiShared& S, const double* __restrict__ H, in
     return X;
 }
 
+template <int PLD>
 __device__ void store_u(Ctl* ctl, const double* E, int j) {
     for (int i = threadIdx.x; i < j; i += CH_BLOCK) ctl->u[i] = E[i * PLD + j];
 }
@@ -621,149 +641,234 @@ __device__ void store_u(Ctl* ctl, const double* E, int j) {
 // One phi test of Krylov dimension j (h_{j+1,j} = hnext, H columns 0..j-1
 // final): returns true when the Krylov cycle is finished (converged, traced
 // at the last dimension, or failed).
-__device__ bool phi_test(PhiShared& S, Ctl* ctl, int* dflag, int j, double hnext) {
+template <int NPM>
+__device__ __forceinline__ bool phi_test(PhiShared<NPM>& S, Ctl* ctl, int* dflag, int j, double hnext, const double* hlast) {
+    constexpr int PLD = PhiShared<NPM>::LD;
+    // One exponential per pass of the loop below (a single call site keeps
+    // the register footprint of one evaluation).  Phases: 0 the test at
+    // tau0; 1 dyadic steps below the squaring chain, until one passes; 2
+    // Newton inside the bracket; 3 the final evaluation at the chosen step.
     const double* H = ctl->H;
-    const double tau0 = ctl->tau0, tol = ctl->tol_phi;
-    int nsq = 0;
-    const double* E = expm_aug(S, H, j, tau0, hnext, &nsq);
-    const double res0 = hnext * fabs(E[(j - 1) * PLD + j]);
-    if (!(res0 < __builtin_inf())) {
+    const double tau0 = ctl->tau0, tol = ctl->tol_phi, tau_min = ctl->tau_min;
+    int phase = 0, kk = 0, it = 0, kchain = 0;   // kchain: deepest level of the first squaring chain
+    double s = tau0, lo = -1.0, hi = 0.0, rlo = 0.0, rhi = 0.0, prev = 0.0, step_prev = 1.0;
+    int fail = 0;   // ch_status of a failed cycle
+    auto finish = [&](const double* E, double sf, double res, int conv) {
+        store_u<PLD>(ctl, E, j);
         if (threadIdx.x == 0) {
-            ctl->status = CH_ENONFINITE;
-            ctl->halted = 1;
-            ctl->done = 1;
-            if (dflag) *dflag = ctl->cyc;
-            ctl->j = 0;
-        }
-        return true;
-    }
-    if (res0 <= tol) {
-        store_u(ctl, E, j);
-        if (threadIdx.x == 0) {
-            ctl->tau_acc = tau0;
-            ctl->resnorm = res0;
-            ctl->converged = 1;
+            ctl->tau_acc = sf;
+            ctl->resnorm = res;
+            ctl->converged = conv;
+            if (!conv) ctl->traced = 1;
             ctl->done = 1;
             if (dflag) *dflag = ctl->cyc;
             ctl->j = j;
         }
-        return true;
-    }
-    if (j < ctl->m_max) {
-        if (threadIdx.x == 0) ctl->resnorm = res0;
-        return false;
-    }
-    // ---- trace: largest passing dyadic step below tau0 ----
-    const double tau_min = ctl->tau_min;
-    double lo = -1.0, hi = 0.0, rlo = 0.0, rhi = 0.0;
-    const int kmax = nsq < NLVL - 1 ? nsq : NLVL - 1;
-    for (int kk = 1; kk <= kmax; ++kk) {
-        if (S.lvl[kk] <= tol) {
-            lo = ldexp(tau0, -kk);
-            rlo = S.lvl[kk];
-            hi = 2.0 * lo;
-            rhi = S.lvl[kk - 1];
-            break;
+    };
+    // first Newton iterate inside [lo, hi]: log resnorm against log2(s / lo)
+    // through the chain's values at lo / 2, lo and hi (quadratic) when they
+    // are at hand, else through lo and hi
+    auto first_guess = [&](bool chain) {
+        double g = -1.0;
+        if (rlo > 0.0 && rhi > rlo) {
+            const double y0 = log(rlo), y1 = log(rhi), yt = log(tol);
+            double x = (yt - y0) / (y1 - y0);
+            const int kl = (int)lrint(log2(tau0 / lo));   // lo = tau0 2^-kl
+            if (chain && kl + 1 <= kchain && S.lvl[kl + 1] > 0.0 && S.lvl[kl + 1] < rlo) {
+                const double ym = log(S.lvl[kl + 1]);
+                const double bq = 0.5 * (y1 - ym), cq = 0.5 * (y1 + ym) - y0;
+                const double disc = bq * bq - 4.0 * cq * (y0 - yt);
+                if (fabs(cq) > 1e-12 * fabs(bq) && disc >= 0.0) {
+                    const double xq = (-bq + sqrt(disc)) / (2.0 * cq);
+                    if (xq > 0.0 && xq < 1.0) x = xq;
+                }
+            }
+            g = lo * exp2(x);
         }
-    }
-    bool underflow = false;
-    if (lo < 0.0) {
-        double prev = S.lvl[kmax];
-        for (int kk = kmax + 1;; ++kk) {
-            const double s = ldexp(tau0, -kk);
-            if (kk > 1100 || s == 0.0 || s < tau_min) {
-                underflow = true;
+        if (!(g > lo && g < hi)) g = 0.5 * (lo + hi);
+        return g;
+    };
+    for (;;) {
+        int nsq = 0;
+        const double* E = expm_aug<NPM>(S, H, hlast, j, s, hnext, &nsq);
+        const double uj = E[(j - 1) * PLD + j];
+        const double r = hnext * fabs(uj);
+        if (phase == 0) {
+            if (!(r < __builtin_inf())) {
+                fail = CH_ENONFINITE;
                 break;
             }
-            int nq;
-            const double* Es = expm_aug(S, H, j, s, hnext, &nq);
-            const double r = hnext * fabs(Es[(j - 1) * PLD + j]);
+            if (r <= tol) {
+                finish(E, tau0, r, 1);
+                return true;
+            }
+            if (j < ctl->m_max) {
+                if (threadIdx.x == 0) ctl->resnorm = r;
+                return false;
+            }
+            // ---- trace: largest passing dyadic step below tau0 ----
+            const int kmax = nsq < NLVL - 1 ? nsq : NLVL - 1;
+            kchain = kmax;
+            for (int q = 1; q <= kmax; ++q) {
+                if (S.lvl[q] <= tol) {
+                    lo = ldexp(tau0, -q);
+                    rlo = S.lvl[q];
+                    hi = 2.0 * lo;
+                    rhi = S.lvl[q - 1];
+                    break;
+                }
+            }
+            if (lo < 0.0) {   // below the chain: more halvings, one evaluation each
+                prev = S.lvl[kmax];
+                kk = kmax + 1;
+                s = ldexp(tau0, -kk);
+                if (kk > 1100 || s == 0.0 || s < tau_min) {
+                    fail = CH_ETAU_UNDERFLOW;
+                    break;
+                }
+                phase = 1;
+                continue;
+            }
+            if (lo < tau_min) {
+                fail = CH_ETAU_UNDERFLOW;
+                break;
+            }
+            s = first_guess(true);
+            phase = 2;
+            continue;
+        }
+        if (phase == 1) {
             if (r <= tol) {
                 lo = s;
                 rlo = r;
                 hi = 2.0 * s;
                 rhi = prev;
-                break;
+                if (lo < tau_min) {
+                    fail = CH_ETAU_UNDERFLOW;
+                    break;
+                }
+                s = first_guess(false);
+                phase = 2;
+                continue;
             }
             prev = r;
+            ++kk;
+            s = ldexp(tau0, -kk);
+            if (kk > 1100 || s == 0.0 || s < tau_min) {
+                fail = CH_ETAU_UNDERFLOW;
+                break;
+            }
+            continue;
         }
-    }
-    if (!underflow && lo < tau_min) underflow = true;
-    if (underflow) {
-        if (threadIdx.x == 0) {
-            ctl->status = CH_ETAU_UNDERFLOW;
-            ctl->halted = 1;
-            ctl->done = 1;
-            if (dflag) *dflag = ctl->cyc;
-            ctl->j = 0;
+        if (phase == 2) {
+            // Newton on log resnorm against log s, d resnorm / ds =
+            // h_{j+1,j} |e_j^T exp(-s H) e_1| from the same exponential; it
+            // converges quadratically, so a Newton step below 1e-7 s after
+            // one below 1e-3 s leaves the next iterate within about 1e-14 of
+            // the crossing.  Bisection steps (Newton iterate outside the
+            // bracket) say nothing about convergence and reset that count.
+            const double dr = hnext * (uj >= 0.0 ? 1.0 : -1.0) * E[(j - 1) * PLD + 0];
+            if (r <= tol) {
+                lo = s;
+                rlo = r;
+            } else {
+                hi = s;
+                rhi = r;
+            }
+            double sn = -1.0;
+            if (r > 0.0 && dr > 0.0) sn = s * exp(-log(r / tol) * r / (s * dr));
+            bool stop;
+            if (hi - lo <= 0x1p-47 * lo) {
+                sn = lo;
+                stop = true;
+            } else if (sn > 0.0 && fabs(sn - s) <= 1e-14 * s) {
+                // s is the crossing to rounding; from the passing side the
+                // Newton iterate may round onto lo itself
+                if (r <= tol) sn = s;
+                stop = true;
+            } else {
+                const bool newton = sn > lo && sn < hi;
+                if (!newton) sn = 0.5 * (lo + hi);
+                const double step = fabs(sn - s) / s;
+                stop = (newton && step <= 1e-7 && step_prev <= 1e-3) || ++it >= 60;
+                step_prev = newton ? step : 1.0;
+            }
+            s = sn;
+            if (stop) phase = 3;
+            continue;
         }
+        finish(E, s, r, 0);   // phase 3
         return true;
     }
-    // ---- refine the crossing inside [lo, hi] ----
-    // First guess: log resnorm against log2(s / lo) through the chain's
-    // values at lo / 2, lo and hi (quadratic), else through lo and hi.
-    double s = -1.0;
-    if (rlo > 0.0 && rhi > rlo) {
-        const double y0 = log(rlo), y1 = log(rhi), yt = log(tol);
-        double x = (yt - y0) / (y1 - y0);
-        const int kl = (int)lrint(log2(tau0 / lo));   // lo = tau0 2^-kl
-        if (kl + 1 <= kmax && S.lvl[kl + 1] > 0.0 && S.lvl[kl + 1] < rlo) {
-            const double ym = log(S.lvl[kl + 1]);
-            const double bq = 0.5 * (y1 - ym), cq = 0.5 * (y1 + ym) - y0;
-            const double disc = bq * bq - 4.0 * cq * (y0 - yt);
-            if (fabs(cq) > 1e-12 * fabs(bq) && disc >= 0.0) {
-                const double xq = (-bq + sqrt(disc)) / (2.0 * cq);
-                if (xq > 0.0 && xq < 1.0) x = xq;
-            }
-        }
-        s = lo * exp2(x);
-    }
-    if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
-    // Newton on log resnorm against log s; it converges quadratically, so a
-    // step below 1e-7 s after one below 1e-3 s leaves the next iterate within
-    // about 1e-14 of the crossing.
-    double step_prev = 1.0;
-    for (int it = 0; it < 60; ++it) {
-        int nq;
-        const double* Es = expm_aug(S, H, j, s, hnext, &nq);
-        const double uj = Es[(j - 1) * PLD + j];
-        const double r = hnext * fabs(uj);
-        const double dr = hnext * (uj >= 0.0 ? 1.0 : -1.0) * Es[(j - 1) * PLD + 0];
-        if (r <= tol) {
-            lo = s;
-            rlo = r;
-        } else {
-            hi = s;
-            rhi = r;
-        }
-        if (hi - lo <= 0x1p-47 * lo) {
-            s = lo;
-            break;
-        }
-        double sn = -1.0;
-        if (r > 0.0 && dr > 0.0) sn = s * exp(-log(r / tol) * r / (s * dr));
-        if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
-        const double step = fabs(sn - s) / s;
-        if (step <= 1e-14 || (step <= 1e-7 && step_prev <= 1e-3)) {
-            s = sn;
-            break;
-        }
-        step_prev = step;
-        s = sn;
-    }
-    int nq;
-    const double* Ef = expm_aug(S, H, j, s, hnext, &nq);
-    store_u(ctl, Ef, j);
     if (threadIdx.x == 0) {
-        ctl->tau_acc = s;
-        ctl->resnorm = hnext * fabs(Ef[(j - 1) * PLD + j]);
-        ctl->converged = 0;
-        ctl->traced = 1;
+        ctl->status = fail;
+        ctl->halted = 1;
         ctl->done = 1;
-            if (dflag) *dflag = ctl->cyc;
-        ctl->j = j;
+        if (dflag) *dflag = ctl->cyc;
+        ctl->j = 0;
     }
     return true;
+}
+
+// ---------------------------------------------------------------------------
+// DCGS2 update pass of iteration j with the phi test of Krylov dimension j in
+// the same launch (padded orders up to 32, j <= 31): workgroup w < ninst
+// tests instance w, forming column j - 1 of H from its own copy of the
+// iteration's coefficients; the others do the update pass.  The test then
+// overlaps the update instead of needing a second stream.
+// ---------------------------------------------------------------------------
+constexpr int NPS = 32;
+union DcPhiLds {
+    DcCoef C;
+    PhiShared<NPS> P;
+};
+
+__device__ void taylor_coefficients(double* c) {
+    if (threadIdx.x == 0) {   // 1 / k!, k = 0..19
+        double f = 1.0;
+        c[0] = 1.0;
+        for (int i = 1; i < 20; ++i) {
+            f /= double(i);
+            c[i] = f;
+        }
+    }
+}
+
+template <bool SINGLE>
+__device__ __forceinline__ void dc_phi_wg(DcPhiLds& L, Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst& inst0,
+                          int w, int j, int* __restrict__ dflags) {
+    const Inst I = SINGLE ? inst0 : insts[w];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->done | ctl->halted) return;
+    int* dflag = dflags ? dflags + I.slot : nullptr;
+    dc_prepare(L.C, ctl, j, true, false);   // column j - 1 of H, rho = h_{j+1,j} last
+    __syncthreads();
+    const double h = (int)threadIdx.x < j ? L.C.hf[threadIdx.x] : 0.0;
+    const double hnext = L.C.hf[j];
+    __syncthreads();                        // the coefficients are dead from here on
+    if ((int)threadIdx.x < j) L.P.hcol[threadIdx.x] = h;
+    taylor_coefficients(L.P.c);
+    __syncthreads();
+    phi_test<NPS>(L.P, ctl, dflag, j, hnext, L.P.hcol);
+}
+
+// Three workgroups per CU: the LDS of the phi part (about 51 KB) admits no
+// more, and the matching register cap (168) keeps the update workgroups at
+// three waves per SIMD instead of the one the unbounded phi code would leave.
+// An update workgroup that starts after the test of its own launch has ended
+// the cycle skips its share; the columns j and j + 1 it would write are not
+// read by a finished cycle (its result uses columns 0..j-1 and u).
+template <typename TV, bool SINGLE>
+__global__ __launch_bounds__(CH_BLOCK, 3) void k_dc_update_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                            const int* __restrict__ cb2i, const Inst inst0, int ninst,
+                                                            TV* __restrict__ V, size_t ldv, int j,
+                                                            int* __restrict__ dflags) {
+    __shared__ DcPhiLds L;
+    if ((int)blockIdx.x < ninst) {
+        dc_phi_wg<SINGLE>(L, ctls, insts, inst0, blockIdx.x, j, dflags);
+        return;
+    }
+    dc_update_wg<TV, SINGLE, 0>(L.C, ctls, insts, cb2i, inst0, blockIdx.x - ninst, V, ldv, j);
 }
 
 // MGS iteration k: dimension j = k + 1, h_{j+1,j} from the norm partials of
@@ -778,21 +883,13 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
     Ctl* ctl = ctls + I.slot;
     int* dflag = dflags ? dflags + I.slot : nullptr;
     if (ctl->done | ctl->halted) return;
-    __shared__ PhiShared S;
-    if (threadIdx.x == 0) {
-        // Taylor coefficients 1 / k!, k = 0..19
-        double c = 1.0;
-        S.c[0] = 1.0;
-        for (int i = 1; i < 20; ++i) {
-            c /= double(i);
-            S.c[i] = c;
-        }
-    }
+    __shared__ PhiShared<NPMAX> S;
+    taylor_coefficients(S.c);
     __syncthreads();
     if (DC) {
         for (int j = k; j <= k_last; ++j) {
             __syncthreads();   // the previous test's reads of ctl are complete
-            if (phi_test(S, ctl, dflag, j, ctl->H[j + (j - 1) * CH_LDH])) return;
+            if (phi_test<NPMAX>(S, ctl, dflag, j, ctl->H[j + (j - 1) * CH_LDH], nullptr)) return;
         }
         return;
     }
@@ -805,7 +902,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
         ctl->vscale[k + 1] = hnext > 0.0 ? 1.0 / hnext : 0.0;
     }
     __syncthreads();   // H column k complete (written by the Gram-Schmidt launches and above)
-    phi_test(S, ctl, dflag, k + 1, hnext);
+    phi_test<NPMAX>(S, ctl, dflag, k + 1, hnext, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1253,9 +1350,28 @@ static void launch_dc_update_t(const Table& t, const DevBuffers& b, int j, bool 
         hipLaunchKernelGGL((k_dc_update<TV, false, 0>), CARGS, V, b.ldv, j);
 }
 
-hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s, bool timing) {
-    if (prec == CH_FP64) launch_dc_update_t<double>(t, b, j, timing, s);
-    else launch_dc_update_t<float>(t, b, j, timing, s);
+template <typename TV>
+static void launch_dc_update_phi_t(const Table& t, const DevBuffers& b, int j, hipStream_t s) {
+    TV* V = static_cast<TV*>(b.V);
+    const dim3 grid(t.ninst + t.cgrid);
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_dc_update_phi<TV, true>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i, t.hinst[0],
+                           t.ninst, V, b.ldv, j, b.dflag);
+    else
+        hipLaunchKernelGGL((k_dc_update_phi<TV, false>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i,
+                           t.hinst[0], t.ninst, V, b.ldv, j, b.dflag);
+}
+
+hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s, bool timing,
+                            bool with_phi) {
+    if (with_phi) {
+        if (prec == CH_FP64) launch_dc_update_phi_t<double>(t, b, j, s);
+        else launch_dc_update_phi_t<float>(t, b, j, s);
+    } else if (prec == CH_FP64) {
+        launch_dc_update_t<double>(t, b, j, timing, s);
+    } else {
+        launch_dc_update_t<float>(t, b, j, timing, s);
+    }
     return hipGetLastError();
 }
 
@@ -1279,6 +1395,13 @@ hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, Pa
         const bool store = k < m_max;
         if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_DC, store, s)) != hipSuccess) return e;
         if ((e = launch_dots_reduce(t, b, k, s)) != hipSuccess) return e;
+        if (phi_in_update(m_max)) {
+            // the test of dimension k rides in the update launch; the last
+            // one (and its residual-time trace) follows the final pass
+            if (store) return launch_dc_update(t, prec, b, k, s, false, k >= 1);
+            if ((e = launch_dc_finish(t, b, k, s)) != hipSuccess || k == 0) return e;
+            return launch_phi(t, b, ps, k, k, true, s);
+        }
         e = store ? launch_dc_update(t, prec, b, k, s) : launch_dc_finish(t, b, k, s);
         if (e != hipSuccess || k == 0) return e;
         if (!env) return launch_phi(t, b, ps, k, k, true, s);
@@ -1305,7 +1428,7 @@ hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq
         hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, m_max, env, s);
         if (e != hipSuccess) return e;
     }
-    if (dc && env) {   // the cycle's result is the last phi test's
+    if (dc && env && !phi_in_update(m_max)) {   // the cycle's result is the last phi test's
         hipError_t e = hipEventRecord(env->ev_side, env->side);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, env->ev_side, 0);
         return e;

@@ -88,6 +88,26 @@ def test_ee_step_trace_parity(ctx, dim, n):
     assert rel(host(yg), y_ref) <= TOL_FP64
 
 
+@pytest.mark.parametrize("m_max", [4, 6, 9])
+def test_ee_trace_refinement_seeds(ctx, m_max):
+    """Residual-time traces over several fields: the refined step is the
+    crossing of the residual test to 1e-12 however the refinement reaches it
+    (from the passing side, the failing side, or through bisection)."""
+    n = 32
+    po, pg = probs(2, n, 0.05)
+    for seed in range(6):
+        say(f"EE trace m_max={m_max} seed={seed}")
+        y0 = uniform_field(n, 2, 0.1, 0.05, seed=900 + 10 * m_max + seed)
+        y_ref, tau_ref, info = O.ee_step(y0, po, 1e-2, 1e-7, m_max)
+        assert not info.converged
+        yg = dev(y0)
+        rec = ctx.step_ee(pg, yg, 1e-2, m_max=m_max, tol_phi_fixed=1e-7)
+        assert rec["traced"] == 1 and rec["j"] == m_max
+        assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12)
+        assert rec["resnorm"] <= 1e-7 * (1 + 1e-12)
+        assert rel(host(yg), y_ref) <= TOL_FP64
+
+
 def test_ee_adaptive_run_parity(ctx):
     say("EE adaptive run 48^2")
     po, pg = probs(2, 48, 0.03)
