@@ -174,7 +174,9 @@ def c3_form(ctx, ch, torch, steps: int = 20, warmup: int = 0):
                      "effective_GBps": round(f["effective_GBps"], 1),
                      "dc_matvec_GBps": round(mv["achieved_GBps"], 1), "dc_update_GBps": round(up["achieved_GBps"], 1),
                      "dc_matvec_frac": round(mv["achieved_GBps"] / HBM_PEAK_GBPS, 4),
-                     "dc_update_frac": round(up["achieved_GBps"] / HBM_PEAK_GBPS, 4)}
+                     "dc_update_frac": round(up["achieved_GBps"] / HBM_PEAK_GBPS, 4),
+                     "dc_matvec_avg_launch_us": round(mv["avg_launch_us"], 3),
+                     "dc_matvec_bytes_per_launch": mv["bytes_per_launch"], "dc_matvec_launches": mv["launches"]}
     return out
 
 
@@ -368,6 +370,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="FP32-mixed form only, printing the work of its dominant kernel class (hardware-counter runs)")
+    ap.add_argument("--only-3d", action="store_true", help="the 256^3 forms alone (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the grid would be split into "
@@ -395,6 +398,10 @@ def main():
                             args.steps, args.warmup, M_MAX, TOL, True, N)
         print(json.dumps({"mode": "counters", "kernel": DOMINANT, "source_sha": kernel_source_sha(),
                           "replay": f["kernels"]["dc_matvec"]}), flush=True)
+        return
+    if args.only_3d:
+        with ch.Context(0) as ctx:
+            print(json.dumps({"mode": "only-3d", "c3_3d": c3_form(ctx, ch, torch)}), flush=True)
         return
     with ch.Context(0) as ctx:
         f32 = run_ee_form(ctx, ch, torch, ch.Problem(2, N_SIDE, EPS, False, ch.CH_FP32_MIXED), y0, TAU0, T_END,

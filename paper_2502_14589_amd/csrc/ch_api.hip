@@ -225,6 +225,19 @@ int strip_vx(int n, int prec) {
     return vx;
 }
 
+// Workgroups of the 3-D marching matvec of one instance: one per 64 x 8 x-y
+// tile and run of planes, capped (larger grids loop over the work items).
+static int march_blocks(int n) {
+    const long long items = (long long)((n + 63) / 64) * ((n + 7) / 8) * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
+    return (int)std::min<long long>(items, CH_WBLK_MAX);
+}
+
+// Workgroups of the 2-D strip kernels (dim 2) or the 3-D marching matvec
+// (dim 3) of one instance.
+int wide_blocks(int dim, int n, int prec) {
+    return dim == 2 ? strip_blocks(n, strip_vx(n, prec)) : march_blocks(n);
+}
+
 // Workgroup ranges of each instance and the block-to-instance maps.  prec:
 // the precision of the run's basis (selects the strip width).
 int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, int prec, Table* t) {
@@ -238,7 +251,7 @@ int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, int prec, T
         int sblk, cblk;
         inst_blocks(dim, n, m.sh.N, &sblk, &cblk);
         const int vx = strip_vx(n, prec);
-        const int wblk = dim == 2 ? strip_blocks(n, vx) : 0;
+        const int wblk = wide_blocks(dim, n, prec);
         I.off = (long long)m.off;
         I.N = m.sh.N;
         I.n = n;
@@ -1130,7 +1143,7 @@ int ch_submit(ch_server* S, const ch_request* q, unsigned long long* ticket) {
     r->N = sh.N;
     r->len = pad64(sh.N);
     inst_blocks(2, q->n, sh.N, &r->sblk, &r->cblk);
-    r->wblk = strip_blocks(q->n, strip_vx(q->n, S->prec));
+    r->wblk = wide_blocks(2, q->n, S->prec);
     if (r->len > S->pool_pts || r->sblk > CH_MAXB || r->cblk > CH_MAXB || r->wblk > CH_MAXB) {
         delete r;
         return CH_ENOMEM;

@@ -14,6 +14,9 @@
 #define CH_WBLK_MAX 2048         // most strip workgroups per instance (larger grids loop over strips)
 #endif
                                  // <= 8 * CH_BLOCK partials per instance (sum_partials)
+#ifndef CH_MARCH_L
+#define CH_MARCH_L 16            // planes per run of the 3-D marching matvec
+#endif
 #ifndef CH_CBLK_MAX
 #define CH_CBLK_MAX 512          // most streaming workgroups per instance
 #endif
@@ -76,7 +79,7 @@ struct Inst {
     int cblk0, cblk;    // streaming workgroups [cblk0, cblk0 + cblk)
     double eps2, inv_h2;
     int eyre;
-    int wblk0, wblk;    // 2-D row-strip workgroups [wblk0, wblk0 + wblk)
+    int wblk0, wblk;    // 2-D row-strip / 3-D marching workgroups [wblk0, wblk0 + wblk)
     int vx;             // 2-D strips: columns per lane (divides n)
 };
 
@@ -122,7 +125,7 @@ struct Table {
     const int* cb2i;    // streaming workgroup -> instance
     const int* wb2i;    // 2-D strip workgroup -> instance
     int ninst, sgrid, cgrid, dim;
-    int wgrid;          // 2-D strip workgroups
+    int wgrid;          // 2-D strip / 3-D marching workgroups
     const Inst* hinst;  // host copy
 };
 
@@ -164,6 +167,10 @@ hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const dou
                                   int pos, bool timing, hipStream_t s);
 hipError_t launch_est_ee_strip(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
                                double* pout, hipStream_t s);
+// 3-D DCGS2 matvec on z-marching x-y tiles (ch_march.hip); its workgroups are
+// the instance's wblk range, so its partials are of kind PK_STRIP too.
+hipError_t launch_matvec_march(const Table& t, int prec, const DevBuffers& b, const double* y, int k, bool store_w,
+                               double* pout, bool timing, hipStream_t s);
 // with_phi: the same launch runs the phi test of Krylov dimension j (one
 // extra workgroup per instance; padded orders up to 32).
 hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s,

@@ -1329,7 +1329,7 @@ bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected) {
 
 hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStream_t s) {
     const dim3 grid(2 * k + 2, t.ninst);
-    const int kind = uses_strips(t) ? PK_STRIP : PK_TILE;
+    const int kind = PK_STRIP;   // the DCGS2 matvec runs on strips (2-D) or marching tiles (3-D)
     if (t.ninst == 1)
         hipLaunchKernelGGL((k_dots_reduce<true>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.hinst[0], t.ninst,
                            b.dots, kind);

@@ -476,6 +476,7 @@ static hipError_t launch_matvec_t(const Table& t, const DevBuffers& b, PartSeq& 
 
 hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
                          int dots, bool store_w, hipStream_t s, bool timing) {
+    if (t.dim == 3 && dots == MV_DOTS_DC) return launch_matvec_march(t, prec, b, y, k, store_w, b.dots, timing, s);
     if (uses_strips(t)) {
         if (dots == MV_DOTS_DC) return launch_matvec_strip(t, prec, b, y, k, dots, store_w, b.dots, timing, s);
         const hipError_t e = launch_matvec_strip(t, prec, b, y, k, dots, store_w, ps.out(), false, s);

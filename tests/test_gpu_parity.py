@@ -457,6 +457,23 @@ def test_strip_widths_ee_trace_and_lim(ctx, n):
     assert rel(host(yl), yl_ref) <= TOL_FP64
 
 
+def test_march_workgroups_loop_over_runs(ctx):
+    """264^3: 5 x 33 x-y tiles (the last 8 columns wide) times 17 runs of
+    planes (the last 8 deep) are more work items than the marching matvec's
+    workgroups of one instance, so each takes several; one traced EE2 step
+    (Krylov dimension 3) against the oracle."""
+    say("264^3 marching matvec in a loop: EE step m = 3")
+    n = 264
+    po, pg = probs(3, n, 0.02)
+    y0 = uniform_field(n, 3, 0.1, 0.05, seed=792)
+    y_ref, tau_ref, info = O.ee_step(y0, po, 1e-9, 1e-10, 3)
+    yg = dev(y0)
+    rec = ctx.step_ee(pg, yg, 1e-9, m_max=3, tol_phi_fixed=1e-10)
+    assert rec["j"] == info.j
+    assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12)
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
 def test_strip_workgroups_loop_over_strips(ctx):
     """3000^2 (FP64: 25 x 1500 strips, more than the strip workgroups of one
     instance take at once, so each loops): a phi action (Krylov dimension at
