@@ -114,9 +114,6 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctls, const 
 #ifndef CH_DCU_Q
 #define CH_DCU_Q 2
 #endif
-#ifndef CH_DCU_RB
-#define CH_DCU_RB 2
-#endif
 
 struct DcCoef {
     double s[CH_MMAX + 1], t[CH_MMAX + 1], g[CH_MMAX + 1], hf[CH_MMAX + 1];
@@ -188,8 +185,33 @@ __device__ void dc_prepare(DcCoef& C, Ctl* ctl, int j, bool fin, bool publish) {
     __syncthreads();
 }
 
+// 16-byte raw buffer accesses over one span of a column: reads past the
+// span's end return zeros and stores there are dropped, so the pass below has
+// no branch around a memory access (a branch would make the compiler wait for
+// every outstanding load where it joins, prefetches included).
+using u32x4v = unsigned __attribute__((ext_vector_type(4)));
+constexpr unsigned DCU_OFF = 0x80000000u;   // an offset past any span
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename VT>
+__device__ __forceinline__ VT load16(__amdgpu_buffer_rsrc_t r, unsigned bo) {
+    return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(r, bo, 0u, 0));
+}
+
+template <typename VT>
+__device__ __forceinline__ void store16(VT v, __amdgpu_buffer_rsrc_t r, unsigned bo) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4v, v), r, bo, 0u, 0);
+}
+
 // The update pass of one workgroup; bid: its index among the launch's
-// streaming workgroups.
+// streaming workgroups.  The instance's vectors (16 bytes) are taken in spans
+// of cblk * CH_BLOCK * Q; thread t of the workgroups handles vectors t,
+// t + cblk * CH_BLOCK, ... of each span.  Basis columns come in blocks of two
+// through two buffers that alternate, so the loads of one block are in
+// flight while the other is summed and no loaded value is copied.
 template <typename TV, bool SINGLE, int TAG>
 __device__ __forceinline__ void dc_update_wg(DcCoef& C, Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                              const int* __restrict__ cb2i, const Inst& inst0, int bid,
@@ -198,94 +220,93 @@ __device__ __forceinline__ void dc_update_wg(DcCoef& C, Ctl* __restrict__ ctls, 
     Ctl* ctl = ctls + I.slot;
     if (ctl->done | ctl->halted) return;
     using VT = typename Vec16<TV>::type;
-    constexpr int VW = Vec16<TV>::W, Q = CH_DCU_Q, RB = CH_DCU_RB;
+    constexpr int VW = Vec16<TV>::W, Q = CH_DCU_Q, RB = 2;
     const TV* Vi = V + I.off;
     TV* U = V + (size_t)j * ldv + I.off;
     TV* Wc = V + (size_t)(j + 1) * ldv + I.off;
-    VT* U4 = reinterpret_cast<VT*>(U);
-    VT* W4 = reinterpret_cast<VT*>(Wc);
     const long long NV = I.N / VW;
     const long long per = (long long)I.cblk * CH_BLOCK;
-    const long long lt = (long long)(bid - I.cblk0) * CH_BLOCK + threadIdx.x;
-    long long qq[Q];
-    bool ok[Q];
+    const long long span = per * Q;   // vectors per span: at most 2^18 (4 MiB)
+    const int lt = (bid - I.cblk0) * CH_BLOCK + threadIdx.x;
+    unsigned rel[Q];   // byte offsets of this thread's vectors in a span
+#pragma unroll
+    for (int u = 0; u < Q; ++u) rel[u] = (unsigned)(lt + u * per) * 16u;
+    auto vrs = [&](const TV* col, long long v0) {
+        const long long left = NV - v0;
+        const long long nv = left < span ? (left > 0 ? left : 0) : span;
+        return span_rsrc(col + v0 * VW, (unsigned)nv * 16u);
+    };
     VT uv[Q], wv[Q];
-    auto load_uw = [&](long long q0) {
+    auto load_uw = [&](long long v0) {
+        const __amdgpu_buffer_rsrc_t ru = vrs(U, v0), rw = vrs(Wc, v0);
 #pragma unroll
         for (int u = 0; u < Q; ++u) {
-            qq[u] = q0 + u * per;
-            ok[u] = qq[u] < NV;
-            if (ok[u]) {
-                uv[u] = U4[qq[u]];
-                wv[u] = W4[qq[u]];
-            }
+            uv[u] = load16<VT>(ru, rel[u]);
+            wv[u] = load16<VT>(rw, rel[u]);
         }
     };
-    auto load_cols = [&](int i0, VT (&v)[RB][Q]) {
+    auto load_blk = [&](long long v0, int i0, VT (&b)[RB][Q]) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+        for (int r = 0; r < RB; ++r) {
+            const int i = i0 + r;
+            const bool live = i < j;
+            const __amdgpu_buffer_rsrc_t rc = vrs(Vi + (size_t)(live ? i : 0) * ldv, v0);
 #pragma unroll
-            for (int u = 0; u < Q; ++u) {
-                const VT* col = reinterpret_cast<const VT*>(Vi + (size_t)(i0 + r) * ldv);
-                if (ok[u] && i0 + r < j) v[r][u] = col[qq[u]];
-                else {
-                    TV* ve = reinterpret_cast<TV*>(&v[r][u]);
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) ve[e] = TV(0);
-                }
-            }
+            for (int u = 0; u < Q; ++u) b[r][u] = load16<VT>(rc, live ? rel[u] : DCU_OFF);
+        }
     };
     // the first vectors and basis columns are requested before the
-    // coefficients are formed, so the loads overlap that latency; later
-    // blocks of RB columns are requested one block ahead
-    VT cur[RB][Q];
-    load_uw(lt);
-    load_cols(0, cur);
+    // coefficients are formed, so the loads overlap that latency
+    VT ba[RB][Q], bb[RB][Q];
+    load_uw(0);
+    load_blk(0, 0, ba);
     dc_prepare(C, ctl, j, false, TAG == 0 && bid == I.cblk0);   // timing launches publish nothing
     const double* ca = C.ca;
     const double* cb = C.cb;
     const double cbw = C.cbw, cq = C.cq;
-    for (long long q0 = lt; q0 < NV; q0 += per * Q) {
-        if (q0 != lt) {
-            load_uw(q0);
-            load_cols(0, cur);
+    double xq[Q][VW], xu[Q][VW];
+    auto acc = [&](const VT (&b)[RB][Q], int i0) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const bool live = i0 + r < j;
+            const int i = live ? i0 + r : 0;
+            const double a = live ? ca[i] : 0.0;
+            const double c = live ? cb[i] : 0.0;
+#pragma unroll
+            for (int u = 0; u < Q; ++u) {
+                const TV* ve = reinterpret_cast<const TV*>(&b[r][u]);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    xq[u][e] += a * double(ve[e]);
+                    xu[u][e] += c * double(ve[e]);
+                }
+            }
         }
-        double xq[Q][VW], xu[Q][VW];
+    };
+    for (long long v0 = 0; v0 < NV; v0 += span) {
+        if (v0 != 0) {
+            load_uw(v0);
+            load_blk(v0, 0, ba);
+        }
 #pragma unroll
         for (int u = 0; u < Q; ++u) {
             const TV* ue = reinterpret_cast<const TV*>(&uv[u]);
             const TV* we = reinterpret_cast<const TV*>(&wv[u]);
 #pragma unroll
             for (int e = 0; e < VW; ++e) {
-                xq[u][e] = ok[u] ? ca[j] * double(ue[e]) : 0.0;
-                xu[u][e] = ok[u] ? cbw * double(we[e]) : 0.0;
+                xq[u][e] = ca[j] * double(ue[e]);
+                xu[u][e] = cbw * double(we[e]);
             }
         }
-        for (int i0 = 0; i0 < j; i0 += RB) {
-            VT nxt[RB][Q];
-            load_cols(i0 + RB, nxt);
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const double a = i0 + r < j ? ca[i0 + r] : 0.0;
-                const double c = i0 + r < j ? cb[i0 + r] : 0.0;
-#pragma unroll
-                for (int u = 0; u < Q; ++u) {
-                    const TV* ve = reinterpret_cast<const TV*>(&cur[r][u]);
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) {
-                        xq[u][e] += a * double(ve[e]);
-                        xu[u][e] += c * double(ve[e]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-#pragma unroll
-                for (int u = 0; u < Q; ++u) cur[r][u] = nxt[r][u];
+        for (int i0 = 0; i0 < j; i0 += 2 * RB) {
+            load_blk(v0, i0 + RB, bb);
+            acc(ba, i0);
+            load_blk(v0, i0 + 2 * RB, ba);
+            acc(bb, i0 + RB);
         }
+        const __amdgpu_buffer_rsrc_t ru = vrs(U, v0), rw = vrs(Wc, v0);
 #pragma unroll
         for (int u = 0; u < Q; ++u) {
-            if (!ok[u]) continue;
             VT qv, nv;
             TV* qe = reinterpret_cast<TV*>(&qv);
             TV* ne = reinterpret_cast<TV*>(&nv);
@@ -294,20 +315,21 @@ __device__ __forceinline__ void dc_update_wg(DcCoef& C, Ctl* __restrict__ ctls, 
                 qe[e] = TV(xq[u][e]);
                 ne[e] = TV(xu[u][e] + cq * double(qe[e]));   // with q_j as stored
             }
-            U4[qq[u]] = qv;
-            W4[qq[u]] = nv;
+            store16<VT>(qv, ru, rel[u]);
+            store16<VT>(nv, rw, rel[u]);
         }
     }
+    // elements past the last whole vector
     for (long long e = NV * VW + lt; e < I.N; e += per) {
-        double xq = ca[j] * double(U[e]), xu = cbw * double(Wc[e]);
+        double sq = ca[j] * double(U[e]), su = cbw * double(Wc[e]);
         for (int i = 0; i < j; ++i) {
             const double v = double(Vi[(size_t)i * ldv + e]);
-            xq += ca[i] * v;
-            xu += cb[i] * v;
+            sq += ca[i] * v;
+            su += cb[i] * v;
         }
-        const TV qs = TV(xq);
+        const TV qs = TV(sq);
         U[e] = qs;
-        Wc[e] = TV(xu + cq * double(qs));
+        Wc[e] = TV(su + cq * double(qs));
     }
 }
 

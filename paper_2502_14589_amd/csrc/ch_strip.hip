@@ -24,9 +24,6 @@
 namespace {
 
 constexpr int SR = CH_STRIP_ROWS;
-#ifndef CH_STRIP_RB
-#define CH_STRIP_RB 1
-#endif
 
 // Raw buffer resource over one grid row (wave-uniform base; lanes address it
 // by byte offset; an offset past the row reads zero and drops a store).  The
@@ -248,11 +245,10 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
         bool rowin[SR];
 #pragma unroll
         for (int i = 0; i < SR; ++i) rowin[i] = P.r0 + i < n;
-        if (A.store_w && P.out) {
+        // stores outside the grid or of no use go past the row (dropped)
 #pragma unroll
-            for (int i = 0; i < SR; ++i)
-                if (rowin[i]) store_row<TV, VX>(grid_row(Wc, P.r0 + i, n), bo, w[i]);
-        }
+        for (int i = 0; i < SR; ++i)
+            store_row<TV, VX>(grid_row(Wc, P.r0 + i, n), A.store_w && P.out && rowin[i] ? bo : OFF_ROW, w[i]);
         // the strip's points (zero outside the grid), in FP64
         double ud[SR][VX], wd[SR][VX];
 #pragma unroll
@@ -273,54 +269,47 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
                 for (int e = 0; e < VX; ++e) one += wd[i][e] * double(v0[e]);
             }
         } else {
-            // RB columns per block, four per wave_sum8; the loads of the
-            // next block are in flight while this one is summed
-            constexpr int RB = CH_STRIP_RB;
+            // Columns in blocks of two through two buffers that alternate:
+            // the loads of one block are in flight while the other is summed,
+            // and no loaded value is copied between registers.  A column past
+            // k reads zeros (an offset past the row), so the loads sit in no
+            // branch; a branch around them would make the compiler wait for
+            // every outstanding load where it joins.
+            constexpr int RB = 2;
             auto fetch = [&](int c0, TV (&bl)[RB][SR][VX]) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    if (c0 + r < k) {
-                        const TV* Q = A.V + (size_t)(c0 + r) * A.ldv + I.off;
+                    const int c = c0 + r;
+                    const TV* Q = A.V + (size_t)(c < k ? c : 0) * A.ldv + I.off;
+                    const unsigned o = c < k ? bd : OFF_ROW;
 #pragma unroll
-                        for (int i = 0; i < SR; ++i) load_row<TV, VX>(grid_row(Q, P.r0 + i, n), bd, bl[r][i]);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < SR; ++i)
-#pragma unroll
-                            for (int e = 0; e < VX; ++e) bl[r][i][e] = TV(0);
-                    }
+                    for (int i = 0; i < SR; ++i) load_row<TV, VX>(grid_row(Q, P.r0 + i, n), o, bl[r][i]);
                 }
             };
-            TV cur[RB][SR][VX];
-            fetch(0, cur);
-            static_assert(4 % RB == 0, "blocks of 1, 2 or 4 columns");
-            for (int c0 = 0; c0 < k; c0 += 4) {
-                double a[8];
+            auto sums = [&](const TV (&bl)[RB][SR][VX], double* a) {
 #pragma unroll
-                for (int h = 0; h < 4 / RB; ++h) {
-                    TV nxt[RB][SR][VX];
-                    fetch(c0 + (h + 1) * RB, nxt);
+                for (int r = 0; r < RB; ++r) {
+                    double su = 0.0, sw = 0.0;
 #pragma unroll
-                    for (int r = 0; r < RB; ++r) {
-                        double su = 0.0, sw = 0.0;
+                    for (int i = 0; i < SR; ++i)
 #pragma unroll
-                        for (int i = 0; i < SR; ++i)
-#pragma unroll
-                            for (int e = 0; e < VX; ++e) {
-                                const double qv = double(cur[r][i][e]);
-                                su += ud[i][e] * qv;
-                                sw += wd[i][e] * qv;
-                            }
-                        a[2 * (h * RB + r)] = su;
-                        a[2 * (h * RB + r) + 1] = sw;
-                    }
-#pragma unroll
-                    for (int r = 0; r < RB; ++r)
-#pragma unroll
-                        for (int i = 0; i < SR; ++i)
-#pragma unroll
-                            for (int e = 0; e < VX; ++e) cur[r][i][e] = nxt[r][i][e];
+                        for (int e = 0; e < VX; ++e) {
+                            const double qv = double(bl[r][i][e]);
+                            su += ud[i][e] * qv;
+                            sw += wd[i][e] * qv;
+                        }
+                    a[2 * r] = su;
+                    a[2 * r + 1] = sw;
                 }
+            };
+            TV ba[RB][SR][VX], bb[RB][SR][VX];
+            fetch(0, ba);
+            for (int c0 = 0; c0 < k; c0 += 2 * RB) {   // four columns per wave_sum8
+                double a[8];
+                fetch(c0 + RB, bb);
+                sums(ba, a);
+                fetch(c0 + 2 * RB, ba);
+                sums(bb, a + 2 * RB);
                 const double tot = wave_sum8(a);
                 const int c = c0 + (hv >> 1);   // column of the value this lane holds
                 if (hv >= 0 && c < k) red[(hv & 1) ? k + c : c][wv] += tot;
