@@ -497,6 +497,7 @@ struct PhiShared {
     double c[20];               // 1 / k!
     double lvl[NLVL];           // lvl[kk] = resnorm at s 2^-kk from the squaring chain
     double red;
+    int nsq;                    // squarings of the last evaluation (order-16 path)
     double hcol[NPM];           // column j - 1 of H when it is not yet in the control block
 };
 
@@ -568,6 +569,121 @@ struct TaylorBlock {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Padded order 16: the whole exponential in the registers of wave 0.  A
+// 16 x 16 matrix M is held in the layout the matrix cores return it in
+// ("C layout": lane l, element v holds M(4 v + l / 16, l % 16)), which is
+// also the layout of a right operand's K slices; a left operand is wanted
+// transposed ("A layout": lane l, element q holds M(l % 16, 4 q + l / 16)),
+// made by a round trip through a block of LDS that only wave 0 touches (one
+// wave's LDS accesses complete in order, so no barrier is needed).  Same
+// products, epilogue and accumulation order as mm_t, without a workgroup
+// barrier per product.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ dbl4 mm16(const dbl4& a, const dbl4& b) {
+    dbl4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], c1, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], c1, 0, 0, 0);
+    return c0 + c1;
+}
+
+// C layout -> A layout through T (16 rows of stride 17)
+__device__ __forceinline__ dbl4 to_a(const dbl4& c, double* T) {
+    const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[(4 * v + lk) * 17 + li] = c[v];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    dbl4 a;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = T[li * 17 + 4 * q + lk];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    return a;
+}
+
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+    const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double elem(const dbl4& e, int v) {
+    return v == 0 ? e[0] : (v == 1 ? e[1] : (v == 2 ? e[2] : e[3]));
+}
+
+// As expm_aug for n = j + 1 <= 16.  Call from every thread.
+template <int NPM>
+__device__ const double* expm16(PhiShared<NPM>& S, const double* __restrict__ H, const double* hlast, int j,
+                                double s, double hnext, int* nsq_out) {
+    constexpr int PLD = PhiShared<NPM>::LD;
+    static_assert(16 * 17 <= NPM * PLD, "transpose block");
+    double* E = S.B[4];
+    __syncthreads();   // every wave's reads of the previous evaluation are done
+    if (threadIdx.x < 64) {
+        const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+        double* T = S.B[5];
+        dbl4 x;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 4 * v + lk, c = li;
+            double val = 0.0;
+            if (r < j && c < j) val = -s * (hlast && c == j - 1 ? hlast[r] : H[r + c * CH_LDH]);
+            else if (r == 0 && c == j) val = s;
+            x[v] = val;
+        }
+        // 1-norm: column sums (rows over v and the four lane groups), max over columns
+        double cs = (fabs(x[0]) + fabs(x[1])) + (fabs(x[2]) + fabs(x[3]));
+        cs += __shfl_xor(cs, 16, 64);
+        cs += __shfl_xor(cs, 32, 64);
+        const double nrm = wave_max(cs);
+        int nsq = 0;
+        if (nrm > THETA19 && nrm < __builtin_inf()) nsq = (int)ceil(log2(nrm / THETA19));
+        if (nsq > 1100) nsq = 1100;
+        const double scale = ldexp(1.0, -nsq);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] *= scale;
+        const dbl4 xa = to_a(x, T);
+        const dbl4 x2 = mm16(xa, x);
+        const dbl4 x2a = to_a(x2, T);
+        const dbl4 x3 = mm16(x2a, x);
+        const dbl4 x4a = to_a(mm16(x2a, x2), T);
+        // T_19 = B_0 + X^4 (B_1 + X^4 (B_2 + X^4 (B_3 + X^4 B_4))),
+        // B_i = sum_{q=0..3} X^q / (4i + q)!
+        auto blk = [&](int i) {
+            const double* f = S.c + 4 * i;
+            dbl4 b;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                b[v] = ((4 * v + lk == li ? f[0] : 0.0) + f[1] * x[v] + f[2] * x2[v]) + f[3] * x3[v];
+            return b;
+        };
+        dbl4 R = blk(4);
+        for (int i = 3; i >= 0; --i) R = mm16(x4a, R) + blk(i);
+        // resnorm at every dyadic level: element (j - 1, j)
+        const int lr = j + 16 * ((j - 1) & 3), vr = (j - 1) >> 2;
+        if (nsq < NLVL) {
+            const double rv = hnext * fabs(readlane_d(elem(R, vr), lr));
+            if (l == 0) S.lvl[nsq] = rv;
+        }
+        for (int i = 1; i <= nsq; ++i) {
+            R = mm16(to_a(R, T), R);
+            const int kk = nsq - i;
+            if (kk < NLVL) {
+                const double rv = hnext * fabs(readlane_d(elem(R, vr), lr));
+                if (l == 0) S.lvl[kk] = rv;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) E[(4 * v + lk) * PLD + li] = R[v];
+        if (l == 0) S.nsq = nsq;
+    }
+    __syncthreads();
+    *nsq_out = S.nsq;
+    return E;
+}
+
 // exp(s [[-H_jj, e_1], [0, 0]]); returns the LDS matrix holding it and the
 // number of squarings in *nsq_out.  Records resnorm at every dyadic level of
 // the squaring chain in S.lvl.  Column j - 1 of H comes from hlast when it is
@@ -577,6 +693,7 @@ __device__ const double* expm_aug(PhiShared<NPM>& S, const double* __restrict__ 
                                   double s, double hnext, int* nsq_out) {
     constexpr int PLD = PhiShared<NPM>::LD;
     const int n = j + 1;
+    if (n <= 16) return expm16<NPM>(S, H, hlast, j, s, hnext, nsq_out);
     const int np = (n + 15) & ~15;
     double* X1 = S.B[0];
     for (int idx = threadIdx.x; idx < np * np; idx += CH_BLOCK) {
