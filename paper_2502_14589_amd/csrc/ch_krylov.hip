@@ -921,9 +921,13 @@ __device__ __forceinline__ bool phi_test(PhiShared<NPM>& S, Ctl* ctl, int* dflag
                 sn = lo;
                 stop = true;
             } else if (sn > 0.0 && fabs(sn - s) <= 1e-14 * s) {
-                // s is the crossing to rounding; from the passing side the
-                // Newton iterate may round onto lo itself
-                if (r <= tol) sn = s;
+                // s is the crossing to rounding (from the passing side the
+                // Newton iterate may round onto lo itself); passing, it is
+                // the step, and this exponential its result
+                if (r <= tol) {
+                    finish(E, s, r, 0);
+                    return true;
+                }
                 stop = true;
             } else {
                 const bool newton = sn > lo && sn < hi;
