@@ -373,7 +373,7 @@ def main():
     ap.add_argument("--only-3d", action="store_true", help="the 256^3 forms alone (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the grid would be split into "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the grid would be split into "
               "slabs with 2-cell halo exchanges and scalar all-reduces per Gram-Schmidt reduction); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)

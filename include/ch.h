@@ -246,9 +246,10 @@ enum ch_kernel {
     CH_KERNEL_MGS = 0,      /* one modified Gram-Schmidt pass (axpy + next dot) over the grid */
     CH_KERNEL_MATVEC = 1,   /* one fused Jacobian matvec Ahat v with its first dot */
     CH_KERNEL_PHI = 2,      /* one small-matrix phi evaluation of the last step's H (no trace) */
-    /* the two CH_ORTH_DCGS2 passes of Arnoldi iteration j = m_max - 1: */
+    /* the CH_ORTH_DCGS2 passes of the Arnoldi iteration j each launch names: */
     CH_KERNEL_DC_MATVEC = 3,   /* matvec Ahat u_j with the 2j + 2 dot products against the basis */
-    CH_KERNEL_DC_UPDATE = 4,   /* q_j and u_{j+1} from one pass over the basis */
+    CH_KERNEL_DC_UPDATE = 4,   /* q_j and u_{j+1} from one pass over the basis (without the phi
+                                  test workgroup a run's update launch may carry) */
     CH_KERNEL_LIM_STAGE = 5,   /* one LIM Chebyshev stage */
     CH_KERNEL_DC_ITER = 6      /* one whole DCGS2 iteration: matvec, dot totals, update */
 };

@@ -103,8 +103,12 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctls, const 
 //                         then, in one pass over the basis,
 //                           q_j = (u_j - Q_{j-1} s) / rho           -> column j,
 //                           u_{j+1} = w / rho - Q_j (g / rho + h')  -> column j + 1.
-//   the phi launch:       tests dimension j on the final columns 0..j-1; it
-//                         reads only H and can overlap the next iteration.
+//   the phi test:         dimension j on the final columns 0..j-1 (it reads
+//                         only H): up to dimension 31 in extra workgroups of
+//                         the update launch (k_dc_update_phi), which form
+//                         column j - 1 themselves; beyond that in a launch of
+//                         its own on a second stream, overlapping the next
+//                         iteration.
 // Every workgroup of the update forms the coefficients itself (same
 // arithmetic, same order: identical in all of them); the first workgroup of
 // an instance publishes column j - 1 and h'.  h' alternates between two
