@@ -175,30 +175,28 @@ hipError_t launch_matvec_march(const Table& t, int prec, const DevBuffers& b, co
 // extra workgroup per instance; padded orders up to 32).
 hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s,
                             bool timing = false, bool with_phi = false);
-// DCGS2 cycles of Krylov dimension up to 31 test convergence inside the update
-// launches; larger ones on a second stream.
-inline bool phi_in_update(int m_max) { return m_max + 1 <= 32; }
+// The DCGS2 phi test of Krylov dimension j rides in the update launch of
+// iteration j when its padded order fits that launch's LDS (j + 1 <= 32).
+inline bool phi_in_update(int j) { return j + 1 <= 32; }
 hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStream_t s);
 hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, int k, int i, hipStream_t s);
 // phi test of iteration k (MGS: dimension k + 1, from the norm
 // partials; dc: DCGS2 iteration k -- dimension k, then the update coefficients).
 // Phi tests: MGS iteration k (dc false), or DCGS2 dimensions k .. k_last.
 hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int k_last, bool dc, hipStream_t s);
-#ifndef CH_PHI_BATCH
-#define CH_PHI_BATCH 1           // DCGS2 phi tests issued together on the second stream
-#endif
-// Arnoldi iteration k: matvec, Gram-Schmidt passes (orth: ch_orth), phi and
-// residual test.
-// Launch environment of the Arnoldi iterations: a second stream for the phi
-// tests of DCGS2 (each test waits for its iteration's update launch through
-// ev_main, then overlaps the next iterations; the cycle's end waits for the
-// last test through ev_side).
+// Launch environment of the Arnoldi iterations: a second stream for the
+// DCGS2 phi tests too large for the update launch (each waits for its
+// iteration's update through ev_main, then overlaps the next iterations; the
+// last test and the cycle's end wait for them through ev_side).
 struct LaunchEnv {
     hipStream_t side;
     hipEvent_t ev_main, ev_side;
 };
+// Arnoldi iteration k: matvec, Gram-Schmidt passes (orth: ch_orth), phi and
+// residual test.  side_used (DCGS2): set when a test went to the second
+// stream and the main stream has not yet waited for it.
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               int orth, int m_max, const LaunchEnv* env, hipStream_t s);
+                               int orth, int m_max, const LaunchEnv* env, hipStream_t s, bool* side_used = nullptr);
 // True when every instance has reported the current cycle finished:
 // expected[slot] is the number of cycles the host has issued for that slot.
 bool all_cycles_done(const Table& t, const DevBuffers& b, const int* expected);

@@ -1536,29 +1536,32 @@ hipError_t launch_dc_finish(const Table& t, const DevBuffers& b, int j, hipStrea
 // dimension k + 1.  DCGS2: iteration k (0..m_max) finishes column k - 1,
 // tests dimension k and (k < m_max) makes columns k and k + 1.
 hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int k,
-                               int orth, int m_max, const LaunchEnv* env, hipStream_t s) {
+                               int orth, int m_max, const LaunchEnv* env, hipStream_t s, bool* side_used) {
     hipError_t e;
     if (orth == CH_ORTH_DCGS2) {
         const bool store = k < m_max;
         if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_DC, store, s)) != hipSuccess) return e;
         if ((e = launch_dots_reduce(t, b, k, s)) != hipSuccess) return e;
-        if (phi_in_update(m_max)) {
-            // the test of dimension k rides in the update launch; the last
-            // one (and its residual-time trace) follows the final pass
-            if (store) return launch_dc_update(t, prec, b, k, s, false, k >= 1);
-            if ((e = launch_dc_finish(t, b, k, s)) != hipSuccess || k == 0) return e;
-            return launch_phi(t, b, ps, k, k, true, s);
+        if (store) {
+            // the test of dimension k rides in the update launch when it fits
+            if (k >= 1 && phi_in_update(k)) return launch_dc_update(t, prec, b, k, s, false, true);
+            if ((e = launch_dc_update(t, prec, b, k, s)) != hipSuccess || k == 0) return e;
+            if (!env) return launch_phi(t, b, ps, k, k, true, s);
+            // a larger one on the second stream, overlapping the next iterations
+            if ((e = hipEventRecord(env->ev_main, s)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(env->side, env->ev_main, 0)) != hipSuccess) return e;
+            if (side_used) *side_used = true;
+            return launch_phi(t, b, ps, k, k, true, env->side);
         }
-        e = store ? launch_dc_update(t, prec, b, k, s) : launch_dc_finish(t, b, k, s);
-        if (e != hipSuccess || k == 0) return e;
-        if (!env) return launch_phi(t, b, ps, k, k, true, s);
-        // the tests of CH_PHI_BATCH consecutive dimensions share one launch
-        // (and one cross-stream dependency); the last dimension closes a batch
-        if (k % CH_PHI_BATCH != 0 && k != m_max) return hipSuccess;
-        const int k0 = k % CH_PHI_BATCH == 0 ? k - CH_PHI_BATCH + 1 : k - k % CH_PHI_BATCH + 1;
-        if ((e = hipEventRecord(env->ev_main, s)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(env->side, env->ev_main, 0)) != hipSuccess) return e;
-        return launch_phi(t, b, ps, k0 < 1 ? 1 : k0, k, true, env->side);
+        // the last test (and its residual-time trace) follows the final pass,
+        // after every earlier test
+        if ((e = launch_dc_finish(t, b, k, s)) != hipSuccess || k == 0) return e;
+        if (env && side_used && *side_used) {
+            if ((e = hipEventRecord(env->ev_side, env->side)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, env->ev_side, 0)) != hipSuccess) return e;
+            *side_used = false;
+        }
+        return launch_phi(t, b, ps, k, k, true, s);
     }
     if ((e = launch_matvec(t, prec, b, ps, y, k, MV_DOTS_ONE, true, s)) != hipSuccess) return e;
     for (int i = 1; i <= k + 1; ++i)
@@ -1570,12 +1573,13 @@ hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq
                           int orth, const int* expected, const LaunchEnv* env, hipStream_t s) {
     const bool dc = orth == CH_ORTH_DCGS2;
     const int iters = dc ? m_max + 1 : m_max;
+    bool side_used = false;
     for (int k = 0; k < iters; ++k) {
         if (k > 0 && all_cycles_done(t, b, expected)) break;
-        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, m_max, env, s);
+        hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, m_max, env, s, &side_used);
         if (e != hipSuccess) return e;
     }
-    if (dc && env && !phi_in_update(m_max)) {   // the cycle's result is the last phi test's
+    if (side_used) {   // a cycle stopped early: its result may be a test still on the second stream
         hipError_t e = hipEventRecord(env->ev_side, env->side);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, env->ev_side, 0);
         return e;

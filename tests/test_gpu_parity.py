@@ -108,6 +108,23 @@ def test_ee_trace_refinement_seeds(ctx, m_max):
         assert rel(host(yg), y_ref) <= TOL_FP64
 
 
+@pytest.mark.parametrize("tau,j_expect", [(1.5e-4, 32), (2e-4, 36), (1e-2, 40)])
+def test_ee_step_krylov_dimension_above_31(ctx, tau, j_expect):
+    """Krylov dimension 40: the tests of dimensions up to 31 ride in the
+    update launches, larger ones run on the second stream, and the last
+    one (here a trace at tau = 1e-2) waits for them."""
+    say(f"EE step m_max=40 tau={tau}")
+    po, pg = probs(2, 40, 0.05)
+    y0 = uniform_field(40, 2, 0.1, 0.3, seed=140)
+    y_ref, tau_ref, info = O.ee_step(y0, po, tau, 1e-8, 40)
+    assert info.j == j_expect
+    yg = dev(y0)
+    rec = ctx.step_ee(pg, yg, tau, m_max=40, tol_phi_fixed=1e-8)
+    assert rec["j"] == info.j and rec["traced"] == (0 if info.converged else 1)
+    assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12)
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
 def test_ee_adaptive_run_parity(ctx):
     say("EE adaptive run 48^2")
     po, pg = probs(2, 48, 0.03)
