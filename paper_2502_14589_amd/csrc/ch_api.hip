@@ -39,7 +39,9 @@ struct ch_ctx {
     size_t rec_n = 0;        // step records allocated
     ch_step_record* rec = nullptr;
     std::vector<int> expect; // per slot: Krylov cycles issued (compared with the device's `cyc`)
-    int* hflag = nullptr;    // pinned, device-mapped: `cyc` of the last finished cycle per slot
+    int* hflag = nullptr;    // pinned, device-mapped: `cyc` of the last finished cycle per slot, then
+                             // the sequence number of the last DCGS2 update launch begun
+    int useq = 0;            // DCGS2 update launches issued (their sequence numbers)
     Ctl* hctl = nullptr;     // pinned mirror of the control blocks
     // instance table
     Inst* d_inst = nullptr;
@@ -127,6 +129,9 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         ctx->hflag = nullptr;
         b.hflag = nullptr;
         b.dflag = nullptr;
+        b.hprog = nullptr;
+        b.dprog = nullptr;
+        b.hseq = nullptr;
         ctx->slots = 0;
         if ((rc = alloc_dev(ctx, (void**)&b.ctl, sizeof(Ctl) * nslots))) return rc;
         free_dev(b.lorder);
@@ -136,12 +141,17 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         if ((rc = alloc_dev(ctx, (void**)&b.lorder, sizeof(int) * CH_PMAX * nslots))) return rc;
         if ((rc = alloc_dev(ctx, (void**)&b.lcoef, sizeof(double) * 4 * CH_PMAX * nslots))) return rc;
         HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hctl, sizeof(Ctl) * nslots, hipHostMallocDefault));
-        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, sizeof(int) * nslots,
+        // the finished-cycle word of every slot, then the update-launch progress word
+        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, sizeof(int) * (nslots + 1),
                                    hipHostMallocMapped | hipHostMallocCoherent));
-        for (int i = 0; i < nslots; ++i) ctx->hflag[i] = -1;
+        for (int i = 0; i <= nslots; ++i) ctx->hflag[i] = -1;
         ctx->expect.assign(nslots, 0);
         HIP_TRY(ctx, hipHostGetDevicePointer((void**)&b.dflag, ctx->hflag, 0));
         b.hflag = ctx->hflag;
+        b.dprog = b.dflag + nslots;
+        b.hprog = ctx->hflag + nslots;
+        ctx->useq = 0;
+        b.hseq = &ctx->useq;
         ctx->slots = nslots;
     }
     if (pts > ctx->pts) {

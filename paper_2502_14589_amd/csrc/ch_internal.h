@@ -14,6 +14,10 @@
 #define CH_WBLK_MAX 2048         // most strip workgroups per instance (larger grids loop over strips)
 #endif
                                  // <= 8 * CH_BLOCK partials per instance (sum_partials)
+#ifndef CH_LOOKAHEAD
+#define CH_LOOKAHEAD 2           // DCGS2 iterations the host issues ahead of the device's update launches
+#endif
+#define CH_LOOKAHEAD_WAIT_S 0.05 // longest host wait for that progress (then it issues anyway)
 #ifndef CH_MARCH_L
 #define CH_MARCH_L 16            // planes per run of the 3-D marching matvec
 #endif
@@ -116,6 +120,9 @@ struct DevBuffers {
     Ctl* ctl;           // control blocks, one per slot
     int* dflag;         // device view of `hflag`, one word per slot
     const volatile int* hflag;   // pinned host words: `cyc` of the last finished Krylov cycle per slot
+    int* dprog;         // device view of `hprog`
+    const volatile int* hprog;   // pinned host word: sequence number of the last DCGS2 update launch begun
+    int* hseq;          // host counter of the DCGS2 update launches issued
 };
 
 // The instance table of one launch sequence (device pointers + host mirror sizes).

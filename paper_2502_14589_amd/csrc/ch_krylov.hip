@@ -16,6 +16,8 @@
 // workgroup per instance.
 #include "ch_common.h"
 
+#include <chrono>
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -337,10 +339,20 @@ __device__ __forceinline__ void dc_update_wg(DcCoef& C, Ctl* __restrict__ ctls, 
     }
 }
 
+// Progress report of an update launch: workgroup 0 writes the launch's
+// sequence number to a pinned host word as the launch begins (whatever the
+// state of its instances), so the host can keep the number of iterations it
+// has issued ahead of the device small.
+__device__ __forceinline__ void report_launch(int* dprog, int seq) {
+    if (dprog && blockIdx.x == 0 && threadIdx.x == 0) *dprog = seq;
+}
+
 template <typename TV, bool SINGLE, int TAG>   // TAG: as for the matvec
 __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ cb2i, const Inst inst0, int ninst,
-                                                        TV* __restrict__ V, size_t ldv, int j) {
+                                                        TV* __restrict__ V, size_t ldv, int j,
+                                                        int* __restrict__ dprog, int seq) {
+    report_launch(dprog, seq);
     __shared__ DcCoef C;
     dc_update_wg<TV, SINGLE, TAG>(C, ctls, insts, cb2i, inst0, blockIdx.x, V, ldv, j);
 }
@@ -1009,7 +1021,9 @@ template <typename TV, bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK, 3) void k_dc_update_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                             const int* __restrict__ cb2i, const Inst inst0, int ninst,
                                                             TV* __restrict__ V, size_t ldv, int j,
-                                                            int* __restrict__ dflags) {
+                                                            int* __restrict__ dflags, int* __restrict__ dprog,
+                                                            int seq) {
+    report_launch(dprog, seq);
     __shared__ DcPhiLds L;
     if ((int)blockIdx.x < ninst) {
         dc_phi_wg<SINGLE>(L, ctls, insts, inst0, blockIdx.x, j, dflags);
@@ -1489,24 +1503,28 @@ hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStr
 template <typename TV>
 static void launch_dc_update_t(const Table& t, const DevBuffers& b, int j, bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
-    if (timing)
-        hipLaunchKernelGGL((k_dc_update<TV, true, 1>), CARGS, V, b.ldv, j);
-    else if (t.ninst == 1)
-        hipLaunchKernelGGL((k_dc_update<TV, true, 0>), CARGS, V, b.ldv, j);
+    if (timing) {
+        hipLaunchKernelGGL((k_dc_update<TV, true, 1>), CARGS, V, b.ldv, j, nullptr, 0);
+        return;
+    }
+    const int seq = b.hseq ? ++*b.hseq : 0;
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_dc_update<TV, true, 0>), CARGS, V, b.ldv, j, b.dprog, seq);
     else
-        hipLaunchKernelGGL((k_dc_update<TV, false, 0>), CARGS, V, b.ldv, j);
+        hipLaunchKernelGGL((k_dc_update<TV, false, 0>), CARGS, V, b.ldv, j, b.dprog, seq);
 }
 
 template <typename TV>
 static void launch_dc_update_phi_t(const Table& t, const DevBuffers& b, int j, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     const dim3 grid(t.ninst + t.cgrid);
+    const int seq = b.hseq ? ++*b.hseq : 0;
     if (t.ninst == 1)
         hipLaunchKernelGGL((k_dc_update_phi<TV, true>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i, t.hinst[0],
-                           t.ninst, V, b.ldv, j, b.dflag);
+                           t.ninst, V, b.ldv, j, b.dflag, b.dprog, seq);
     else
         hipLaunchKernelGGL((k_dc_update_phi<TV, false>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i,
-                           t.hinst[0], t.ninst, V, b.ldv, j, b.dflag);
+                           t.hinst[0], t.ninst, V, b.ldv, j, b.dflag, b.dprog, seq);
 }
 
 hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s, bool timing,
@@ -1569,15 +1587,34 @@ hipError_t launch_arnoldi_iter(const Table& t, int prec, const DevBuffers& b, Pa
     return launch_phi(t, b, ps, k, k, false, s);
 }
 
+// Waits (a bounded time) until the update launch with sequence number `seq`
+// has begun on the device, or every instance has finished its cycle.
+static void wait_progress(const Table& t, const DevBuffers& b, const int* expected, int seq) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (long long spin = 0;; ++spin) {
+        if (*b.hprog >= seq || all_cycles_done(t, b, expected)) return;
+        if ((spin & 255) == 255 &&
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > CH_LOOKAHEAD_WAIT_S)
+            return;   // issue anyway: the launches are correct whenever they run
+    }
+}
+
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
                           int orth, const int* expected, const LaunchEnv* env, hipStream_t s) {
     const bool dc = orth == CH_ORTH_DCGS2;
     const int iters = dc ? m_max + 1 : m_max;
     bool side_used = false;
+    int useq[CH_MMAX + 2];   // sequence number of each iteration's update launch
     for (int k = 0; k < iters; ++k) {
+        // the host issues at most CH_LOOKAHEAD iterations ahead of the
+        // device's update launches: once a test ends the cycle, few launches
+        // are left that only find it finished and exit
+        if (dc && b.hprog && b.hseq && expected && k > CH_LOOKAHEAD)
+            wait_progress(t, b, expected, useq[k - 1 - CH_LOOKAHEAD]);
         if (k > 0 && all_cycles_done(t, b, expected)) break;
         hipError_t e = launch_arnoldi_iter(t, prec, b, ps, y, k, orth, m_max, env, s, &side_used);
         if (e != hipSuccess) return e;
+        useq[k] = b.hseq ? *b.hseq : 0;
     }
     if (side_used) {   // a cycle stopped early: its result may be a test still on the second stream
         hipError_t e = hipEventRecord(env->ev_side, env->side);
