@@ -108,11 +108,12 @@ __device__ __forceinline__ double red_identity() {
     return -__builtin_inf();
 }
 
-// Workgroup reduction of NR values; the result is valid in thread 0.
+// Workgroup reduction of NR values (up to 16 waves); the result is valid in
+// thread 0.
 template <int NR, int OP>
 __device__ __forceinline__ void block_reduce(double (&x)[NR], double (*lds)[NR]) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    constexpr int nw = CH_BLOCK / 64;
+    const int nw = (int)(blockDim.x >> 6);
 #pragma unroll
     for (int r = 0; r < NR; ++r) x[r] = red_wave<OP>(x[r]);
     if (lane == 0) {

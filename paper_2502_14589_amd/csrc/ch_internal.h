@@ -96,7 +96,10 @@ struct Inst {
 #define CH_STRIP_ROWS 2
 #endif
 static_assert(CH_STRIP_ROWS <= 4, "strip rows: the periodic row wrap assumes n > CH_STRIP_ROWS (n >= 5)");
-#define CH_STRIP_WAVES (CH_BLOCK / 64)
+#ifndef CH_STRIP_WAVES
+#define CH_STRIP_WAVES 4         // waves per workgroup of the 2-D strip kernels
+#endif
+#define CH_STRIP_BLOCK (64 * CH_STRIP_WAVES)
 #define CH_STRIP_HALO(vx) ((vx) >= 2 ? 1 : 2)
 __host__ __device__ constexpr int strip_cols(int vx) { return (64 - 2 * CH_STRIP_HALO(vx)) * vx; }
 __host__ __device__ constexpr long long strip_count(int n, int vx) {

@@ -332,7 +332,7 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
 // VX: the strip width of a single-instance launch; 0: per instance (batches).
 // TAG distinguishes the launches of the timing aid (same code, another symbol).
 template <typename TV, bool SINGLE, int DM, int TAG, int VX>
-__global__ __launch_bounds__(CH_BLOCK) void k_matvec_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+__global__ __launch_bounds__(CH_STRIP_BLOCK) void k_matvec_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        TV* __restrict__ V, size_t ldv, int k, int store_w,
                                                        const TV* __restrict__ ybase, double* __restrict__ pout) {
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_s(Ctl* __restrict__ ctls, c
     }
     if (DM == DM_DC) {
         __syncthreads();
-        for (int i = threadIdx.x; i < nrows; i += CH_BLOCK) {
+        for (int i = threadIdx.x; i < nrows; i += CH_STRIP_BLOCK) {
             double t = red[i][0];
 #pragma unroll
             for (int x = 1; x < W; ++x) t += red[i][x];
@@ -429,7 +429,7 @@ __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restri
 }
 
 template <bool SINGLE, int TAG, int VX>
-__global__ __launch_bounds__(CH_BLOCK) void k_lim_stage_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+__global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                           const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                           const double* __restrict__ ybase,
                                                           const double* __restrict__ zbase, double* __restrict__ obase,
@@ -531,7 +531,7 @@ __device__ __forceinline__ void est_strips(const Inst& I, const double* __restri
 }
 
 template <typename TV, bool SINGLE, int VX>
-__global__ __launch_bounds__(CH_BLOCK) void k_est_ee_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+__global__ __launch_bounds__(CH_STRIP_BLOCK) void k_est_ee_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        const double* __restrict__ y0base,
                                                        const double* __restrict__ y1base, double* __restrict__ fbase,
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_ee_s(Ctl* __restrict__ ctls, c
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-#define WARGS dim3(t.wgrid), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.wb2i, t.hinst[0], t.ninst
+#define WARGS dim3(t.wgrid), dim3(CH_STRIP_BLOCK), 0, s, b.ctl, t.inst, t.wb2i, t.hinst[0], t.ninst
 
 template <typename TV, int DM, bool TIMING, int VX>
 static void launch_matvec_one(const Table& t, const DevBuffers& b, const TV* y, int k, int store_w, double* pout,
