@@ -251,19 +251,22 @@ enum ch_kernel {
     CH_KERNEL_DC_UPDATE = 4,   /* q_j and u_{j+1} from one pass over the basis (without the phi
                                   test workgroup a run's update launch may carry) */
     CH_KERNEL_LIM_STAGE = 5,   /* one LIM Chebyshev stage */
-    CH_KERNEL_DC_ITER = 6      /* one whole DCGS2 iteration: matvec, dot totals, update */
+    CH_KERNEL_DC_ITER = 6,     /* one whole DCGS2 iteration: matvec, dot totals, update */
+    CH_KERNEL_LIM_STAGE2 = 7   /* two consecutive LIM stages in one launch (2-D only: the form
+                                  ch_run_lim uses there for every stage after the first) */
 };
 
 /*
  * Measurement aid for the roofline figures: `count` back-to-back launches of
  * one kernel of the path, bracketed by HIP events on the context's stream, on
  * the workspace of an earlier run on this problem (ch_run_ee with Krylov
- * dimension >= m_max; ch_run_lim for CH_KERNEL_LIM_STAGE).  iters[i] is the
+ * dimension >= m_max; ch_run_lim for CH_KERNEL_LIM_STAGE and CH_KERNEL_LIM_STAGE2).  iters[i] is the
  * Arnoldi iteration of launch i: CH_KERNEL_DC_MATVEC 0..m_max (w stored below
  * m_max), CH_KERNEL_DC_UPDATE and CH_KERNEL_DC_ITER 0..m_max-1, CH_KERNEL_MGS (pass 1 of the
  * iteration) 1..m_max-1, CH_KERNEL_MATVEC 0..m_max-1, CH_KERNEL_PHI (a
  * not-converged test of that dimension) 1..min(m_max-1, last step's j);
- * ignored (may be NULL) for CH_KERNEL_LIM_STAGE.  The DCGS2 and LIM kernels
+ * ignored (may be NULL) for the two LIM kernels; CH_KERNEL_LIM_STAGE2 on a 3-D
+ * problem returns CH_EINVAL.  The DCGS2 and LIM kernels
  * are launched under a symbol of their own, so a profiler reports these
  * launches apart from the path's.  *total_us: elapsed time of the sequence;
  * *total_bytes: its algorithmic bytes (each operand vector read or written

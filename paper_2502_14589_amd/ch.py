@@ -29,7 +29,7 @@ EXPORTED = (
 )
 CH_REQ_QUEUED, CH_REQ_RUNNING, CH_REQ_DONE, CH_REQ_FAILED = 0, 1, 2, 3
 CH_KERNEL_MGS, CH_KERNEL_MATVEC, CH_KERNEL_PHI = 0, 1, 2
-CH_KERNEL_DC_MATVEC, CH_KERNEL_DC_UPDATE, CH_KERNEL_LIM_STAGE, CH_KERNEL_DC_ITER = 3, 4, 5, 6
+CH_KERNEL_DC_MATVEC, CH_KERNEL_DC_UPDATE, CH_KERNEL_LIM_STAGE, CH_KERNEL_DC_ITER, CH_KERNEL_LIM_STAGE2 = 3, 4, 5, 6, 7
 CH_ORTH_DCGS2, CH_ORTH_MGS = 0, 1
 
 

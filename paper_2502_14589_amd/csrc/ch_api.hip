@@ -544,12 +544,17 @@ int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double 
         if (ctx->hctl[0].halted) break;
         const int p = ctx->hctl[0].p;
         // 2p - 1 stages (the nodes in the plan's order, then again without
-        // beta_1) ping-pong between zbuf and yout so that the last one lands in yout.
+        // beta_1) ping-pong between zbuf and yout so that the last launch
+        // writes yout.  On 2-D strips stage 0 runs alone and the rest in
+        // pairs, two stages per launch.
         const int nst = 2 * p - 1;
+        const bool pairs = lim_stage_pairs(t);
+        const int nl = pairs ? p : nst;
         const double* src = yin;
-        for (int q = 0; q < nst; ++q) {
-            double* dst = ((nst - 1 - q) % 2 == 0) ? yout : b.zbuf;
-            HIP_TRY(ctx, launch_lim_stage(t, b, yin, src, dst, q, ctx->stream));
+        for (int l = 0; l < nl; ++l) {
+            double* dst = ((nl - 1 - l) % 2 == 0) ? yout : b.zbuf;
+            if (pairs && l > 0) HIP_TRY(ctx, launch_lim_stage2(t, b, yin, src, dst, 2 * l - 1, ctx->stream));
+            else HIP_TRY(ctx, launch_lim_stage(t, b, yin, src, dst, l, ctx->stream));
             src = dst;
         }
         HIP_TRY(ctx, launch_est_lim(t, b, ps, yin, yout, ctx->stream));
@@ -965,14 +970,13 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
 
 int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, const int* iters, int count,
                    double* total_us, double* total_bytes) {
-    if (!ctx || !total_us || !total_bytes || count < 1 || (!iters && kernel != CH_KERNEL_LIM_STAGE))
-        return CH_EINVAL;
+    const bool lim = kernel == CH_KERNEL_LIM_STAGE || kernel == CH_KERNEL_LIM_STAGE2;
+    if (!ctx || !total_us || !total_bytes || count < 1 || (!iters && !lim)) return CH_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
     Shape sh;
     int rc = check_problem(prob, &sh);
     if (rc) return rc;
-    if (m_max < 1 || m_max > CH_MMAX || kernel < CH_KERNEL_MGS || kernel > CH_KERNEL_DC_ITER) return CH_EINVAL;
-    const bool lim = kernel == CH_KERNEL_LIM_STAGE;
+    if (m_max < 1 || m_max > CH_MMAX || kernel < CH_KERNEL_MGS || kernel > CH_KERNEL_LIM_STAGE2) return CH_EINVAL;
     const int prec = lim ? CH_FP64 : prob->prec;
     const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
     const DevBuffers& b = ctx->b;
@@ -1009,13 +1013,15 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, c
     for (int i = 0; i <= CH_MMAX; ++i) h.vscale[i] = 1.0;
     for (int i = 0; i < CH_DROWS; ++i) h.dt[i] = 0.0;
     for (int i = 0; i <= CH_MMAX; ++i) h.h1[0][i] = h.h1[1][i] = 0.0;
+    if (kernel == CH_KERNEL_LIM_STAGE2 && !lim_stage_pairs(t)) return CH_EINVAL;
     if (lim) {
-        h.p = 1;
+        // order 2, both stage positions with a_m = 0 (node beta_1)
+        h.p = 2;
         h.lam = 1.0;
         if (!(h.tau0 > 0.0)) h.tau0 = 1e-9;
-        const int zero = 0;
-        const double cf[2] = {0.0, 1.0};   // node beta_1: a_1 = 0
-        HIP_TRY(ctx, hipMemcpyAsync(b.lorder, &zero, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+        const int ord[2] = {0, 1};
+        const double cf[4] = {0.0, 1.0, 0.0, 1.0};
+        HIP_TRY(ctx, hipMemcpyAsync(b.lorder, ord, sizeof(ord), hipMemcpyHostToDevice, ctx->stream));
         HIP_TRY(ctx, hipMemcpyAsync(b.lcoef, cf, sizeof(cf), hipMemcpyHostToDevice, ctx->stream));
     }
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
@@ -1048,6 +1054,9 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, c
                 if (e == hipSuccess) e = launch_dc_update(t, prec, b, k, ctx->stream, true);
                 return e;
             }
+            case CH_KERNEL_LIM_STAGE2:  // read y^n, the stage before the pair; write the second
+                bytes += 24.0 * N;
+                return launch_lim_stage2(t, b, y, y, b.zbuf, 0, ctx->stream, true);
             default:                    // read y^n, the previous stage; write the next
                 bytes += 24.0 * N;
                 return launch_lim_stage(t, b, y, y, b.zbuf, 0, ctx->stream, true);

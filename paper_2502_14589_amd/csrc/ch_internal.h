@@ -175,6 +175,8 @@ hipError_t launch_matvec_strip(const Table& t, int prec, const DevBuffers& b, co
                                bool store_w, double* pout, bool timing, hipStream_t s);
 hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
                                   int pos, bool timing, hipStream_t s);
+hipError_t launch_lim_stage2_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
+                                   int pos, bool timing, hipStream_t s);
 hipError_t launch_est_ee_strip(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
                                double* pout, hipStream_t s);
 // 3-D DCGS2 matvec on z-marching x-y tiles (ch_march.hip); its workgroups are
@@ -225,6 +227,10 @@ hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, hip
 // Stage pos (0 .. 2p - 2) of the LIM step.
 hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
                             int pos, hipStream_t s, bool timing = false);
+// Stages pos and pos + 1 in one launch (2-D strips only: lim_stage_pairs).
+inline bool lim_stage_pairs(const Table& t) { return uses_strips(t); }
+hipError_t launch_lim_stage2(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
+                             int pos, hipStream_t s, bool timing = false);
 hipError_t launch_est_lim(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y0, const double* y1,
                           hipStream_t s);
 hipError_t launch_lim_end(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s);

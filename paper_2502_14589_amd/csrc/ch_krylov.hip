@@ -1257,43 +1257,82 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctls, 
 // the growth of intermediate stages, and so the amplification of rounding,
 // small (below 10^7.2 up to p = 4096, against 10^105 at p = 209 for the
 // order i = 1..p).  0-based indices into order[0..p); one workgroup.
-__device__ void lim_leja_order(int p, int* __restrict__ order) {
-    __shared__ double nd[CH_PMAX], score[CH_PMAX];
-    __shared__ unsigned char taken[CH_PMAX];
-    __shared__ double red[CH_BLOCK / 64][1];
-    __shared__ double best_s;
-    __shared__ int pick;
-    const double pi = 3.141592653589793;
-    for (int i = threadIdx.x; i < p; i += CH_BLOCK) {
-        nd[i] = cos(pi * double(2 * i + 1) / double(2 * p));
-        score[i] = 0.0;
-        taken[i] = 0;
-    }
+// The log-distances come from one table: with theta_i = pi (2i + 1) / (2p),
+// cos a - cos b = -2 sin((a + b)/2) sin((a - b)/2) gives
+//   log|beta_i - beta_r| = log 2 + L[i + r + 1] + L[|i - r|],
+//   L[k] = log sin(pi k / (2p)),  1 <= k <= 2p - 1,
+// so a step costs two table reads per open node instead of a logarithm (and
+// has no cancellation between nearby nodes).  The sums stay in registers; a
+// pick costs two workgroup reductions.  order is in LDS.
+// Wave-wide reduction with a uniform result: DPP within the four rows, then
+// the four row results by readlane (no LDS permute on the critical path).
+template <typename Op>
+__device__ __forceinline__ double wave_reduce_rl(double x, Op op) {
+    x = op(x, dpp_move<DPP_XOR1>(x));
+    x = op(x, dpp_move<DPP_XOR2>(x));
+    x = op(x, dpp_move<DPP_HMIR>(x));
+    x = op(x, dpp_move<DPP_MIR>(x));
+    return op(op(readlane_d(x, 0), readlane_d(x, 16)), op(readlane_d(x, 32), readlane_d(x, 48)));
+}
+
+__device__ __forceinline__ void lim_leja_order(int p, int* __restrict__ order) {
+    constexpr int K = CH_PMAX / CH_BLOCK, G = 8, NW = CH_BLOCK / 64;
+    __shared__ double L[2 * CH_PMAX];
+    __shared__ double wmax[NW], wmin[NW];
+    const double pi = 3.141592653589793, log2 = 0.6931471805599453;
+    for (int k = threadIdx.x; k < 2 * CH_PMAX; k += CH_BLOCK)
+        L[k] = (k == 0 || k >= 2 * p) ? 0.0 : log(sin(pi * double(k) / double(2 * p)));
+    // Thread t owns nodes t + CH_BLOCK k, in groups of G whose table reads are
+    // in flight together.  Taken nodes and nodes past p hold -inf, which no
+    // update or comparison changes.
+    const int tid = threadIdx.x, w = tid >> 6;
+    const int gn = (p + CH_BLOCK * G - 1) / (CH_BLOCK * G);
+    double sc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) sc[k] = tid + CH_BLOCK * k < p ? 0.0 : -__builtin_inf();
     __syncthreads();
     int r = 0;
     for (int s = 0; s < p; ++s) {
-        if (threadIdx.x == 0) order[s] = r;
-        const double br = nd[r];
-        for (int i = threadIdx.x; i < p; i += CH_BLOCK) {
-            if (i == r) taken[i] = 1;
-            else score[i] += log(fabs(nd[i] - br));
+        if (tid == 0) order[s] = r;
+        double best = -__builtin_inf();
+#pragma unroll
+        for (int g = 0; g < K / G; ++g) {
+            if (g < gn) {
+#pragma unroll
+                for (int k = g * G; k < g * G + G; ++k) {
+                    const int i = tid + CH_BLOCK * k, d = i - r;
+                    const double t = log2 + (L[i + r + 1] + L[d < 0 ? -d : d]);
+                    // the node just taken becomes -inf; an added mask (rather
+                    // than a select) keeps the loop free of branches
+                    sc[k] = (sc[k] + t) + (d == 0 ? -__builtin_inf() : 0.0);
+                    best = fmax(best, sc[k]);
+                }
+            }
         }
-        __syncthreads();
         if (s == p - 1) break;
-        double v[1] = {-__builtin_inf()};
-        for (int i = threadIdx.x; i < p; i += CH_BLOCK)
-            if (!taken[i]) v[0] = fmax(v[0], score[i]);
-        block_reduce<1, RED_MAX>(v, red);
-        if (threadIdx.x == 0) best_s = v[0];
+        best = wave_reduce_rl(best, [](double x, double y) { return fmax(x, y); });
+        if ((tid & 63) == 0) wmax[w] = best;
         __syncthreads();
-        const double lim = best_s - 1e-9 * fmax(1.0, fabs(best_s));
-        double c[1] = {double(p)};
-        for (int i = threadIdx.x; i < p; i += CH_BLOCK)
-            if (!taken[i] && score[i] >= lim) c[0] = fmin(c[0], double(i));
-        block_reduce<1, RED_MIN>(c, red);
-        if (threadIdx.x == 0) pick = (int)c[0];
+        best = wmax[0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) best = fmax(best, wmax[q]);
+        const double lim = best - 1e-9 * fmax(1.0, fabs(best));
+        double c = double(p);
+#pragma unroll
+        for (int g = K / G - 1; g >= 0; --g) {
+            if (g < gn) {
+#pragma unroll
+                for (int k = g * G + G - 1; k >= g * G; --k)
+                    if (sc[k] >= lim) c = double(tid + CH_BLOCK * k);
+            }
+        }
+        c = wave_reduce_rl(c, [](double x, double y) { return fmin(x, y); });
+        if ((tid & 63) == 0) wmin[w] = c;
         __syncthreads();
-        r = pick;
+        c = wmin[0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) c = fmin(c, wmin[q]);
+        r = (int)c;
     }
 }
 
@@ -1358,9 +1397,11 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, c
     __syncthreads();
     const int p = sp;
     if (p == 0) return;
-    int* order = orders + (size_t)I.slot * CH_PMAX;
+    __shared__ int order[CH_PMAX];
     lim_leja_order(p, order);
     __syncthreads();
+    int* gorder = orders + (size_t)I.slot * CH_PMAX;
+    for (int i = threadIdx.x; i < p; i += CH_BLOCK) gorder[i] = order[i];
     // Fig. 1: beta_i = cos(pi (2i - 1) / (2p)), z_1 = beta_1,
     // a_m = lambda_max (z_1 - beta_m) / (1 + z_1).  Stage position pos takes
     // the node order[pos] (first sweep, pos < p) or order[pos - p + 1]

@@ -537,6 +537,12 @@ hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq&
                       : launch_est_ee_t<3, float>(t, b, ps, y0, y1, b.y32, s);
 }
 
+hipError_t launch_lim_stage2(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
+                             int pos, hipStream_t s, bool timing) {
+    if (!lim_stage_pairs(t)) return hipErrorInvalidValue;
+    return launch_lim_stage2_strip(t, b, y, z, out, pos, timing, s);
+}
+
 hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
                             int pos, hipStream_t s, bool timing) {
     if (uses_strips(t)) return launch_lim_stage_strip(t, b, y, z, out, pos, timing, s);

@@ -449,6 +449,129 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage_s(Ctl* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Two consecutive LIM stages (positions pos and pos + 1) in one pass: the
+// first stage's result stays in registers.  A strip of LIM2_ROWS output rows
+// reads z with a halo of 4 rows and 4 columns (two stencil radii) and y^n with
+// a halo of 3 rows; the HBM traffic of the pair is that of one stage (read
+// y^n and z, write the result).  Each point is computed with the same
+// expressions as two launches of the single stage.  Two rows per strip: with
+// four, the registers (192) leave two waves per SIMD and the pair is slower;
+// sharing the block's rows through LDS exposes their load latency at the
+// barrier and is slower too.
+// ---------------------------------------------------------------------------
+#ifndef CH_LIM2_ROWS
+#define CH_LIM2_ROWS 2
+#endif
+constexpr int LIM2_ROWS = CH_LIM2_ROWS;
+template <int VX>
+constexpr int lim2_halo_lanes() { return VX >= 2 ? 2 : 4; }   // 4 columns
+template <int VX>
+constexpr int lim2_cols() { return (64 - 2 * lim2_halo_lanes<VX>()) * VX; }
+
+// Periodic row index for any r.
+__device__ __forceinline__ int wrap_row_any(int r, int n) {
+    r %= n;
+    return r < 0 ? r + n : r;
+}
+
+template <int VX>
+__device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restrict__ ybase,
+                                            const double* __restrict__ zbase, double* __restrict__ obase,
+                                            double ta1, double inv1, double ta2, double inv2, double tau, int wv) {
+    constexpr int R = LIM2_ROWS, HL = lim2_halo_lanes<VX>(), OW = lim2_cols<VX>(), W = CH_STRIP_WAVES;
+    constexpr int NZ = R + 8, NY = R + 6, NQ1 = R + 6, NO1 = R + 4, NQ2 = R + 2;
+    const int lane = threadIdx.x & 63;
+    const int n = I.n;
+    const double* Z = zbase + I.off;
+    const double* Y = ybase + I.off;
+    double* O = obase + I.off;
+    const double inv_h2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
+    const int eyre = I.eyre;
+    const unsigned rb = (unsigned)n * 8u;
+    const int nsx = (n + OW - 1) / OW;
+    const int ns = nsx * ((n + R - 1) / R);
+    const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
+    for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
+        const int sx = s % nsx, r0 = (s / nsx) * R;
+        const int c = sx * OW + (lane - HL) * VX;
+        int xl = c % n;
+        if (xl < 0) xl += n;
+        const bool out = lane >= HL && lane < 64 - HL && c < n;
+        const unsigned bo = (unsigned)xl * 8u;
+        const unsigned bs = c < n + HL * VX ? bo : OFF_ROW;
+        // z rows r0 - 4 + j, y rows r0 - 3 + j
+        double z[NZ][VX], y[NY][VX];
+#pragma unroll
+        for (int j = 0; j < NZ; ++j)
+            load_row<double, VX>(row_rsrc(Z + (size_t)wrap_row_any(r0 - 4 + j, n) * n, rb), bs, z[j]);
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+            load_row<double, VX>(row_rsrc(Y + (size_t)wrap_row_any(r0 - 3 + j, n) * n, rb), bs, y[j]);
+        // first stage: q1 on rows r0 - 3 + j, its result o1 on rows r0 - 2 + j
+        double q1[NQ1][VX];
+#pragma unroll
+        for (int j = 0; j < NQ1; ++j) {
+            const double xl1 = wave_shift<DPP_WAVE_SHR1>(z[j + 1][VX - 1]), xr1 = wave_shift<DPP_WAVE_SHL1>(z[j + 1][0]);
+#pragma unroll
+            for (int e = 0; e < VX; ++e)
+                q1[j][e] = dcoef(y[j][e], eyre) * z[j + 1][e] + e2ih2 * lap5<double, VX>(z[j], z[j + 1], z[j + 2], xl1, xr1, e) -
+                           ccoef(y[j][e], eyre);
+        }
+        double o1[NO1][VX];
+#pragma unroll
+        for (int j = 0; j < NO1; ++j) {
+            const double xl1 = wave_shift<DPP_WAVE_SHR1>(q1[j + 1][VX - 1]), xr1 = wave_shift<DPP_WAVE_SHL1>(q1[j + 1][0]);
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const double r = -inv_h2 * lap5<double, VX>(q1[j], q1[j + 1], q1[j + 2], xl1, xr1, e);
+                o1[j][e] = (y[j + 1][e] + ta1 * z[j + 2][e] + tau * r) * inv1;
+            }
+        }
+        // second stage: q2 on rows r0 - 1 + j, the output on rows r0 + i
+        double q2[NQ2][VX];
+#pragma unroll
+        for (int j = 0; j < NQ2; ++j) {
+            const double xl1 = wave_shift<DPP_WAVE_SHR1>(o1[j + 1][VX - 1]), xr1 = wave_shift<DPP_WAVE_SHL1>(o1[j + 1][0]);
+#pragma unroll
+            for (int e = 0; e < VX; ++e)
+                q2[j][e] = dcoef(y[j + 2][e], eyre) * o1[j + 1][e] +
+                           e2ih2 * lap5<double, VX>(o1[j], o1[j + 1], o1[j + 2], xl1, xr1, e) - ccoef(y[j + 2][e], eyre);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const double xl1 = wave_shift<DPP_WAVE_SHR1>(q2[i + 1][VX - 1]), xr1 = wave_shift<DPP_WAVE_SHL1>(q2[i + 1][0]);
+            double o[VX];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                const double r = -inv_h2 * lap5<double, VX>(q2[i], q2[i + 1], q2[i + 2], xl1, xr1, e);
+                o[e] = (y[i + 3][e] + ta2 * o1[i + 2][e] + tau * r) * inv2;
+            }
+            if (out && r0 + i < n) store_row<double, VX>(row_rsrc(O + (size_t)(r0 + i) * n, rb), bo, o);
+        }
+    }
+}
+
+template <bool SINGLE, int TAG, int VX>
+__global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage2_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                           const int* __restrict__ wb2i, const Inst inst0, int ninst,
+                                                           const double* __restrict__ ybase,
+                                                           const double* __restrict__ zbase, double* __restrict__ obase,
+                                                           const double* __restrict__ coefs, int pos) {
+    const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->halted || pos + 1 >= 2 * ctl->p - 1) return;
+    const double* cf = coefs + ((size_t)I.slot * 2 * CH_PMAX + pos) * 2;
+    const double ta1 = cf[0], inv1 = cf[1], ta2 = cf[2], inv2 = cf[3], tau = ctl->tau0;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if constexpr (VX > 0) {
+        lim2_strips<VX>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
+    } else {
+        if (I.vx == 1) lim2_strips<1>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
+        else lim2_strips<2>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // EE2 estimate and next start vector (Fig. 4; eq. LIMest):
 //   f1 = f(y^{n+1});  y_PC = y^n + tau/2 (f(y^n) + f1)  (eq. LIMest, since
 //   f(y) = -A (F'(y) + eps^2 A y));  est = ||y^{n+1} - y_PC|| / ||y_PC||.
@@ -614,6 +737,21 @@ hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const dou
         else hipLaunchKernelGGL((k_lim_stage_s<true, 0, 1>), WARGS, y, z, out, b.lcoef, pos);
     } else {
         hipLaunchKernelGGL((k_lim_stage_s<false, 0, 0>), WARGS, y, z, out, b.lcoef, pos);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lim_stage2_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
+                                   int pos, bool timing, hipStream_t s) {
+    const bool two = t.hinst[0].vx >= 2;
+    if (timing) {
+        if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 1, 2>), WARGS, y, z, out, b.lcoef, pos);
+        else hipLaunchKernelGGL((k_lim_stage2_s<true, 1, 1>), WARGS, y, z, out, b.lcoef, pos);
+    } else if (t.ninst == 1) {
+        if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 2>), WARGS, y, z, out, b.lcoef, pos);
+        else hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 1>), WARGS, y, z, out, b.lcoef, pos);
+    } else {
+        hipLaunchKernelGGL((k_lim_stage2_s<false, 0, 0>), WARGS, y, z, out, b.lcoef, pos);
     }
     return hipGetLastError();
 }

@@ -71,7 +71,8 @@ def test_header_constants_match_binding():
     assert f"#define CH_PMAX {ch.CH_PMAX}" in text
     for name in ("CH_OK", "CH_EINVAL", "CH_ENOMEM", "CH_ENONFINITE", "CH_ETAU_UNDERFLOW", "CH_EDEVICE",
                  "CH_ORTH_DCGS2", "CH_ORTH_MGS", "CH_KERNEL_MGS", "CH_KERNEL_MATVEC", "CH_KERNEL_PHI",
-                 "CH_KERNEL_DC_MATVEC", "CH_KERNEL_DC_UPDATE", "CH_KERNEL_LIM_STAGE", "CH_KERNEL_DC_ITER"):
+                 "CH_KERNEL_DC_MATVEC", "CH_KERNEL_DC_UPDATE", "CH_KERNEL_LIM_STAGE", "CH_KERNEL_DC_ITER",
+                 "CH_KERNEL_LIM_STAGE2"):
         m = re.search(rf"{name}\s*=\s*(-?\d+)", text)
         assert m and int(m.group(1)) == getattr(ch, name)
 

@@ -234,9 +234,14 @@ def test_constant_ee_with_restarts(ctx):
 
 # --- LIM (Fig. 1, Fig. 2) ------------------------------------------------------------------
 
-@pytest.mark.parametrize("dim,n,eps,tau", [(2, 40, 0.05, 1e-4), (2, 130, 0.02, 1e-5), (3, 12, 0.05, 1e-4)])
+@pytest.mark.parametrize("dim,n,eps,tau", [(2, 40, 0.05, 1e-4), (2, 130, 0.02, 1e-5), (3, 12, 0.05, 1e-4),
+                                            (2, 41, 0.05, 1e-4), (2, 7, 0.2, 1e-3), (2, 6, 0.2, 1e-3),
+                                            (2, 5, 0.3, 1e-3), (2, 64, 0.05, 1e-7)])
 def test_lim_constant_steps_parity(ctx, dim, n, eps, tau):
-    say(f"LIM const dim={dim} n={n}")
+    """2-D: stage 0 alone, then two stages per launch (their halo of 4 rows
+    and columns wraps the period several times for n = 5..7; odd n use one
+    column per lane; p = 1 has no pair, p = 2 one)."""
+    say(f"LIM const dim={dim} n={n} tau={tau}")
     po, pg = probs(dim, n, eps)
     y0 = uniform_field(n, dim, 0.1, 0.3, seed=400 + n)
     y_ref, ps = O.lim_const_run(y0, po, tau, 6)

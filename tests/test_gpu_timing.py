@@ -87,6 +87,19 @@ def test_time_kernel_lim_stage(ctx):
     assert us > 0 and nb == 7 * 24 * n * n
     with pytest.raises(ch.ChError):
         ctx.time_kernel(pg, ch.CH_KERNEL_LIM_STAGE, 1, count=0)
+    us2, nb2 = ctx.time_kernel(pg, ch.CH_KERNEL_LIM_STAGE2, 1, count=5)
+    assert us2 > 0 and nb2 == 5 * 24 * n * n
+
+
+def test_time_kernel_lim_stage_pair_is_2d_only(ctx):
+    n = 12
+    say("ch_time_kernel LIM stage pair on 12^3: rejected")
+    pg = ch.Problem(3, n, 0.05)
+    y = dev(uniform_field(n, 3, 0.1, 0.05, seed=613))
+    ctx.run_lim(pg, y, 1e-7, T=1e-6, max_steps=1, tol=1e-4)
+    ctx.time_kernel(pg, ch.CH_KERNEL_LIM_STAGE, 1, count=2)
+    with pytest.raises(ch.ChError):
+        ctx.time_kernel(pg, ch.CH_KERNEL_LIM_STAGE2, 1, count=2)
 
 
 def test_time_kernel_needs_workspace():
