@@ -3,6 +3,7 @@
 1024^2 (eps = 0.01, y0 = 0.1 + U(-0.05, 0.05)): the first adaptive EE2 steps
 from tau0 = T = 1e-3 (the first one runs the residual-time trace from 1e-3
 down to ~1e-8), element by element against the oracle.
+One LIM step of the same field (p = 33 and 66), element by element.
 256^3 (eps = 0.02): element-by-element LIM step, the 3-D start-vector stencil
 at sampled points, mass conservation of a full EE2 step.
 """
@@ -95,6 +96,24 @@ def test_large_2d_first_steps_fp32_mixed_adaptive(ctx, large_ref):
     assert abs(st["t"] - t_ref) <= 1e-2 * t_ref
     y = yg.cpu().numpy()
     assert abs(y.sum() - y0.sum()) <= 1e-7 * np.abs(y0).sum()
+
+
+@pytest.mark.parametrize("tau", [2.5e-7, 1e-6])
+def test_large_2d_lim_step_elementwise(ctx, tau):
+    """One LIM step of the 1024^2 workload at the adaptive run's first step
+    (tau = 2.5e-7: p = 33) and at four times it (p = 66): stage 0 alone, then
+    32 or 65 launches of two stages, element by element against the oracle."""
+    say(f"1024^2 LIM step tau={tau:g}")
+    po, pg = O.Problem(2, 1024, 0.01), ch.Problem(2, 1024, 0.01)
+    y0 = large_2d_field(1, 1024)
+    y_ref, p = O.lim_step(y0, po, tau)
+    assert p == {2.5e-7: 33, 1e-6: 66}[tau]
+    yg = dev(y0)
+    rec = ctx.step_lim(pg, yg, tau)
+    assert rec["j"] == p and rec["matvecs"] == 2 * p - 1
+    y = yg.cpu().numpy()
+    assert rel(y, y_ref) <= 1e-10
+    assert float(np.max(np.abs(y - y_ref))) <= 1e-10 * float(np.max(np.abs(y_ref)))
 
 
 def test_cube_3d_lim_step_elementwise(ctx):
