@@ -273,6 +273,29 @@ def test_lim_large_order_parity(ctx, tl):
     assert rel(host(yg), y_ref) <= TOL_FP64
 
 
+def test_lim_maximum_order(ctx):
+    """p = CH_PMAX = 4096 (8191 stages: stage 0, then 4095 two-stage
+    launches; the plan's Leja order at its largest size) against the oracle
+    at the FP64 tolerance (the Leja order keeps the rounding of 8191 stages
+    small: ~3e-13 measured), and p = CH_PMAX + 1 refused with CH_EINVAL."""
+    say("LIM at the maximum order")
+    po, pg = probs(2, 64, 0.01)
+    y0 = uniform_field(64, 2, 0.7, 0.05, seed=421)
+    lam = O.lambda_max(y0, po)
+    y_ref, p = O.lim_step(y0, po, 2.7195e7 / lam)
+    assert p == ch.CH_PMAX
+    yg = dev(y0)
+    rec = ctx.step_lim(pg, yg, 2.7195e7 / lam)
+    assert rec["j"] == p and rec["matvecs"] == 2 * p - 1
+    err = rel(host(yg), y_ref)
+    say(f"  p = {p}: rel. difference {err:.3e}")
+    assert err <= TOL_FP64
+    yg = dev(y0)
+    with pytest.raises(ch.ChError) as e:
+        ctx.step_lim(pg, yg, 2.75e7 / lam)
+    assert e.value.status == ch.CH_EINVAL
+
+
 def test_small_2d_lim_200_steps(ctx):
     say("LIM constant 64^2 x 200")
     po, pg = probs(2, 64, 0.05)
