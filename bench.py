@@ -151,7 +151,12 @@ def lim_form(ctx, ch, torch, y0, steps, warmup):
                                "bound": "hbm", "achieved": round(stage["achieved_GBps"], 1), "peak": HBM_PEAK_GBPS,
                                "unit": "GB/s", "frac": round(stage["achieved_GBps"] / HBM_PEAK_GBPS, 4),
                                "avg_launch_us": round(stage["avg_launch_us"], 3),
-                               "bytes_per_launch": stage["bytes_per_launch"], "launches": stage["launches"]}}
+                               "bytes_per_launch": stage["bytes_per_launch"], "launches": stage["launches"]},
+            # the stage rate in the terms of the one-stage form (24 bytes per
+            # point per stage): the bandwidth that form would need to match it
+            "per_stage_us": round(stage["avg_launch_us"] / 2.0, 3),
+            "single_stage_equivalent_GBps": round(2.0 * stage["achieved_GBps"], 1),
+            "single_stage_equivalent_frac": round(2.0 * stage["achieved_GBps"] / HBM_PEAK_GBPS, 4)}
 
 
 def c3_form(ctx, ch, torch, steps: int = 20, warmup: int = 0):
