@@ -116,6 +116,23 @@ def test_large_2d_lim_step_elementwise(ctx, tau):
     assert float(np.max(np.abs(y - y_ref))) <= 1e-10 * float(np.max(np.abs(y_ref)))
 
 
+@pytest.mark.parametrize("n", [2048, 1999])
+def test_large_2d_lim_step_wide_grids(ctx, n):
+    """A LIM step of order 3 (stage 0, then two two-stage launches) on grids
+    larger than the workload: 2048^2 (two FP64 values per lane) and the odd
+    1999^2 (one value per lane, a ragged last strip in both directions)."""
+    say(f"{n}^2 LIM step, p = 3")
+    po, pg = O.Problem(2, n, 0.01), ch.Problem(2, n, 0.01)
+    y0 = uniform_field(n, 2, 0.1, 0.05, seed=700 + n)
+    tau = 12.0 / O.lambda_max(y0, po)
+    y_ref, p = O.lim_step(y0, po, tau)
+    assert p == 3
+    yg = dev(y0)
+    rec = ctx.step_lim(pg, yg, tau)
+    assert rec["j"] == p
+    assert rel(yg.cpu().numpy(), y_ref) <= 1e-10
+
+
 def test_cube_3d_lim_step_elementwise(ctx):
     say("256^3 LIM step")
     po, pg = O.Problem(3, 256, 0.02), ch.Problem(3, 256, 0.02)
