@@ -4,7 +4,7 @@
 from tau0 = T = 1e-3 (the first one runs the residual-time trace from 1e-3
 down to ~1e-8), element by element against the oracle.
 One LIM step of the same field (p = 33 and 66), element by element; LIM
-steps on 2048^2 and 1999^2, and a traced EE2 step on 1999^2.
+steps on 2048^2 and 1999^2, and traced EE2 steps on 1999^2 and 127^3.
 256^3 (eps = 0.02): element-by-element LIM step, the 3-D start-vector stencil
 at sampled points, mass conservation of a full EE2 step.
 """
@@ -148,6 +148,24 @@ def test_odd_wide_grid_ee_step_traced(ctx):
     for prec, tol in ((ch.CH_FP64, 1e-10), (ch.CH_FP32_MIXED, 1e-5)):
         yg = dev(y0)
         rec = ctx.step_ee(ch.Problem(2, n, 0.01, False, prec), yg, 1e-8, m_max=12, tol_phi_fixed=1e-8)
+        assert rec["j"] == 12 and rec["traced"] == 1
+        assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12 if prec == ch.CH_FP64 else 1e-5)
+        assert rel(yg.cpu().numpy(), y_ref) <= tol
+
+
+def test_odd_cube_ee_step_traced(ctx):
+    """One EE2 step on the odd 127^3 grid (the marching matvec's 64 x 8 tiles
+    and 16-plane runs all ragged) from tau0 = 1e-6 with Krylov dimension 12:
+    traced.  FP64 to the parity tolerance, FP32-mixed to 1e-5."""
+    n = 127
+    say(f"{n}^3 EE2 step with trace")
+    po = O.Problem(3, n, 0.02)
+    y0 = uniform_field(n, 3, 0.0, 0.05, seed=3127)
+    y_ref, tau_ref, info = O.ee_step(y0, po, 1e-6, 1e-8, 12)
+    assert not info.converged and info.j == 12
+    for prec, tol in ((ch.CH_FP64, 1e-10), (ch.CH_FP32_MIXED, 1e-5)):
+        yg = dev(y0)
+        rec = ctx.step_ee(ch.Problem(3, n, 0.02, False, prec), yg, 1e-6, m_max=12, tol_phi_fixed=1e-8)
         assert rec["j"] == 12 and rec["traced"] == 1
         assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12 if prec == ch.CH_FP64 else 1e-5)
         assert rel(yg.cpu().numpy(), y_ref) <= tol
