@@ -3,7 +3,8 @@
 1024^2 (eps = 0.01, y0 = 0.1 + U(-0.05, 0.05)): the first adaptive EE2 steps
 from tau0 = T = 1e-3 (the first one runs the residual-time trace from 1e-3
 down to ~1e-8), element by element against the oracle.
-One LIM step of the same field (p = 33 and 66), element by element; LIM
+One LIM step of the same field (p = 33 and 66) and its first 6 adaptive LIM
+steps, element by element; LIM
 steps on 2048^2 and 1999^2, and traced EE2 steps on 1999^2 and 127^3.
 256^3 (eps = 0.02): element-by-element LIM step, the 3-D start-vector stencil
 at sampled points, mass conservation of a full EE2 step.
@@ -115,6 +116,21 @@ def test_large_2d_lim_step_elementwise(ctx, tau):
     y = yg.cpu().numpy()
     assert rel(y, y_ref) <= 1e-10
     assert float(np.max(np.abs(y - y_ref))) <= 1e-10 * float(np.max(np.abs(y_ref)))
+
+
+def test_large_2d_lim_adaptive_first_steps(ctx):
+    """The first 6 adaptive LIM steps (Fig. 2) of the 1024^2 workload as the
+    benchmark runs them (tol 1e-4, tau0 = 2.5e-7): orders, steps and the
+    field against the oracle."""
+    say("1024^2 adaptive LIM, 6 steps")
+    po, pg = O.Problem(2, 1024, 0.01), ch.Problem(2, 1024, 0.01)
+    y0 = large_2d_field(1, 1024)
+    y_ref, rec_ref = O.lim_adaptive(y0, po, 2.5e-7, 1e-3, 1e-4, max_steps=6)
+    yg = dev(y0)
+    st, recs = ctx.run_lim(pg, yg, 2.5e-7, T=1e-3, max_steps=6, tol=1e-4, records=True)
+    assert [r["j"] for r in recs] == rec_ref.js
+    np.testing.assert_allclose([r["tau"] for r in recs], rec_ref.taus, rtol=1e-10)
+    assert rel(yg.cpu().numpy(), y_ref) <= 1e-10
 
 
 @pytest.mark.parametrize("n", [2048, 1999])
