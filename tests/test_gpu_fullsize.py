@@ -4,8 +4,8 @@
 from tau0 = T = 1e-3 (the first one runs the residual-time trace from 1e-3
 down to ~1e-8), element by element against the oracle.
 One LIM step of the same field (p = 33 and 66) and its first 6 adaptive LIM
-steps, element by element; LIM
-steps on 2048^2 and 1999^2, and traced EE2 steps on 1999^2 and 127^3.
+steps, element by element; LIM steps on 2048^2 and 1999^2, and traced EE2
+steps on 1999^2 and 127^3.
 256^3 (eps = 0.02): element-by-element LIM step, the 3-D start-vector stencil
 at sampled points, mass conservation of a full EE2 step.
 """
