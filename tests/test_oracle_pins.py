@@ -421,6 +421,96 @@ def test_order_ee2_two_lim_one():
     assert all(0.8 <= r <= 1.3 for r in r_lim), (errs_lim, r_lim)
 
 
+# --- P16: the predictor-corrector estimate (eq. LIMest, Section 3.3) ------------------------------
+#
+# On an even grid the checkerboard mode v = (-1)^(sum of indices) has v^2 = 1,
+# so the span of {1, v} is closed under the cubic F'(y) = y^3 - y and both
+# A 1 = 0 and A v = lam v with lam = 4 dim / h^2 (the highest Fourier mode).
+# For y = c + a v:  F'(y) = (c^3 + 3 c a^2 - c) + (3 c^2 a + a^3 - a) v  exactly,
+# so f(y) = -lam (3 c^2 a + a^3 - a + eps^2 lam a) v  and, with
+# y^n = c + a v and y^{n+1} = c + b v,
+#     y_PC = c + p v,  p = a + tau/2 (f_a + f_b),
+#     est  = |b - p| / sqrt(c^2 + p^2)          (v is orthogonal to 1, |v|^2 = |1|^2 = N).
+# Everything is exact: no linearisation, any amplitude.
+
+def checkerboard(prob):
+    idx = np.indices(prob.shape).sum(axis=0)
+    return np.where(idx % 2 == 0, 1.0, -1.0).ravel()
+
+
+def est_closed_form(dim, h, eps, c, a, b, tau, *, sign=1.0, half=0.5, norm_by="pc"):
+    """eq. LIMest for y^n = c + a v, y^{n+1} = c + b v (checkerboard v).  The
+    keyword arguments build the plausible mistakes the pin must reject."""
+    lam = 4.0 * dim / h ** 2
+
+    def f_coef(x):
+        return -lam * (3 * c * c * x + x ** 3 - x + eps ** 2 * lam * x)
+
+    p = a + sign * half * tau * (f_coef(a) + f_coef(b))
+    den = math.hypot(c, p) if norm_by == "pc" else math.hypot(c, b)
+    return abs(b - p) / den, p
+
+
+PC_CASES = [
+    # dim, n, eps, c, a, b, tau
+    (2, 16, 0.05, 0.3, 0.2, 0.15, 2e-6),
+    (2, 8, 0.1, -0.4, 0.05, -0.02, 1e-4),
+    (3, 6, 0.08, 0.6, -0.3, -0.25, 1e-5),
+    (2, 32, 0.02, 0.0, 0.7, 0.69, 1e-7),
+]
+
+
+@pytest.mark.parametrize("case", PC_CASES)
+def test_pc_estimate_checkerboard_closed_form(case):
+    dim, n, eps, c, a, b, tau = case
+    prob = O.Problem(dim, n, eps)
+    v = checkerboard(prob)
+    est, y_pc = O.pc_estimate(c + a * v, c + b * v, tau, prob)
+    want, p = est_closed_form(dim, prob.h, eps, c, a, b, tau)
+    assert est == pytest.approx(want, rel=1e-11)
+    np.testing.assert_allclose(y_pc, c + p * v, rtol=0, atol=1e-12 * (abs(c) + abs(p)))
+    # the case separates the estimate from its plausible misreadings: a sign
+    # flip in y_PC, a dropped 1/2, the norm of y^{n+1} as the denominator
+    for wrong in (dict(sign=-1.0), dict(half=1.0), dict(norm_by="np1")):
+        bad, _ = est_closed_form(dim, prob.h, eps, c, a, b, tau, **wrong)
+        assert abs(bad - want) > 1e-4 * want, wrong
+
+
+def test_pc_estimate_hand_computed_2x2():
+    """2 x 2 periodic grid (h = 1/2, lam = 32), eps = 1/4, tau = 1/1000,
+    y^n = 1/2 + v/5, y^{n+1} = 1/2 + v/10 (v the checkerboard):
+      odd parts of F':  3/4 * 1/5 + 1/125 - 1/5 = -21/500;  3/4 * 1/10 + 1/1000 - 1/10 = -3/125
+      f coefficients:  -32 (-21/500 + 2/5) = -1432/125;   -32 (-3/125 + 1/5) = -704/125
+      p = 1/5 + 1/2000 (-2136/125) = 5983/31250 = 0.191456
+      est = |1/10 - 0.191456| / sqrt(1/4 + 0.191456^2) = 0.091456 / sqrt(0.286655399936)."""
+    prob = O.Problem(2, 2, 0.25)
+    v = np.array([1.0, -1.0, -1.0, 1.0])
+    est, y_pc = O.pc_estimate(0.5 + 0.2 * v, 0.5 + 0.1 * v, 1e-3, prob)
+    assert est == pytest.approx(0.091456 / math.sqrt(0.286655399936), rel=1e-13)
+    np.testing.assert_allclose(y_pc, 0.5 + 0.191456 * v, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("ubar,k,tau", [(0.0, (1, 2), 3e-6), (0.6, (2, 0), 1e-5), (-0.7, (3, 1), 4e-6)])
+def test_pc_estimate_small_mode_linearised(ubar, k, tau):
+    """A small Fourier mode delta cos(2 pi k.x) around ubar, advanced by its
+    exact linearised factor r = exp(-mu tau), mu = lam (3 ubar^2 - 1 + eps^2 lam):
+    to first order in delta, y_PC - ubar is the trapezoidal amplitude
+    (1 - tau mu (1 + r) / 2) delta cos, so
+    est = delta |r - 1 + tau mu (1 + r) / 2| |cos| / sqrt(ubar^2 N + delta^2 (1 - tau mu (1 + r)/2)^2 |cos|^2)."""
+    n, eps, delta = 32, 0.05, 1e-7
+    prob = O.Problem(2, n, eps)
+    lam = fourier_eig(prob, k)
+    mu = lam * (3 * ubar ** 2 - 1 + eps ** 2 * lam)
+    r = math.exp(-mu * tau)
+    v = fourier_mode(n, 2, k, 1.0)
+    est, _ = O.pc_estimate(ubar + delta * v, ubar + delta * r * v, tau, prob)
+    amp = 1.0 - 0.5 * tau * mu * (1.0 + r)
+    nv = np.linalg.norm(v)
+    want = delta * abs(r - 1.0 + 0.5 * tau * mu * (1.0 + r)) * nv / math.sqrt(
+        ubar ** 2 * prob.N + (delta * amp * nv) ** 2)
+    assert est == pytest.approx(want, rel=1e-5)
+
+
 # --- P13: controller rules ------------------------------------------------------------------
 
 def test_controller_rules_table():
