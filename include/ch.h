@@ -12,9 +12,12 @@
  *        y^n, giving y' = -Ahat_n y + ghat^n (eq. IVPlin) with
  *        Ahat_n = A (J_n + eps^2 A), ghat^n = A (J_n y^n - F'(y^n)) (eq. A_g);
  *        its solution y^n + tau phi(-tau Ahat_n)(ghat^n - Ahat_n y^n) (eq. yt) is
- *        evaluated by Arnoldi with modified Gram-Schmidt and the residual-time
- *        (RT) restart of the Krylov algorithm (Fig. 3); adaptive steps follow
- *        Fig. 4 (eqs. tol_phi, LIMest, EEdt).
+ *        evaluated by the Arnoldi process with the residual-time (RT) restart
+ *        of the Krylov algorithm (Fig. 3) -- by default with classical
+ *        Gram-Schmidt applied twice and its second projection delayed
+ *        (CH_ORTH_DCGS2), or with the modified Gram-Schmidt that Fig. 3
+ *        prints (CH_ORTH_MGS); adaptive steps follow Fig. 4 (eqs. tol_phi,
+ *        LIMest, EEdt).
  *   LIM  the Chebyshev local-iteration scheme (Fig. 1), 2p-1 explicit-Euler-like
  *        stages with p from eq. p and lambda_max = ||Ahat_n||_1; adaptive steps
  *        follow Fig. 2 (eqs. LIMest, LIMdt).
@@ -231,13 +234,20 @@ int ch_server_create(int device, int prec, const ch_ee_opts *opts, size_t hbm_bu
                      ch_server **out);
 /* Stops admitting, finishes the requests in flight, fails the queued ones, frees everything. */
 int ch_server_destroy(ch_server *srv);
-/* Queue a request; CH_ENOMEM if its footprint can never fit the budget.  Thread-safe. */
+/*
+ * Queue a request; CH_ENOMEM if its footprint can never fit the budget.
+ * Thread-safe.  y0 is copied on the server's own non-blocking stream before
+ * the call returns, so the work that writes y0 must have completed when it is
+ * called (the copy does not wait for other streams).  Request buffers are
+ * recycled: steady serving makes no device allocation.  A request's latency
+ * counts from the moment ch_submit is entered.
+ */
 int ch_submit(ch_server *srv, const ch_request *req, unsigned long long *ticket);
 /*
  * State of a request.  When it is CH_REQ_DONE and y_out (DEVICE, n*n FP64) is
- * not NULL, the result is copied there and the ticket is released (later
- * polls return CH_ENOENT).  stats and latency_s (queue wait, service, total in
- * seconds) may be NULL.  Thread-safe.
+ * not NULL, the result is copied there (complete when the call returns) and
+ * the ticket is released (later polls return CH_ENOENT).  stats and latency_s
+ * (queue wait, service, total in seconds) may be NULL.  Thread-safe.
  */
 int ch_poll(ch_server *srv, unsigned long long ticket, int *state, double *y_out, ch_run_stats *stats,
             double *latency_s);

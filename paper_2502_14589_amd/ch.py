@@ -306,7 +306,10 @@ class Server:
 
     def submit(self, y0, n: int, eps: float, steps: int, tau0: float = 1e-3) -> int:
         """Queue a 2-D request (y0 is copied); returns its ticket."""
+        import torch
+
         _check_field(y0, n * n)
+        torch.cuda.current_stream(y0.device).synchronize()   # the library copies y0 on its own stream
         req = ChRequest(int(n), float(eps), c_void_p(y0.data_ptr()), int(steps), float(tau0))
         t = ctypes.c_ulonglong()
         rc = self.lib.ch_submit(self._ptr, byref(req), byref(t))

@@ -248,37 +248,42 @@ int wide_blocks(int dim, int n, int prec) {
     return dim == 2 ? strip_blocks(n, strip_vx(n, prec)) : march_blocks(n);
 }
 
-// Workgroup ranges of each instance and the block-to-instance maps.  prec:
-// the precision of the run's basis (selects the strip width).
+// Instance record of member m (index i) whose workgroup ranges start at
+// sblk0, cblk0, wblk0.  prec: the precision of the run's basis (selects the
+// strip width).
+Inst make_inst(const Member& m, int i, int dim, int prec, int sblk0, int cblk0, int wblk0) {
+    Inst I{};
+    const int n = m.sh.n;
+    int sblk, cblk;
+    inst_blocks(dim, n, m.sh.N, &sblk, &cblk);
+    I.off = (long long)m.off;
+    I.N = m.sh.N;
+    I.n = n;
+    I.slot = m.slot >= 0 ? m.slot : i;
+    I.sblk0 = sblk0;
+    I.sblk = sblk;
+    I.cblk0 = cblk0;
+    I.cblk = cblk;
+    I.wblk0 = wblk0;
+    I.wblk = wide_blocks(dim, n, prec);
+    I.vx = strip_vx(n, prec);
+    I.eps2 = m.eps * m.eps;
+    I.inv_h2 = double(n) * double(n);
+    I.eyre = m.eyre;
+    return I;
+}
+
+// Workgroup ranges of each instance and the block-to-instance maps.
 int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, int prec, Table* t) {
     const int ni = (int)ms.size();
     ctx->h_inst.assign(ni, Inst{});
     std::vector<int> sb, cb, wb;
     for (int i = 0; i < ni; ++i) {
-        const Member& m = ms[i];
         Inst& I = ctx->h_inst[i];
-        const int n = m.sh.n;
-        int sblk, cblk;
-        inst_blocks(dim, n, m.sh.N, &sblk, &cblk);
-        const int vx = strip_vx(n, prec);
-        const int wblk = wide_blocks(dim, n, prec);
-        I.off = (long long)m.off;
-        I.N = m.sh.N;
-        I.n = n;
-        I.slot = m.slot >= 0 ? m.slot : i;
-        I.sblk0 = (int)sb.size();
-        I.sblk = sblk;
-        I.cblk0 = (int)cb.size();
-        I.cblk = cblk;
-        I.wblk0 = (int)wb.size();
-        I.wblk = wblk;
-        I.vx = vx;
-        I.eps2 = m.eps * m.eps;
-        I.inv_h2 = double(n) * double(n);
-        I.eyre = m.eyre;
-        sb.insert(sb.end(), sblk, i);
-        cb.insert(cb.end(), cblk, i);
-        wb.insert(wb.end(), wblk, i);
+        I = make_inst(ms[i], i, dim, prec, (int)sb.size(), (int)cb.size(), (int)wb.size());
+        sb.insert(sb.end(), I.sblk, i);
+        cb.insert(cb.end(), I.cblk, i);
+        wb.insert(wb.end(), I.wblk, i);
     }
     if (sb.size() > (size_t)CH_MAXB || cb.size() > (size_t)CH_MAXB || wb.size() > (size_t)CH_MAXB) {
         ctx->err = "batch too large for one launch (workgroup table)";
@@ -515,6 +520,48 @@ int run_ee_batch(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, in
     return status;
 }
 
+// Reads the scalar head of control block 0 into h (host memory of any kind).
+int read_head(ch_ctx* ctx, const DevBuffers& b, Ctl* h) {
+    HIP_TRY(ctx, hipMemcpyAsync(h, b.ctl, CTL_HEAD, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return CH_OK;
+}
+
+// LIM step s of a single-grid run (Figs. 1 and 2): bounds of the spectrum,
+// the plan (whose order p the host reads to size the stage launches), the
+// 2p - 1 stages, the estimate and the controller.  The state ping-pongs
+// between b.ybuf[s & 1] and b.ybuf[(s + 1) & 1].  *halted: the run had
+// nothing left to do (t >= T, the step limit, or an error in the plan).
+int issue_lim_step(ch_ctx* ctx, const Table& t, const DevBuffers& b, PartSeq& ps, Ctl* h, long long s,
+                   bool* halted) {
+    const double* yin = b.ybuf[s & 1];
+    double* yout = b.ybuf[(s + 1) & 1];
+    HIP_TRY(ctx, launch_lim_begin(t, b, ps, yin, ctx->stream));
+    HIP_TRY(ctx, launch_lim_plan(t, b, ps, ctx->stream));
+    int rc;
+    if ((rc = read_head(ctx, b, h))) return rc;
+    *halted = h->halted != 0;
+    if (*halted) return CH_OK;
+    const int p = h->p;
+    // 2p - 1 stages (the nodes in the plan's order, then again without
+    // beta_1) ping-pong between zbuf and yout so that the last launch
+    // writes yout.  On 2-D strips stage 0 runs alone and the rest in
+    // pairs, two stages per launch.
+    const int nst = 2 * p - 1;
+    const bool pairs = lim_stage_pairs(t);
+    const int nl = pairs ? p : nst;
+    const double* src = yin;
+    for (int l = 0; l < nl; ++l) {
+        double* dst = ((nl - 1 - l) % 2 == 0) ? yout : b.zbuf;
+        if (pairs && l > 0) HIP_TRY(ctx, launch_lim_stage2(t, b, yin, src, dst, 2 * l - 1, ctx->stream));
+        else HIP_TRY(ctx, launch_lim_stage(t, b, yin, src, dst, l, ctx->stream));
+        src = dst;
+    }
+    HIP_TRY(ctx, launch_est_lim(t, b, ps, yin, yout, ctx->stream));
+    HIP_TRY(ctx, launch_lim_end(t, b, ps, ctx->stream));
+    return CH_OK;
+}
+
 int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t0, double T, int max_steps,
             double tol, ch_run_stats* stats, ch_step_record* records) {
     Shape sh;
@@ -536,29 +583,9 @@ int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double 
     ps.base = b.part;
     for (long long s = 0;; ++s) {
         if (max_steps > 0 && s >= max_steps) break;
-        const double* yin = b.ybuf[s & 1];
-        double* yout = b.ybuf[(s + 1) & 1];
-        HIP_TRY(ctx, launch_lim_begin(t, b, ps, yin, ctx->stream));
-        HIP_TRY(ctx, launch_lim_plan(t, b, ps, ctx->stream));
-        if ((rc = read_heads(ctx, 1))) return rc;
-        if (ctx->hctl[0].halted) break;
-        const int p = ctx->hctl[0].p;
-        // 2p - 1 stages (the nodes in the plan's order, then again without
-        // beta_1) ping-pong between zbuf and yout so that the last launch
-        // writes yout.  On 2-D strips stage 0 runs alone and the rest in
-        // pairs, two stages per launch.
-        const int nst = 2 * p - 1;
-        const bool pairs = lim_stage_pairs(t);
-        const int nl = pairs ? p : nst;
-        const double* src = yin;
-        for (int l = 0; l < nl; ++l) {
-            double* dst = ((nl - 1 - l) % 2 == 0) ? yout : b.zbuf;
-            if (pairs && l > 0) HIP_TRY(ctx, launch_lim_stage2(t, b, yin, src, dst, 2 * l - 1, ctx->stream));
-            else HIP_TRY(ctx, launch_lim_stage(t, b, yin, src, dst, l, ctx->stream));
-            src = dst;
-        }
-        HIP_TRY(ctx, launch_est_lim(t, b, ps, yin, yout, ctx->stream));
-        HIP_TRY(ctx, launch_lim_end(t, b, ps, ctx->stream));
+        bool halted = false;
+        if ((rc = issue_lim_step(ctx, t, b, ps, ctx->hctl, s, &halted))) return rc;
+        if (halted) break;
     }
     if ((rc = read_heads(ctx, 1))) return rc;
     if ((rc = copy_out(ctx, m, 0, y))) return rc;
@@ -603,6 +630,7 @@ struct Req {
     int sblk = 0, cblk = 0;    // workgroups in a batched launch
     int wblk = 0;              // 2-D strip workgroups
     double* buf = nullptr;     // device: y0 until admission, the result after
+    size_t cap = 0;            // bytes of buf (a pooled buffer may be larger than needed)
     int state = CH_REQ_QUEUED;
     int status = CH_OK;
     ch_run_stats stats{};
@@ -615,7 +643,10 @@ struct Req {
 
 struct ch_server {
     ch_ctx* ctx = nullptr;     // private context on a private stream
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // the scheduler's stream (non-blocking)
+    hipStream_t io = nullptr;       // copies of ch_submit / ch_poll (non-blocking)
+    std::mutex buf_mu;
+    std::multimap<size_t, double*> spare;   // request buffers released by ch_poll, by size
     int device = 0, prec = CH_FP64, max_slots = 0;
     ch_ee_opts opts{};
     size_t pool_pts = 0;
@@ -633,6 +664,35 @@ struct ch_server {
 };
 
 namespace {
+
+// Request buffers are recycled: a released one of at least `bytes` (and at
+// most twice that) is reused, so steady serving makes no hipMalloc or hipFree
+// calls (hipFree synchronises the device).
+double* take_buffer(ch_server* S, size_t bytes, size_t* cap) {
+    {
+        std::lock_guard<std::mutex> lk(S->buf_mu);
+        auto it = S->spare.lower_bound(bytes);
+        if (it != S->spare.end() && it->first <= 2 * bytes) {
+            double* p = it->second;
+            *cap = it->first;
+            S->spare.erase(it);
+            return p;
+        }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    *cap = bytes;
+    return static_cast<double*>(p);
+}
+
+void give_buffer(ch_server* S, double* p, size_t cap) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(S->buf_mu);
+    S->spare.emplace(cap, p);
+}
 
 bool pool_alloc(ch_server* S, size_t len, size_t* off) {
     for (auto it = S->free_.begin(); it != S->free_.end(); ++it) {
@@ -1107,13 +1167,21 @@ int ch_server_create(int device, int prec, const ch_ee_opts* opts, size_t hbm_bu
     S->slot_req.assign(max_slots, nullptr);
     S->free_[0] = pts;
     int rc;
-    if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&S->stream) != hipSuccess) {
+    // Non-blocking streams: neither the scheduler's work nor the request
+    // copies wait for (or hold up) work on the null stream.
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete S;
+        return CH_EDEVICE;
+    }
+    if (hipStreamCreateWithFlags(&S->io, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(S->stream);
         delete S;
         return CH_EDEVICE;
     }
     if ((rc = ch_create(&S->ctx, device, S->stream)) != CH_OK ||
         (rc = ensure(S->ctx, pts, opts->m_max, prec, max_slots, 0, false)) != CH_OK) {
         if (S->ctx) ch_destroy(S->ctx);
+        (void)hipStreamDestroy(S->io);
         (void)hipStreamDestroy(S->stream);
         delete S;
         return rc;
@@ -1141,13 +1209,16 @@ int ch_server_destroy(ch_server* S) {
         free_dev(kv.second->buf);
         delete kv.second;
     }
+    for (auto& kv : S->spare) free_dev(kv.second);
     ch_destroy(S->ctx);
+    (void)hipStreamDestroy(S->io);
     (void)hipStreamDestroy(S->stream);
     delete S;
     return CH_OK;
 }
 
 int ch_submit(ch_server* S, const ch_request* q, unsigned long long* ticket) {
+    const double t_enter = now_s();   // latencies count from here
     if (!S || !q || !ticket || !q->y0) return CH_EINVAL;
     Shape sh;
     int rc = check_grid(2, q->n, q->eps, 0, &sh);
@@ -1167,25 +1238,27 @@ int ch_submit(ch_server* S, const ch_request* q, unsigned long long* ticket) {
         delete r;
         return CH_ENOMEM;
     }
-    if (hipSetDevice(S->device) != hipSuccess || hipMalloc(&r->buf, sizeof(double) * r->N) != hipSuccess) {
+    if (hipSetDevice(S->device) != hipSuccess || !(r->buf = take_buffer(S, sizeof(double) * r->N, &r->cap))) {
         (void)hipGetLastError();
         delete r;
         return CH_ENOMEM;
     }
-    if (hipMemcpy(r->buf, q->y0, sizeof(double) * r->N, hipMemcpyDeviceToDevice) != hipSuccess) {
-        (void)hipFree(r->buf);
+    if (hipMemcpyAsync(r->buf, q->y0, sizeof(double) * r->N, hipMemcpyDeviceToDevice, S->io) != hipSuccess ||
+        hipStreamSynchronize(S->io) != hipSuccess) {
+        (void)hipGetLastError();
+        give_buffer(S, r->buf, r->cap);
         delete r;
         return CH_EDEVICE;
     }
     {
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->stop) {
-            (void)hipFree(r->buf);
+            give_buffer(S, r->buf, r->cap);
             delete r;
             return S->fatal != CH_OK ? S->fatal : CH_EBUSY;
         }
         r->id = S->next_id++;
-        r->t_submit = now_s();
+        r->t_submit = t_enter;
         S->reqs[r->id] = r;
         S->queue.push_back(r);
         *ticket = r->id;
@@ -1217,9 +1290,13 @@ int ch_poll(ch_server* S, unsigned long long ticket, int* state, double* y_out, 
     int rc = r->status;
     if (r->state == CH_REQ_DONE) {
         (void)hipSetDevice(S->device);
-        if (hipMemcpy(y_out, r->buf, sizeof(double) * r->N, hipMemcpyDeviceToDevice) != hipSuccess) rc = CH_EDEVICE;
+        if (hipMemcpyAsync(y_out, r->buf, sizeof(double) * r->N, hipMemcpyDeviceToDevice, S->io) != hipSuccess ||
+            hipStreamSynchronize(S->io) != hipSuccess) {
+            (void)hipGetLastError();
+            rc = CH_EDEVICE;
+        }
     }
-    free_dev(r->buf);
+    give_buffer(S, r->buf, r->cap);
     delete r;
     return rc;
 }
