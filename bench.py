@@ -3,27 +3,32 @@
 
 Workload: 2-D periodic Cahn-Hilliard on [0,1]^2, 1024 x 1024 grid (h = 1/1024),
 eps = 0.01, y0 = 0.1 + iid U(-0.05, 0.05) (seed 1), adaptive EE2 (Fig. 4) with
-tol = 1e-4, Krylov dimension 30, tau0 = T = 1e-3.  A step is one pass of the
-whole hot path: the Arnoldi process (DCGS2 orthogonalisation) driven by the
-fused Jacobian stencil matvec, the small-matrix phi with the residual-time
-trace, the solution update and the error estimate / step controller (whose
-stencil also yields the next start vector).
+tol = 1e-4, Krylov dimension 30, tau0 = T = 1e-3, run from y0 to t = T.  A
+step is one pass of the whole hot path: the Arnoldi process (DCGS2
+orthogonalisation) driven by the fused Jacobian stencil matvec, the
+small-matrix phi with the residual-time trace, the solution update and the
+error estimate / step controller (whose stencil also yields the next start
+vector).  The timed region is the whole run to T: the adaptive controller,
+not --steps, fixes how many steps that is (about 15000, nearly all at the
+largest Krylov dimension with a trace).
 
 Forms: FP32-mixed (Krylov basis and stencils in FP32; state, reductions, phi,
 update and estimate in FP64) and plain FP64.  `value` is the FP32-mixed steps/s;
-the FP64 figures, the adaptive LIM at the same size, the 3-D 256^3 EE2 case,
-the batched and served forms and the FP32-vs-FP64 state difference are
-reported beside it.  The roofline figures come from back-to-back launches of
-the kernel over the Arnoldi iterations the timed steps worked through, timed
-by HIP events on the launching stream.  The CPU baseline
-is the FP64 NumPy/SciPy oracle on the first steps of the same workload.
+the FP64 figures, the relative difference of the two states at T, the adaptive
+LIM at the same size, the 3-D 256^3 EE2 case and the batched and served forms
+are reported beside it.  The roofline figures come from back-to-back launches
+of the kernel over the Arnoldi iterations of every REPLAY_EVERY-th step of the
+timed run, timed by HIP events on the launching stream.  The CPU baseline is
+the FP64 NumPy/SciPy oracle on the first steps of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+        W untimed warm-up steps (a throw-away run from y0), then the timed
+        runs to T; K is the window of the adaptive LIM form.
     python bench.py --copy-calibration     (plain copy of known size, for the
                                             hardware-counter scale)
-    python bench.py --counters             (FP32-mixed form only, with the work
-                                            of its dominant kernel class, for
-                                            hardware-counter runs)
+    python bench.py --counters             (FP32-mixed run to T, then the
+                                            replay of its dominant kernel alone
+                                            inside a profiler region)
 """
 from __future__ import annotations
 
@@ -41,6 +46,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 N_SIDE, EPS, TOL, M_MAX, TAU0, T_END, SEED = 1024, 0.01, 1e-4, 30, 1e-3, 1e-3, 1
+MAX_STEPS = 60000           # cap of the run to T (records buffer)
+REPLAY_EVERY = 10           # replay the Arnoldi iterations of every 10th step
 LIM_TAU0 = 2.5e-7
 C3_SIDE, C3_EPS, C3_TOL, C3_M, C3_SEED = 256, 0.02, 1e-6, 40, 2
 HBM_PEAK_GBPS = 8000.0
@@ -90,40 +97,73 @@ def replay(ctx, prob, kernel, m_max, iters=None, count=0):
             "bytes_per_launch": nbytes / n, "achieved_GBps": nbytes / (us * 1e-6) / 1e9 if us > 0 else 0.0}
 
 
-def run_ee_form(ctx, ch, torch, prob, y0, tau0, T, steps, warmup, m_max, tol, fp32, N):
-    """Warm-up steps, then `steps` timed steps, then back-to-back launches of
-    the DCGS2 kernels over the Arnoldi iterations the timed steps worked
-    through, for the per-kernel figures."""
+class ProfilerRegion:
+    """roctxProfilerPause / roctxProfilerResume when the roctx library is
+    present: under `rocprofv3 --selected-regions` only the resumed parts of the
+    process are recorded (the replay, not the 1.5M launches of the run)."""
+
+    def __init__(self, enabled: bool):
+        self.lib = None
+        if enabled:
+            import ctypes
+
+            for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so", "libroctx64.so"):
+                try:
+                    self.lib = ctypes.CDLL(name)
+                    break
+                except OSError:
+                    continue
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(0)
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(0)
+
+
+def run_ee_form(ctx, ch, torch, prob, y0, tau0, T, warmup, m_max, tol, fp32, N, max_steps=MAX_STEPS,
+                replay_every=REPLAY_EVERY, region=None):
+    """W warm-up steps (a throw-away run from y0: allocations, code objects),
+    then the timed run from y0 until t = T (or max_steps), then back-to-back
+    launches of the DCGS2 kernels over the Arnoldi iterations of every
+    replay_every-th step, for the per-kernel figures.  Returns the figures and
+    the final state."""
+    ctx.run_ee(prob, torch.from_numpy(y0.copy()).to("cuda"), tau0, T=T, max_steps=max(warmup, 1), m_max=m_max,
+               tol=tol)
     y = torch.from_numpy(y0.copy()).to("cuda")
-    if warmup > 0:
-        st_w, _ = ctx.run_ee(prob, y, tau0, t0=0.0, T=T, max_steps=warmup, m_max=m_max, tol=tol)
-    else:   # time from y0: one throw-away step first (allocations, code objects)
-        ctx.run_ee(prob, y.clone(), tau0, t0=0.0, T=T, max_steps=1, m_max=m_max, tol=tol)
-        st_w = {"t": 0.0, "tau_next": tau0}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st, recs = ctx.run_ee(prob, y, st_w["tau_next"], t0=st_w["t"], T=T, max_steps=steps, m_max=m_max, tol=tol,
-                          records=True)
+    st, recs = ctx.run_ee(prob, y, tau0, t0=0.0, T=T, max_steps=max_steps, m_max=m_max, tol=tol, records=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
     w = 4 if fp32 else 8
     nbytes = sum(ee_step_bytes(r["j"], m_max, w, N, fp32) for r in recs)
-    mv, up, phi = dc_iters(recs, m_max)
+    sample = recs[::replay_every]
+    mv, up, phi = dc_iters(sample, m_max)
     last_j = recs[-1]["j"] if recs else 0
-    kern = {"dc_matvec": replay(ctx, prob, ch.CH_KERNEL_DC_MATVEC, m_max, mv),
-            "dc_update": replay(ctx, prob, ch.CH_KERNEL_DC_UPDATE, m_max, up)}
+    if region is not None:
+        region.resume()
+    kern = {"dc_matvec": replay(ctx, prob, ch.CH_KERNEL_DC_MATVEC, m_max, mv)}
+    if region is not None:
+        region.pause()
+    kern["dc_update"] = replay(ctx, prob, ch.CH_KERNEL_DC_UPDATE, m_max, up)
     phi = [k for k in phi if k <= last_j]
     if phi:
         kern["phi"] = replay(ctx, prob, ch.CH_KERNEL_PHI, m_max, phi)
+    js = [r["j"] for r in recs]
     return {
         "steps": st["steps"], "seconds": dt, "steps_per_s": st["steps"] / dt,
         "ms_per_step": 1000.0 * dt / max(st["steps"], 1), "t_end": st["t"],
-        "mean_j": sum(r["j"] for r in recs) / max(len(recs), 1),
+        "mean_j": sum(js) / max(len(js), 1),
+        "frac_at_m_max": sum(1 for j in js if j == m_max) / max(len(js), 1),
         "traced_frac": sum(r["traced"] for r in recs) / max(len(recs), 1),
-        "matvecs_per_s": st["matvecs"] / dt, "sim_time_per_s": (st["t"] - st_w["t"]) / dt,
+        "matvecs_per_s": st["matvecs"] / dt, "sim_time_per_s": st["t"] / dt,
         "effective_GBps": nbytes / dt / 1e9, "kernels": kern,
-    }
+        "replayed_steps": f"every {replay_every}th step of the timed run ({len(sample)} steps)",
+    }, y
 
 
 def lim_form(ctx, ch, torch, y0, steps, warmup):
@@ -159,7 +199,7 @@ def lim_form(ctx, ch, torch, y0, steps, warmup):
             "single_stage_equivalent_frac": round(2.0 * stage["achieved_GBps"] / HBM_PEAK_GBPS, 4)}
 
 
-def c3_form(ctx, ch, torch, steps: int = 20, warmup: int = 0):
+def c3_form(ctx, ch, torch, steps: int = 20, warmup: int = 1):
     """3-D periodic 256^3, eps = 0.02, y0 = U(-0.05, 0.05) (seed 2), adaptive
     EE2 with Krylov dimension 40 and tol 1e-6, tau0 = 1e-3, the 20-step
     horizon from y0: FP32-mixed and FP64.  The FP64 basis (41 x 128 MiB) is far
@@ -172,8 +212,8 @@ def c3_form(ctx, ch, torch, steps: int = 20, warmup: int = 0):
     out = {"workload": "3-D periodic 256^3, eps 0.02, y0 = U(-0.05,0.05) seed 2, adaptive EE2, Krylov dim 40, "
                        "tol 1e-6, tau0 1e-3, 20 steps from y0"}
     for name, prec in (("fp32_mixed", ch.CH_FP32_MIXED), ("fp64", ch.CH_FP64)):
-        f = run_ee_form(ctx, ch, torch, ch.Problem(3, C3_SIDE, C3_EPS, False, prec), y0, 1e-3, math.inf, steps,
-                        warmup, C3_M, C3_TOL, prec == ch.CH_FP32_MIXED, N)
+        f, _ = run_ee_form(ctx, ch, torch, ch.Problem(3, C3_SIDE, C3_EPS, False, prec), y0, 1e-3, math.inf,
+                           warmup, C3_M, C3_TOL, prec == ch.CH_FP32_MIXED, N, max_steps=steps, replay_every=1)
         mv = f["kernels"]["dc_matvec"]
         up = f["kernels"]["dc_update"]
         out[name] = {"steps_per_s": round(f["steps_per_s"], 3), "ms_per_step": round(f["ms_per_step"], 3),
@@ -185,22 +225,6 @@ def c3_form(ctx, ch, torch, steps: int = 20, warmup: int = 0):
                      "dc_matvec_avg_launch_us": round(mv["avg_launch_us"], 3),
                      "dc_matvec_bytes_per_launch": mv["bytes_per_launch"], "dc_matvec_launches": mv["launches"]}
     return out
-
-
-def precision_gap(ctx, ch, torch, y0, steps: int = 10, tau: float = 1e-9):
-    """FP32-mixed vs FP64 state after the same constant-step EE2 sequence
-    (same tau, Krylov dimension and tol_phi), so only the precision differs."""
-    import numpy as np
-
-    out = {}
-    for prec in (ch.CH_FP32_MIXED, ch.CH_FP64):
-        y = torch.from_numpy(y0.copy()).to("cuda")
-        ctx.run_ee(ch.Problem(2, N_SIDE, EPS, False, prec), y, tau, max_steps=steps, m_max=M_MAX,
-                   tol_phi_fixed=1e-8, constant_step=True)
-        out[prec] = y.cpu().numpy()
-    a, b = out[ch.CH_FP32_MIXED], out[ch.CH_FP64]
-    return {"fp32_vs_fp64_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
-            "compared": f"{steps} constant EE2 steps of tau={tau:g} from y0, Krylov dim {M_MAX}, tol_phi 1e-8"}
 
 
 def batched(ctx, ch, torch, steps: int = 50, sequential_sample: int = 8):
@@ -247,51 +271,79 @@ def batched(ctx, ch, torch, steps: int = 50, sequential_sample: int = 8):
             "speedup_vs_one_at_a_time": round(total_steps / dt / seq_rate, 2), "status": rc}
 
 
-def serving(ch, torch, count: int = 60, rate: float = 200.0):
-    """Replay `count` Poisson arrivals (rate 200/s) of 2-D requests: sides
-    128/256/512/1024 w.p. 0.4/0.3/0.2/0.1, eps log-uniform [0.005, 0.05],
-    horizons U{10..200} adaptive EE2 steps, FP32-mixed, seed 4; fields resident
-    on the device before the trace starts."""
-    from paper_2502_14589_amd.inputs import request_trace
+def serve_trace(ch, torch, reqs, label):
+    """Replay one arrival trace through a server (fields resident on the
+    device before it starts); returns latencies and served work."""
+    import numpy as np
 
-    reqs = request_trace(count, rate)
+    count = len(reqs)
     fields = [torch.from_numpy(r.y0.copy()).to("cuda") for r in reqs]
     outs = [torch.empty_like(f) for f in fields]
     torch.cuda.synchronize()
     lat, done, tickets = {}, {}, []
+    busy_from = None
     with ch.Server(0, ch.CH_FP32_MIXED, m_max=M_MAX, tol=TOL, hbm_budget=32 << 30, max_slots=128) as srv:
         t0 = time.perf_counter()
+        open_ = set()
         while len(done) < count:
             now = time.perf_counter() - t0
             while len(tickets) < count and reqs[len(tickets)].arrival <= now:
-                r = reqs[len(tickets)]
-                tickets.append(srv.submit(fields[len(tickets)], r.n, r.eps, r.steps, tau0=TAU0))
-            for k, t in enumerate(tickets):
-                if k in done:
-                    continue
-                state, rc, st, lt = srv.poll(t, outs[k])
+                k = len(tickets)
+                r = reqs[k]
+                tickets.append(srv.submit(fields[k], r.n, r.eps, r.steps, tau0=TAU0))
+                open_.add(k)
+                if busy_from is None:
+                    busy_from = time.perf_counter() - t0
+            for k in list(open_):
+                state, rc, st, lt = srv.poll(tickets[k], outs[k])
                 if state in (ch.CH_REQ_DONE, ch.CH_REQ_FAILED):
                     done[k] = (state, st)
                     lat[k] = lt
-            if now > 300:
+                    open_.discard(k)
+            if now > 600:
                 raise RuntimeError("serving trace did not finish")
-            time.sleep(0.0005)
+            time.sleep(0.0002)
         makespan = time.perf_counter() - t0
-    import numpy as np
-
     tot = np.array([lat[k][2] for k in range(count)])
     que = np.array([lat[k][0] for k in range(count)])
     steps = sum(done[k][1]["steps"] for k in range(count))
     psteps = sum(done[k][1]["steps"] * reqs[k].n ** 2 for k in range(count))
-    return {"workload": f"{count} Poisson arrivals at {rate:g}/s, sides 128/256/512/1024 (0.4/0.3/0.2/0.1), "
-                        "eps log-uniform [0.005,0.05], horizons U{10..200} adaptive EE2 steps, FP32-mixed",
-            "requests": count, "failed": sum(1 for k in range(count) if done[k][0] != ch.CH_REQ_DONE),
+    rate = count / reqs[-1].arrival
+    return {"trace": label, "requests": count, "offered_rate_per_s": round(rate, 2),
+            "failed": sum(1 for k in range(count) if done[k][0] != ch.CH_REQ_DONE),
             "makespan_s": round(makespan, 3), "latency_p50_s": round(float(np.percentile(tot, 50)), 4),
             "latency_p99_s": round(float(np.percentile(tot, 99)), 4),
             "queue_p50_s": round(float(np.percentile(que, 50)), 4),
             "queue_p99_s": round(float(np.percentile(que, 99)), 4),
-            "request_steps_per_s": round(steps / makespan, 1), "point_steps_per_s": round(psteps / makespan, 1),
+            "request_steps_per_s": round(steps / (makespan - busy_from), 1),
+            "point_steps_per_s": round(psteps / (makespan - busy_from), 1),
             "offered_point_steps_per_s": round(rate * float(np.mean([r.n ** 2 * r.steps for r in reqs])), 1)}
+
+
+def serving(ch, torch, count: int = 2000, rate: float = 200.0, count_sus: int = 1000):
+    """Poisson arrivals of 2-D requests: sides 128/256/512/1024 w.p.
+    0.4/0.3/0.2/0.1, eps log-uniform [0.005, 0.05], horizons U{10..200}
+    adaptive EE2 steps, FP32-mixed, seed 4.  First `count` arrivals at 200/s
+    (the configured rate; above capacity, so the server runs saturated and
+    its point-step rate is the capacity); then `count_sus` arrivals (seed 5)
+    at 80% of the sustainable request rate that capacity implies, where the
+    queue stays bounded."""
+    import numpy as np
+
+    from paper_2502_14589_amd.inputs import request_trace
+
+    warm = request_trace(8, rate, seed=40)
+    serve_trace(ch, torch, warm, "warm-up")
+    reqs = request_trace(count, rate)
+    hot = serve_trace(ch, torch, reqs, f"{count} arrivals at {rate:g}/s")
+    mean_work = float(np.mean([r.n ** 2 * r.steps for r in reqs]))
+    del reqs
+    sustainable = hot["point_steps_per_s"] / mean_work
+    sus = serve_trace(ch, torch, request_trace(count_sus, 0.8 * sustainable, seed=5),
+                      f"{count_sus} arrivals at 0.8 x the sustainable rate")
+    return {"workload": "Poisson arrivals, sides 128/256/512/1024 (0.4/0.3/0.2/0.1), eps log-uniform "
+                        "[0.005,0.05], horizons U{10..200} adaptive EE2 steps, FP32-mixed, Krylov dim 30, tol 1e-4",
+            "sustainable_rate_per_s": round(sustainable, 2), "at_200_per_s": hot, "at_0.8_sustainable": sus}
 
 
 def kernel_source_sha() -> str:
@@ -302,9 +354,10 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(bytes_per_launch: float):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on the current kernel sources (else None)."""
+    summary, if it was taken on the current kernel sources and on the same
+    replay (the same algorithmic bytes per launch, to 0.1%); else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             lines = [ln for ln in f if ":" in ln and not ln.startswith(("#", "|", " ", "`"))]
@@ -314,6 +367,8 @@ def measured_traffic():
     if kv.get("source_sha") != kernel_source_sha():
         return None
     try:
+        if abs(float(kv["replay_bytes_per_launch"]) - bytes_per_launch) > 1e-3 * bytes_per_launch:
+            return None
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -330,12 +385,18 @@ def roofline(k, traffic=None):
 
 
 def cpu_baseline(y0, seconds: float):
-    """The FP64 oracle on the first adaptive EE2 steps of the workload, one BLAS thread."""
+    """The FP64 oracle on the first adaptive EE2 steps of the workload, one BLAS thread.
+
+    The first step runs at the largest Krylov dimension with the trace (as
+    nearly every step of the run to T does); the following ones are the ramp of
+    the step size.  Reported: steps/s over the sample, and the seconds of the
+    first step alone."""
     from threadpoolctl import threadpool_limits
 
     from oracle import ch_oracle as O
 
     prob = O.Problem(2, N_SIDE, EPS)
+    js, first = [], None
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         steps = 0
@@ -345,11 +406,15 @@ def cpu_baseline(y0, seconds: float):
             t += rec.t
             tau = O.ee_dt(rec.taus[-1], rec.ests[-1], TOL)
             steps += 1
+            js.append(rec.js[-1])
+            if first is None:
+                first = time.perf_counter() - t0
         dt = time.perf_counter() - t0
     return {"value": round(steps / dt, 5), "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} adaptive EE2 steps of the 1024^2 workload from y0 (FP64 NumPy/SciPy, "
-                      f"single thread), {dt:.1f} s on {platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} host cores present"}
+            "first_step_s_at_m_max": round(first, 3),
+            "sample": f"first {steps} adaptive EE2 steps of the 1024^2 workload from y0 (Krylov dimensions "
+                      f"{js}; the first traced at 30), FP64 NumPy/SciPy, single thread, {dt:.1f} s on "
+                      f"{platform.processor() or platform.machine()}, {os.cpu_count()} host cores present"}
 
 
 def copy_calibration(torch, mib: int = 256, reps: int = 10):
@@ -365,18 +430,24 @@ def copy_calibration(torch, mib: int = 256, reps: int = 10):
           flush=True)
 
 
+def progress(msg: str):
+    """Progress of the long legs on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=40, help="timed steps of the adaptive LIM window")
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--T", type=float, default=T_END, help="horizon of the timed EE2 runs (the workload: 1e-3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and served forms")
-    ap.add_argument("--no-extra", action="store_true", help="skip LIM, 3-D and the FP32/FP64 comparison")
+    ap.add_argument("--no-extra", action="store_true", help="skip LIM and 3-D")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--counters", action="store_true",
-                    help="FP32-mixed form only, printing the work of its dominant kernel class (hardware-counter runs)")
+                    help="FP32-mixed run to T, then the replay of its dominant kernel inside a profiler region")
     ap.add_argument("--only-3d", action="store_true", help="the 256^3 forms alone (profiling runs)")
     ap.add_argument("--only-lim", action="store_true", help="the adaptive LIM form alone (profiling runs)")
     args = ap.parse_args()
@@ -398,13 +469,19 @@ def main():
 
     y0 = large_2d_field(SEED, N_SIDE)
     N = N_SIDE * N_SIDE
+    T = args.T
+    workload = (f"2-D periodic Cahn-Hilliard 1024x1024, eps=0.01, y0=0.1+U(-0.05,0.05) seed 1, adaptive EE2 "
+                f"(Fig. 4) tol=1e-4, Krylov dim 30, tau0=1e-3, whole run from y0 to T={T:g}")
     if args.counters:
-        # the FP32-mixed form alone; its dominant kernel's replay runs under a
-        # symbol of its own (first dispatch of that symbol: one warm launch)
+        # the FP32-mixed run to T; the replay of its dominant kernel runs under
+        # a symbol of its own and alone inside the profiler region
+        region = ProfilerRegion(True)
+        region.pause()
         with ch.Context(0) as ctx:
-            f = run_ee_form(ctx, ch, torch, ch.Problem(2, N_SIDE, EPS, False, ch.CH_FP32_MIXED), y0, TAU0, T_END,
-                            args.steps, args.warmup, M_MAX, TOL, True, N)
+            f, _ = run_ee_form(ctx, ch, torch, ch.Problem(2, N_SIDE, EPS, False, ch.CH_FP32_MIXED), y0, TAU0, T,
+                               args.warmup, M_MAX, TOL, True, N, region=region)
         print(json.dumps({"mode": "counters", "kernel": DOMINANT, "source_sha": kernel_source_sha(),
+                          "workload": workload, "replayed": f["replayed_steps"],
                           "replay": f["kernels"]["dc_matvec"]}), flush=True)
         return
     if args.only_3d:
@@ -417,29 +494,48 @@ def main():
                   flush=True)
         return
     with ch.Context(0) as ctx:
-        f32 = run_ee_form(ctx, ch, torch, ch.Problem(2, N_SIDE, EPS, False, ch.CH_FP32_MIXED), y0, TAU0, T_END,
-                          args.steps, args.warmup, M_MAX, TOL, True, N)
-        f64 = run_ee_form(ctx, ch, torch, ch.Problem(2, N_SIDE, EPS, False, ch.CH_FP64), y0, TAU0, T_END,
-                          args.steps, args.warmup, M_MAX, TOL, False, N)
-        acc = lim = c3 = None
+        progress(f"FP32-mixed EE2 run to T={T:g}")
+        f32, y32 = run_ee_form(ctx, ch, torch, ch.Problem(2, N_SIDE, EPS, False, ch.CH_FP32_MIXED), y0, TAU0, T,
+                               args.warmup, M_MAX, TOL, True, N)
+        progress(f"FP32-mixed: {f32['steps']} steps in {f32['seconds']:.1f} s; FP64 EE2 run to T")
+        f64, y64 = run_ee_form(ctx, ch, torch, ch.Problem(2, N_SIDE, EPS, False, ch.CH_FP64), y0, TAU0, T,
+                               args.warmup, M_MAX, TOL, False, N)
+        progress(f"FP64: {f64['steps']} steps in {f64['seconds']:.1f} s")
+        gap = float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64))
+        gap_max = float((y32 - y64).abs().max() / y64.abs().max())
+        lim = c3 = None
         if not args.no_extra:
-            acc = precision_gap(ctx, ch, torch, y0)
+            progress("adaptive LIM window")
             lim = lim_form(ctx, ch, torch, y0, args.steps, args.warmup)
+            progress("3-D 256^3")
             c3 = c3_form(ctx, ch, torch)
-        batch = None if args.no_batch else batched(ctx, ch, torch)
-    serve = None if args.no_batch else serving(ch, torch)
-    t_rel = abs(f32["t_end"] - f64["t_end"]) / f64["t_end"]
+        batch = None
+        if not args.no_batch:
+            progress("batched")
+            batch = batched(ctx, ch, torch)
+    serve = None
+    if not args.no_batch:
+        progress("serving")
+        serve = serving(ch, torch)
 
     def kern_summary(f):
         return {k: {"avg_launch_us": round(v["avg_launch_us"], 3), "achieved_GBps": round(v["achieved_GBps"], 1),
                     "launches": v["launches"]} for k, v in f["kernels"].items()}
 
+    def detail(f):
+        return {"steps": f["steps"], "seconds": round(f["seconds"], 3), "t_end": f["t_end"],
+                "mean_j": round(f["mean_j"], 3), "frac_at_m_max": round(f["frac_at_m_max"], 4),
+                "traced_frac": round(f["traced_frac"], 4), "matvecs_per_s": round(f["matvecs_per_s"], 1),
+                "sim_time_per_s": f["sim_time_per_s"], "kernels": kern_summary(f),
+                "replayed": f["replayed_steps"]}
+
+    mv32 = f32["kernels"]["dc_matvec"]
     out = {
         "metric": METRIC,
         "value": round(f32["steps_per_s"], 3),
         "unit": "steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": f32["steps"],
         "warmup": args.warmup,
         "ms_per_step": round(f32["ms_per_step"], 4),
         "higher_is_better": True,
@@ -447,25 +543,23 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "2-D periodic Cahn-Hilliard 1024x1024, eps=0.01, y0=0.1+U(-0.05,0.05) seed 1, "
-                               "adaptive EE2 tol=1e-4, Krylov dim 30, tau0=T=1e-3",
-                   "grid": [N_SIDE, N_SIDE], "form": "FP32-mixed", "orthogonalisation": "DCGS2",
-                   "parallelism": "single GPU"},
+        "config": {"workload": workload, "grid": [N_SIDE, N_SIDE], "form": "FP32-mixed",
+                   "orthogonalisation": "DCGS2", "parallelism": "single GPU",
+                   "timed": "the whole run from y0 to T (its step count is set by the controller, not --steps)"},
         "hbm_GBps_effective": round(f32["effective_GBps"], 1),
-        "roofline": roofline(f32["kernels"]["dc_matvec"], measured_traffic()),
-        "fp32_detail": {"mean_j": f32["mean_j"], "traced_frac": f32["traced_frac"],
-                        "matvecs_per_s": round(f32["matvecs_per_s"], 1), "sim_time_per_s": f32["sim_time_per_s"],
-                        "kernels": kern_summary(f32)},
-        "fp64_plain": {"value": round(f64["steps_per_s"], 3), "ms_per_step": round(f64["ms_per_step"], 4),
-                       "hbm_GBps_effective": round(f64["effective_GBps"], 1),
-                       "roofline": roofline(f64["kernels"]["dc_matvec"]),
-                       "mean_j": f64["mean_j"], "traced_frac": f64["traced_frac"],
-                       "matvecs_per_s": round(f64["matvecs_per_s"], 1), "sim_time_per_s": f64["sim_time_per_s"],
-                       "kernels": kern_summary(f64)},
+        "roofline": roofline(mv32, measured_traffic(mv32["bytes_per_launch"])),
+        "fp32_detail": detail(f32),
+        "fp64_plain": dict(detail(f64), value=round(f64["steps_per_s"], 3), ms_per_step=round(f64["ms_per_step"], 4),
+                           hbm_GBps_effective=round(f64["effective_GBps"], 1),
+                           roofline=roofline(f64["kernels"]["dc_matvec"])),
         "speedup_fp32_vs_fp64": round(f32["steps_per_s"] / f64["steps_per_s"], 3),
+        "time_to_T_speedup_fp32_vs_fp64": round(f64["seconds"] / f32["seconds"], 3),
+        "accuracy": {"fp32_vs_fp64_rel_l2_at_T": gap, "fp32_vs_fp64_max_rel_at_T": gap_max,
+                     "stated_bound": 1e-5,
+                     "compared": "FP32-mixed and FP64 states at the common end time T (both runs clip their last "
+                                 "step onto T, Fig. 4)"},
     }
-    if acc is not None:
-        out["accuracy"] = dict(acc, adaptive_t_rel_diff=t_rel)
+    if lim is not None:
         out["lim"] = lim
         out["c3_3d"] = c3
     if batch is not None:
@@ -473,6 +567,7 @@ def main():
     if serve is not None:
         out["serving"] = serve
     if not args.no_cpu_baseline:
+        progress("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(y0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

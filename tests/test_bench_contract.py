@@ -34,3 +34,18 @@ def test_ee_step_bytes_counts_each_vector_once():
     # at j = m_max the last matvec stores no w
     assert bench.ee_step_bytes(30, 30, w, N, True) - bench.ee_step_bytes(29, 30, w, N, True) == N * (
         (30 + 2) * w + (29 + 4) * w + w)
+
+
+def test_traffic_is_used_only_for_the_same_replay(tmp_path, monkeypatch):
+    """The counter-measured traffic is attached to the roofline only when it
+    was taken on the current kernel sources and on a replay of the same
+    algorithmic bytes per launch."""
+    f = tmp_path / "traffic.md"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    sha = bench.kernel_source_sha()
+    f.write_text(f"source_sha: {sha}\nreplay_bytes_per_launch: 1000000\ntraffic_bytes_per_launch: 1013000\n")
+    assert bench.measured_traffic(1000000.0) == 1013000.0
+    assert bench.measured_traffic(1000500.0) == 1013000.0
+    assert bench.measured_traffic(1002000.0) is None
+    f.write_text("source_sha: 0000\nreplay_bytes_per_launch: 1000000\ntraffic_bytes_per_launch: 1013000\n")
+    assert bench.measured_traffic(1000000.0) is None
