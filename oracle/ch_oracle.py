@@ -248,16 +248,17 @@ def krylov_phi_cycle(matvec, y: np.ndarray, v1: np.ndarray, tau0: float, tol_phi
     beta = float(np.linalg.norm(v1))
     if beta == 0.0:                                          # reading R3
         return y.copy(), tau0, KrylovInfo(0, tau0, True, 0.0, 0.0)
-    V = np.zeros((N, m_max + 1))
+    # basis vector i is the row V[i] (contiguous), H is (m_max + 1) x m_max
+    V = np.zeros((m_max + 1, N))
     H = np.zeros((m_max + 1, m_max))
-    V[:, 0] = v1 / beta
+    V[0] = v1 / beta
     tau = tau0
     converged = False
     for j in range(1, m_max + 1):
-        w = matvec(V[:, j - 1])
+        w = matvec(V[j - 1])
         for i in range(1, j + 1):
-            H[i - 1, j - 1] = w @ V[:, i - 1]
-            w = w - H[i - 1, j - 1] * V[:, i - 1]
+            H[i - 1, j - 1] = w @ V[i - 1]
+            w = w - H[i - 1, j - 1] * V[i - 1]
         H[j, j - 1] = np.linalg.norm(w)
         Hj = H[:j, :j]
         u = phiv_small(Hj, tau0)
@@ -271,12 +272,12 @@ def krylov_phi_cycle(matvec, y: np.ndarray, v1: np.ndarray, tau0: float, tol_phi
             u = phiv_small(Hj, tau)
             resnorm = H[j, j - 1] * abs(u[-1])
             break
-        V[:, j] = w / H[j, j - 1]
-    y_new = y + V[:, :j] @ (beta * u)
+        V[j] = w / H[j, j - 1]
+    y_new = y + (beta * u) @ V[:j]
     info = KrylovInfo(j, tau, converged, float(resnorm), beta)
     if keep_basis:
         info.H = H[: j + 1, :j].copy()
-        info.V = V[:, : j + 1].copy()
+        info.V = V[: j + 1].T.copy()                         # columns v_1 .. v_{j+1}
         info.V[:, j] = w / H[j, j - 1] if H[j, j - 1] != 0 else 0.0
         info.u = u.copy()
     return y_new, tau, info

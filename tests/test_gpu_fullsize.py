@@ -2,7 +2,11 @@
 
 1024^2 (eps = 0.01, y0 = 0.1 + U(-0.05, 0.05)): the first adaptive EE2 steps
 from tau0 = T = 1e-3 (the first one runs the residual-time trace from 1e-3
-down to ~1e-8), element by element against the oracle.
+down to ~1e-8), element by element against the oracle; the first 50 steps
+against the oracle's stored prefix (step sequence, sampled field, norm, mass,
+random projections), in FP64 and, at the prefix's end time, in FP32-mixed.
+3-D at the 256^3 workload's parameters (Krylov dimension 40, tol 1e-6) on
+64^3, adaptive, element by element.
 One LIM step of the same field (p = 33 and 66) and its first 6 adaptive LIM
 steps, element by element; LIM steps on 2048^2 and 1999^2, and traced EE2
 steps on 1999^2 and 127^3.
@@ -47,6 +51,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def max_rel(a, b):
+    """max |a - b| over max |b|: a single wrong halo row cannot hide in a norm."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 @pytest.fixture(scope="module")
 def large_ref():
     """Oracle: first 3 adaptive EE2 steps of the 1024^2 workload (tol 1e-4, m = 30)."""
@@ -65,7 +74,161 @@ def test_large_2d_first_steps_fp64(ctx, large_ref):
                           records=True)
     assert [r["j"] for r in recs] == rec_ref.js
     np.testing.assert_allclose([r["tau"] for r in recs], rec_ref.taus, rtol=1e-10)
-    assert rel(yg.cpu().numpy(), y_ref) <= 1e-10
+    y = yg.cpu().numpy()
+    assert rel(y, y_ref) <= 1e-10 and max_rel(y, y_ref) <= 1e-10
+
+
+def read_prefix():
+    """The oracle's first 50 adaptive EE2 steps of the 1024^2 workload
+    (tests/golden/make_c2_prefix.py)."""
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_prefix50.txt")
+    g = {"steps": [], "idx": [], "y": [], "proj": []}
+    ct = {"idx": [], "y": [], "proj": []}   # the run to the common end time t_50
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.split()
+            if f[0] == "ct":
+                if f[1] == "y":
+                    ct["idx"].append(int(f[2]))
+                    ct["y"].append(float(f[3]))
+                elif f[1] == "proj":
+                    ct["proj"].append(float(f[3]))
+                else:
+                    ct[f[1]] = float(f[2])
+                continue
+            if f[0] == "step":
+                g["steps"].append((int(f[2]), float(f[3]), float(f[4]), float(f[5]), float(f[6])))
+            elif f[0] == "y":
+                g["idx"].append(int(f[1]))
+                g["y"].append(float(f[2]))
+            elif f[0] == "proj":
+                g["proj"].append(float(f[2]))
+            else:
+                g[f[0]] = float(f[1])
+    g["idx"] = np.array(g["idx"])
+    g["y"] = np.array(g["y"])
+    ct["idx"] = np.array(ct["idx"])
+    ct["y"] = np.array(ct["y"])
+    g["ct"] = ct
+    # Conditioning of the workload, from the oracle's rounding twin: how far a
+    # change of rounding alone moves the accepted steps (traced at the largest
+    # Krylov dimension) and the field.  FP64 parity is held to 1e-10 or ten
+    # times the twin's spread, whichever is larger.
+    g["tau_spread"] = max(abs(s[4] - s[1]) / s[1] for s in g["steps"])
+    g["state_tol"] = max(1e-10, 10.0 * max(g["twin_rel_l2"], g["twin_max_rel"]))
+    return g
+
+
+def prefix_checks(y, g, N, tol, mass_tol=1e-12):
+    """Sampled values, norm, mass and the random projections of y against the
+    prefix.  mass_tol: relative to sum |y| (FP64: roundoff; the FP32-mixed form
+    keeps its basis orthogonal to the constant vector to FP32 rounding)."""
+    import importlib.util
+    import os
+
+    spec = importlib.util.spec_from_file_location(
+        "make_c2_prefix", os.path.join(os.path.dirname(__file__), "golden", "make_c2_prefix.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    idx, proj = mk.sample_plan(N)
+    assert np.array_equal(idx, g["idx"])
+    errs = {
+        "sampled_max": float(np.max(np.abs(y[idx] - g["y"])) / g["maxabs"]),
+        "norm": abs(float(np.linalg.norm(y)) - g["norm"]) / g["norm"],
+        "proj": max(abs(float(proj[k] @ y) - g["proj"][k]) / (float(np.linalg.norm(proj[k])) * g["norm"])
+                    for k in range(len(g["proj"]))),
+    }
+    say(f"prefix errors: {errs}")
+    assert all(v <= tol for v in errs.values()), errs
+    assert abs(float(y.sum()) - g["sum"]) <= mass_tol * float(np.abs(y).sum())
+    return errs
+
+
+def test_large_2d_prefix50_fp64(ctx):
+    """The first 50 adaptive EE2 steps of the 1024^2 workload, FP64, against
+    the oracle's stored prefix: Krylov dimensions equal; accepted steps, times
+    and estimates to 1e-10 (estimates 1e-8) up to the first step the
+    residual-time trace shortens, and from there to ten times the spread of the
+    oracle's rounding twin (the trace's crossing at the largest Krylov
+    dimension moves by up to a few 1e-8 under rounding alone); the field after
+    step 50 at 4096 sampled points (max-abs), in norm and in four random
+    projections to 1e-10 or ten times the twin's distance."""
+    say("1024^2 FP64 first 50 adaptive EE2 steps vs the stored oracle prefix")
+    g = read_prefix()
+    y0 = large_2d_field(1, 1024)
+    yg = dev(y0)
+    st, recs = ctx.run_ee(ch.Problem(2, 1024, 0.01), yg, 1e-3, T=1e-3, max_steps=50, m_max=30, tol=1e-4,
+                          records=True)
+    assert st["steps"] == 50 == len(g["steps"])
+    assert [r["j"] for r in recs] == [s[0] for s in g["steps"]]
+    assert max(r["j"] for r in recs) == 30 and sum(r["traced"] for r in recs) >= 10
+    first = next(k for k, r in enumerate(recs) if r["traced"] and k > 0)
+    cond = max(1e-10, 10.0 * g["tau_spread"])
+    say(f"first traced step {first}; twin spread {g['tau_spread']:.2e}; tolerance past it {cond:.2e}")
+    for k, (r, s) in enumerate(zip(recs, g["steps"])):
+        tol = 1e-10 if k < first else cond
+        assert abs(r["tau"] - s[1]) <= tol * s[1], (k, r["tau"], s[1])
+        assert abs(r["t"] - s[3]) <= tol * s[3], (k, r["t"], s[3])
+        assert abs(r["est"] - s[2]) <= max(1e-8, 3 * tol) * s[2], (k, r["est"], s[2])
+    prefix_checks(yg.cpu().numpy(), g, 1024 * 1024, g["state_tol"])
+
+
+def test_large_2d_prefix_fp32_mixed_at_common_time(ctx):
+    """The precision form against FP64 at a common time: adaptive runs (tol
+    1e-4, Krylov dimension 30) from y0 to T_c = t_50 of the prefix (Fig. 4
+    with T = T_c: the first step is clipped to T_c, the last lands on it), on
+    the GPU in both forms and in the oracle.  FP64 on the GPU matches the
+    oracle's run to T_c (to 1e-10 or ten times the rounding twin's distance);
+    the FP32-mixed state is within the stated 1e-5 of both."""
+    say("1024^2 FP32-mixed vs FP64 at the prefix end time")
+    g = read_prefix()
+    T = g["t_end"]
+    y0 = large_2d_field(1, 1024)
+    out = {}
+    for prec in (ch.CH_FP64, ch.CH_FP32_MIXED):
+        yg = dev(y0)
+        st, _ = ctx.run_ee(ch.Problem(2, 1024, 0.01, False, prec), yg, 1e-3, T=T, max_steps=100, m_max=30,
+                           tol=1e-4)
+        assert st["t"] == T
+        out[prec] = (yg.cpu().numpy(), st)
+    y64, y32 = out[ch.CH_FP64][0], out[ch.CH_FP32_MIXED][0]
+    prefix_checks(y64, g["ct"], 1024 * 1024, g["state_tol"])
+    errs = prefix_checks(y32, g["ct"], 1024 * 1024, 1e-5, mass_tol=1e-7)
+    gap = rel(y32, y64)
+    say(f"FP32-mixed vs FP64 at t = {T:.6e}: rel L2 {gap:.3e}, max {max_rel(y32, y64):.3e}, "
+        f"steps {out[ch.CH_FP32_MIXED][1]['steps']} vs {out[ch.CH_FP64][1]['steps']}")
+    assert gap <= 1e-5 and max_rel(y32, y64) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [ch.CH_FP64, ch.CH_FP32_MIXED])
+def test_cube_c3_parameters_adaptive(ctx, prec):
+    """The 256^3 workload's parameters (eps 0.02, Krylov dimension 40, tol
+    1e-6, tau0 1e-3, y0 = U(-0.05, 0.05) seed 2) on 64^3: five adaptive EE2
+    steps.  The first is traced at dimension 40, so the phi tests of
+    dimensions 32..39 run on the second stream.  FP64 against the oracle to
+    1e-10 (dimensions equal, steps to 1e-10); FP32-mixed to 1e-5."""
+    say(f"64^3 adaptive EE2, Krylov dimension 40, tol 1e-6, prec {prec}")
+    n = 64
+    po = O.Problem(3, n, 0.02)
+    y0 = cube_3d_field(2, n)
+    y_ref, rec_ref = O.ee_adaptive(y0, po, 1e-3, math.inf, 1e-6, 40, max_steps=5)
+    assert rec_ref.js[0] == 40
+    yg = dev(y0)
+    st, recs = ctx.run_ee(ch.Problem(3, n, 0.02, False, prec), yg, 1e-3, max_steps=5, m_max=40, tol=1e-6,
+                          records=True)
+    assert [r["j"] for r in recs] == rec_ref.js
+    y = yg.cpu().numpy()
+    if prec == ch.CH_FP64:
+        np.testing.assert_allclose([r["tau"] for r in recs], rec_ref.taus, rtol=1e-10)
+        assert rel(y, y_ref) <= 1e-10 and max_rel(y, y_ref) <= 1e-10
+    else:
+        np.testing.assert_allclose([r["tau"] for r in recs], rec_ref.taus, rtol=1e-4)
+        say(f"FP32-mixed rel. error vs FP64 oracle: {rel(y, y_ref):.3e}")
+        assert rel(y, y_ref) <= 1e-5 and max_rel(y, y_ref) <= 1e-5
 
 
 def test_large_2d_fp32_mixed_accuracy(ctx):
@@ -166,7 +329,8 @@ def test_odd_wide_grid_ee_step_traced(ctx):
         rec = ctx.step_ee(ch.Problem(2, n, 0.01, False, prec), yg, 1e-8, m_max=12, tol_phi_fixed=1e-8)
         assert rec["j"] == 12 and rec["traced"] == 1
         assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12 if prec == ch.CH_FP64 else 1e-5)
-        assert rel(yg.cpu().numpy(), y_ref) <= tol
+        y = yg.cpu().numpy()
+        assert rel(y, y_ref) <= tol and max_rel(y, y_ref) <= tol
 
 
 def test_odd_cube_ee_step_traced(ctx):
@@ -184,7 +348,8 @@ def test_odd_cube_ee_step_traced(ctx):
         rec = ctx.step_ee(ch.Problem(3, n, 0.02, False, prec), yg, 1e-6, m_max=12, tol_phi_fixed=1e-8)
         assert rec["j"] == 12 and rec["traced"] == 1
         assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12 if prec == ch.CH_FP64 else 1e-5)
-        assert rel(yg.cpu().numpy(), y_ref) <= tol
+        y = yg.cpu().numpy()
+        assert rel(y, y_ref) <= tol and max_rel(y, y_ref) <= tol
 
 
 def test_cube_3d_lim_step_elementwise(ctx):
@@ -261,4 +426,5 @@ def test_largest_krylov_dimension(ctx):
     rec = ctx.step_ee(pg, yg, 1e-2, m_max=ch.CH_MMAX, tol_phi_fixed=1e-9)
     assert rec["j"] == info.j
     assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12)
-    assert rel(yg.cpu().numpy(), y_ref) <= 1e-10
+    y = yg.cpu().numpy()
+    assert rel(y, y_ref) <= 1e-10 and max_rel(y, y_ref) <= 1e-10
