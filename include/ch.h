@@ -69,6 +69,8 @@ enum ch_precision {
 #define CH_MMAX 47
 /* Largest Chebyshev order p of one LIM step. */
 #define CH_PMAX 4096
+/* Largest grid (points) of ch_step_lim_noalloc. */
+#define CH_NOALLOC_MAX_POINTS (1 << 20)
 
 typedef struct {
     int dim;        /* 2 or 3 */
@@ -186,6 +188,27 @@ int ch_run_lim(ch_ctx *ctx, const ch_problem *prob, double *y, double tau0, doub
 /* One LIM step (Fig. 1 with the controller of Fig. 2). */
 int ch_step_lim(ch_ctx *ctx, const ch_problem *prob, double *y, double tau, double t, double T,
                 double tol, ch_step_record *out);
+
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ch_step_lim without
+ * any allocation.  Same arguments, kernels and result as ch_step_lim; its
+ * scratch (two state buffers and a stage buffer of up to
+ * CH_NOALLOC_MAX_POINTS points, reduction partials, node order, stage
+ * coefficients, control block, step record, instance table: 26.3 MB) is a
+ * file-scope device array that every GPU the library runs on holds until the
+ * process ends, located per device by ch_create.  A grid of more than
+ * CH_NOALLOC_MAX_POINTS points returns CH_EINVAL (ch_last_error_message says
+ * why); a device without that address returns CH_EDEVICE.  The call makes no
+ * hipMalloc, hipFree or other allocating call; like ch_step_lim it reads the
+ * Chebyshev order back to the host once and returns after its stream has
+ * drained.  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (from several threads or contexts) race and must be
+ * serialised by the caller.  The control block, the instance record and the
+ * maps are rewritten by every call; nothing carries over between calls.
+ */
+int ch_step_lim_noalloc(ch_ctx *ctx, const ch_problem *prob, double *y, double tau, double t, double T,
+                        double tol, ch_step_record *out);
 
 enum ch_phi_mode {
     CH_PHI_SHRINK = 0,   /* one Fig. 3 cycle: the RT trace may shorten tau (nonlinear RT restart) */

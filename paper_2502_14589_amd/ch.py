@@ -20,10 +20,12 @@ CH_FP64, CH_FP32_MIXED = 0, 1
 CH_PHI_SHRINK, CH_PHI_RESTART = 0, 1
 CH_MMAX = 47
 CH_PMAX = 4096
+CH_NOALLOC_MAX_POINTS = 1 << 20
 
 EXPORTED = (
     "ch_create", "ch_destroy", "ch_strerror", "ch_last_error_message",
-    "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_step_lim", "ch_phiv", "ch_time_kernel",
+    "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_step_lim", "ch_step_lim_noalloc", "ch_phiv",
+    "ch_time_kernel",
 
     "ch_server_create", "ch_server_destroy", "ch_submit", "ch_poll",
 )
@@ -100,6 +102,8 @@ def load_library(path: str = LIB_PATH):
                                P(ChRunStats), P(ChStepRecord)]
     lib.ch_step_lim.argtypes = [c_void_p, P(ChProblem), c_void_p, c_double, c_double, c_double, c_double,
                                 P(ChStepRecord)]
+    lib.ch_step_lim_noalloc.argtypes = [c_void_p, P(ChProblem), c_void_p, c_double, c_double, c_double, c_double,
+                                        P(ChStepRecord)]
     lib.ch_phiv.argtypes = [c_void_p, P(ChProblem), c_void_p, c_void_p, c_double, c_int, c_double, c_int,
                             P(ChStepRecord)]
     lib.ch_run_ee_batch.argtypes = [c_void_p, c_int, P(ChBatchItem), c_int, c_int, c_int, P(ChEeOpts),
@@ -110,7 +114,7 @@ def load_library(path: str = LIB_PATH):
     lib.ch_poll.argtypes = [c_void_p, ctypes.c_ulonglong, P(c_int), c_void_p, P(ChRunStats), P(c_double)]
     lib.ch_time_kernel.argtypes = [c_void_p, P(ChProblem), c_int, c_int, P(c_int), c_int, P(c_double), P(c_double)]
     for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim",
-                 "ch_step_lim", "ch_phiv", "ch_time_kernel", "ch_server_create", "ch_server_destroy", "ch_submit",
+                 "ch_step_lim", "ch_step_lim_noalloc", "ch_phiv", "ch_time_kernel", "ch_server_create", "ch_server_destroy", "ch_submit",
                  "ch_poll"):
         getattr(lib, name).restype = c_int
     _lib = lib
@@ -260,6 +264,18 @@ class Context:
                                   float(tol), byref(rec))
         self._raise(rc, "ch_step_lim")
         return rec.as_dict()
+
+    def step_lim_noalloc(self, prob: Problem, y, tau: float, *, t: float = 0.0, T: float = math.inf,
+                         tol: float = 0.0, raise_on_error: bool = True):
+        """ch_step_lim without device allocation (scratch in a static device array)."""
+        _check_field(y, prob.N)
+        rec = ChStepRecord()
+        pb = prob.c()
+        rc = self.lib.ch_step_lim_noalloc(self._ptr, byref(pb), c_void_p(y.data_ptr()), float(tau), float(t),
+                                          float(T), float(tol), byref(rec))
+        if raise_on_error:
+            self._raise(rc, "ch_step_lim_noalloc")
+        return rec.as_dict(), rc
 
     # -- phi action --------------------------------------------------------
     def phiv(self, prob: Problem, y, y_out, tau0: float, *, mode: int = CH_PHI_SHRINK, tol_phi: float = 1e-8,

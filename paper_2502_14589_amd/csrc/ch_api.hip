@@ -883,6 +883,71 @@ void serve_loop(ch_server* S) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Scratch of ch_step_lim_noalloc: one file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends) carved into the
+// two state buffers and the stage buffer of a grid of at most
+// CH_NOALLOC_MAX_POINTS points, the reduction partials, the LIM node order
+// and stage coefficients, one control block, one step record and the
+// instance table.  Host code never names the array: it uses the per-device
+// address hipGetSymbolAddress returns.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t na_align(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t NA_PTS = (size_t)CH_NOALLOC_MAX_POINTS;
+constexpr size_t NA_MAP = CH_SBLK_MAX > CH_WBLK_MAX ? CH_SBLK_MAX : CH_WBLK_MAX;   // >= CH_CBLK_MAX too
+constexpr size_t NA_Y0 = 0;
+constexpr size_t NA_Y1 = NA_Y0 + na_align(sizeof(double) * NA_PTS);
+constexpr size_t NA_Z = NA_Y1 + na_align(sizeof(double) * NA_PTS);
+constexpr size_t NA_PART = NA_Z + na_align(sizeof(double) * NA_PTS);
+constexpr size_t NA_ORDER = NA_PART + na_align(sizeof(double) * 2 * CH_NRED * CH_MAXB);
+constexpr size_t NA_COEF = NA_ORDER + na_align(sizeof(int) * CH_PMAX);
+constexpr size_t NA_CTL = NA_COEF + na_align(sizeof(double) * 4 * CH_PMAX);
+constexpr size_t NA_REC = NA_CTL + na_align(sizeof(Ctl));
+constexpr size_t NA_INST = NA_REC + na_align(sizeof(ch_step_record));
+constexpr size_t NA_MAPS = NA_INST + na_align(sizeof(Inst));
+constexpr size_t NA_BYTES = NA_MAPS + na_align(sizeof(int) * NA_MAP);
+static_assert(CH_CBLK_MAX <= NA_MAP, "map of the streaming workgroups");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mu;
+void* na_ptr[NA_MAX_DEVICES];   // address of `scratch` on each device (null: not looked up)
+
+// Once per device, with that device current: the device address of the
+// scratch array.  Called by ch_create; a failure is reported by the entry
+// point that needs it, not by ch_create.
+void noalloc_setup(int device) {
+    if (device < 0 || device >= NA_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(na_mu);
+    if (na_ptr[device]) return;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    na_ptr[device] = p;
+}
+
+void* noalloc_scratch(int device) {
+    if (device < 0 || device >= NA_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(na_mu);
+    return na_ptr[device];
+}
+
+// Host copy of the control block and zeros for the workgroup maps (a
+// single-grid launch never reads them; they are kept valid regardless).
+thread_local Ctl na_hctl;
+const int na_zero_map[NA_MAP] = {};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -900,6 +965,7 @@ int ch_create(ch_ctx** out, int device, void* hip_stream) {
     if (!ctx) return CH_ENOMEM;
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    noalloc_setup(device);
     LaunchEnv& sd = ctx->env;
     if (hipStreamCreateWithFlags(&sd.side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sd.ev_main, hipEventDisableTiming) != hipSuccess ||
@@ -988,6 +1054,69 @@ int ch_step_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau, doub
     const int rc = ch_run_lim(ctx, prob, y, tau, t, T, 1, tol, &st, &rec);
     if (out) *out = rec;
     return rc;
+}
+
+int ch_step_lim_noalloc(ch_ctx* ctx, const ch_problem* prob, double* y, double tau, double t, double T, double tol,
+                        ch_step_record* out) {
+    if (!ctx) return CH_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
+    Shape sh;
+    int rc = check_problem(prob, &sh);
+    if (rc) return rc;
+    if (!y || !(tau > 0.0)) return CH_EINVAL;
+    if ((size_t)sh.N > NA_PTS) {
+        ctx->err = "grid larger than the no-allocation scratch (CH_NOALLOC_MAX_POINTS points)";
+        return CH_EINVAL;
+    }
+    unsigned char* base = static_cast<unsigned char*>(noalloc_scratch(ctx->device));
+    if (!base) {
+        ctx->err = "no device address for the no-allocation scratch on this device";
+        return CH_EDEVICE;
+    }
+    DevBuffers b{};
+    b.ybuf[0] = reinterpret_cast<double*>(base + NA_Y0);
+    b.ybuf[1] = reinterpret_cast<double*>(base + NA_Y1);
+    b.zbuf = reinterpret_cast<double*>(base + NA_Z);
+    b.part = reinterpret_cast<double*>(base + NA_PART);
+    b.lorder = reinterpret_cast<int*>(base + NA_ORDER);
+    b.lcoef = reinterpret_cast<double*>(base + NA_COEF);
+    b.ctl = reinterpret_cast<Ctl*>(base + NA_CTL);
+    ch_step_record* drec = reinterpret_cast<ch_step_record*>(base + NA_REC);
+    Inst* dinst = reinterpret_cast<Inst*>(base + NA_INST);
+    int* dmap = reinterpret_cast<int*>(base + NA_MAPS);
+    const Member m{sh, prob->eps, prob->eyre, 0};
+    const Inst I = make_inst(m, 0, sh.dim, CH_FP64, 0, 0, 0);
+    Table tb{};
+    tb.inst = dinst;
+    tb.sb2i = tb.cb2i = tb.wb2i = dmap;
+    tb.ninst = 1;
+    tb.sgrid = I.sblk;
+    tb.cgrid = I.cblk;
+    tb.wgrid = I.wblk;
+    tb.dim = sh.dim;
+    tb.hinst = &I;
+    Ctl* h = &na_hctl;
+    init_ctl(h, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, t, tau, T, tol, 0.0, 0.0, 0, 1, drec, 1, 0);
+    // every control value, the instance record and the maps are written before
+    // the first launch; partials are written by their producers before use
+    HIP_TRY(ctx, hipMemcpyAsync(dinst, &I, sizeof(Inst), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(dmap, na_zero_map, sizeof(na_zero_map), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(b.ctl, h, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(b.ybuf[0], y, sizeof(double) * sh.N, hipMemcpyDeviceToDevice, ctx->stream));
+    PartSeq ps;
+    ps.base = b.part;
+    bool halted = false;
+    if ((rc = issue_lim_step(ctx, tb, b, ps, h, 0, &halted))) return rc;
+    if ((rc = read_head(ctx, b, h))) return rc;
+    ch_step_record rec;
+    memset(&rec, 0, sizeof(rec));
+    if (h->status == CH_OK && h->steps == 1) {
+        HIP_TRY(ctx, hipMemcpyAsync(y, b.ybuf[h->cur], sizeof(double) * sh.N, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(&rec, drec, sizeof(rec), hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (out) *out = rec;
+    return h->status;
 }
 
 int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out, double tau0, int mode,
