@@ -19,6 +19,8 @@
 // arithmetic.
 #include "ch_common.h"
 
+#include <type_traits>
+
 namespace {
 
 // x-y tile of a workgroup: MX x MY outputs per plane, two per thread.
@@ -59,6 +61,16 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned bo) {
     else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, bo, 0u, 0));
 }
 
+// NPT consecutive values of 16 bytes in all (one buffer load).
+template <typename T, int NPT>
+__device__ __forceinline__ void bload16(__amdgpu_buffer_rsrc_t r, unsigned bo, T (&v)[NPT]) {
+    static_assert(NPT * sizeof(T) == 16, "16-byte vector");
+    struct P { T e[NPT]; };
+    const P p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b128(r, bo, 0u, 0));
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) v[e] = p.e[e];
+}
+
 template <typename T>
 __device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned bo) {
     using u32x2 = unsigned __attribute__((ext_vector_type(2)));
@@ -88,7 +100,7 @@ __device__ __forceinline__ MarchItem march_item(int it, int n) {
 //   issue the loads of operand plane p + 2 and state plane p + 1;
 //   q(p) on the halo-1 region;                         barrier
 //   w(p - 1) = A q on the tile, stored; first basis columns of the dot
-//   phase issued;                                      barrier
+//   phase issued (FP64: at the start of the step);     barrier
 //   dot products of plane p - 1;
 //   the loaded planes into the rings;                  barrier.
 // The step's loads have its whole arithmetic to arrive, and nothing is carried
@@ -98,7 +110,11 @@ __device__ __forceinline__ MarchItem march_item(int it, int n) {
 // pass and the dot phase's operand values) come before the step's first
 // barrier.
 // FP32: four workgroups per CU (128 registers); FP64: three (LDS-bound).
-template <typename TV, typename TY, bool SINGLE, int TAG>
+// DV: the dot-phase form -- 1: 16-byte vectors (n a multiple of NPT), 0:
+// scalar points, 2: chosen per instance at run time (batches).  BIGK: room
+// for the dot rows of iterations k > CH_MSMALL (the LDS of the small form
+// keeps FP64 at three workgroups per CU).
+template <typename TV, typename TY, bool SINGLE, int TAG, int DV, bool BIGK>
 __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        TV* __restrict__ V, size_t ldv, int k, int store_w,
@@ -117,7 +133,7 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
     __shared__ TV sd[2][MQP];
     __shared__ TV sq[3][MQP];
     __shared__ TV sw[MPTS];
-    __shared__ double red[CH_DROWS][NW];
+    __shared__ double red[BIGK ? CH_DROWS : CH_DROWS_SMALL][NW];
     // dot phase: thread t of column group g takes plane points t + GT e, so
     // the lanes of a wave read consecutive x; the columns are split over CG
     // groups (FP32: two, FP64: one)
@@ -147,6 +163,18 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
     const int nitems = ntx * nty * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
     const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
     constexpr int RB = 4;   // columns per wave_sum8 (two sums each)
+    static_assert(NPT * sizeof(TV) == 16, "dot-phase points of a thread: one 16-byte vector");
+    // Dot-phase points of thread gt: the NPT consecutive x of vector gt of the
+    // plane tile (one 16-byte load per basis column) when n is a multiple of
+    // NPT, else the scalar points gt + GT e.  Every grid of the same n takes
+    // the same form, so batched and separate runs sum in the same order.
+    // FP64 requests the first block of basis columns of a step before the
+    // next planes (loads complete in issue order, so the dot phase then waits
+    // for its columns but not for the prefetch); in FP32 that was slower (the
+    // registers held across the stencil passes).
+    constexpr bool EARLY = sizeof(TV) == 8;
+    auto items = [&](auto vec_c) {
+    constexpr bool VEC = decltype(vec_c)::value;
     for (int it = lb; it < nitems; it += I.wblk) {
         const MarchItem m = march_item<MX, MY>(it, n);
         // byte offsets in a plane of this thread's operand and state values
@@ -170,9 +198,11 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
         unsigned dof[NPT];
         int dsv[NPT];
         bool din[NPT];
+        int dsw[NPT];
 #pragma unroll
         for (int e = 0; e < NPT; ++e) {
-            const int j = gt + GT * e;
+            const int j = VEC ? NPT * gt + e : gt + GT * e;
+            dsw[e] = j;
             const int cy = j / MX, cx = j - cy * MX;
             const int gx = m.x0 + cx, gy = m.y0 + cy;
             din[e] = gx < n && gy < n;
@@ -217,6 +247,24 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
         for (int p = z0 - 1; p <= z0 + m.zl; ++p) {
             const int zo = p - 1;   // plane of this step's w
             const bool more = p + 1 <= z0 + m.zl;
+            // the basis columns of the dot phase (plane p - 1), in blocks of RB
+            const TV* colbase = V + I.off + (size_t)(zo >= z0 ? zo : z0) * n2;
+            auto fetch = [&](int l0, TV (&v)[RB][NPT]) {
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const bool live = zo >= z0 && l0 + r < kg;
+                    const int c = live ? grp + CG * (l0 + r) : 0;
+                    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(colbase + (size_t)c * ldv, pv);
+                    if constexpr (VEC) {
+                        bload16<TV, NPT>(rs, live ? dof[0] : MOFF, v[r]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < NPT; ++e) v[r][e] = bload<TV>(rs, live ? dof[e] : MOFF);
+                    }
+                }
+            };
+            TV cur[RB][NPT];
+            if constexpr (EARLY) fetch(0, cur);
             TV nv[NVL];
             TY ny[NQL];
             if (more) {   // the next step's planes, in flight during this one
@@ -266,24 +314,11 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
                     bstore<TV>(w, rw, inb && store_w ? (unsigned)(gy * n + gx) * ES : MOFF);
                     sw[i0] = w;
                 }
-                // the first basis columns of the dot phase, in flight during the barrier
-                const TV* colbase = V + I.off + (size_t)zo * n2;
-                auto fetch = [&](int l0, TV (&v)[RB][NPT]) {
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) {
-                        const bool live = l0 + r < kg;
-                        const int c = live ? grp + CG * (l0 + r) : 0;
-                        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(colbase + (size_t)c * ldv, pv);
-#pragma unroll
-                        for (int e = 0; e < NPT; ++e) v[r][e] = bload<TV>(rs, live ? dof[e] : MOFF);
-                    }
-                };
-                TV cur[RB][NPT];
-                fetch(0, cur);
+                if constexpr (!EARLY) fetch(0, cur);   // the first basis columns, in flight during the barrier
                 __syncthreads();
                 double wd[NPT];
 #pragma unroll
-                for (int e = 0; e < NPT; ++e) wd[e] = double(sw[gt + GT * e]);
+                for (int e = 0; e < NPT; ++e) wd[e] = double(sw[dsw[e]]);
                 // the loads of the next four columns are in flight while this
                 // block is summed
                 for (int l0 = 0; l0 < kg; l0 += RB) {
@@ -327,6 +362,9 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
             __syncthreads();
         }
     }
+    };
+    if (DV == 1 || (DV == 2 && n % NPT == 0)) items(std::true_type{});
+    else items(std::false_type{});
     __syncthreads();
     for (int i = tid; i < nrows; i += CH_BLOCK) {
         double a = red[i][0];
@@ -347,12 +385,21 @@ template <typename TV, typename TY>
 static void launch_matvec_m(const Table& t, const DevBuffers& b, const TY* y, int k, int store_w, double* pout,
                             bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
-    if (timing)
-        hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1>), MARGS, V, b.ldv, k, store_w, y, pout);
-    else if (t.ninst == 1)
-        hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0>), MARGS, V, b.ldv, k, store_w, y, pout);
-    else
-        hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0>), MARGS, V, b.ldv, k, store_w, y, pout);
+    constexpr int NPT = 16 / (int)sizeof(TV);   // dot-phase points per thread
+    const bool vec = t.hinst[0].n % NPT == 0;
+    if (k > CH_MSMALL) {
+        if (timing) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 2, true>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else if (t.ninst == 1) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 2, true>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, true>), MARGS, V, b.ldv, k, store_w, y, pout);
+    } else if (timing) {
+        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 1, false>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 0, false>), MARGS, V, b.ldv, k, store_w, y, pout);
+    } else if (t.ninst == 1) {
+        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 1, false>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 0, false>), MARGS, V, b.ldv, k, store_w, y, pout);
+    } else {
+        hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, false>), MARGS, V, b.ldv, k, store_w, y, pout);
+    }
 }
 
 hipError_t launch_matvec_march(const Table& t, int prec, const DevBuffers& b, const double* y, int k, bool store_w,
