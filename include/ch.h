@@ -65,8 +65,10 @@ enum ch_precision {
                            Hessenberg phi, solution update and error estimate in FP64 */
 };
 
-/* Largest Krylov dimension m_max (the phi of H_{m,m} is evaluated in one workgroup's LDS). */
-#define CH_MMAX 47
+/* Largest Krylov dimension m_max: the paper's EE2(100) of Table 1.  The phi
+ * of H_{m,m} runs in one workgroup: in its LDS up to order 48 (Krylov
+ * dimension 47), beyond that in a device scratch of 0.6 MB per instance. */
+#define CH_MMAX 100
 /* Largest Chebyshev order p of one LIM step. */
 #define CH_PMAX 4096
 /* Largest grid (points) of ch_step_lim_noalloc. */

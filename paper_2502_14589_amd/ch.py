@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("CH_LIB_PATH") or os.path.join(os.path.dirname(os.path
 CH_OK, CH_EINVAL, CH_ENOMEM, CH_ENONFINITE, CH_ETAU_UNDERFLOW, CH_EBUSY, CH_ENOENT, CH_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 CH_FP64, CH_FP32_MIXED = 0, 1
 CH_PHI_SHRINK, CH_PHI_RESTART = 0, 1
-CH_MMAX = 47
+CH_MMAX = 100
 CH_PMAX = 4096
 CH_NOALLOC_MAX_POINTS = 1 << 20
 

@@ -37,6 +37,7 @@ struct ch_ctx {
     size_t z_pts = 0;
     int slots = 0;           // control blocks allocated
     size_t rec_n = 0;        // step records allocated
+    int phibig_slots = 0;    // slots of the phi scratch of orders above 48
     ch_step_record* rec = nullptr;
     std::vector<int> expect; // per slot: Krylov cycles issued (compared with the device's `cyc`)
     int* hflag = nullptr;    // pinned, device-mapped: `cyc` of the last finished cycle per slot, then
@@ -183,6 +184,13 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
             if ((rc = alloc_dev(ctx, (void**)&b.y32, sizeof(float) * pts))) return rc;
             ctx->y32_pts = pts;
         }
+    }
+    if (m_max > CH_MSMALL && nslots > ctx->phibig_slots) {
+        free_dev(b.phibig);
+        b.phibig = nullptr;
+        ctx->phibig_slots = 0;
+        if ((rc = alloc_dev(ctx, &b.phibig, phi_big_bytes() * nslots))) return rc;
+        ctx->phibig_slots = nslots;
     }
     if (need_z && pts > ctx->z_pts) {
         free_dev(b.zbuf);
@@ -988,6 +996,7 @@ int ch_destroy(ch_ctx* ctx) {
     DevBuffers& b = ctx->b;
     for (void* p : {(void*)b.V, (void*)b.ybuf[0], (void*)b.ybuf[1], (void*)b.fcur, (void*)b.y32, (void*)b.zbuf,
                     (void*)b.part, (void*)b.dots, (void*)b.lorder, (void*)b.ctl, (void*)ctx->rec, (void*)ctx->d_inst, (void*)ctx->d_sb2i,
+                    b.phibig,
                     (void*)ctx->d_cb2i, (void*)ctx->d_wb2i, (void*)b.lcoef})
         free_dev(p);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);

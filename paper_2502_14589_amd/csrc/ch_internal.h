@@ -27,6 +27,8 @@
 #define CH_NRED 4                // most sums reduced by one launch
 #define CH_BLOCK 256             // threads per workgroup of the streaming and stencil kernels
 #define CH_DROWS (2 * CH_MMAX + 2)   // dot-product rows of one DCGS2 iteration
+#define CH_MSMALL 47                 // Krylov dimensions up to which the LDS-sized forms apply
+#define CH_DROWS_SMALL (2 * CH_MSMALL + 2)
 
 // Dot products a matvec launch produces (see k_matvec).
 enum MatvecDots { MV_DOTS_ONE = 0, MV_DOTS_DC = 1 };
@@ -126,7 +128,12 @@ struct DevBuffers {
     int* dprog;         // device view of `hprog`
     const volatile int* hprog;   // pinned host word: sequence number of the last DCGS2 update launch begun
     int* hseq;          // host counter of the DCGS2 update launches issued
+    void* phibig;       // per-slot device scratch of the phi of orders above 48 (phi_big_bytes each)
 };
+
+// Bytes of the device scratch one instance needs for the phi tests of Krylov
+// dimensions above CH_MSMALL (ch_krylov.hip).
+size_t phi_big_bytes();
 
 // The instance table of one launch sequence (device pointers + host mirror sizes).
 struct Table {

@@ -124,7 +124,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_mgs(Ctl* __restrict__ ctls, const 
 struct DcCoef {
     double s[CH_MMAX + 1], t[CH_MMAX + 1], g[CH_MMAX + 1], hf[CH_MMAX + 1];
     double ca[CH_MMAX + 1], cb[CH_MMAX + 1];
-    double hs[CH_MMAX * (CH_MMAX + 1)];   // H_j staged column by column, leading dimension j + 1
+    // H_j staged column by column, leading dimension j + 1 (j <= CH_MSMALL;
+    // larger j read the control block directly)
+    double hs[CH_MSMALL * (CH_MSMALL + 1)];
     double rho, st, cbw, cq;
 };
 
@@ -161,15 +163,23 @@ __device__ void dc_prepare(DcCoef& C, Ctl* ctl, int j, bool fin, bool publish) {
     __syncthreads();
     // H_j ((j + 1) x j, Hessenberg): columns 0..j-2 are final in ctl->H, column j - 1 is C.hf
     const int ld = j + 1;
-    for (int idx = threadIdx.x; idx < ld * j; idx += CH_BLOCK) {
-        const int c = idx / ld, r = idx - c * ld;
-        C.hs[idx] = r > c + 1 ? 0.0 : (c == j - 1 ? C.hf[r] : ctl->H[r + c * CH_LDH]);
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r <= j; r += CH_BLOCK) {   // g = H_j s
-        double g = 0.0;
-        for (int c = r > 0 ? r - 1 : 0; c < j; ++c) g += C.hs[r + c * ld] * C.s[c];
-        C.g[r] = g;
+    if (j <= CH_MSMALL) {
+        for (int idx = threadIdx.x; idx < ld * j; idx += CH_BLOCK) {
+            const int c = idx / ld, r = idx - c * ld;
+            C.hs[idx] = r > c + 1 ? 0.0 : (c == j - 1 ? C.hf[r] : ctl->H[r + c * CH_LDH]);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r <= j; r += CH_BLOCK) {   // g = H_j s
+            double g = 0.0;
+            for (int c = r > 0 ? r - 1 : 0; c < j; ++c) g += C.hs[r + c * ld] * C.s[c];
+            C.g[r] = g;
+        }
+    } else {
+        for (int r = threadIdx.x; r <= j; r += CH_BLOCK) {   // g = H_j s, same order of terms
+            double g = 0.0;
+            for (int c = r > 0 ? r - 1 : 0; c < j; ++c) g += (c == j - 1 ? C.hf[r] : ctl->H[r + c * CH_LDH]) * C.s[c];
+            C.g[r] = g;
+        }
     }
     __syncthreads();
     const double ir = 1.0 / rho;
@@ -499,8 +509,10 @@ __global__ __launch_bounds__(CH_BLOCK) void k_update(Ctl* __restrict__ ctls, con
 // ---------------------------------------------------------------------------
 // Orders are padded to a multiple of 16 for the matrix cores; the padding is
 // a zero block of the argument, whose exponential is an identity block.
-constexpr int NPMAX = 48;          // largest padded order
-static_assert(CH_MMAX + 1 <= NPMAX, "augmented matrix exceeds the padded order");
+constexpr int NPMAX = 48;          // largest padded order in LDS
+constexpr int NPBIG = 112;         // largest padded order (device scratch)
+static_assert(CH_MSMALL + 1 <= NPMAX, "augmented matrix exceeds the padded LDS order");
+static_assert(CH_MMAX + 1 <= NPBIG, "augmented matrix exceeds the padded order");
 constexpr double THETA19 = 1.2603811;
 constexpr int NLVL = 80;
 
@@ -569,7 +581,11 @@ __device__ void mm(double* __restrict__ C, const double* __restrict__ A, const d
     constexpr int PLD = NPM + 1;
     if (np <= 16) mm_t<1, PLD>(C, A, B, epi);
     else if (NPM >= 32 && np <= 32) mm_t<(NPM >= 32 ? 2 : 1), PLD>(C, A, B, epi);
-    else if (NPM >= 48) mm_t<(NPM >= 48 ? 3 : 1), PLD>(C, A, B, epi);
+    else if (NPM >= 48 && np <= 48) mm_t<(NPM >= 48 ? 3 : 1), PLD>(C, A, B, epi);
+    else if (NPM >= 64 && np <= 64) mm_t<(NPM >= 64 ? 4 : 1), PLD>(C, A, B, epi);
+    else if (NPM >= 80 && np <= 80) mm_t<(NPM >= 80 ? 5 : 1), PLD>(C, A, B, epi);
+    else if (NPM >= 96 && np <= 96) mm_t<(NPM >= 96 ? 6 : 1), PLD>(C, A, B, epi);
+    else if (NPM >= 112) mm_t<(NPM >= 112 ? 7 : 1), PLD>(C, A, B, epi);
 }
 
 // B_i(r, c) = sum_{q=0..3} X^q(r, c) / (4i + q)!
@@ -1036,21 +1052,18 @@ __global__ __launch_bounds__(CH_BLOCK, 3) void k_dc_update_phi(Ctl* __restrict__
 // the final Gram-Schmidt pass.  DCGS2 (DC): dimensions k .. k_last (>= 1),
 // in order, until one ends the cycle; H is final up to column k_last - 1
 // (written by the update launches of those iterations).
-template <bool SINGLE, bool DC>
-__global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst, int k,
-                                                  int k_last, const double* __restrict__ pin, int pin_stencil,
-                                                  int* __restrict__ dflags) {
-    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];   // one workgroup per instance
-    Ctl* ctl = ctls + I.slot;
-    int* dflag = dflags ? dflags + I.slot : nullptr;
-    if (ctl->done | ctl->halted) return;
-    __shared__ PhiShared<NPMAX> S;
+// BIG: orders above NPMAX, with the matrices in the instance's slot of the
+// device scratch `big` (the workgroup's global writes are ordered for its
+// other threads by the same barriers as LDS).
+template <int NPM>
+__device__ __forceinline__ void phi_tests(PhiShared<NPM>& S, Ctl* ctl, int* dflag, const Inst& I, bool dc, int k,
+                                          int k_last, const double* __restrict__ pin, int pin_stencil) {
     taylor_coefficients(S.c);
     __syncthreads();
-    if (DC) {
+    if (dc) {
         for (int j = k; j <= k_last; ++j) {
             __syncthreads();   // the previous test's reads of ctl are complete
-            if (phi_test<NPMAX>(S, ctl, dflag, j, ctl->H[j + (j - 1) * CH_LDH], nullptr)) return;
+            if (phi_test<NPM>(S, ctl, dflag, j, ctl->H[j + (j - 1) * CH_LDH], nullptr)) return;
         }
         return;
     }
@@ -1063,7 +1076,23 @@ __global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const 
         ctl->vscale[k + 1] = hnext > 0.0 ? 1.0 / hnext : 0.0;
     }
     __syncthreads();   // H column k complete (written by the Gram-Schmidt launches and above)
-    phi_test<NPMAX>(S, ctl, dflag, k + 1, hnext, nullptr);
+    phi_test<NPM>(S, ctl, dflag, k + 1, hnext, nullptr);
+}
+
+template <bool SINGLE, bool DC, bool BIG>
+__global__ __launch_bounds__(CH_BLOCK) void k_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst, int k,
+                                                  int k_last, const double* __restrict__ pin, int pin_stencil,
+                                                  int* __restrict__ dflags, PhiShared<NPBIG>* __restrict__ big) {
+    const Inst I = SINGLE ? inst0 : insts[blockIdx.x];   // one workgroup per instance
+    Ctl* ctl = ctls + I.slot;
+    int* dflag = dflags ? dflags + I.slot : nullptr;
+    if (ctl->done | ctl->halted) return;
+    if constexpr (BIG) {
+        phi_tests<NPBIG>(big[I.slot], ctl, dflag, I, DC, k, k_last, pin, pin_stencil);
+    } else {
+        __shared__ PhiShared<NPMAX> S;
+        phi_tests<NPMAX>(S, ctl, dflag, I, DC, k, k_last, pin, pin_stencil);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1506,17 +1535,30 @@ hipError_t launch_mgs_pass(const Table& t, int prec, const DevBuffers& b, PartSe
     return hipGetLastError();
 }
 
-hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int k_last, bool dc, hipStream_t s) {
-    if (dc)
-        if (t.ninst == 1)
-            hipLaunchKernelGGL((k_phi<true, true>), IARGS, k, k_last, nullptr, 0, b.dflag);
-        else
-            hipLaunchKernelGGL((k_phi<false, true>), IARGS, k, k_last, nullptr, 0, b.dflag);
+size_t phi_big_bytes() { return sizeof(PhiShared<NPBIG>); }
+
+template <bool DC, bool BIG>
+static void launch_phi_t(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int k_last, hipStream_t s) {
+    auto* big = static_cast<PhiShared<NPBIG>*>(b.phibig);
+    const double* pin = DC ? nullptr : ps.in();
+    const int pk = DC ? 0 : ps.stencil;
+    if (t.ninst == 1)
+        hipLaunchKernelGGL((k_phi<true, DC, BIG>), IARGS, k, k_last, pin, pk, b.dflag, big);
     else
-        if (t.ninst == 1)
-            hipLaunchKernelGGL((k_phi<true, false>), IARGS, k, k, ps.in(), ps.stencil, b.dflag);
-        else
-            hipLaunchKernelGGL((k_phi<false, false>), IARGS, k, k, ps.in(), ps.stencil, b.dflag);
+        hipLaunchKernelGGL((k_phi<false, DC, BIG>), IARGS, k, k_last, pin, pk, b.dflag, big);
+}
+
+hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, int k_last, bool dc, hipStream_t s) {
+    // the largest Krylov dimension tested: k_last (DCGS2) or k + 1 (MGS)
+    const bool big = (dc ? k_last : k + 1) + 1 > NPMAX;
+    if (big && !b.phibig) return hipErrorInvalidValue;
+    if (dc) {
+        if (big) launch_phi_t<true, true>(t, b, ps, k, k_last, s);
+        else launch_phi_t<true, false>(t, b, ps, k, k_last, s);
+    } else {
+        if (big) launch_phi_t<false, true>(t, b, ps, k, k, s);
+        else launch_phi_t<false, false>(t, b, ps, k, k, s);
+    }
     return hipGetLastError();
 }
 

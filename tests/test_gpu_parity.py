@@ -125,6 +125,37 @@ def test_ee_step_krylov_dimension_above_31(ctx, tau, j_expect):
     assert rel(host(yg), y_ref) <= TOL_FP64
 
 
+@pytest.mark.parametrize("dim,n,eps,tau,j_expect", [
+    (2, 32, 0.05, 1e-3, 53),     # tests of dimensions 48..53 in the device-scratch phi
+    (2, 32, 0.05, 3e-3, 88),
+    (2, 32, 0.05, 1e-2, 100),    # traced at the paper's largest dimension (Table 1, EE2(100))
+    (3, 12, 0.08, 2e-2, 74),
+    (3, 12, 0.08, 1e-1, 100),
+])
+@pytest.mark.parametrize("orth,prec", [(ch.CH_ORTH_DCGS2, ch.CH_FP64), (ch.CH_ORTH_MGS, ch.CH_FP64),
+                                       (ch.CH_ORTH_DCGS2, ch.CH_FP32_MIXED)])
+def test_ee_step_krylov_dimension_up_to_100(ctx, dim, n, eps, tau, j_expect, orth, prec):
+    """Krylov dimension up to 100: tests of orders above 48 keep their
+    matrices in the instance's device scratch instead of LDS; the 3-D matvec's
+    dot rows of iterations above 47 take the large-row form.  FP64 (DCGS2 and
+    the MGS of Fig. 3) against the oracle to 1e-10; FP32-mixed to 1e-5."""
+    say(f"EE step m_max=100 dim={dim} n={n} tau={tau} orth={orth} prec={prec}")
+    po = O.Problem(dim, n, eps)
+    pg = ch.Problem(dim, n, eps, False, prec)
+    y0 = uniform_field(n, dim, 0.1, 0.05, seed=4000 + n)
+    y_ref, tau_ref, info = O.ee_step(y0, po, tau, 1e-9 if dim == 2 else 1e-10, 100)
+    assert info.j == j_expect
+    yg = dev(y0)
+    rec = ctx.step_ee(pg, yg, tau, m_max=100, tol_phi_fixed=1e-9 if dim == 2 else 1e-10, orth=orth)
+    if prec == ch.CH_FP64:
+        assert rec["j"] == info.j and rec["traced"] == (0 if info.converged else 1)
+        assert rec["tau"] == pytest.approx(tau_ref, rel=1e-10)
+        assert rel(host(yg), y_ref) <= TOL_FP64
+    else:
+        assert abs(rec["j"] - info.j) <= 1
+        assert rel(host(yg), y_ref) <= 1e-5
+
+
 def test_ee_adaptive_run_parity(ctx):
     say("EE adaptive run 48^2")
     po, pg = probs(2, 48, 0.03)
