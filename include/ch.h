@@ -187,6 +187,20 @@ int ch_run_ee_batch(ch_ctx *ctx, int count, ch_batch_item *items, int dim, int e
 int ch_run_lim(ch_ctx *ctx, const ch_problem *prob, double *y, double tau0, double t0, double T,
                int max_steps, double tol, ch_run_stats *stats, ch_step_record *records);
 
+/*
+ * Adaptive (Fig. 2, tol > 0) or constant-step (tol <= 0) LIM on `count`
+ * independent instances at once (ragged sizes, each with its own eps, step
+ * sizes, final time and step limit; items as for ch_run_ee_batch): every
+ * kernel launch covers all instances.  Each step's Chebyshev order p (eq. p)
+ * is each instance's own; the stage launches run up to the largest, and an
+ * instance skips those past its last stage.  Each instance's result equals
+ * that of a separate ch_run_lim call (bit for bit) and does not depend on the
+ * other members.  stats: NULL or `count` entries.  Returns the first failing
+ * instance's status; the other instances complete.
+ */
+int ch_run_lim_batch(ch_ctx *ctx, int count, ch_batch_item *items, int dim, int eyre, double tol,
+                     ch_run_stats *stats);
+
 /* One LIM step (Fig. 1 with the controller of Fig. 2). */
 int ch_step_lim(ch_ctx *ctx, const ch_problem *prob, double *y, double tau, double t, double T,
                 double tol, ch_step_record *out);
@@ -227,34 +241,43 @@ int ch_phiv(ch_ctx *ctx, const ch_problem *prob, const double *y, double *y_out,
             int mode, double tol_phi, int m_max, ch_step_record *out);
 
 /*
- * Serving: continuous batching of EE2 solve requests on one GPU.
+ * Serving: continuous batching of EE2 and LIM solve requests on one GPU.
  *
  * A server owns a private context and stream and a scheduler thread.  Each
  * request is copied to device memory at submit and queued.  Between batch
  * steps, the scheduler admits queued requests in arrival order while a control
  * block, pooled HBM for the request's footprint and workgroup-table room are
  * free.  The footprint is ((m_max + 1) w + 28) bytes per grid point, where
- * w = 8 (FP64) or 4 (FP32-mixed).  All admitted requests advance together,
- * one adaptive EE2 step per batch step, each with its own grid, eps, steps and
- * horizon.  Finished requests leave the batch, freeing their slot and memory
- * for the queue.  A request's result does not depend on what else was in the
- * batch: it equals that of a separate ch_run_ee call.
+ * w = 8 (FP64) or 4 (FP32-mixed), whatever the method.  All admitted requests
+ * advance together, one adaptive step per batch step (EE2: Fig. 4; LIM:
+ * Fig. 2, always in FP64), each with its own grid, eps, tolerance, steps and
+ * final time.  Finished requests leave the batch, freeing their slot and
+ * memory for the queue.  A request's result does not depend on what else was
+ * in the batch: it equals that of a separate ch_run_ee or ch_run_lim call.
  */
 typedef struct ch_server ch_server;
+
+enum ch_method { CH_METHOD_EE = 0, CH_METHOD_LIM = 1 };
 
 typedef struct {
     int n;              /* points per direction (2-D periodic, h = 1/n), >= 5 */
     double eps;         /* interface parameter epsilon > 0 */
-    const double *y0;   /* DEVICE field, FP64, n*n values; copied at submit */
-    int steps;          /* horizon: accepted adaptive EE2 steps (> 0) */
+    const double *y0;   /* FP64 field, n*n values, device or host (y0_on_host); copied at submit */
+    int steps;          /* accepted steps to take (<= 0: until T, which must then be finite) */
     double tau0;        /* first proposed step > 0 */
+    int method;         /* ch_method */
+    double T;           /* final time (INFINITY: the horizon is `steps`); the last step is clipped onto it */
+    double tol;         /* > 0: this request's tolerance (eqs. EEdt / LIMdt, tol_phi); <= 0: the server's
+                           (LIM with both <= 0: constant steps of tau0) */
+    int y0_on_host;     /* 0: y0 is device memory; 1: host memory */
 } ch_request;
 
 enum ch_request_state { CH_REQ_QUEUED = 0, CH_REQ_RUNNING = 1, CH_REQ_DONE = 2, CH_REQ_FAILED = 3 };
 
-/* Create a server on `device`: precision, Krylov dimension and tolerances
- * (opts; constant_step must be 0) are common to all requests; hbm_budget is
- * the pooled footprint in bytes; max_slots bounds the requests in flight. */
+/* Create a server on `device`: precision, Krylov dimension and the default
+ * tolerances (opts; constant_step must be 0) are common to all EE2 requests;
+ * hbm_budget is the pooled footprint in bytes; max_slots bounds the requests
+ * in flight. */
 int ch_server_create(int device, int prec, const ch_ee_opts *opts, size_t hbm_budget, int max_slots,
                      ch_server **out);
 /* Stops admitting, finishes the requests in flight, fails the queued ones, frees everything. */

@@ -24,12 +24,13 @@ CH_NOALLOC_MAX_POINTS = 1 << 20
 
 EXPORTED = (
     "ch_create", "ch_destroy", "ch_strerror", "ch_last_error_message",
-    "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_step_lim", "ch_step_lim_noalloc", "ch_phiv",
+    "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_run_lim_batch", "ch_step_lim", "ch_step_lim_noalloc", "ch_phiv",
     "ch_time_kernel",
 
     "ch_server_create", "ch_server_destroy", "ch_submit", "ch_poll",
 )
 CH_REQ_QUEUED, CH_REQ_RUNNING, CH_REQ_DONE, CH_REQ_FAILED = 0, 1, 2, 3
+CH_METHOD_EE, CH_METHOD_LIM = 0, 1
 CH_KERNEL_MGS, CH_KERNEL_MATVEC, CH_KERNEL_PHI = 0, 1, 2
 CH_KERNEL_DC_MATVEC, CH_KERNEL_DC_UPDATE, CH_KERNEL_LIM_STAGE, CH_KERNEL_DC_ITER, CH_KERNEL_LIM_STAGE2 = 3, 4, 5, 6, 7
 CH_ORTH_DCGS2, CH_ORTH_MGS = 0, 1
@@ -67,7 +68,8 @@ class ChBatchItem(ctypes.Structure):
 
 
 class ChRequest(ctypes.Structure):
-    _fields_ = [("n", c_int), ("eps", c_double), ("y0", c_void_p), ("steps", c_int), ("tau0", c_double)]
+    _fields_ = [("n", c_int), ("eps", c_double), ("y0", c_void_p), ("steps", c_int), ("tau0", c_double),
+                ("method", c_int), ("T", c_double), ("tol", c_double), ("y0_on_host", c_int)]
 
 
 class ChError(RuntimeError):
@@ -108,12 +110,13 @@ def load_library(path: str = LIB_PATH):
                             P(ChStepRecord)]
     lib.ch_run_ee_batch.argtypes = [c_void_p, c_int, P(ChBatchItem), c_int, c_int, c_int, P(ChEeOpts),
                                     P(ChRunStats)]
+    lib.ch_run_lim_batch.argtypes = [c_void_p, c_int, P(ChBatchItem), c_int, c_int, c_double, P(ChRunStats)]
     lib.ch_server_create.argtypes = [c_int, c_int, P(ChEeOpts), ctypes.c_size_t, c_int, P(c_void_p)]
     lib.ch_server_destroy.argtypes = [c_void_p]
     lib.ch_submit.argtypes = [c_void_p, P(ChRequest), P(ctypes.c_ulonglong)]
     lib.ch_poll.argtypes = [c_void_p, ctypes.c_ulonglong, P(c_int), c_void_p, P(ChRunStats), P(c_double)]
     lib.ch_time_kernel.argtypes = [c_void_p, P(ChProblem), c_int, c_int, P(c_int), c_int, P(c_double), P(c_double)]
-    for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim",
+    for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_run_lim_batch",
                  "ch_step_lim", "ch_step_lim_noalloc", "ch_phiv", "ch_time_kernel", "ch_server_create", "ch_server_destroy", "ch_submit",
                  "ch_poll"):
         getattr(lib, name).restype = c_int
@@ -256,6 +259,23 @@ class Context:
         out["rc"] = rc
         return out, ([r.as_dict() for r in recs[: st.steps]] if recs is not None else None)
 
+    def run_lim_batch(self, fields, ns, eps, *, dim: int = 2, eyre: bool = False, tau0=1e-6, T=math.inf,
+                      max_steps=10, tol: float = 1e-4, raise_on_error: bool = True):
+        """Adaptive (tol > 0) or constant-step LIM on many instances at once (fields updated in place)."""
+        count = len(fields)
+        as_list = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * count
+        tau0s, Ts, steps = as_list(tau0), as_list(T), as_list(max_steps)
+        items = (ChBatchItem * count)()
+        for i, y in enumerate(fields):
+            _check_field(y, ns[i] ** dim)
+            items[i] = ChBatchItem(int(ns[i]), float(eps[i]), c_void_p(y.data_ptr()), float(tau0s[i]),
+                                   float(Ts[i]), int(steps[i]))
+        st = (ChRunStats * count)()
+        rc = self.lib.ch_run_lim_batch(self._ptr, count, items, int(dim), int(bool(eyre)), float(tol), st)
+        if raise_on_error:
+            self._raise(rc, "ch_run_lim_batch")
+        return [s.as_dict() for s in st], rc
+
     def step_lim(self, prob: Problem, y, tau: float, *, t: float = 0.0, T: float = math.inf, tol: float = 0.0):
         _check_field(y, prob.N)
         rec = ChStepRecord()
@@ -320,13 +340,22 @@ class Server:
         if rc != CH_OK:
             raise ChError(rc, f"ch_server_create: {self.lib.ch_strerror(rc).decode()}")
 
-    def submit(self, y0, n: int, eps: float, steps: int, tau0: float = 1e-3) -> int:
-        """Queue a 2-D request (y0 is copied); returns its ticket."""
+    def submit(self, y0, n: int, eps: float, steps: int = 0, tau0: float = 1e-3, *, method: int = CH_METHOD_EE,
+               T: float = math.inf, tol: float = 0.0) -> int:
+        """Queue a 2-D request (y0 is copied: a CUDA tensor, or a host numpy
+        array); returns its ticket.  steps <= 0 runs until T."""
+        import numpy as np
         import torch
 
-        _check_field(y0, n * n)
-        torch.cuda.current_stream(y0.device).synchronize()   # the library copies y0 on its own stream
-        req = ChRequest(int(n), float(eps), c_void_p(y0.data_ptr()), int(steps), float(tau0))
+        if isinstance(y0, np.ndarray):
+            if y0.dtype != np.float64 or not y0.flags["C_CONTIGUOUS"] or y0.size != n * n:
+                raise ValueError("host fields must be contiguous float64 arrays of n*n values")
+            ptr, host = c_void_p(y0.ctypes.data), 1
+        else:
+            _check_field(y0, n * n)
+            torch.cuda.current_stream(y0.device).synchronize()   # the library copies y0 on its own stream
+            ptr, host = c_void_p(y0.data_ptr()), 0
+        req = ChRequest(int(n), float(eps), ptr, int(steps), float(tau0), int(method), float(T), float(tol), host)
         t = ctypes.c_ulonglong()
         rc = self.lib.ch_submit(self._ptr, byref(req), byref(t))
         if rc != CH_OK:

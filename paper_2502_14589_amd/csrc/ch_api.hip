@@ -44,13 +44,16 @@ struct ch_ctx {
                              // the sequence number of the last DCGS2 update launch begun
     int useq = 0;            // DCGS2 update launches issued (their sequence numbers)
     Ctl* hctl = nullptr;     // pinned mirror of the control blocks
-    // instance table
-    Inst* d_inst = nullptr;
-    int* d_sb2i = nullptr;
-    int* d_cb2i = nullptr;
-    int* d_wb2i = nullptr;
-    size_t inst_cap = 0, map_cap = 0;
-    std::vector<Inst> h_inst;
+    // instance tables: store 0 serves every run; the server keeps the
+    // table of its LIM members in store 1 beside that of its EE members
+    struct TableStore {
+        Inst* d_inst = nullptr;
+        int* d_sb2i = nullptr;
+        int* d_cb2i = nullptr;
+        int* d_wb2i = nullptr;
+        size_t inst_cap = 0, map_cap = 0;
+        std::vector<Inst> h_inst;
+    } store[2];
     LaunchEnv env{};         // second stream for the DCGS2 phi tests
     std::string err;
 };
@@ -281,13 +284,15 @@ Inst make_inst(const Member& m, int i, int dim, int prec, int sblk0, int cblk0, 
     return I;
 }
 
-// Workgroup ranges of each instance and the block-to-instance maps.
-int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, int prec, Table* t) {
+// Workgroup ranges of each instance and the block-to-instance maps, kept in
+// table store `which` of the context.
+int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, int prec, Table* t, int which = 0) {
     const int ni = (int)ms.size();
-    ctx->h_inst.assign(ni, Inst{});
+    ch_ctx::TableStore& ts = ctx->store[which];
+    ts.h_inst.assign(ni, Inst{});
     std::vector<int> sb, cb, wb;
     for (int i = 0; i < ni; ++i) {
-        Inst& I = ctx->h_inst[i];
+        Inst& I = ts.h_inst[i];
         I = make_inst(ms[i], i, dim, prec, (int)sb.size(), (int)cb.size(), (int)wb.size());
         sb.insert(sb.end(), I.sblk, i);
         cb.insert(cb.end(), I.cblk, i);
@@ -298,44 +303,44 @@ int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, int prec, T
         return CH_EINVAL;
     }
     int rc;
-    if ((size_t)ni > ctx->inst_cap) {
-        free_dev(ctx->d_inst);
-        ctx->d_inst = nullptr;
-        ctx->inst_cap = 0;
-        if ((rc = alloc_dev(ctx, (void**)&ctx->d_inst, sizeof(Inst) * ni))) return rc;
-        ctx->inst_cap = ni;
+    if ((size_t)ni > ts.inst_cap) {
+        free_dev(ts.d_inst);
+        ts.d_inst = nullptr;
+        ts.inst_cap = 0;
+        if ((rc = alloc_dev(ctx, (void**)&ts.d_inst, sizeof(Inst) * ni))) return rc;
+        ts.inst_cap = ni;
     }
     const size_t mneed = std::max(std::max(sb.size(), cb.size()), std::max(wb.size(), (size_t)1));
-    if (mneed > ctx->map_cap) {
-        free_dev(ctx->d_sb2i);
-        free_dev(ctx->d_cb2i);
-        free_dev(ctx->d_wb2i);
-        ctx->d_sb2i = ctx->d_cb2i = ctx->d_wb2i = nullptr;
-        ctx->map_cap = 0;
-        if ((rc = alloc_dev(ctx, (void**)&ctx->d_sb2i, sizeof(int) * mneed))) return rc;
-        if ((rc = alloc_dev(ctx, (void**)&ctx->d_cb2i, sizeof(int) * mneed))) return rc;
-        if ((rc = alloc_dev(ctx, (void**)&ctx->d_wb2i, sizeof(int) * mneed))) return rc;
-        ctx->map_cap = mneed;
+    if (mneed > ts.map_cap) {
+        free_dev(ts.d_sb2i);
+        free_dev(ts.d_cb2i);
+        free_dev(ts.d_wb2i);
+        ts.d_sb2i = ts.d_cb2i = ts.d_wb2i = nullptr;
+        ts.map_cap = 0;
+        if ((rc = alloc_dev(ctx, (void**)&ts.d_sb2i, sizeof(int) * mneed))) return rc;
+        if ((rc = alloc_dev(ctx, (void**)&ts.d_cb2i, sizeof(int) * mneed))) return rc;
+        if ((rc = alloc_dev(ctx, (void**)&ts.d_wb2i, sizeof(int) * mneed))) return rc;
+        ts.map_cap = mneed;
     }
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_inst, ctx->h_inst.data(), sizeof(Inst) * ni, hipMemcpyHostToDevice,
+    HIP_TRY(ctx, hipMemcpyAsync(ts.d_inst, ts.h_inst.data(), sizeof(Inst) * ni, hipMemcpyHostToDevice,
                                 ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_sb2i, sb.data(), sizeof(int) * sb.size(), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->d_cb2i, cb.data(), sizeof(int) * cb.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ts.d_sb2i, sb.data(), sizeof(int) * sb.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ts.d_cb2i, cb.data(), sizeof(int) * cb.size(), hipMemcpyHostToDevice, ctx->stream));
     if (!wb.empty())
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_wb2i, wb.data(), sizeof(int) * wb.size(), hipMemcpyHostToDevice,
+        HIP_TRY(ctx, hipMemcpyAsync(ts.d_wb2i, wb.data(), sizeof(int) * wb.size(), hipMemcpyHostToDevice,
                                     ctx->stream));
     // the host vectors must outlive the asynchronous copies
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    t->inst = ctx->d_inst;
-    t->sb2i = ctx->d_sb2i;
-    t->cb2i = ctx->d_cb2i;
-    t->wb2i = ctx->d_wb2i;
+    t->inst = ts.d_inst;
+    t->sb2i = ts.d_sb2i;
+    t->cb2i = ts.d_cb2i;
+    t->wb2i = ts.d_wb2i;
     t->ninst = ni;
     t->sgrid = (int)sb.size();
     t->cgrid = (int)cb.size();
     t->wgrid = (int)wb.size();
     t->dim = dim;
-    t->hinst = ctx->h_inst.data();
+    t->hinst = ts.h_inst.data();
     return CH_OK;
 }
 
@@ -535,35 +540,38 @@ int read_head(ch_ctx* ctx, const DevBuffers& b, Ctl* h) {
     return CH_OK;
 }
 
-// LIM step s of a single-grid run (Figs. 1 and 2): bounds of the spectrum,
-// the plan (whose order p the host reads to size the stage launches), the
-// 2p - 1 stages, the estimate and the controller.  The state ping-pongs
-// between b.ybuf[s & 1] and b.ybuf[(s + 1) & 1].  *halted: the run had
-// nothing left to do (t >= T, the step limit, or an error in the plan).
-int issue_lim_step(ch_ctx* ctx, const Table& t, const DevBuffers& b, PartSeq& ps, Ctl* h, long long s,
+// LIM step s of every instance of a table (Figs. 1 and 2): bounds of the
+// spectrum, the plan (whose Chebyshev orders the host reads to size the
+// stage launches: the largest order decides, instances of smaller order
+// skip the launches past their last), the stages, the estimate and the
+// controller.  Every live instance has taken s steps, so its state
+// ping-pongs between b.ybuf[s & 1] and b.ybuf[(s + 1) & 1].  hctl: host copies
+// of the control blocks, indexed by slot.  *halted: no instance had anything
+// left to do (t >= T, the step limit, or an error in the plan).
+int issue_lim_step(ch_ctx* ctx, const Table& t, const DevBuffers& b, PartSeq& ps, Ctl* hctl, long long s,
                    bool* halted) {
     const double* yin = b.ybuf[s & 1];
     double* yout = b.ybuf[(s + 1) & 1];
     HIP_TRY(ctx, launch_lim_begin(t, b, ps, yin, ctx->stream));
     HIP_TRY(ctx, launch_lim_plan(t, b, ps, ctx->stream));
-    int rc;
-    if ((rc = read_head(ctx, b, h))) return rc;
-    *halted = h->halted != 0;
-    if (*halted) return CH_OK;
-    const int p = h->p;
-    // 2p - 1 stages (the nodes in the plan's order, then again without
-    // beta_1) ping-pong between zbuf and yout so that the last launch
-    // writes yout.  On 2-D strips stage 0 runs alone and the rest in
-    // pairs, two stages per launch.
-    const int nst = 2 * p - 1;
+    for (int i = 0; i < t.ninst; ++i) {
+        const int slot = t.hinst[i].slot;
+        HIP_TRY(ctx, hipMemcpyAsync(hctl + slot, b.ctl + slot, CTL_HEAD, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const bool pairs = lim_stage_pairs(t);
-    const int nl = pairs ? p : nst;
-    const double* src = yin;
+    int nl = 0;
+    for (int i = 0; i < t.ninst; ++i) {
+        const Ctl& h = hctl[t.hinst[i].slot];
+        if (!h.halted) nl = std::max(nl, lim_launches(h.p, pairs));
+    }
+    *halted = nl == 0;
+    if (*halted) return CH_OK;
+    // 2p - 1 stages (the nodes in the plan's order, then again without
+    // beta_1); on 2-D strips stage 0 runs alone and the rest in pairs
     for (int l = 0; l < nl; ++l) {
-        double* dst = ((nl - 1 - l) % 2 == 0) ? yout : b.zbuf;
-        if (pairs && l > 0) HIP_TRY(ctx, launch_lim_stage2(t, b, yin, src, dst, 2 * l - 1, ctx->stream));
-        else HIP_TRY(ctx, launch_lim_stage(t, b, yin, src, dst, l, ctx->stream));
-        src = dst;
+        if (pairs && l > 0) HIP_TRY(ctx, launch_lim_stage2(t, b, yin, yout, l, ctx->stream));
+        else HIP_TRY(ctx, launch_lim_stage(t, b, yin, yout, l, pairs, ctx->stream));
     }
     HIP_TRY(ctx, launch_est_lim(t, b, ps, yin, yout, ctx->stream));
     HIP_TRY(ctx, launch_lim_end(t, b, ps, ctx->stream));
@@ -607,6 +615,51 @@ int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double 
     return h.status;
 }
 
+int run_lim_batch(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, int eyre, double tol,
+                  ch_run_stats* stats) {
+    if (count < 1 || !items) return CH_EINVAL;
+    std::vector<Member> ms(count);
+    size_t pts = 0;
+    for (int i = 0; i < count; ++i) {
+        const ch_batch_item& it = items[i];
+        int rc = check_grid(dim, it.n, it.eps, eyre, &ms[i].sh);
+        if (rc) return rc;
+        if (!it.y || !(it.tau0 > 0.0) || (it.max_steps <= 0 && !(it.T < INFINITY))) return CH_EINVAL;
+        ms[i].eps = it.eps;
+        ms[i].eyre = eyre;
+        ms[i].off = pts;
+        pts += pad64(ms[i].sh.N);
+    }
+    int rc;
+    if ((rc = ensure(ctx, pts, 0, CH_FP64, count, 0, true))) return rc;
+    Table t;
+    if ((rc = build_table(ctx, ms, dim, CH_FP64, &t))) return rc;
+    const DevBuffers& b = ctx->b;
+    for (int i = 0; i < count; ++i) {
+        const ch_batch_item& it = items[i];
+        init_ctl(ctx->hctl + i, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, 0.0, it.tau0, it.T, tol, 0.0, 0.0, 0,
+                 it.max_steps, nullptr, 0, ctx->expect[i]);
+        if ((rc = copy_in(ctx, ms[i], it.y))) return rc;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl) * count, hipMemcpyHostToDevice, ctx->stream));
+    PartSeq ps;
+    ps.base = b.part;
+    for (long long s = 0;; ++s) {
+        bool halted = false;
+        if ((rc = issue_lim_step(ctx, t, b, ps, ctx->hctl, s, &halted))) return rc;
+        if (halted) break;
+    }
+    if ((rc = read_heads(ctx, count))) return rc;
+    int status = CH_OK;
+    for (int i = 0; i < count; ++i) {
+        if ((rc = copy_out(ctx, ms[i], i, items[i].y))) return rc;
+        if (stats) fill_stats(ctx->hctl[i], stats + i);
+        if (ctx->hctl[i].status != CH_OK && status == CH_OK) status = ctx->hctl[i].status;
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return status;
+}
+
 void record_from_head(const Ctl& h, ch_step_record* out) {
     if (!out) return;
     memset(out, 0, sizeof(*out));
@@ -633,6 +686,8 @@ struct Req {
     unsigned long long id = 0;
     int n = 0, steps = 0;
     double eps = 0, tau0 = 0;
+    int method = CH_METHOD_EE;
+    double T = INFINITY, tol = 0.0;
     long long N = 0;
     size_t len = 0;            // pooled points (padded)
     int sblk = 0, cblk = 0;    // workgroups in a batched launch
@@ -753,6 +808,7 @@ Member member_of(const Req* r) {
 }
 
 // One iteration of the scheduler: admit, start, one batch step, retire.
+// t: the tables of the EE2 members (t[0]) and the LIM members (t[1]).
 int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
     ch_ctx* ctx = S->ctx;
     const DevBuffers& b = ctx->b;
@@ -793,42 +849,65 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
     int rc;
     const int p = (int)(*par & 1);
     if (!admitted.empty()) {
-        // start: state into the buffer of the current parity, f(y0), first step begin
+        // start: state into the buffer of the current parity; EE2: f(y0) and
+        // the first step's begin
         std::vector<Member> ms;
         for (Req* r : admitted) {
-            init_ctl(ctx->hctl + r->slot, MODE_EE, 0.0, r->tau0, INFINITY, S->opts.tol, S->opts.tol_phi_fixed,
-                     S->opts.tau_min, S->opts.m_max, r->steps, nullptr, 0, ctx->expect[r->slot]);
+            const double tol = r->tol > 0.0 ? r->tol : S->opts.tol;
+            if (r->method == CH_METHOD_LIM)
+                init_ctl(ctx->hctl + r->slot, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, 0.0, r->tau0, r->T, tol, 0.0,
+                         0.0, 0, r->steps, nullptr, 0, ctx->expect[r->slot]);
+            else
+                init_ctl(ctx->hctl + r->slot, MODE_EE, 0.0, r->tau0, r->T, tol, r->tol > 0.0 ? 0.0 : S->opts.tol_phi_fixed,
+                         S->opts.tau_min, S->opts.m_max, r->steps, nullptr, 0, ctx->expect[r->slot]);
             ctx->hctl[r->slot].cur = p;
             HIP_TRY(ctx, hipMemcpyAsync(b.ctl + r->slot, ctx->hctl + r->slot, sizeof(Ctl), hipMemcpyHostToDevice,
                                         ctx->stream));
             HIP_TRY(ctx, hipMemcpyAsync(b.ybuf[p] + r->off, r->buf, sizeof(double) * r->N, hipMemcpyDeviceToDevice,
                                         ctx->stream));
-            ms.push_back(member_of(r));
+            if (r->method == CH_METHOD_EE) ms.push_back(member_of(r));
         }
-        Table ta;
-        if ((rc = build_table(ctx, ms, 2, S->prec, &ta))) return rc;
-        PartSeq ps;
-        ps.base = b.part;
-        HIP_TRY(ctx, launch_resid(ta, S->prec, b, ps, b.ybuf[p], b.ybuf[p], true, true, ctx->stream));
-        HIP_TRY(ctx, launch_after_resid(ta, b, ps, true, ctx->stream));
-        for (Req* r : admitted) ctx->expect[r->slot] += 1;
+        if (!ms.empty()) {
+            Table ta;
+            if ((rc = build_table(ctx, ms, 2, S->prec, &ta))) return rc;
+            PartSeq ps;
+            ps.base = b.part;
+            HIP_TRY(ctx, launch_resid(ta, S->prec, b, ps, b.ybuf[p], b.ybuf[p], true, true, ctx->stream));
+            HIP_TRY(ctx, launch_after_resid(ta, b, ps, true, ctx->stream));
+            for (Req* r : admitted)
+                if (r->method == CH_METHOD_EE) ctx->expect[r->slot] += 1;
+        }
         *dirty = true;
     }
     if (live.empty()) return CH_OK;
+    std::vector<Req*> ee, lim;
+    for (Req* r : live) (r->method == CH_METHOD_LIM ? lim : ee).push_back(r);
     if (*dirty) {
-        std::vector<Member> ms;
-        for (Req* r : live) ms.push_back(member_of(r));
-        if ((rc = build_table(ctx, ms, 2, S->prec, t))) return rc;
+        // EE2 members in table store 0 (t[0]), LIM members in store 1 (t[1])
+        std::vector<Member> me, ml;
+        for (Req* r : ee) me.push_back(member_of(r));
+        for (Req* r : lim) ml.push_back(member_of(r));
+        if (!me.empty() && (rc = build_table(ctx, me, 2, S->prec, &t[0], 0))) return rc;
+        if (!ml.empty() && (rc = build_table(ctx, ml, 2, CH_FP64, &t[1], 1))) return rc;
         *dirty = false;
     }
-    PartSeq ps;
-    ps.base = b.part;
-    HIP_TRY(ctx, launch_arnoldi(*t, S->prec, b, ps, b.ybuf[p], S->opts.m_max, S->opts.orth, ctx->expect.data(),
-                                &ctx->env, ctx->stream));
-    HIP_TRY(ctx, launch_update(*t, S->prec, b, b.ybuf[p], b.ybuf[p ^ 1], S->opts.orth == CH_ORTH_DCGS2, ctx->stream));
-    HIP_TRY(ctx, launch_est_ee(*t, S->prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
-    HIP_TRY(ctx, launch_step_end(*t, b, ps, true, ctx->stream));
-    for (Req* r : live) ctx->expect[r->slot] += 1;
+    if (!ee.empty()) {
+        PartSeq ps;
+        ps.base = b.part;
+        HIP_TRY(ctx, launch_arnoldi(t[0], S->prec, b, ps, b.ybuf[p], S->opts.m_max, S->opts.orth, ctx->expect.data(),
+                                    &ctx->env, ctx->stream));
+        HIP_TRY(ctx, launch_update(t[0], S->prec, b, b.ybuf[p], b.ybuf[p ^ 1], S->opts.orth == CH_ORTH_DCGS2,
+                                   ctx->stream));
+        HIP_TRY(ctx, launch_est_ee(t[0], S->prec, b, ps, b.ybuf[p], b.ybuf[p ^ 1], ctx->stream));
+        HIP_TRY(ctx, launch_step_end(t[0], b, ps, true, ctx->stream));
+        for (Req* r : ee) ctx->expect[r->slot] += 1;
+    }
+    if (!lim.empty()) {
+        PartSeq ps;
+        ps.base = b.part;
+        bool halted = false;
+        if ((rc = issue_lim_step(ctx, t[1], b, ps, ctx->hctl, *par, &halted))) return rc;
+    }
     *par += 1;
     if ((rc = read_slot_heads(ctx, live))) return rc;
     std::vector<Req*> done;
@@ -864,10 +943,10 @@ int serve_once(ch_server* S, long long* par, Table* t, bool* dirty) {
 void serve_loop(ch_server* S) {
     (void)hipSetDevice(S->device);
     long long par = 0;
-    Table t{};
+    Table t[2]{};
     bool dirty = true;
     for (;;) {
-        const int rc = serve_once(S, &par, &t, &dirty);
+        const int rc = serve_once(S, &par, t, &dirty);
         if (rc == 1) break;
         if (rc != CH_OK) {   // device error: fail everything and stop
             std::lock_guard<std::mutex> lk(S->mu);
@@ -995,10 +1074,11 @@ int ch_destroy(ch_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->env.side);
     DevBuffers& b = ctx->b;
     for (void* p : {(void*)b.V, (void*)b.ybuf[0], (void*)b.ybuf[1], (void*)b.fcur, (void*)b.y32, (void*)b.zbuf,
-                    (void*)b.part, (void*)b.dots, (void*)b.lorder, (void*)b.ctl, (void*)ctx->rec, (void*)ctx->d_inst, (void*)ctx->d_sb2i,
-                    b.phibig,
-                    (void*)ctx->d_cb2i, (void*)ctx->d_wb2i, (void*)b.lcoef})
+                    (void*)b.part, (void*)b.dots, (void*)b.lorder, (void*)b.ctl, (void*)ctx->rec, b.phibig,
+                    (void*)b.lcoef})
         free_dev(p);
+    for (auto& ts : ctx->store)
+        for (void* p : {(void*)ts.d_inst, (void*)ts.d_sb2i, (void*)ts.d_cb2i, (void*)ts.d_wb2i}) free_dev(p);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
     if (ctx->hflag) (void)hipHostFree(ctx->hflag);
     (void)hipEventDestroy(ctx->env.ev_main);
@@ -1046,6 +1126,13 @@ int ch_run_ee_batch(ch_ctx* ctx, int count, ch_batch_item* items, int dim, int e
     if (!ctx) return CH_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
     return run_ee_batch(ctx, count, items, dim, eyre, prec, opts, stats);
+}
+
+int ch_run_lim_batch(ch_ctx* ctx, int count, ch_batch_item* items, int dim, int eyre, double tol,
+                     ch_run_stats* stats) {
+    if (!ctx) return CH_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
+    return run_lim_batch(ctx, count, items, dim, eyre, tol, stats);
 }
 
 int ch_run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t0, double T, int max_steps,
@@ -1254,10 +1341,10 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, c
             }
             case CH_KERNEL_LIM_STAGE2:  // read y^n, the stage before the pair; write the second
                 bytes += 24.0 * N;
-                return launch_lim_stage2(t, b, y, y, b.zbuf, 0, ctx->stream, true);
+                return launch_lim_stage2(t, b, y, b.ybuf[1], 1, ctx->stream, true);
             default:                    // read y^n, the previous stage; write the next
                 bytes += 24.0 * N;
-                return launch_lim_stage(t, b, y, y, b.zbuf, 0, ctx->stream, true);
+                return launch_lim_stage(t, b, y, b.ybuf[1], 0, lim_stage_pairs(t), ctx->stream, true);
         }
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1317,7 +1404,7 @@ int ch_server_create(int device, int prec, const ch_ee_opts* opts, size_t hbm_bu
         return CH_EDEVICE;
     }
     if ((rc = ch_create(&S->ctx, device, S->stream)) != CH_OK ||
-        (rc = ensure(S->ctx, pts, opts->m_max, prec, max_slots, 0, false)) != CH_OK) {
+        (rc = ensure(S->ctx, pts, opts->m_max, prec, max_slots, 0, true)) != CH_OK) {
         if (S->ctx) ch_destroy(S->ctx);
         (void)hipStreamDestroy(S->io);
         (void)hipStreamDestroy(S->stream);
@@ -1361,13 +1448,18 @@ int ch_submit(ch_server* S, const ch_request* q, unsigned long long* ticket) {
     Shape sh;
     int rc = check_grid(2, q->n, q->eps, 0, &sh);
     if (rc) return rc;
-    if (q->steps < 1 || !(q->tau0 > 0.0)) return CH_EINVAL;
+    if (!(q->tau0 > 0.0) || (q->method != CH_METHOD_EE && q->method != CH_METHOD_LIM)) return CH_EINVAL;
+    if ((q->steps < 1 && !(q->T < INFINITY)) || !(q->T > 0.0) || !(q->tol < INFINITY)) return CH_EINVAL;
+    if (q->y0_on_host != 0 && q->y0_on_host != 1) return CH_EINVAL;
     Req* r = new (std::nothrow) Req();
     if (!r) return CH_ENOMEM;
     r->n = q->n;
     r->eps = q->eps;
     r->steps = q->steps;
     r->tau0 = q->tau0;
+    r->method = q->method;
+    r->T = q->T;
+    r->tol = q->tol;
     r->N = sh.N;
     r->len = pad64(sh.N);
     inst_blocks(2, q->n, sh.N, &r->sblk, &r->cblk);
@@ -1381,7 +1473,8 @@ int ch_submit(ch_server* S, const ch_request* q, unsigned long long* ticket) {
         delete r;
         return CH_ENOMEM;
     }
-    if (hipMemcpyAsync(r->buf, q->y0, sizeof(double) * r->N, hipMemcpyDeviceToDevice, S->io) != hipSuccess ||
+    if (hipMemcpyAsync(r->buf, q->y0, sizeof(double) * r->N,
+                       q->y0_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, S->io) != hipSuccess ||
         hipStreamSynchronize(S->io) != hipSuccess) {
         (void)hipGetLastError();
         give_buffer(S, r->buf, r->cap);

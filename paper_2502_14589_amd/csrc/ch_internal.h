@@ -180,10 +180,10 @@ hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStr
 inline bool uses_strips(const Table& t) { return t.dim == 2; }
 hipError_t launch_matvec_strip(const Table& t, int prec, const DevBuffers& b, const double* y, int k, int dots,
                                bool store_w, double* pout, bool timing, hipStream_t s);
-hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                                  int pos, bool timing, hipStream_t s);
-hipError_t launch_lim_stage2_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                                   int pos, bool timing, hipStream_t s);
+hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
+                                  bool pairs, bool timing, hipStream_t s);
+hipError_t launch_lim_stage2_strip(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
+                                   bool timing, hipStream_t s);
 hipError_t launch_est_ee_strip(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
                                double* pout, hipStream_t s);
 // 3-D DCGS2 matvec on z-marching x-y tiles (ch_march.hip); its workgroups are
@@ -231,13 +231,38 @@ hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq&
 hipError_t launch_step_end(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_next, hipStream_t s);
 hipError_t launch_lim_begin(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y, hipStream_t s);
 hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s);
-// Stage pos (0 .. 2p - 2) of the LIM step.
-hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                            int pos, hipStream_t s, bool timing = false);
-// Stages pos and pos + 1 in one launch (2-D strips only: lim_stage_pairs).
+// Launch l of the stages of a LIM step whose Chebyshev order p each
+// instance reads from its control block: single stages (pairs = 0: 2p - 1
+// launches, stage l), or stage 0 alone and then two stages per launch
+// (pairs = 1: p launches, stages 2l - 1 and 2l).  The launches ping-pong
+// between zbuf and yout so that each instance's last launch writes yout;
+// launch 0 reads y^n.  Launches past an instance's last do nothing for it,
+// so one sequence serves a batch whose members have different p.
+struct LimLaunch {
+    int pos;            // first stage position of the launch
+    const double* src;  // the previous stage (y^n for launch 0)
+    double* dst;
+    bool live;
+};
+__host__ __device__ inline LimLaunch lim_launch(int p, int l, bool pairs, const double* yin, double* yout,
+                                                double* zbuf) {
+    const int nl = pairs ? p : 2 * p - 1;
+    LimLaunch L;
+    L.live = l < nl;
+    L.pos = pairs ? (l == 0 ? 0 : 2 * l - 1) : l;
+    L.dst = ((nl - 1 - l) & 1) == 0 ? yout : zbuf;
+    L.src = l == 0 ? yin : (((nl - l) & 1) == 0 ? yout : zbuf);
+    return L;
+}
+// Launches of one LIM step of order p.
+inline int lim_launches(int p, bool pairs) { return pairs ? p : 2 * p - 1; }
+// Stage launch l (a single stage; with pairs only l = 0).
+hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l, bool pairs,
+                            hipStream_t s, bool timing = false);
+// Two stages per launch (2-D strips only: lim_stage_pairs), launch l >= 1.
 inline bool lim_stage_pairs(const Table& t) { return uses_strips(t); }
-hipError_t launch_lim_stage2(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                             int pos, hipStream_t s, bool timing = false);
+hipError_t launch_lim_stage2(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
+                             hipStream_t s, bool timing = false);
 hipError_t launch_est_lim(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y0, const double* y1,
                           hipStream_t s);
 hipError_t launch_lim_end(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s);

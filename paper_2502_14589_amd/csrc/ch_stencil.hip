@@ -340,11 +340,17 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_ee(Ctl* __restrict__ ctls, con
 template <int DIM, bool SINGLE, int TAG>
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ sb2i, const Inst inst0, int ninst, const double* __restrict__ ybase,
-                                                        const double* __restrict__ zbase, double* __restrict__ obase,
-                                                        const double* __restrict__ coefs, int pos) {
+                                                        double* youtbase, double* zbufbase,
+                                                        const double* __restrict__ coefs, int l) {
     const Inst I = SINGLE ? inst0 : insts[sb2i[blockIdx.x]];
     Ctl* ctl = ctls + I.slot;
-    if (ctl->halted || pos >= 2 * ctl->p - 1) return;
+    if (ctl->halted) return;
+    // stage launch l of this instance (single stages: launch l is stage l)
+    const LimLaunch L = lim_launch(ctl->p, l, false, ybase, youtbase, zbufbase);
+    if (!L.live) return;
+    const double* zbase = L.src;
+    double* obase = L.dst;
+    const int pos = L.pos;
     using R1 = Region<DIM, 1>;
     using R2 = Region<DIM, 2>;
     __shared__ double sz[R2::SIZE];
@@ -537,29 +543,30 @@ hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq&
                       : launch_est_ee_t<3, float>(t, b, ps, y0, y1, b.y32, s);
 }
 
-hipError_t launch_lim_stage2(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                             int pos, hipStream_t s, bool timing) {
+hipError_t launch_lim_stage2(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
+                             hipStream_t s, bool timing) {
     if (!lim_stage_pairs(t)) return hipErrorInvalidValue;
-    return launch_lim_stage2_strip(t, b, y, z, out, pos, timing, s);
+    return launch_lim_stage2_strip(t, b, yin, yout, l, timing, s);
 }
 
-hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                            int pos, hipStream_t s, bool timing) {
-    if (uses_strips(t)) return launch_lim_stage_strip(t, b, y, z, out, pos, timing, s);
+hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l, bool pairs,
+                            hipStream_t s, bool timing) {
+    if (uses_strips(t)) return launch_lim_stage_strip(t, b, yin, yout, l, pairs, timing, s);
+    if (pairs) return hipErrorInvalidValue;
     if (t.dim == 2)
         if (timing)
-            hipLaunchKernelGGL((k_lim_stage<2, true, 1>), SARGS, y, z, out, b.lcoef, pos);
+            hipLaunchKernelGGL((k_lim_stage<2, true, 1>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
         else if (t.ninst == 1)
-            hipLaunchKernelGGL((k_lim_stage<2, true, 0>), SARGS, y, z, out, b.lcoef, pos);
+            hipLaunchKernelGGL((k_lim_stage<2, true, 0>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
         else
-            hipLaunchKernelGGL((k_lim_stage<2, false, 0>), SARGS, y, z, out, b.lcoef, pos);
+            hipLaunchKernelGGL((k_lim_stage<2, false, 0>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
     else
         if (timing)
-            hipLaunchKernelGGL((k_lim_stage<3, true, 1>), SARGS, y, z, out, b.lcoef, pos);
+            hipLaunchKernelGGL((k_lim_stage<3, true, 1>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
         else if (t.ninst == 1)
-            hipLaunchKernelGGL((k_lim_stage<3, true, 0>), SARGS, y, z, out, b.lcoef, pos);
+            hipLaunchKernelGGL((k_lim_stage<3, true, 0>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
         else
-            hipLaunchKernelGGL((k_lim_stage<3, false, 0>), SARGS, y, z, out, b.lcoef, pos);
+            hipLaunchKernelGGL((k_lim_stage<3, false, 0>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
     return hipGetLastError();
 }
 

@@ -428,15 +428,22 @@ __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restri
     }
 }
 
+// Stage launch l (lim_launch) of each instance: its source and destination
+// follow from its own Chebyshev order.
 template <bool SINGLE, int TAG, int VX>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                           const int* __restrict__ wb2i, const Inst inst0, int ninst,
-                                                          const double* __restrict__ ybase,
-                                                          const double* __restrict__ zbase, double* __restrict__ obase,
-                                                          const double* __restrict__ coefs, int pos) {
+                                                          const double* __restrict__ ybase, double* youtbase,
+                                                          double* zbufbase, const double* __restrict__ coefs, int l,
+                                                          int pairs) {
     const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
     Ctl* ctl = ctls + I.slot;
-    if (ctl->halted || pos >= 2 * ctl->p - 1) return;
+    if (ctl->halted) return;
+    const LimLaunch L = lim_launch(ctl->p, l, pairs != 0, ybase, youtbase, zbufbase);
+    if (!L.live) return;
+    const double* zbase = L.src;
+    double* obase = L.dst;
+    const int pos = L.pos;
     const double* cf = coefs + ((size_t)I.slot * 2 * CH_PMAX + pos) * 2;
     const double ta = cf[0], inv = cf[1], tau = ctl->tau0;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -554,12 +561,16 @@ __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restr
 template <bool SINGLE, int TAG, int VX>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage2_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                            const int* __restrict__ wb2i, const Inst inst0, int ninst,
-                                                           const double* __restrict__ ybase,
-                                                           const double* __restrict__ zbase, double* __restrict__ obase,
-                                                           const double* __restrict__ coefs, int pos) {
+                                                           const double* __restrict__ ybase, double* youtbase,
+                                                           double* zbufbase, const double* __restrict__ coefs, int l) {
     const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
     Ctl* ctl = ctls + I.slot;
-    if (ctl->halted || pos + 1 >= 2 * ctl->p - 1) return;
+    if (ctl->halted) return;
+    const LimLaunch L = lim_launch(ctl->p, l, true, ybase, youtbase, zbufbase);
+    if (!L.live) return;
+    const double* zbase = L.src;
+    double* obase = L.dst;
+    const int pos = L.pos;
     const double* cf = coefs + ((size_t)I.slot * 2 * CH_PMAX + pos) * 2;
     const double ta1 = cf[0], inv1 = cf[1], ta2 = cf[2], inv2 = cf[3], tau = ctl->tau0;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -726,32 +737,33 @@ hipError_t launch_matvec_strip(const Table& t, int prec, const DevBuffers& b, co
     return hipGetLastError();
 }
 
-hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                                  int pos, bool timing, hipStream_t s) {
+hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
+                                  bool pairs, bool timing, hipStream_t s) {
     const bool two = t.hinst[0].vx >= 2;
+    const int pr = pairs ? 1 : 0;
     if (timing) {
-        if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 1, 2>), WARGS, y, z, out, b.lcoef, pos);
-        else hipLaunchKernelGGL((k_lim_stage_s<true, 1, 1>), WARGS, y, z, out, b.lcoef, pos);
+        if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 1, 2>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
+        else hipLaunchKernelGGL((k_lim_stage_s<true, 1, 1>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
     } else if (t.ninst == 1) {
-        if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 0, 2>), WARGS, y, z, out, b.lcoef, pos);
-        else hipLaunchKernelGGL((k_lim_stage_s<true, 0, 1>), WARGS, y, z, out, b.lcoef, pos);
+        if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 0, 2>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
+        else hipLaunchKernelGGL((k_lim_stage_s<true, 0, 1>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
     } else {
-        hipLaunchKernelGGL((k_lim_stage_s<false, 0, 0>), WARGS, y, z, out, b.lcoef, pos);
+        hipLaunchKernelGGL((k_lim_stage_s<false, 0, 0>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_lim_stage2_strip(const Table& t, const DevBuffers& b, const double* y, const double* z, double* out,
-                                   int pos, bool timing, hipStream_t s) {
+hipError_t launch_lim_stage2_strip(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
+                                   bool timing, hipStream_t s) {
     const bool two = t.hinst[0].vx >= 2;
     if (timing) {
-        if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 1, 2>), WARGS, y, z, out, b.lcoef, pos);
-        else hipLaunchKernelGGL((k_lim_stage2_s<true, 1, 1>), WARGS, y, z, out, b.lcoef, pos);
+        if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 1, 2>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
+        else hipLaunchKernelGGL((k_lim_stage2_s<true, 1, 1>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
     } else if (t.ninst == 1) {
-        if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 2>), WARGS, y, z, out, b.lcoef, pos);
-        else hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 1>), WARGS, y, z, out, b.lcoef, pos);
+        if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 2>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
+        else hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 1>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
     } else {
-        hipLaunchKernelGGL((k_lim_stage2_s<false, 0, 0>), WARGS, y, z, out, b.lcoef, pos);
+        hipLaunchKernelGGL((k_lim_stage2_s<false, 0, 0>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
     }
     return hipGetLastError();
 }

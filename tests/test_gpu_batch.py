@@ -127,3 +127,39 @@ def test_batched_workload_64_instances(ctx):
         yr, rec = O.ee_adaptive(inst[i].y0, O.Problem(2, inst[i].n, inst[i].eps), 1e-3, math.inf, 1e-4, 30,
                                 max_steps=10)
         assert rel(gs[i].cpu().numpy(), yr) <= 1e-5, (i, inst[i].n)
+
+
+LIM_2D = [(40, 0.05, 0.1), (64, 0.03, -0.2), (33, 0.06, 0.0), (96, 0.02, 0.25), (70, 0.04, 0.15)]
+
+
+@pytest.mark.parametrize("dim,tol", [(2, 1e-4), (2, 0.0), (3, 1e-4)])
+def test_lim_batch_equals_separate_runs(ctx, dim, tol):
+    """LIM on ragged instances in one batch (Figs. 1 and 2): each instance has
+    its own Chebyshev order p per step (the stage launches run to the
+    largest; an instance skips those past its last); every result equals its
+    separate ch_run_lim run bit for bit, and the FP64 oracle to 1e-10."""
+    say(f"LIM batch dim={dim} tol={tol}")
+    cases = LIM_2D if dim == 2 else [(12, 0.05, 0.1), (17, 0.04, -0.1), (10, 0.06, 0.0)]
+    ys = [uniform_field(n, dim, m, 0.05, seed=1200 + n) for n, e, m in cases]
+    ns, eps = [c[0] for c in cases], [c[1] for c in cases]
+    taus = [1e-4 if dim == 2 else 2e-3] * len(cases)
+    steps = [4, 6, 3, 5, 2][: len(cases)]
+    gs = [dev(y) for y in ys]
+    st, rc = ctx.run_lim_batch(gs, ns, eps, dim=dim, tau0=taus, max_steps=steps, tol=tol)
+    assert rc == ch.CH_OK
+    ps_seen = set()
+    for i, (y, g) in enumerate(zip(ys, gs)):
+        assert st[i]["steps"] == steps[i]
+        solo = dev(y)
+        st1, recs = ctx.run_lim(ch.Problem(dim, ns[i], eps[i]), solo, taus[i], max_steps=steps[i], tol=tol,
+                                records=True)
+        ps_seen.update(r["j"] for r in recs)
+        assert st1["matvecs"] == st[i]["matvecs"]
+        assert np.array_equal(solo.cpu().numpy(), g.cpu().numpy()), i
+        po = O.Problem(dim, ns[i], eps[i])
+        if tol > 0:
+            y_ref, _ = O.lim_adaptive(y, po, taus[i], math.inf, tol, max_steps=steps[i])
+        else:
+            y_ref, _ = O.lim_const_run(y, po, taus[i], steps[i])
+        assert rel(g.cpu().numpy(), y_ref) <= 1e-10, i
+    assert len(ps_seen) >= 3      # the members' orders differ
