@@ -4,8 +4,9 @@
  *
  *     y' = -A (F'(y) + eps^2 A y),   F'(y) = y^3 - y        (Section 2, eq. IVP, eq. F)
  *
- * on a periodic grid of n^dim points over [0,1]^dim (h = 1/n), where -A is the
- * standard (2 dim + 1)-point Laplacian.  Two schemes of Botchev (arXiv
+ * on a grid of n^dim points over [0,L]^dim (h = L/n; periodic, or with the
+ * homogeneous Neumann conditions of the paper on a cell-centred grid), where
+ * -A is the standard (2 dim + 1)-point Laplacian.  Two schemes of Botchev (arXiv
  * 2502.14589) are provided:
  *
  *   EE2  exponential Euler of order 2 (Section 4): the Jacobian is frozen at
@@ -74,12 +75,25 @@ enum ch_precision {
 /* Largest grid (points) of ch_step_lim_noalloc. */
 #define CH_NOALLOC_MAX_POINTS (1 << 20)
 
+/*
+ * Boundary conditions of the grid (Section 2, eq. CH; Section 5.1).
+ *   CH_BC_PERIODIC: nodes x_i = i h on the torus [0, L)^dim.
+ *   CH_BC_NEUMANN: homogeneous Neumann conditions for c and mu on the
+ *     cell-centred grid x_i = (i + 1/2) h of (0, L)^dim (the paper's test
+ *     problem): a mirror ghost cell y_{-1} = y_0, y_n = y_{n-1}, so the
+ *     boundary rows of A have (number of neighbours) / h^2 on the diagonal,
+ *     A is symmetric positive semidefinite and A 1 = 0.  2-D only.
+ */
+enum ch_bc { CH_BC_PERIODIC = 0, CH_BC_NEUMANN = 1 };
+
 typedef struct {
     int dim;        /* 2 or 3 */
-    int n;          /* grid points per direction, >= 5; periodic; h = 1/n */
+    int n;          /* grid points per direction, >= 5; h = length / n */
     double eps;     /* interface parameter epsilon > 0 */
     int eyre;       /* 0: eq. A_g; 1: Eyre splitting eq. A_g_cs */
     int prec;       /* ch_precision (EE2 only; LIM always runs in FP64) */
+    int bc;         /* ch_bc (0, the zero-initialised default: periodic) */
+    double length;  /* side L of the domain (<= 0: 1, the unit cube) */
 } ch_problem;
 
 /*

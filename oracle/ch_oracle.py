@@ -10,7 +10,10 @@ module imports nothing from the product package.
 
 Conventions (the paper's notation):
   * ``y`` is the grid vector (length N = n**dim), row-major with x fastest,
-    on the periodic unit cube [0,1]^dim with h = 1/n.
+    on the periodic cube [0,L)^dim with h = L/n (L = 1 by default), or, with
+    bc = "neumann", on the cell-centred grid x_i = (i + 1/2) h of (0,L)^dim
+    with the homogeneous Neumann conditions of the paper's problem (Section 2,
+    eq. CH; Section 5.1): the mirror ghost cell y_{-1} = y_0, y_n = y_{n-1}.
   * ``A`` is the symmetric positive semidefinite matrix whose negative is the
     standard second-order Laplacian (Section 2, eq. IVP).
   * F'(y) = y(y^2 - 1) (eq. F); J_n = 3 diag(y^2) - I (eq. J).
@@ -77,10 +80,12 @@ class Problem:
     n: int
     eps: float
     eyre: bool = False
+    bc: str = "periodic"       # or "neumann"
+    length: float = 1.0        # side L of the domain
 
     @property
     def h(self) -> float:
-        return 1.0 / self.n
+        return self.length / self.n
 
     @property
     def N(self) -> int:
@@ -97,9 +102,21 @@ class Problem:
 # ---------------------------------------------------------------------------
 
 def lap(y: np.ndarray, prob: Problem) -> np.ndarray:
-    """A y, where -A is the standard (2*dim+1)-point periodic Laplacian (eq. IVP)."""
+    """A y, where -A is the standard (2*dim+1)-point Laplacian (eq. IVP): periodic,
+    or with homogeneous Neumann conditions on the cell-centred grid, whose ghost
+    values mirror the boundary cells (np.pad in "edge" mode)."""
     Y = np.asarray(y, dtype=np.float64).reshape(prob.shape)
     out = (2.0 * prob.dim) * Y
+    if prob.bc == "neumann":
+        P = np.pad(Y, 1, mode="edge")
+        inner = tuple(slice(1, -1) for _ in range(prob.dim))
+        for ax in range(prob.dim):
+            lo = list(inner)
+            hi = list(inner)
+            lo[ax] = slice(0, -2)
+            hi[ax] = slice(2, None)
+            out = out - P[tuple(lo)] - P[tuple(hi)]
+        return (out / prob.h ** 2).ravel()
     for ax in range(prob.dim):
         out = out - np.roll(Y, 1, axis=ax) - np.roll(Y, -1, axis=ax)
     return (out / prob.h ** 2).ravel()
@@ -143,14 +160,19 @@ def ghat(y: np.ndarray, prob: Problem) -> np.ndarray:
 
 
 def assemble_A(prob: Problem):
-    """A as a scipy.sparse matrix (Kronecker sum of periodic 1-D second differences)."""
+    """A as a scipy.sparse matrix (Kronecker sum of 1-D second differences: periodic,
+    or Neumann on the cell-centred grid, whose end rows read (y_0 - y_1) / h^2)."""
     import scipy.sparse as sp
 
     n, h = prob.n, prob.h
     e = np.ones(n)
     T = sp.diags([-e[:-1], 2 * e, -e[:-1]], [-1, 0, 1], format="lil")
-    T[0, n - 1] = -1.0
-    T[n - 1, 0] = -1.0
+    if prob.bc == "neumann":
+        T[0, 0] = 1.0
+        T[n - 1, n - 1] = 1.0
+    else:
+        T[0, n - 1] = -1.0
+        T[n - 1, 0] = -1.0
     T = sp.csr_matrix(T) / h ** 2
     I = sp.identity(n, format="csr")
     if prob.dim == 2:
@@ -449,8 +471,12 @@ def lambda_max(y: np.ndarray, prob: Problem) -> float:
 
     Column j of Ahat_n = A diag(d) + eps^2 A^2 is d_j A e_j + eps^2 A^2 e_j, so
     its absolute sum is a sum over the stencil offsets of
-    |d_j a_off + eps^2 b_off|.
+    |d_j a_off + eps^2 b_off|.  With Neumann boundaries the columns near the
+    boundary differ; there the 1-norm is taken from the assembled sparse matrix.
     """
+    if prob.bc == "neumann":
+        M = abs(assemble_ahat(y, prob))
+        return float(np.asarray(M.sum(axis=0)).max())
     if prob.n < 5:
         raise ValueError("n >= 5 required (stencil offsets alias on smaller tori)")
     d = jac_diag(y, prob)
@@ -562,13 +588,17 @@ def lim_const_run(y0: np.ndarray, prob: Problem, tau: float, n_steps: int):
 # ---------------------------------------------------------------------------
 
 def energy(y: np.ndarray, prob: Problem) -> float:
-    """Discrete Ginzburg-Landau energy on the periodic grid (eq. Ediscr with wrap-around).
+    """Discrete Ginzburg-Landau energy (eq. Ediscr): periodic with wrap-around, or
+    on the Neumann grid, where the differences to the mirror ghost cells vanish.
 
     E_h = h^d sum F(y) + eps^2/2 h^(d-2) sum over grid edges of (difference)^2.
     """
     Y = y.reshape(prob.shape)
     h, d = prob.h, prob.dim
-    grad2 = sum(np.sum((np.roll(Y, -1, axis=ax) - Y) ** 2) for ax in range(d))
+    if prob.bc == "neumann":
+        grad2 = sum(np.sum(np.diff(Y, axis=ax) ** 2) for ax in range(d))
+    else:
+        grad2 = sum(np.sum((np.roll(Y, -1, axis=ax) - Y) ** 2) for ax in range(d))
     return float(h ** d * np.sum(Fenergy(Y)) + 0.5 * prob.eps ** 2 * h ** (d - 2) * grad2)
 
 

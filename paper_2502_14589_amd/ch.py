@@ -17,6 +17,7 @@ LIB_PATH = os.environ.get("CH_LIB_PATH") or os.path.join(os.path.dirname(os.path
 
 CH_OK, CH_EINVAL, CH_ENOMEM, CH_ENONFINITE, CH_ETAU_UNDERFLOW, CH_EBUSY, CH_ENOENT, CH_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 CH_FP64, CH_FP32_MIXED = 0, 1
+CH_BC_PERIODIC, CH_BC_NEUMANN = 0, 1
 CH_PHI_SHRINK, CH_PHI_RESTART = 0, 1
 CH_MMAX = 100
 CH_PMAX = 4096
@@ -37,7 +38,8 @@ CH_ORTH_DCGS2, CH_ORTH_MGS = 0, 1
 
 
 class ChProblem(ctypes.Structure):
-    _fields_ = [("dim", c_int), ("n", c_int), ("eps", c_double), ("eyre", c_int), ("prec", c_int)]
+    _fields_ = [("dim", c_int), ("n", c_int), ("eps", c_double), ("eyre", c_int), ("prec", c_int), ("bc", c_int),
+                ("length", c_double)]
 
 
 class ChEeOpts(ctypes.Structure):
@@ -126,16 +128,20 @@ def load_library(path: str = LIB_PATH):
 
 @dataclass
 class Problem:
-    """Periodic Cahn-Hilliard grid: n**dim points on [0,1]^dim, h = 1/n."""
+    """Cahn-Hilliard grid: n**dim points on [0,L]^dim, h = L/n; periodic, or
+    (bc = CH_BC_NEUMANN, 2-D) the cell-centred grid with Neumann boundaries."""
 
     dim: int
     n: int
     eps: float
     eyre: bool = False
     precision: int = CH_FP64
+    bc: int = CH_BC_PERIODIC
+    length: float = 1.0
 
     def c(self) -> ChProblem:
-        return ChProblem(self.dim, self.n, float(self.eps), int(bool(self.eyre)), int(self.precision))
+        return ChProblem(self.dim, self.n, float(self.eps), int(bool(self.eyre)), int(self.precision), int(self.bc),
+                         float(self.length))
 
     @property
     def N(self) -> int:

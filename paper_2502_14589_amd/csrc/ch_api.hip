@@ -89,6 +89,8 @@ size_t pad64(size_t x) { return (x + 63) / 64 * 64; }
 struct Shape {
     int dim, n;
     long long N;
+    int bc = CH_BC_PERIODIC;
+    double length = 1.0;
 };
 
 int check_grid(int dim, int n, double eps, int eyre, Shape* sh) {
@@ -110,7 +112,14 @@ bool orth_ok(int orth) { return orth == CH_ORTH_DCGS2 || orth == CH_ORTH_MGS; }
 int check_problem(const ch_problem* p, Shape* sh) {
     if (!p) return CH_EINVAL;
     if (p->prec != CH_FP64 && p->prec != CH_FP32_MIXED) return CH_EINVAL;
-    return check_grid(p->dim, p->n, p->eps, p->eyre, sh);
+    if (p->bc != CH_BC_PERIODIC && p->bc != CH_BC_NEUMANN) return CH_EINVAL;
+    if (p->bc == CH_BC_NEUMANN && p->dim != 2) return CH_EINVAL;   // the paper's 2-D setting only
+    if (!(p->length < INFINITY) || p->length != p->length) return CH_EINVAL;
+    const int rc = check_grid(p->dim, p->n, p->eps, p->eyre, sh);
+    if (rc) return rc;
+    sh->bc = p->bc;
+    sh->length = p->length > 0.0 ? p->length : 1.0;
+    return CH_OK;
 }
 
 // Workspace for `pts` pooled points, a basis of m_max + 1 columns in `prec`,
@@ -279,8 +288,10 @@ Inst make_inst(const Member& m, int i, int dim, int prec, int sblk0, int cblk0, 
     I.wblk = wide_blocks(dim, n, prec);
     I.vx = strip_vx(n, prec);
     I.eps2 = m.eps * m.eps;
-    I.inv_h2 = double(n) * double(n);
+    const double inv_h = double(n) / m.sh.length;   // h = L / n
+    I.inv_h2 = inv_h * inv_h;
     I.eyre = m.eyre;
+    I.bc = m.sh.bc;
     return I;
 }
 

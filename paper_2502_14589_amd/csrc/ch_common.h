@@ -258,9 +258,11 @@ __device__ __forceinline__ TileOrigin tile_origin(int t, int ntx, int nty) {
 }
 
 // Global index of point i of the halo-H region around the tile (periodic wrap
-// unless the whole region is inside the grid).
+// or Neumann mirror, bc_index, unless the whole region is inside the grid).
+// Tile regions reach at most TX + H past the grid (< n for n >= 5 whenever a
+// tile starts inside it), so one fold suffices except in the periodic wrap.
 template <int DIM, int H>
-__device__ __forceinline__ size_t region_index(const TileOrigin& o, int n, int i, bool interior) {
+__device__ __forceinline__ size_t region_index(const TileOrigin& o, int n, int i, bool interior, int bc) {
     using R = Region<DIM, H>;
     const int cx = i % R::X;
     const int rr = i / R::X;
@@ -268,9 +270,15 @@ __device__ __forceinline__ size_t region_index(const TileOrigin& o, int n, int i
     const int cz = rr / R::Y;
     int gx = o.x0 + cx - H, gy = o.y0 + cy - H, gz = DIM == 3 ? o.z0 + cz - H : 0;
     if (!interior) {
-        gx = wrapi(gx, n);
-        gy = wrapi(gy, n);
-        if (DIM == 3) gz = wrapi(gz, n);
+        if (bc == CH_BC_NEUMANN) {
+            gx = bc_index(min(gx, 2 * n - 1), n, bc);
+            gy = bc_index(min(gy, 2 * n - 1), n, bc);
+            if (DIM == 3) gz = bc_index(min(gz, 2 * n - 1), n, bc);
+        } else {
+            gx = wrapi(gx, n);
+            gy = wrapi(gy, n);
+            if (DIM == 3) gz = wrapi(gz, n);
+        }
     }
     return ((size_t)gz * n + gy) * n + gx;
 }
@@ -286,7 +294,7 @@ __device__ __forceinline__ bool region_inside(const TileOrigin& o, int n) {
 // index.  Every load of both regions is issued before the first value is
 // used, so a workgroup waits for memory once per tile.
 template <int DIM, int HA, int HB, typename TA, typename TB, typename PA, typename PB>
-__device__ __forceinline__ void load_regions(const TileOrigin& o, int n, const TA* __restrict__ a, PA&& putA,
+__device__ __forceinline__ void load_regions(const TileOrigin& o, int n, int bc, const TA* __restrict__ a, PA&& putA,
                                              const TB* __restrict__ b, PB&& putB) {
     using RA = Region<DIM, HA>;
     using RB = Region<DIM, HB>;
@@ -298,12 +306,12 @@ __device__ __forceinline__ void load_regions(const TileOrigin& o, int n, const T
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
         const int i = threadIdx.x + u * CH_BLOCK;
-        if (i < RA::SIZE) va[u] = a[region_index<DIM, HA>(o, n, i, ina)];
+        if (i < RA::SIZE) va[u] = a[region_index<DIM, HA>(o, n, i, ina, bc)];
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
         const int i = threadIdx.x + u * CH_BLOCK;
-        if (i < RB::SIZE) vb[u] = b[region_index<DIM, HB>(o, n, i, inb)];
+        if (i < RB::SIZE) vb[u] = b[region_index<DIM, HB>(o, n, i, inb, bc)];
     }
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
@@ -319,7 +327,7 @@ __device__ __forceinline__ void load_regions(const TileOrigin& o, int n, const T
 
 // One region of halo H, its loads issued together (see load_regions).
 template <int DIM, int H, typename TS, typename Put>
-__device__ __forceinline__ void load_region(const TileOrigin& o, int n, const TS* __restrict__ src, Put&& put) {
+__device__ __forceinline__ void load_region(const TileOrigin& o, int n, int bc, const TS* __restrict__ src, Put&& put) {
     using R = Region<DIM, H>;
     constexpr int NL = (R::SIZE + CH_BLOCK - 1) / CH_BLOCK;
     const bool in = region_inside<DIM, H>(o, n);
@@ -327,7 +335,7 @@ __device__ __forceinline__ void load_region(const TileOrigin& o, int n, const TS
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
         const int i = threadIdx.x + u * CH_BLOCK;
-        if (i < R::SIZE) v[u] = src[region_index<DIM, H>(o, n, i, in)];
+        if (i < R::SIZE) v[u] = src[region_index<DIM, H>(o, n, i, in, bc)];
     }
 #pragma unroll
     for (int u = 0; u < NL; ++u) {

@@ -87,7 +87,15 @@ struct Inst {
     int eyre;
     int wblk0, wblk;    // 2-D row-strip / 3-D marching workgroups [wblk0, wblk0 + wblk)
     int vx;             // 2-D strips: columns per lane (divides n)
+    int bc;             // ch_bc
 };
+
+// Grid index of a point g outside [0, n) (within n of it): periodic wrap,
+// or the mirror of the cell-centred Neumann grid (ghost -1 -> 0, n -> n - 1).
+__host__ __device__ inline int bc_index(int g, int n, int bc) {
+    if (bc == CH_BC_NEUMANN) return g < 0 ? -g - 1 : (g >= n ? 2 * n - 1 - g : g);
+    return g < 0 ? g + n : (g >= n ? g - n : g);
+}
 
 // 2-D row strips (ch_strip.hip): each wave of a strip workgroup owns a strip
 // of CH_STRIP_ROWS rows by strip_cols(vx) columns; lane L holds vx

@@ -1253,8 +1253,31 @@ __global__ __launch_bounds__(CH_BLOCK) void k_step_end(Ctl* __restrict__ ctls, c
 
 // ---------------------------------------------------------------------------
 // LIM step begin (Figs. 1 and 2: bounds of the spectrum): partials of
-// min/max y^2 (and a non-finite flag) ...
+// min/max y^2 (and a non-finite flag) on periodic grids; with Neumann
+// boundaries, of the largest absolute column sum of Ahat_n itself ...
 // ---------------------------------------------------------------------------
+// Absolute sum of column j = (ix, iy) of Ahat_n = A (J_n + eps^2 A) [+ A with
+// the Eyre splitting] on the 2-D cell-centred Neumann grid, d = the diagonal
+// of J_n at j, a = 1/h^2, e = eps^2/h^4.  A_jj = deg_j a and A_ij = -a for the
+// existing neighbours i (deg: their number), so column j of Ahat_n = A D +
+// eps^2 A^2 holds d deg_j a + e (deg_j^2 + deg_j) on the diagonal,
+// -d a - e (deg_i + deg_j) at each neighbour, e at each point two steps away
+// along an axis and 2 e at each diagonal point, where those exist.  On a
+// periodic grid (deg = 4 everywhere) this is the closed form of k_lim_plan.
+__device__ __forceinline__ double neumann_colsum(int ix, int iy, int n, double d, double a, double e) {
+    auto deg = [n](int x, int y) { return (x > 0) + (x < n - 1) + (y > 0) + (y < n - 1); };
+    const int dj = deg(ix, iy);
+    double s = fabs(d * dj * a + e * double(dj * dj + dj));
+    if (ix > 0) s += fabs(-d * a - e * double(deg(ix - 1, iy) + dj));
+    if (ix < n - 1) s += fabs(-d * a - e * double(deg(ix + 1, iy) + dj));
+    if (iy > 0) s += fabs(-d * a - e * double(deg(ix, iy - 1) + dj));
+    if (iy < n - 1) s += fabs(-d * a - e * double(deg(ix, iy + 1) + dj));
+    s += e * double((ix > 1) + (ix < n - 2) + (iy > 1) + (iy < n - 2));
+    s += 2.0 * e * double((ix > 0 && iy > 0) + (ix > 0 && iy < n - 1) + (ix < n - 1 && iy > 0) +
+                          (ix < n - 1 && iy < n - 1));
+    return s;
+}
+
 template <bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ cb2i, const Inst inst0, int ninst, const double* __restrict__ ybase,
@@ -1265,11 +1288,18 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctls, 
     const double* y = ybase + I.off;
     double mn = __builtin_inf(), mx = -__builtin_inf(), bad = 0.0;
     const long long stride = (long long)I.cblk * CH_BLOCK;
+    const bool neu = I.bc == CH_BC_NEUMANN;
+    const double a = I.inv_h2, e = I.eps2 * I.inv_h2 * I.inv_h2;
     for (long long q = (long long)(blockIdx.x - I.cblk0) * CH_BLOCK + threadIdx.x; q < I.N; q += stride) {
         const double v = y[q] * y[q];
         if (v < __builtin_inf()) {
-            mn = fmin(mn, v);
-            mx = fmax(mx, v);
+            if (neu) {   // the column sum itself (2-D: q = iy n + ix)
+                const int iy = (int)(q / I.n), ix = (int)(q - (long long)iy * I.n);
+                mx = fmax(mx, neumann_colsum(ix, iy, I.n, 3.0 * v - 1.0 + I.eyre, a, e));
+            } else {
+                mn = fmin(mn, v);
+                mx = fmax(mx, v);
+            }
         } else {
             bad = 1.0;
         }
@@ -1401,7 +1431,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, c
             const double e = I.eps2 * inv_h2 * inv_h2;
             const double dmin = 3.0 * ymin2 - 1.0 + I.eyre, dmax = 3.0 * ymax2 - 1.0 + I.eyre;
             double gmin, gmax;
-            if (dim == 2) {
+            if (I.bc == CH_BC_NEUMANN) {   // the largest column sum, from the begin launch
+                gmin = gmax = tot[1];
+            } else if (dim == 2) {
                 gmin = fabs(4.0 * dmin * inv_h2 + 20.0 * e) + 4.0 * fabs(dmin * inv_h2 + 8.0 * e) + 12.0 * e;
                 gmax = fabs(4.0 * dmax * inv_h2 + 20.0 * e) + 4.0 * fabs(dmax * inv_h2 + 8.0 * e) + 12.0 * e;
             } else {

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
     double dot = 0.0;
     for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
         const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_regions<DIM, 2, 1>(o, n, Vk, [&](int i, TV v) { sv[i] = sc * v; },
+        load_regions<DIM, 2, 1>(o, n, I.bc, Vk, [&](int i, TV v) { sv[i] = sc * v; },
                                 y, [&](int i, TY v) { sd[i] = dcoef(TV(v), eyre); });
         __syncthreads();
         for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK)
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctls, cons
     double acc_r = 0.0, acc_g = 0.0;
     for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
         const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_regions<DIM, 2, 1>(o, n, z, [&](int i, double v) { sz[i] = v; }, y, [&](int i, double v) {
+        load_regions<DIM, 2, 1>(o, n, I.bc, z, [&](int i, double v) { sz[i] = v; }, y, [&](int i, double v) {
             sdq[i] = dcoef(v, eyre);
             sc[i] = ccoef(v, eyre);
         });
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_ee(Ctl* __restrict__ ctls, con
     double a_err = 0.0, a_pc = 0.0, a_f = 0.0, a_g = 0.0;
     for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
         const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_region<DIM, 2>(o, n, y1, [&](int i, double v) { s1[i] = v; });
+        load_region<DIM, 2>(o, n, I.bc, y1, [&](int i, double v) { s1[i] = v; });
         __syncthreads();
         for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK) {
             const double v = s1[r1_to_r2<DIM>(i)];
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, 
     const int lb = blockIdx.x - I.sblk0;
     for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
         const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_regions<DIM, 2, 1>(o, n, z, [&](int i, double v) { sz[i] = v; }, y, [&](int i, double v) {
+        load_regions<DIM, 2, 1>(o, n, I.bc, z, [&](int i, double v) { sz[i] = v; }, y, [&](int i, double v) {
             sdq[i] = dcoef(v, eyre);
             sc[i] = ccoef(v, eyre);
         });
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctls, co
     double a_err = 0.0, a_pc = 0.0;
     for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
         const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_regions<DIM, 2, 2>(o, n, y0, [&](int i, double v) { s0[i] = v; }, y1, [&](int i, double v) { s1[i] = v; });
+        load_regions<DIM, 2, 2>(o, n, I.bc, y0, [&](int i, double v) { s0[i] = v; }, y1, [&](int i, double v) { s1[i] = v; });
         __syncthreads();
         for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK) {
             const int c = r1_to_r2<DIM>(i);

@@ -140,34 +140,59 @@ struct StripPos {
     int xl;         // lane's first column, in [0, n)
     bool out;       // the lane's columns are outputs of this strip
     bool need;      // ... or the halo of one
+    bool rev;       // the lane's values are those of its columns in reverse (Neumann mirror)
 };
+
+// Grid column of the first of the VX columns [c, c + VX) of a lane (c a
+// multiple of VX, VX dividing n, -n < c < 2n): periodic wrap, or, past a
+// Neumann boundary, the mirror chunk [-c - VX, -c) or [2n - c - VX, 2n - c),
+// whose values the lane then takes in reverse order (rev).
+template <int VX>
+__device__ __forceinline__ int chunk_col(int c, int n, int bc, bool& rev) {
+    rev = false;
+    if (bc == CH_BC_NEUMANN && (c < 0 || c >= n)) {
+        rev = VX > 1;
+        const int x = c < 0 ? -c - VX : 2 * n - c - VX;
+        return x < 0 ? 0 : x;   // lanes past the halo (never read) stay in bounds
+    }
+    const int x = c % n;
+    return x < 0 ? x + n : x;
+}
+
+// Reverse the VX values of a lane when `rev`, without a branch.
+template <typename T, int VX>
+__device__ __forceinline__ void flip_if(bool rev, T (&v)[VX]) {
+    if constexpr (VX > 1) {
+        T t[VX];
+#pragma unroll
+        for (int e = 0; e < VX; ++e) t[e] = v[VX - 1 - e];
+#pragma unroll
+        for (int e = 0; e < VX; ++e) v[e] = rev ? t[e] : v[e];
+    }
+}
 
 // A lane offset past every row: the load returns zeros without a memory
 // access (lanes that neither own nor border an output column).
 constexpr unsigned OFF_ROW = 0x80000000u;
 
 template <int VX>
-__device__ __forceinline__ StripPos<VX> strip_pos(int s, int nsx, int n, int lane) {
+__device__ __forceinline__ StripPos<VX> strip_pos(int s, int nsx, int n, int lane, int bc) {
     constexpr int HL = CH_STRIP_HALO(VX), OW = strip_cols(VX);
     StripPos<VX> p;
     const int sx = s % nsx;
     p.r0 = (s / nsx) * SR;
-    const int c = sx * OW + (lane - HL) * VX;     // first column, before the periodic wrap
-    int xl = c % n;
-    if (xl < 0) xl += n;
-    p.xl = xl;
+    const int c = sx * OW + (lane - HL) * VX;     // first column, before the boundary fold
+    p.xl = chunk_col<VX>(c, n, bc, p.rev);
     p.out = lane >= HL && lane < 64 - HL && c < n;
     p.need = c < n + HL * VX;
     return p;
 }
 
-// Periodic row index for r in [-n, 2n).
-__device__ __forceinline__ int wrap_row(int r, int n) { return r < 0 ? r + n : (r >= n ? r - n : r); }
-
-// Row r (periodic) of an instance's field of n x n values of type T.
+// Row r (r in [-n, 2n): periodic wrap or Neumann mirror) of an instance's
+// field of n x n values of type T.
 template <typename T>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t grid_row(const T* f, int r, int n) {
-    return row_rsrc(f + (size_t)wrap_row(r, n) * n, (unsigned)n * (unsigned)sizeof(T));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t grid_row(const T* f, int r, int n, int bc) {
+    return row_rsrc(f + (size_t)bc_index(r, n, bc) * n, (unsigned)n * (unsigned)sizeof(T));
 }
 
 // ---------------------------------------------------------------------------
@@ -191,12 +216,13 @@ struct MatvecArgs {
 
 // The strips of this wave; dot-product totals go to red[.][wv] (DM_DC) or
 // are returned per lane (DM_ONE).
-template <typename TV, int DM, int VX>
+template <typename TV, int DM, int VX, bool NEU>
 __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<TV, DM>& A, TV sc, int wv,
                                                 double (*red)[CH_STRIP_WAVES]) {
     constexpr int NU = SR + 4, ND = SR + 2, W = CH_STRIP_WAVES;
     const int lane = threadIdx.x & 63;
     const int n = I.n, k = A.k;
+    constexpr int bc = NEU ? CH_BC_NEUMANN : CH_BC_PERIODIC;
     const TV* U = A.V + (size_t)k * A.ldv + I.off;
     TV* Wc = A.V + (size_t)(k + 1) * A.ldv + I.off;
     const TV* Y = A.y + I.off;
@@ -208,15 +234,19 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
     const int hv = wave_sum8_holder(lane);
     double one = 0.0;
     for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
-        const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane);
+        const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane, bc);
         const unsigned bo = (unsigned)P.xl * (unsigned)sizeof(TV);
         const unsigned bs = P.need ? bo : OFF_ROW;   // stencil operands
         const unsigned bd = P.out ? bo : OFF_ROW;    // basis columns of the dot products
         TV u[NU][VX], d[ND][VX];
 #pragma unroll
-        for (int j = 0; j < NU; ++j) load_row<TV, VX>(grid_row(U, P.r0 - 2 + j, n), bs, u[j]);
+        for (int j = 0; j < NU; ++j) load_row<TV, VX>(grid_row(U, P.r0 - 2 + j, n, bc), bs, u[j]);
 #pragma unroll
-        for (int j = 0; j < ND; ++j) load_row<TV, VX>(grid_row(Y, P.r0 - 1 + j, n), bs, d[j]);
+        for (int j = 0; j < ND; ++j) load_row<TV, VX>(grid_row(Y, P.r0 - 1 + j, n, bc), bs, d[j]);
+#pragma unroll
+        for (int j = 0; j < NU; ++j) flip_if<TV, VX>(P.rev, u[j]);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) flip_if<TV, VX>(P.rev, d[j]);
 #pragma unroll
         for (int j = 0; j < NU; ++j)
 #pragma unroll
@@ -248,7 +278,7 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
         // stores outside the grid or of no use go past the row (dropped)
 #pragma unroll
         for (int i = 0; i < SR; ++i)
-            store_row<TV, VX>(grid_row(Wc, P.r0 + i, n), A.store_w && P.out && rowin[i] ? bo : OFF_ROW, w[i]);
+            store_row<TV, VX>(grid_row(Wc, P.r0 + i, n, bc), A.store_w && P.out && rowin[i] ? bo : OFF_ROW, w[i]);
         // the strip's points (zero outside the grid), in FP64
         double ud[SR][VX], wd[SR][VX];
 #pragma unroll
@@ -264,7 +294,7 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
 #pragma unroll
             for (int i = 0; i < SR; ++i) {
                 TV v0[VX];
-                load_row<TV, VX>(grid_row(V0, P.r0 + i, n), bd, v0);
+                load_row<TV, VX>(grid_row(V0, P.r0 + i, n, bc), bd, v0);
 #pragma unroll
                 for (int e = 0; e < VX; ++e) one += wd[i][e] * double(v0[e]);
             }
@@ -283,7 +313,7 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
                     const TV* Q = A.V + (size_t)(c < k ? c : 0) * A.ldv + I.off;
                     const unsigned o = c < k ? bd : OFF_ROW;
 #pragma unroll
-                    for (int i = 0; i < SR; ++i) load_row<TV, VX>(grid_row(Q, P.r0 + i, n), o, bl[r][i]);
+                    for (int i = 0; i < SR; ++i) load_row<TV, VX>(grid_row(Q, P.r0 + i, n, bc), o, bl[r][i]);
                 }
             };
             auto sums = [&](const TV (&bl)[RB][SR][VX], double* a) {
@@ -331,7 +361,8 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
 
 // VX: the strip width of a single-instance launch; 0: per instance (batches).
 // TAG distinguishes the launches of the timing aid (same code, another symbol).
-template <typename TV, bool SINGLE, int DM, int TAG, int VX>
+// NEU: the single grid has Neumann boundaries (batches are periodic).
+template <typename TV, bool SINGLE, int DM, int TAG, int VX, bool NEU = false>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_matvec_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        TV* __restrict__ V, size_t ldv, int k, int store_w,
@@ -350,14 +381,14 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_matvec_s(Ctl* __restrict__ c
     const MatvecArgs<TV, DM> A{V, ldv, k, store_w, ybase};
     double one;
     if constexpr (VX > 0) {
-        one = matvec_strips<TV, DM, VX>(I, A, sc, wv, red);
+        one = matvec_strips<TV, DM, VX, NEU>(I, A, sc, wv, red);
     } else {
         if (I.vx == 1) {
-            one = matvec_strips<TV, DM, 1>(I, A, sc, wv, red);
+            one = matvec_strips<TV, DM, 1, false>(I, A, sc, wv, red);
         } else if (sizeof(TV) == 8 || I.vx == 2) {
-            one = matvec_strips<TV, DM, 2>(I, A, sc, wv, red);
+            one = matvec_strips<TV, DM, 2, false>(I, A, sc, wv, red);
         } else {
-            one = matvec_strips<TV, DM, (sizeof(TV) == 4 ? 4 : 2)>(I, A, sc, wv, red);
+            one = matvec_strips<TV, DM, (sizeof(TV) == 4 ? 4 : 2), false>(I, A, sc, wv, red);
         }
     }
     if (DM == DM_DC) {
@@ -380,13 +411,14 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_matvec_s(Ctl* __restrict__ c
 // The coefficients (tau a_m, 1 / (1 + tau a_m)) of stage position `pos` come
 // from the plan launch.
 // ---------------------------------------------------------------------------
-template <int VX>
+template <int VX, bool NEU>
 __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restrict__ ybase,
                                            const double* __restrict__ zbase, double* __restrict__ obase, double ta,
                                            double inv, double tau, int wv) {
     constexpr int NU = SR + 4, ND = SR + 2, W = CH_STRIP_WAVES;
     const int lane = threadIdx.x & 63;
     const int n = I.n;
+    constexpr int bc = NEU ? CH_BC_NEUMANN : CH_BC_PERIODIC;
     const double* Z = zbase + I.off;
     const double* Y = ybase + I.off;
     double* O = obase + I.off;
@@ -396,14 +428,18 @@ __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restri
     const int ns = nsx * ((n + SR - 1) / SR);
     const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
     for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
-        const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane);
+        const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane, bc);
         const unsigned bo = (unsigned)P.xl * 8u;
         const unsigned bs = P.need ? bo : OFF_ROW;
         double z[NU][VX], y[ND][VX];
 #pragma unroll
-        for (int j = 0; j < NU; ++j) load_row<double, VX>(grid_row(Z, P.r0 - 2 + j, n), bs, z[j]);
+        for (int j = 0; j < NU; ++j) load_row<double, VX>(grid_row(Z, P.r0 - 2 + j, n, bc), bs, z[j]);
 #pragma unroll
-        for (int j = 0; j < ND; ++j) load_row<double, VX>(grid_row(Y, P.r0 - 1 + j, n), bs, y[j]);
+        for (int j = 0; j < ND; ++j) load_row<double, VX>(grid_row(Y, P.r0 - 1 + j, n, bc), bs, y[j]);
+#pragma unroll
+        for (int j = 0; j < NU; ++j) flip_if<double, VX>(P.rev, z[j]);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) flip_if<double, VX>(P.rev, y[j]);
         // inner expression d z + eps^2 A z - c on rows r0 - 1 .. r0 + SR
         double q[ND][VX];
 #pragma unroll
@@ -423,14 +459,14 @@ __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restri
                 const double r = -inv_h2 * lap5<double, VX>(q[i], q[i + 1], q[i + 2], xl, xr, e);
                 o[e] = (y[i + 1][e] + ta * z[i + 2][e] + tau * r) * inv;
             }
-            if (P.out && P.r0 + i < n) store_row<double, VX>(grid_row(O, P.r0 + i, n), bo, o);
+            if (P.out && P.r0 + i < n) store_row<double, VX>(grid_row(O, P.r0 + i, n, bc), bo, o);
         }
     }
 }
 
 // Stage launch l (lim_launch) of each instance: its source and destination
 // follow from its own Chebyshev order.
-template <bool SINGLE, int TAG, int VX>
+template <bool SINGLE, int TAG, int VX, bool NEU = false>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                           const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                           const double* __restrict__ ybase, double* youtbase,
@@ -448,10 +484,10 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage_s(Ctl* __restrict_
     const double ta = cf[0], inv = cf[1], tau = ctl->tau0;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if constexpr (VX > 0) {
-        lim_strips<VX>(I, ybase, zbase, obase, ta, inv, tau, wv);
+        lim_strips<VX, NEU>(I, ybase, zbase, obase, ta, inv, tau, wv);
     } else {
-        if (I.vx == 1) lim_strips<1>(I, ybase, zbase, obase, ta, inv, tau, wv);
-        else lim_strips<2>(I, ybase, zbase, obase, ta, inv, tau, wv);
+        if (I.vx == 1) lim_strips<1, false>(I, ybase, zbase, obase, ta, inv, tau, wv);
+        else lim_strips<2, false>(I, ybase, zbase, obase, ta, inv, tau, wv);
     }
 }
 
@@ -481,7 +517,7 @@ __device__ __forceinline__ int wrap_row_any(int r, int n) {
     return r < 0 ? r + n : r;
 }
 
-template <int VX>
+template <int VX, bool NEU>
 __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restrict__ ybase,
                                             const double* __restrict__ zbase, double* __restrict__ obase,
                                             double ta1, double inv1, double ta2, double inv2, double tau, int wv) {
@@ -498,11 +534,14 @@ __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restr
     const int nsx = (n + OW - 1) / OW;
     const int ns = nsx * ((n + R - 1) / R);
     const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
+    constexpr int bc = NEU ? CH_BC_NEUMANN : CH_BC_PERIODIC;
+    // rows r0 - 4 .. r0 + R + 3: periodic, or mirrored (within n of the grid for n >= 5)
+    auto row = [&](int r) { return bc == CH_BC_NEUMANN ? bc_index(r, n, bc) : wrap_row_any(r, n); };
     for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
         const int sx = s % nsx, r0 = (s / nsx) * R;
         const int c = sx * OW + (lane - HL) * VX;
-        int xl = c % n;
-        if (xl < 0) xl += n;
+        bool rev;
+        const int xl = chunk_col<VX>(c, n, bc, rev);
         const bool out = lane >= HL && lane < 64 - HL && c < n;
         const unsigned bo = (unsigned)xl * 8u;
         const unsigned bs = c < n + HL * VX ? bo : OFF_ROW;
@@ -510,10 +549,14 @@ __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restr
         double z[NZ][VX], y[NY][VX];
 #pragma unroll
         for (int j = 0; j < NZ; ++j)
-            load_row<double, VX>(row_rsrc(Z + (size_t)wrap_row_any(r0 - 4 + j, n) * n, rb), bs, z[j]);
+            load_row<double, VX>(row_rsrc(Z + (size_t)row(r0 - 4 + j) * n, rb), bs, z[j]);
 #pragma unroll
         for (int j = 0; j < NY; ++j)
-            load_row<double, VX>(row_rsrc(Y + (size_t)wrap_row_any(r0 - 3 + j, n) * n, rb), bs, y[j]);
+            load_row<double, VX>(row_rsrc(Y + (size_t)row(r0 - 3 + j) * n, rb), bs, y[j]);
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) flip_if<double, VX>(rev, z[j]);
+#pragma unroll
+        for (int j = 0; j < NY; ++j) flip_if<double, VX>(rev, y[j]);
         // first stage: q1 on rows r0 - 3 + j, its result o1 on rows r0 - 2 + j
         double q1[NQ1][VX];
 #pragma unroll
@@ -558,7 +601,7 @@ __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restr
     }
 }
 
-template <bool SINGLE, int TAG, int VX>
+template <bool SINGLE, int TAG, int VX, bool NEU = false>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage2_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                            const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                            const double* __restrict__ ybase, double* youtbase,
@@ -575,10 +618,10 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage2_s(Ctl* __restrict
     const double ta1 = cf[0], inv1 = cf[1], ta2 = cf[2], inv2 = cf[3], tau = ctl->tau0;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if constexpr (VX > 0) {
-        lim2_strips<VX>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
+        lim2_strips<VX, NEU>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
     } else {
-        if (I.vx == 1) lim2_strips<1>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
-        else lim2_strips<2>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
+        if (I.vx == 1) lim2_strips<1, false>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
+        else lim2_strips<2, false>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
     }
 }
 
@@ -589,7 +632,7 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage2_s(Ctl* __restrict
 // f1 becomes the next step's f(y^n) and start vector; ||A c(y^{n+1})|| the next
 // ||ghat||.  Lane partials of the four sums are returned in acc.
 // ---------------------------------------------------------------------------
-template <typename TV, int VX>
+template <typename TV, int VX, bool NEU>
 __device__ __forceinline__ void est_strips(const Inst& I, const double* __restrict__ y0base,
                                            const double* __restrict__ y1base, double* __restrict__ fbase,
                                            TV* __restrict__ V0base, float* __restrict__ y32base, double half_tau,
@@ -597,6 +640,7 @@ __device__ __forceinline__ void est_strips(const Inst& I, const double* __restri
     constexpr int NU = SR + 4, ND = SR + 2, W = CH_STRIP_WAVES;
     const int lane = threadIdx.x & 63;
     const int n = I.n;
+    constexpr int bc = NEU ? CH_BC_NEUMANN : CH_BC_PERIODIC;
     const double* Y0 = y0base + I.off;
     const double* Y1 = y1base + I.off;
     double* F = fbase + I.off;
@@ -608,17 +652,19 @@ __device__ __forceinline__ void est_strips(const Inst& I, const double* __restri
     const int ns = nsx * ((n + SR - 1) / SR);
     const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
     for (int s = lb * W + wv; s < ns; s += I.wblk * W) {
-        const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane);
+        const StripPos<VX> P = strip_pos<VX>(s, nsx, n, lane, bc);
         const unsigned bo = (unsigned)P.xl * 8u;
         const unsigned bs = P.need ? bo : OFF_ROW, bd = P.out ? bo : OFF_ROW;
         double y1[NU][VX], y0[SR][VX], f0[SR][VX];
 #pragma unroll
-        for (int j = 0; j < NU; ++j) load_row<double, VX>(grid_row(Y1, P.r0 - 2 + j, n), bs, y1[j]);
+        for (int j = 0; j < NU; ++j) load_row<double, VX>(grid_row(Y1, P.r0 - 2 + j, n, bc), bs, y1[j]);
 #pragma unroll
         for (int i = 0; i < SR; ++i) {
-            load_row<double, VX>(grid_row(Y0, P.r0 + i, n), bd, y0[i]);
-            load_row<double, VX>(grid_row(F, P.r0 + i, n), bd, f0[i]);
+            load_row<double, VX>(grid_row(Y0, P.r0 + i, n, bc), bd, y0[i]);
+            load_row<double, VX>(grid_row(F, P.r0 + i, n, bc), bd, f0[i]);
         }
+#pragma unroll
+        for (int j = 0; j < NU; ++j) flip_if<double, VX>(P.rev, y1[j]);
         // inner expressions on rows r0 - 1 .. r0 + SR: F'(y) + eps^2 A y and c(y)
         double q[ND][VX], c[ND][VX];
 #pragma unroll
@@ -656,15 +702,15 @@ __device__ __forceinline__ void est_strips(const Inst& I, const double* __restri
                 yf[e] = float(yv);
             }
             if (in) {
-                store_row<double, VX>(grid_row(F, P.r0 + i, n), bo, f1);
-                store_row<TV, VX>(grid_row(V0, P.r0 + i, n), (unsigned)P.xl * (unsigned)sizeof(TV), fv);
-                if (Y32) store_row<float, VX>(grid_row(Y32, P.r0 + i, n), (unsigned)P.xl * 4u, yf);
+                store_row<double, VX>(grid_row(F, P.r0 + i, n, bc), bo, f1);
+                store_row<TV, VX>(grid_row(V0, P.r0 + i, n, bc), (unsigned)P.xl * (unsigned)sizeof(TV), fv);
+                if (Y32) store_row<float, VX>(grid_row(Y32, P.r0 + i, n, bc), (unsigned)P.xl * 4u, yf);
             }
         }
     }
 }
 
-template <typename TV, bool SINGLE, int VX>
+template <typename TV, bool SINGLE, int VX, bool NEU = false>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_est_ee_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        const double* __restrict__ y0base,
@@ -678,11 +724,11 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_est_ee_s(Ctl* __restrict__ c
     const double half_tau = 0.5 * (ctl->mode == MODE_EE ? ctl->tau_acc : ctl->tau_step);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (VX > 0) {
-        est_strips<TV, VX>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+        est_strips<TV, VX, NEU>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
     } else {
-        if (I.vx == 1) est_strips<TV, 1>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
-        else if (sizeof(TV) == 8 || I.vx == 2) est_strips<TV, 2>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
-        else est_strips<TV, (sizeof(TV) == 4 ? 4 : 2)>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+        if (I.vx == 1) est_strips<TV, 1, false>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+        else if (sizeof(TV) == 8 || I.vx == 2) est_strips<TV, 2, false>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+        else est_strips<TV, (sizeof(TV) == 4 ? 4 : 2), false>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
     }
     write_partials<4, RED_SUM>(acc, pout);
 }
@@ -694,11 +740,18 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_est_ee_s(Ctl* __restrict__ c
 // ---------------------------------------------------------------------------
 #define WARGS dim3(t.wgrid), dim3(CH_STRIP_BLOCK), 0, s, b.ctl, t.inst, t.wb2i, t.hinst[0], t.ninst
 
+// A single grid with Neumann boundaries (batches are periodic).
+static bool neumann(const Table& t) { return t.ninst == 1 && t.hinst[0].bc == CH_BC_NEUMANN; }
+
 template <typename TV, int DM, bool TIMING, int VX>
 static void launch_matvec_one(const Table& t, const DevBuffers& b, const TV* y, int k, int store_w, double* pout,
                               hipStream_t s) {
-    hipLaunchKernelGGL((k_matvec_s<TV, true, DM, TIMING ? 1 : 0, VX>), WARGS, static_cast<TV*>(b.V), b.ldv, k,
-                       store_w, y, pout);
+    if (neumann(t))
+        hipLaunchKernelGGL((k_matvec_s<TV, true, DM, TIMING ? 1 : 0, VX, true>), WARGS, static_cast<TV*>(b.V), b.ldv,
+                           k, store_w, y, pout);
+    else
+        hipLaunchKernelGGL((k_matvec_s<TV, true, DM, TIMING ? 1 : 0, VX>), WARGS, static_cast<TV*>(b.V), b.ldv, k,
+                           store_w, y, pout);
 }
 
 template <typename TV, int DM, bool TIMING>
@@ -741,7 +794,10 @@ hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const dou
                                   bool pairs, bool timing, hipStream_t s) {
     const bool two = t.hinst[0].vx >= 2;
     const int pr = pairs ? 1 : 0;
-    if (timing) {
+    if (neumann(t)) {
+        if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 0, 2, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
+        else hipLaunchKernelGGL((k_lim_stage_s<true, 0, 1, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
+    } else if (timing) {
         if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 1, 2>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
         else hipLaunchKernelGGL((k_lim_stage_s<true, 1, 1>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
     } else if (t.ninst == 1) {
@@ -756,7 +812,10 @@ hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const dou
 hipError_t launch_lim_stage2_strip(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
                                    bool timing, hipStream_t s) {
     const bool two = t.hinst[0].vx >= 2;
-    if (timing) {
+    if (neumann(t)) {
+        if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 2, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
+        else hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 1, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
+    } else if (timing) {
         if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 1, 2>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
         else hipLaunchKernelGGL((k_lim_stage2_s<true, 1, 1>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
     } else if (t.ninst == 1) {
@@ -777,6 +836,14 @@ static void launch_est_ee_s(const Table& t, const DevBuffers& b, const double* y
         return;
     }
     const int vx = t.hinst[0].vx;
+    if (neumann(t)) {
+        if (sizeof(TV) == 4 && vx >= 4)
+            hipLaunchKernelGGL((k_est_ee_s<TV, true, (sizeof(TV) == 4 ? 4 : 2), true>), WARGS, y0, y1, b.fcur, V0, y32,
+                               pout);
+        else if (vx >= 2) hipLaunchKernelGGL((k_est_ee_s<TV, true, 2, true>), WARGS, y0, y1, b.fcur, V0, y32, pout);
+        else hipLaunchKernelGGL((k_est_ee_s<TV, true, 1, true>), WARGS, y0, y1, b.fcur, V0, y32, pout);
+        return;
+    }
     if constexpr (sizeof(TV) == 4) {
         if (vx >= 4) {
             hipLaunchKernelGGL((k_est_ee_s<TV, true, 4>), WARGS, y0, y1, b.fcur, V0, y32, pout);

@@ -35,6 +35,11 @@ def cube_3d_field(seed: int = 2, n: int = 256) -> np.ndarray:
     return uniform_field(n, 3, 0.0, 0.05, seed)
 
 
+def paper_field(n: int, seed: int) -> np.ndarray:
+    """The paper's initial data (Section 5.1): iid U(-0.01, 0.01) on an n^2 grid."""
+    return uniform_field(n, 2, 0.0, 0.01, seed)
+
+
 @dataclass
 class Instance:
     n: int

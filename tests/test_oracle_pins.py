@@ -583,6 +583,130 @@ def test_paper_lim_matvec_counts():
         assert (2 * p - 1) * steps == int(count), (grid, eyre, tau, p)
 
 
+def test_paper_lim_matvec_counts_on_the_neumann_operator():
+    """The same rows on the paper's own operator: homogeneous Neumann conditions
+    on the cell-centred n x n grid of (0,64)^2 (Section 5.1), in the paper's
+    units (h = 64/n, eps = eps_4, tau as printed).  lambda_max = ||Ahat||_1 comes
+    from the assembled matrix, boundary columns included, for constant states
+    and for the paper's initial data y0 ~ U(-0.01, 0.01)."""
+    eps = _paper_eps4()
+    rows = _read_golden("paper_lim_counts.txt")
+    for grid, eyre, tau, count in rows:
+        n = int(grid)
+        prob = O.Problem(2, n, eps, eyre == "1", bc="neumann", length=64.0)
+        ps = set()
+        for y in (np.full(prob.N, 0.0), np.full(prob.N, 0.5), np.full(prob.N, 1.0),
+                  uniform_field(n, 2, 0.0, 0.01, seed=1000 + n)):
+            ps.add(O.lim_order(float(tau), O.lambda_max(y, prob)))
+        assert len(ps) == 1, (grid, tau, ps)
+        steps = round(1000.0 / float(tau))
+        assert (2 * ps.pop() - 1) * steps == int(count), (grid, eyre, tau)
+
+
+# --- P17: the Neumann grid of the paper's test problem (Section 5.1) ------------------------------
+
+def neumann_mode(n, k):
+    """cos(pi k_x (i + 1/2) / n) cos(pi k_y (j + 1/2) / n) on the cell-centred grid (x fastest)."""
+    c = [np.cos(np.pi * kk * (np.arange(n) + 0.5) / n) for kk in k]
+    return np.outer(c[1], c[0]).ravel()
+
+
+@pytest.mark.parametrize("n,k,length", [(12, (1, 0), 1.0), (16, (3, 5), 64.0), (9, (8, 2), 2.5), (7, (0, 0), 1.0)])
+def test_neumann_lap_dct_eigenpairs(n, k, length):
+    """Textbook: the cell-centred Neumann second difference has the DCT-II
+    vectors as eigenvectors, eigenvalues (4/h^2) sin^2(pi k / (2n)) per axis."""
+    prob = O.Problem(2, n, 0.05, bc="neumann", length=length)
+    v = neumann_mode(n, k)
+    lam = sum(4.0 / prob.h ** 2 * math.sin(math.pi * kk / (2 * n)) ** 2 for kk in k)
+    np.testing.assert_allclose(O.lap(v, prob), lam * v, rtol=0, atol=1e-12 * max(lam, 1.0 / prob.h ** 2))
+
+
+def test_neumann_assembly_symmetric_psd_and_matches_lap():
+    prob = O.Problem(2, 9, 0.05, bc="neumann", length=3.0)
+    A = O.assemble_A(prob)
+    y = np.random.default_rng(3).standard_normal(prob.N)
+    np.testing.assert_allclose(O.lap(y, prob), A @ y, rtol=0, atol=1e-11 * np.abs(A @ y).max())
+    assert abs(A - A.T).max() == 0
+    np.testing.assert_allclose(A @ np.ones(prob.N), 0.0, atol=1e-12)
+    ev = np.linalg.eigvalsh(A.toarray())
+    assert ev.min() > -1e-9 * ev.max()
+    # boundary rows: (number of neighbours) / h^2 on the diagonal
+    d = A.diagonal() * prob.h ** 2
+    assert d[0] == 2 and d[1] == 3 and d[prob.n + 1] == 4
+
+
+def neumann_colsums_by_degree(y, prob):
+    """Column sums of |Ahat| counted from the degree of each cell (test-side
+    derivation): diagonal |d deg a + e (deg^2 + deg)|, neighbours
+    |d a + e (deg_i + deg_j)|, e per axis-2 point and 2 e per diagonal point."""
+    n, a, e = prob.n, 1.0 / prob.h ** 2, prob.eps ** 2 / prob.h ** 4
+    d = 3.0 * y * y - 1.0 + (1.0 if prob.eyre else 0.0)
+    deg = lambda x, z: (x > 0) + (x < n - 1) + (z > 0) + (z < n - 1)
+    out = np.zeros(prob.N)
+    for iz in range(n):
+        for ix in range(n):
+            j = iz * n + ix
+            dj = deg(ix, iz)
+            s = abs(d[j] * dj * a + e * (dj * dj + dj))
+            for x, z in ((ix - 1, iz), (ix + 1, iz), (ix, iz - 1), (ix, iz + 1)):
+                if 0 <= x < n and 0 <= z < n:
+                    s += abs(d[j] * a + e * (deg(x, z) + dj))
+            s += e * sum(0 <= x < n and 0 <= z < n for x, z in ((ix - 2, iz), (ix + 2, iz), (ix, iz - 2), (ix, iz + 2)))
+            s += 2 * e * sum(0 <= x < n and 0 <= z < n for x, z in ((ix - 1, iz - 1), (ix + 1, iz - 1),
+                                                                    (ix - 1, iz + 1), (ix + 1, iz + 1)))
+            out[j] = s
+    return out
+
+
+@pytest.mark.parametrize("eyre", [False, True])
+def test_neumann_lambda_max_by_cell_degree(eyre):
+    prob = O.Problem(2, 7, 0.9606, eyre, bc="neumann", length=64.0 * 7 / 64)
+    y = uniform_field(7, 2, 0.2, 0.6, seed=71)
+    want = neumann_colsums_by_degree(y, prob).max()
+    assert O.lambda_max(y, prob) == pytest.approx(want, rel=1e-13)
+    # states whose largest column sum is at the boundary: a large value in a
+    # corner cell, then in an edge cell
+    for j in (0, 3):
+        yb = np.zeros(prob.N)
+        yb[j] = 3.0
+        cb = neumann_colsums_by_degree(yb, prob)
+        assert int(np.argmax(cb)) == j
+        assert O.lambda_max(yb, prob) == pytest.approx(cb.max(), rel=1e-13)
+    # the boundary is not a no-op: for a constant state the corner columns sum
+    # to less than the interior ones, which keep the periodic closed form
+    c = neumann_colsums_by_degree(np.full(prob.N, 0.2), prob)
+    assert c[0] < c[3 * 7 + 3]
+    per = O.Problem(2, 7, 0.9606, eyre, length=prob.length)
+    assert c[3 * 7 + 3] == pytest.approx(O.lambda_max(np.full(prob.N, 0.2), per), rel=1e-13)
+
+
+def test_neumann_mass_and_energy():
+    prob = O.Problem(2, 16, 0.06, bc="neumann", length=1.0)
+    y0 = uniform_field(16, 2, 0.1, 0.3, seed=161)
+    y, rec = O.ee_const_run(y0, prob, 2e-5, 6, 1e-10, 30)
+    z, ps = O.lim_const_run(y0, prob, 2e-5, 6)
+    for yy in (y, z):
+        assert abs(yy.sum() - y0.sum()) <= 1e-12 * np.abs(y0).sum()
+    E = [O.energy(y0, prob)]
+    yy = y0.copy()
+    for _ in range(6):
+        yy, _ = O.ee_step_const(yy, prob, 2e-5, 1e-10, 30)
+        E.append(O.energy(yy, prob))
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(E, E[1:])), E
+
+
+def test_neumann_linearised_mode_growth():
+    """A small DCT mode around ubar evolves as delta exp(-mu t), mu = lam (3 ubar^2 - 1 + eps^2 lam)."""
+    n, eps, ubar, delta, tau = 24, 0.05, 0.6, 1e-7, 3e-5
+    prob = O.Problem(2, n, eps, bc="neumann", length=2.0)
+    k = (3, 1)
+    v = neumann_mode(n, k)
+    lam = sum(4.0 / prob.h ** 2 * math.sin(math.pi * kk / (2 * n)) ** 2 for kk in k)
+    mu = lam * (3 * ubar ** 2 - 1 + eps ** 2 * lam)
+    y1, _, info = O.ee_step(ubar + delta * v, prob, tau, 1e-13, 30)
+    np.testing.assert_allclose(y1 - ubar, delta * math.exp(-mu * tau) * v, rtol=0, atol=1e-6 * delta)
+
+
 def test_linear_rt_restart_solves_frozen_linear_problem():
     """Constant-step EE2 with restarts reaches the exact linear solution (eq. yt) at the full tau."""
     prob = O.Problem(2, 8, 0.05)
