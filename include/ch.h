@@ -94,6 +94,15 @@ typedef struct {
     int prec;       /* ch_precision (EE2 only; LIM always runs in FP64) */
     int bc;         /* ch_bc (0, the zero-initialised default: periodic) */
     double length;  /* side L of the domain (<= 0: 1, the unit cube) */
+    /* Variable mobility (Section 2, Remark 1): with mobility != 0 the equation is
+     * c_t = div(M(c) grad mu), M(c) = max(mob0 + mob1 (1 - c^2), 0), discretised as
+     * y' = -A_M(y) (F'(y) + eps^2 A y), (A_M v)_i = h^-2 sum over the neighbours k of
+     * (M_i + M_k)/2 (v_i - v_k); A_M is frozen at y^n within a step:
+     * Ahat_n = A_M(y^n) (J_n + eps^2 A [+ I]).  Single 2-D periodic grids only: with
+     * dim 3, Neumann boundaries, negative or non-finite coefficients or mob0 + mob1 = 0
+     * the calls return CH_EINVAL.  mobility = 0 (zero-initialised) is M = 1. */
+    int mobility;
+    double mob0, mob1;
 } ch_problem;
 
 /*

@@ -21,6 +21,13 @@ Conventions (the paper's notation):
     with the Eyre splitting Ahat_n = A (J_n + eps^2 A + I),
     ghat^n = A (J_n y^n + y^n - F'(y^n)) (eq. A_g_cs).
   * Norms are Euclidean (Section 1, last paragraph).
+  * Variable mobility (Section 2, Remark 1; reading R12): with
+    mobility = (m0, m1) the equation is c_t = div(M(c) grad mu),
+    M(c) = max(m0 + m1 (1 - c^2), 0), discretised as
+    y' = -A_M(y) (F'(y) + eps^2 A y) with the flux-form matrix
+    (A_M(y) v)_i = h^-2 sum over the neighbours k of (M_i + M_k)/2 (v_i - v_k).
+    A step freezes A_M at y^n: Ahat_n = A_M(y^n) (J_n + eps^2 A [+ I]),
+    ghat^n = A_M(y^n) (J_n y^n [+ y^n] - F'(y^n)).  Periodic grids only.
 
 Every function follows the definition or the algorithm box it cites, step by
 step, with library primitives (``numpy`` array arithmetic, ``scipy.linalg.expm``)
@@ -53,6 +60,12 @@ the docstring (these readings are listed in the design notes as well):
       remaining one), which destroys the adaptive 1024^2 run; Leja order keeps
       it below 10^7.2 up to p = 4096.  Both sweeps (m = 1..p, then 2..p) follow
       the same order.
+  R12 variable mobility (Remark 1 gives only the structure A_M(y)): M(c) =
+      max(m0 + m1 (1 - c^2), 0), faces take the arithmetic mean of the two
+      cell mobilities, the step freezes A_M at y^n, the LIM bound is the
+      1-norm of the assembled Ahat_n, and the estimate of eq. LIMest is the
+      trapezoidal rule y_PC = y^n + tau/2 (f(y^n) + f(y^{n+1})) (with M = 1
+      it is eq. LIMest exactly).
 """
 
 from __future__ import annotations
@@ -82,6 +95,7 @@ class Problem:
     eyre: bool = False
     bc: str = "periodic"       # or "neumann"
     length: float = 1.0        # side L of the domain
+    mobility: tuple | None = None   # (m0, m1): M(c) = max(m0 + m1 (1 - c^2), 0); None: M = 1
 
     @property
     def h(self) -> float:
@@ -122,6 +136,33 @@ def lap(y: np.ndarray, prob: Problem) -> np.ndarray:
     return (out / prob.h ** 2).ravel()
 
 
+def mobility_of(y: np.ndarray, prob: Problem) -> np.ndarray:
+    """M(c) = max(m0 + m1 (1 - c^2), 0) (reading R12 of Section 2, Remark 1)."""
+    m0, m1 = prob.mobility
+    return np.maximum(m0 + m1 * (1.0 - y * y), 0.0)
+
+
+def lap_M(v: np.ndarray, y: np.ndarray, prob: Problem) -> np.ndarray:
+    """A_M(y) v = h^-2 sum over the neighbours k of (M_i + M_k)/2 (v_i - v_k): the
+    flux form of -div(M grad) on the periodic grid (Section 2, Remark 1)."""
+    if prob.bc != "periodic":
+        raise ValueError("variable mobility is defined on periodic grids")
+    V = np.asarray(v, dtype=np.float64).reshape(prob.shape)
+    M = mobility_of(np.asarray(y, dtype=np.float64), prob).reshape(prob.shape)
+    out = np.zeros_like(V)
+    for ax in range(prob.dim):
+        for shift in (1, -1):
+            Mk = np.roll(M, shift, axis=ax)
+            Vk = np.roll(V, shift, axis=ax)
+            out = out + 0.5 * (M + Mk) * (V - Vk)
+    return (out / prob.h ** 2).ravel()
+
+
+def outer(v: np.ndarray, y: np.ndarray, prob: Problem) -> np.ndarray:
+    """The outer operator of the splitting: A v, or A_M(y) v with variable mobility."""
+    return lap(v, prob) if prob.mobility is None else lap_M(v, y, prob)
+
+
 def Fprime(y: np.ndarray) -> np.ndarray:
     """F'(c) = c (c^2 - 1), the derivative of F(c) = (1 - c^2)^2 / 4 (eq. F)."""
     return y * (y * y - 1.0)
@@ -133,8 +174,9 @@ def Fenergy(y: np.ndarray) -> np.ndarray:
 
 
 def rhs(y: np.ndarray, prob: Problem) -> np.ndarray:
-    """f(y) = -A (F'(y) + eps^2 A y), the semi-discrete right-hand side (eq. IVP)."""
-    return -lap(Fprime(y) + prob.eps ** 2 * lap(y, prob), prob)
+    """f(y) = -A (F'(y) + eps^2 A y), the semi-discrete right-hand side (eq. IVP);
+    -A_M(y) (F'(y) + eps^2 A y) with variable mobility."""
+    return -outer(Fprime(y) + prob.eps ** 2 * lap(y, prob), y, prob)
 
 
 def jac_diag(y: np.ndarray, prob: Problem) -> np.ndarray:
@@ -146,8 +188,9 @@ def jac_diag(y: np.ndarray, prob: Problem) -> np.ndarray:
 
 
 def ahat_mv(v: np.ndarray, y: np.ndarray, prob: Problem) -> np.ndarray:
-    """Ahat_n v = A ((J_n + eps^2 A [+ I]) v) (eq. A_g / A_g_cs), frozen at y^n = y."""
-    return lap(jac_diag(y, prob) * v + prob.eps ** 2 * lap(v, prob), prob)
+    """Ahat_n v = A ((J_n + eps^2 A [+ I]) v) (eq. A_g / A_g_cs), frozen at y^n = y
+    (A_M(y^n) in place of the outer A with variable mobility)."""
+    return outer(jac_diag(y, prob) * v + prob.eps ** 2 * lap(v, prob), y, prob)
 
 
 def ghat(y: np.ndarray, prob: Problem) -> np.ndarray:
@@ -156,7 +199,7 @@ def ghat(y: np.ndarray, prob: Problem) -> np.ndarray:
     inner = Jy - Fprime(y)
     if prob.eyre:
         inner = inner + y
-    return lap(inner, prob)
+    return outer(inner, y, prob)
 
 
 def assemble_A(prob: Problem):
@@ -181,12 +224,39 @@ def assemble_A(prob: Problem):
     return (sp.kron(I, sp.kron(I, T)) + sp.kron(I, sp.kron(T, I)) + sp.kron(T, sp.kron(I, I))).tocsr()
 
 
+def assemble_AM(y: np.ndarray, prob: Problem):
+    """A_M(y) as a scipy.sparse matrix: D^T W D with D the (edge x point)
+    incidence matrix of the periodic grid (one row per edge i -> i + e_ax,
+    entries +1 at i and -1 at its neighbour) and W = diag((M_i + M_k)/2) / h^2."""
+    import scipy.sparse as sp
+
+    N = prob.N
+    idx = np.arange(N).reshape(prob.shape)
+    M = mobility_of(np.asarray(y, dtype=np.float64), prob).reshape(prob.shape)
+    rows, cols, vals, w = [], [], [], []
+    e = 0
+    for ax in range(prob.dim):
+        nb = np.roll(idx, -1, axis=ax).ravel()
+        Mk = np.roll(M, -1, axis=ax).ravel()
+        m = idx.size
+        rows += [np.arange(e, e + m)] * 2
+        cols += [idx.ravel(), nb]
+        vals += [np.ones(m), -np.ones(m)]
+        w.append(0.5 * (M.ravel() + Mk))
+        e += m
+    D = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(e, N))
+    W = sp.diags(np.concatenate(w) / prob.h ** 2)
+    return (D.T @ W @ D).tocsr()
+
+
 def assemble_ahat(y: np.ndarray, prob: Problem):
-    """Ahat_n = A (J_n + eps^2 A [+ I]) assembled as a sparse matrix (eq. A_g / A_g_cs)."""
+    """Ahat_n = A (J_n + eps^2 A [+ I]) assembled as a sparse matrix (eq. A_g / A_g_cs);
+    A_M(y^n) (J_n + eps^2 A [+ I]) with variable mobility."""
     import scipy.sparse as sp
 
     A = assemble_A(prob)
-    return (A @ (sp.diags(jac_diag(y, prob)) + prob.eps ** 2 * A)).tocsr()
+    Aout = A if prob.mobility is None else assemble_AM(y, prob)
+    return (Aout @ (sp.diags(jac_diag(y, prob)) + prob.eps ** 2 * A)).tocsr()
 
 
 # ---------------------------------------------------------------------------
@@ -366,8 +436,13 @@ def pc_estimate(y_n: np.ndarray, y_np1: np.ndarray, tau: float, prob: Problem):
     """Predictor-corrector estimate (eq. LIMest).
 
     y_PC = y^n - tau/2 A (F'(y^n) + F'(y^{n+1}) + eps^2 A (y^n + y^{n+1}));
-    est = ||y^{n+1} - y_PC|| / ||y_PC||.  Returns (est, y_PC).
+    est = ||y^{n+1} - y_PC|| / ||y_PC||.  Returns (est, y_PC).  With variable
+    mobility the outer operators of the two states differ: y_PC = y^n +
+    tau/2 (f(y^n) + f(y^{n+1})) (reading R12).
     """
+    if prob.mobility is not None:
+        y_pc = y_n + 0.5 * tau * (rhs(y_n, prob) + rhs(y_np1, prob))
+        return float(np.linalg.norm(y_np1 - y_pc) / np.linalg.norm(y_pc)), y_pc
     inner = Fprime(y_n) + Fprime(y_np1) + prob.eps ** 2 * lap(y_n + y_np1, prob)
     y_pc = y_n - 0.5 * tau * lap(inner, prob)
     return float(np.linalg.norm(y_np1 - y_pc) / np.linalg.norm(y_pc)), y_pc
@@ -472,9 +547,10 @@ def lambda_max(y: np.ndarray, prob: Problem) -> float:
     Column j of Ahat_n = A diag(d) + eps^2 A^2 is d_j A e_j + eps^2 A^2 e_j, so
     its absolute sum is a sum over the stencil offsets of
     |d_j a_off + eps^2 b_off|.  With Neumann boundaries the columns near the
-    boundary differ; there the 1-norm is taken from the assembled sparse matrix.
+    boundary differ, and with variable mobility every column differs; there the
+    1-norm is taken from the assembled sparse matrix.
     """
-    if prob.bc == "neumann":
+    if prob.bc == "neumann" or prob.mobility is not None:
         M = abs(assemble_ahat(y, prob))
         return float(np.asarray(M.sum(axis=0)).max())
     if prob.n < 5:

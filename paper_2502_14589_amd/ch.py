@@ -39,7 +39,7 @@ CH_ORTH_DCGS2, CH_ORTH_MGS = 0, 1
 
 class ChProblem(ctypes.Structure):
     _fields_ = [("dim", c_int), ("n", c_int), ("eps", c_double), ("eyre", c_int), ("prec", c_int), ("bc", c_int),
-                ("length", c_double)]
+                ("length", c_double), ("mobility", c_int), ("mob0", c_double), ("mob1", c_double)]
 
 
 class ChEeOpts(ctypes.Structure):
@@ -129,7 +129,10 @@ def load_library(path: str = LIB_PATH):
 @dataclass
 class Problem:
     """Cahn-Hilliard grid: n**dim points on [0,L]^dim, h = L/n; periodic, or
-    (bc = CH_BC_NEUMANN, 2-D) the cell-centred grid with Neumann boundaries."""
+    (bc = CH_BC_NEUMANN, 2-D) the cell-centred grid with Neumann boundaries.
+
+    mobility=(m0, m1) selects the variable mobility M(c) = max(m0 + m1 (1 - c^2), 0)
+    of Section 2, Remark 1 (2-D periodic grids); None is the constant M = 1."""
 
     dim: int
     n: int
@@ -138,10 +141,12 @@ class Problem:
     precision: int = CH_FP64
     bc: int = CH_BC_PERIODIC
     length: float = 1.0
+    mobility: tuple | None = None
 
     def c(self) -> ChProblem:
+        m0, m1 = self.mobility if self.mobility is not None else (0.0, 0.0)
         return ChProblem(self.dim, self.n, float(self.eps), int(bool(self.eyre)), int(self.precision), int(self.bc),
-                         float(self.length))
+                         float(self.length), int(self.mobility is not None), float(m0), float(m1))
 
     @property
     def N(self) -> int:

@@ -91,6 +91,8 @@ struct Shape {
     long long N;
     int bc = CH_BC_PERIODIC;
     double length = 1.0;
+    int mob = 0;
+    double m0 = 1.0, m1 = 0.0;
 };
 
 int check_grid(int dim, int n, double eps, int eyre, Shape* sh) {
@@ -115,10 +117,20 @@ int check_problem(const ch_problem* p, Shape* sh) {
     if (p->bc != CH_BC_PERIODIC && p->bc != CH_BC_NEUMANN) return CH_EINVAL;
     if (p->bc == CH_BC_NEUMANN && p->dim != 2) return CH_EINVAL;   // the paper's 2-D setting only
     if (!(p->length < INFINITY) || p->length != p->length) return CH_EINVAL;
+    if (p->mobility != 0 && p->mobility != 1) return CH_EINVAL;
+    if (p->mobility) {   // 2-D periodic; M >= 0 somewhere
+        if (p->dim != 2 || p->bc != CH_BC_PERIODIC) return CH_EINVAL;
+        if (!(p->mob0 >= 0.0 && p->mob0 < INFINITY) || !(p->mob1 >= 0.0 && p->mob1 < INFINITY) ||
+            !(p->mob0 + p->mob1 > 0.0))
+            return CH_EINVAL;
+    }
     const int rc = check_grid(p->dim, p->n, p->eps, p->eyre, sh);
     if (rc) return rc;
     sh->bc = p->bc;
     sh->length = p->length > 0.0 ? p->length : 1.0;
+    sh->mob = p->mobility;
+    sh->m0 = p->mobility ? p->mob0 : 1.0;
+    sh->m1 = p->mobility ? p->mob1 : 0.0;
     return CH_OK;
 }
 
@@ -292,6 +304,7 @@ Inst make_inst(const Member& m, int i, int dim, int prec, int sblk0, int cblk0, 
     I.inv_h2 = inv_h * inv_h;
     I.eyre = m.eyre;
     I.bc = m.sh.bc;
+    I.mob = m.sh.mob;
     return I;
 }
 
@@ -373,6 +386,12 @@ void init_ctl(Ctl* c, int mode, double t0, double tau0, double T, double tol, do
     c->max_steps = max_steps;
     c->rec = rec;
     c->rec_cap = rec ? rec_cap : 0;
+}
+
+// The mobility coefficients of a single-grid run (M = 1 unless the problem sets them).
+static void set_mobility(Ctl* c, const Shape& sh) {
+    c->mob0 = sh.m0;
+    c->mob1 = sh.m1;
 }
 
 // Bytes of the control block's scalar head (everything before the Arnoldi arrays).
@@ -485,6 +504,7 @@ int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t
     const bool constant = opts->constant_step != 0;
     init_ctl(ctx->hctl, constant ? MODE_EE_CONST : MODE_EE, t0, tau0, T, opts->tol, opts->tol_phi_fixed,
              opts->tau_min, opts->m_max, max_steps, recs ? ctx->rec : nullptr, recs, ctx->expect[0]);
+    set_mobility(ctx->hctl, sh);
     HIP_TRY(ctx, hipMemcpyAsync(ctx->b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     if ((rc = copy_in(ctx, m, y))) return rc;
     const long long limit = max_steps > 0 ? max_steps : (1LL << 40);
@@ -604,6 +624,7 @@ int run_lim(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double 
     const DevBuffers& b = ctx->b;
     init_ctl(ctx->hctl, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, t0, tau0, T, tol, 0.0, 0.0, 0, max_steps,
              recs ? ctx->rec : nullptr, recs, ctx->expect[0]);
+    set_mobility(ctx->hctl, sh);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     if ((rc = copy_in(ctx, m, y))) return rc;
     PartSeq ps;
@@ -1204,6 +1225,7 @@ int ch_step_lim_noalloc(ch_ctx* ctx, const ch_problem* prob, double* y, double t
     tb.hinst = &I;
     Ctl* h = &na_hctl;
     init_ctl(h, tol > 0.0 ? MODE_LIM : MODE_LIM_CONST, t, tau, T, tol, 0.0, 0.0, 0, 1, drec, 1, 0);
+    set_mobility(h, sh);
     // every control value, the instance record and the maps are written before
     // the first launch; partials are written by their producers before use
     HIP_TRY(ctx, hipMemcpyAsync(dinst, &I, sizeof(Inst), hipMemcpyHostToDevice, ctx->stream));
@@ -1243,6 +1265,7 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     if ((rc = build_table(ctx, {m}, sh.dim, prec, &t))) return rc;
     const DevBuffers& b = ctx->b;
     init_ctl(ctx->hctl, MODE_PHI, 0.0, tau0, INFINITY, 0.0, tol_phi, 0.0, m_max, 0, nullptr, 0, ctx->expect[0]);
+    set_mobility(ctx->hctl, sh);
     HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     if ((rc = copy_in(ctx, m, y))) return rc;
     PartSeq ps;

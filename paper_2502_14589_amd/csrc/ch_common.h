@@ -392,6 +392,18 @@ __device__ __forceinline__ T lap1_at(const T* s1, int i1) {
     return lap_at<DIM, R1::X, R1::X * R1::Y>(s1, i1);
 }
 
+// Flux form of the variable-mobility operator (Section 2, Remark 1), unscaled:
+// sum over the neighbours k of c of (m_c + m_k)/2 (s_c - s_k), for values s
+// and mobilities m in two halo-1 regions (2-D).  With m = 1 it is lap1_at.
+template <typename T>
+__device__ __forceinline__ T lap1m_at(const T* s1, const T* m1, int i1) {
+    using R1 = Region<2, 1>;
+    constexpr int RX = R1::X;
+    const T sc = s1[i1], mc = m1[i1];
+    auto flux = [&](int k) { return (mc + m1[k]) * (sc - s1[k]); };
+    return T(0.5) * ((flux(i1 - 1) + flux(i1 + 1)) + (flux(i1 - RX) + flux(i1 + RX)));
+}
+
 template <int DIM>
 constexpr int tile_points() {
     return Geo<DIM>::TX * Geo<DIM>::TY * Geo<DIM>::TZ;

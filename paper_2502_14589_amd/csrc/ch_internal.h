@@ -44,6 +44,7 @@ struct Ctl {
     double T, tol, tol_phi_fixed, tau_min, tau_fixed;
     int mode, m_max, rec_cap, max_steps;   // max_steps <= 0: no step limit
     ch_step_record* rec;                   // rec_cap records (device), or null
+    double mob0, mob1;                     // mobility M(c) = max(mob0 + mob1 (1 - c^2), 0) (Inst::mob)
     // run state
     double t, tau;
     int cur;         // ping-pong buffer holding the latest accepted state
@@ -88,7 +89,15 @@ struct Inst {
     int wblk0, wblk;    // 2-D row-strip / 3-D marching workgroups [wblk0, wblk0 + wblk)
     int vx;             // 2-D strips: columns per lane (divides n)
     int bc;             // ch_bc
+    int mob;            // variable mobility, coefficients in the control block
 };
+
+// The mobility of a state value (Section 2, Remark 1).
+template <typename T>
+__host__ __device__ inline T mobility_of(T y, T m0, T m1) {
+    const T m = m0 + m1 * (T(1) - y * y);
+    return m > T(0) ? m : T(0);
+}
 
 // Grid index of a point g outside [0, n) (within n of it): periodic wrap,
 // or the mirror of the cell-centred Neumann grid (ghost -1 -> 0, n -> n - 1).
@@ -186,6 +195,8 @@ hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq&
 hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStream_t s);
 // 2-D row-strip forms (ch_strip.hip); every 2-D launch uses them.
 inline bool uses_strips(const Table& t) { return t.dim == 2; }
+// A single 2-D grid with variable mobility (batches have constant mobility).
+inline bool mobility(const Table& t) { return t.ninst == 1 && t.hinst[0].mob != 0; }
 hipError_t launch_matvec_strip(const Table& t, int prec, const DevBuffers& b, const double* y, int k, int dots,
                                bool store_w, double* pout, bool timing, hipStream_t s);
 hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,

@@ -1278,6 +1278,45 @@ __device__ __forceinline__ double neumann_colsum(int ix, int iy, int n, double d
     return s;
 }
 
+// Absolute sum of column j = (ix, iy) of Ahat_n = A_M (D + eps^2 A) on the
+// periodic grid with variable mobility (Section 2, Remark 1), a = 1/h^2,
+// mu_ik = (M_i + M_k)/2 and S_i = sum of mu_ik over the four neighbours k of i:
+//   row j:                    a S_j (d_j + 4 a eps^2) + a^2 eps^2 S_j
+//   neighbour i of j:        -a mu_ij (d_j + 4 a eps^2) - a^2 eps^2 S_i
+//   i = j +- 2 e_x, +- 2 e_y: a^2 eps^2 mu_(i, midpoint)
+//   diagonal i = j + e_x + e_y (four): a^2 eps^2 (mu_(i, j + e_x) + mu_(i, j + e_y))
+// The entries need M at the 13 points within distance 2 (in the 1-norm) of
+// j; with M = 1 the sum is the closed form of k_lim_plan.
+__device__ __forceinline__ double mobility_colsum(const double* __restrict__ y, int ix, int iy, int n, double d,
+                                                  double a, double eps2, double m0, double m1) {
+    const double ae = a * a * eps2;
+    auto M = [&](int dx, int dy) {
+        const int x = wrapi(ix + dx, n), yy = wrapi(iy + dy, n);
+        return mobility_of(y[(size_t)yy * n + x], m0, m1);
+    };
+    const double mc = M(0, 0);
+    const double mxp = M(1, 0), mxm = M(-1, 0), myp = M(0, 1), mym = M(0, -1);
+    const double mpp = M(1, 1), mpm = M(1, -1), mmp = M(-1, 1), mmm = M(-1, -1);
+    const double m2xp = M(2, 0), m2xm = M(-2, 0), m2yp = M(0, 2), m2ym = M(0, -2);
+    const double uxp = 0.5 * (mc + mxp), uxm = 0.5 * (mc + mxm), uyp = 0.5 * (mc + myp), uym = 0.5 * (mc + mym);
+    const double Sj = (uxp + uxm) + (uyp + uym);
+    // S of the four neighbours (faces to j, the axis-2 point and two diagonals)
+    const double Sxp = uxp + 0.5 * (mxp + m2xp) + 0.5 * (mxp + mpp) + 0.5 * (mxp + mpm);
+    const double Sxm = uxm + 0.5 * (mxm + m2xm) + 0.5 * (mxm + mmp) + 0.5 * (mxm + mmm);
+    const double Syp = uyp + 0.5 * (myp + m2yp) + 0.5 * (myp + mpp) + 0.5 * (myp + mmp);
+    const double Sym = uym + 0.5 * (mym + m2ym) + 0.5 * (mym + mpm) + 0.5 * (mym + mmm);
+    const double b = d + 4.0 * a * eps2;   // B_jj
+    double s = fabs(a * Sj * b + ae * Sj);
+    s += fabs(a * uxp * b + ae * Sxp) + fabs(a * uxm * b + ae * Sxm);
+    s += fabs(a * uyp * b + ae * Syp) + fabs(a * uym * b + ae * Sym);
+    // axis-2 points: the face between the point and the midpoint
+    s += ae * (0.5 * (m2xp + mxp) + 0.5 * (m2xm + mxm) + 0.5 * (m2yp + myp) + 0.5 * (m2ym + mym));
+    // diagonal points: their faces to the two common neighbours of j
+    s += ae * ((0.5 * (mpp + mxp) + 0.5 * (mpp + myp)) + (0.5 * (mpm + mxp) + 0.5 * (mpm + mym)) +
+               (0.5 * (mmp + mxm) + 0.5 * (mmp + myp)) + (0.5 * (mmm + mxm) + 0.5 * (mmm + mym)));
+    return s;
+}
+
 template <bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ cb2i, const Inst inst0, int ninst, const double* __restrict__ ybase,
@@ -1296,6 +1335,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_begin(Ctl* __restrict__ ctls, 
             if (neu) {   // the column sum itself (2-D: q = iy n + ix)
                 const int iy = (int)(q / I.n), ix = (int)(q - (long long)iy * I.n);
                 mx = fmax(mx, neumann_colsum(ix, iy, I.n, 3.0 * v - 1.0 + I.eyre, a, e));
+            } else if (I.mob) {
+                const int iy = (int)(q / I.n), ix = (int)(q - (long long)iy * I.n);
+                mx = fmax(mx, mobility_colsum(y, ix, iy, I.n, 3.0 * v - 1.0 + I.eyre, a, I.eps2, ctl->mob0, ctl->mob1));
             } else {
                 mn = fmin(mn, v);
                 mx = fmax(mx, v);
@@ -1431,7 +1473,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, c
             const double e = I.eps2 * inv_h2 * inv_h2;
             const double dmin = 3.0 * ymin2 - 1.0 + I.eyre, dmax = 3.0 * ymax2 - 1.0 + I.eyre;
             double gmin, gmax;
-            if (I.bc == CH_BC_NEUMANN) {   // the largest column sum, from the begin launch
+            if (I.bc == CH_BC_NEUMANN || I.mob) {   // the largest column sum, from the begin launch
                 gmin = gmax = tot[1];
             } else if (dim == 2) {
                 gmin = fabs(4.0 * dmin * inv_h2 + 20.0 * e) + 4.0 * fabs(dmin * inv_h2 + 8.0 * e) + 12.0 * e;

@@ -211,8 +211,10 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec(Ctl* __restrict__ ctls, con
 // With z = y this is f(y) (eq. IVP), the EE2 start vector of Fig. 3.
 // Writes r to V_0 (and FP64 to fcur when write_f), optionally the FP32 copy
 // of y; partials of ||r||^2 and ||A c(y)||^2 = ||ghat||^2 (eq. tol_phi).
+// MOB: the outer operator is A_M(y) (variable mobility, Section 2, Remark 1;
+// 2-D single grids).
 // ---------------------------------------------------------------------------
-template <int DIM, typename TV, bool SINGLE>
+template <int DIM, typename TV, bool SINGLE, bool MOB = false>
 __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                     const int* __restrict__ sb2i, const Inst inst0, int ninst, const double* __restrict__ ybase,
                                                     const double* __restrict__ zbase, double* __restrict__ fbase,
@@ -226,6 +228,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctls, cons
     __shared__ double sz[R2::SIZE];
     __shared__ double sdq[R1::SIZE];   // d(y), then the inner expression
     __shared__ double sc[R1::SIZE];
+    __shared__ double sm[MOB ? R1::SIZE : 1];
     const double* y = ybase + I.off;
     const double* z = zbase + I.off;
     double* fout = fbase ? fbase + I.off : nullptr;
@@ -242,6 +245,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctls, cons
         load_regions<DIM, 2, 1>(o, n, I.bc, z, [&](int i, double v) { sz[i] = v; }, y, [&](int i, double v) {
             sdq[i] = dcoef(v, eyre);
             sc[i] = ccoef(v, eyre);
+            if constexpr (MOB) sm[i] = mobility_of(v, ctl->mob0, ctl->mob1);
         });
         __syncthreads();
         for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK)
@@ -251,8 +255,14 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctls, cons
             int i1;
             size_t gi;
             if (out_point<DIM>(i, o, n, i1, gi)) {
-                const double r = -inv_h2 * lap1_at<DIM>(sdq, i1);
-                const double g = inv_h2 * lap1_at<DIM>(sc, i1);
+                double r, g;
+                if constexpr (MOB) {
+                    r = -inv_h2 * lap1m_at(sdq, sm, i1);
+                    g = inv_h2 * lap1m_at(sc, sm, i1);
+                } else {
+                    r = -inv_h2 * lap1_at<DIM>(sdq, i1);
+                    g = inv_h2 * lap1_at<DIM>(sc, i1);
+                }
                 V0[gi] = TV(r);
                 if (fout) fout[gi] = r;
                 if (y32) y32[gi] = float(y[gi]);
@@ -395,8 +405,11 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, 
 // LIM estimate (Fig. 2; eq. LIMest):
 //   y_PC = y^n - tau/2 A (F'(y^n) + F'(y^{n+1}) + eps^2 A (y^n + y^{n+1}));
 // partials of ||y^{n+1} - y_PC||^2 and ||y_PC||^2 go to the controller.
+// MOB: y_PC = y^n + tau/2 (f(y^n) + f(y^{n+1})) with the variable-mobility
+// right-hand side f(y) = -A_M(y) (F'(y) + eps^2 A y), whose outer operator
+// differs between the two states (2-D single grids).
 // ---------------------------------------------------------------------------
-template <int DIM, bool SINGLE>
+template <int DIM, bool SINGLE, bool MOB = false>
 __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                       const int* __restrict__ sb2i, const Inst inst0, int ninst, const double* __restrict__ y0base,
                                                       const double* __restrict__ y1base, double* __restrict__ pout) {
@@ -408,6 +421,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctls, co
     __shared__ double s0[R2::SIZE];
     __shared__ double s1[R2::SIZE];
     __shared__ double sq[R1::SIZE];
+    __shared__ double sq1[MOB ? R1::SIZE : 1];
+    __shared__ double sm0[MOB ? R1::SIZE : 1];
+    __shared__ double sm1[MOB ? R1::SIZE : 1];
     const double* y0 = y0base + I.off;
     const double* y1 = y1base + I.off;
     const int n = I.n;
@@ -424,8 +440,15 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctls, co
         for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK) {
             const int c = r1_to_r2<DIM>(i);
             const double a = s0[c], b = s1[c];
-            sq[i] = a * (a * a - 1.0) + b * (b * b - 1.0) +
-                    e2ih2 * (lap2_at_r1<DIM>(s0, i) + lap2_at_r1<DIM>(s1, i));
+            if constexpr (MOB) {
+                sq[i] = a * (a * a - 1.0) + e2ih2 * lap2_at_r1<DIM>(s0, i);
+                sq1[i] = b * (b * b - 1.0) + e2ih2 * lap2_at_r1<DIM>(s1, i);
+                sm0[i] = mobility_of(a, ctl->mob0, ctl->mob1);
+                sm1[i] = mobility_of(b, ctl->mob0, ctl->mob1);
+            } else {
+                sq[i] = a * (a * a - 1.0) + b * (b * b - 1.0) +
+                        e2ih2 * (lap2_at_r1<DIM>(s0, i) + lap2_at_r1<DIM>(s1, i));
+            }
         }
         __syncthreads();
         for (int i = threadIdx.x; i < tile_points<DIM>(); i += CH_BLOCK) {
@@ -433,7 +456,11 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_lim(Ctl* __restrict__ ctls, co
             size_t gi;
             if (out_point<DIM>(i, o, n, i1, gi)) {
                 const int c = r1_to_r2<DIM>(i1);
-                const double ypc = s0[c] - 0.5 * tau * inv_h2 * lap1_at<DIM>(sq, i1);
+                double ypc;
+                if constexpr (MOB)
+                    ypc = s0[c] - 0.5 * tau * inv_h2 * (lap1m_at(sq, sm0, i1) + lap1m_at(sq1, sm1, i1));
+                else
+                    ypc = s0[c] - 0.5 * tau * inv_h2 * lap1_at<DIM>(sq, i1);
                 const double e = s1[c] - ypc;
                 a_err += e * e;
                 a_pc += ypc * ypc;
@@ -499,7 +526,10 @@ hipError_t launch_matvec(const Table& t, int prec, const DevBuffers& b, PartSeq&
 template <int DIM, typename TV>
 static hipError_t launch_resid_t(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y, const double* z,
                                  bool write_f, bool write_y32, hipStream_t s) {
-    if (t.ninst == 1)
+    if (DIM == 2 && mobility(t))
+        hipLaunchKernelGGL((k_resid<2, TV, true, true>), SARGS, y, z, write_f ? b.fcur : nullptr, static_cast<TV*>(b.V),
+                           write_y32 ? b.y32 : nullptr, ps.out());
+    else if (t.ninst == 1)
         hipLaunchKernelGGL((k_resid<DIM, TV, true>), SARGS, y, z, write_f ? b.fcur : nullptr, static_cast<TV*>(b.V),
                        write_y32 ? b.y32 : nullptr, ps.out());
     else
@@ -573,7 +603,9 @@ hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y
 hipError_t launch_est_lim(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y0, const double* y1,
                           hipStream_t s) {
     if (t.dim == 2)
-        if (t.ninst == 1)
+        if (mobility(t))
+            hipLaunchKernelGGL((k_est_lim<2, true, true>), SARGS, y0, y1, ps.out());
+        else if (t.ninst == 1)
             hipLaunchKernelGGL((k_est_lim<2, true>), SARGS, y0, y1, ps.out());
         else
             hipLaunchKernelGGL((k_est_lim<2, false>), SARGS, y0, y1, ps.out());

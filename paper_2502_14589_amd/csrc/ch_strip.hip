@@ -124,6 +124,57 @@ __device__ __forceinline__ T lap5(const T (&up)[VX], const T (&c)[VX], const T (
     return T(4) * c[e] - nb;
 }
 
+// Flux form of the variable-mobility operator (Section 2, Remark 1),
+// unscaled: sum over the four neighbours k of (m_c + m_k)/2 (q_c - q_k), the
+// mobilities m laid out as the values q (mxl, mxr: the lane neighbours' m).
+// With m = 1 it equals lap5.
+template <typename T, int VX>
+__device__ __forceinline__ T lap5m(const T (&up)[VX], const T (&c)[VX], const T (&dn)[VX], T xl, T xr,
+                                   const T (&mup)[VX], const T (&mc)[VX], const T (&mdn)[VX], T mxl, T mxr, int e) {
+    const T l = e > 0 ? c[e - 1] : xl, r = e < VX - 1 ? c[e + 1] : xr;
+    const T ml = e > 0 ? mc[e - 1] : mxl, mr = e < VX - 1 ? mc[e + 1] : mxr;
+    const T q = c[e], m = mc[e];
+    const T fx = (m + ml) * (q - l) + (m + mr) * (q - r);
+    const T fy = (m + mup[e]) * (q - up[e]) + (m + mdn[e]) * (q - dn[e]);
+    return T(0.5) * (fx + fy);
+}
+
+// The outer operator at element e of row c: A (MOB false) or A_M (MOB true,
+// mobility rows m), both unscaled.
+template <bool MOB, typename T, int VX>
+__device__ __forceinline__ T outer_op(const T (&up)[VX], const T (&c)[VX], const T (&dn)[VX], T xl, T xr,
+                                      const T (&mup)[VX], const T (&mc)[VX], const T (&mdn)[VX], T mxl, T mxr, int e) {
+    if constexpr (MOB) return lap5m<T, VX>(up, c, dn, xl, xr, mup, mc, mdn, mxl, mxr, e);
+    else return lap5<T, VX>(up, c, dn, xl, xr, e);
+}
+
+// Mobility coefficients (from the control block) of a MOB launch.
+struct Mob {
+    double m0, m1;
+};
+__device__ __forceinline__ Mob mob_of(const Ctl* ctl, bool on) { return on ? Mob{ctl->mob0, ctl->mob1} : Mob{0.0, 0.0}; }
+
+// Mobility rows of a block of state rows (MOB), or nothing.
+template <bool MOB, typename T, int VX, int NR>
+struct MobRows {
+    T m[MOB ? NR : 1][VX];
+    __device__ __forceinline__ void set(int j, const T (&y)[VX], T m0, T m1) {
+        if constexpr (MOB) {
+#pragma unroll
+            for (int e = 0; e < VX; ++e) m[j][e] = mobility_of(y[e], m0, m1);
+        }
+    }
+    __device__ __forceinline__ const T (&row(int j) const)[VX] { return m[MOB ? j : 0]; }
+    __device__ __forceinline__ T left(int j) const {
+        if constexpr (MOB) return wave_shift<DPP_WAVE_SHR1>(m[j][VX - 1]);
+        else return T(0);
+    }
+    __device__ __forceinline__ T right(int j) const {
+        if constexpr (MOB) return wave_shift<DPP_WAVE_SHL1>(m[j][0]);
+        else return T(0);
+    }
+};
+
 template <typename T>
 __device__ __forceinline__ T dcoef(T y, int eyre) {
     return T(3) * y * y - T(1) + T(eyre);
@@ -216,9 +267,9 @@ struct MatvecArgs {
 
 // The strips of this wave; dot-product totals go to red[.][wv] (DM_DC) or
 // are returned per lane (DM_ONE).
-template <typename TV, int DM, int VX, bool NEU>
+template <typename TV, int DM, int VX, bool NEU, bool MOB>
 __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<TV, DM>& A, TV sc, int wv,
-                                                double (*red)[CH_STRIP_WAVES]) {
+                                                double (*red)[CH_STRIP_WAVES], Mob mob) {
     constexpr int NU = SR + 4, ND = SR + 2, W = CH_STRIP_WAVES;
     const int lane = threadIdx.x & 63;
     const int n = I.n, k = A.k;
@@ -251,6 +302,9 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
         for (int j = 0; j < NU; ++j)
 #pragma unroll
             for (int e = 0; e < VX; ++e) u[j][e] *= sc;
+        MobRows<MOB, TV, VX, ND> mb;
+#pragma unroll
+        for (int j = 0; j < ND; ++j) mb.set(j, d[j], TV(mob.m0), TV(mob.m1));
 #pragma unroll
         for (int j = 0; j < ND; ++j)
 #pragma unroll
@@ -264,13 +318,16 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
             for (int e = 0; e < VX; ++e)
                 q[j][e] = d[j][e] * u[j + 1][e] + e2ih2 * lap5<TV, VX>(u[j], u[j + 1], u[j + 2], xl, xr, e);
         }
-        // w = A q on rows r0 .. r0 + SR - 1
+        // w = A q (A_M q with mobility) on rows r0 .. r0 + SR - 1
         TV w[SR][VX];
 #pragma unroll
         for (int i = 0; i < SR; ++i) {
             const TV xl = wave_shift<DPP_WAVE_SHR1>(q[i + 1][VX - 1]), xr = wave_shift<DPP_WAVE_SHL1>(q[i + 1][0]);
+            const TV ml = mb.left(i + 1), mr = mb.right(i + 1);
 #pragma unroll
-            for (int e = 0; e < VX; ++e) w[i][e] = ih2 * lap5<TV, VX>(q[i], q[i + 1], q[i + 2], xl, xr, e);
+            for (int e = 0; e < VX; ++e)
+                w[i][e] = ih2 * outer_op<MOB, TV, VX>(q[i], q[i + 1], q[i + 2], xl, xr, mb.row(i), mb.row(i + 1),
+                                                      mb.row(i + 2), ml, mr, e);
         }
         bool rowin[SR];
 #pragma unroll
@@ -362,7 +419,7 @@ __device__ __forceinline__ double matvec_strips(const Inst& I, const MatvecArgs<
 // VX: the strip width of a single-instance launch; 0: per instance (batches).
 // TAG distinguishes the launches of the timing aid (same code, another symbol).
 // NEU: the single grid has Neumann boundaries (batches are periodic).
-template <typename TV, bool SINGLE, int DM, int TAG, int VX, bool NEU = false>
+template <typename TV, bool SINGLE, int DM, int TAG, int VX, bool NEU = false, bool MOB = false>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_matvec_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        TV* __restrict__ V, size_t ldv, int k, int store_w,
@@ -381,14 +438,14 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_matvec_s(Ctl* __restrict__ c
     const MatvecArgs<TV, DM> A{V, ldv, k, store_w, ybase};
     double one;
     if constexpr (VX > 0) {
-        one = matvec_strips<TV, DM, VX, NEU>(I, A, sc, wv, red);
+        one = matvec_strips<TV, DM, VX, NEU, MOB>(I, A, sc, wv, red, mob_of(ctl, MOB));
     } else {
         if (I.vx == 1) {
-            one = matvec_strips<TV, DM, 1, false>(I, A, sc, wv, red);
+            one = matvec_strips<TV, DM, 1, false, false>(I, A, sc, wv, red, Mob{});
         } else if (sizeof(TV) == 8 || I.vx == 2) {
-            one = matvec_strips<TV, DM, 2, false>(I, A, sc, wv, red);
+            one = matvec_strips<TV, DM, 2, false, false>(I, A, sc, wv, red, Mob{});
         } else {
-            one = matvec_strips<TV, DM, (sizeof(TV) == 4 ? 4 : 2), false>(I, A, sc, wv, red);
+            one = matvec_strips<TV, DM, (sizeof(TV) == 4 ? 4 : 2), false, false>(I, A, sc, wv, red, Mob{});
         }
     }
     if (DM == DM_DC) {
@@ -411,10 +468,10 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_matvec_s(Ctl* __restrict__ c
 // The coefficients (tau a_m, 1 / (1 + tau a_m)) of stage position `pos` come
 // from the plan launch.
 // ---------------------------------------------------------------------------
-template <int VX, bool NEU>
+template <int VX, bool NEU, bool MOB>
 __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restrict__ ybase,
                                            const double* __restrict__ zbase, double* __restrict__ obase, double ta,
-                                           double inv, double tau, int wv) {
+                                           double inv, double tau, int wv, Mob mob) {
     constexpr int NU = SR + 4, ND = SR + 2, W = CH_STRIP_WAVES;
     const int lane = threadIdx.x & 63;
     const int n = I.n;
@@ -440,6 +497,9 @@ __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restri
         for (int j = 0; j < NU; ++j) flip_if<double, VX>(P.rev, z[j]);
 #pragma unroll
         for (int j = 0; j < ND; ++j) flip_if<double, VX>(P.rev, y[j]);
+        MobRows<MOB, double, VX, ND> mb;
+#pragma unroll
+        for (int j = 0; j < ND; ++j) mb.set(j, y[j], mob.m0, mob.m1);
         // inner expression d z + eps^2 A z - c on rows r0 - 1 .. r0 + SR
         double q[ND][VX];
 #pragma unroll
@@ -453,10 +513,12 @@ __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restri
 #pragma unroll
         for (int i = 0; i < SR; ++i) {
             const double xl = wave_shift<DPP_WAVE_SHR1>(q[i + 1][VX - 1]), xr = wave_shift<DPP_WAVE_SHL1>(q[i + 1][0]);
+            const double ml = mb.left(i + 1), mr = mb.right(i + 1);
             double o[VX];
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                const double r = -inv_h2 * lap5<double, VX>(q[i], q[i + 1], q[i + 2], xl, xr, e);
+                const double r = -inv_h2 * outer_op<MOB, double, VX>(q[i], q[i + 1], q[i + 2], xl, xr, mb.row(i),
+                                                                    mb.row(i + 1), mb.row(i + 2), ml, mr, e);
                 o[e] = (y[i + 1][e] + ta * z[i + 2][e] + tau * r) * inv;
             }
             if (P.out && P.r0 + i < n) store_row<double, VX>(grid_row(O, P.r0 + i, n, bc), bo, o);
@@ -466,7 +528,7 @@ __device__ __forceinline__ void lim_strips(const Inst& I, const double* __restri
 
 // Stage launch l (lim_launch) of each instance: its source and destination
 // follow from its own Chebyshev order.
-template <bool SINGLE, int TAG, int VX, bool NEU = false>
+template <bool SINGLE, int TAG, int VX, bool NEU = false, bool MOB = false>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                           const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                           const double* __restrict__ ybase, double* youtbase,
@@ -484,10 +546,10 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage_s(Ctl* __restrict_
     const double ta = cf[0], inv = cf[1], tau = ctl->tau0;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if constexpr (VX > 0) {
-        lim_strips<VX, NEU>(I, ybase, zbase, obase, ta, inv, tau, wv);
+        lim_strips<VX, NEU, MOB>(I, ybase, zbase, obase, ta, inv, tau, wv, mob_of(ctl, MOB));
     } else {
-        if (I.vx == 1) lim_strips<1, false>(I, ybase, zbase, obase, ta, inv, tau, wv);
-        else lim_strips<2, false>(I, ybase, zbase, obase, ta, inv, tau, wv);
+        if (I.vx == 1) lim_strips<1, false, false>(I, ybase, zbase, obase, ta, inv, tau, wv, Mob{});
+        else lim_strips<2, false, false>(I, ybase, zbase, obase, ta, inv, tau, wv, Mob{});
     }
 }
 
@@ -517,10 +579,11 @@ __device__ __forceinline__ int wrap_row_any(int r, int n) {
     return r < 0 ? r + n : r;
 }
 
-template <int VX, bool NEU>
+template <int VX, bool NEU, bool MOB>
 __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restrict__ ybase,
                                             const double* __restrict__ zbase, double* __restrict__ obase,
-                                            double ta1, double inv1, double ta2, double inv2, double tau, int wv) {
+                                            double ta1, double inv1, double ta2, double inv2, double tau, int wv,
+                                            Mob mob) {
     constexpr int R = LIM2_ROWS, HL = lim2_halo_lanes<VX>(), OW = lim2_cols<VX>(), W = CH_STRIP_WAVES;
     constexpr int NZ = R + 8, NY = R + 6, NQ1 = R + 6, NO1 = R + 4, NQ2 = R + 2;
     const int lane = threadIdx.x & 63;
@@ -557,6 +620,9 @@ __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restr
         for (int j = 0; j < NZ; ++j) flip_if<double, VX>(rev, z[j]);
 #pragma unroll
         for (int j = 0; j < NY; ++j) flip_if<double, VX>(rev, y[j]);
+        MobRows<MOB, double, VX, NY> mb;   // mobility rows r0 - 3 + j
+#pragma unroll
+        for (int j = 0; j < NY; ++j) mb.set(j, y[j], mob.m0, mob.m1);
         // first stage: q1 on rows r0 - 3 + j, its result o1 on rows r0 - 2 + j
         double q1[NQ1][VX];
 #pragma unroll
@@ -571,9 +637,11 @@ __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restr
 #pragma unroll
         for (int j = 0; j < NO1; ++j) {
             const double xl1 = wave_shift<DPP_WAVE_SHR1>(q1[j + 1][VX - 1]), xr1 = wave_shift<DPP_WAVE_SHL1>(q1[j + 1][0]);
+            const double ml = mb.left(j + 1), mr = mb.right(j + 1);
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                const double r = -inv_h2 * lap5<double, VX>(q1[j], q1[j + 1], q1[j + 2], xl1, xr1, e);
+                const double r = -inv_h2 * outer_op<MOB, double, VX>(q1[j], q1[j + 1], q1[j + 2], xl1, xr1, mb.row(j),
+                                                                    mb.row(j + 1), mb.row(j + 2), ml, mr, e);
                 o1[j][e] = (y[j + 1][e] + ta1 * z[j + 2][e] + tau * r) * inv1;
             }
         }
@@ -590,10 +658,12 @@ __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restr
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const double xl1 = wave_shift<DPP_WAVE_SHR1>(q2[i + 1][VX - 1]), xr1 = wave_shift<DPP_WAVE_SHL1>(q2[i + 1][0]);
+            const double ml = mb.left(i + 3), mr = mb.right(i + 3);
             double o[VX];
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                const double r = -inv_h2 * lap5<double, VX>(q2[i], q2[i + 1], q2[i + 2], xl1, xr1, e);
+                const double r = -inv_h2 * outer_op<MOB, double, VX>(q2[i], q2[i + 1], q2[i + 2], xl1, xr1, mb.row(i + 2),
+                                                                    mb.row(i + 3), mb.row(i + 4), ml, mr, e);
                 o[e] = (y[i + 3][e] + ta2 * o1[i + 2][e] + tau * r) * inv2;
             }
             if (out && r0 + i < n) store_row<double, VX>(row_rsrc(O + (size_t)(r0 + i) * n, rb), bo, o);
@@ -601,7 +671,7 @@ __device__ __forceinline__ void lim2_strips(const Inst& I, const double* __restr
     }
 }
 
-template <bool SINGLE, int TAG, int VX, bool NEU = false>
+template <bool SINGLE, int TAG, int VX, bool NEU = false, bool MOB = false>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage2_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                            const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                            const double* __restrict__ ybase, double* youtbase,
@@ -618,10 +688,10 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage2_s(Ctl* __restrict
     const double ta1 = cf[0], inv1 = cf[1], ta2 = cf[2], inv2 = cf[3], tau = ctl->tau0;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if constexpr (VX > 0) {
-        lim2_strips<VX, NEU>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
+        lim2_strips<VX, NEU, MOB>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv, mob_of(ctl, MOB));
     } else {
-        if (I.vx == 1) lim2_strips<1, false>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
-        else lim2_strips<2, false>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv);
+        if (I.vx == 1) lim2_strips<1, false, false>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv, Mob{});
+        else lim2_strips<2, false, false>(I, ybase, zbase, obase, ta1, inv1, ta2, inv2, tau, wv, Mob{});
     }
 }
 
@@ -632,11 +702,11 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_lim_stage2_s(Ctl* __restrict
 // f1 becomes the next step's f(y^n) and start vector; ||A c(y^{n+1})|| the next
 // ||ghat||.  Lane partials of the four sums are returned in acc.
 // ---------------------------------------------------------------------------
-template <typename TV, int VX, bool NEU>
+template <typename TV, int VX, bool NEU, bool MOB>
 __device__ __forceinline__ void est_strips(const Inst& I, const double* __restrict__ y0base,
                                            const double* __restrict__ y1base, double* __restrict__ fbase,
                                            TV* __restrict__ V0base, float* __restrict__ y32base, double half_tau,
-                                           int wv, double (&acc)[4]) {
+                                           int wv, double (&acc)[4], Mob mob) {
     constexpr int NU = SR + 4, ND = SR + 2, W = CH_STRIP_WAVES;
     const int lane = threadIdx.x & 63;
     const int n = I.n;
@@ -665,6 +735,9 @@ __device__ __forceinline__ void est_strips(const Inst& I, const double* __restri
         }
 #pragma unroll
         for (int j = 0; j < NU; ++j) flip_if<double, VX>(P.rev, y1[j]);
+        MobRows<MOB, double, VX, ND> mb;   // M(y^{n+1}) on rows r0 - 1 .. r0 + SR
+#pragma unroll
+        for (int j = 0; j < ND; ++j) mb.set(j, y1[j + 1], mob.m0, mob.m1);
         // inner expressions on rows r0 - 1 .. r0 + SR: F'(y) + eps^2 A y and c(y)
         double q[ND][VX], c[ND][VX];
 #pragma unroll
@@ -681,14 +754,17 @@ __device__ __forceinline__ void est_strips(const Inst& I, const double* __restri
         for (int i = 0; i < SR; ++i) {
             const double ql = wave_shift<DPP_WAVE_SHR1>(q[i + 1][VX - 1]), qr = wave_shift<DPP_WAVE_SHL1>(q[i + 1][0]);
             const double cl = wave_shift<DPP_WAVE_SHR1>(c[i + 1][VX - 1]), cr = wave_shift<DPP_WAVE_SHL1>(c[i + 1][0]);
+            const double ml = mb.left(i + 1), mr = mb.right(i + 1);
             const bool in = P.out && P.r0 + i < n;
             double f1[VX];
             TV fv[VX];
             float yf[VX];
 #pragma unroll
             for (int e = 0; e < VX; ++e) {
-                f1[e] = -inv_h2 * lap5<double, VX>(q[i], q[i + 1], q[i + 2], ql, qr, e);
-                const double g1 = inv_h2 * lap5<double, VX>(c[i], c[i + 1], c[i + 2], cl, cr, e);
+                f1[e] = -inv_h2 * outer_op<MOB, double, VX>(q[i], q[i + 1], q[i + 2], ql, qr, mb.row(i), mb.row(i + 1),
+                                                            mb.row(i + 2), ml, mr, e);
+                const double g1 = inv_h2 * outer_op<MOB, double, VX>(c[i], c[i + 1], c[i + 2], cl, cr, mb.row(i),
+                                                                     mb.row(i + 1), mb.row(i + 2), ml, mr, e);
                 const double ypc = y0[i][e] + half_tau * (f0[i][e] + f1[e]);
                 const double yv = y1[i + 2][e];
                 const double er = yv - ypc;
@@ -710,7 +786,7 @@ __device__ __forceinline__ void est_strips(const Inst& I, const double* __restri
     }
 }
 
-template <typename TV, bool SINGLE, int VX, bool NEU = false>
+template <typename TV, bool SINGLE, int VX, bool NEU = false, bool MOB = false>
 __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_est_ee_s(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        const double* __restrict__ y0base,
@@ -724,11 +800,11 @@ __global__ __launch_bounds__(CH_STRIP_BLOCK) void k_est_ee_s(Ctl* __restrict__ c
     const double half_tau = 0.5 * (ctl->mode == MODE_EE ? ctl->tau_acc : ctl->tau_step);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (VX > 0) {
-        est_strips<TV, VX, NEU>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+        est_strips<TV, VX, NEU, MOB>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc, mob_of(ctl, MOB));
     } else {
-        if (I.vx == 1) est_strips<TV, 1, false>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
-        else if (sizeof(TV) == 8 || I.vx == 2) est_strips<TV, 2, false>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
-        else est_strips<TV, (sizeof(TV) == 4 ? 4 : 2), false>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc);
+        if (I.vx == 1) est_strips<TV, 1, false, false>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc, Mob{});
+        else if (sizeof(TV) == 8 || I.vx == 2) est_strips<TV, 2, false, false>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc, Mob{});
+        else est_strips<TV, (sizeof(TV) == 4 ? 4 : 2), false, false>(I, y0base, y1base, fbase, V0base, y32base, half_tau, wv, acc, Mob{});
     }
     write_partials<4, RED_SUM>(acc, pout);
 }
@@ -746,7 +822,10 @@ static bool neumann(const Table& t) { return t.ninst == 1 && t.hinst[0].bc == CH
 template <typename TV, int DM, bool TIMING, int VX>
 static void launch_matvec_one(const Table& t, const DevBuffers& b, const TV* y, int k, int store_w, double* pout,
                               hipStream_t s) {
-    if (neumann(t))
+    if (mobility(t))
+        hipLaunchKernelGGL((k_matvec_s<TV, true, DM, TIMING ? 1 : 0, VX, false, true>), WARGS, static_cast<TV*>(b.V),
+                           b.ldv, k, store_w, y, pout);
+    else if (neumann(t))
         hipLaunchKernelGGL((k_matvec_s<TV, true, DM, TIMING ? 1 : 0, VX, true>), WARGS, static_cast<TV*>(b.V), b.ldv,
                            k, store_w, y, pout);
     else
@@ -794,7 +873,10 @@ hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const dou
                                   bool pairs, bool timing, hipStream_t s) {
     const bool two = t.hinst[0].vx >= 2;
     const int pr = pairs ? 1 : 0;
-    if (neumann(t)) {
+    if (mobility(t)) {
+        if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 0, 2, false, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
+        else hipLaunchKernelGGL((k_lim_stage_s<true, 0, 1, false, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
+    } else if (neumann(t)) {
         if (two) hipLaunchKernelGGL((k_lim_stage_s<true, 0, 2, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
         else hipLaunchKernelGGL((k_lim_stage_s<true, 0, 1, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l, pr);
     } else if (timing) {
@@ -812,7 +894,10 @@ hipError_t launch_lim_stage_strip(const Table& t, const DevBuffers& b, const dou
 hipError_t launch_lim_stage2_strip(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
                                    bool timing, hipStream_t s) {
     const bool two = t.hinst[0].vx >= 2;
-    if (neumann(t)) {
+    if (mobility(t)) {
+        if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 2, false, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
+        else hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 1, false, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
+    } else if (neumann(t)) {
         if (two) hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 2, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
         else hipLaunchKernelGGL((k_lim_stage2_s<true, 0, 1, true>), WARGS, yin, yout, b.zbuf, b.lcoef, l);
     } else if (timing) {
@@ -836,6 +921,14 @@ static void launch_est_ee_s(const Table& t, const DevBuffers& b, const double* y
         return;
     }
     const int vx = t.hinst[0].vx;
+    if (mobility(t)) {
+        if (sizeof(TV) == 4 && vx >= 4)
+            hipLaunchKernelGGL((k_est_ee_s<TV, true, (sizeof(TV) == 4 ? 4 : 2), false, true>), WARGS, y0, y1, b.fcur,
+                               V0, y32, pout);
+        else if (vx >= 2) hipLaunchKernelGGL((k_est_ee_s<TV, true, 2, false, true>), WARGS, y0, y1, b.fcur, V0, y32, pout);
+        else hipLaunchKernelGGL((k_est_ee_s<TV, true, 1, false, true>), WARGS, y0, y1, b.fcur, V0, y32, pout);
+        return;
+    }
     if (neumann(t)) {
         if (sizeof(TV) == 4 && vx >= 4)
             hipLaunchKernelGGL((k_est_ee_s<TV, true, (sizeof(TV) == 4 ? 4 : 2), true>), WARGS, y0, y1, b.fcur, V0, y32,

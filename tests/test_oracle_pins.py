@@ -732,3 +732,175 @@ def test_krylov_beta_zero_and_breakdown():
     y2, tau2, info2 = O.krylov_phi_cycle(lambda x: lam * x, np.zeros(prob.N), g, 0.01, 1e-12, 10)
     assert info2.j == 1 and info2.converged
     np.testing.assert_allclose(y2, -(1 - math.exp(-lam * 0.01)) * v, atol=1e-13)
+
+
+# --- P18: variable mobility (Section 2, Remark 1) -------------------------------------------
+
+MOBS = [(1.0, 0.0), (0.3, 1.0), (0.0, 1.0)]   # constant, positive, degenerate (M = 0 for |c| >= 1)
+
+
+def mob_field(n, seed):
+    """A field that crosses |c| = 1, so the degenerate mobility clips somewhere."""
+    y = uniform_field(n, 2, 0.0, 1.3, seed=seed)
+    return y
+
+
+def edge_sum(y, v, w, prob):
+    """sum over the grid edges (i, i + e_ax) of (M_i + M_k)/2 (v_i - v_k)(w_i - w_k),
+    by explicit loops over points and their forward neighbours."""
+    n = prob.n
+    m0, m1 = prob.mobility
+    M = lambda c: max(m0 + m1 * (1.0 - c * c), 0.0)
+    tot = 0.0
+    for iy in range(n):
+        for ix in range(n):
+            i = iy * n + ix
+            for k in (iy * n + (ix + 1) % n, ((iy + 1) % n) * n + ix):
+                mu = 0.5 * (M(y[i]) + M(y[k]))
+                tot += mu * (v[i] - v[k]) * (w[i] - w[k])
+    return tot
+
+
+def test_mobility_constant_reduces_to_the_constant_problem():
+    """M = 1 gives A_M = A: every operator, lambda_max (assembled 1-norm against
+    the stencil closed form) and whole EE2/LIM steps agree with M = 1;
+    M = c scales A_M by c."""
+    n, eps = 16, 0.05
+    p1 = O.Problem(2, n, eps)
+    pm = O.Problem(2, n, eps, mobility=(1.0, 0.0))
+    y = uniform_field(n, 2, 0.1, 0.3, seed=1800)
+    v = uniform_field(n, 2, 0.0, 1.0, seed=1801)
+    np.testing.assert_allclose(O.lap_M(v, y, pm), O.lap(v, p1), rtol=0, atol=1e-12 * np.abs(O.lap(v, p1)).max())
+    for f in (lambda p: O.rhs(y, p), lambda p: O.ghat(y, p), lambda p: O.ahat_mv(v, y, p)):
+        a, b = f(pm), f(p1)
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(b).max())
+    assert O.lambda_max(y, pm) == pytest.approx(O.lambda_max(y, p1), rel=1e-13)
+    tau = 20.0 / O.lambda_max(y, p1)
+    ya, _, _ = O.ee_step(y, pm, tau, 1e-10, 30)
+    yb, _, _ = O.ee_step(y, p1, tau, 1e-10, 30)
+    assert O.rel_error(ya, yb) <= 1e-12
+    ya, pa = O.lim_step(y, pm, tau)
+    yb, pb = O.lim_step(y, p1, tau)
+    assert pa == pb and O.rel_error(ya, yb) <= 1e-12
+    y2 = O.ee_step(y, p1, tau, 1e-10, 30)[0]
+    assert O.pc_estimate(y, y2, tau, pm)[0] == pytest.approx(O.pc_estimate(y, y2, tau, p1)[0], rel=1e-8)
+    p3 = O.Problem(2, n, eps, mobility=(3.0, 0.0))
+    np.testing.assert_allclose(O.lap_M(v, y, p3), 3.0 * O.lap(v, p1), rtol=0, atol=1e-11 * np.abs(O.lap(v, p1)).max())
+
+
+@pytest.mark.parametrize("mob", MOBS)
+def test_mobility_operator_is_the_edge_quadratic_form(mob):
+    """w^T A_M v = h^-2 sum over edges of mu_e (v_i - v_k)(w_i - w_k) (the weak
+    form of -div(M grad)); A_M is symmetric, positive semidefinite, kills
+    constants, and its matrix-free and assembled forms agree."""
+    n = 7
+    prob = O.Problem(2, n, 0.1, mobility=mob)
+    y = mob_field(n, 1810)
+    v = uniform_field(n, 2, 0.0, 1.0, seed=1811)
+    w = uniform_field(n, 2, 0.0, 1.0, seed=1812)
+    q = w @ O.lap_M(v, y, prob)
+    assert q == pytest.approx(edge_sum(y, v, w, prob) / prob.h ** 2, rel=1e-12)
+    AM = O.assemble_AM(y, prob).toarray()
+    np.testing.assert_allclose(AM, AM.T, rtol=0, atol=1e-12 * np.abs(AM).max())
+    np.testing.assert_allclose(AM @ v, O.lap_M(v, y, prob), rtol=0, atol=1e-12 * np.abs(AM).max())
+    assert np.abs(AM @ np.ones(n * n)).max() <= 1e-12 * np.abs(AM).max()
+    assert np.linalg.eigvalsh(AM).min() >= -1e-12 * np.abs(AM).max()
+
+
+@pytest.mark.parametrize("mob", MOBS[1:])
+def test_mobility_energy_dissipation_identity(mob):
+    """dE/dt = -h^(d-2) sum over edges of mu_e (mu_i - mu_k)^2 <= 0 along
+    y' = -A_M(y) mu, mu = F'(y) + eps^2 A y (the energy law of Remark 1's
+    equation), by a central difference of the discrete energy (eq. Ediscr)."""
+    n = 12
+    prob = O.Problem(2, n, 0.08, mobility=mob)
+    y = mob_field(n, 1820)
+    f = O.rhs(y, prob)
+    dt = 1e-9 / np.abs(f).max()
+    dE = (O.energy(y + dt * f, prob) - O.energy(y - dt * f, prob)) / (2 * dt)
+    mu = O.Fprime(y) + prob.eps ** 2 * O.lap(y, prob)
+    expect = -edge_sum(y, mu, mu, prob) * prob.h ** (2 - 2)
+    assert expect < 0
+    assert dE == pytest.approx(expect, rel=1e-5)
+
+
+def test_mobility_mass_conservation_ee_and_lim():
+    prob = O.Problem(2, 24, 0.04, mobility=(0.1, 1.0))
+    y0 = uniform_field(24, 2, 0.1, 0.5, seed=1830)
+    m0, s0 = O.mass(y0), np.abs(y0).sum()
+    y1, _ = O.ee_adaptive(y0, prob, 1e-5, np.inf, 1e-4, 20, max_steps=10)
+    assert abs(O.mass(y1) - m0) <= 1e-12 * s0
+    y2, _ = O.lim_adaptive(y0, prob, 1e-6, np.inf, 1e-4, max_steps=10)
+    assert abs(O.mass(y2) - m0) <= 1e-12 * s0
+
+
+@pytest.mark.parametrize("ubar,mob", [(0.3, (0.2, 1.0)), (-0.6, (0.5, 2.0)), (0.0, (1.0, 0.5))])
+def test_mobility_linearised_mode_growth(ubar, mob):
+    """Around a constant ubar, A_M(y) = M(ubar) A to first order, so a small
+    Fourier mode evolves as delta exp(-mu t), mu = M(ubar) lam (3 ubar^2 - 1 + eps^2 lam)."""
+    n, eps, delta, tau = 20, 0.05, 1e-7, 4e-5
+    prob = O.Problem(2, n, eps, mobility=mob)
+    k = (2, 1)
+    v = fourier_mode(n, 2, k, 1.0)
+    lam = fourier_eig(prob, k)
+    M = max(mob[0] + mob[1] * (1 - ubar ** 2), 0.0)
+    mu = M * lam * (3 * ubar ** 2 - 1 + eps ** 2 * lam)
+    y1, t1, info = O.ee_step(ubar + delta * v, prob, tau, 1e-13, 30)
+    assert t1 == tau
+    np.testing.assert_allclose(y1 - ubar, delta * math.exp(-mu * tau) * v, rtol=0, atol=1e-6 * delta)
+
+
+@pytest.mark.parametrize("mob", MOBS[1:])
+def test_mobility_lambda_max_is_the_largest_matrix_free_column(mob):
+    """||Ahat_n||_1 from the assembled matrix equals the largest absolute column
+    sum of the matrix-free operator, column by column (Ahat_n e_j)."""
+    n = 7
+    prob = O.Problem(2, n, 0.15, mobility=mob)
+    y = mob_field(n, 1840)
+    y[3] = 1.7      # a spike: the largest column is near it
+    cols = []
+    for j in range(n * n):
+        e = np.zeros(n * n)
+        e[j] = 1.0
+        cols.append(np.abs(O.ahat_mv(e, y, prob)).sum())
+    assert O.lambda_max(y, prob) == pytest.approx(max(cols), rel=1e-13)
+
+
+@pytest.mark.parametrize("eyre", [False, True])
+def test_mobility_ee_step_matches_dense_expm(eyre):
+    """The EE2 step with A_M frozen at y^n is the exact solution of the frozen
+    linear problem (eq. yt) with the mobility matrices."""
+    prob = O.Problem(2, 8, 0.05, eyre, mobility=(0.2, 1.0))
+    y = uniform_field(8, 2, 0.0, 0.6, seed=1850)
+    tau = 2e-3
+    ref = brute_force_ee(y, prob, tau)
+    y1, t1, info = O.ee_step(y, prob, tau, 1e-13, 64)
+    assert t1 == tau and info.converged
+    assert O.rel_error(y1, ref) <= 1e-11
+
+
+def test_mobility_pc_estimate_leading_term():
+    """With A_M frozen at y^n (Remark 1) Ahat_n misses the derivative of A_M, so
+    the EE2 step and the trapezoidal y_PC differ by tau^2/2 B f + O(tau^3), with
+    B f = d/ds A_M(y + s f) mu at s = 0 (a central difference in y here): est
+    ||y_PC|| / (tau^2/2 ||B f||) -> 1 and halving tau divides est by 4.  With
+    constant mobility B = 0 and the ratio is 8 (third order)."""
+    n = 24
+    y = fourier_mode(n, 2, (1, 0), 0.5) + fourier_mode(n, 2, (0, 1), 0.3) + 0.1
+    for mob, ratio in (((0.1, 1.0), 4.0), ((0.7, 0.0), 8.0)):
+        prob = O.Problem(2, n, 0.08, mobility=mob)
+        f = O.rhs(y, prob)
+        mu = O.Fprime(y) + prob.eps ** 2 * O.lap(y, prob)
+        ds = 1e-6 / np.abs(f).max()
+        Bf = (O.lap_M(mu, y + ds * f, prob) - O.lap_M(mu, y - ds * f, prob)) / (2 * ds)
+        ests = []
+        for tau in (4e-7, 2e-7, 1e-7):
+            y1, t1, _ = O.ee_step(y, prob, tau, 1e-13, 60)
+            assert t1 == tau
+            est, ypc = O.pc_estimate(y, y1, tau, prob)
+            ests.append(est)
+            if ratio == 4.0:
+                lead = 0.5 * tau ** 2 * np.linalg.norm(Bf) / np.linalg.norm(ypc)
+                assert est == pytest.approx(lead, rel=0.02), (tau, est, lead)
+        r1, r2 = ests[0] / ests[1], ests[1] / ests[2]
+        assert abs(r1 - ratio) < 0.15 * ratio and abs(r2 - ratio) < 0.15 * ratio, (mob, r1, r2)
