@@ -130,6 +130,11 @@ typedef struct {
     double tau_min;         /* trace underflow threshold (>= 0) */
     int constant_step;      /* 1: constant tau with linear RT restarts (no controller) */
     int orth;               /* ch_orth (0, the zero-initialised default: CH_ORTH_DCGS2) */
+    /* DCGS2 only: > 0 issues the Arnoldi iterations of a cycle as HIP graphs of
+     * graph_chunk iterations each (1..CH_MMAX + 1), captured once per context,
+     * instance table and buffers and then replayed; 0 launches every kernel
+     * directly.  The launches and their results are the same either way. */
+    int graph_chunk;
 } ch_ee_opts;
 
 /* Per-step record (one per accepted step). */

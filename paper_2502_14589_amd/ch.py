@@ -44,7 +44,7 @@ class ChProblem(ctypes.Structure):
 
 class ChEeOpts(ctypes.Structure):
     _fields_ = [("m_max", c_int), ("tol", c_double), ("tol_phi_fixed", c_double), ("tau_min", c_double),
-                ("constant_step", c_int), ("orth", c_int)]
+                ("constant_step", c_int), ("orth", c_int), ("graph_chunk", c_int)]
 
 
 class ChStepRecord(ctypes.Structure):
@@ -204,11 +204,12 @@ class Context:
     def run_ee(self, prob: Problem, y, tau0: float, *, t0: float = 0.0, T: float = math.inf, max_steps: int = 0,
                m_max: int = 30, tol: float = 1e-4, tol_phi_fixed: float = 0.0, tau_min: float = 0.0,
                constant_step: bool = False, records: bool = False, raise_on_error: bool = True,
-               orth: int = CH_ORTH_DCGS2):
-        """Adaptive (Fig. 4) or constant-step EE2 run on y in place; returns (stats, records)."""
+               orth: int = CH_ORTH_DCGS2, graph_chunk: int = 0):
+        """Adaptive (Fig. 4) or constant-step EE2 run on y in place; returns (stats, records).
+        graph_chunk > 0 replays the DCGS2 iterations as captured HIP graphs of that many iterations."""
         _check_field(y, prob.N)
         opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), int(bool(constant_step)),
-                        int(orth))
+                        int(orth), int(graph_chunk))
         st = ChRunStats()
         recs = (ChStepRecord * max_steps)() if (records and max_steps > 0) else None
         pb = prob.c()
@@ -236,7 +237,7 @@ class Context:
     def run_ee_batch(self, fields, ns, eps, *, dim: int = 2, eyre: bool = False, precision: int = CH_FP64,
                      tau0=1e-3, T=math.inf, max_steps=50, m_max: int = 30, tol: float = 1e-4,
                      tol_phi_fixed: float = 0.0, tau_min: float = 0.0, raise_on_error: bool = True,
-                     orth: int = CH_ORTH_DCGS2):
+                     orth: int = CH_ORTH_DCGS2, graph_chunk: int = 0):
         """Adaptive EE2 on many instances at once (each field updated in place); returns per-instance stats."""
         count = len(fields)
         as_list = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * count
@@ -246,7 +247,7 @@ class Context:
             _check_field(y, ns[i] ** dim)
             items[i] = ChBatchItem(int(ns[i]), float(eps[i]), c_void_p(y.data_ptr()), float(tau0s[i]),
                                    float(Ts[i]), int(steps[i]))
-        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), 0, int(orth))
+        opts = ChEeOpts(int(m_max), float(tol), float(tol_phi_fixed), float(tau_min), 0, int(orth), int(graph_chunk))
         st = (ChRunStats * count)()
         rc = self.lib.ch_run_ee_batch(self._ptr, count, items, int(dim), int(bool(eyre)), int(precision),
                                       byref(opts), st)

@@ -54,7 +54,8 @@ struct ch_ctx {
         size_t inst_cap = 0, map_cap = 0;
         std::vector<Inst> h_inst;
     } store[2];
-    LaunchEnv env{};         // second stream for the DCGS2 phi tests
+    LaunchEnv env{};         // second stream for the DCGS2 phi tests, capture stream, graph switch
+    GraphCache graphs;       // captured DCGS2 iterations
     std::string err;
 };
 
@@ -159,6 +160,9 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         b.hseq = nullptr;
         ctx->slots = 0;
         if ((rc = alloc_dev(ctx, (void**)&b.ctl, sizeof(Ctl) * nslots))) return rc;
+        if (!b.dcount) {
+            if ((rc = alloc_dev(ctx, (void**)&b.dcount, sizeof(int)))) return rc;
+        }
         free_dev(b.lorder);
         free_dev(b.lcoef);
         b.lorder = nullptr;
@@ -175,6 +179,9 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         b.hflag = ctx->hflag;
         b.dprog = b.dflag + nslots;
         b.hprog = ctx->hflag + nslots;
+        // the device's count of update launches begun restarts with the host's count of those issued
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, hipMemset(b.dcount, 0, sizeof(int)));
         ctx->useq = 0;
         b.hseq = &ctx->useq;
         ctx->slots = nslots;
@@ -446,6 +453,8 @@ void fill_stats(const Ctl& h, ch_run_stats* st) {
 
 // Issue EE2 steps for every instance of the table until all are halted (each
 // stops at its own T or step limit) or `max_launch` steps have been issued.
+bool graph_chunk_ok(const ch_ee_opts* o) { return o->graph_chunk >= 0 && o->graph_chunk <= CH_MMAX + 1; }
+
 int issue_ee_steps(ch_ctx* ctx, const Table& t, int prec, int m_max, int orth, bool constant, long long max_launch) {
     const DevBuffers& b = ctx->b;
     PartSeq ps;
@@ -490,7 +499,7 @@ int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t
     int rc = check_problem(prob, &sh);
     if (rc) return rc;
     if (!y || !opts) return CH_EINVAL;
-    if (opts->m_max < 1 || opts->m_max > CH_MMAX || !orth_ok(opts->orth)) return CH_EINVAL;
+    if (opts->m_max < 1 || opts->m_max > CH_MMAX || !orth_ok(opts->orth) || !graph_chunk_ok(opts)) return CH_EINVAL;
     if (!(tau0 > 0.0) || !(opts->tau_min >= 0.0)) return CH_EINVAL;
     if (!(opts->tol > 0.0) && !(opts->tol_phi_fixed > 0.0)) return CH_EINVAL;
     if (max_steps <= 0 && !(T < INFINITY)) return CH_EINVAL;
@@ -508,7 +517,10 @@ int run_ee(ch_ctx* ctx, const ch_problem* prob, double* y, double tau0, double t
     HIP_TRY(ctx, hipMemcpyAsync(ctx->b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
     if ((rc = copy_in(ctx, m, y))) return rc;
     const long long limit = max_steps > 0 ? max_steps : (1LL << 40);
-    if ((rc = issue_ee_steps(ctx, t, prec, opts->m_max, opts->orth, constant, limit))) return rc;
+    ctx->env.graph_chunk = opts->graph_chunk;
+    rc = issue_ee_steps(ctx, t, prec, opts->m_max, opts->orth, constant, limit);
+    ctx->env.graph_chunk = 0;
+    if (rc) return rc;
     if ((rc = read_heads(ctx, 1))) return rc;
     if ((rc = copy_out(ctx, m, 0, y))) return rc;
     const Ctl& h = ctx->hctl[0];
@@ -525,7 +537,9 @@ int run_ee_batch(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, in
                  const ch_ee_opts* opts, ch_run_stats* stats) {
     if (count < 1 || !items || !opts) return CH_EINVAL;
     if (prec != CH_FP64 && prec != CH_FP32_MIXED) return CH_EINVAL;
-    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step || !orth_ok(opts->orth)) return CH_EINVAL;
+    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step || !orth_ok(opts->orth) ||
+        !graph_chunk_ok(opts))
+        return CH_EINVAL;
     if (!(opts->tol > 0.0) && !(opts->tol_phi_fixed > 0.0)) return CH_EINVAL;
     std::vector<Member> ms(count);
     size_t pts = 0;
@@ -552,7 +566,10 @@ int run_ee_batch(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, in
         if ((rc = copy_in(ctx, ms[i], it.y))) return rc;
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->b.ctl, ctx->hctl, sizeof(Ctl) * count, hipMemcpyHostToDevice, ctx->stream));
-    if ((rc = issue_ee_steps(ctx, t, prec, opts->m_max, opts->orth, false, limit))) return rc;
+    ctx->env.graph_chunk = opts->graph_chunk;
+    rc = issue_ee_steps(ctx, t, prec, opts->m_max, opts->orth, false, limit);
+    ctx->env.graph_chunk = 0;
+    if (rc) return rc;
     if ((rc = read_heads(ctx, count))) return rc;
     int status = CH_OK;
     for (int i = 0; i < count; ++i) {
@@ -1086,11 +1103,14 @@ int ch_create(ch_ctx** out, int device, void* hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     noalloc_setup(device);
     LaunchEnv& sd = ctx->env;
+    sd.graphs = &ctx->graphs;
     if (hipStreamCreateWithFlags(&sd.side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sd.ev_main, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&sd.ev_side, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&sd.ev_side, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&sd.cap, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
         if (sd.ev_main) (void)hipEventDestroy(sd.ev_main);
+        if (sd.ev_side) (void)hipEventDestroy(sd.ev_side);
         if (sd.side) (void)hipStreamDestroy(sd.side);
         delete ctx;
         return CH_EDEVICE;
@@ -1105,9 +1125,10 @@ int ch_destroy(ch_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipStreamSynchronize(ctx->env.side);
     DevBuffers& b = ctx->b;
+    destroy_graphs(ctx->graphs);
     for (void* p : {(void*)b.V, (void*)b.ybuf[0], (void*)b.ybuf[1], (void*)b.fcur, (void*)b.y32, (void*)b.zbuf,
                     (void*)b.part, (void*)b.dots, (void*)b.lorder, (void*)b.ctl, (void*)ctx->rec, b.phibig,
-                    (void*)b.lcoef})
+                    (void*)b.lcoef, (void*)b.dcount})
         free_dev(p);
     for (auto& ts : ctx->store)
         for (void* p : {(void*)ts.d_inst, (void*)ts.d_sb2i, (void*)ts.d_cb2i, (void*)ts.d_wb2i}) free_dev(p);
@@ -1116,6 +1137,7 @@ int ch_destroy(ch_ctx* ctx) {
     (void)hipEventDestroy(ctx->env.ev_main);
     (void)hipEventDestroy(ctx->env.ev_side);
     (void)hipStreamDestroy(ctx->env.side);
+    (void)hipStreamDestroy(ctx->env.cap);
     delete ctx;
     return CH_OK;
 }
@@ -1409,7 +1431,9 @@ int ch_server_create(int device, int prec, const ch_ee_opts* opts, size_t hbm_bu
     if (!out || !opts) return CH_EINVAL;
     *out = nullptr;
     if (prec != CH_FP64 && prec != CH_FP32_MIXED) return CH_EINVAL;
-    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step || !orth_ok(opts->orth)) return CH_EINVAL;
+    if (opts->m_max < 1 || opts->m_max > CH_MMAX || opts->constant_step || !orth_ok(opts->orth) ||
+        !graph_chunk_ok(opts))
+        return CH_EINVAL;
     if (!(opts->tol > 0.0) && !(opts->tol_phi_fixed > 0.0)) return CH_EINVAL;
     if (max_slots < 1 || max_slots > 4096) return CH_EINVAL;
     const size_t esz = prec == CH_FP64 ? 8 : 4;

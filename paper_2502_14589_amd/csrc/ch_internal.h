@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+#include <vector>
 
 
 #include "../../include/ch.h"
@@ -145,6 +146,7 @@ struct DevBuffers {
     int* dprog;         // device view of `hprog`
     const volatile int* hprog;   // pinned host word: sequence number of the last DCGS2 update launch begun
     int* hseq;          // host counter of the DCGS2 update launches issued
+    int* dcount;        // device counter of the DCGS2 update launches begun (mirrors hseq)
     void* phibig;       // per-slot device scratch of the phi of orders above 48 (phi_big_bytes each)
 };
 
@@ -226,10 +228,25 @@ hipError_t launch_phi(const Table& t, const DevBuffers& b, PartSeq& ps, int k, i
 // DCGS2 phi tests too large for the update launch (each waits for its
 // iteration's update through ev_main, then overlaps the next iterations; the
 // last test and the cycle's end wait for them through ev_side).
+// Captured Arnoldi iterations: a graph per run of iterations [k0, k1) of a
+// cycle, keyed by every value its launches take as arguments.
+struct GraphEntry {
+    std::vector<unsigned long long> key;
+    hipGraphExec_t exec;
+    int updates;            // DCGS2 update launches in the graph
+};
+struct GraphCache {
+    std::vector<GraphEntry> e;
+    size_t next = 0;        // the entry replaced when the cache is full
+};
 struct LaunchEnv {
     hipStream_t side;
     hipEvent_t ev_main, ev_side;
+    hipStream_t cap;        // capture stream (a caller's stream may be the null stream)
+    int graph_chunk;        // > 0: issue DCGS2 iterations as graphs of this many
+    GraphCache* graphs;
 };
+void destroy_graphs(GraphCache& g);
 // Arnoldi iteration k: matvec, Gram-Schmidt passes (orth: ch_orth), phi and
 // residual test.  side_used (DCGS2): set when a test went to the second
 // stream and the main stream has not yet waited for it.

@@ -16,6 +16,9 @@
 // workgroup per instance.
 #include "ch_common.h"
 
+#include <algorithm>
+#include <cstdint>
+
 #include <chrono>
 
 namespace {
@@ -349,20 +352,23 @@ __device__ __forceinline__ void dc_update_wg(DcCoef& C, Ctl* __restrict__ ctls, 
     }
 }
 
-// Progress report of an update launch: workgroup 0 writes the launch's
-// sequence number to a pinned host word as the launch begins (whatever the
-// state of its instances), so the host can keep the number of iterations it
-// has issued ahead of the device small.
-__device__ __forceinline__ void report_launch(int* dprog, int seq) {
-    if (dprog && blockIdx.x == 0 && threadIdx.x == 0) *dprog = seq;
+// Progress report of an update launch: workgroup 0 counts the launch on a
+// device counter as the launch begins (whatever the state of its instances)
+// and writes the count to a pinned host word, so the host, which counts the
+// update launches it issues, can keep the number of iterations it has issued
+// ahead of the device small.  The count lives on the device so that launches
+// replayed from a graph number themselves.
+__device__ __forceinline__ void report_launch(int* dprog, int* dcount) {
+    if (dprog && blockIdx.x == 0 && threadIdx.x == 0)
+        *dprog = __hip_atomic_fetch_add(dcount, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
 }
 
 template <typename TV, bool SINGLE, int TAG>   // TAG: as for the matvec
 __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ cb2i, const Inst inst0, int ninst,
                                                         TV* __restrict__ V, size_t ldv, int j,
-                                                        int* __restrict__ dprog, int seq) {
-    report_launch(dprog, seq);
+                                                        int* __restrict__ dprog, int* __restrict__ dcount) {
+    report_launch(dprog, dcount);
     __shared__ DcCoef C;
     dc_update_wg<TV, SINGLE, TAG>(C, ctls, insts, cb2i, inst0, blockIdx.x, V, ldv, j);
 }
@@ -1038,8 +1044,8 @@ __global__ __launch_bounds__(CH_BLOCK, 3) void k_dc_update_phi(Ctl* __restrict__
                                                             const int* __restrict__ cb2i, const Inst inst0, int ninst,
                                                             TV* __restrict__ V, size_t ldv, int j,
                                                             int* __restrict__ dflags, int* __restrict__ dprog,
-                                                            int seq) {
-    report_launch(dprog, seq);
+                                                            int* __restrict__ dcount) {
+    report_launch(dprog, dcount);
     __shared__ DcPhiLds L;
     if ((int)blockIdx.x < ninst) {
         dc_phi_wg<SINGLE>(L, ctls, insts, inst0, blockIdx.x, j, dflags);
@@ -1661,27 +1667,27 @@ template <typename TV>
 static void launch_dc_update_t(const Table& t, const DevBuffers& b, int j, bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     if (timing) {
-        hipLaunchKernelGGL((k_dc_update<TV, true, 1>), CARGS, V, b.ldv, j, nullptr, 0);
+        hipLaunchKernelGGL((k_dc_update<TV, true, 1>), CARGS, V, b.ldv, j, nullptr, nullptr);
         return;
     }
-    const int seq = b.hseq ? ++*b.hseq : 0;
+    if (b.hseq) ++*b.hseq;
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_dc_update<TV, true, 0>), CARGS, V, b.ldv, j, b.dprog, seq);
+        hipLaunchKernelGGL((k_dc_update<TV, true, 0>), CARGS, V, b.ldv, j, b.dprog, b.dcount);
     else
-        hipLaunchKernelGGL((k_dc_update<TV, false, 0>), CARGS, V, b.ldv, j, b.dprog, seq);
+        hipLaunchKernelGGL((k_dc_update<TV, false, 0>), CARGS, V, b.ldv, j, b.dprog, b.dcount);
 }
 
 template <typename TV>
 static void launch_dc_update_phi_t(const Table& t, const DevBuffers& b, int j, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     const dim3 grid(t.ninst + t.cgrid);
-    const int seq = b.hseq ? ++*b.hseq : 0;
+    if (b.hseq) ++*b.hseq;
     if (t.ninst == 1)
         hipLaunchKernelGGL((k_dc_update_phi<TV, true>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i, t.hinst[0],
-                           t.ninst, V, b.ldv, j, b.dflag, b.dprog, seq);
+                           t.ninst, V, b.ldv, j, b.dflag, b.dprog, b.dcount);
     else
         hipLaunchKernelGGL((k_dc_update_phi<TV, false>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i,
-                           t.hinst[0], t.ninst, V, b.ldv, j, b.dflag, b.dprog, seq);
+                           t.hinst[0], t.ninst, V, b.ldv, j, b.dflag, b.dprog, b.dcount);
 }
 
 hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s, bool timing,
@@ -1756,9 +1762,101 @@ static void wait_progress(const Table& t, const DevBuffers& b, const int* expect
     }
 }
 
+void destroy_graphs(GraphCache& g) {
+    for (GraphEntry& e : g.e) (void)hipGraphExecDestroy(e.exec);
+    g.e.clear();
+    g.next = 0;
+}
+
+// Every value the launches of DCGS2 iterations [k0, k1) take as arguments.
+static std::vector<unsigned long long> graph_key(const Table& t, int prec, const DevBuffers& b, const double* y,
+                                                 int m_max, int k0, int k1) {
+    std::vector<unsigned long long> k;
+    auto p = [&k](const void* q) { k.push_back((unsigned long long)(uintptr_t)q); };
+    auto v = [&k](long long x) { k.push_back((unsigned long long)x); };
+    auto d = [&k](double x) { k.push_back(__builtin_bit_cast(unsigned long long, x)); };
+    v(prec), v(m_max), v(k0), v(k1), v(t.ninst), v(t.sgrid), v(t.cgrid), v(t.wgrid), v(t.dim);
+    p(t.inst), p(t.sb2i), p(t.cb2i), p(t.wb2i);
+    p(y), p(b.V), v((long long)b.ldv), p(b.ctl), p(b.dots), p(b.dflag), p(b.dprog), p(b.dcount), p(b.y32);
+    p(b.phibig), p(b.part);
+    const Inst& I = t.hinst[0];   // passed by value to single-instance launches
+    v(I.off), v(I.N), v(I.n), v(I.slot), v(I.sblk0), v(I.sblk), v(I.cblk0), v(I.cblk), d(I.eps2), d(I.inv_h2);
+    v(I.eyre), v(I.wblk0), v(I.wblk), v(I.vx), v(I.bc), v(I.mob);
+    return k;
+}
+
+// The graph of DCGS2 iterations [k0, k1), captured on env.cap on first use.
+static hipError_t iteration_graph(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y,
+                                  int m_max, int k0, int k1, const LaunchEnv& env, hipStream_t s,
+                                  const GraphEntry** out) {
+    GraphCache& g = *env.graphs;
+    std::vector<unsigned long long> key = graph_key(t, prec, b, y, m_max, k0, k1);
+    for (const GraphEntry& e : g.e)
+        if (e.key == key) {
+            *out = &e;
+            return hipSuccess;
+        }
+    hipError_t e = hipStreamBeginCapture(env.cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const int seq0 = b.hseq ? *b.hseq : 0;
+    for (int k = k0; k < k1 && e == hipSuccess; ++k)
+        e = launch_arnoldi_iter(t, prec, b, ps, y, k, CH_ORTH_DCGS2, m_max, nullptr, env.cap);
+    const int updates = b.hseq ? *b.hseq - seq0 : 0;
+    if (b.hseq) *b.hseq = seq0;   // counted again at each replay
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(env.cap, &graph);
+    if (e == hipSuccess) e = ec;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    constexpr size_t CAP = 256;
+    GraphEntry ne{std::move(key), exec, updates};
+    if (g.e.size() < CAP) {
+        g.e.push_back(std::move(ne));
+        *out = &g.e.back();
+    } else {   // replace the oldest, once no launch of it can still be running
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            return e;
+        }
+        GraphEntry& old = g.e[g.next];
+        (void)hipGraphExecDestroy(old.exec);
+        old = std::move(ne);
+        *out = &old;
+        g.next = (g.next + 1) % CAP;
+    }
+    return hipSuccess;
+}
+
+// The DCGS2 iterations of a cycle as replayed graphs of env.graph_chunk
+// iterations, with the same lookahead as direct issue (in whole graphs).  The
+// tests of every iteration run on the main stream (no second stream).
+static hipError_t launch_arnoldi_graphs(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y,
+                                        int m_max, const int* expected, const LaunchEnv& env, hipStream_t s) {
+    const int iters = m_max + 1, C = env.graph_chunk;
+    int useq[CH_MMAX + 2];
+    for (int k0 = 0; k0 < iters; k0 += C) {
+        const int k1 = std::min(iters, k0 + C);
+        if (b.hprog && b.hseq && expected && k0 > CH_LOOKAHEAD) wait_progress(t, b, expected, useq[k0 - 1 - CH_LOOKAHEAD]);
+        if (k0 > 0 && all_cycles_done(t, b, expected)) break;
+        const GraphEntry* g = nullptr;
+        hipError_t e = iteration_graph(t, prec, b, ps, y, m_max, k0, k1, env, s, &g);
+        if (e != hipSuccess) return e;
+        if ((e = hipGraphLaunch(g->exec, s)) != hipSuccess) return e;
+        // iteration k < m_max has one update launch, in order
+        int q = b.hseq ? *b.hseq : 0;
+        for (int k = k0; k < k1; ++k) useq[k] = k < m_max ? ++q : q;
+        if (b.hseq) *b.hseq += g->updates;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_arnoldi(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y, int m_max,
                           int orth, const int* expected, const LaunchEnv* env, hipStream_t s) {
     const bool dc = orth == CH_ORTH_DCGS2;
+    if (dc && env && env->graph_chunk > 0 && env->graphs && env->cap)
+        return launch_arnoldi_graphs(t, prec, b, ps, y, m_max, expected, *env, s);
     const int iters = dc ? m_max + 1 : m_max;
     bool side_used = false;
     int useq[CH_MMAX + 2];   // sequence number of each iteration's update launch
