@@ -261,6 +261,22 @@ def batched(ctx, ch, torch, steps: int = 50, sequential_sample: int = 8):
         seq_time += time.perf_counter() - t1
         seq_steps += s1["steps"]
     seq_rate = seq_steps / seq_time
+    # the same batch with every side's launch shape tuned (ch_tune_shape)
+    shapes = {}
+    t_tune = time.perf_counter()
+    for n in sorted(set(ns)):
+        sh, best_us, default_us = ctx.tune_shape(ch.Problem(2, n, 0.02, False, ch.CH_FP32_MIXED), m_max=M_MAX)
+        shapes[n] = {"shape": sh, "iteration_us": round(best_us, 2), "default_iteration_us": round(default_us, 2)}
+    t_tune = time.perf_counter() - t_tune
+    fields = [torch.from_numpy(it.y0.copy()).to("cuda") for it in inst]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_t, rc_t = ctx.run_ee_batch(fields, ns, eps, precision=ch.CH_FP32_MIXED, tau0=TAU0, max_steps=steps,
+                                  m_max=M_MAX, tol=TOL)
+    torch.cuda.synchronize()
+    dt_t = time.perf_counter() - t0
+    for n in shapes:
+        ctx.set_shape(2, n, ch.CH_FP32_MIXED, None)
     return {"workload": "64 ragged 2-D periodic instances, sides {128,192,256,384,512}, eps log-uniform "
                         "[0.01,0.05], 50 adaptive EE2 steps each, FP32-mixed, Krylov dim 30, tol 1e-4",
             "instances": len(inst), "points": points, "instance_steps": total_steps, "seconds": round(dt, 4),
@@ -268,7 +284,39 @@ def batched(ctx, ch, torch, steps: int = 50, sequential_sample: int = 8):
             "point_steps_per_s": round(sum(n * n * x["steps"] for n, x in zip(ns, st)) / dt, 1),
             "one_at_a_time_instance_steps_per_s": round(seq_rate, 1),
             "one_at_a_time_sample": f"{len(idx)} of {len(inst)} instances",
-            "speedup_vs_one_at_a_time": round(total_steps / dt / seq_rate, 2), "status": rc}
+            "speedup_vs_one_at_a_time": round(total_steps / dt / seq_rate, 2), "status": rc,
+            "tuned": {"instance_steps_per_s": round(sum(x["steps"] for x in st_t) / dt_t, 1),
+                      "seconds": round(dt_t, 4), "tuning_seconds": round(t_tune, 3), "status": rc_t,
+                      "shapes_by_side": shapes}}
+
+
+def graph_issue(ctx, ch, torch):
+    """Adaptive EE2 (FP32-mixed, Krylov dimension 30, tol 1e-4, tau0 1e-5) from
+    y0 = 0.1 + U(-0.05, 0.05) at 128^2 (eps 0.02, 300 steps) and 1024^2 (eps
+    0.01, 100 steps), with every kernel launched directly and with each Krylov
+    cycle's iterations replayed from one captured graph (graph_chunk 31)."""
+    from paper_2502_14589_amd.inputs import uniform_field
+
+    out = {}
+    for n, eps, steps in ((128, 0.02, 300), (1024, 0.01, 100)):
+        prob = ch.Problem(2, n, eps, False, ch.CH_FP32_MIXED)
+        y0 = torch.from_numpy(uniform_field(n, 2, 0.1, 0.05, seed=1)).to("cuda")
+        res = {}
+        for chunk in (0, M_MAX + 1):
+            ctx.run_ee(prob, y0.clone(), 1e-5, max_steps=steps, m_max=M_MAX, tol=TOL, graph_chunk=chunk)   # warm
+            rates = []
+            for _ in range(2):
+                y = y0.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.run_ee(prob, y, 1e-5, max_steps=steps, m_max=M_MAX, tol=TOL, graph_chunk=chunk)
+                torch.cuda.synchronize()
+                rates.append(steps / (time.perf_counter() - t0))
+            res["graphs" if chunk else "direct"] = round(max(rates), 1)
+        res["graph_vs_direct"] = round(res["graphs"] / res["direct"], 3)
+        out[f"{n}x{n}"] = res
+    out["unit"] = "steps/s (best of two runs)"
+    return out
 
 
 def serve_trace(ch, torch, reqs, label):
@@ -509,10 +557,12 @@ def main():
             lim = lim_form(ctx, ch, torch, y0, args.steps, args.warmup)
             progress("3-D 256^3")
             c3 = c3_form(ctx, ch, torch)
-        batch = None
+        batch = graphs = None
         if not args.no_batch:
             progress("batched")
             batch = batched(ctx, ch, torch)
+            progress("graph-issued Krylov cycles")
+            graphs = graph_issue(ctx, ch, torch)
     serve = None
     if not args.no_batch:
         progress("serving")
@@ -564,6 +614,7 @@ def main():
         out["c3_3d"] = c3
     if batch is not None:
         out["batched"] = batch
+        out["graph_issue"] = graphs
     if serve is not None:
         out["serving"] = serve
     if not args.no_cpu_baseline:

@@ -362,6 +362,48 @@ enum ch_kernel {
 int ch_time_kernel(ch_ctx *ctx, const ch_problem *prob, int kernel, int m_max, const int *iters, int count,
                    double *total_us, double *total_bytes);
 
+/*
+ * Launch shape of one grid (dim, n, precision); the same for every instance of
+ * that grid in single runs, batches and served requests on the context:
+ *   vx    2-D: grid columns per lane of the row-strip kernels (1, 2, or 4 in
+ *         FP32-mixed; a divisor of n); unused in 3-D;
+ *   wblk  workgroups of the 2-D row-strip kernels or the 3-D marching matvec
+ *         (1..2048; each loops over its share of strips or x-y tiles);
+ *   cblk  workgroups of the streaming passes (DCGS2 update, state update):
+ *         1..512, each looping over chunks of 2048 points.
+ * The shape changes the order in which the partial sums of dot products are
+ * added, so results of two shapes agree to rounding, not bit for bit.  LIM runs
+ * use the shape of (dim, n, CH_FP64).
+ */
+typedef struct {
+    int vx;
+    int wblk;
+    int cblk;
+} ch_shape;
+
+/* The shape runs on this context use for (dim, n, prec): the one set or tuned
+ * last, else the built-in choice.  CH_EINVAL for an invalid grid or precision. */
+int ch_get_shape(ch_ctx *ctx, int dim, int n, int prec, ch_shape *out);
+
+/* Sets the shape of (dim, n, prec) for later runs on this context; shape NULL
+ * restores the built-in choice.  CH_EINVAL for an out-of-range shape. */
+int ch_set_shape(ch_ctx *ctx, int dim, int n, int prec, const ch_shape *shape);
+
+/*
+ * Launch-shape tuner for one grid and precision (prob->dim, n, prec) at Krylov
+ * dimension m_max (DCGS2): times the matvec with its dot products for every
+ * valid vx and workgroup counts from the built-in choice down to a quarter of
+ * it, then the update pass for streaming workgroup counts likewise, each over
+ * Arnoldi iterations 1, m_max/2 and m_max - 1 (back-to-back launches under HIP
+ * events, best of three), and keeps the fastest shape for later runs on this
+ * context (as ch_set_shape).  *best: that shape; *best_us and *default_us: the
+ * time of one matvec plus one update pass, averaged over those iterations, for
+ * it and for the built-in choice.  Allocates the workspace of such a run and
+ * overwrites its contents.
+ */
+int ch_tune_shape(ch_ctx *ctx, const ch_problem *prob, int m_max, ch_shape *best, double *best_us,
+                  double *default_us);
+
 
 #ifdef __cplusplus
 }

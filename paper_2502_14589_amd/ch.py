@@ -26,7 +26,7 @@ CH_NOALLOC_MAX_POINTS = 1 << 20
 EXPORTED = (
     "ch_create", "ch_destroy", "ch_strerror", "ch_last_error_message",
     "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_run_lim_batch", "ch_step_lim", "ch_step_lim_noalloc", "ch_phiv",
-    "ch_time_kernel",
+    "ch_time_kernel", "ch_get_shape", "ch_set_shape", "ch_tune_shape",
 
     "ch_server_create", "ch_server_destroy", "ch_submit", "ch_poll",
 )
@@ -40,6 +40,10 @@ CH_ORTH_DCGS2, CH_ORTH_MGS = 0, 1
 class ChProblem(ctypes.Structure):
     _fields_ = [("dim", c_int), ("n", c_int), ("eps", c_double), ("eyre", c_int), ("prec", c_int), ("bc", c_int),
                 ("length", c_double), ("mobility", c_int), ("mob0", c_double), ("mob1", c_double)]
+
+
+class ChShape(ctypes.Structure):
+    _fields_ = [("vx", c_int), ("wblk", c_int), ("cblk", c_int)]
 
 
 class ChEeOpts(ctypes.Structure):
@@ -118,9 +122,12 @@ def load_library(path: str = LIB_PATH):
     lib.ch_submit.argtypes = [c_void_p, P(ChRequest), P(ctypes.c_ulonglong)]
     lib.ch_poll.argtypes = [c_void_p, ctypes.c_ulonglong, P(c_int), c_void_p, P(ChRunStats), P(c_double)]
     lib.ch_time_kernel.argtypes = [c_void_p, P(ChProblem), c_int, c_int, P(c_int), c_int, P(c_double), P(c_double)]
+    lib.ch_get_shape.argtypes = [c_void_p, c_int, c_int, c_int, P(ChShape)]
+    lib.ch_set_shape.argtypes = [c_void_p, c_int, c_int, c_int, P(ChShape)]
+    lib.ch_tune_shape.argtypes = [c_void_p, P(ChProblem), c_int, P(ChShape), P(c_double), P(c_double)]
     for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_run_lim_batch",
                  "ch_step_lim", "ch_step_lim_noalloc", "ch_phiv", "ch_time_kernel", "ch_server_create", "ch_server_destroy", "ch_submit",
-                 "ch_poll"):
+                 "ch_poll", "ch_get_shape", "ch_set_shape", "ch_tune_shape"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -336,6 +343,26 @@ class Context:
         rc = self.lib.ch_time_kernel(self._ptr, byref(pb), int(kernel), int(m_max), arr, n, byref(us), byref(by))
         self._raise(rc, "ch_time_kernel")
         return us.value, by.value
+
+    # -- launch shapes -------------------------------------------------------
+    def get_shape(self, dim: int, n: int, precision: int = CH_FP64) -> dict:
+        """The launch shape runs use for this grid: {'vx', 'wblk', 'cblk'}."""
+        out = ChShape()
+        self._raise(self.lib.ch_get_shape(self._ptr, int(dim), int(n), int(precision), byref(out)), "ch_get_shape")
+        return {"vx": out.vx, "wblk": out.wblk, "cblk": out.cblk}
+
+    def set_shape(self, dim: int, n: int, precision: int = CH_FP64, shape: dict | None = None):
+        """Sets (or with None clears) the launch shape of this grid for later runs."""
+        ptr = byref(ChShape(int(shape["vx"]), int(shape["wblk"]), int(shape["cblk"]))) if shape is not None else None
+        self._raise(self.lib.ch_set_shape(self._ptr, int(dim), int(n), int(precision), ptr), "ch_set_shape")
+
+    def tune_shape(self, prob: Problem, m_max: int = 30):
+        """Times candidate launch shapes and keeps the fastest: (shape, best_us, default_us)."""
+        out, b, d = ChShape(), c_double(), c_double()
+        pb = prob.c()
+        self._raise(self.lib.ch_tune_shape(self._ptr, byref(pb), int(m_max), byref(out), byref(b), byref(d)),
+                    "ch_tune_shape")
+        return {"vx": out.vx, "wblk": out.wblk, "cblk": out.cblk}, b.value, d.value
 
 
 class Server:

@@ -56,6 +56,11 @@ struct ch_ctx {
     } store[2];
     LaunchEnv env{};         // second stream for the DCGS2 phi tests, capture stream, graph switch
     GraphCache graphs;       // captured DCGS2 iterations
+    struct ShapeEntry {      // launch shapes set or tuned for (dim, n, prec)
+        int dim, n, prec;
+        ch_shape s;
+    };
+    std::vector<ShapeEntry> shapes;
     std::string err;
 };
 
@@ -315,6 +320,34 @@ Inst make_inst(const Member& m, int i, int dim, int prec, int sblk0, int cblk0, 
     return I;
 }
 
+// The built-in launch shape of one grid.
+ch_shape default_shape(int dim, int n, int prec) {
+    long long N = (long long)n * n;
+    if (dim == 3) N *= n;
+    int sblk, cblk;
+    inst_blocks(dim, n, N, &sblk, &cblk);
+    ch_shape s;
+    s.vx = strip_vx(n, prec);
+    s.wblk = wide_blocks(dim, n, prec);
+    s.cblk = cblk;
+    return s;
+}
+
+bool shape_ok(int dim, int n, int prec, const ch_shape& s) {
+    if (s.wblk < 1 || s.wblk > CH_WBLK_MAX || s.cblk < 1 || s.cblk > CH_CBLK_MAX) return false;
+    if (dim == 2) {
+        const int maxvx = prec == CH_FP64 ? 2 : 4;
+        if (s.vx < 1 || s.vx > maxvx || (s.vx & (s.vx - 1)) || n % s.vx) return false;
+    }
+    return true;
+}
+
+const ch_shape* find_shape(const ch_ctx* ctx, int dim, int n, int prec) {
+    for (const auto& e : ctx->shapes)
+        if (e.dim == dim && e.n == n && e.prec == prec) return &e.s;
+    return nullptr;
+}
+
 // Workgroup ranges of each instance and the block-to-instance maps, kept in
 // table store `which` of the context.
 int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, int prec, Table* t, int which = 0) {
@@ -325,6 +358,11 @@ int build_table(ch_ctx* ctx, const std::vector<Member>& ms, int dim, int prec, T
     for (int i = 0; i < ni; ++i) {
         Inst& I = ts.h_inst[i];
         I = make_inst(ms[i], i, dim, prec, (int)sb.size(), (int)cb.size(), (int)wb.size());
+        if (const ch_shape* sp = find_shape(ctx, dim, ms[i].sh.n, prec)) {
+            I.vx = sp->vx;
+            I.wblk = sp->wblk;
+            I.cblk = sp->cblk;
+        }
         sb.insert(sb.end(), I.sblk, i);
         cb.insert(cb.end(), I.cblk, i);
         wb.insert(wb.end(), I.wblk, i);
@@ -1309,6 +1347,9 @@ int ch_phiv(ch_ctx* ctx, const ch_problem* prob, const double* y, double* y_out,
     return h.status;
 }
 
+static int time_kernel_core(ch_ctx* ctx, const Shape& sh, const ch_problem* prob, int kernel, int m_max,
+                            const int* iters, int count, double* total_us, double* total_bytes);
+
 int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, const int* iters, int count,
                    double* total_us, double* total_bytes) {
     const bool lim = kernel == CH_KERNEL_LIM_STAGE || kernel == CH_KERNEL_LIM_STAGE2;
@@ -1327,6 +1368,17 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, c
             : (ctx->v_bytes < (size_t)(m_max + 1) * b.ldv * esz ||
                (prec == CH_FP32_MIXED && ctx->y32_pts < (size_t)sh.N)))
         return CH_EINVAL;
+    return time_kernel_core(ctx, sh, prob, kernel, m_max, iters, count, total_us, total_bytes);
+}
+
+// ch_time_kernel after its checks: the workspace holds this problem.
+static int time_kernel_core(ch_ctx* ctx, const Shape& sh, const ch_problem* prob, int kernel, int m_max,
+                            const int* iters, int count, double* total_us, double* total_bytes) {
+    const bool lim = kernel == CH_KERNEL_LIM_STAGE || kernel == CH_KERNEL_LIM_STAGE2;
+    const int prec = lim ? CH_FP64 : prob->prec;
+    const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
+    const DevBuffers& b = ctx->b;
+    int rc;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl, b.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     Ctl& h = ctx->hctl[0];
@@ -1423,6 +1475,142 @@ int ch_time_kernel(ch_ctx* ctx, const ch_problem* prob, int kernel, int m_max, c
     HIP_TRY(ctx, err);
     *total_us = 1000.0 * ms;
     *total_bytes = bytes;
+    return CH_OK;
+}
+
+static bool grid_ok(int dim, int n, int prec) {
+    return (dim == 2 || dim == 3) && n >= 5 && (prec == CH_FP64 || prec == CH_FP32_MIXED);
+}
+
+static void put_shape(ch_ctx* ctx, int dim, int n, int prec, const ch_shape& s) {
+    for (auto& e : ctx->shapes)
+        if (e.dim == dim && e.n == n && e.prec == prec) {
+            e.s = s;
+            return;
+        }
+    ctx->shapes.push_back({dim, n, prec, s});
+}
+
+static void drop_shape(ch_ctx* ctx, int dim, int n, int prec) {
+    auto& v = ctx->shapes;
+    for (size_t i = 0; i < v.size(); ++i)
+        if (v[i].dim == dim && v[i].n == n && v[i].prec == prec) {
+            v.erase(v.begin() + (long)i);
+            return;
+        }
+}
+
+int ch_get_shape(ch_ctx* ctx, int dim, int n, int prec, ch_shape* out) {
+    if (!ctx || !out || !grid_ok(dim, n, prec)) return CH_EINVAL;
+    const ch_shape* s = find_shape(ctx, dim, n, prec);
+    *out = s ? *s : default_shape(dim, n, prec);
+    return CH_OK;
+}
+
+int ch_set_shape(ch_ctx* ctx, int dim, int n, int prec, const ch_shape* shape) {
+    if (!ctx || !grid_ok(dim, n, prec)) return CH_EINVAL;
+    if (!shape) {
+        drop_shape(ctx, dim, n, prec);
+        return CH_OK;
+    }
+    if (!shape_ok(dim, n, prec, *shape)) return CH_EINVAL;
+    put_shape(ctx, dim, n, prec, *shape);
+    return CH_OK;
+}
+
+int ch_tune_shape(ch_ctx* ctx, const ch_problem* prob, int m_max, ch_shape* best, double* best_us,
+                  double* default_us) {
+    if (!ctx || !best || !best_us || !default_us) return CH_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
+    Shape sh;
+    int rc = check_problem(prob, &sh);
+    if (rc) return rc;
+    if (m_max < 2 || m_max > CH_MMAX) return CH_EINVAL;
+    const int prec = prob->prec, dim = sh.dim, n = sh.n;
+    if ((rc = ensure(ctx, pad64(sh.N), m_max, prec, 1, 0, false))) return rc;
+    // the workspace of a run: zero fields and a live control block
+    const DevBuffers& b = ctx->b;
+    const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
+    HIP_TRY(ctx, hipMemsetAsync(b.V, 0, (size_t)(m_max + 1) * b.ldv * esz, ctx->stream));
+    HIP_TRY(ctx, hipMemsetAsync(b.ybuf[0], 0, sizeof(double) * sh.N, ctx->stream));
+    if (prec == CH_FP32_MIXED) HIP_TRY(ctx, hipMemsetAsync(b.y32, 0, sizeof(float) * sh.N, ctx->stream));
+    init_ctl(ctx->hctl, MODE_EE, 0.0, 1e-6, INFINITY, 1e-4, 0.0, 0.0, m_max, 0, nullptr, 0, ctx->expect[0]);
+    HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+    const ch_shape* prev = find_shape(ctx, dim, n, prec);
+    const bool had = prev != nullptr;
+    const ch_shape saved = had ? *prev : default_shape(dim, n, prec);
+    const ch_shape dflt = default_shape(dim, n, prec);
+    // per-iteration time of `kernel` with shape s: iterations 1, m_max/2,
+    // m_max - 1 five times over, best of three sequences
+    auto timed = [&](const ch_shape& s, int kernel, double* us) -> int {
+        put_shape(ctx, dim, n, prec, s);
+        const int its[3] = {1, m_max / 2, m_max - 1};
+        int seq[15];
+        for (int i = 0; i < 15; ++i) seq[i] = its[i % 3];
+        double bt = INFINITY;
+        for (int trial = 0; trial < 3; ++trial) {
+            double t_us = 0.0, bytes = 0.0;
+            const int r = time_kernel_core(ctx, sh, prob, kernel, m_max, seq, 15, &t_us, &bytes);
+            if (r) return r;
+            bt = std::min(bt, t_us / 15.0);
+        }
+        *us = bt;
+        return CH_OK;
+    };
+    auto counts = [](int d) {   // d, 3d/4, d/2, d/4 (distinct, >= 1)
+        std::vector<int> v;
+        for (int c : {d, (3 * d) / 4, d / 2, d / 4})
+            if (c >= 1 && std::find(v.begin(), v.end(), c) == v.end()) v.push_back(c);
+        return v;
+    };
+    auto restore = [&]() {
+        if (had) put_shape(ctx, dim, n, prec, saved);
+        else drop_shape(ctx, dim, n, prec);
+    };
+    std::vector<int> vxs;
+    if (dim == 2) {
+        for (int vx : {1, 2, 4})
+            if (shape_ok(dim, n, prec, ch_shape{vx, 1, 1})) vxs.push_back(vx);
+    } else {
+        vxs.push_back(dflt.vx);
+    }
+    ch_shape bs = dflt;
+    double bmv = INFINITY, dmv = INFINITY;
+    for (int vx : vxs) {
+        const int w0 = dim == 2 ? strip_blocks(n, vx) : dflt.wblk;
+        for (int w : counts(w0)) {
+            const ch_shape c{vx, w, dflt.cblk};
+            double us;
+            if ((rc = timed(c, CH_KERNEL_DC_MATVEC, &us))) {
+                restore();
+                return rc;
+            }
+            if (vx == dflt.vx && w == dflt.wblk) dmv = us;
+            if (us < bmv) {
+                bmv = us;
+                bs = c;
+            }
+        }
+    }
+    double bup = INFINITY, dup = INFINITY;
+    int bc = dflt.cblk;
+    for (int c : counts(dflt.cblk)) {
+        double us;
+        if ((rc = timed(ch_shape{bs.vx, bs.wblk, c}, CH_KERNEL_DC_UPDATE, &us))) {
+            restore();
+            return rc;
+        }
+        if (c == dflt.cblk) dup = us;
+        if (us < bup) {
+            bup = us;
+            bc = c;
+        }
+    }
+    bs.cblk = bc;
+    put_shape(ctx, dim, n, prec, bs);
+    *best = bs;
+    *best_us = bmv + bup;
+    *default_us = dmv + dup;
     return CH_OK;
 }
 

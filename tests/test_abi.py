@@ -42,7 +42,8 @@ def test_struct_layouts_match_header(tmp_path):
     if not shutil.which("gcc"):
         pytest.skip("gcc not available")
     structs = {"ch_problem": ch.ChProblem, "ch_ee_opts": ch.ChEeOpts, "ch_step_record": ch.ChStepRecord,
-               "ch_run_stats": ch.ChRunStats, "ch_batch_item": ch.ChBatchItem, "ch_request": ch.ChRequest}
+               "ch_run_stats": ch.ChRunStats, "ch_batch_item": ch.ChBatchItem, "ch_request": ch.ChRequest,
+               "ch_shape": ch.ChShape}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ch.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
