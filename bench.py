@@ -27,8 +27,9 @@ the FP64 NumPy/SciPy oracle on the first steps of the same workload.
     python bench.py --copy-calibration     (plain copy of known size, for the
                                             hardware-counter scale)
     python bench.py --counters             (FP32-mixed run to T, then the
-                                            replay of its dominant kernel alone
-                                            inside a profiler region)
+                                            replay of its dominant kernel, under
+                                            a symbol of its own that a profiler's
+                                            kernel filter selects)
 """
 from __future__ import annotations
 
@@ -97,34 +98,8 @@ def replay(ctx, prob, kernel, m_max, iters=None, count=0):
             "bytes_per_launch": nbytes / n, "achieved_GBps": nbytes / (us * 1e-6) / 1e9 if us > 0 else 0.0}
 
 
-class ProfilerRegion:
-    """roctxProfilerPause / roctxProfilerResume when the roctx library is
-    present: under `rocprofv3 --selected-regions` only the resumed parts of the
-    process are recorded (the replay, not the 1.5M launches of the run)."""
-
-    def __init__(self, enabled: bool):
-        self.lib = None
-        if enabled:
-            import ctypes
-
-            for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so", "libroctx64.so"):
-                try:
-                    self.lib = ctypes.CDLL(name)
-                    break
-                except OSError:
-                    continue
-
-    def pause(self):
-        if self.lib is not None:
-            self.lib.roctxProfilerPause(0)
-
-    def resume(self):
-        if self.lib is not None:
-            self.lib.roctxProfilerResume(0)
-
-
 def run_ee_form(ctx, ch, torch, prob, y0, tau0, T, warmup, m_max, tol, fp32, N, max_steps=MAX_STEPS,
-                replay_every=REPLAY_EVERY, region=None):
+                replay_every=REPLAY_EVERY):
     """W warm-up steps (a throw-away run from y0: allocations, code objects),
     then the timed run from y0 until t = T (or max_steps), then back-to-back
     launches of the DCGS2 kernels over the Arnoldi iterations of every
@@ -144,11 +119,7 @@ def run_ee_form(ctx, ch, torch, prob, y0, tau0, T, warmup, m_max, tol, fp32, N, 
     sample = recs[::replay_every]
     mv, up, phi = dc_iters(sample, m_max)
     last_j = recs[-1]["j"] if recs else 0
-    if region is not None:
-        region.resume()
     kern = {"dc_matvec": replay(ctx, prob, ch.CH_KERNEL_DC_MATVEC, m_max, mv)}
-    if region is not None:
-        region.pause()
     kern["dc_update"] = replay(ctx, prob, ch.CH_KERNEL_DC_UPDATE, m_max, up)
     phi = [k for k in phi if k <= last_j]
     if phi:
@@ -163,6 +134,7 @@ def run_ee_form(ctx, ch, torch, prob, y0, tau0, T, warmup, m_max, tol, fp32, N, 
         "matvecs_per_s": st["matvecs"] / dt, "sim_time_per_s": st["t"] / dt,
         "effective_GBps": nbytes / dt / 1e9, "kernels": kern,
         "replayed_steps": f"every {replay_every}th step of the timed run ({len(sample)} steps)",
+        "replay_plan": {"dc_matvec": mv},
     }, y
 
 
@@ -495,7 +467,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--counters", action="store_true",
-                    help="FP32-mixed run to T, then the replay of its dominant kernel inside a profiler region")
+                    help="FP32-mixed run to T, then the replay of its dominant kernel (its own symbol)")
+    ap.add_argument("--plan-out", help="--counters: write the replay's Arnoldi iterations to this file")
+    ap.add_argument("--plan-in", help="--counters: skip the run to T and replay the iterations of this file "
+                                      "(a counter run then sees only one warm step and the replay)")
     ap.add_argument("--only-3d", action="store_true", help="the 256^3 forms alone (profiling runs)")
     ap.add_argument("--only-lim", action="store_true", help="the adaptive LIM form alone (profiling runs)")
     args = ap.parse_args()
@@ -522,15 +497,25 @@ def main():
                 f"(Fig. 4) tol=1e-4, Krylov dim 30, tau0=1e-3, whole run from y0 to T={T:g}")
     if args.counters:
         # the FP32-mixed run to T; the replay of its dominant kernel runs under
-        # a symbol of its own and alone inside the profiler region
-        region = ProfilerRegion(True)
-        region.pause()
+        # a symbol of its own, which a counter run selects by name
+        prob = ch.Problem(2, N_SIDE, EPS, False, ch.CH_FP32_MIXED)
         with ch.Context(0) as ctx:
-            f, _ = run_ee_form(ctx, ch, torch, ch.Problem(2, N_SIDE, EPS, False, ch.CH_FP32_MIXED), y0, TAU0, T,
-                               args.warmup, M_MAX, TOL, True, N, region=region)
+            if args.plan_in:
+                with open(args.plan_in) as fh:
+                    plan = json.load(fh)
+                # one step sets up the workspace the replay runs on
+                ctx.run_ee(prob, torch.from_numpy(y0.copy()).to("cuda"), TAU0, T=T, max_steps=1, m_max=M_MAX,
+                           tol=TOL)
+                rep_mv = replay(ctx, prob, ch.CH_KERNEL_DC_MATVEC, M_MAX, plan["dc_matvec"])
+                replayed = plan["replayed"]
+            else:
+                f, _ = run_ee_form(ctx, ch, torch, prob, y0, TAU0, T, args.warmup, M_MAX, TOL, True, N)
+                rep_mv, replayed = f["kernels"]["dc_matvec"], f["replayed_steps"]
+                if args.plan_out:
+                    with open(args.plan_out, "w") as fh:
+                        json.dump({"dc_matvec": f["replay_plan"]["dc_matvec"], "replayed": replayed}, fh)
         print(json.dumps({"mode": "counters", "kernel": DOMINANT, "source_sha": kernel_source_sha(),
-                          "workload": workload, "replayed": f["replayed_steps"],
-                          "replay": f["kernels"]["dc_matvec"]}), flush=True)
+                          "workload": workload, "replayed": replayed, "replay": rep_mv}), flush=True)
         return
     if args.only_3d:
         with ch.Context(0) as ctx:
