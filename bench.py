@@ -233,12 +233,9 @@ def batched(ctx, ch, torch, steps: int = 50, sequential_sample: int = 8):
         seq_time += time.perf_counter() - t1
         seq_steps += s1["steps"]
     seq_rate = seq_steps / seq_time
-    # the same batch with every side's launch shape tuned (ch_tune_shape)
-    shapes = {}
+    # the same batch with its launch shapes tuned together (ch_tune_batch_shapes)
     t_tune = time.perf_counter()
-    for n in sorted(set(ns)):
-        sh, best_us, default_us = ctx.tune_shape(ch.Problem(2, n, 0.02, False, ch.CH_FP32_MIXED), m_max=M_MAX)
-        shapes[n] = {"shape": sh, "iteration_us": round(best_us, 2), "default_iteration_us": round(default_us, 2)}
+    shapes, best_us, default_us = ctx.tune_batch_shapes(ns, eps, precision=ch.CH_FP32_MIXED, m_max=M_MAX)
     t_tune = time.perf_counter() - t_tune
     fields = [torch.from_numpy(it.y0.copy()).to("cuda") for it in inst]
     torch.cuda.synchronize()
@@ -259,7 +256,8 @@ def batched(ctx, ch, torch, steps: int = 50, sequential_sample: int = 8):
             "speedup_vs_one_at_a_time": round(total_steps / dt / seq_rate, 2), "status": rc,
             "tuned": {"instance_steps_per_s": round(sum(x["steps"] for x in st_t) / dt_t, 1),
                       "seconds": round(dt_t, 4), "tuning_seconds": round(t_tune, 3), "status": rc_t,
-                      "shapes_by_side": shapes}}
+                      "shapes_by_side": shapes, "batched_iteration_us": round(best_us, 2),
+                      "default_batched_iteration_us": round(default_us, 2)}}
 
 
 def graph_issue(ctx, ch, torch):

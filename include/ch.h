@@ -404,6 +404,22 @@ int ch_set_shape(ch_ctx *ctx, int dim, int n, int prec, const ch_shape *shape);
 int ch_tune_shape(ch_ctx *ctx, const ch_problem *prob, int m_max, ch_shape *best, double *best_us,
                   double *default_us);
 
+/*
+ * Launch-shape tuner for a batch (ch_run_ee_batch): the grids of items[0..count)
+ * (n and eps are read; y, tau0, T and max_steps are not), all in precision
+ * prec, timed together as ch_run_ee_batch launches them, one DCGS2 iteration
+ * (matvec, dot totals, update pass) over all instances at Arnoldi iterations 1,
+ * m_max/2 and m_max - 1 (best of three).  Starting from the built-in shapes, it
+ * visits each distinct n, largest total size first, tries for it the candidate
+ * shapes of ch_tune_shape with the others fixed, and keeps a change when the
+ * whole batch's iteration gets at least 0.5% faster.  The chosen shapes are
+ * kept for later runs on this context.  *best_us and *default_us: one batched
+ * iteration with them and with the built-in shapes.  Allocates the workspace
+ * of such a batch and overwrites its contents.
+ */
+int ch_tune_batch_shapes(ch_ctx *ctx, int count, const ch_batch_item *items, int dim, int eyre, int prec, int m_max,
+                         double *best_us, double *default_us);
+
 
 #ifdef __cplusplus
 }

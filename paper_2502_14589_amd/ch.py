@@ -26,7 +26,7 @@ CH_NOALLOC_MAX_POINTS = 1 << 20
 EXPORTED = (
     "ch_create", "ch_destroy", "ch_strerror", "ch_last_error_message",
     "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_run_lim_batch", "ch_step_lim", "ch_step_lim_noalloc", "ch_phiv",
-    "ch_time_kernel", "ch_get_shape", "ch_set_shape", "ch_tune_shape",
+    "ch_time_kernel", "ch_get_shape", "ch_set_shape", "ch_tune_shape", "ch_tune_batch_shapes",
 
     "ch_server_create", "ch_server_destroy", "ch_submit", "ch_poll",
 )
@@ -125,9 +125,11 @@ def load_library(path: str = LIB_PATH):
     lib.ch_get_shape.argtypes = [c_void_p, c_int, c_int, c_int, P(ChShape)]
     lib.ch_set_shape.argtypes = [c_void_p, c_int, c_int, c_int, P(ChShape)]
     lib.ch_tune_shape.argtypes = [c_void_p, P(ChProblem), c_int, P(ChShape), P(c_double), P(c_double)]
+    lib.ch_tune_batch_shapes.argtypes = [c_void_p, c_int, P(ChBatchItem), c_int, c_int, c_int, c_int, P(c_double),
+                                         P(c_double)]
     for name in ("ch_create", "ch_destroy", "ch_run_ee", "ch_step_ee", "ch_run_ee_batch", "ch_run_lim", "ch_run_lim_batch",
                  "ch_step_lim", "ch_step_lim_noalloc", "ch_phiv", "ch_time_kernel", "ch_server_create", "ch_server_destroy", "ch_submit",
-                 "ch_poll", "ch_get_shape", "ch_set_shape", "ch_tune_shape"):
+                 "ch_poll", "ch_get_shape", "ch_set_shape", "ch_tune_shape", "ch_tune_batch_shapes"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -363,6 +365,18 @@ class Context:
         self._raise(self.lib.ch_tune_shape(self._ptr, byref(pb), int(m_max), byref(out), byref(b), byref(d)),
                     "ch_tune_shape")
         return {"vx": out.vx, "wblk": out.wblk, "cblk": out.cblk}, b.value, d.value
+
+    def tune_batch_shapes(self, ns, eps, *, dim: int = 2, eyre: bool = False, precision: int = CH_FP64,
+                          m_max: int = 30):
+        """Tunes the launch shapes of a batch's grids together: (shapes by n, best_us, default_us)."""
+        count = len(ns)
+        items = (ChBatchItem * count)()
+        for i in range(count):
+            items[i] = ChBatchItem(int(ns[i]), float(eps[i]), None, 1.0, 1.0, 1)
+        b, d = c_double(), c_double()
+        self._raise(self.lib.ch_tune_batch_shapes(self._ptr, count, items, int(dim), int(bool(eyre)), int(precision),
+                                                  int(m_max), byref(b), byref(d)), "ch_tune_batch_shapes")
+        return {n: self.get_shape(dim, n, precision) for n in sorted(set(int(x) for x in ns))}, b.value, d.value
 
 
 class Server:

@@ -1614,6 +1614,124 @@ int ch_tune_shape(ch_ctx* ctx, const ch_problem* prob, int m_max, ch_shape* best
     return CH_OK;
 }
 
+int ch_tune_batch_shapes(ch_ctx* ctx, int count, const ch_batch_item* items, int dim, int eyre, int prec, int m_max,
+                         double* best_us, double* default_us) {
+    if (!ctx || count < 1 || !items || !best_us || !default_us) return CH_EINVAL;
+    if (prec != CH_FP64 && prec != CH_FP32_MIXED) return CH_EINVAL;
+    if (m_max < 2 || m_max > CH_MMAX) return CH_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return CH_EDEVICE;
+    std::vector<Member> ms(count);
+    size_t pts = 0;
+    for (int i = 0; i < count; ++i) {
+        const int rc = check_grid(dim, items[i].n, items[i].eps, eyre, &ms[i].sh);
+        if (rc) return rc;
+        ms[i].eps = items[i].eps;
+        ms[i].eyre = eyre;
+        ms[i].off = pts;
+        pts += pad64(ms[i].sh.N);
+    }
+    int rc;
+    if ((rc = ensure(ctx, pts, m_max, prec, count, 0, false))) return rc;
+    const DevBuffers& b = ctx->b;
+    const size_t esz = prec == CH_FP64 ? sizeof(double) : sizeof(float);
+    HIP_TRY(ctx, hipMemsetAsync(b.V, 0, (size_t)(m_max + 1) * b.ldv * esz, ctx->stream));
+    HIP_TRY(ctx, hipMemsetAsync(b.ybuf[0], 0, sizeof(double) * pts, ctx->stream));
+    if (prec == CH_FP32_MIXED) HIP_TRY(ctx, hipMemsetAsync(b.y32, 0, sizeof(float) * pts, ctx->stream));
+    HIP_TRY(ctx, hipMemsetAsync(b.part, 0, 2 * sizeof(double) * CH_NRED * CH_MAXB, ctx->stream));
+    for (int i = 0; i < count; ++i)
+        init_ctl(ctx->hctl + i, MODE_EE, 0.0, 1e-6, INFINITY, 1e-4, 0.0, 0.0, m_max, 0, nullptr, 0, ctx->expect[i]);
+    HIP_TRY(ctx, hipMemcpyAsync(b.ctl, ctx->hctl, sizeof(Ctl) * count, hipMemcpyHostToDevice, ctx->stream));
+    // distinct sides, largest total size first
+    std::vector<std::pair<long long, int>> sides;
+    for (const Member& m : ms) {
+        auto it = std::find_if(sides.begin(), sides.end(), [&](const auto& e) { return e.second == m.sh.n; });
+        if (it == sides.end()) sides.push_back({m.sh.N, m.sh.n});
+        else it->first += m.sh.N;
+    }
+    std::sort(sides.begin(), sides.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+    for (const auto& e : sides) drop_shape(ctx, dim, e.second, prec);   // start from the built-in shapes
+    // one batched DCGS2 iteration: iterations 1, m/2, m - 1 five times over, best of three sequences
+    auto timed = [&](double* us) -> int {
+        Table t;
+        int r = build_table(ctx, ms, dim, prec, &t);
+        if (r) return r;
+        PartSeq ps;
+        ps.base = b.part;
+        const int its[3] = {1, m_max / 2, m_max - 1};
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        float ms_ = 0.f;
+        double bt = INFINITY;
+        auto seq = [&]() -> hipError_t {
+            hipError_t e;
+            if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) return e;
+            for (int trial = 0; trial < 4; ++trial) {   // the first is a warm sequence
+                if ((e = hipEventRecord(e0, ctx->stream)) != hipSuccess) return e;
+                for (int q = 0; q < 15; ++q) {
+                    const int k = its[q % 3];
+                    if ((e = launch_matvec(t, prec, b, ps, b.ybuf[0], k, MV_DOTS_DC, true, ctx->stream)) != hipSuccess)
+                        return e;
+                    if ((e = launch_dots_reduce(t, b, k, ctx->stream)) != hipSuccess) return e;
+                    if ((e = launch_dc_update(t, prec, b, k, ctx->stream, false, false)) != hipSuccess) return e;
+                }
+                if ((e = hipEventRecord(e1, ctx->stream)) != hipSuccess) return e;
+                if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+                if ((e = hipEventElapsedTime(&ms_, e0, e1)) != hipSuccess) return e;
+                if (trial > 0) bt = std::min(bt, 1000.0 * ms_ / 15.0);
+            }
+            return hipSuccess;
+        };
+        const hipError_t err = seq();
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        HIP_TRY(ctx, err);
+        *us = bt;
+        return CH_OK;
+    };
+    auto counts = [](int d) {
+        std::vector<int> v;
+        for (int c : {d, (3 * d) / 4, d / 2, d / 4})
+            if (c >= 1 && std::find(v.begin(), v.end(), c) == v.end()) v.push_back(c);
+        return v;
+    };
+    double cur;
+    if ((rc = timed(&cur))) return rc;
+    const double dflt_us = cur;
+    for (const auto& e : sides) {
+        const int n = e.second;
+        ch_shape bs = default_shape(dim, n, prec);
+        auto try_shape = [&](const ch_shape& c) -> int {
+            put_shape(ctx, dim, n, prec, c);
+            double us;
+            const int r = timed(&us);
+            if (r) return r;
+            if (us < 0.995 * cur) {
+                cur = us;
+                bs = c;
+            }
+            put_shape(ctx, dim, n, prec, bs);
+            return CH_OK;
+        };
+        const ch_shape d = bs;
+        for (int vx : {1, 2, 4}) {
+            if (dim == 3 && vx != d.vx) continue;
+            if (!shape_ok(dim, n, prec, ch_shape{vx, 1, 1})) continue;
+            const int w0 = dim == 2 ? strip_blocks(n, vx) : d.wblk;
+            for (int w : counts(w0)) {
+                if (vx == d.vx && w == d.wblk) continue;
+                if ((rc = try_shape(ch_shape{vx, w, bs.cblk}))) return rc;
+            }
+        }
+        for (int c : counts(d.cblk)) {
+            if (c == bs.cblk) continue;
+            if ((rc = try_shape(ch_shape{bs.vx, bs.wblk, c}))) return rc;
+        }
+        if (bs.vx == d.vx && bs.wblk == d.wblk && bs.cblk == d.cblk) drop_shape(ctx, dim, n, prec);
+    }
+    *best_us = cur;
+    *default_us = dflt_us;
+    return CH_OK;
+}
+
 int ch_server_create(int device, int prec, const ch_ee_opts* opts, size_t hbm_budget, int max_slots,
                      ch_server** out) {
     if (!out || !opts) return CH_EINVAL;

@@ -1,5 +1,5 @@
-"""Launch shapes per grid (ch_set_shape / ch_get_shape) and the shape tuner
-(ch_tune_shape).
+"""Launch shapes per grid (ch_set_shape / ch_get_shape) and the shape tuners
+(ch_tune_shape for one grid, ch_tune_batch_shapes for a batch's grids together).
 
 A shape only changes how the work of a launch is split over workgroups (and so
 the order in which partial dot products are added): runs under unusual shapes
@@ -136,3 +136,24 @@ def test_tuner_keeps_the_fastest_shape(ctx, dim, n, prec):
     st, recs = ctx.run_ee(prob, yg, 1e-5, max_steps=2, m_max=30, records=True)
     tol = TOL_FP64 if prec == ch.CH_FP64 else 1e-5
     assert rel(yg.cpu().numpy(), y_ref) <= tol
+
+
+def test_batch_tuner_keeps_shapes_that_speed_up_the_batch(ctx):
+    """The batch tuner starts from the built-in shapes and keeps only changes
+    that make the batched iteration faster; the batch then still equals its
+    members' solo runs bit for bit and matches the oracle."""
+    ns = [64, 96, 128, 96, 64, 128]
+    eps = [0.03, 0.02, 0.02, 0.04, 0.05, 0.03]
+    shapes, best_us, default_us = ctx.tune_batch_shapes(ns, eps, precision=ch.CH_FP64, m_max=20)
+    assert 0.0 < best_us <= default_us
+    assert set(shapes) == {64, 96, 128}
+    y0s = [uniform_field(n, 2, 0.1, 0.05, seed=7700 + i) for i, n in enumerate(ns)]
+    fields = [dev(y) for y in y0s]
+    st, rc = ctx.run_ee_batch(fields, ns, eps, max_steps=6, tau0=1e-5, m_max=20)
+    assert rc == 0
+    for i in (0, 2):
+        yg = dev(y0s[i])
+        ctx.run_ee(ch.Problem(2, ns[i], eps[i]), yg, 1e-5, max_steps=6, m_max=20)
+        assert np.array_equal(yg.cpu().numpy(), fields[i].cpu().numpy())
+        y_ref, _ = O.ee_adaptive(y0s[i], O.Problem(2, ns[i], eps[i]), 1e-5, np.inf, 1e-4, 20, max_steps=6)
+        assert rel(fields[i].cpu().numpy(), y_ref) <= TOL_FP64
