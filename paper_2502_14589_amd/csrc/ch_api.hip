@@ -43,6 +43,7 @@ struct ch_ctx {
     int* hflag = nullptr;    // pinned, device-mapped: `cyc` of the last finished cycle per slot, then
                              // the sequence number of the last DCGS2 update launch begun
     int useq = 0;            // DCGS2 update launches issued (their sequence numbers)
+    int lseq = 0;            // LIM plan launches issued (the tags of their pinned orders)
     Ctl* hctl = nullptr;     // pinned mirror of the control blocks
     // instance tables: store 0 serves every run; the server keeps the
     // table of its LIM members in store 1 beside that of its EE members
@@ -163,6 +164,8 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         b.hprog = nullptr;
         b.dprog = nullptr;
         b.hseq = nullptr;
+        b.hlim = nullptr;
+        b.dlim = nullptr;
         ctx->slots = 0;
         if ((rc = alloc_dev(ctx, (void**)&b.ctl, sizeof(Ctl) * nslots))) return rc;
         if (!b.dcount) {
@@ -175,15 +178,18 @@ int ensure(ch_ctx* ctx, size_t pts, int m_max, int prec, int nslots, size_t recs
         if ((rc = alloc_dev(ctx, (void**)&b.lorder, sizeof(int) * CH_PMAX * nslots))) return rc;
         if ((rc = alloc_dev(ctx, (void**)&b.lcoef, sizeof(double) * 4 * CH_PMAX * nslots))) return rc;
         HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hctl, sizeof(Ctl) * nslots, hipHostMallocDefault));
-        // the finished-cycle word of every slot, then the update-launch progress word
-        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, sizeof(int) * (nslots + 1),
+        // the finished-cycle word of every slot, the update-launch progress
+        // word, then the LIM order and its tag of every slot
+        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->hflag, sizeof(int) * (3 * nslots + 1),
                                    hipHostMallocMapped | hipHostMallocCoherent));
-        for (int i = 0; i <= nslots; ++i) ctx->hflag[i] = -1;
+        for (int i = 0; i < 3 * nslots + 1; ++i) ctx->hflag[i] = -1;
         ctx->expect.assign(nslots, 0);
         HIP_TRY(ctx, hipHostGetDevicePointer((void**)&b.dflag, ctx->hflag, 0));
         b.hflag = ctx->hflag;
         b.dprog = b.dflag + nslots;
         b.hprog = ctx->hflag + nslots;
+        b.dlim = b.dflag + nslots + 1;
+        b.hlim = ctx->hflag + nslots + 1;
         // the device's count of update launches begun restarts with the host's count of those issued
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         HIP_TRY(ctx, hipMemset(b.dcount, 0, sizeof(int)));
@@ -631,34 +637,63 @@ int read_head(ch_ctx* ctx, const DevBuffers& b, Ctl* h) {
 // stage launches: the largest order decides, instances of smaller order
 // skip the launches past their last), the stages, the estimate and the
 // controller.  Every live instance has taken s steps, so its state
-// ping-pongs between b.ybuf[s & 1] and b.ybuf[(s + 1) & 1].  hctl: host copies
-// of the control blocks, indexed by slot.  *halted: no instance had anything
-// left to do (t >= T, the step limit, or an error in the plan).
+// ping-pongs between b.ybuf[s & 1] and b.ybuf[(s + 1) & 1].  The orders come
+// from the pinned words the plan writes when the buffers have them (one host
+// wait on the plan, no copies), else from copies of the control heads into
+// hctl (indexed by slot), which the caller must not rely on being current in
+// the first case.  *halted: no instance had anything left to do (t >= T, the
+// step limit, or an error in the plan).
 int issue_lim_step(ch_ctx* ctx, const Table& t, const DevBuffers& b, PartSeq& ps, Ctl* hctl, long long s,
                    bool* halted) {
     const double* yin = b.ybuf[s & 1];
     double* yout = b.ybuf[(s + 1) & 1];
+    const int seq = ++ctx->lseq;
     HIP_TRY(ctx, launch_lim_begin(t, b, ps, yin, ctx->stream));
-    HIP_TRY(ctx, launch_lim_plan(t, b, ps, ctx->stream));
-    for (int i = 0; i < t.ninst; ++i) {
-        const int slot = t.hinst[i].slot;
-        HIP_TRY(ctx, hipMemcpyAsync(hctl + slot, b.ctl + slot, CTL_HEAD, hipMemcpyDeviceToHost, ctx->stream));
-    }
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, launch_lim_plan(t, b, ps, seq, ctx->stream));
     const bool pairs = lim_stage_pairs(t);
+    auto stage = [&](int l) -> hipError_t {
+        return pairs && l > 0 ? launch_lim_stage2(t, b, yin, yout, l, ctx->stream)
+                              : launch_lim_stage(t, b, yin, yout, l, pairs, ctx->stream);
+    };
     int nl = 0;
-    for (int i = 0; i < t.ninst; ++i) {
-        const Ctl& h = hctl[t.hinst[i].slot];
-        if (!h.halted) nl = std::max(nl, lim_launches(h.p, pairs));
+    // every instance's order from the pinned words the plan writes (a
+    // bounded wait); else from copies of the control blocks
+    bool got = false;
+    if (b.hlim) {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (long long spin = 0;; ++spin) {
+            bool all = true;
+            for (int i = 0; i < t.ninst && all; ++i) all = b.hlim[2 * t.hinst[i].slot + 1] == seq;
+            if (all) {
+                got = true;
+                break;
+            }
+            if ((spin & 255) == 255 &&
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > CH_PLAN_WAIT_S)
+                break;
+        }
+        if (got)
+            for (int i = 0; i < t.ninst; ++i) {
+                const int p = b.hlim[2 * t.hinst[i].slot];
+                if (p > 0) nl = std::max(nl, lim_launches(p, pairs));
+            }
+    }
+    if (!got) {
+        for (int i = 0; i < t.ninst; ++i) {
+            const int slot = t.hinst[i].slot;
+            HIP_TRY(ctx, hipMemcpyAsync(hctl + slot, b.ctl + slot, CTL_HEAD, hipMemcpyDeviceToHost, ctx->stream));
+        }
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < t.ninst; ++i) {
+            const Ctl& h = hctl[t.hinst[i].slot];
+            if (!h.halted) nl = std::max(nl, lim_launches(h.p, pairs));
+        }
     }
     *halted = nl == 0;
     if (*halted) return CH_OK;
     // 2p - 1 stages (the nodes in the plan's order, then again without
     // beta_1); on 2-D strips stage 0 runs alone and the rest in pairs
-    for (int l = 0; l < nl; ++l) {
-        if (pairs && l > 0) HIP_TRY(ctx, launch_lim_stage2(t, b, yin, yout, l, ctx->stream));
-        else HIP_TRY(ctx, launch_lim_stage(t, b, yin, yout, l, pairs, ctx->stream));
-    }
+    for (int l = 0; l < nl; ++l) HIP_TRY(ctx, stage(l));
     HIP_TRY(ctx, launch_est_lim(t, b, ps, yin, yout, ctx->stream));
     HIP_TRY(ctx, launch_lim_end(t, b, ps, ctx->stream));
     return CH_OK;

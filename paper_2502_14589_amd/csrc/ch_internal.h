@@ -19,6 +19,7 @@
 #define CH_LOOKAHEAD 2           // DCGS2 iterations the host issues ahead of the device's update launches
 #endif
 #define CH_LOOKAHEAD_WAIT_S 0.05 // longest host wait for that progress (then it issues anyway)
+#define CH_PLAN_WAIT_S 1.0       // longest host wait for the LIM orders a plan publishes (then it copies them)
 #ifndef CH_MARCH_L
 #define CH_MARCH_L 16            // planes per run of the 3-D marching matvec
 #endif
@@ -147,6 +148,8 @@ struct DevBuffers {
     const volatile int* hprog;   // pinned host word: sequence number of the last DCGS2 update launch begun
     int* hseq;          // host counter of the DCGS2 update launches issued
     int* dcount;        // device counter of the DCGS2 update launches begun (mirrors hseq)
+    int* dlim;          // device view of `hlim`
+    const volatile int* hlim;   // pinned host words, per slot: the LIM plan's order p (0: halted), then its tag
     void* phibig;       // per-slot device scratch of the phi of orders above 48 (phi_big_bytes each)
 };
 
@@ -266,7 +269,9 @@ hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq&
                          const double* y1, hipStream_t s);
 hipError_t launch_step_end(const Table& t, const DevBuffers& b, PartSeq& ps, bool begin_next, hipStream_t s);
 hipError_t launch_lim_begin(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y, hipStream_t s);
-hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s);
+// seq: the tag the plan writes beside each instance's order in the pinned
+// words (when the buffers have them).
+hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, int seq, hipStream_t s);
 // Launch l of the stages of a LIM step whose Chebyshev order p each
 // instance reads from its control block: single stages (pairs = 0: 2p - 1
 // launches, stage l), or stage 0 alone and then two stages per launch

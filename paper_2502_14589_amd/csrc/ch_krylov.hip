@@ -1450,13 +1450,28 @@ __device__ __forceinline__ void lim_leja_order(int p, int* __restrict__ order) {
 // max(g(d_min), g(d_max)):
 //   2-D: g(d) = |4d/h^2 + 20e| + 4|d/h^2 + 8e| + 12e,      e = eps^2/h^4
 //   3-D: g(d) = |6d/h^2 + 42e| + 6|d/h^2 + 12e| + 30e
+// The order of an instance's step (0: halted) to its pinned host words, then
+// the tag of this plan launch, so that the host, which waits for the tags,
+// sizes the stage launches without copying the control blocks back.
+__device__ __forceinline__ void publish_order(int* dlim, int slot, int p, int seq) {
+    if (dlim && threadIdx.x == 0) {
+        dlim[2 * slot] = p;
+        __threadfence_system();
+        dlim[2 * slot + 1] = seq;
+    }
+}
+
 template <bool SINGLE>
 __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, const Inst* __restrict__ insts, const Inst inst0, int ninst,
                                                        const double* __restrict__ pin, int pin_stencil, int dim,
-                                                       int* __restrict__ orders, double* __restrict__ coefs) {
+                                                       int* __restrict__ orders, double* __restrict__ coefs,
+                                                       int* __restrict__ dlim, int seq) {
     const Inst I = SINGLE ? inst0 : insts[blockIdx.x];
     Ctl* ctl = ctls + I.slot;
-    if (ctl->halted) return;
+    if (ctl->halted) {
+        publish_order(dlim, I.slot, 0, seq);
+        return;
+    }
     double tot[3];
     sum_inst_partials<3, RED_MAX>(pin, I, pin_stencil, tot);
     __shared__ int sp;
@@ -1505,6 +1520,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_plan(Ctl* __restrict__ ctls, c
     }
     __syncthreads();
     const int p = sp;
+    publish_order(dlim, I.slot, p, seq);
     if (p == 0) return;
     __shared__ int order[CH_PMAX];
     lim_leja_order(p, order);
@@ -1928,11 +1944,11 @@ hipError_t launch_lim_begin(const Table& t, const DevBuffers& b, PartSeq& ps, co
     return hipGetLastError();
 }
 
-hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, hipStream_t s) {
+hipError_t launch_lim_plan(const Table& t, const DevBuffers& b, PartSeq& ps, int seq, hipStream_t s) {
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_lim_plan<true>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder, b.lcoef);
+        hipLaunchKernelGGL((k_lim_plan<true>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder, b.lcoef, b.dlim, seq);
     else
-        hipLaunchKernelGGL((k_lim_plan<false>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder, b.lcoef);
+        hipLaunchKernelGGL((k_lim_plan<false>), IARGS, ps.in(), ps.stencil, t.dim, b.lorder, b.lcoef, b.dlim, seq);
     return hipGetLastError();
 }
 
