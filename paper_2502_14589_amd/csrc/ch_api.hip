@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -448,12 +449,21 @@ static void set_mobility(Ctl* c, const Shape& sh) {
 // Bytes of the control block's scalar head (everything before the Arnoldi arrays).
 constexpr size_t CTL_HEAD = offsetof(Ctl, H);
 
-int read_heads(ch_ctx* ctx, int n) {
-    for (int i = 0; i < n; ++i)
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl + i, ctx->b.ctl + i, CTL_HEAD, hipMemcpyDeviceToHost, ctx->stream));
+// The heads of the control blocks of slots [lo, hi] into hctl: one strided
+// copy (the blocks are contiguous, sizeof(Ctl) apart), then a sync.
+int copy_heads_to(ch_ctx* ctx, Ctl* h, const Ctl* d, int lo, int hi) {
+    if (hi == lo)
+        HIP_TRY(ctx, hipMemcpyAsync(h + lo, d + lo, CTL_HEAD, hipMemcpyDeviceToHost, ctx->stream));
+    else if (hi > lo)
+        HIP_TRY(ctx, hipMemcpy2DAsync(h + lo, sizeof(Ctl), d + lo, sizeof(Ctl), CTL_HEAD, (size_t)(hi - lo + 1),
+                                      hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return CH_OK;
 }
+
+int copy_heads(ch_ctx* ctx, int lo, int hi) { return copy_heads_to(ctx, ctx->hctl, ctx->b.ctl, lo, hi); }
+
+int read_heads(ch_ctx* ctx, int n) { return copy_heads(ctx, 0, n - 1); }
 
 bool all_halted(const ch_ctx* ctx, int n) {
     for (int i = 0; i < n; ++i)
@@ -679,11 +689,13 @@ int issue_lim_step(ch_ctx* ctx, const Table& t, const DevBuffers& b, PartSeq& ps
             }
     }
     if (!got) {
+        int lo = INT_MAX, hi = -1;
         for (int i = 0; i < t.ninst; ++i) {
-            const int slot = t.hinst[i].slot;
-            HIP_TRY(ctx, hipMemcpyAsync(hctl + slot, b.ctl + slot, CTL_HEAD, hipMemcpyDeviceToHost, ctx->stream));
+            lo = std::min(lo, t.hinst[i].slot);
+            hi = std::max(hi, t.hinst[i].slot);
         }
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        int rc = copy_heads_to(ctx, hctl, b.ctl, lo, hi);
+        if (rc) return rc;
         for (int i = 0; i < t.ninst; ++i) {
             const Ctl& h = hctl[t.hinst[i].slot];
             if (!h.halted) nl = std::max(nl, lim_launches(h.p, pairs));
@@ -909,12 +921,15 @@ void pool_free(ch_server* S, size_t off, size_t len) {
     }
 }
 
+// The heads of the given requests' slots (one strided copy over the range
+// they span: the slots in between are copied too and not read).
 int read_slot_heads(ch_ctx* ctx, const std::vector<Req*>& rs) {
-    for (Req* r : rs)
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->hctl + r->slot, ctx->b.ctl + r->slot, CTL_HEAD, hipMemcpyDeviceToHost,
-                                    ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    return CH_OK;
+    int lo = INT_MAX, hi = -1;
+    for (Req* r : rs) {
+        lo = std::min(lo, r->slot);
+        hi = std::max(hi, r->slot);
+    }
+    return copy_heads(ctx, lo, hi);
 }
 
 Member member_of(const Req* r) {
