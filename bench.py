@@ -289,6 +289,82 @@ def graph_issue(ctx, ch, torch):
     return out
 
 
+# Constant-step LIM and EE2 runs printed in the paper's Tables 1 (no splitting;
+# EE2 with Krylov dimension 100 and the tolerance in the last field) and 2
+# (Eyre splitting; EE2(30) with tol 1e-2): tau -> (matvecs, error).
+PAPER_TABLE1 = {
+    64: {"lim": {1.0: (12960, 9.60e-2), 0.5: (18000, 1.10e-3), 0.25: (27856, 2.52e-3), 0.125: (40000, 8.34e-4),
+                 0.0625: (48000, 3.20e-4)},
+         "ee": {1.0: (10217, 3.24e-4, 1e-3), 0.5: (24824, 1.55e-4, 1e-5), 0.25: (39138, 3.88e-5, 1e-6),
+                0.125: (63039, 9.52e-6, 1e-7)}},
+    128: {"lim": {1.0: (50770, 2.90e-2), 0.5: (69908, 1.17e-2), 0.25: (99824, 5.70e-3), 0.125: (136000, 2.14e-3),
+                  0.0625: (207350, 1.44e-3)},
+          "ee": {1.0: (41266, 1.60e-3, 1e-3), 0.5: (92650, 3.61e-4, 1e-5), 0.25: (141148, 9.08e-5, 1e-6),
+                 0.125: (210401, 2.27e-5, 1e-7)}},
+}
+PAPER_TABLE2 = {
+    64: {"lim": {0.5: (21878, 9.93e-1), 0.25: (28000, 6.34e-1), 0.125: (40000, 5.05e-1), 0.0625: (48000, 7.47e-2),
+                 0.03125: (96000, 3.85e-2)},
+         "ee": {0.5: (13776, 4.84e-1), 0.25: (17391, 5.33e-1), 0.125: (16965, 6.67e-2), 0.0625: (23910, 2.41e-2),
+                0.03125: (35818, 1.13e-2)}},
+    128: {"lim": {0.5: (70000, 8.02e-1), 0.25: (100000, 5.65e-1), 0.125: (150444, 3.06e-2), 0.0625: (208000, 1.84e-2),
+                  0.03125: (288000, 1.03e-2)},
+          "ee": {0.5: (54973, 7.98e-1), 0.25: (66443, 4.58e-2), 0.125: (78237, 2.92e-2), 0.0625: (76857, 2.16e-2),
+                 0.03125: (110008, 1.15e-2)}},
+}
+
+
+def paper_mode(ctx, ch, torch, grids=(64, 128), ref_tau=1.0 / 64):
+    """The constant-step runs of Tables 1 and 2 on the paper's problem
+    (Section 5.1): homogeneous Neumann conditions on the cell-centred n x n grid
+    of (0, 64)^2, eps = eps_4 of the 64^2 grid (eq. eps), y0 ~ U(-0.01, 0.01)
+    (seed n), T = 1000, FP64.  Errors as in eq. acc_reached, against an EE2 run
+    with tau = ref_tau, Krylov dimension 100 and tol 1e-9 on the same grid
+    (the paper's random initial data and reference are not published, so the
+    errors compare in magnitude only; the LIM matvec counts do not depend on
+    them)."""
+    from paper_2502_14589_amd.inputs import paper_field
+
+    eps4 = 4.0 / (2.0 * math.sqrt(2.0) * math.atanh(0.9))
+    T = 1000.0
+    out = {"workload": "Neumann (0,64)^2, eps_4, y0 ~ U(-0.01,0.01) seed n, T = 1000, FP64, constant tau",
+           "reference": f"EE2 tau = {ref_tau:g}, Krylov dimension 100, tol 1e-9", "rows": []}
+
+    def run(kind, n, eyre, tau, tol=0.0, m_max=100):
+        prob = ch.Problem(2, n, eps4, eyre, ch.CH_FP64, ch.CH_BC_NEUMANN, 64.0)
+        y = torch.from_numpy(paper_field(n, seed=n)).to("cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "lim":
+            st, _ = ctx.run_lim(prob, y, tau, T=T, tol=0.0)
+        else:
+            st, _ = ctx.run_ee(prob, y, tau, T=T, m_max=m_max, tol=tol, constant_step=True)
+        torch.cuda.synchronize()
+        return y, st, time.perf_counter() - t0
+
+    for n in grids:
+        progress(f"paper mode {n}^2: reference")
+        yref, _, tref = run("ee", n, False, ref_tau, tol=1e-9)
+        nref = float(torch.linalg.norm(yref))
+        for table, eyre in ((PAPER_TABLE1, False), (PAPER_TABLE2, True)):
+            for kind in ("lim", "ee"):
+                for tau, printed in table[n][kind].items():
+                    tol = printed[2] if (kind == "ee" and not eyre) else 1e-2
+                    m_max = 30 if eyre else 100
+                    y, st, sec = run(kind, n, eyre, tau, tol=tol, m_max=m_max)
+                    err = float(torch.linalg.norm(y - yref)) / nref
+                    out["rows"].append({
+                        "grid": n, "table": 2 if eyre else 1, "method": "LIM" if kind == "lim" else f"EE2({m_max})",
+                        "tau": tau, "tol": tol if kind == "ee" else None, "status": st["rc"] if "rc" in st else None,
+                        "t_end": st["t"], "steps": st["steps"], "matvecs": st["matvecs"],
+                        # EE2: the Krylov matvecs without each step's start vector
+                        "matvecs_less_start_vectors": st["matvecs"] - st["steps"] if kind == "ee" else None,
+                        "paper_matvecs": printed[0], "error": err, "paper_error": printed[1],
+                        "seconds": round(sec, 3)})
+        out[f"reference_seconds_{n}"] = round(tref, 3)
+    return out
+
+
 def serve_trace(ch, torch, reqs, label):
     """Replay one arrival trace through a server (fields resident on the
     device before it starts); returns latencies and served work."""
@@ -471,6 +547,8 @@ def main():
                                       "(a counter run then sees only one warm step and the replay)")
     ap.add_argument("--only-3d", action="store_true", help="the 256^3 forms alone (profiling runs)")
     ap.add_argument("--only-lim", action="store_true", help="the adaptive LIM form alone (profiling runs)")
+    ap.add_argument("--paper", action="store_true",
+                    help="the constant-step runs of the paper's Tables 1 and 2 on its Neumann problem (about two minutes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (the grid would be split into "
@@ -518,6 +596,10 @@ def main():
     if args.only_3d:
         with ch.Context(0) as ctx:
             print(json.dumps({"mode": "only-3d", "c3_3d": c3_form(ctx, ch, torch)}), flush=True)
+        return
+    if args.paper:
+        with ch.Context(0) as ctx:
+            print(json.dumps({"mode": "paper", "paper": paper_mode(ctx, ch, torch)}), flush=True)
         return
     if args.only_lim:
         with ch.Context(0) as ctx:
