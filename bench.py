@@ -312,10 +312,27 @@ PAPER_TABLE2 = {
           "ee": {0.5: (54973, 7.98e-1), 0.25: (66443, 4.58e-2), 0.125: (78237, 2.92e-2), 0.0625: (76857, 2.16e-2),
                  0.03125: (110008, 1.15e-2)}},
 }
+# Adaptive runs printed in Tables 3 (128^2) and 4 (192^2): (method, Krylov
+# dimension or None, tol, tau0, matvecs, error); EE2 starts from tau0 = 1.
+PAPER_TABLES34 = {
+    128: [("lim", None, 1e-2, 1.0, 38940, 2.73e-3), ("lim", None, 1e-3, 0.5, 120476, 3.62e-4),
+          ("lim", None, 1e-4, 0.25, 397133, 1.22e-4),
+          ("ee", 10, 1e-2, 1.0, 42856, 9.63e-3), ("ee", 10, 1e-3, 1.0, 57100, 3.31e-3),
+          ("ee", 10, 1e-4, 1.0, 110088, 7.57e-5),
+          ("ee", 30, 1e-2, 1.0, 22800, 4.62e-3), ("ee", 30, 1e-3, 1.0, 44493, 7.03e-4),
+          ("ee", 30, 1e-4, 1.0, 73867, 1.28e-4)],
+    192: [("lim", None, 1e-2, 1.0, 85843, 1.12e-3), ("lim", None, 1e-3, 0.5, 265411, 1.82e-4),
+          ("lim", None, 1e-4, 0.25, 893808, 3.79e-5),
+          ("ee", 10, 1e-2, 1.0, 201460, 1.07e-3), ("ee", 10, 1e-3, 1.0, 208018, 1.04e-3),
+          ("ee", 10, 1e-4, 1.0, 339418, 4.33e-4), ("ee", 10, 1e-5, 1.0, 546624, 5.35e-6),
+          ("ee", 30, 1e-2, 1.0, 75053, 2.99e-3), ("ee", 30, 1e-3, 1.0, 126485, 5.35e-4),
+          ("ee", 30, 1e-4, 1.0, 221243, 1.21e-5)],
+}
 
 
-def paper_mode(ctx, ch, torch, grids=(64, 128), ref_tau=1.0 / 64):
-    """The constant-step runs of Tables 1 and 2 on the paper's problem
+def paper_mode(ctx, ch, torch, grids=(64, 128, 192), ref_tau=1.0 / 64):
+    """The constant-step runs of Tables 1 and 2 and the adaptive runs of Tables
+    3 and 4 on the paper's problem
     (Section 5.1): homogeneous Neumann conditions on the cell-centred n x n grid
     of (0, 64)^2, eps = eps_4 of the 64^2 grid (eq. eps), y0 ~ U(-0.01, 0.01)
     (seed n), T = 1000, FP64.  Errors as in eq. acc_reached, against an EE2 run
@@ -327,18 +344,19 @@ def paper_mode(ctx, ch, torch, grids=(64, 128), ref_tau=1.0 / 64):
 
     eps4 = 4.0 / (2.0 * math.sqrt(2.0) * math.atanh(0.9))
     T = 1000.0
-    out = {"workload": "Neumann (0,64)^2, eps_4, y0 ~ U(-0.01,0.01) seed n, T = 1000, FP64, constant tau",
+    out = {"workload": "Neumann (0,64)^2, eps_4, y0 ~ U(-0.01,0.01) seed n, T = 1000, FP64; constant tau (Tables 1-2), adaptive tau (Tables 3-4)",
            "reference": f"EE2 tau = {ref_tau:g}, Krylov dimension 100, tol 1e-9", "rows": []}
 
-    def run(kind, n, eyre, tau, tol=0.0, m_max=100):
+    def run(kind, n, eyre, tau, tol=0.0, m_max=100, adaptive=False):
         prob = ch.Problem(2, n, eps4, eyre, ch.CH_FP64, ch.CH_BC_NEUMANN, 64.0)
         y = torch.from_numpy(paper_field(n, seed=n)).to("cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if kind == "lim":
-            st, _ = ctx.run_lim(prob, y, tau, T=T, tol=0.0)
+            st, _ = ctx.run_lim(prob, y, tau, T=T, tol=tol if adaptive else 0.0, raise_on_error=not adaptive)
         else:
-            st, _ = ctx.run_ee(prob, y, tau, T=T, m_max=m_max, tol=tol, constant_step=True)
+            st, _ = ctx.run_ee(prob, y, tau, T=T, m_max=m_max, tol=tol, constant_step=not adaptive,
+                               raise_on_error=not adaptive)
         torch.cuda.synchronize()
         return y, st, time.perf_counter() - t0
 
@@ -346,7 +364,19 @@ def paper_mode(ctx, ch, torch, grids=(64, 128), ref_tau=1.0 / 64):
         progress(f"paper mode {n}^2: reference")
         yref, _, tref = run("ee", n, False, ref_tau, tol=1e-9)
         nref = float(torch.linalg.norm(yref))
+        for meth, mk, tol, tau0, mv_p, err_p in PAPER_TABLES34.get(n, []):
+            y, st, sec = run(meth, n, False, tau0, tol=tol, m_max=mk or 30, adaptive=True)
+            err = float(torch.linalg.norm(y - yref)) / nref
+            out["rows"].append({
+                "grid": n, "table": 3 if n == 128 else 4, "method": "LIM" if meth == "lim" else f"EE2({mk})",
+                "adaptive": True, "tau0": tau0, "tol": tol, "status": st.get("rc"), "t_end": st["t"],
+                "steps": st["steps"], "restarts": st["restarts"],
+                "matvecs": st["matvecs"],
+                "matvecs_less_start_vectors": st["matvecs"] - st["steps"] if meth == "ee" else None,
+                "paper_matvecs": mv_p, "error": err, "paper_error": err_p, "seconds": round(sec, 3)})
         for table, eyre in ((PAPER_TABLE1, False), (PAPER_TABLE2, True)):
+            if n not in table:
+                continue
             for kind in ("lim", "ee"):
                 for tau, printed in table[n][kind].items():
                     tol = printed[2] if (kind == "ee" and not eyre) else 1e-2
@@ -548,7 +578,7 @@ def main():
     ap.add_argument("--only-3d", action="store_true", help="the 256^3 forms alone (profiling runs)")
     ap.add_argument("--only-lim", action="store_true", help="the adaptive LIM form alone (profiling runs)")
     ap.add_argument("--paper", action="store_true",
-                    help="the constant-step runs of the paper's Tables 1 and 2 on its Neumann problem (about two minutes)")
+                    help="the runs of the paper's Tables 1-4 on its Neumann problem (a few minutes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (the grid would be split into "
