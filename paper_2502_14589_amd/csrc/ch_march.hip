@@ -8,36 +8,54 @@
 // <u, w>).
 //
 // Layout.  A workgroup owns an MX x MY block of (x, y) columns and a run of
-// up to CH_MARCH_L planes in z.  It walks the run plane by plane keeping three
-// operand planes (halo 2 in x and y), two planes of d and three planes of the
-// inner expression q = d u + eps^2 A u (halo 1) in LDS, as rings: each step
-// reads one new operand plane and one plane of the state, forms q on one
-// plane and w on the plane below it.  An operand plane region is read
-// (L + 4) / L times per run, (MX + 4)(MY + 4) / (MX MY) = 1.6 times the tile,
-// against (TX + 4)(TY + 4)(TZ + 4) / (TX TY TZ) = 4.5 for a 32 x 4 x 4 tile
-// staged whole; the next step's loads are issued before the current step's
-// arithmetic.
+// up to CH_MARCH_L planes in z, which it walks plane by plane.  Thread t owns
+// the same two consecutive-x columns of the block in every pass (the stencil
+// passes and the dot phase), plus one column of the halo-1 ring around the
+// block.  In LDS: a ring of three operand planes (halo 2 in x and y) and two
+// planes of the inner expression q = d u + eps^2 A u (halo 1); what the
+// stencils take from the planes above and below a point -- the operand and q
+// at the point itself -- stays in the owning thread's registers, and so do
+// d = 3 y^2 - 1 at its points and the w and u values of its dot products.  A
+// plane step has one barrier: it reads one operand plane and the state at the
+// thread's points (requested a step ahead), forms q on one plane and w on the
+// plane below it, and runs that plane's dot phase.  An operand plane region
+// is read (L + 4) / L times per run, (MX + 4)(MY + 4) / (MX MY) = 1.6 times
+// the tile, against (TX + 4)(TY + 4)(TZ + 4) / (TX TY TZ) = 4.5 for a
+// 32 x 4 x 4 tile staged whole.
 #include "ch_common.h"
 
 #include <type_traits>
 
 namespace {
 
-// x-y tile of a workgroup: MX x MY outputs per plane, two per thread.
+// x-y tile of a workgroup: MX x MY outputs per plane, NPT consecutive x per
+// thread; the halo-1 ring of the q region is spread over the threads.
 template <typename TV>
 struct MGeo {
     static constexpr int MX = 64, MY = 8;
     static constexpr int MVX = MX + 4, MVY = MY + 4;   // operand plane region (halo 2)
     static constexpr int MQX = MX + 2, MQY = MY + 2;   // inner-expression plane region (halo 1)
-    static constexpr int MVP = MVX * MVY, MQP = MQX * MQY;
+    static constexpr int MQS = MQX + 2;                // q plane row stride (even: pairs stay aligned)
+    static constexpr int MVP = MVX * MVY, MQP = MQX * MQY, MQPS = MQY * MQS;
     static constexpr int NVL = (MVP + CH_BLOCK - 1) / CH_BLOCK;   // operand values per thread and plane
-    static constexpr int NQL = (MQP + CH_BLOCK - 1) / CH_BLOCK;   // q values per thread and plane
-    static constexpr int MPTS = MX * MY;
-    static constexpr int MPPT = MPTS / CH_BLOCK;
-    static_assert(MPPT * CH_BLOCK == MPTS, "plane outputs per thread");
-    // the q pass's reads stay in the operand plane region
-    static_assert(MQY * MVX + MQX + MVX < MVP, "q pass reads");
+    static constexpr int NPT = 2;                                 // tile points per thread
+    static constexpr int TXT = MX / NPT;                          // threads per tile row
+    static constexpr int NRING = MQP - MX * MY;                   // halo-1 ring of the q region
+    static constexpr int NRL = (NRING + CH_BLOCK - 1) / CH_BLOCK; // ring points per thread
+    static constexpr int NQL = NPT + NRL;                         // q points per thread
+    static_assert(TXT * MY == CH_BLOCK, "one thread per point pair of the tile");
+    static_assert(MVX % 2 == 0 && MQS % 2 == 0 && MVP % 4 == 0 && MQPS % 4 == 0, "aligned LDS pairs");
 };
+
+// Two consecutive LDS values at an even index, as one access.
+template <typename T>
+struct alignas(2 * sizeof(T)) LPair {
+    T a, b;
+};
+template <typename T>
+__device__ __forceinline__ LPair<T> lds_pair(const T* p) {
+    return *reinterpret_cast<const LPair<T>*>(p);
+}
 
 template <typename T>
 __device__ __forceinline__ T mdcoef(T y, int eyre) {
@@ -61,14 +79,15 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned bo) {
     else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, bo, 0u, 0));
 }
 
-// NPT consecutive values of 16 bytes in all (one buffer load).
-template <typename T, int NPT>
-__device__ __forceinline__ void bload16(__amdgpu_buffer_rsrc_t r, unsigned bo, T (&v)[NPT]) {
-    static_assert(NPT * sizeof(T) == 16, "16-byte vector");
-    struct P { T e[NPT]; };
-    const P p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b128(r, bo, 0u, 0));
-#pragma unroll
-    for (int e = 0; e < NPT; ++e) v[e] = p.e[e];
+// Two consecutive values (one buffer load of 16 bytes in FP64, 8 in FP32).
+template <typename T>
+__device__ __forceinline__ void bload2(__amdgpu_buffer_rsrc_t r, unsigned bo, T (&v)[2]) {
+    struct P { T e[2]; };
+    P p;
+    if constexpr (sizeof(T) == 8) p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b128(r, bo, 0u, 0));
+    else p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b64(r, bo, 0u, 0));
+    v[0] = p.e[0];
+    v[1] = p.e[1];
 }
 
 template <typename T>
@@ -76,6 +95,16 @@ __device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned b
     using u32x2 = unsigned __attribute__((ext_vector_type(2)));
     if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, bo, 0u, 0);
     else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, bo, 0u, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore2(const T (&v)[2], __amdgpu_buffer_rsrc_t r, unsigned bo) {
+    struct P { T e[2]; };
+    const P p{{v[0], v[1]}};
+    using u32x2 = unsigned __attribute__((ext_vector_type(2)));
+    using u32x4 = unsigned __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, p), r, bo, 0u, 0);
+    else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, p), r, bo, 0u, 0);
 }
 
 // Work item it of an instance: x-y tile and run of planes.
@@ -96,51 +125,44 @@ __device__ __forceinline__ MarchItem march_item(int it, int n) {
     return m;
 }
 
-// Step p of a run (planes p - 1, p, p + 1 of the operand and d(p) in LDS):
-//   issue the loads of operand plane p + 2 and state plane p + 1;
-//   q(p) on the halo-1 region;                         barrier
-//   w(p - 1) = A q on the tile, stored; first basis columns of the dot
-//   phase issued (FP64: at the start of the step);     barrier
-//   dot products of plane p - 1;
-//   the loaded planes into the rings;                  barrier.
-// The step's loads have its whole arithmetic to arrive, and nothing is carried
-// from one step to the next in registers.  Rings: operand plane z in slot
-// (z - z0 + 2) mod 3, d in (z - z0 + 1) mod 2, q in (z - z0 + 1) mod 3.
-// Operand plane p + 2 takes the slot of plane p - 1, whose last reads (the q
-// pass and the dot phase's operand values) come before the step's first
-// barrier.
-// FP32: four workgroups per CU (128 registers); FP64: three (LDS-bound).
-// DV: the dot-phase form -- 1: 16-byte vectors (n a multiple of NPT), 0:
+// Step p of a run (operand planes p and p + 1 and q(p - 1) in LDS; in
+// registers at the thread's points: the operand of plane p - 1, d(p), and
+// q(p - 2), q(p - 1) at its tile pair):
+//   request the first basis columns of the dot phase (FP64), then operand
+//   plane p + 2 and the state of plane p + 1 at the thread's q points;
+//   q(p) at the thread's q points, stored to the free q plane;
+//   w(p - 1) at its tile pair from q(p - 1) in LDS and q(p - 2), q(p) in
+//   registers, stored; the dot phase of plane p - 1 (its u and w values in
+//   registers);
+//   operand plane p + 2 into the ring slot of plane p - 1, d(p + 1) from the
+//   state;                                            barrier.
+// Rings: operand plane z in slot (z - z0 + 2) mod 3, q(z) in (z - z0 + 1) mod
+// 2.  Operand plane p + 2 takes the slot of plane p - 1, which no thread reads
+// in step p (its values at each thread's points are in registers); q(p)
+// takes the buffer of q(p - 2), last read in step p - 1.
+// DV: the dot-phase form -- 1: the tile pair as one vector (n even), 0: two
 // scalar points, 2: chosen per instance at run time (batches).  BIGK: room
-// for the dot rows of iterations k > CH_MSMALL (the LDS of the small form
-// keeps FP64 at three workgroups per CU).
+// for the dot rows of iterations k > CH_MSMALL.
 template <typename TV, typename TY, bool SINGLE, int TAG, int DV, bool BIGK>
-__global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+__global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        TV* __restrict__ V, size_t ldv, int k, int store_w,
                                                        const TY* __restrict__ ybase, double* __restrict__ pout) {
     using G = MGeo<TV>;
-    constexpr int MX = G::MX, MY = G::MY, MVX = G::MVX, MVP = G::MVP, MQX = G::MQX, MQP = G::MQP;
-    constexpr int NVL = G::NVL, NQL = G::NQL, MPTS = G::MPTS, MPPT = G::MPPT;
+    constexpr int MX = G::MX, MY = G::MY, MVX = G::MVX, MVP = G::MVP, MQX = G::MQX, MQY = G::MQY, MQS = G::MQS,
+                  MQPS = G::MQPS;
+    constexpr int NVL = G::NVL, NPT = G::NPT, TXT = G::TXT, NRING = G::NRING, NQL = G::NQL;
+    static_assert(G::MQP == MQX * MQY, "q region");
     const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
     Ctl* ctl = ctls + I.slot;
     if (ctl->done | ctl->halted) return;
     constexpr int NW = CH_BLOCK / 64;
-    // The region passes run over whole passes of the workgroup with no
-    // bounds test: lanes past a region's end repeat its last point, so they
-    // load, compute and store the same value as the lane that owns it.
-    __shared__ TV sv[3][MVP];
-    __shared__ TV sd[2][MQP];
-    __shared__ TV sq[3][MQP];
-    __shared__ TV sw[MPTS];
+    // The operand pass runs over whole passes of the workgroup with no bounds
+    // test: lanes past the region's end repeat its last point, so they load
+    // and store the same value as the lane that owns it.
+    __shared__ __attribute__((aligned(16))) TV sv[3][MVP];
+    __shared__ __attribute__((aligned(16))) TV sq[2][MQPS];   // q(x, y) at y * MQS + x + 1
     __shared__ double red[BIGK ? CH_DROWS : CH_DROWS_SMALL][NW];
-    // dot phase: thread t of column group g takes plane points t + GT e, so
-    // the lanes of a wave read consecutive x; the columns are split over CG
-    // groups (FP32: two, FP64: one)
-    constexpr int CG = sizeof(TV) == 4 ? 2 : 1;
-    constexpr int GT = CH_BLOCK / CG;
-    constexpr int NPT = MPTS / GT;
-    static_assert(GT % 64 == 0 && (MX % 64 == 0 || 64 % MX == 0) && NPT * GT == MPTS, "dot-phase split");
     constexpr unsigned ES = sizeof(TV);
     const TV* Vk = V + (size_t)k * ldv + I.off;
     TV* W = V + (size_t)(k + 1) * ldv + I.off;
@@ -155,32 +177,48 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
     const int nrows = 2 * k + 2;
     for (int i = tid; i < nrows * NW; i += CH_BLOCK) red[i / NW][i % NW] = 0.0;
     const int hv = wave_sum8_holder(lane);
-    // GT is a multiple of 64, so grp is wave-uniform; saying so keeps the
-    // column resources in scalar registers
-    const int grp = __builtin_amdgcn_readfirstlane(tid / GT), gt = tid % GT;
-    const int kg = (k - grp + CG - 1) / CG;       // dot columns grp, grp + CG, ... below k
     const int ntx = (n + MX - 1) / MX, nty = (n + MY - 1) / MY;
     const int nitems = ntx * nty * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
     const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
     constexpr int RB = 4;   // columns per wave_sum8 (two sums each)
-    static_assert(NPT * sizeof(TV) == 16, "dot-phase points of a thread: one 16-byte vector");
-    // Dot-phase points of thread gt: the NPT consecutive x of vector gt of the
-    // plane tile (one 16-byte load per basis column) when n is a multiple of
-    // NPT, else the scalar points gt + GT e.  Every grid of the same n takes
-    // the same form, so batched and separate runs sum in the same order.
+    // the thread's q points in the q region: its tile pair, then its ring point
+    // (lanes past the ring's end repeat its last point)
+    int qrx[NQL], qry[NQL];
+    const int cx = NPT * (tid % TXT), cy = tid / TXT;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+        qrx[e] = cx + 1 + e;
+        qry[e] = cy + 1;
+    }
+#pragma unroll
+    for (int l = NPT; l < NQL; ++l) {
+        const int r = min(tid + (l - NPT) * CH_BLOCK, NRING - 1);
+        if (r < MQX) {
+            qrx[l] = r;
+            qry[l] = 0;
+        } else if (r < 2 * MQX) {
+            qrx[l] = r - MQX;
+            qry[l] = MQY - 1;
+        } else if (r < 2 * MQX + MY) {
+            qrx[l] = 0;
+            qry[l] = 1 + r - 2 * MQX;
+        } else {
+            qrx[l] = MQX - 1;
+            qry[l] = 1 + r - 2 * MQX - MY;
+        }
+    }
     // FP64 requests the first block of basis columns of a step before the
     // next planes (loads complete in issue order, so the dot phase then waits
-    // for its columns but not for the prefetch); in FP32 that was slower (the
-    // registers held across the stencil passes).
+    // for its columns but not for the prefetch)
     constexpr bool EARLY = sizeof(TV) == 8;
     auto items = [&](auto vec_c) {
     constexpr bool VEC = decltype(vec_c)::value;
     for (int it = lb; it < nitems; it += I.wblk) {
         const MarchItem m = march_item<MX, MY>(it, n);
-        // byte offsets in a plane of this thread's operand and state values
-        // (periodic wrap; the region may extend past the grid, whose outputs
-        // are masked below)
-        unsigned vo[NVL], qo[NQL];
+        // byte offsets in a plane of the thread's operand-region values and
+        // of its q points (periodic wrap; the region may extend past the
+        // grid, whose outputs are masked below)
+        unsigned vo[NVL], qpos[NQL];
 #pragma unroll
         for (int l = 0; l < NVL; ++l) {
             const int i = min(tid + l * CH_BLOCK, MVP - 1);
@@ -188,75 +226,72 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
             vo[l] = (unsigned)(wrapi(m.y0 - 2 + ry, n) * n + wrapi(m.x0 - 2 + rx, n)) * ES;
         }
 #pragma unroll
-        for (int l = 0; l < NQL; ++l) {
-            const int i = min(tid + l * CH_BLOCK, MQP - 1);
-            const int ry = i / MQX, rx = i - ry * MQX;
-            qo[l] = (unsigned)(wrapi(m.y0 - 1 + ry, n) * n + wrapi(m.x0 - 1 + rx, n)) * (unsigned)sizeof(TY);
-        }
-        // this thread's dot-phase points: plane offsets (MOFF outside the
-        // grid) and operand-ring indices
-        unsigned dof[NPT];
-        int dsv[NPT];
+        for (int l = 0; l < NQL; ++l)
+            qpos[l] = (unsigned)(wrapi(m.y0 - 1 + qry[l], n) * n + wrapi(m.x0 - 1 + qrx[l], n));
+        // the tile pair: plane offset (MOFF outside the grid) and which
+        // points are in the grid
+        const int gx = m.x0 + cx, gy = m.y0 + cy;
         bool din[NPT];
-        int dsw[NPT];
+        unsigned dof[NPT];
 #pragma unroll
         for (int e = 0; e < NPT; ++e) {
-            const int j = VEC ? NPT * gt + e : gt + GT * e;
-            dsw[e] = j;
-            const int cy = j / MX, cx = j - cy * MX;
-            const int gx = m.x0 + cx, gy = m.y0 + cy;
-            din[e] = gx < n && gy < n;
-            dof[e] = din[e] ? (unsigned)(gy * n + gx) * ES : MOFF;
-            dsv[e] = (cy + 2) * MVX + (cx + 2);
+            din[e] = gx + e < n && gy < n;
+            dof[e] = din[e] ? (unsigned)(gy * n + gx + e) * ES : MOFF;
         }
         auto load_v = [&](int z, TV (&r)[NVL]) {
             const __amdgpu_buffer_rsrc_t rs = plane_rsrc(Vk + (size_t)wrapi(z, n) * n2, pv);
 #pragma unroll
             for (int l = 0; l < NVL; ++l) r[l] = bload<TV>(rs, vo[l]);
         };
-        auto load_y = [&](int z, TY (&r)[NQL]) {
-            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(y + (size_t)wrapi(z, n) * n2, py);
-#pragma unroll
-            for (int l = 0; l < NQL; ++l) r[l] = bload<TY>(rs, qo[l]);
-        };
         auto store_v = [&](int z, const TV (&r)[NVL]) {
             TV* d = sv[(z - m.z0 + 2) % 3];
 #pragma unroll
             for (int l = 0; l < NVL; ++l) d[min(tid + l * CH_BLOCK, MVP - 1)] = sc * r[l];
         };
-        auto store_d = [&](int z, const TY (&r)[NQL]) {
-            TV* d = sd[(z - m.z0 + 1) & 1];
+        auto load_y = [&](int z, TY (&r)[NQL]) {
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(y + (size_t)wrapi(z, n) * n2, py);
 #pragma unroll
-            for (int l = 0; l < NQL; ++l) d[min(tid + l * CH_BLOCK, MQP - 1)] = mdcoef(TV(r[l]), eyre);
+            for (int l = 0; l < NQL; ++l) r[l] = bload<TY>(rs, qpos[l] * (unsigned)sizeof(TY));
         };
         const int z0 = m.z0;
+        // registers carried between steps: operand of the plane below and
+        // d of the current plane at the q points; q two planes and one plane
+        // below at the tile pair
+        TV vm[NQL], dr[NQL], qm2[NPT], qm1[NPT];
         {
-            TV a[NVL], b[NVL], c[NVL];
+            TV a[NVL], b[NVL];
             TY yy[NQL];
-            load_v(z0 - 2, a);
-            load_v(z0 - 1, b);
-            load_v(z0, c);
+            load_v(z0 - 1, a);
+            load_v(z0, b);
+            {
+                const __amdgpu_buffer_rsrc_t rs = plane_rsrc(Vk + (size_t)wrapi(z0 - 2, n) * n2, pv);
+#pragma unroll
+                for (int l = 0; l < NQL; ++l) vm[l] = sc * bload<TV>(rs, qpos[l] * ES);
+            }
             load_y(z0 - 1, yy);
-            __syncthreads();   // the previous item's readers of the rings are done
-            store_v(z0 - 2, a);
-            store_v(z0 - 1, b);
-            store_v(z0, c);
-            store_d(z0 - 1, yy);
+            // the previous item's last step ended with a barrier after its
+            // last reads of the rings
+            store_v(z0 - 1, a);
+            store_v(z0, b);
+#pragma unroll
+            for (int l = 0; l < NQL; ++l) dr[l] = mdcoef(TV(yy[l]), eyre);
+#pragma unroll
+            for (int e = 0; e < NPT; ++e) qm2[e] = qm1[e] = TV(0);
             __syncthreads();
         }
         for (int p = z0 - 1; p <= z0 + m.zl; ++p) {
             const int zo = p - 1;   // plane of this step's w
             const bool more = p + 1 <= z0 + m.zl;
+            const bool dots = zo >= z0;
             // the basis columns of the dot phase (plane p - 1), in blocks of RB
-            const TV* colbase = V + I.off + (size_t)(zo >= z0 ? zo : z0) * n2;
+            const TV* colbase = V + I.off + (size_t)(dots ? zo : z0) * n2;
             auto fetch = [&](int l0, TV (&v)[RB][NPT]) {
 #pragma unroll
                 for (int r = 0; r < RB; ++r) {
-                    const bool live = zo >= z0 && l0 + r < kg;
-                    const int c = live ? grp + CG * (l0 + r) : 0;
-                    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(colbase + (size_t)c * ldv, pv);
+                    const bool live = dots && l0 + r < k;
+                    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(colbase + (size_t)(live ? l0 + r : 0) * ldv, pv);
                     if constexpr (VEC) {
-                        bload16<TV, NPT>(rs, live ? dof[0] : MOFF, v[r]);
+                        bload2<TV>(rs, live ? dof[0] : MOFF, v[r]);
                     } else {
 #pragma unroll
                         for (int e = 0; e < NPT; ++e) v[r][e] = bload<TV>(rs, live ? dof[e] : MOFF);
@@ -267,61 +302,71 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
             if constexpr (EARLY) fetch(0, cur);
             TV nv[NVL];
             TY ny[NQL];
-            if (more) {   // the next step's planes, in flight during this one
+            if (more) {   // the next step's operand plane and state, in flight during this one
                 load_v(p + 2, nv);
                 load_y(p + 1, ny);
             }
-            // q(p) on the halo-1 region
-            const int qs = (p - z0 + 1) % 3;
+            // q(p) at the q points, into the free q plane
+            TV vc[NQL], qn[NQL];
             {
                 const TV* v0 = sv[(p - z0 + 2) % 3];
-                const TV* vm = sv[(p - z0 + 1) % 3];
                 const TV* vp = sv[(p - z0 + 3) % 3];
-                const TV* dp = sd[(p - z0 + 1) & 1];
+                TV* qd = sq[(p - z0 + 1) & 1];
+                {   // the tile pair: every operand value as part of an aligned pair
+                    static_assert(NPT == 2, "pair pass");
+                    const int c = (qry[0] + 1) * MVX + (qrx[0] + 1);
+                    const LPair<TV> lft = lds_pair(v0 + c - 2), mid = lds_pair(v0 + c), rgt = lds_pair(v0 + c + 2);
+                    const LPair<TV> up = lds_pair(v0 + c - MVX), dn = lds_pair(v0 + c + MVX), ab = lds_pair(vp + c);
+                    vc[0] = mid.a;
+                    vc[1] = mid.b;
+                    TV nb0 = (lft.b + mid.b) + (up.a + dn.a);
+                    TV nb1 = (mid.a + rgt.a) + (up.b + dn.b);
+                    nb0 += vm[0] + ab.a;
+                    nb1 += vm[1] + ab.b;
+                    qn[0] = dr[0] * vc[0] + e2ih2 * (TV(6) * vc[0] - nb0);
+                    qn[1] = dr[1] * vc[1] + e2ih2 * (TV(6) * vc[1] - nb1);
+                    *reinterpret_cast<LPair<TV>*>(qd + qry[0] * MQS + qrx[0] + 1) = LPair<TV>{qn[0], qn[1]};
+                }
 #pragma unroll
-                for (int l = 0; l < NQL; ++l) {
-                    const int i = min(tid + l * CH_BLOCK, MQP - 1);
-                    const int ry = i / MQX, rx = i - ry * MQX;
-                    const int c = (ry + 1) * MVX + (rx + 1);
+                for (int l = NPT; l < NQL; ++l) {
+                    const int c = (qry[l] + 1) * MVX + (qrx[l] + 1);
+                    vc[l] = v0[c];
                     TV nb = (v0[c - 1] + v0[c + 1]) + (v0[c - MVX] + v0[c + MVX]);
-                    nb += vm[c] + vp[c];
-                    sq[qs][i] = dp[i] * v0[c] + e2ih2 * (TV(6) * v0[c] - nb);
+                    nb += vm[l] + vp[c];
+                    qn[l] = dr[l] * vc[l] + e2ih2 * (TV(6) * vc[l] - nb);
+                    qd[qry[l] * MQS + qrx[l] + 1] = qn[l];
                 }
             }
-            if (zo >= z0) {
-                // the dot phase's operand values (plane p - 1), read before
-                // the barrier after which plane p + 2 may take their slot
-                const TV* um = sv[(p - z0 + 1) % 3];
-                double ud[NPT];
+            if (dots) {
+                // w(p - 1) at the tile pair: A q from q(p - 1) in LDS (written
+                // in the previous step) and q(p - 2), q(p) in registers
+                const TV* qmid = sq[(p - z0) & 1];
+                TV w[NPT];
+                double ud[NPT], wd[NPT];
+                {   // q(p - 1) of the pair itself is in registers
+                    const int c = qry[0] * MQS + qrx[0] + 1;
+                    const LPair<TV> lft = lds_pair(qmid + c - 2), rgt = lds_pair(qmid + c + 2);
+                    const LPair<TV> up = lds_pair(qmid + c - MQS), dn = lds_pair(qmid + c + MQS);
+                    TV nb[NPT] = {(lft.b + qm1[1]) + (up.a + dn.a), (qm1[0] + rgt.a) + (up.b + dn.b)};
 #pragma unroll
-                for (int e = 0; e < NPT; ++e) ud[e] = din[e] ? double(um[dsv[e]]) : 0.0;
-                __syncthreads();
-                // w(p - 1) on the tile: A q from q planes p - 2, p - 1, p
-                const TV* qlo = sq[(p - z0 + 2) % 3];    // plane p - 2
-                const TV* qmid = sq[(p - z0) % 3];       // plane p - 1
-                const TV* qhi = sq[qs];                  // plane p
-                const __amdgpu_buffer_rsrc_t rw = plane_rsrc(W + (size_t)zo * n2, pv);
-#pragma unroll
-                for (int mm = 0; mm < MPPT; ++mm) {
-                    const int i0 = tid + mm * CH_BLOCK;
-                    const int cy = i0 / MX, cx = i0 - cy * MX;
-                    const int gx = m.x0 + cx, gy = m.y0 + cy;
-                    const bool inb = gx < n && gy < n;
-                    const int c = (cy + 1) * MQX + (cx + 1);
-                    TV nb = (qmid[c - 1] + qmid[c + 1]) + (qmid[c - MQX] + qmid[c + MQX]);
-                    nb += qlo[c] + qhi[c];
-                    const TV w = inb ? ih2 * (TV(6) * qmid[c] - nb) : TV(0);
-                    bstore<TV>(w, rw, inb && store_w ? (unsigned)(gy * n + gx) * ES : MOFF);
-                    sw[i0] = w;
+                    for (int e = 0; e < NPT; ++e) {
+                        nb[e] += qm2[e] + qn[e];
+                        w[e] = din[e] ? ih2 * (TV(6) * qm1[e] - nb[e]) : TV(0);
+                        ud[e] = din[e] ? double(vm[e]) : 0.0;
+                        wd[e] = double(w[e]);
+                    }
                 }
-                if constexpr (!EARLY) fetch(0, cur);   // the first basis columns, in flight during the barrier
-                __syncthreads();
-                double wd[NPT];
+                const __amdgpu_buffer_rsrc_t rw = plane_rsrc(W + (size_t)zo * n2, pv);
+                if constexpr (VEC) {
+                    bstore2<TV>(w, rw, store_w ? dof[0] : MOFF);
+                } else {
 #pragma unroll
-                for (int e = 0; e < NPT; ++e) wd[e] = double(sw[dsw[e]]);
+                    for (int e = 0; e < NPT; ++e) bstore<TV>(w[e], rw, store_w ? dof[e] : MOFF);
+                }
+                if constexpr (!EARLY) fetch(0, cur);
                 // the loads of the next four columns are in flight while this
                 // block is summed
-                for (int l0 = 0; l0 < kg; l0 += RB) {
+                for (int l0 = 0; l0 < k; l0 += RB) {
                     TV nxt[RB][NPT];
                     fetch(l0 + RB, nxt);
                     double a[8];
@@ -337,10 +382,7 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
                     }
                     const double tot = wave_sum8(a);
                     const int l = l0 + (hv >> 1);
-                    if (hv >= 0 && l < kg) {
-                        const int c = grp + CG * l;
-                        red[(hv & 1) ? k + c : c][wid] += tot;
-                    }
+                    if (hv >= 0 && l < k) red[(hv & 1) ? k + l : l][wid] += tot;
                 }
                 double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -349,15 +391,20 @@ __global__ __launch_bounds__(CH_BLOCK, sizeof(TV) == 4 ? 4 : 3) void k_matvec_m(
                     a[1] += ud[e] * wd[e];
                 }
                 const double tot = wave_sum8(a);
-                if (grp == 0 && (hv == 0 || hv == 1)) red[2 * k + hv][wid] += tot;
-            } else {
-                __syncthreads();   // the q pass's reads of plane p - 1 are done
+                if (hv == 0 || hv == 1) red[2 * k + hv][wid] += tot;
             }
-            // the loaded planes into their slots: operand p + 2 replaces
-            // p - 1, d(p + 1) replaces d(p - 1) (last read in the previous step)
+            // operand plane p + 2 into the slot of plane p - 1; d(p + 1)
             if (more) {
                 store_v(p + 2, nv);
-                store_d(p + 1, ny);
+#pragma unroll
+                for (int l = 0; l < NQL; ++l) dr[l] = mdcoef(TV(ny[l]), eyre);
+            }
+#pragma unroll
+            for (int l = 0; l < NQL; ++l) vm[l] = vc[l];
+#pragma unroll
+            for (int e = 0; e < NPT; ++e) {
+                qm2[e] = qm1[e];
+                qm1[e] = qn[e];
             }
             __syncthreads();
         }
@@ -385,8 +432,7 @@ template <typename TV, typename TY>
 static void launch_matvec_m(const Table& t, const DevBuffers& b, const TY* y, int k, int store_w, double* pout,
                             bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
-    constexpr int NPT = 16 / (int)sizeof(TV);   // dot-phase points per thread
-    const bool vec = t.hinst[0].n % NPT == 0;
+    const bool vec = t.hinst[0].n % MGeo<TV>::NPT == 0;   // the tile pair as one vector
     if (k > CH_MSMALL) {
         if (timing) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 2, true>), MARGS, V, b.ldv, k, store_w, y, pout);
         else if (t.ninst == 1) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 2, true>), MARGS, V, b.ldv, k, store_w, y, pout);
