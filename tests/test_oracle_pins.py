@@ -511,6 +511,33 @@ def test_pc_estimate_small_mode_linearised(ubar, k, tau):
     assert est == pytest.approx(want, rel=1e-5)
 
 
+def test_pc_estimate_is_second_order_for_the_lim_step():
+    """For tau lambda_max <= 1 eq. p gives p = 1 and the LIM step is explicit
+    Euler, y^{n+1} = y + tau f(y); then y^{n+1} - y_PC = tau/2 (f(y) - f(y +
+    tau f)) = -tau^2/2 f'(y) f + O(tau^3), so on a smooth state est ||y_PC|| /
+    (tau^2/2 ||f'(y) f||) -> 1 and halving tau divides est by 4 (the order the
+    eq. LIMdt rule is not built for; the paper reports observing est = O(tau))."""
+    n = 16
+    prob = O.Problem(2, n, 0.1)
+    y = fourier_mode(n, 2, (1, 0), 0.4) + fourier_mode(n, 2, (1, 1), 0.2) + 0.1
+    lam = O.lambda_max(y, prob)
+    f = O.rhs(y, prob)
+    ds = 1e-6 / np.abs(f).max()
+    Jf = (O.rhs(y + ds * f, prob) - O.rhs(y - ds * f, prob)) / (2 * ds)
+    ests = []
+    for c in (0.02, 0.01, 0.005):
+        tau = c / lam
+        y1, p = O.lim_step(y, prob, tau)
+        assert p == 1
+        np.testing.assert_allclose(y1, y + tau * f, rtol=0, atol=1e-14)
+        est, ypc = O.pc_estimate(y, y1, tau, prob)
+        lead = 0.5 * tau ** 2 * np.linalg.norm(Jf) / np.linalg.norm(ypc)
+        assert est == pytest.approx(lead, rel=0.03), (c, est, lead)
+        ests.append(est)
+    assert ests[0] / ests[1] == pytest.approx(4.0, rel=0.05)
+    assert ests[1] / ests[2] == pytest.approx(4.0, rel=0.05)
+
+
 # --- P13: controller rules ------------------------------------------------------------------
 
 def test_controller_rules_table():
