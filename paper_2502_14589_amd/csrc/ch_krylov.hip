@@ -215,9 +215,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void* p, unsig
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-template <typename VT>
+// AUX: the cache-policy bits of the load (2: non-temporal).
+template <typename VT, int AUX = 0>
 __device__ __forceinline__ VT load16(__amdgpu_buffer_rsrc_t r, unsigned bo) {
-    return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(r, bo, 0u, 0));
+    return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b128(r, bo, 0u, AUX));
 }
 
 template <typename VT>
@@ -230,8 +231,9 @@ __device__ __forceinline__ void store16(VT v, __amdgpu_buffer_rsrc_t r, unsigned
 // of cblk * CH_BLOCK * Q; thread t of the workgroups handles vectors t,
 // t + cblk * CH_BLOCK, ... of each span.  Basis columns come in blocks of two
 // through two buffers that alternate, so the loads of one block are in
-// flight while the other is summed and no loaded value is copied.
-template <typename TV, bool SINGLE, int TAG>
+// flight while the other is summed and no loaded value is copied.  NT: the
+// basis columns are loaded with the streaming hint (stream_columns).
+template <typename TV, bool SINGLE, int TAG, bool NT>
 __device__ __forceinline__ void dc_update_wg(DcCoef& C, Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                              const int* __restrict__ cb2i, const Inst& inst0, int bid,
                                              TV* __restrict__ V, size_t ldv, int j) {
@@ -271,7 +273,7 @@ __device__ __forceinline__ void dc_update_wg(DcCoef& C, Ctl* __restrict__ ctls, 
             const bool live = i < j;
             const __amdgpu_buffer_rsrc_t rc = vrs(Vi + (size_t)(live ? i : 0) * ldv, v0);
 #pragma unroll
-            for (int u = 0; u < Q; ++u) b[r][u] = load16<VT>(rc, live ? rel[u] : DCU_OFF);
+            for (int u = 0; u < Q; ++u) b[r][u] = load16<VT, NT ? 2 : 0>(rc, live ? rel[u] : DCU_OFF);
         }
     };
     // the first vectors and basis columns are requested before the
@@ -363,14 +365,14 @@ __device__ __forceinline__ void report_launch(int* dprog, int* dcount) {
         *dprog = __hip_atomic_fetch_add(dcount, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
 }
 
-template <typename TV, bool SINGLE, int TAG>   // TAG: as for the matvec
+template <typename TV, bool SINGLE, int TAG, bool NT>   // TAG: as for the matvec
 __global__ __launch_bounds__(CH_BLOCK) void k_dc_update(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                         const int* __restrict__ cb2i, const Inst inst0, int ninst,
                                                         TV* __restrict__ V, size_t ldv, int j,
                                                         int* __restrict__ dprog, int* __restrict__ dcount) {
     report_launch(dprog, dcount);
     __shared__ DcCoef C;
-    dc_update_wg<TV, SINGLE, TAG>(C, ctls, insts, cb2i, inst0, blockIdx.x, V, ldv, j);
+    dc_update_wg<TV, SINGLE, TAG, NT>(C, ctls, insts, cb2i, inst0, blockIdx.x, V, ldv, j);
 }
 
 // Iteration j = m_max: column j - 1 of H only (one workgroup per instance).
@@ -1039,7 +1041,7 @@ __device__ __forceinline__ void dc_phi_wg(DcPhiLds& L, Ctl* __restrict__ ctls, c
 // An update workgroup that starts after the test of its own launch has ended
 // the cycle skips its share; the columns j and j + 1 it would write are not
 // read by a finished cycle (its result uses columns 0..j-1 and u).
-template <typename TV, bool SINGLE>
+template <typename TV, bool SINGLE, bool NT>
 __global__ __launch_bounds__(CH_BLOCK, 3) void k_dc_update_phi(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                             const int* __restrict__ cb2i, const Inst inst0, int ninst,
                                                             TV* __restrict__ V, size_t ldv, int j,
@@ -1051,7 +1053,7 @@ __global__ __launch_bounds__(CH_BLOCK, 3) void k_dc_update_phi(Ctl* __restrict__
         dc_phi_wg<SINGLE>(L, ctls, insts, inst0, blockIdx.x, j, dflags);
         return;
     }
-    dc_update_wg<TV, SINGLE, 0>(L.C, ctls, insts, cb2i, inst0, blockIdx.x - ninst, V, ldv, j);
+    dc_update_wg<TV, SINGLE, 0, NT>(L.C, ctls, insts, cb2i, inst0, blockIdx.x - ninst, V, ldv, j);
 }
 
 // MGS iteration k: dimension j = k + 1, h_{j+1,j} from the norm partials of
@@ -1679,31 +1681,43 @@ hipError_t launch_dots_reduce(const Table& t, const DevBuffers& b, int k, hipStr
     return hipGetLastError();
 }
 
-template <typename TV>
-static void launch_dc_update_t(const Table& t, const DevBuffers& b, int j, bool timing, hipStream_t s) {
+template <typename TV, bool NT>
+static void launch_dc_update_nt(const Table& t, const DevBuffers& b, int j, bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     if (timing) {
-        hipLaunchKernelGGL((k_dc_update<TV, true, 1>), CARGS, V, b.ldv, j, nullptr, nullptr);
+        hipLaunchKernelGGL((k_dc_update<TV, true, 1, NT>), CARGS, V, b.ldv, j, nullptr, nullptr);
         return;
     }
     if (b.hseq) ++*b.hseq;
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_dc_update<TV, true, 0>), CARGS, V, b.ldv, j, b.dprog, b.dcount);
+        hipLaunchKernelGGL((k_dc_update<TV, true, 0, NT>), CARGS, V, b.ldv, j, b.dprog, b.dcount);
     else
-        hipLaunchKernelGGL((k_dc_update<TV, false, 0>), CARGS, V, b.ldv, j, b.dprog, b.dcount);
+        hipLaunchKernelGGL((k_dc_update<TV, false, 0, NT>), CARGS, V, b.ldv, j, b.dprog, b.dcount);
 }
 
 template <typename TV>
-static void launch_dc_update_phi_t(const Table& t, const DevBuffers& b, int j, hipStream_t s) {
+static void launch_dc_update_t(const Table& t, const DevBuffers& b, int j, bool timing, hipStream_t s) {
+    if (stream_columns(b.ldv, sizeof(TV), j)) launch_dc_update_nt<TV, true>(t, b, j, timing, s);
+    else launch_dc_update_nt<TV, false>(t, b, j, timing, s);
+}
+
+template <typename TV, bool NT>
+static void launch_dc_update_phi_nt(const Table& t, const DevBuffers& b, int j, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     const dim3 grid(t.ninst + t.cgrid);
     if (b.hseq) ++*b.hseq;
     if (t.ninst == 1)
-        hipLaunchKernelGGL((k_dc_update_phi<TV, true>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i, t.hinst[0],
-                           t.ninst, V, b.ldv, j, b.dflag, b.dprog, b.dcount);
-    else
-        hipLaunchKernelGGL((k_dc_update_phi<TV, false>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i,
+        hipLaunchKernelGGL((k_dc_update_phi<TV, true, NT>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i,
                            t.hinst[0], t.ninst, V, b.ldv, j, b.dflag, b.dprog, b.dcount);
+    else
+        hipLaunchKernelGGL((k_dc_update_phi<TV, false, NT>), grid, dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.cb2i,
+                           t.hinst[0], t.ninst, V, b.ldv, j, b.dflag, b.dprog, b.dcount);
+}
+
+template <typename TV>
+static void launch_dc_update_phi_t(const Table& t, const DevBuffers& b, int j, hipStream_t s) {
+    if (stream_columns(b.ldv, sizeof(TV), j)) launch_dc_update_phi_nt<TV, true>(t, b, j, s);
+    else launch_dc_update_phi_nt<TV, false>(t, b, j, s);
 }
 
 hipError_t launch_dc_update(const Table& t, int prec, const DevBuffers& b, int j, hipStream_t s, bool timing,

@@ -73,19 +73,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, unsi
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-template <typename T>
+// AUX: the cache-policy bits of the load (2: non-temporal).
+template <typename T, int AUX = 0>
 __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned bo) {
-    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, bo, 0u, 0));
-    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, bo, 0u, 0));
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, bo, 0u, AUX));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, bo, 0u, AUX));
 }
 
 // Two consecutive values (one buffer load of 16 bytes in FP64, 8 in FP32).
-template <typename T>
+template <typename T, int AUX = 0>
 __device__ __forceinline__ void bload2(__amdgpu_buffer_rsrc_t r, unsigned bo, T (&v)[2]) {
     struct P { T e[2]; };
     P p;
-    if constexpr (sizeof(T) == 8) p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b128(r, bo, 0u, 0));
-    else p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b64(r, bo, 0u, 0));
+    if constexpr (sizeof(T) == 8) p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b128(r, bo, 0u, AUX));
+    else p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b64(r, bo, 0u, AUX));
     v[0] = p.e[0];
     v[1] = p.e[1];
 }
@@ -142,8 +143,9 @@ __device__ __forceinline__ MarchItem march_item(int it, int n) {
 // takes the buffer of q(p - 2), last read in step p - 1.
 // DV: the dot-phase form -- 1: the tile pair as one vector (n even), 0: two
 // scalar points, 2: chosen per instance at run time (batches).  BIGK: room
-// for the dot rows of iterations k > CH_MSMALL.
-template <typename TV, typename TY, bool SINGLE, int TAG, int DV, bool BIGK>
+// for the dot rows of iterations k > CH_MSMALL.  NT: the basis columns are
+// loaded with the streaming hint (stream_columns).
+template <typename TV, typename TY, bool SINGLE, int TAG, int DV, bool BIGK, bool NT>
 __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        TV* __restrict__ V, size_t ldv, int k, int store_w,
@@ -291,10 +293,10 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
                     const bool live = dots && l0 + r < k;
                     const __amdgpu_buffer_rsrc_t rs = plane_rsrc(colbase + (size_t)(live ? l0 + r : 0) * ldv, pv);
                     if constexpr (VEC) {
-                        bload2<TV>(rs, live ? dof[0] : MOFF, v[r]);
+                        bload2<TV, NT ? 2 : 0>(rs, live ? dof[0] : MOFF, v[r]);
                     } else {
 #pragma unroll
-                        for (int e = 0; e < NPT; ++e) v[r][e] = bload<TV>(rs, live ? dof[e] : MOFF);
+                        for (int e = 0; e < NPT; ++e) v[r][e] = bload<TV, NT ? 2 : 0>(rs, live ? dof[e] : MOFF);
                     }
                 }
             };
@@ -428,24 +430,31 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
 // ---------------------------------------------------------------------------
 #define MARGS dim3(t.wgrid), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.wb2i, t.hinst[0], t.ninst
 
-template <typename TV, typename TY>
+template <typename TV, typename TY, bool NT>
 static void launch_matvec_m(const Table& t, const DevBuffers& b, const TY* y, int k, int store_w, double* pout,
                             bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     const bool vec = t.hinst[0].n % MGeo<TV>::NPT == 0;   // the tile pair as one vector
     if (k > CH_MSMALL) {
-        if (timing) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 2, true>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else if (t.ninst == 1) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 2, true>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, true>), MARGS, V, b.ldv, k, store_w, y, pout);
+        if (timing) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 2, true, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else if (t.ninst == 1) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 2, true, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, true, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
     } else if (timing) {
-        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 1, false>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 0, false>), MARGS, V, b.ldv, k, store_w, y, pout);
+        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 1, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 0, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
     } else if (t.ninst == 1) {
-        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 1, false>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 0, false>), MARGS, V, b.ldv, k, store_w, y, pout);
+        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 1, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 0, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
     } else {
-        hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, false>), MARGS, V, b.ldv, k, store_w, y, pout);
+        hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
     }
+}
+
+template <typename TV, typename TY>
+static void launch_matvec_m(const Table& t, const DevBuffers& b, const TY* y, int k, int store_w, double* pout,
+                            bool timing, hipStream_t s) {
+    if (stream_columns(b.ldv, sizeof(TV), k)) launch_matvec_m<TV, TY, true>(t, b, y, k, store_w, pout, timing, s);
+    else launch_matvec_m<TV, TY, false>(t, b, y, k, store_w, pout, timing, s);
 }
 
 hipError_t launch_matvec_march(const Table& t, int prec, const DevBuffers& b, const double* y, int k, bool store_w,
