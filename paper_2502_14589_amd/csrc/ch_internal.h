@@ -210,15 +210,6 @@ hipError_t launch_lim_stage2_strip(const Table& t, const DevBuffers& b, const do
                                    bool timing, hipStream_t s);
 hipError_t launch_est_ee_strip(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
                                double* pout, hipStream_t s);
-// Basis columns 0..k are read by the matvec and the update of DCGS2 iteration
-// k and again by the next iteration.  Once they exceed the last-level cache
-// (256 MB on this part) that cyclic scan gets no hits from it, and the column
-// loads carry the streaming (non-temporal) hint so that they do not displace
-// what is reused (the stencil halos, w, u).  Below that they keep the default
-// policy and stay cached between iterations.
-constexpr double CH_LLC_BYTES = 256.0 * 1024.0 * 1024.0;
-inline bool stream_columns(size_t ldv, size_t esz, int k) { return double(ldv) * double(esz) * (k + 1) > CH_LLC_BYTES; }
-
 // 3-D DCGS2 matvec on z-marching x-y tiles (ch_march.hip); its workgroups are
 // the instance's wblk range, so its partials are of kind PK_STRIP too.
 hipError_t launch_matvec_march(const Table& t, int prec, const DevBuffers& b, const double* y, int k, bool store_w,

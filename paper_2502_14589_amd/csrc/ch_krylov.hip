@@ -15,6 +15,7 @@
 // workgroups [cblk0, cblk0 + cblk) (map cb2i), single-workgroup kernels one
 // workgroup per instance.
 #include "ch_common.h"
+#include "ch_stream.h"
 
 #include <algorithm>
 #include <cstdint>

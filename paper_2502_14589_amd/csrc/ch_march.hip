@@ -23,6 +23,7 @@
 // the tile, against (TX + 4)(TY + 4)(TZ + 4) / (TX TY TZ) = 4.5 for a
 // 32 x 4 x 4 tile staged whole.
 #include "ch_common.h"
+#include "ch_stream.h"
 
 #include <type_traits>
 
