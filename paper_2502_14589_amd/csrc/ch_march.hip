@@ -92,21 +92,21 @@ __device__ __forceinline__ void bload2(__amdgpu_buffer_rsrc_t r, unsigned bo, T 
     v[1] = p.e[1];
 }
 
-template <typename T>
+template <typename T, int AUX = 0>
 __device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned bo) {
     using u32x2 = unsigned __attribute__((ext_vector_type(2)));
-    if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, bo, 0u, 0);
-    else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, bo, 0u, 0);
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, bo, 0u, AUX);
+    else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, bo, 0u, AUX);
 }
 
-template <typename T>
+template <typename T, int AUX = 0>
 __device__ __forceinline__ void bstore2(const T (&v)[2], __amdgpu_buffer_rsrc_t r, unsigned bo) {
     struct P { T e[2]; };
     const P p{{v[0], v[1]}};
     using u32x2 = unsigned __attribute__((ext_vector_type(2)));
     using u32x4 = unsigned __attribute__((ext_vector_type(4)));
-    if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, p), r, bo, 0u, 0);
-    else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, p), r, bo, 0u, 0);
+    if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, p), r, bo, 0u, AUX);
+    else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, p), r, bo, 0u, AUX);
 }
 
 // Work item it of an instance: x-y tile and run of planes.
@@ -145,8 +145,9 @@ __device__ __forceinline__ MarchItem march_item(int it, int n) {
 // DV: the dot-phase form -- 1: the tile pair as one vector (n even), 0: two
 // scalar points, 2: chosen per instance at run time (batches).  BIGK: room
 // for the dot rows of iterations k > CH_MSMALL.  NT: the basis columns are
-// loaded with the streaming hint (stream_columns).
-template <typename TV, typename TY, bool SINGLE, int TAG, int DV, bool BIGK, bool NT>
+// loaded with the streaming hint (stream_columns); NTW: w is stored with it
+// (stream_store).
+template <typename TV, typename TY, bool SINGLE, int TAG, int DV, bool BIGK, bool NT, bool NTW>
 __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        TV* __restrict__ V, size_t ldv, int k, int store_w,
@@ -361,10 +362,10 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
                 }
                 const __amdgpu_buffer_rsrc_t rw = plane_rsrc(W + (size_t)zo * n2, pv);
                 if constexpr (VEC) {
-                    bstore2<TV>(w, rw, store_w ? dof[0] : MOFF);
+                    bstore2<TV, NTW ? 2 : 0>(w, rw, store_w ? dof[0] : MOFF);
                 } else {
 #pragma unroll
-                    for (int e = 0; e < NPT; ++e) bstore<TV>(w[e], rw, store_w ? dof[e] : MOFF);
+                    for (int e = 0; e < NPT; ++e) bstore<TV, NTW ? 2 : 0>(w[e], rw, store_w ? dof[e] : MOFF);
                 }
                 if constexpr (!EARLY) fetch(0, cur);
                 // the loads of the next four columns are in flight while this
@@ -431,31 +432,34 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
 // ---------------------------------------------------------------------------
 #define MARGS dim3(t.wgrid), dim3(CH_BLOCK), 0, s, b.ctl, t.inst, t.wb2i, t.hinst[0], t.ninst
 
-template <typename TV, typename TY, bool NT>
+template <typename TV, typename TY, bool NT, bool NTW>
 static void launch_matvec_m(const Table& t, const DevBuffers& b, const TY* y, int k, int store_w, double* pout,
                             bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
     const bool vec = t.hinst[0].n % MGeo<TV>::NPT == 0;   // the tile pair as one vector
     if (k > CH_MSMALL) {
-        if (timing) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 2, true, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else if (t.ninst == 1) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 2, true, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, true, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
+        if (timing) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 2, true, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else if (t.ninst == 1) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 2, true, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, true, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
     } else if (timing) {
-        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 1, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 0, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
+        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 1, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 0, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
     } else if (t.ninst == 1) {
-        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 1, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 0, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
+        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 1, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 0, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
     } else {
-        hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, false, NT>), MARGS, V, b.ldv, k, store_w, y, pout);
+        hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
     }
 }
 
 template <typename TV, typename TY>
 static void launch_matvec_m(const Table& t, const DevBuffers& b, const TY* y, int k, int store_w, double* pout,
                             bool timing, hipStream_t s) {
-    if (stream_columns(b.ldv, sizeof(TV), k)) launch_matvec_m<TV, TY, true>(t, b, y, k, store_w, pout, timing, s);
-    else launch_matvec_m<TV, TY, false>(t, b, y, k, store_w, pout, timing, s);
+    const bool nt = stream_columns(b.ldv, sizeof(TV), k), ntw = stream_store(b.ldv, sizeof(TV), k);
+    if (nt && ntw) launch_matvec_m<TV, TY, true, true>(t, b, y, k, store_w, pout, timing, s);
+    else if (nt) launch_matvec_m<TV, TY, true, false>(t, b, y, k, store_w, pout, timing, s);
+    else if (ntw) launch_matvec_m<TV, TY, false, true>(t, b, y, k, store_w, pout, timing, s);
+    else launch_matvec_m<TV, TY, false, false>(t, b, y, k, store_w, pout, timing, s);
 }
 
 hipError_t launch_matvec_march(const Table& t, int prec, const DevBuffers& b, const double* y, int k, bool store_w,

@@ -11,3 +11,9 @@
 // policy and stay cached between iterations.
 constexpr double CH_LLC_BYTES = 256.0 * 1024.0 * 1024.0;
 inline bool stream_columns(size_t ldv, size_t esz, int k) { return double(ldv) * double(esz) * (k + 1) > CH_LLC_BYTES; }
+
+// The 3-D matvec's w is read back by the update of the same iteration; in
+// between, the two launches move about k + 3 columns (the basis, u, y and w).
+// When those exceed the last-level cache, w does not survive there either, and
+// it is written with the streaming hint, leaving the cache to the halos.
+inline bool stream_store(size_t ldv, size_t esz, int k) { return double(ldv) * double(esz) * (k + 3) > CH_LLC_BYTES; }
