@@ -1,0 +1,10 @@
+// Launchers of the 3-D marching kernels declared outside ch_internal.h.
+#pragma once
+
+#include "ch_internal.h"
+
+// 3-D estimate pass of EE2 on z-marching x-y tiles (ch_march.hip): the same
+// outputs and partials as the tile kernel k_est_ee, over the instance's wblk
+// range (partials of kind PK_STRIP).
+hipError_t launch_est_march(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
+                            double* pout, hipStream_t s);

@@ -425,6 +425,242 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// 3-D estimate pass of EE2 (Fig. 4; eq. LIMest with the EE2 step in place of
+// the LIM step; eqs. IVP, A_g, tol_phi) on the same z-marching tiles: at every
+// point of the grid
+//   f1 = f(y^{n+1}) = -A q,  q = F'(y^{n+1}) + eps^2 A y^{n+1},
+//   g1 = A c,  c = 2 y^3 (+ y with the Eyre splitting)      (ghat at y^{n+1}),
+//   y_PC = y^n + tau/2 (f(y^n) + f1),
+// with the sums of (y^{n+1} - y_PC)^2, y_PC^2, f1^2 and g1^2 as the
+// workgroup's partials.  f1 replaces f(y^n) and becomes the next start vector
+// (basis column 0, in TV); the mixed form also writes the FP32 copy of
+// y^{n+1}.  The operand y^{n+1} keeps a ring of four planes, so that plane p - 1
+// is still there while step p forms g1 on it from c of its in-plane
+// neighbours; the thread's own y of planes p - 2 .. p give c above and below.
+// DV as for the matvec.
+template <typename TV, bool SINGLE, int DV>
+__global__ __launch_bounds__(CH_BLOCK) void k_est_m(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                    const int* __restrict__ wb2i, const Inst inst0, int ninst,
+                                                    const double* __restrict__ y0base, const double* __restrict__ y1base,
+                                                    double* __restrict__ fbase, TV* __restrict__ V0base,
+                                                    float* __restrict__ y32base, double* __restrict__ pout) {
+    using G = MGeo<double>;
+    constexpr int MX = G::MX, MY = G::MY, MVX = G::MVX, MVP = G::MVP, MQX = G::MQX, MQY = G::MQY, MQS = G::MQS,
+                  MQPS = G::MQPS;
+    constexpr int NVL = G::NVL, NPT = G::NPT, TXT = G::TXT, NRING = G::NRING, NQL = G::NQL;
+    static_assert(NPT == 2, "pair passes");
+    const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->halted) return;
+    __shared__ __attribute__((aligned(16))) double sv[4][MVP];
+    __shared__ __attribute__((aligned(16))) double sq[2][MQPS];   // q(x, y) at y * MQS + x + 1
+    const double* y0 = y0base + I.off;
+    const double* y1 = y1base + I.off;
+    double* fcur = fbase + I.off;
+    TV* V0 = V0base + I.off;
+    float* y32 = y32base ? y32base + I.off : nullptr;
+    const int n = I.n, eyre = I.eyre;
+    const size_t n2 = (size_t)n * n;
+    const unsigned pb = (unsigned)n2 * 8u, pt = (unsigned)n2 * (unsigned)sizeof(TV), pf = (unsigned)n2 * 4u;
+    const double ih2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
+    const double half_tau = 0.5 * (ctl->mode == MODE_EE ? ctl->tau_acc : ctl->tau_step);
+    const int tid = threadIdx.x;
+    const int ntx = (n + MX - 1) / MX, nty = (n + MY - 1) / MY;
+    const int nitems = ntx * nty * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
+    const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
+    int qrx[NQL], qry[NQL];
+    const int cx = NPT * (tid % TXT), cy = tid / TXT;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+        qrx[e] = cx + 1 + e;
+        qry[e] = cy + 1;
+    }
+#pragma unroll
+    for (int l = NPT; l < NQL; ++l) {
+        const int r = min(tid + (l - NPT) * CH_BLOCK, NRING - 1);
+        if (r < MQX) {
+            qrx[l] = r;
+            qry[l] = 0;
+        } else if (r < 2 * MQX) {
+            qrx[l] = r - MQX;
+            qry[l] = MQY - 1;
+        } else if (r < 2 * MQX + MY) {
+            qrx[l] = 0;
+            qry[l] = 1 + r - 2 * MQX;
+        } else {
+            qrx[l] = MQX - 1;
+            qry[l] = 1 + r - 2 * MQX - MY;
+        }
+    }
+    auto cc = [eyre](double v) { return 2.0 * v * v * v + (eyre ? v : 0.0); };
+    double a_err = 0.0, a_pc = 0.0, a_f = 0.0, a_g = 0.0;
+    auto items = [&](auto vec_c) {
+    constexpr bool VEC = decltype(vec_c)::value;
+    for (int it = lb; it < nitems; it += I.wblk) {
+        const MarchItem m = march_item<MX, MY>(it, n);
+        unsigned vo[NVL], qpos[NQL];
+#pragma unroll
+        for (int l = 0; l < NVL; ++l) {
+            const int i = min(tid + l * CH_BLOCK, MVP - 1);
+            const int ry = i / MVX, rx = i - ry * MVX;
+            vo[l] = (unsigned)(wrapi(m.y0 - 2 + ry, n) * n + wrapi(m.x0 - 2 + rx, n)) * 8u;
+        }
+#pragma unroll
+        for (int l = 0; l < NQL; ++l)
+            qpos[l] = (unsigned)(wrapi(m.y0 - 1 + qry[l], n) * n + wrapi(m.x0 - 1 + qrx[l], n));
+        const int gx = m.x0 + cx, gy = m.y0 + cy;
+        bool din[NPT];
+        unsigned pidx[NPT];   // plane index of the pair's points (MOFF / 8 outside the grid)
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) {
+            din[e] = gx + e < n && gy < n;
+            pidx[e] = din[e] ? (unsigned)(gy * n + gx + e) : (MOFF >> 3);
+        }
+        auto load_v = [&](int z, double (&r)[NVL]) {
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(y1 + (size_t)wrapi(z, n) * n2, pb);
+#pragma unroll
+            for (int l = 0; l < NVL; ++l) r[l] = bload<double>(rs, vo[l]);
+        };
+        auto store_v = [&](int z, const double (&r)[NVL]) {
+            double* d = sv[(z - m.z0 + 2) & 3];
+#pragma unroll
+            for (int l = 0; l < NVL; ++l) d[min(tid + l * CH_BLOCK, MVP - 1)] = r[l];
+        };
+        // the pair's values of a field plane (y^n, f(y^n)): one 16-byte load, or two
+        auto load_pair = [&](const double* base, int z, double (&v)[NPT]) {
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(base + (size_t)z * n2, pb);
+            if constexpr (VEC) {
+                bload2<double>(rs, pidx[0] * 8u, v);
+            } else {
+#pragma unroll
+                for (int e = 0; e < NPT; ++e) v[e] = bload<double>(rs, pidx[e] * 8u);
+            }
+        };
+        const int z0 = m.z0;
+        // carried between steps: y of the plane below at the q points, y two
+        // planes below and q one and two planes below at the tile pair
+        double vm[NQL], ym2[NPT], qm2[NPT], qm1[NPT];
+        {
+            double a[NVL], b[NVL];
+            load_v(z0 - 1, a);
+            load_v(z0, b);
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(y1 + (size_t)wrapi(z0 - 2, n) * n2, pb);
+#pragma unroll
+            for (int l = 0; l < NQL; ++l) vm[l] = bload<double>(rs, qpos[l] * 8u);
+            store_v(z0 - 1, a);
+            store_v(z0, b);
+#pragma unroll
+            for (int e = 0; e < NPT; ++e) ym2[e] = qm2[e] = qm1[e] = 0.0;
+            __syncthreads();
+        }
+        for (int p = z0 - 1; p <= z0 + m.zl; ++p) {
+            const int zo = p - 1;   // plane of this step's f1, g1 and sums
+            const bool more = p + 1 <= z0 + m.zl;
+            const bool outp = zo >= z0;
+            double o0[NPT], of[NPT];
+            if (outp) {   // y^n and f(y^n) at the pair, in flight during the q pass
+                load_pair(y0, zo, o0);
+                load_pair(fcur, zo, of);
+            }
+            double nv[NVL];
+            if (more) load_v(p + 2, nv);
+            double vc[NQL], qn[NQL];
+            {
+                const double* v0 = sv[(p - z0 + 2) & 3];
+                const double* vp = sv[(p - z0 + 3) & 3];
+                double* qd = sq[(p - z0 + 1) & 1];
+                const int c = (qry[0] + 1) * MVX + (qrx[0] + 1);
+                const LPair<double> lft = lds_pair(v0 + c - 2), mid = lds_pair(v0 + c), rgt = lds_pair(v0 + c + 2);
+                const LPair<double> up = lds_pair(v0 + c - MVX), dn = lds_pair(v0 + c + MVX), ab = lds_pair(vp + c);
+                vc[0] = mid.a;
+                vc[1] = mid.b;
+                double nb0 = (lft.b + mid.b) + (up.a + dn.a);
+                double nb1 = (mid.a + rgt.a) + (up.b + dn.b);
+                nb0 += vm[0] + ab.a;
+                nb1 += vm[1] + ab.b;
+                qn[0] = vc[0] * (vc[0] * vc[0] - 1.0) + e2ih2 * (6.0 * vc[0] - nb0);
+                qn[1] = vc[1] * (vc[1] * vc[1] - 1.0) + e2ih2 * (6.0 * vc[1] - nb1);
+                *reinterpret_cast<LPair<double>*>(qd + qry[0] * MQS + qrx[0] + 1) = LPair<double>{qn[0], qn[1]};
+#pragma unroll
+                for (int l = NPT; l < NQL; ++l) {
+                    const int cr = (qry[l] + 1) * MVX + (qrx[l] + 1);
+                    vc[l] = v0[cr];
+                    double nb = (v0[cr - 1] + v0[cr + 1]) + (v0[cr - MVX] + v0[cr + MVX]);
+                    nb += vm[l] + vp[cr];
+                    qn[l] = vc[l] * (vc[l] * vc[l] - 1.0) + e2ih2 * (6.0 * vc[l] - nb);
+                    qd[qry[l] * MQS + qrx[l] + 1] = qn[l];
+                }
+            }
+            if (outp) {
+                // f1 = -A q and g1 = A c on plane p - 1 at the pair
+                const double* qmid = sq[(p - z0) & 1];
+                const double* ym = sv[(p - z0 + 1) & 3];   // y of plane p - 1
+                const int c = qry[0] * MQS + qrx[0] + 1;
+                const LPair<double> lft = lds_pair(qmid + c - 2), rgt = lds_pair(qmid + c + 2);
+                const LPair<double> up = lds_pair(qmid + c - MQS), dn = lds_pair(qmid + c + MQS);
+                double nb[NPT] = {(lft.b + qm1[1]) + (up.a + dn.a), (qm1[0] + rgt.a) + (up.b + dn.b)};
+                const int cv = (qry[0] + 1) * MVX + (qrx[0] + 1);
+                const LPair<double> yl = lds_pair(ym + cv - 2), yr = lds_pair(ym + cv + 2);
+                const LPair<double> yu = lds_pair(ym + cv - MVX), yd = lds_pair(ym + cv + MVX);
+                const double c0 = cc(vm[0]), c1 = cc(vm[1]);
+                double gb[NPT] = {(cc(yl.b) + c1) + (cc(yu.a) + cc(yd.a)), (c0 + cc(yr.a)) + (cc(yu.b) + cc(yd.b))};
+                const double cown[NPT] = {c0, c1};
+                double f1[NPT];
+                TV ft[NPT];
+                float yf[NPT];
+#pragma unroll
+                for (int e = 0; e < NPT; ++e) {
+                    nb[e] += qm2[e] + qn[e];
+                    gb[e] += cc(ym2[e]) + cc(vc[e]);
+                    f1[e] = -ih2 * (6.0 * qm1[e] - nb[e]);
+                    const double g1 = ih2 * (6.0 * cown[e] - gb[e]);
+                    const double ypc = o0[e] + half_tau * (of[e] + f1[e]);
+                    const double er = vm[e] - ypc;
+                    if (din[e]) {
+                        a_err += er * er;
+                        a_pc += ypc * ypc;
+                        a_f += f1[e] * f1[e];
+                        a_g += g1 * g1;
+                    }
+                    ft[e] = TV(f1[e]);
+                    yf[e] = float(vm[e]);
+                }
+                const __amdgpu_buffer_rsrc_t rf = plane_rsrc(fcur + (size_t)zo * n2, pb);
+                const __amdgpu_buffer_rsrc_t rt = plane_rsrc(V0 + (size_t)zo * n2, pt);
+                if constexpr (VEC) {
+                    bstore2<double>(f1, rf, pidx[0] * 8u);
+                    bstore2<TV>(ft, rt, pidx[0] * (unsigned)sizeof(TV));
+                    if (y32) bstore2<float>(yf, plane_rsrc(y32 + (size_t)zo * n2, pf), pidx[0] * 4u);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < NPT; ++e) {
+                        bstore<double>(f1[e], rf, pidx[e] * 8u);
+                        bstore<TV>(ft[e], rt, pidx[e] * (unsigned)sizeof(TV));
+                        if (y32) bstore<float>(yf[e], plane_rsrc(y32 + (size_t)zo * n2, pf), pidx[e] * 4u);
+                    }
+                }
+            }
+            if (more) store_v(p + 2, nv);   // into the slot of plane p - 2
+#pragma unroll
+            for (int e = 0; e < NPT; ++e) {
+                ym2[e] = vm[e];
+                qm2[e] = qm1[e];
+                qm1[e] = qn[e];
+            }
+#pragma unroll
+            for (int l = 0; l < NQL; ++l) vm[l] = vc[l];
+            __syncthreads();
+        }
+    }
+    };
+    if (DV == 1 || (DV == 2 && n % NPT == 0)) items(std::true_type{});
+    else items(std::false_type{});
+    double x[4] = {a_err, a_pc, a_f, a_g};
+    write_partials<4, RED_SUM>(x, pout);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -467,5 +703,26 @@ hipError_t launch_matvec_march(const Table& t, int prec, const DevBuffers& b, co
     const int sw = store_w ? 1 : 0;
     if (prec == CH_FP64) launch_matvec_m<double, double>(t, b, y, k, sw, pout, timing, s);
     else launch_matvec_m<float, float>(t, b, b.y32, k, sw, pout, timing, s);
+    return hipGetLastError();
+}
+
+template <typename TV>
+static void launch_est_m(const Table& t, const DevBuffers& b, const double* y0, const double* y1, float* y32,
+                         double* pout, hipStream_t s) {
+    TV* V0 = static_cast<TV*>(b.V);
+    if (t.ninst == 1) {
+        if (t.hinst[0].n % MGeo<double>::NPT == 0)
+            hipLaunchKernelGGL((k_est_m<TV, true, 1>), MARGS, y0, y1, b.fcur, V0, y32, pout);
+        else
+            hipLaunchKernelGGL((k_est_m<TV, true, 0>), MARGS, y0, y1, b.fcur, V0, y32, pout);
+    } else {
+        hipLaunchKernelGGL((k_est_m<TV, false, 2>), MARGS, y0, y1, b.fcur, V0, y32, pout);
+    }
+}
+
+hipError_t launch_est_march(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
+                            double* pout, hipStream_t s) {
+    if (prec == CH_FP64) launch_est_m<double>(t, b, y0, y1, nullptr, pout, s);
+    else launch_est_m<float>(t, b, y0, y1, b.y32, pout, s);
     return hipGetLastError();
 }

@@ -13,6 +13,7 @@
 // One launch covers every instance of a batch: workgroup b works on instance
 // sb2i[b], on the tiles lb, lb + sblk, ... of that instance (lb = b - sblk0).
 #include "ch_common.h"
+#include "ch_march.h"
 
 namespace {
 
@@ -563,6 +564,11 @@ hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq&
                          const double* y1, hipStream_t s) {
     if (uses_strips(t)) {
         const hipError_t e = launch_est_ee_strip(t, prec, b, y0, y1, ps.out(), s);
+        ps.produced(PK_STRIP);
+        return e;
+    }
+    if (t.dim == 3) {
+        const hipError_t e = launch_est_march(t, prec, b, y0, y1, ps.out(), s);
         ps.produced(PK_STRIP);
         return e;
     }
