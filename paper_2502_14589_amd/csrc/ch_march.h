@@ -3,8 +3,9 @@
 
 #include "ch_internal.h"
 
-// 3-D estimate pass of EE2 on z-marching x-y tiles (ch_march.hip): the same
-// outputs and partials as the tile kernel k_est_ee, over the instance's wblk
-// range (partials of kind PK_STRIP).
+// 3-D estimate pass of EE2 on z-marching x-y tiles (ch_march.hip): f(y^{n+1})
+// into the field f and basis column 0 (and the FP32 copy of y^{n+1} in the
+// mixed form), with the partials of the estimate sums and of ||f||^2 and
+// ||ghat||^2 over the instance's wblk range (partials of kind PK_STRIP).
 hipError_t launch_est_march(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
                             double* pout, hipStream_t s);

@@ -278,73 +278,6 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctls, cons
 }
 
 // ---------------------------------------------------------------------------
-// EE2 estimate and next start vector (Fig. 4; eq. LIMest):
-//   f1 = f(y^{n+1});  y_PC = y^n + tau/2 (f(y^n) + f1)  (eq. LIMest, since
-//   f(y) = -A (F'(y) + eps^2 A y));  est = ||y^{n+1} - y_PC|| / ||y_PC||.
-// f1 becomes the next step's f(y^n) and start vector; ||A c(y^{n+1})|| the next
-// ||ghat||.  Partials of the four sums go to the step controller.
-// ---------------------------------------------------------------------------
-template <int DIM, typename TV, bool SINGLE>
-__global__ __launch_bounds__(CH_BLOCK) void k_est_ee(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
-                                                     const int* __restrict__ sb2i, const Inst inst0, int ninst, const double* __restrict__ y0base,
-                                                     const double* __restrict__ y1base, double* __restrict__ fbase,
-                                                     TV* __restrict__ V0base, float* __restrict__ y32base,
-                                                     double* __restrict__ pout) {
-    const Inst I = SINGLE ? inst0 : insts[sb2i[blockIdx.x]];
-    Ctl* ctl = ctls + I.slot;
-    if (ctl->halted) return;
-    using R1 = Region<DIM, 1>;
-    using R2 = Region<DIM, 2>;
-    __shared__ double s1[R2::SIZE];
-    __shared__ double sq[R1::SIZE];
-    __shared__ double sc[R1::SIZE];
-    const double* y0 = y0base + I.off;
-    const double* y1 = y1base + I.off;
-    double* fcur = fbase + I.off;
-    TV* V0 = V0base + I.off;
-    float* y32 = y32base ? y32base + I.off : nullptr;
-    const int n = I.n, eyre = I.eyre;
-    const double inv_h2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
-    int ntx, nty;
-    const int nt = num_tiles<DIM>(n, ntx, nty);
-    const int lb = blockIdx.x - I.sblk0;
-    const double half_tau = 0.5 * (ctl->mode == MODE_EE ? ctl->tau_acc : ctl->tau_step);
-    double a_err = 0.0, a_pc = 0.0, a_f = 0.0, a_g = 0.0;
-    for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
-        const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_region<DIM, 2>(o, n, I.bc, y1, [&](int i, double v) { s1[i] = v; });
-        __syncthreads();
-        for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK) {
-            const double v = s1[r1_to_r2<DIM>(i)];
-            sq[i] = v * (v * v - 1.0) + e2ih2 * lap2_at_r1<DIM>(s1, i);
-            sc[i] = ccoef(v, eyre);
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < tile_points<DIM>(); i += CH_BLOCK) {
-            int i1;
-            size_t gi;
-            if (out_point<DIM>(i, o, n, i1, gi)) {
-                const double f1 = -inv_h2 * lap1_at<DIM>(sq, i1);
-                const double g1 = inv_h2 * lap1_at<DIM>(sc, i1);
-                const double ypc = y0[gi] + half_tau * (fcur[gi] + f1);
-                const double yv = y1[gi];
-                const double e = yv - ypc;
-                a_err += e * e;
-                a_pc += ypc * ypc;
-                a_f += f1 * f1;
-                a_g += g1 * g1;
-                fcur[gi] = f1;
-                V0[gi] = TV(f1);
-                if (y32) y32[gi] = float(yv);
-            }
-        }
-        __syncthreads();
-    }
-    double x[4] = {a_err, a_pc, a_f, a_g};
-    write_partials<4, RED_SUM>(x, pout);
-}
-
-// ---------------------------------------------------------------------------
 // LIM stage (one iteration of Fig. 1):
 //   y_next = (y^n + tau a_m z + tau (ghat - Ahat z)) / (1 + tau a_m)
 // ---------------------------------------------------------------------------
@@ -549,17 +482,6 @@ hipError_t launch_resid(const Table& t, int prec, const DevBuffers& b, PartSeq& 
                       : launch_resid_t<3, float>(t, b, ps, y, z, write_f, write_y32, s);
 }
 
-template <int DIM, typename TV>
-static hipError_t launch_est_ee_t(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y0,
-                                  const double* y1, float* y32, hipStream_t s) {
-    if (t.ninst == 1)
-        hipLaunchKernelGGL((k_est_ee<DIM, TV, true>), SARGS, y0, y1, b.fcur, static_cast<TV*>(b.V), y32, ps.out());
-    else
-        hipLaunchKernelGGL((k_est_ee<DIM, TV, false>), SARGS, y0, y1, b.fcur, static_cast<TV*>(b.V), y32, ps.out());
-    ps.produced(PK_TILE);
-    return hipGetLastError();
-}
-
 hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq& ps, const double* y0,
                          const double* y1, hipStream_t s) {
     if (uses_strips(t)) {
@@ -567,16 +489,9 @@ hipError_t launch_est_ee(const Table& t, int prec, const DevBuffers& b, PartSeq&
         ps.produced(PK_STRIP);
         return e;
     }
-    if (t.dim == 3) {
-        const hipError_t e = launch_est_march(t, prec, b, y0, y1, ps.out(), s);
-        ps.produced(PK_STRIP);
-        return e;
-    }
-    if (prec == CH_FP64)
-        return t.dim == 2 ? launch_est_ee_t<2, double>(t, b, ps, y0, y1, nullptr, s)
-                          : launch_est_ee_t<3, double>(t, b, ps, y0, y1, nullptr, s);
-    return t.dim == 2 ? launch_est_ee_t<2, float>(t, b, ps, y0, y1, b.y32, s)
-                      : launch_est_ee_t<3, float>(t, b, ps, y0, y1, b.y32, s);
+    const hipError_t e = launch_est_march(t, prec, b, y0, y1, ps.out(), s);   // 3-D
+    ps.produced(PK_STRIP);
+    return e;
 }
 
 hipError_t launch_lim_stage2(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
