@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "ch_internal.h"
+#include "ch_march.h"
 
 struct ch_ctx {
     int device = 0;
@@ -286,17 +287,19 @@ int strip_vx(int n, int prec) {
     return vx;
 }
 
-// Workgroups of the 3-D marching matvec of one instance: one per 64 x 8 x-y
-// tile and run of planes, capped (larger grids loop over the work items).
-static int march_blocks(int n) {
-    const long long items = (long long)((n + 63) / 64) * ((n + 7) / 8) * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
+// Workgroups of the 3-D marching matvec of one instance: one per 64-wide x-y
+// block (march_rows high) and run of planes, capped (larger grids loop over
+// the work items).
+static int march_blocks(int n, int prec) {
+    const int my = march_rows(prec);
+    const long long items = (long long)((n + 63) / 64) * ((n + my - 1) / my) * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
     return (int)std::min<long long>(items, CH_WBLK_MAX);
 }
 
 // Workgroups of the 2-D strip kernels (dim 2) or the 3-D marching matvec
 // (dim 3) of one instance.
 int wide_blocks(int dim, int n, int prec) {
-    return dim == 2 ? strip_blocks(n, strip_vx(n, prec)) : march_blocks(n);
+    return dim == 2 ? strip_blocks(n, strip_vx(n, prec)) : march_blocks(n, prec);
 }
 
 // Instance record of member m (index i) whose workgroup ranges start at

@@ -3,6 +3,10 @@
 
 #include "ch_internal.h"
 
+// Rows (y) of the x-y block of a marching workgroup: 8 in FP64 (two x per
+// thread), 16 in FP32 (four x per thread); the block is 64 wide.
+constexpr int march_rows(int prec) { return prec == CH_FP64 ? 8 : 16; }
+
 // 3-D estimate pass of EE2 on z-marching x-y tiles (ch_march.hip): f(y^{n+1})
 // into the field f and basis column 0 (and the FP32 copy of y^{n+1} in the
 // mixed form), with the partials of the estimate sums and of ||f||^2 and

@@ -24,29 +24,49 @@
 // 32 x 4 x 4 tile staged whole.
 #include "ch_common.h"
 #include "ch_stream.h"
+#include "ch_march.h"
 
 #include <type_traits>
 
 namespace {
 
+static_assert(march_rows(CH_FP64) == 8 && march_rows(CH_FP32_MIXED) == 16, "block heights of MGeo");
+
 // x-y tile of a workgroup: MX x MY outputs per plane, NPT consecutive x per
-// thread; the halo-1 ring of the q region is spread over the threads.
+// thread (one 16-byte vector: FP64 pairs in a 64 x 8 block, FP32 quads in a
+// 64 x 16 block); the halo-1 ring of the q region is spread over the threads.
+// In LDS each region row has a leading pad and a stride that put every
+// thread's first point on a multiple of NPT, so its NPT values are one
+// aligned access.
 template <typename TV>
 struct MGeo {
-    static constexpr int MX = 64, MY = 8;
+    static constexpr int NPT = 16 / (int)sizeof(TV);              // tile points per thread
+    static constexpr int MX = 64, TXT = MX / NPT, MY = CH_BLOCK / TXT;
     static constexpr int MVX = MX + 4, MVY = MY + 4;   // operand plane region (halo 2)
     static constexpr int MQX = MX + 2, MQY = MY + 2;   // inner-expression plane region (halo 1)
-    static constexpr int MQS = MQX + 2;                // q plane row stride (even: pairs stay aligned)
-    static constexpr int MVP = MVX * MVY, MQP = MQX * MQY, MQPS = MQY * MQS;
+    static constexpr int PV = (NPT - 2 % NPT) % NPT;   // leading pad of an operand row in LDS
+    static constexpr int PQ = (NPT - 1 % NPT) % NPT;   // leading pad of a q row in LDS
+    static constexpr int MVS = (MVX + PV + NPT - 1) / NPT * NPT;   // operand row stride in LDS
+    static constexpr int MQS = (MQX + PQ + NPT - 1) / NPT * NPT;   // q row stride in LDS
+    static constexpr int MVP = MVX * MVY, MQP = MQX * MQY;          // region points
+    static constexpr int MVPS = MVY * MVS, MQPS = MQY * MQS;        // LDS plane sizes
     static constexpr int NVL = (MVP + CH_BLOCK - 1) / CH_BLOCK;   // operand values per thread and plane
-    static constexpr int NPT = 2;                                 // tile points per thread
-    static constexpr int TXT = MX / NPT;                          // threads per tile row
     static constexpr int NRING = MQP - MX * MY;                   // halo-1 ring of the q region
     static constexpr int NRL = (NRING + CH_BLOCK - 1) / CH_BLOCK; // ring points per thread
     static constexpr int NQL = NPT + NRL;                         // q points per thread
-    static_assert(TXT * MY == CH_BLOCK, "one thread per point pair of the tile");
-    static_assert(MVX % 2 == 0 && MQS % 2 == 0 && MVP % 4 == 0 && MQPS % 4 == 0, "aligned LDS pairs");
+    static_assert(TXT * MY == CH_BLOCK, "one thread per point group of the tile");
+    static_assert(MVS % NPT == 0 && MQS % NPT == 0 && MVPS % NPT == 0 && MQPS % NPT == 0, "aligned LDS vectors");
 };
+
+// NPT consecutive LDS values at a multiple of NPT, as one 16-byte access.
+template <typename T, int NPT>
+struct alignas(16) LVec {
+    T e[NPT];
+};
+template <typename T, int NPT>
+__device__ __forceinline__ LVec<T, NPT> lds_vec(const T* p) {
+    return *reinterpret_cast<const LVec<T, NPT>*>(p);
+}
 
 // Two consecutive LDS values at an even index, as one access.
 template <typename T>
@@ -81,6 +101,16 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned bo) {
     else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, bo, 0u, AUX));
 }
 
+// 16 bytes of consecutive values (NPT of them) as one buffer load.
+template <typename T, int NPT, int AUX = 0>
+__device__ __forceinline__ void bload16(__amdgpu_buffer_rsrc_t r, unsigned bo, T (&v)[NPT]) {
+    static_assert(NPT * sizeof(T) == 16, "16-byte vector");
+    struct P { T e[NPT]; };
+    const P p = __builtin_bit_cast(P, __builtin_amdgcn_raw_buffer_load_b128(r, bo, 0u, AUX));
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) v[e] = p.e[e];
+}
+
 // Two consecutive values (one buffer load of 16 bytes in FP64, 8 in FP32).
 template <typename T, int AUX = 0>
 __device__ __forceinline__ void bload2(__amdgpu_buffer_rsrc_t r, unsigned bo, T (&v)[2]) {
@@ -107,6 +137,17 @@ __device__ __forceinline__ void bstore2(const T (&v)[2], __amdgpu_buffer_rsrc_t 
     using u32x4 = unsigned __attribute__((ext_vector_type(4)));
     if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, p), r, bo, 0u, AUX);
     else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, p), r, bo, 0u, AUX);
+}
+
+template <typename T, int NPT, int AUX = 0>
+__device__ __forceinline__ void bstore16(const T (&v)[NPT], __amdgpu_buffer_rsrc_t r, unsigned bo) {
+    static_assert(NPT * sizeof(T) == 16, "16-byte vector");
+    struct P { T e[NPT]; };
+    P p;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) p.e[e] = v[e];
+    using u32x4 = unsigned __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, p), r, bo, 0u, AUX);
 }
 
 // Work item it of an instance: x-y tile and run of planes.
@@ -154,7 +195,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
                                                        const TY* __restrict__ ybase, double* __restrict__ pout) {
     using G = MGeo<TV>;
     constexpr int MX = G::MX, MY = G::MY, MVX = G::MVX, MVP = G::MVP, MQX = G::MQX, MQY = G::MQY, MQS = G::MQS,
-                  MQPS = G::MQPS;
+                  MQPS = G::MQPS, MVS = G::MVS, MVPS = G::MVPS, PV = G::PV, PQ = G::PQ;
     constexpr int NVL = G::NVL, NPT = G::NPT, TXT = G::TXT, NRING = G::NRING, NQL = G::NQL;
     static_assert(G::MQP == MQX * MQY, "q region");
     const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
@@ -164,8 +205,8 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
     // The operand pass runs over whole passes of the workgroup with no bounds
     // test: lanes past the region's end repeat its last point, so they load
     // and store the same value as the lane that owns it.
-    __shared__ __attribute__((aligned(16))) TV sv[3][MVP];
-    __shared__ __attribute__((aligned(16))) TV sq[2][MQPS];   // q(x, y) at y * MQS + x + 1
+    __shared__ __attribute__((aligned(16))) TV sv[3][MVPS];   // operand (x, y) at y * MVS + x + PV
+    __shared__ __attribute__((aligned(16))) TV sq[2][MQPS];   // q(x, y) at y * MQS + x + PQ
     __shared__ double red[BIGK ? CH_DROWS : CH_DROWS_SMALL][NW];
     constexpr unsigned ES = sizeof(TV);
     const TV* Vk = V + (size_t)k * ldv + I.off;
@@ -185,7 +226,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
     const int nitems = ntx * nty * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
     const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
     constexpr int RB = 4;   // columns per wave_sum8 (two sums each)
-    // the thread's q points in the q region: its tile pair, then its ring point
+    // the thread's q points in the q region: its tile points, then its ring point
     // (lanes past the ring's end repeat its last point)
     int qrx[NQL], qry[NQL];
     const int cx = NPT * (tid % TXT), cy = tid / TXT;
@@ -250,7 +291,11 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
         auto store_v = [&](int z, const TV (&r)[NVL]) {
             TV* d = sv[(z - m.z0 + 2) % 3];
 #pragma unroll
-            for (int l = 0; l < NVL; ++l) d[min(tid + l * CH_BLOCK, MVP - 1)] = sc * r[l];
+            for (int l = 0; l < NVL; ++l) {
+                const int i = min(tid + l * CH_BLOCK, MVP - 1);
+                const int ry = i / MVX, rx = i - ry * MVX;
+                d[ry * MVS + rx + PV] = sc * r[l];
+            }
         };
         auto load_y = [&](int z, TY (&r)[NQL]) {
             const __amdgpu_buffer_rsrc_t rs = plane_rsrc(y + (size_t)wrapi(z, n) * n2, py);
@@ -295,7 +340,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
                     const bool live = dots && l0 + r < k;
                     const __amdgpu_buffer_rsrc_t rs = plane_rsrc(colbase + (size_t)(live ? l0 + r : 0) * ldv, pv);
                     if constexpr (VEC) {
-                        bload2<TV, NT ? 2 : 0>(rs, live ? dof[0] : MOFF, v[r]);
+                        bload16<TV, NPT, NT ? 2 : 0>(rs, live ? dof[0] : MOFF, v[r]);
                     } else {
 #pragma unroll
                         for (int e = 0; e < NPT; ++e) v[r][e] = bload<TV, NT ? 2 : 0>(rs, live ? dof[e] : MOFF);
@@ -316,29 +361,33 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
                 const TV* v0 = sv[(p - z0 + 2) % 3];
                 const TV* vp = sv[(p - z0 + 3) % 3];
                 TV* qd = sq[(p - z0 + 1) & 1];
-                {   // the tile pair: every operand value as part of an aligned pair
-                    static_assert(NPT == 2, "pair pass");
-                    const int c = (qry[0] + 1) * MVX + (qrx[0] + 1);
-                    const LPair<TV> lft = lds_pair(v0 + c - 2), mid = lds_pair(v0 + c), rgt = lds_pair(v0 + c + 2);
-                    const LPair<TV> up = lds_pair(v0 + c - MVX), dn = lds_pair(v0 + c + MVX), ab = lds_pair(vp + c);
-                    vc[0] = mid.a;
-                    vc[1] = mid.b;
-                    TV nb0 = (lft.b + mid.b) + (up.a + dn.a);
-                    TV nb1 = (mid.a + rgt.a) + (up.b + dn.b);
-                    nb0 += vm[0] + ab.a;
-                    nb1 += vm[1] + ab.b;
-                    qn[0] = dr[0] * vc[0] + e2ih2 * (TV(6) * vc[0] - nb0);
-                    qn[1] = dr[1] * vc[1] + e2ih2 * (TV(6) * vc[1] - nb1);
-                    *reinterpret_cast<LPair<TV>*>(qd + qry[0] * MQS + qrx[0] + 1) = LPair<TV>{qn[0], qn[1]};
+                {   // the tile points: every operand value as part of an aligned vector
+                    const int c = (qry[0] + 1) * MVS + (qrx[0] + 1) + PV;
+                    const LVec<TV, NPT> lft = lds_vec<TV, NPT>(v0 + c - NPT), mid = lds_vec<TV, NPT>(v0 + c),
+                                        rgt = lds_vec<TV, NPT>(v0 + c + NPT);
+                    const LVec<TV, NPT> up = lds_vec<TV, NPT>(v0 + c - MVS), dn = lds_vec<TV, NPT>(v0 + c + MVS),
+                                        ab = lds_vec<TV, NPT>(vp + c);
+                    LVec<TV, NPT> qv;
+#pragma unroll
+                    for (int e = 0; e < NPT; ++e) {
+                        vc[e] = mid.e[e];
+                        const TV left = e == 0 ? lft.e[NPT - 1] : mid.e[e - 1];
+                        const TV right = e == NPT - 1 ? rgt.e[0] : mid.e[e + 1];
+                        TV nb = (left + right) + (up.e[e] + dn.e[e]);
+                        nb += vm[e] + ab.e[e];
+                        qn[e] = dr[e] * vc[e] + e2ih2 * (TV(6) * vc[e] - nb);
+                        qv.e[e] = qn[e];
+                    }
+                    *reinterpret_cast<LVec<TV, NPT>*>(qd + qry[0] * MQS + qrx[0] + PQ) = qv;
                 }
 #pragma unroll
                 for (int l = NPT; l < NQL; ++l) {
-                    const int c = (qry[l] + 1) * MVX + (qrx[l] + 1);
+                    const int c = (qry[l] + 1) * MVS + (qrx[l] + 1) + PV;
                     vc[l] = v0[c];
-                    TV nb = (v0[c - 1] + v0[c + 1]) + (v0[c - MVX] + v0[c + MVX]);
+                    TV nb = (v0[c - 1] + v0[c + 1]) + (v0[c - MVS] + v0[c + MVS]);
                     nb += vm[l] + vp[c];
                     qn[l] = dr[l] * vc[l] + e2ih2 * (TV(6) * vc[l] - nb);
-                    qd[qry[l] * MQS + qrx[l] + 1] = qn[l];
+                    qd[qry[l] * MQS + qrx[l] + PQ] = qn[l];
                 }
             }
             if (dots) {
@@ -347,22 +396,24 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
                 const TV* qmid = sq[(p - z0) & 1];
                 TV w[NPT];
                 double ud[NPT], wd[NPT];
-                {   // q(p - 1) of the pair itself is in registers
-                    const int c = qry[0] * MQS + qrx[0] + 1;
-                    const LPair<TV> lft = lds_pair(qmid + c - 2), rgt = lds_pair(qmid + c + 2);
-                    const LPair<TV> up = lds_pair(qmid + c - MQS), dn = lds_pair(qmid + c + MQS);
-                    TV nb[NPT] = {(lft.b + qm1[1]) + (up.a + dn.a), (qm1[0] + rgt.a) + (up.b + dn.b)};
+                {   // q(p - 1) of the thread's own points is in registers
+                    const int c = qry[0] * MQS + qrx[0] + PQ;
+                    const LVec<TV, NPT> lft = lds_vec<TV, NPT>(qmid + c - NPT), rgt = lds_vec<TV, NPT>(qmid + c + NPT);
+                    const LVec<TV, NPT> up = lds_vec<TV, NPT>(qmid + c - MQS), dn = lds_vec<TV, NPT>(qmid + c + MQS);
 #pragma unroll
                     for (int e = 0; e < NPT; ++e) {
-                        nb[e] += qm2[e] + qn[e];
-                        w[e] = din[e] ? ih2 * (TV(6) * qm1[e] - nb[e]) : TV(0);
+                        const TV left = e == 0 ? lft.e[NPT - 1] : qm1[e - 1];
+                        const TV right = e == NPT - 1 ? rgt.e[0] : qm1[e + 1];
+                        TV nb = (left + right) + (up.e[e] + dn.e[e]);
+                        nb += qm2[e] + qn[e];
+                        w[e] = din[e] ? ih2 * (TV(6) * qm1[e] - nb) : TV(0);
                         ud[e] = din[e] ? double(vm[e]) : 0.0;
                         wd[e] = double(w[e]);
                     }
                 }
                 const __amdgpu_buffer_rsrc_t rw = plane_rsrc(W + (size_t)zo * n2, pv);
                 if constexpr (VEC) {
-                    bstore2<TV, NTW ? 2 : 0>(w, rw, store_w ? dof[0] : MOFF);
+                    bstore16<TV, NPT, NTW ? 2 : 0>(w, rw, store_w ? dof[0] : MOFF);
                 } else {
 #pragma unroll
                     for (int e = 0; e < NPT; ++e) bstore<TV, NTW ? 2 : 0>(w[e], rw, store_w ? dof[e] : MOFF);
@@ -450,7 +501,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_m(Ctl* __restrict__ ctls, cons
     constexpr int MX = G::MX, MY = G::MY, MVX = G::MVX, MVP = G::MVP, MQX = G::MQX, MQY = G::MQY, MQS = G::MQS,
                   MQPS = G::MQPS;
     constexpr int NVL = G::NVL, NPT = G::NPT, TXT = G::TXT, NRING = G::NRING, NQL = G::NQL;
-    static_assert(NPT == 2, "pair passes");
+    static_assert(NPT == 2 && G::MVS == MVX && G::PV == 0 && G::PQ == 1 && G::MVPS == MVP, "FP64 pair layout");
     const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
     Ctl* ctl = ctls + I.slot;
     if (ctl->halted) return;
