@@ -13,3 +13,8 @@ constexpr int march_rows(int prec) { return prec == CH_FP64 ? 8 : 16; }
 // ||ghat||^2 over the instance's wblk range (partials of kind PK_STRIP).
 hipError_t launch_est_march(const Table& t, int prec, const DevBuffers& b, const double* y0, const double* y1,
                             double* pout, hipStream_t s);
+
+// 3-D LIM stage launch l (one stage of Fig. 1) on z-marching x-y tiles
+// (ch_march.hip), with the launch bookkeeping of lim_launch.
+hipError_t launch_lim_stage_march(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
+                                  bool timing, hipStream_t s);

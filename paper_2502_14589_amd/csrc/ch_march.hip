@@ -712,6 +712,216 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_m(Ctl* __restrict__ ctls, cons
     write_partials<4, RED_SUM>(x, pout);
 }
 
+
+// ---------------------------------------------------------------------------
+// 3-D LIM stage (one iteration of Fig. 1) on the same z-marching tiles:
+//   y_next = (y^n + tau a_m z + tau (ghat - Ahat z)) / (1 + tau a_m),
+//   ghat - Ahat z = -A q,  q = d z + eps^2 A z - c,  d = 3 y^2 - 1 (+1),
+//   c = 2 y^3 (+ y)  (eqs. A_g, J; eq. A_g_cs with the Eyre splitting),
+// with d and c of y^n at the thread's points.  The operand z (the previous
+// stage; y^n for the first) keeps a ring of three planes, q two planes, as in
+// the matvec.  (tau a_m, 1 / (1 + tau a_m)) of the launch's stage position
+// come from the plan launch; launches past the instance's 2p - 1 stages do
+// nothing.
+template <bool SINGLE, int TAG, int DV>
+__global__ __launch_bounds__(CH_BLOCK) void k_lim_stage_m(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                          const int* __restrict__ wb2i, const Inst inst0, int ninst,
+                                                          const double* __restrict__ ybase, double* youtbase,
+                                                          double* zbufbase, const double* __restrict__ coefs, int l) {
+    using G = MGeo<double>;
+    constexpr int MX = G::MX, MY = G::MY, MVX = G::MVX, MVP = G::MVP, MQX = G::MQX, MQY = G::MQY, MQS = G::MQS,
+                  MQPS = G::MQPS;
+    constexpr int NVL = G::NVL, NPT = G::NPT, TXT = G::TXT, NRING = G::NRING, NQL = G::NQL;
+    static_assert(NPT == 2 && G::MVS == MVX && G::PV == 0 && G::PQ == 1 && G::MVPS == MVP, "FP64 pair layout");
+    const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->halted) return;
+    const LimLaunch L = lim_launch(ctl->p, l, false, ybase, youtbase, zbufbase);
+    if (!L.live) return;
+    __shared__ __attribute__((aligned(16))) double sv[3][MVP];
+    __shared__ __attribute__((aligned(16))) double sq[2][MQPS];   // q(x, y) at y * MQS + x + 1
+    const double* yn = ybase + I.off;
+    const double* zs = L.src + I.off;
+    double* out = L.dst + I.off;
+    const int n = I.n, eyre = I.eyre;
+    const size_t n2 = (size_t)n * n;
+    const unsigned pb = (unsigned)n2 * 8u;
+    const double ih2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
+    const double tau = ctl->tau0;
+    const double* cf = coefs + ((size_t)I.slot * 2 * CH_PMAX + L.pos) * 2;
+    const double ta = cf[0], inv = cf[1];
+    const int tid = threadIdx.x;
+    const int ntx = (n + MX - 1) / MX, nty = (n + MY - 1) / MY;
+    const int nitems = ntx * nty * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
+    const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
+    int qrx[NQL], qry[NQL];
+    const int cx = NPT * (tid % TXT), cy = tid / TXT;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+        qrx[e] = cx + 1 + e;
+        qry[e] = cy + 1;
+    }
+#pragma unroll
+    for (int m = NPT; m < NQL; ++m) {
+        const int r = min(tid + (m - NPT) * CH_BLOCK, NRING - 1);
+        if (r < MQX) {
+            qrx[m] = r;
+            qry[m] = 0;
+        } else if (r < 2 * MQX) {
+            qrx[m] = r - MQX;
+            qry[m] = MQY - 1;
+        } else if (r < 2 * MQX + MY) {
+            qrx[m] = 0;
+            qry[m] = 1 + r - 2 * MQX;
+        } else {
+            qrx[m] = MQX - 1;
+            qry[m] = 1 + r - 2 * MQX - MY;
+        }
+    }
+    auto items = [&](auto vec_c) {
+    constexpr bool VEC = decltype(vec_c)::value;
+    for (int it = lb; it < nitems; it += I.wblk) {
+        const MarchItem m = march_item<MX, MY>(it, n);
+        unsigned vo[NVL], qpos[NQL];
+#pragma unroll
+        for (int q = 0; q < NVL; ++q) {
+            const int i = min(tid + q * CH_BLOCK, MVP - 1);
+            const int ry = i / MVX, rx = i - ry * MVX;
+            vo[q] = (unsigned)(wrapi(m.y0 - 2 + ry, n) * n + wrapi(m.x0 - 2 + rx, n)) * 8u;
+        }
+#pragma unroll
+        for (int q = 0; q < NQL; ++q)
+            qpos[q] = (unsigned)(wrapi(m.y0 - 1 + qry[q], n) * n + wrapi(m.x0 - 1 + qrx[q], n)) * 8u;
+        const int gx = m.x0 + cx, gy = m.y0 + cy;
+        unsigned dof[NPT];   // byte offsets of the pair in a plane (MOFF outside the grid)
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) dof[e] = gx + e < n && gy < n ? (unsigned)(gy * n + gx + e) * 8u : MOFF;
+        auto load_v = [&](int z, double (&r)[NVL]) {
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(zs + (size_t)wrapi(z, n) * n2, pb);
+#pragma unroll
+            for (int q = 0; q < NVL; ++q) r[q] = bload<double>(rs, vo[q]);
+        };
+        auto store_v = [&](int z, const double (&r)[NVL]) {
+            double* d = sv[(z - m.z0 + 2) % 3];
+#pragma unroll
+            for (int q = 0; q < NVL; ++q) d[min(tid + q * CH_BLOCK, MVP - 1)] = r[q];
+        };
+        auto load_y = [&](int z, double (&r)[NQL]) {
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(yn + (size_t)wrapi(z, n) * n2, pb);
+#pragma unroll
+            for (int q = 0; q < NQL; ++q) r[q] = bload<double>(rs, qpos[q]);
+        };
+        const int z0 = m.z0;
+        // carried between steps: z of the plane below and d, c of the current
+        // plane at the q points; y^n of the current plane and of the plane
+        // below and q one and two planes below at the tile pair
+        double vm[NQL], dr[NQL], cr[NQL], yp[NPT], ym[NPT], qm2[NPT], qm1[NPT];
+        {
+            double a[NVL], b[NVL], yy[NQL];
+            load_v(z0 - 1, a);
+            load_v(z0, b);
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(zs + (size_t)wrapi(z0 - 2, n) * n2, pb);
+#pragma unroll
+            for (int q = 0; q < NQL; ++q) vm[q] = bload<double>(rs, qpos[q]);
+            load_y(z0 - 1, yy);
+            store_v(z0 - 1, a);
+            store_v(z0, b);
+#pragma unroll
+            for (int q = 0; q < NQL; ++q) {
+                dr[q] = 3.0 * yy[q] * yy[q] - 1.0 + double(eyre);
+                cr[q] = 2.0 * yy[q] * yy[q] * yy[q] + (eyre ? yy[q] : 0.0);
+            }
+#pragma unroll
+            for (int e = 0; e < NPT; ++e) {
+                yp[e] = yy[e];
+                ym[e] = qm2[e] = qm1[e] = 0.0;
+            }
+            __syncthreads();
+        }
+        for (int p = z0 - 1; p <= z0 + m.zl; ++p) {
+            const int zo = p - 1;
+            const bool more = p + 1 <= z0 + m.zl;
+            double nv[NVL], ny[NQL];
+            if (more) {   // the next step's operand plane and state, in flight during this one
+                load_v(p + 2, nv);
+                load_y(p + 1, ny);
+            }
+            double vc[NQL], qn[NQL];
+            {
+                const double* v0 = sv[(p - z0 + 2) % 3];
+                const double* vp = sv[(p - z0 + 3) % 3];
+                double* qd = sq[(p - z0 + 1) & 1];
+                const int c = (qry[0] + 1) * MVX + (qrx[0] + 1);
+                const LPair<double> lft = lds_pair(v0 + c - 2), mid = lds_pair(v0 + c), rgt = lds_pair(v0 + c + 2);
+                const LPair<double> up = lds_pair(v0 + c - MVX), dn = lds_pair(v0 + c + MVX), ab = lds_pair(vp + c);
+                vc[0] = mid.a;
+                vc[1] = mid.b;
+                double nb0 = (lft.b + mid.b) + (up.a + dn.a);
+                double nb1 = (mid.a + rgt.a) + (up.b + dn.b);
+                nb0 += vm[0] + ab.a;
+                nb1 += vm[1] + ab.b;
+                qn[0] = dr[0] * vc[0] + e2ih2 * (6.0 * vc[0] - nb0) - cr[0];
+                qn[1] = dr[1] * vc[1] + e2ih2 * (6.0 * vc[1] - nb1) - cr[1];
+                *reinterpret_cast<LPair<double>*>(qd + qry[0] * MQS + qrx[0] + 1) = LPair<double>{qn[0], qn[1]};
+#pragma unroll
+                for (int q = NPT; q < NQL; ++q) {
+                    const int cc = (qry[q] + 1) * MVX + (qrx[q] + 1);
+                    vc[q] = v0[cc];
+                    double nb = (v0[cc - 1] + v0[cc + 1]) + (v0[cc - MVX] + v0[cc + MVX]);
+                    nb += vm[q] + vp[cc];
+                    qn[q] = dr[q] * vc[q] + e2ih2 * (6.0 * vc[q] - nb) - cr[q];
+                    qd[qry[q] * MQS + qrx[q] + 1] = qn[q];
+                }
+            }
+            if (zo >= z0) {   // the stage on plane p - 1 at the pair
+                const double* qmid = sq[(p - z0) & 1];
+                const int c = qry[0] * MQS + qrx[0] + 1;
+                const LPair<double> lft = lds_pair(qmid + c - 2), rgt = lds_pair(qmid + c + 2);
+                const LPair<double> up = lds_pair(qmid + c - MQS), dn = lds_pair(qmid + c + MQS);
+                double nb[NPT] = {(lft.b + qm1[1]) + (up.a + dn.a), (qm1[0] + rgt.a) + (up.b + dn.b)};
+                double o[NPT];
+#pragma unroll
+                for (int e = 0; e < NPT; ++e) {
+                    nb[e] += qm2[e] + qn[e];
+                    const double r = -ih2 * (6.0 * qm1[e] - nb[e]);
+                    o[e] = (ym[e] + ta * vm[e] + tau * r) * inv;
+                }
+                const __amdgpu_buffer_rsrc_t ro = plane_rsrc(out + (size_t)zo * n2, pb);
+                if constexpr (VEC) {
+                    bstore2<double>(o, ro, dof[0]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < NPT; ++e) bstore<double>(o[e], ro, dof[e]);
+                }
+            }
+            // y^n of plane p at the pair serves the stage on plane p next step
+#pragma unroll
+            for (int e = 0; e < NPT; ++e) ym[e] = yp[e];
+            if (more) {
+                store_v(p + 2, nv);
+#pragma unroll
+                for (int q = 0; q < NQL; ++q) {
+                    dr[q] = 3.0 * ny[q] * ny[q] - 1.0 + double(eyre);
+                    cr[q] = 2.0 * ny[q] * ny[q] * ny[q] + (eyre ? ny[q] : 0.0);
+                }
+#pragma unroll
+                for (int e = 0; e < NPT; ++e) yp[e] = ny[e];
+            }
+#pragma unroll
+            for (int e = 0; e < NPT; ++e) {
+                qm2[e] = qm1[e];
+                qm1[e] = qn[e];
+            }
+#pragma unroll
+            for (int q = 0; q < NQL; ++q) vm[q] = vc[q];
+            __syncthreads();
+        }
+    }
+    };
+    if (DV == 1 || (DV == 2 && n % NPT == 0)) items(std::true_type{});
+    else items(std::false_type{});
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -775,5 +985,20 @@ hipError_t launch_est_march(const Table& t, int prec, const DevBuffers& b, const
                             double* pout, hipStream_t s) {
     if (prec == CH_FP64) launch_est_m<double>(t, b, y0, y1, nullptr, pout, s);
     else launch_est_m<float>(t, b, y0, y1, b.y32, pout, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_lim_stage_march(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
+                                  bool timing, hipStream_t s) {
+    const bool vec = t.hinst[0].n % MGeo<double>::NPT == 0;
+    if (timing) {
+        if (vec) hipLaunchKernelGGL((k_lim_stage_m<true, 1, 1>), MARGS, yin, yout, b.zbuf, b.lcoef, l);
+        else hipLaunchKernelGGL((k_lim_stage_m<true, 1, 0>), MARGS, yin, yout, b.zbuf, b.lcoef, l);
+    } else if (t.ninst == 1) {
+        if (vec) hipLaunchKernelGGL((k_lim_stage_m<true, 0, 1>), MARGS, yin, yout, b.zbuf, b.lcoef, l);
+        else hipLaunchKernelGGL((k_lim_stage_m<true, 0, 0>), MARGS, yin, yout, b.zbuf, b.lcoef, l);
+    } else {
+        hipLaunchKernelGGL((k_lim_stage_m<false, 0, 2>), MARGS, yin, yout, b.zbuf, b.lcoef, l);
+    }
     return hipGetLastError();
 }

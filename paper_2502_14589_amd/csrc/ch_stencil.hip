@@ -278,64 +278,6 @@ __global__ __launch_bounds__(CH_BLOCK) void k_resid(Ctl* __restrict__ ctls, cons
 }
 
 // ---------------------------------------------------------------------------
-// LIM stage (one iteration of Fig. 1):
-//   y_next = (y^n + tau a_m z + tau (ghat - Ahat z)) / (1 + tau a_m)
-// ---------------------------------------------------------------------------
-template <int DIM, bool SINGLE, int TAG>
-__global__ __launch_bounds__(CH_BLOCK) void k_lim_stage(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
-                                                        const int* __restrict__ sb2i, const Inst inst0, int ninst, const double* __restrict__ ybase,
-                                                        double* youtbase, double* zbufbase,
-                                                        const double* __restrict__ coefs, int l) {
-    const Inst I = SINGLE ? inst0 : insts[sb2i[blockIdx.x]];
-    Ctl* ctl = ctls + I.slot;
-    if (ctl->halted) return;
-    // stage launch l of this instance (single stages: launch l is stage l)
-    const LimLaunch L = lim_launch(ctl->p, l, false, ybase, youtbase, zbufbase);
-    if (!L.live) return;
-    const double* zbase = L.src;
-    double* obase = L.dst;
-    const int pos = L.pos;
-    using R1 = Region<DIM, 1>;
-    using R2 = Region<DIM, 2>;
-    __shared__ double sz[R2::SIZE];
-    __shared__ double sdq[R1::SIZE];
-    __shared__ double sc[R1::SIZE];
-    const double* y = ybase + I.off;
-    const double* z = zbase + I.off;
-    double* out = obase + I.off;
-    const int n = I.n, eyre = I.eyre;
-    const double inv_h2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
-    const double tau = ctl->tau0;
-    // (tau a_m, 1 / (1 + tau a_m)) of stage position pos, set by the plan launch
-    const double* cf = coefs + ((size_t)I.slot * 2 * CH_PMAX + pos) * 2;
-    const double ta = cf[0], inv = cf[1];
-    int ntx, nty;
-    const int nt = num_tiles<DIM>(n, ntx, nty);
-    const int lb = blockIdx.x - I.sblk0;
-    for (int t = xcd_remap(lb, I.sblk); t < nt; t += I.sblk) {
-        const TileOrigin o = tile_origin<DIM>(t, ntx, nty);
-        load_regions<DIM, 2, 1>(o, n, I.bc, z, [&](int i, double v) { sz[i] = v; }, y, [&](int i, double v) {
-            sdq[i] = dcoef(v, eyre);
-            sc[i] = ccoef(v, eyre);
-        });
-        __syncthreads();
-        for (int i = threadIdx.x; i < R1::SIZE; i += CH_BLOCK)
-            sdq[i] = sdq[i] * sz[r1_to_r2<DIM>(i)] + e2ih2 * lap2_at_r1<DIM>(sz, i) - sc[i];
-        __syncthreads();
-        for (int i = threadIdx.x; i < tile_points<DIM>(); i += CH_BLOCK) {
-            int i1;
-            size_t gi;
-            if (out_point<DIM>(i, o, n, i1, gi)) {
-                const double r = -inv_h2 * lap1_at<DIM>(sdq, i1);
-                const double zc = sz[r1_to_r2<DIM>(i1)];
-                out[gi] = (y[gi] + ta * zc + tau * r) * inv;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
 // LIM estimate (Fig. 2; eq. LIMest):
 //   y_PC = y^n - tau/2 A (F'(y^n) + F'(y^{n+1}) + eps^2 A (y^n + y^{n+1}));
 // partials of ||y^{n+1} - y_PC||^2 and ||y_PC||^2 go to the controller.
@@ -504,21 +446,7 @@ hipError_t launch_lim_stage(const Table& t, const DevBuffers& b, const double* y
                             hipStream_t s, bool timing) {
     if (uses_strips(t)) return launch_lim_stage_strip(t, b, yin, yout, l, pairs, timing, s);
     if (pairs) return hipErrorInvalidValue;
-    if (t.dim == 2)
-        if (timing)
-            hipLaunchKernelGGL((k_lim_stage<2, true, 1>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
-        else if (t.ninst == 1)
-            hipLaunchKernelGGL((k_lim_stage<2, true, 0>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
-        else
-            hipLaunchKernelGGL((k_lim_stage<2, false, 0>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
-    else
-        if (timing)
-            hipLaunchKernelGGL((k_lim_stage<3, true, 1>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
-        else if (t.ninst == 1)
-            hipLaunchKernelGGL((k_lim_stage<3, true, 0>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
-        else
-            hipLaunchKernelGGL((k_lim_stage<3, false, 0>), SARGS, yin, yout, b.zbuf, b.lcoef, l);
-    return hipGetLastError();
+    return launch_lim_stage_march(t, b, yin, yout, l, timing, s);   // 3-D
 }
 
 hipError_t launch_est_lim(const Table& t, const DevBuffers& b, PartSeq& ps, const double* y0, const double* y1,
