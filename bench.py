@@ -176,7 +176,7 @@ def c3_form(ctx, ch, torch, steps: int = 20, warmup: int = 1):
     EE2 with Krylov dimension 40 and tol 1e-6, tau0 = 1e-3, the 20-step
     horizon from y0: FP32-mixed and FP64.  The FP64 basis (41 x 128 MiB) is far
     larger than the 256 MB last-level cache, so its kernel figures are
-    HBM-bound."""
+    HBM-bound.  Also the roofline of one FP64 LIM stage (Fig. 1) on that field."""
     from paper_2502_14589_amd.inputs import cube_3d_field
 
     y0 = cube_3d_field(C3_SEED, C3_SIDE)
@@ -196,6 +196,18 @@ def c3_form(ctx, ch, torch, steps: int = 20, warmup: int = 1):
                      "dc_update_frac": round(up["achieved_GBps"] / HBM_PEAK_GBPS, 4),
                      "dc_matvec_avg_launch_us": round(mv["avg_launch_us"], 3),
                      "dc_matvec_bytes_per_launch": mv["bytes_per_launch"], "dc_matvec_launches": mv["launches"]}
+    # the LIM stage (Fig. 1) on the same field, FP64: a short adaptive run sets
+    # up the workspace, then back-to-back stage launches are timed
+    prob = ch.Problem(3, C3_SIDE, C3_EPS, False, ch.CH_FP64)
+    y = torch.from_numpy(y0.copy()).to("cuda")
+    ctx.run_lim(prob, y, 1e-6, max_steps=3, tol=1e-4)
+    count = 40
+    us, by = ctx.time_kernel(prob, ch.CH_KERNEL_LIM_STAGE, 1, count=count)
+    gbps = by / us / 1e3
+    out["lim_stage_fp64"] = {"kernel": "one LIM stage (read y^n and the previous stage, write the next)",
+                             "bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                             "frac": round(gbps / HBM_PEAK_GBPS, 4), "avg_launch_us": round(us / count, 3),
+                             "bytes_per_launch": by / count, "launches": count}
     return out
 
 
