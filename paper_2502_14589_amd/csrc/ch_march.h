@@ -18,3 +18,9 @@ hipError_t launch_est_march(const Table& t, int prec, const DevBuffers& b, const
 // (ch_march.hip), with the launch bookkeeping of lim_launch.
 hipError_t launch_lim_stage_march(const Table& t, const DevBuffers& b, const double* yin, double* yout, int l,
                                   bool timing, hipStream_t s);
+
+// 3-D LIM estimate (eq. LIMest) on z-marching x-y tiles (ch_march.hip):
+// partials of ||y^{n+1} - y_PC||^2 and ||y_PC||^2 over the instance's wblk
+// range (partials of kind PK_STRIP).
+hipError_t launch_est_lim_march(const Table& t, const DevBuffers& b, const double* y0, const double* y1, double* pout,
+                                hipStream_t s);

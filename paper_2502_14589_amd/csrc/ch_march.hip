@@ -922,6 +922,219 @@ __global__ __launch_bounds__(CH_BLOCK) void k_lim_stage_m(Ctl* __restrict__ ctls
     else items(std::false_type{});
 }
 
+
+// ---------------------------------------------------------------------------
+// 3-D LIM estimate (Fig. 2; eq. LIMest) on the same z-marching tiles:
+//   y_PC = y^n - tau/2 A (F'(y^n) + F'(y^{n+1}) + eps^2 A (y^n + y^{n+1})),
+// partials of ||y^{n+1} - y_PC||^2 and ||y_PC||^2.  A is linear, so the
+// operand ring holds s = y^n + y^{n+1}; the two states themselves are loaded
+// at the thread's points for the cubic terms and the sums.
+template <bool SINGLE, int DV>
+__global__ __launch_bounds__(CH_BLOCK) void k_est_lim_m(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
+                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
+                                                        const double* __restrict__ y0base,
+                                                        const double* __restrict__ y1base, double* __restrict__ pout) {
+    using G = MGeo<double>;
+    constexpr int MX = G::MX, MY = G::MY, MVX = G::MVX, MVP = G::MVP, MQX = G::MQX, MQY = G::MQY, MQS = G::MQS,
+                  MQPS = G::MQPS;
+    constexpr int NVL = G::NVL, NPT = G::NPT, TXT = G::TXT, NRING = G::NRING, NQL = G::NQL;
+    static_assert(NPT == 2 && G::MVS == MVX && G::PV == 0 && G::PQ == 1 && G::MVPS == MVP, "FP64 pair layout");
+    const Inst I = SINGLE ? inst0 : insts[wb2i[blockIdx.x]];
+    Ctl* ctl = ctls + I.slot;
+    if (ctl->halted) return;
+    __shared__ __attribute__((aligned(16))) double sv[3][MVP];
+    __shared__ __attribute__((aligned(16))) double sq[2][MQPS];   // q(x, y) at y * MQS + x + 1
+    const double* ya = y0base + I.off;
+    const double* yb = y1base + I.off;
+    const int n = I.n;
+    const size_t n2 = (size_t)n * n;
+    const unsigned pb = (unsigned)n2 * 8u;
+    const double ih2 = I.inv_h2, e2ih2 = I.eps2 * I.inv_h2;
+    const double half_tau = 0.5 * ctl->tau0;
+    const int tid = threadIdx.x;
+    const int ntx = (n + MX - 1) / MX, nty = (n + MY - 1) / MY;
+    const int nitems = ntx * nty * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
+    const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
+    int qrx[NQL], qry[NQL];
+    const int cx = NPT * (tid % TXT), cy = tid / TXT;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+        qrx[e] = cx + 1 + e;
+        qry[e] = cy + 1;
+    }
+#pragma unroll
+    for (int m = NPT; m < NQL; ++m) {
+        const int r = min(tid + (m - NPT) * CH_BLOCK, NRING - 1);
+        if (r < MQX) {
+            qrx[m] = r;
+            qry[m] = 0;
+        } else if (r < 2 * MQX) {
+            qrx[m] = r - MQX;
+            qry[m] = MQY - 1;
+        } else if (r < 2 * MQX + MY) {
+            qrx[m] = 0;
+            qry[m] = 1 + r - 2 * MQX;
+        } else {
+            qrx[m] = MQX - 1;
+            qry[m] = 1 + r - 2 * MQX - MY;
+        }
+    }
+    double a_err = 0.0, a_pc = 0.0;
+    auto items = [&](auto vec_c) {
+    constexpr bool VEC = decltype(vec_c)::value;
+    (void)VEC;
+    for (int it = lb; it < nitems; it += I.wblk) {
+        const MarchItem m = march_item<MX, MY>(it, n);
+        unsigned vo[NVL], qpos[NQL];
+#pragma unroll
+        for (int q = 0; q < NVL; ++q) {
+            const int i = min(tid + q * CH_BLOCK, MVP - 1);
+            const int ry = i / MVX, rx = i - ry * MVX;
+            vo[q] = (unsigned)(wrapi(m.y0 - 2 + ry, n) * n + wrapi(m.x0 - 2 + rx, n)) * 8u;
+        }
+#pragma unroll
+        for (int q = 0; q < NQL; ++q)
+            qpos[q] = (unsigned)(wrapi(m.y0 - 1 + qry[q], n) * n + wrapi(m.x0 - 1 + qrx[q], n)) * 8u;
+        const int gx = m.x0 + cx, gy = m.y0 + cy;
+        bool din[NPT];
+#pragma unroll
+        for (int e = 0; e < NPT; ++e) din[e] = gx + e < n && gy < n;
+        // s = y^n + y^{n+1} over the operand region of plane z
+        auto load_s = [&](int z, double (&r)[NVL]) {
+            const __amdgpu_buffer_rsrc_t ra = plane_rsrc(ya + (size_t)wrapi(z, n) * n2, pb);
+            const __amdgpu_buffer_rsrc_t rb = plane_rsrc(yb + (size_t)wrapi(z, n) * n2, pb);
+            double t[NVL];
+#pragma unroll
+            for (int q = 0; q < NVL; ++q) {
+                r[q] = bload<double>(ra, vo[q]);
+                t[q] = bload<double>(rb, vo[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < NVL; ++q) r[q] += t[q];
+        };
+        auto store_s = [&](int z, const double (&r)[NVL]) {
+            double* d = sv[(z - m.z0 + 2) % 3];
+#pragma unroll
+            for (int q = 0; q < NVL; ++q) d[min(tid + q * CH_BLOCK, MVP - 1)] = r[q];
+        };
+        // both states at the q points of plane z
+        auto load_ab = [&](int z, double (&a)[NQL], double (&b)[NQL]) {
+            const __amdgpu_buffer_rsrc_t ra = plane_rsrc(ya + (size_t)wrapi(z, n) * n2, pb);
+            const __amdgpu_buffer_rsrc_t rb = plane_rsrc(yb + (size_t)wrapi(z, n) * n2, pb);
+#pragma unroll
+            for (int q = 0; q < NQL; ++q) {
+                a[q] = bload<double>(ra, qpos[q]);
+                b[q] = bload<double>(rb, qpos[q]);
+            }
+        };
+        const int z0 = m.z0;
+        // carried: s of the plane below at the q points; F'(y^n) + F'(y^{n+1})
+        // of the current plane at the q points; both states of the plane
+        // below at the pair; q one and two planes below at the pair
+        double sm[NQL], fr[NQL], am[NPT], bm[NPT], ap[NPT], bp[NPT], qm2[NPT], qm1[NPT];
+        {
+            double a[NVL], b[NVL], aa[NQL], bb[NQL];
+            load_s(z0 - 1, a);
+            load_s(z0, b);
+            {
+                double ta[NQL], tb[NQL];
+                load_ab(z0 - 2, ta, tb);
+#pragma unroll
+                for (int q = 0; q < NQL; ++q) sm[q] = ta[q] + tb[q];
+            }
+            load_ab(z0 - 1, aa, bb);
+            store_s(z0 - 1, a);
+            store_s(z0, b);
+#pragma unroll
+            for (int q = 0; q < NQL; ++q) fr[q] = aa[q] * (aa[q] * aa[q] - 1.0) + bb[q] * (bb[q] * bb[q] - 1.0);
+#pragma unroll
+            for (int e = 0; e < NPT; ++e) {
+                ap[e] = aa[e];
+                bp[e] = bb[e];
+                am[e] = bm[e] = qm2[e] = qm1[e] = 0.0;
+            }
+            __syncthreads();
+        }
+        for (int p = z0 - 1; p <= z0 + m.zl; ++p) {
+            const bool more = p + 1 <= z0 + m.zl;
+            double nv[NVL], na[NQL], nb2[NQL];
+            if (more) {
+                load_s(p + 2, nv);
+                load_ab(p + 1, na, nb2);
+            }
+            double vc[NQL], qn[NQL];
+            {
+                const double* v0 = sv[(p - z0 + 2) % 3];
+                const double* vp = sv[(p - z0 + 3) % 3];
+                double* qd = sq[(p - z0 + 1) & 1];
+                const int c = (qry[0] + 1) * MVX + (qrx[0] + 1);
+                const LPair<double> lft = lds_pair(v0 + c - 2), mid = lds_pair(v0 + c), rgt = lds_pair(v0 + c + 2);
+                const LPair<double> up = lds_pair(v0 + c - MVX), dn = lds_pair(v0 + c + MVX), ab = lds_pair(vp + c);
+                vc[0] = mid.a;
+                vc[1] = mid.b;
+                double nb0 = (lft.b + mid.b) + (up.a + dn.a);
+                double nb1 = (mid.a + rgt.a) + (up.b + dn.b);
+                nb0 += sm[0] + ab.a;
+                nb1 += sm[1] + ab.b;
+                qn[0] = fr[0] + e2ih2 * (6.0 * vc[0] - nb0);
+                qn[1] = fr[1] + e2ih2 * (6.0 * vc[1] - nb1);
+                *reinterpret_cast<LPair<double>*>(qd + qry[0] * MQS + qrx[0] + 1) = LPair<double>{qn[0], qn[1]};
+#pragma unroll
+                for (int q = NPT; q < NQL; ++q) {
+                    const int cc = (qry[q] + 1) * MVX + (qrx[q] + 1);
+                    vc[q] = v0[cc];
+                    double nb = (v0[cc - 1] + v0[cc + 1]) + (v0[cc - MVX] + v0[cc + MVX]);
+                    nb += sm[q] + vp[cc];
+                    qn[q] = fr[q] + e2ih2 * (6.0 * vc[q] - nb);
+                    qd[qry[q] * MQS + qrx[q] + 1] = qn[q];
+                }
+            }
+            if (p - 1 >= z0) {   // y_PC on plane p - 1 at the pair
+                const double* qmid = sq[(p - z0) & 1];
+                const int c = qry[0] * MQS + qrx[0] + 1;
+                const LPair<double> lft = lds_pair(qmid + c - 2), rgt = lds_pair(qmid + c + 2);
+                const LPair<double> up = lds_pair(qmid + c - MQS), dn = lds_pair(qmid + c + MQS);
+                double nb[NPT] = {(lft.b + qm1[1]) + (up.a + dn.a), (qm1[0] + rgt.a) + (up.b + dn.b)};
+#pragma unroll
+                for (int e = 0; e < NPT; ++e) {
+                    nb[e] += qm2[e] + qn[e];
+                    const double ypc = am[e] - half_tau * (ih2 * (6.0 * qm1[e] - nb[e]));
+                    const double er = bm[e] - ypc;
+                    if (din[e]) {
+                        a_err += er * er;
+                        a_pc += ypc * ypc;
+                    }
+                }
+            }
+            if (more) store_s(p + 2, nv);
+#pragma unroll
+            for (int e = 0; e < NPT; ++e) {
+                am[e] = ap[e];
+                bm[e] = bp[e];
+                qm2[e] = qm1[e];
+                qm1[e] = qn[e];
+            }
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < NQL; ++q) fr[q] = na[q] * (na[q] * na[q] - 1.0) + nb2[q] * (nb2[q] * nb2[q] - 1.0);
+#pragma unroll
+                for (int e = 0; e < NPT; ++e) {
+                    ap[e] = na[e];
+                    bp[e] = nb2[e];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NQL; ++q) sm[q] = vc[q];
+            __syncthreads();
+        }
+    }
+    };
+    if (DV == 1 || (DV == 2 && n % NPT == 0)) items(std::true_type{});
+    else items(std::false_type{});
+    double x[2] = {a_err, a_pc};
+    write_partials<2, RED_SUM>(x, pout);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1000,5 +1213,12 @@ hipError_t launch_lim_stage_march(const Table& t, const DevBuffers& b, const dou
     } else {
         hipLaunchKernelGGL((k_lim_stage_m<false, 0, 2>), MARGS, yin, yout, b.zbuf, b.lcoef, l);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_est_lim_march(const Table& t, const DevBuffers& b, const double* y0, const double* y1, double* pout,
+                                hipStream_t s) {
+    if (t.ninst == 1) hipLaunchKernelGGL((k_est_lim_m<true, 1>), MARGS, y0, y1, pout);
+    else hipLaunchKernelGGL((k_est_lim_m<false, 2>), MARGS, y0, y1, pout);
     return hipGetLastError();
 }

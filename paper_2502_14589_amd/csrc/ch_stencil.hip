@@ -458,11 +458,11 @@ hipError_t launch_est_lim(const Table& t, const DevBuffers& b, PartSeq& ps, cons
             hipLaunchKernelGGL((k_est_lim<2, true>), SARGS, y0, y1, ps.out());
         else
             hipLaunchKernelGGL((k_est_lim<2, false>), SARGS, y0, y1, ps.out());
-    else
-        if (t.ninst == 1)
-            hipLaunchKernelGGL((k_est_lim<3, true>), SARGS, y0, y1, ps.out());
-        else
-            hipLaunchKernelGGL((k_est_lim<3, false>), SARGS, y0, y1, ps.out());
+    else {   // 3-D: the marching tiles
+        const hipError_t e = launch_est_lim_march(t, b, y0, y1, ps.out(), s);
+        ps.produced(PK_STRIP);
+        return e;
+    }
     ps.produced(PK_TILE);
     return hipGetLastError();
 }
