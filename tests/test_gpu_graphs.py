@@ -132,3 +132,23 @@ def test_graph_runs_with_boundary_and_mobility_variants(ctx, kind):
         y, st, recs = run(ctx, prob, y0, chunk, max_steps=15, m_max=30)
         assert np.array_equal(y, ref)
         assert [r["j"] for r in recs] == [r["j"] for r in rec_ref]
+
+
+@pytest.mark.parametrize("prec", [ch.CH_FP64, ch.CH_FP32_MIXED])
+@pytest.mark.parametrize("n", [24, 65])
+def test_graph_runs_equal_direct_runs_3d(ctx, n, prec):
+    """The 3-D marching kernels replayed from graphs (chunks of 4 iterations and
+    a whole cycle) equal their direct issue bit for bit, and the run matches
+    the FP64 oracle."""
+    say(f"3-D graphs n={n} prec={prec}")
+    prob = ch.Problem(3, n, 0.05, precision=prec)
+    y0 = uniform_field(n, 3, 0.1, 0.05, seed=7900 + n)
+    ref, st_ref, rec_ref = run(ctx, prob, y0, 0, max_steps=8, m_max=30, tau0=1e-4)
+    for chunk in (4, 31):
+        y, st, recs = run(ctx, prob, y0, chunk, max_steps=8, m_max=30, tau0=1e-4)
+        assert np.array_equal(y, ref), chunk
+        assert [r["j"] for r in recs] == [r["j"] for r in rec_ref]
+    if prec == ch.CH_FP64:
+        y_or, rec = O.ee_adaptive(y0, O.Problem(3, n, 0.05), 1e-4, np.inf, 1e-4, 30, max_steps=8)
+        assert [r["j"] for r in rec_ref] == rec.js
+        assert np.linalg.norm(ref - y_or) / np.linalg.norm(y_or) <= 1e-10
