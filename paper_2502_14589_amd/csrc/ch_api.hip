@@ -292,7 +292,8 @@ int strip_vx(int n, int prec) {
 // the work items).
 static int march_blocks(int n, int prec) {
     const int my = march_rows(prec);
-    const long long items = (long long)((n + 63) / 64) * ((n + my - 1) / my) * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
+    const int len = prec == CH_FP64 ? CH_MARCH_L : march_len_fp32(n);
+    const long long items = (long long)((n + 63) / 64) * ((n + my - 1) / my) * ((n + len - 1) / len);
     return (int)std::min<long long>(items, CH_WBLK_MAX);
 }
 

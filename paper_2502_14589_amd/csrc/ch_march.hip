@@ -8,7 +8,8 @@
 // <u, w>).
 //
 // Layout.  A workgroup owns an MX x MY block of (x, y) columns and a run of
-// up to CH_MARCH_L planes in z, which it walks plane by plane.  Thread t owns
+// up to CH_MARCH_L planes in z (in the FP32 matvec, the length march_len_fp32
+// picks for the grid), which it walks plane by plane.  Thread t owns
 // the same two consecutive-x columns of the block in every pass (the stencil
 // passes and the dot phase), plus one column of the halo-1 ring around the
 // block.  In LDS: a ring of three operand planes (halo 2 in x and y) and two
@@ -156,15 +157,15 @@ struct MarchItem {
 };
 
 template <int MX, int MY>
-__device__ __forceinline__ MarchItem march_item(int it, int n) {
+__device__ __forceinline__ MarchItem march_item(int it, int n, int len = CH_MARCH_L) {
     const int ntx = (n + MX - 1) / MX, nty = (n + MY - 1) / MY;
     const int nxy = ntx * nty;
     const int c = it / nxy, t = it - c * nxy;
     MarchItem m;
     m.x0 = (t % ntx) * MX;
     m.y0 = (t / ntx) * MY;
-    m.z0 = c * CH_MARCH_L;
-    m.zl = min(CH_MARCH_L, n - m.z0);
+    m.z0 = c * len;
+    m.zl = min(len, n - m.z0);
     return m;
 }
 
@@ -192,7 +193,8 @@ template <typename TV, typename TY, bool SINGLE, int TAG, int DV, bool BIGK, boo
 __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, const Inst* __restrict__ insts,
                                                        const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                        TV* __restrict__ V, size_t ldv, int k, int store_w,
-                                                       const TY* __restrict__ ybase, double* __restrict__ pout) {
+                                                       const TY* __restrict__ ybase, double* __restrict__ pout,
+                                                       int zlen0) {
     using G = MGeo<TV>;
     constexpr int MX = G::MX, MY = G::MY, MVX = G::MVX, MVP = G::MVP, MQX = G::MQX, MQY = G::MQY, MQS = G::MQS,
                   MQPS = G::MQPS, MVS = G::MVS, MVPS = G::MVPS, PV = G::PV, PQ = G::PQ;
@@ -223,7 +225,9 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
     for (int i = tid; i < nrows * NW; i += CH_BLOCK) red[i / NW][i % NW] = 0.0;
     const int hv = wave_sum8_holder(lane);
     const int ntx = (n + MX - 1) / MX, nty = (n + MY - 1) / MY;
-    const int nitems = ntx * nty * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
+    // planes per run: from the host for a single grid, else per instance
+    const int zlen = SINGLE ? zlen0 : (sizeof(TV) == 4 ? march_len_fp32(n) : CH_MARCH_L);
+    const int nitems = ntx * nty * ((n + zlen - 1) / zlen);
     const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
     constexpr int RB = 4;   // columns per wave_sum8 (two sums each)
     // the thread's q points in the q region: its tile points, then its ring point
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_matvec_m(Ctl* __restrict__ ctls, c
     auto items = [&](auto vec_c) {
     constexpr bool VEC = decltype(vec_c)::value;
     for (int it = lb; it < nitems; it += I.wblk) {
-        const MarchItem m = march_item<MX, MY>(it, n);
+        const MarchItem m = march_item<MX, MY>(it, n, zlen);
         // byte offsets in a plane of the thread's operand-region values and
         // of its q points (periodic wrap; the region may extend past the
         // grid, whose outputs are masked below)
@@ -1146,19 +1150,20 @@ template <typename TV, typename TY, bool NT, bool NTW>
 static void launch_matvec_m(const Table& t, const DevBuffers& b, const TY* y, int k, int store_w, double* pout,
                             bool timing, hipStream_t s) {
     TV* V = static_cast<TV*>(b.V);
+    const int zl = sizeof(TV) == 4 ? march_len_fp32(t.hinst[0].n) : CH_MARCH_L;   // single-grid launches
     const bool vec = t.hinst[0].n % MGeo<TV>::NPT == 0;   // the tile pair as one vector
     if (k > CH_MSMALL) {
-        if (timing) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 2, true, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else if (t.ninst == 1) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 2, true, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, true, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
+        if (timing) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 2, true, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout, zl);
+        else if (t.ninst == 1) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 2, true, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout, zl);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, true, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout, zl);
     } else if (timing) {
-        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 1, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 0, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
+        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 1, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout, zl);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 1, 0, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout, zl);
     } else if (t.ninst == 1) {
-        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 1, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
-        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 0, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
+        if (vec) hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 1, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout, zl);
+        else hipLaunchKernelGGL((k_matvec_m<TV, TY, true, 0, 0, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout, zl);
     } else {
-        hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout);
+        hipLaunchKernelGGL((k_matvec_m<TV, TY, false, 0, 2, false, NT, NTW>), MARGS, V, b.ldv, k, store_w, y, pout, zl);
     }
 }
 
