@@ -500,7 +500,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_m(Ctl* __restrict__ ctls, cons
                                                     const int* __restrict__ wb2i, const Inst inst0, int ninst,
                                                     const double* __restrict__ y0base, const double* __restrict__ y1base,
                                                     double* __restrict__ fbase, TV* __restrict__ V0base,
-                                                    float* __restrict__ y32base, double* __restrict__ pout) {
+                                                    float* __restrict__ y32base, double* __restrict__ pout, int zlen0) {
     using G = MGeo<double>;
     constexpr int MX = G::MX, MY = G::MY, MVX = G::MVX, MVP = G::MVP, MQX = G::MQX, MQY = G::MQY, MQS = G::MQS,
                   MQPS = G::MQPS;
@@ -523,7 +523,10 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_m(Ctl* __restrict__ ctls, cons
     const double half_tau = 0.5 * (ctl->mode == MODE_EE ? ctl->tau_acc : ctl->tau_step);
     const int tid = threadIdx.x;
     const int ntx = (n + MX - 1) / MX, nty = (n + MY - 1) / MY;
-    const int nitems = ntx * nty * ((n + CH_MARCH_L - 1) / CH_MARCH_L);
+    // planes per run: the FP32 matvec's in the mixed form (its workgroup
+    // count is sized for them); from the host for a single grid
+    const int zlen = SINGLE ? zlen0 : (sizeof(TV) == 4 ? march_len_fp32(n) : CH_MARCH_L);
+    const int nitems = ntx * nty * ((n + zlen - 1) / zlen);
     const int lb = xcd_remap(blockIdx.x - I.wblk0, I.wblk);
     int qrx[NQL], qry[NQL];
     const int cx = NPT * (tid % TXT), cy = tid / TXT;
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(CH_BLOCK) void k_est_m(Ctl* __restrict__ ctls, cons
     auto items = [&](auto vec_c) {
     constexpr bool VEC = decltype(vec_c)::value;
     for (int it = lb; it < nitems; it += I.wblk) {
-        const MarchItem m = march_item<MX, MY>(it, n);
+        const MarchItem m = march_item<MX, MY>(it, n, zlen);
         unsigned vo[NVL], qpos[NQL];
 #pragma unroll
         for (int l = 0; l < NVL; ++l) {
@@ -1189,13 +1192,14 @@ template <typename TV>
 static void launch_est_m(const Table& t, const DevBuffers& b, const double* y0, const double* y1, float* y32,
                          double* pout, hipStream_t s) {
     TV* V0 = static_cast<TV*>(b.V);
+    const int zl = sizeof(TV) == 4 ? march_len_fp32(t.hinst[0].n) : CH_MARCH_L;   // single-grid launches
     if (t.ninst == 1) {
         if (t.hinst[0].n % MGeo<double>::NPT == 0)
-            hipLaunchKernelGGL((k_est_m<TV, true, 1>), MARGS, y0, y1, b.fcur, V0, y32, pout);
+            hipLaunchKernelGGL((k_est_m<TV, true, 1>), MARGS, y0, y1, b.fcur, V0, y32, pout, zl);
         else
-            hipLaunchKernelGGL((k_est_m<TV, true, 0>), MARGS, y0, y1, b.fcur, V0, y32, pout);
+            hipLaunchKernelGGL((k_est_m<TV, true, 0>), MARGS, y0, y1, b.fcur, V0, y32, pout, zl);
     } else {
-        hipLaunchKernelGGL((k_est_m<TV, false, 2>), MARGS, y0, y1, b.fcur, V0, y32, pout);
+        hipLaunchKernelGGL((k_est_m<TV, false, 2>), MARGS, y0, y1, b.fcur, V0, y32, pout, zl);
     }
 }
 
