@@ -1,17 +1,25 @@
 """3-D grids of every awkward size for the z-marching kernels (the DCGS2
 matvec with its dot phase and the EE2 estimate pass).
 
-A workgroup owns a 64 x 8 block of (x, y) columns and a run of 16 planes, and
-each thread a pair of consecutive x.  The sizes here cover:
+In FP64 a workgroup owns a 64 x 8 block of (x, y) columns and a run of 16
+planes, and each thread a pair of consecutive x; in FP32 a 64 x 16 block and
+four consecutive x, with runs whose length is chosen per grid so that the work
+items fill whole rounds of workgroups (16 on small grids, 17 at 210^3, 22 at
+256^3).  The sizes here cover:
 - grids narrower than the block in x and y, whose halos wrap several times (n = 5, 6, 7);
 - odd n (the pair as two scalar points) and even n (one vector);
 - a single block (16) and runs whose last one has 1 plane (33, 65);
 - two blocks in x with a ragged second one (65, 66).
 
+- FP32 grids whose runs are not 16 planes (210, 256).
+
 Adaptive EE2 (Fig. 4) against the FP64 oracle: equal Krylov dimensions, the
 field to 1e-10 (relative L2 and max-abs).  FP32-mixed: one step to 1e-5.  A
 batch mixing odd and even sizes (the per-instance pair form): every member
-bit-equal to its solo run.
+bit-equal to its solo run.  The FP32 grids with longer runs: a batch (run
+length found per instance on the device) bit-equal to the solo runs (length
+from the host), and within 1e-5 of the FP64 run with the same Krylov
+dimensions.
 """
 import sys
 
@@ -94,3 +102,26 @@ def test_march_batch_of_odd_and_even_sizes(ctx):
         assert np.array_equal(yg.cpu().numpy(), fields[i].cpu().numpy()), n
     y_ref, _ = O.ee_adaptive(y0s[4], O.Problem(3, 33, 0.05), 1e-4, np.inf, 1e-4, 20, max_steps=4)
     assert rel(fields[4].cpu().numpy(), y_ref) <= 1e-10
+
+
+def test_fp32_longer_runs_batch_equals_solo_and_fp64(ctx):
+    ns = [210, 24, 256]
+    eps = [0.02, 0.05, 0.02]
+    kw = dict(tau0=1e-4, max_steps=3, m_max=20, tol=1e-4)
+    y0s = [uniform_field(n, 3, 0.1, 0.05, seed=8400 + i) for i, n in enumerate(ns)]
+    say("3-D FP32 batch with runs of 17, 16 and 22 planes")
+    fields = [dev(y) for y in y0s]
+    st, rc = ctx.run_ee_batch(fields, ns, eps, dim=3, precision=ch.CH_FP32_MIXED, **kw)
+    assert rc == 0 and all(s["steps"] == 3 for s in st)
+    for i, n in enumerate(ns):
+        yg = dev(y0s[i])
+        ctx.run_ee(ch.Problem(3, n, eps[i], precision=ch.CH_FP32_MIXED), yg, kw["tau0"], max_steps=3, m_max=20,
+                   tol=1e-4)
+        assert np.array_equal(yg.cpu().numpy(), fields[i].cpu().numpy()), n
+    y64 = dev(y0s[0])
+    _, r64 = ctx.run_ee(ch.Problem(3, 210, 0.02), y64, kw["tau0"], max_steps=3, m_max=20, tol=1e-4, records=True)
+    y32 = dev(y0s[0])
+    _, r32 = ctx.run_ee(ch.Problem(3, 210, 0.02, precision=ch.CH_FP32_MIXED), y32, kw["tau0"], max_steps=3,
+                        m_max=20, tol=1e-4, records=True)
+    assert [r["j"] for r in r32] == [r["j"] for r in r64]
+    assert rel(y32.cpu().numpy(), y64.cpu().numpy()) <= 1e-5
