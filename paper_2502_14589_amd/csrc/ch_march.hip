@@ -1,4 +1,6 @@
-// 3-D DCGS2 Jacobian matvec by z-marching x-y tiles.
+// 3-D kernels on z-marching x-y tiles: the DCGS2 Jacobian matvec (below),
+// the EE2 estimate pass, the LIM stage and the LIM estimate (further down,
+// each with its own comment).
 //
 // Same operator as the tile kernels (Section 2, eq. IVP; Section 3.1,
 // eqs. J, A_g; Section 3.3, eq. A_g_cs):
@@ -10,9 +12,9 @@
 // Layout.  A workgroup owns an MX x MY block of (x, y) columns and a run of
 // up to CH_MARCH_L planes in z (in the FP32 matvec, the length march_len_fp32
 // picks for the grid), which it walks plane by plane.  Thread t owns
-// the same two consecutive-x columns of the block in every pass (the stencil
-// passes and the dot phase), plus one column of the halo-1 ring around the
-// block.  In LDS: a ring of three operand planes (halo 2 in x and y) and two
+// the same 16 bytes of consecutive-x columns of the block in every pass (the
+// stencil passes and the dot phase: two x in FP64, four in FP32), plus one
+// column of the halo-1 ring around the block.  In LDS: a ring of three operand planes (halo 2 in x and y) and two
 // planes of the inner expression q = d u + eps^2 A u (halo 1); what the
 // stencils take from the planes above and below a point -- the operand and q
 // at the point itself -- stays in the owning thread's registers, and so do
@@ -21,7 +23,7 @@
 // thread's points (requested a step ahead), forms q on one plane and w on the
 // plane below it, and runs that plane's dot phase.  An operand plane region
 // is read (L + 4) / L times per run, (MX + 4)(MY + 4) / (MX MY) = 1.6 times
-// the tile, against (TX + 4)(TY + 4)(TZ + 4) / (TX TY TZ) = 4.5 for a
+// the tile in FP64 (64 x 8) and 1.3 in FP32 (64 x 16), against (TX + 4)(TY + 4)(TZ + 4) / (TX TY TZ) = 4.5 for a
 // 32 x 4 x 4 tile staged whole.
 #include "ch_common.h"
 #include "ch_stream.h"
