@@ -12,12 +12,16 @@ constexpr int march_rows(int prec) { return prec == CH_FP64 ? 8 : 16; }
 // largest share of whole rounds of co-resident workgroups, the shorter on
 // ties.  The kernel holds three workgroups per CU at its register count, so
 // 256 CUs hold 768: at 256^3 runs of 16 give 1024 items (a second round a
-// third full), runs of 22 give 768.  FP64 (four workgroups per CU; 2048 items
-// at 256^3) and the other marching kernels take CH_MARCH_L.
+// third full), runs of 22 give 768.  Only while every item has a workgroup
+// of its own at CH_MARCH_L (at most CH_WBLK_MAX items): beyond that the
+// workgroups loop over items, rounds no longer follow the item count, and
+// longer runs were slower (384^3, 512^3).  FP64 (four workgroups per CU;
+// 2048 items at 256^3) and the LIM kernels take CH_MARCH_L.
 constexpr unsigned MARCH_SLOTS_FP32 = 256u * 3u;
 
 __host__ __device__ inline int march_len_fp32(int n) {
     const unsigned nxy = (unsigned)((n + 63) / 64) * (unsigned)((n + 15) / 16);
+    if ((unsigned long long)nxy * (unsigned)((n + CH_MARCH_L - 1) / CH_MARCH_L) > CH_WBLK_MAX) return CH_MARCH_L;
     int best = CH_MARCH_L;
     unsigned long long bi = 0, br = 1;   // items and rounds of the best length so far
 #pragma unroll
