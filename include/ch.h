@@ -368,7 +368,9 @@ int ch_time_kernel(ch_ctx *ctx, const ch_problem *prob, int kernel, int m_max, c
  *   vx    2-D: grid columns per lane of the row-strip kernels (1, 2, or 4 in
  *         FP32-mixed; a divisor of n); unused in 3-D;
  *   wblk  workgroups of the 2-D row-strip kernels or the 3-D marching matvec
- *         (1..2048; each loops over its share of strips or x-y tiles);
+ *         (1..2048; each loops over its share of strips, or of x-y blocks
+ *         and runs of planes).  Built in: one per four strips, or 512 when
+ *         that would exceed 2048; in 3-D one per work item, at most 2048;
  *   cblk  workgroups of the streaming passes (DCGS2 update, state update):
  *         1..512, each looping over chunks of 2048 points.
  * The shape changes the order in which the partial sums of dot products are
