@@ -9,7 +9,8 @@ random projections), in FP64 and, at the prefix's end time, in FP32-mixed.
 64^3, adaptive, element by element.
 One LIM step of the same field (p = 33 and 66) and its first 6 adaptive LIM
 steps, element by element; LIM steps on 2048^2 and 1999^2, and traced EE2
-steps on 1999^2 and 127^3.
+steps on 1999^2 and 127^3; a traced EE2 step and a batch on 2048^2, whose
+waves loop over several strips.
 256^3 (eps = 0.02): element-by-element LIM step, the 3-D start-vector stencil
 at sampled points, mass conservation of a full EE2 step.
 """
@@ -331,6 +332,38 @@ def test_odd_wide_grid_ee_step_traced(ctx):
         assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12 if prec == ch.CH_FP64 else 1e-5)
         y = yg.cpu().numpy()
         assert rel(y, y_ref) <= tol and max_rel(y, y_ref) <= tol
+
+
+def test_wide_grid_strips_looping_per_wave(ctx):
+    """2048^2 needs more than 2048 strip workgroups at one strip per wave, so
+    its launches run 512 workgroups whose waves loop over 4 or 5 strips each
+    (FP32-mixed, 9216 strips) or 8 or 9 (FP64, 17408 strips).  One traced EE2
+    step of Krylov dimension 12 against the oracle (FP64 to the parity
+    tolerance, FP32-mixed to 1e-5), and a batch holding the grid and a small
+    one equal to their solo runs bit for bit."""
+    n = 2048
+    say(f"{n}^2 EE2 step, looping strips")
+    po = O.Problem(2, n, 0.01)
+    y0 = uniform_field(n, 2, 0.1, 0.05, seed=2800)
+    y_ref, tau_ref, info = O.ee_step(y0, po, 1e-8, 1e-8, 12)
+    assert not info.converged and info.j == 12
+    for prec, tol in ((ch.CH_FP64, 1e-10), (ch.CH_FP32_MIXED, 1e-5)):
+        assert ctx.get_shape(2, n, prec)["wblk"] == 512
+        yg = dev(y0)
+        rec = ctx.step_ee(ch.Problem(2, n, 0.01, False, prec), yg, 1e-8, m_max=12, tol_phi_fixed=1e-8)
+        assert rec["j"] == 12 and rec["traced"] == 1
+        assert rec["tau"] == pytest.approx(tau_ref, rel=1e-12 if prec == ch.CH_FP64 else 1e-5)
+        y = yg.cpu().numpy()
+        assert rel(y, y_ref) <= tol and max_rel(y, y_ref) <= tol
+    y1 = uniform_field(128, 2, 0.1, 0.05, seed=2801)
+    fields = [dev(y0), dev(y1)]
+    st, rc = ctx.run_ee_batch(fields, [n, 128], [0.01, 0.02], precision=ch.CH_FP32_MIXED, tau0=1e-6, max_steps=2,
+                              m_max=12, tol=1e-4)
+    assert rc == 0 and all(s["steps"] == 2 for s in st)
+    for f, y, nn, e in ((fields[0], y0, n, 0.01), (fields[1], y1, 128, 0.02)):
+        yg = dev(y)
+        ctx.run_ee(ch.Problem(2, nn, e, False, ch.CH_FP32_MIXED), yg, 1e-6, max_steps=2, m_max=12, tol=1e-4)
+        assert np.array_equal(yg.cpu().numpy(), f.cpu().numpy()), nn
 
 
 def test_odd_cube_ee_step_traced(ctx):
