@@ -395,7 +395,9 @@ int ch_set_shape(ch_ctx *ctx, int dim, int n, int prec, const ch_shape *shape);
  * Launch-shape tuner for one grid and precision (prob->dim, n, prec) at Krylov
  * dimension m_max (DCGS2): times the matvec with its dot products for every
  * valid vx and workgroup counts from the built-in choice down to a quarter of
- * it, then the update pass for streaming workgroup counts likewise, each over
+ * it, plus the counts below it that make whole rounds of two to four
+ * workgroups per CU, then the update pass for streaming workgroup counts
+ * likewise, each over
  * Arnoldi iterations 1, m_max/2 and m_max - 1 (back-to-back launches under HIP
  * events, best of three), and keeps the fastest shape for later runs on this
  * context (as ch_set_shape).  *best: that shape; *best_us and *default_us: the

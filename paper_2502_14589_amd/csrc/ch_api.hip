@@ -1619,10 +1619,15 @@ int ch_tune_shape(ch_ctx* ctx, const ch_problem* prob, int m_max, ch_shape* best
         *us = bt;
         return CH_OK;
     };
-    auto counts = [](int d) {   // d, 3d/4, d/2, d/4 (distinct, >= 1)
+    // d, 3d/4, d/2, d/4, and below d whole rounds of two, three and four
+    // workgroups per CU (all resident at once, each looping over an equal
+    // share); distinct, >= 1
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) cus = 0;
+    auto counts = [cus](int d) {
         std::vector<int> v;
-        for (int c : {d, (3 * d) / 4, d / 2, d / 4})
-            if (c >= 1 && std::find(v.begin(), v.end(), c) == v.end()) v.push_back(c);
+        for (int c : {d, (3 * d) / 4, d / 2, d / 4, 2 * cus, 3 * cus, 4 * cus})
+            if (c >= 1 && c <= d && std::find(v.begin(), v.end(), c) == v.end()) v.push_back(c);
         return v;
     };
     auto restore = [&]() {
