@@ -185,6 +185,22 @@ def test_trace_is_maximal_admissible_step():
     assert all(b >= a * (1 - 1e-9) for a, b in zip(rs, rs[1:]))
 
 
+@pytest.mark.parametrize("h11,h,tau0", [(2.0, 0.7, 1e-2), (-1.5, 0.7, 1e-2), (1e3, 5.0, 1e-3)])
+def test_trace_matches_closed_form_of_a_one_dimensional_krylov_space(h11, h, tau0):
+    """Reading R1 against a closed form (Fig. 3 trace, eqs. rm, phi_stop): for
+    H = [h11] and h_{2,1} = h the residual is h |s phi(-s h11)| =
+    h |1 - exp(-s h11)| / |h11|, increasing in s for either sign of h11, so
+    the largest admissible step solves h |1 - exp(-s h11)| / |h11| = tol:
+    s* = -log(1 - tol h11 / h) / h11.  The trace (dyadic search, then
+    bisection) must return s* from below, to its bracket width.  (With h11 > 0
+    the residual saturates at h / h11, which must exceed tol for a crossing.)"""
+    tol = 1e-3
+    s_star = -math.log1p(-tol * h11 / h) / h11
+    assert s_star < tau0 / 2          # the dyadic search takes at least one halving
+    s = O.rt_trace(np.array([[h11]]), h, tau0, tol)
+    assert s_star * (1 - 1e-13) <= s <= s_star * (1 + 1e-15)
+
+
 def test_residual_identity_and_arnoldi_health():
     prob = O.Problem(2, 16, 0.05)
     y = uniform_field(16, 2, 0.1, 0.05, seed=9)
