@@ -306,6 +306,24 @@ def test_lim_large_order_parity(ctx, tl):
     assert rel(host(yg), y_ref) <= TOL_FP64
 
 
+@pytest.mark.parametrize("dim,n,c,p", [(2, 40, 0.5, 1), (2, 40, 2.0, 2), (2, 45, 2.0, 2), (3, 12, 0.5, 1),
+                                       (3, 12, 2.0, 2)])
+def test_lim_lowest_orders(ctx, dim, n, c, p):
+    """LIM steps of order 1 (tau lambda_max <= 1: one stage, stage 0 alone)
+    and 2 (three stages: stage 0, then one launch of two in 2-D or two
+    marching launches in 3-D; eq. p) against the oracle."""
+    say(f"LIM order {p} dim={dim} n={n}")
+    po, pg = probs(dim, n, 0.05)
+    y0 = uniform_field(n, dim, 0.1, 0.3, seed=1300 + 10 * dim + p)
+    tau = c / O.lambda_max(y0, po)
+    y_ref, pp = O.lim_step(y0, po, tau)
+    assert pp == p
+    yg = dev(y0)
+    rec = ctx.step_lim(pg, yg, tau)
+    assert rec["j"] == p
+    assert rel(host(yg), y_ref) <= TOL_FP64
+
+
 def test_lim_maximum_order(ctx):
     """p = CH_PMAX = 4096 (8191 stages: stage 0, then 4095 two-stage
     launches; the plan's Leja order at its largest size) against the oracle
