@@ -1580,6 +1580,18 @@ int ch_set_shape(ch_ctx* ctx, int dim, int n, int prec, const ch_shape* shape) {
     return CH_OK;
 }
 
+// Workgroup counts the shape tuners try below the built-in count d: d, 3d/4,
+// d/2, d/4, and whole rounds of two, three and four workgroups per CU (all
+// resident at once, each looping over an equal share); distinct, >= 1.
+static std::vector<int> tuner_counts(const ch_ctx* ctx, int d) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) cus = 0;
+    std::vector<int> v;
+    for (int c : {d, (3 * d) / 4, d / 2, d / 4, 2 * cus, 3 * cus, 4 * cus})
+        if (c >= 1 && c <= d && std::find(v.begin(), v.end(), c) == v.end()) v.push_back(c);
+    return v;
+}
+
 int ch_tune_shape(ch_ctx* ctx, const ch_problem* prob, int m_max, ch_shape* best, double* best_us,
                   double* default_us) {
     if (!ctx || !best || !best_us || !default_us) return CH_EINVAL;
@@ -1619,17 +1631,7 @@ int ch_tune_shape(ch_ctx* ctx, const ch_problem* prob, int m_max, ch_shape* best
         *us = bt;
         return CH_OK;
     };
-    // d, 3d/4, d/2, d/4, and below d whole rounds of two, three and four
-    // workgroups per CU (all resident at once, each looping over an equal
-    // share); distinct, >= 1
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) cus = 0;
-    auto counts = [cus](int d) {
-        std::vector<int> v;
-        for (int c : {d, (3 * d) / 4, d / 2, d / 4, 2 * cus, 3 * cus, 4 * cus})
-            if (c >= 1 && c <= d && std::find(v.begin(), v.end(), c) == v.end()) v.push_back(c);
-        return v;
-    };
+    auto counts = [ctx](int d) { return tuner_counts(ctx, d); };
     auto restore = [&]() {
         if (had) put_shape(ctx, dim, n, prec, saved);
         else drop_shape(ctx, dim, n, prec);
@@ -1754,12 +1756,7 @@ int ch_tune_batch_shapes(ch_ctx* ctx, int count, const ch_batch_item* items, int
         *us = bt;
         return CH_OK;
     };
-    auto counts = [](int d) {
-        std::vector<int> v;
-        for (int c : {d, (3 * d) / 4, d / 2, d / 4})
-            if (c >= 1 && std::find(v.begin(), v.end(), c) == v.end()) v.push_back(c);
-        return v;
-    };
+    auto counts = [ctx](int d) { return tuner_counts(ctx, d); };
     double cur;
     if ((rc = timed(&cur))) return rc;
     const double dflt_us = cur;
