@@ -11,20 +11,22 @@
 //
 // Layout.  A workgroup owns an MX x MY block of (x, y) columns and a run of
 // up to CH_MARCH_L planes in z (in the FP32 matvec, the length march_len_fp32
-// picks for the grid), which it walks plane by plane.  Thread t owns
-// the same 16 bytes of consecutive-x columns of the block in every pass (the
-// stencil passes and the dot phase: two x in FP64, four in FP32), plus one
-// column of the halo-1 ring around the block.  In LDS: a ring of three operand planes (halo 2 in x and y) and two
-// planes of the inner expression q = d u + eps^2 A u (halo 1); what the
-// stencils take from the planes above and below a point -- the operand and q
-// at the point itself -- stays in the owning thread's registers, and so do
+// picks for the grid), which it walks plane by plane.  Thread t owns the same
+// 16 bytes of consecutive-x columns of the block in every pass (the stencil
+// passes and the dot phase: two x in FP64, four in FP32), plus one column of
+// the halo-1 ring around the block.  In LDS: a ring of three operand planes
+// (halo 2 in x and y) and two planes of the inner expression
+// q = d u + eps^2 A u (halo 1); what the stencils take from the planes above
+// and below a point -- the operand and q at the point itself -- stays in the
+// owning thread's registers, and so do
 // d = 3 y^2 - 1 at its points and the w and u values of its dot products.  A
 // plane step has one barrier: it reads one operand plane and the state at the
 // thread's points (requested a step ahead), forms q on one plane and w on the
 // plane below it, and runs that plane's dot phase.  An operand plane region
 // is read (L + 4) / L times per run, (MX + 4)(MY + 4) / (MX MY) = 1.6 times
-// the tile in FP64 (64 x 8) and 1.3 in FP32 (64 x 16), against (TX + 4)(TY + 4)(TZ + 4) / (TX TY TZ) = 4.5 for a
-// 32 x 4 x 4 tile staged whole.
+// the tile in FP64 (64 x 8) and 1.3 in FP32 (64 x 16), against
+// (TX + 4)(TY + 4)(TZ + 4) / (TX TY TZ) = 4.5 for a 32 x 4 x 4 tile staged
+// whole.
 #include "ch_common.h"
 #include "ch_stream.h"
 #include "ch_march.h"
