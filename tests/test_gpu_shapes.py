@@ -67,6 +67,20 @@ def test_shape_round_trip_and_limits(ctx):
             ctx.set_shape(dim, n, prec, s)
 
 
+def test_built_in_workgroup_counts(ctx):
+    """The built-in counts: 2-D one workgroup per four strips (1024^2: 2560
+    strips in FP32, 4608 in FP64), 512 once that exceeds 2048 (2048^2); 3-D
+    one per work item, with FP32 runs sized to fill whole rounds of 768
+    co-resident workgroups while the items at 16-plane runs fit 2048 (256^3:
+    runs of 22, 768 items; 210^3: runs of 17, 728 items), else 16-plane runs
+    capped at 2048 (384^3); FP64 16-plane runs (256^3: 2048 items)."""
+    F32, F64 = ch.CH_FP32_MIXED, ch.CH_FP64
+    for dim, n, prec, w in ((2, 1024, F32, 640), (2, 1024, F64, 1152), (2, 2048, F32, 512), (2, 2048, F64, 512),
+                            (3, 256, F32, 768), (3, 210, F32, 728), (3, 384, F32, 2048), (3, 256, F64, 2048),
+                            (3, 24, F32, 4)):
+        assert ctx.get_shape(dim, n, prec)["wblk"] == w, (dim, n, prec)
+
+
 @pytest.mark.parametrize("prec,shape", [(ch.CH_FP64, {"vx": 1, "wblk": 3, "cblk": 1}),
                                         (ch.CH_FP64, {"vx": 2, "wblk": 1, "cblk": 2}),
                                         (ch.CH_FP32_MIXED, {"vx": 1, "wblk": 2, "cblk": 1}),
